@@ -1,0 +1,298 @@
+"""CPU oracle for the AGIS sampling estimator -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never loads it.
+
+Pieces:
+  * ``agis_oracle.c`` (built into ``liboracle.so`` with gcc): Philox,
+    Lemire draws, Q16 log2 encoding, proposal tables, Algorithm 3 sampler,
+    step distributions, exact counting judges;
+  * ``pattern.py``: the pattern compiler (Algorithm 2, auxiliary arrays,
+    decision function);
+  * ``estimator.py``: Algorithm 1 statistics and the run-to-epsilon loop;
+  * ``tree.py``: exact expectation over the whole sampling tree;
+  * ``judges.py``: exact counts (brute force and closed forms).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from .pattern import compile_pattern, matching_order, automorphisms, step_analysis  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "agis_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MAXK = 8
+CERTAIN_ZERO = -(1 << 31)
+LC_MIN_DEFAULT = -10 * 65536  # log2(2^-10) in Q16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no vectorisation tricks)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_uint32),
+        ("pattern_id", ctypes.c_uint32),
+        ("bmask", ctypes.c_uint8 * MAXK),
+        ("f1", ctypes.c_uint8 * MAXK),
+        ("ie", ctypes.c_uint8 * MAXK),
+        ("f2", ctypes.c_uint8 * MAXK),
+        ("decision", ctypes.c_uint8 * MAXK),
+    ]
+
+
+class Record(ctypes.Structure):
+    _fields_ = [
+        ("v", ctypes.c_uint32 * MAXK),
+        ("num", ctypes.c_uint64 * MAXK),
+        ("den", ctypes.c_uint64 * MAXK),
+        ("x", ctypes.c_double),
+        ("steps", ctypes.c_int32),
+        ("fail_step", ctypes.c_int32),
+    ]
+
+
+RECORD_DTYPE = np.dtype([
+    ("v", np.uint32, (MAXK,)),
+    ("num", np.uint64, (MAXK,)),
+    ("den", np.uint64, (MAXK,)),
+    ("x", np.float64),
+    ("steps", np.int32),
+    ("fail_step", np.int32),
+])
+assert RECORD_DTYPE.itemsize == ctypes.sizeof(Record)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("mean", ctypes.c_double), ("m2", ctypes.c_double),
+                ("nonzero", ctypes.c_uint64)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_bounded.argtypes = [P, u32, u32, u32, u32, u64]
+        L.orc_bounded.restype = u64
+        L.orc_log2fx.argtypes = [u64]
+        L.orc_log2fx.restype = i32
+        L.orc_weight_from_log.argtypes = [i32, i32]
+        L.orc_weight_from_log.restype = u32
+        L.orc_fixed_point_tables.argtypes = [P, P]
+        L.orc_build_tables.argtypes = [P, P, u64, u32, u32, i32, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_step1_table.argtypes = [P, P, P, P, P, P]
+        L.orc_step1_table.restype = u64
+        L.orc_run.argtypes = [P, P, u64, u64, P, P, P, P, P, P, P, P, u64, u64, u64, u64, P, P, P]
+        L.orc_run.restype = ctypes.c_int
+        L.orc_run_indices.argtypes = [P, P, u64, u64, P, P, P, P, P, P, P, P, u64, u64, P, u64, P]
+        L.orc_run_indices.restype = ctypes.c_int
+        L.orc_step_distribution.argtypes = [P, P, u64, u64, P, P, P, P, P, P, P, ctypes.c_int, P, P, P]
+        L.orc_step_distribution.restype = u64
+        L.orc_step_distribution_literal.argtypes = [P, P, u64, u64, P, P, P, P, ctypes.c_int, P, P, P]
+        L.orc_step_distribution_literal.restype = u64
+        L.orc_literal_terms.argtypes = [u64, u32, u32, u32, u32, ctypes.c_double, u64, P, P, P]
+        L.orc_count_embeddings.argtypes = [P, P, u64, u64, P, P, u32]
+        L.orc_count_embeddings.restype = u64
+        L.orc_count_cliques.argtypes = [P, P, u64, u64, u32]
+        L.orc_count_cliques.restype = u64
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- RNG
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return [int(x) for x in out]
+
+
+def bounded(seed: int, c0: int, c1: int, c2: int, tag: int, rng: int) -> int:
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint32)
+    return int(lib().orc_bounded(_p(key), c0, c1, c2, tag, rng))
+
+
+def log2fx(x: int) -> int:
+    return int(lib().orc_log2fx(x))
+
+
+def weight_from_log(lmax: int, lw: int) -> int:
+    return int(lib().orc_weight_from_log(lmax, lw))
+
+
+def fixed_point_tables():
+    lt = np.zeros(4096, dtype=np.int32)
+    et = np.zeros(4096, dtype=np.uint32)
+    lib().orc_fixed_point_tables(_p(lt), _p(et))
+    return lt, et
+
+
+# ---------------------------------------------------------------- tables
+
+class Tables:
+    """Per-vertex proposal tables of Sec. 4.4 (host arrays)."""
+
+    def __init__(self, g, cv_seed: int = 0, lc_min: int = LC_MIN_DEFAULT, exact_cv: bool = False):
+        n = g.n
+        self.n = n
+        self.deg = np.zeros(n, dtype=np.uint32)
+        self.s2 = np.zeros(n, dtype=np.uint64)
+        self.hits = np.zeros(n, dtype=np.uint64)
+        self.trials = np.zeros(n, dtype=np.uint64)
+        self.la = np.zeros(n, dtype=np.int32)
+        self.lc = np.zeros(n, dtype=np.int32)
+        self.cv_seed = cv_seed
+        self.lc_min = lc_min
+        self.exact_cv = exact_cv
+        off = np.ascontiguousarray(g.off, dtype=np.uint64)
+        nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
+        lib().orc_build_tables(_p(off), _p(nbr), n, cv_seed & 0xFFFFFFFF, cv_seed >> 32, lc_min,
+                               1 if exact_cv else 0, _p(self.deg), _p(self.s2), _p(self.hits),
+                               _p(self.trials), _p(self.la), _p(self.lc))
+
+    def cv(self) -> np.ndarray:
+        """Clustering coefficient hits / trials (0 where undefined)."""
+        t = self.trials.astype(np.float64)
+        return np.where(t > 0, self.hits.astype(np.float64) / np.maximum(t, 1), 0.0)
+
+
+def make_plan(compiled: dict, pattern_id: int = 0) -> Plan:
+    P = Plan()
+    P.k = compiled["k"]
+    P.pattern_id = pattern_id
+    for i, s in enumerate(compiled["steps"]):
+        P.bmask[i] = s["bmask"]
+        P.f1[i] = s["f1"]
+        P.ie[i] = s["ie"]
+        P.f2[i] = s["f2"]
+        P.decision[i] = s["decision"]
+    return P
+
+
+class Sampler:
+    """Algorithm 3 over one graph/pattern; all state on the host."""
+
+    def __init__(self, g, tables: Tables, compiled: dict, seed: int, pattern_id: int = 0, learned=None):
+        self.g = g
+        self.off = np.ascontiguousarray(g.off, dtype=np.uint64)
+        self.nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
+        self.t = tables
+        self.compiled = compiled
+        self.plan = make_plan(compiled, pattern_id)
+        self.seed = seed
+        self._learned = learned
+        k = compiled["k"]
+        if learned is not None:
+            self._lt_arrays = [None if learned.get(i) is None else np.ascontiguousarray(learned[i], dtype=np.int32)
+                               for i in range(MAXK)]
+            self._lt_ptrs = (ctypes.c_void_p * MAXK)(*[None if a is None else a.ctypes.data for a in self._lt_arrays])
+            self._lt = ctypes.cast(self._lt_ptrs, ctypes.c_void_p)
+        else:
+            self._lt = None
+        self.q1 = np.zeros(g.n, dtype=np.uint32)
+        self.pre1 = np.zeros(g.n, dtype=np.uint64)
+        self.Q1 = 0
+        weighted0 = compiled["steps"][0]["decision"] == 1 and compiled["steps"][0]["f1"] > 0
+        if weighted0 and g.n > 0:
+            lt0 = None
+            if learned is not None and self._lt_arrays[0] is not None:
+                lt0 = _p(self._lt_arrays[0])
+            self.Q1 = int(lib().orc_step1_table(self._graph_struct(), self._tables_struct(), ctypes.byref(self.plan),
+                                               lt0, _p(self.q1), _p(self.pre1)))
+        del k
+
+    def _graph_struct(self):
+        class G(ctypes.Structure):
+            _fields_ = [("n", ctypes.c_uint64), ("nnz", ctypes.c_uint64), ("off", ctypes.c_void_p),
+                        ("nbr", ctypes.c_void_p)]
+        self._gs = G(self.g.n, self.g.nnz, self.off.ctypes.data, self.nbr.ctypes.data)
+        return ctypes.byref(self._gs)
+
+    def _tables_struct(self):
+        class T(ctypes.Structure):
+            _fields_ = [("deg", ctypes.c_void_p), ("s2", ctypes.c_void_p), ("la", ctypes.c_void_p),
+                        ("lc", ctypes.c_void_p)]
+        t = self.t
+        self._ts = T(t.deg.ctypes.data, t.s2.ctypes.data, t.la.ctypes.data, t.lc.ctypes.data)
+        return ctypes.byref(self._ts)
+
+    def _common(self):
+        t = self.t
+        return (_p(self.off), _p(self.nbr), self.g.n, self.g.nnz, _p(t.deg), _p(t.s2), _p(t.la), _p(t.lc),
+                ctypes.byref(self.plan), self._lt, _p(self.q1), _p(self.pre1), self.Q1, self.seed)
+
+    def run(self, start: int, count: int, stats: Stats = None, want_x: bool = False, want_records: bool = False):
+        st = stats if stats is not None else Stats()
+        xs = np.zeros(count, dtype=np.float64) if want_x else None
+        recs = np.zeros(count, dtype=RECORD_DTYPE) if want_records else None
+        rc = lib().orc_run(*self._common(), start, count, ctypes.byref(st),
+                           _p(xs) if xs is not None else None, _p(recs) if recs is not None else None)
+        if rc != 0:
+            raise MemoryError("oracle scratch allocation failed")
+        return st, xs, recs
+
+    def records(self, indices) -> np.ndarray:
+        idx = np.ascontiguousarray(indices, dtype=np.uint64)
+        recs = np.zeros(idx.size, dtype=RECORD_DTYPE)
+        rc = lib().orc_run_indices(*self._common(), _p(idx), idx.size, _p(recs))
+        if rc != 0:
+            raise MemoryError("oracle scratch allocation failed")
+        return recs
+
+    def step_distribution(self, i: int, tau):
+        t = self.t
+        n = self.g.n
+        tau_a = np.zeros(MAXK, dtype=np.uint32)
+        tau_a[:len(tau)] = tau
+        out_v = np.zeros(max(n, 1), dtype=np.uint32)
+        out_w = np.zeros(max(n, 1), dtype=np.uint64)
+        m = lib().orc_step_distribution(_p(self.off), _p(self.nbr), n, self.g.nnz, _p(t.deg), _p(t.s2), _p(t.la),
+                                        _p(t.lc), ctypes.byref(self.plan), self._lt, _p(self.q1), i, _p(tau_a),
+                                        _p(out_v), _p(out_w))
+        return out_v[:m].copy(), out_w[:m].copy()
+
+    def step_distribution_literal(self, i: int, tau, cv: np.ndarray):
+        t = self.t
+        n = self.g.n
+        tau_a = np.zeros(MAXK, dtype=np.uint32)
+        tau_a[:len(tau)] = tau
+        cvv = np.ascontiguousarray(cv, dtype=np.float64)
+        out_v = np.zeros(max(n, 1), dtype=np.uint32)
+        out_w = np.zeros(max(n, 1), dtype=np.float64)
+        m = lib().orc_step_distribution_literal(_p(self.off), _p(self.nbr), n, self.g.nnz, _p(t.deg), _p(t.s2),
+                                                _p(cvv), ctypes.byref(self.plan), i, _p(tau_a), _p(out_v),
+                                                _p(out_w))
+        return out_v[:m].copy(), out_w[:m].copy()
+
+
+def literal_terms(d, b, f1, ie, f2, cv, s2):
+    a = ctypes.c_double()
+    c = ctypes.c_double()
+    e = ctypes.c_double()
+    lib().orc_literal_terms(d, b, f1, ie, f2, cv, s2, ctypes.byref(a), ctypes.byref(c), ctypes.byref(e))
+    return a.value, c.value, e.value

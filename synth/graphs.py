@@ -1,0 +1,181 @@
+"""Seeded synthetic data graphs in symmetric CSR form.
+
+Layout (the one every consumer expects):
+  * ``off``: uint64[n + 1], row offsets, ``off[0] == 0``, ``off[n] == nnz``;
+  * ``nbr``: uint32[nnz], neighbour ids, each row strictly ascending;
+  * undirected: ``x`` in row ``v`` iff ``v`` in row ``x``; no self-loops;
+    so ``nnz`` is twice the number of undirected edges.
+
+Generators use numpy's PCG64 stream with an explicit seed; they are input
+generators only and draw nothing on behalf of the estimator.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class CSR:
+    off: np.ndarray  # uint64[n+1]
+    nbr: np.ndarray  # uint32[nnz]
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.off.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.nbr.shape[0])
+
+    @property
+    def num_edges(self) -> int:
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.off).astype(np.int64)
+
+    def row(self, v: int) -> np.ndarray:
+        return self.nbr[int(self.off[v]):int(self.off[v + 1])]
+
+    def adjacency_sets(self) -> list:
+        return [set(int(x) for x in self.row(v)) for v in range(self.n)]
+
+
+def csr_from_edges(n: int, u, v, name: str = "") -> CSR:
+    """Symmetrise, drop self-loops and duplicates, and sort an edge list."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    if n > 0 and u.size:
+        if u.min() < 0 or v.min() < 0 or u.max() >= n or v.max() >= n:
+            raise ValueError("edge endpoint out of range")
+    src = np.concatenate([u, v])
+    dst = np.concatenate([v, u])
+    key = np.unique(src * np.int64(n) + dst)
+    rows = key // n
+    cols = (key % n).astype(np.uint32)
+    counts = np.bincount(rows, minlength=n).astype(np.uint64)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(counts, out=off[1:])
+    return CSR(off=off, nbr=cols, name=name)
+
+
+def chung_lu(n: int = 10_000, m: int = 100_000, gamma: float = 2.1, seed: int = 1) -> CSR:
+    """Chung-Lu power-law graph with exactly ``m`` distinct undirected edges.
+
+    Vertex ``i`` has weight ``(i + 1) ** (-1 / (gamma - 1))``; both endpoints
+    of a candidate edge are drawn independently with probability
+    proportional to weight, self-loops are discarded, and candidates are
+    taken in draw order until ``m`` distinct edges exist.
+    """
+    if m > n * (n - 1) // 2:
+        raise ValueError("m exceeds the number of vertex pairs")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    cdf[-1] = 1.0
+    order_keys = np.empty(0, dtype=np.int64)
+    batch = max(2 * m, 1024)
+    while True:
+        a = np.searchsorted(cdf, rng.random(batch), side="right").astype(np.int64)
+        b = np.searchsorted(cdf, rng.random(batch), side="right").astype(np.int64)
+        a = np.minimum(a, n - 1)
+        b = np.minimum(b, n - 1)
+        keep = a != b
+        lo = np.minimum(a[keep], b[keep])
+        hi = np.maximum(a[keep], b[keep])
+        order_keys = np.concatenate([order_keys, lo * n + hi])
+        uniq, first = np.unique(order_keys, return_index=True)
+        if uniq.size >= m:
+            chosen = uniq[np.argsort(first, kind="stable")[:m]]
+            break
+    return csr_from_edges(n, chosen // n, chosen % n, name=f"chung_lu_n{n}_m{m}_g{gamma}_s{seed}")
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         seed: int = 20, chunk: int = 1 << 24) -> CSR:
+    """R-MAT graph: ``edge_factor * 2**scale`` recursive-quadrant draws.
+
+    Each draw descends ``scale`` levels; at each level the quadrant is
+    (0,0) w.p. a, (0,1) w.p. b, (1,0) w.p. c, (1,1) otherwise.  No noise and
+    no vertex permutation.  The result is symmetrised and deduplicated with
+    self-loops removed.
+    """
+    n = 1 << scale
+    total = edge_factor * n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ab, abc = a + b, a + b + c
+    keys = []
+    done = 0
+    while done < total:
+        cnt = min(chunk, total - done)
+        u = np.zeros(cnt, dtype=np.int64)
+        v = np.zeros(cnt, dtype=np.int64)
+        for _ in range(scale):
+            r = rng.random(cnt)
+            bu = (r >= ab).astype(np.int64)
+            bv = (((r >= a) & (r < ab)) | (r >= abc)).astype(np.int64)
+            u = (u << 1) | bu
+            v = (v << 1) | bv
+        keep = u != v
+        u, v = u[keep], v[keep]
+        keys.append(np.unique(np.concatenate([u * n + v, v * n + u])))
+        done += cnt
+    key = np.unique(np.concatenate(keys)) if len(keys) > 1 else keys[0]
+    rows = key // n
+    cols = (key % n).astype(np.uint32)
+    counts = np.bincount(rows, minlength=n).astype(np.uint64)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(counts, out=off[1:])
+    return CSR(off=off, nbr=cols, name=f"rmat{scale}_ef{edge_factor}_s{seed}")
+
+
+def tiny_graph(n: int, p: float, seed: int) -> CSR:
+    """Erdos-Renyi G(n, p) for brute-force checks on a handful of vertices."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    us, vs = [], []
+    for i in range(n):
+        for j in range(i + 1, n):
+            if rng.random() < p:
+                us.append(i)
+                vs.append(j)
+    return csr_from_edges(n, us, vs, name=f"gnp_{n}_{p}_{seed}")
+
+
+def skewed_tiny_graph(n: int, seed: int, hubs: int = 2, p_hub: float = 0.8, p: float = 0.2) -> CSR:
+    """Small graph with a few hub vertices, for tests that need degree skew."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    us, vs = [], []
+    for i in range(n):
+        for j in range(i + 1, n):
+            q = p_hub if (i < hubs or j < hubs) else p
+            if rng.random() < q:
+                us.append(i)
+                vs.append(j)
+    return csr_from_edges(n, us, vs, name=f"skew_{n}_{seed}")
+
+
+def complete_graph(n: int) -> CSR:
+    us, vs = np.triu_indices(n, 1)
+    return csr_from_edges(n, us, vs, name=f"K{n}")
+
+
+def ring_graph(n: int) -> CSR:
+    us = np.arange(n)
+    return csr_from_edges(n, us, (us + 1) % n, name=f"C{n}")
+
+
+def star_graph(leaves: int) -> CSR:
+    return csr_from_edges(leaves + 1, np.zeros(leaves, dtype=np.int64), np.arange(1, leaves + 1), name=f"K1_{leaves}")
+
+
+def complete_bipartite(a: int, b: int) -> CSR:
+    us = np.repeat(np.arange(a), b)
+    vs = np.tile(np.arange(a, a + b), a)
+    return csr_from_edges(a + b, us, vs, name=f"K{a}_{b}")
