@@ -1,0 +1,227 @@
+/*
+ * agis.h -- C-ABI of the MI355X (gfx950) implementation of the AGIS
+ * structure-informed sampling estimator for approximate graph pattern
+ * counting ("AGIS: Fast Approximate Graph Pattern Mining with
+ * Structure-Informed Sampling", PVLDB 19(2)).
+ *
+ * The library estimates C(G, P), the number of embeddings (injective,
+ * edge-preserving maps V_P -> V_G; Sec. 2.1) of a small pattern P in a large
+ * undirected data graph G.  Each sample extends a partial embedding along a
+ * matching order (Algorithm 3), drawing each next vertex either uniformly
+ * (f_uniform, Sec. 5.3) or from the approximate ideal distribution
+ * (f_approx, Eq. probability_function, Sec. 4.2.3) as the decision function
+ * chooses (Definition "Decision Function", Sec. 5.1), and returns the
+ * importance weight 1/p.  The mean of many samples is the estimate;
+ * Algorithm 1 decides when it is within the requested error.
+ *
+ * Conventions for every entry point:
+ *  - Return value: AGIS_OK (0) or a negative AGIS_E_* code.  No C++
+ *    exception crosses this boundary.  After an error, agis_last_error()
+ *    on the same context returns a message (valid until the next call).
+ *  - Pointers documented as "device" point into memory of the context's
+ *    GPU; "host" pointers point into ordinary process memory.
+ *  - Ownership: the caller owns every buffer it passes; the library owns
+ *    the handles it returns (free them with the matching *_destroy).
+ *  - Streams: all GPU work of a context is enqueued on the stream given to
+ *    agis_create (0 = the null stream); entry points return after the work
+ *    they need has finished on that stream.
+ *  - Determinism: sample s of pattern id p under seed S is a pure function
+ *    of (graph, tables, pattern, order, mode, beta, S, p, s) -- independent
+ *    of launch shape, batch size and of the GPU -- so its vertex choices
+ *    and integer factors equal those of a CPU implementation of the same
+ *    definitions bit for bit, and its weight X is the same IEEE double.
+ */
+#ifndef AGIS_H
+#define AGIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AGIS_MAX_K 8
+
+/* Status codes. */
+enum {
+    AGIS_OK = 0,
+    AGIS_E_INVALID_ARG = -1,   /* NULL handle/pointer, bad size or flag */
+    AGIS_E_INVALID_CSR = -2,   /* CSR fails validation (see agis_load_csr) */
+    AGIS_E_PATTERN = -3,       /* pattern not connected, or k outside [2, 8] */
+    AGIS_E_ORDER = -4,         /* order not a permutation, or a prefix is disconnected */
+    AGIS_E_OOM = -5,           /* device allocation failed */
+    AGIS_E_HIP = -6,           /* HIP runtime error (message has the HIP string) */
+    AGIS_E_NOT_CONVERGED = -7, /* run-to-epsilon hit its budget; result is filled */
+    AGIS_E_UNSUPPORTED = -8    /* request outside what this build supports */
+};
+
+/* Proposal modes. */
+enum {
+    AGIS_MODE_UNIFORM = 0, /* f_uniform at every step: edge-uniform first vertex, then uniform over S */
+    AGIS_MODE_SWITCH = 1,  /* the paper's hybrid: f_approx where the decision function says so */
+    AGIS_MODE_ALWAYS = 2,  /* f_approx at every step (beta = -infinity) */
+    AGIS_MODE_LEARNED = 3  /* decisions as SWITCH; weighted steps read learned log-weight tables */
+};
+
+/* agis_load_csr flags. */
+#define AGIS_CSR_VALIDATE 1u
+
+typedef struct agis_ctx agis_ctx;
+typedef struct agis_graph agis_graph;
+typedef struct agis_tables agis_tables;
+
+/* A pattern graph on vertices 0..k-1: bit w of adj[u] is set iff {u, w} is
+ * an edge (symmetric, no self-loops).  2 <= k <= 8, connected. */
+typedef struct {
+    uint32_t k;
+    uint8_t adj[AGIS_MAX_K];
+} agis_pattern;
+
+/* Result of the pattern compiler (Sec. 4.2.2-4.2.3, 5.1, 5.2) for one
+ * matching order: per step i (0-based, vertex order[i]):
+ * bmask: bit j set iff order[j] (j < i) is adjacent to order[i];
+ * b = |B|, f1 = |F1|, i1 = |I1|, ie = |I_effective|, f2 = |F2|;
+ * certainty = cert_num / cert_den (Definition "Decision Function");
+ * decision: 1 = f_approx (or learned), 0 = f_uniform, after the mode and
+ * beta are applied; aut = |Aut(P)|. */
+typedef struct {
+    uint32_t k;
+    uint32_t aut;
+    uint8_t order[AGIS_MAX_K];
+    uint8_t bmask[AGIS_MAX_K];
+    uint8_t b[AGIS_MAX_K];
+    uint8_t f1[AGIS_MAX_K];
+    uint8_t i1[AGIS_MAX_K];
+    uint8_t ie[AGIS_MAX_K];
+    uint8_t f2[AGIS_MAX_K];
+    uint8_t decision[AGIS_MAX_K];
+    int32_t cert_num[AGIS_MAX_K];
+    int32_t cert_den[AGIS_MAX_K];
+} agis_plan;
+
+/* Run parameters.
+ * beta: decision threshold beta_num / beta_den compared exactly; with
+ *   beta_den == 0 the threshold is +infinity if beta_num > 0 (always
+ *   uniform) and -infinity otherwise (always f_approx).  The paper's
+ *   default is 4/5 (Sec. 5.1).
+ * eps, delta: Algorithm 1 target; eps <= 0 means "run exactly n_samples".
+ * check_every: samples between convergence checks (0 = 65536).
+ * min_samples: no convergence is declared before this many samples.
+ * pattern_id: enters the random stream of every sample (Philox counter).
+ * learned: for AGIS_MODE_LEARNED, per step a device int32[n] table of Q16
+ *   log2 weights (NULL for steps that are not weighted); ignored otherwise. */
+typedef struct {
+    int32_t mode;
+    int32_t beta_num;
+    int32_t beta_den;
+    uint32_t pattern_id;
+    double eps;
+    double delta;
+    uint64_t check_every;
+    uint64_t min_samples;
+    const int32_t* learned[AGIS_MAX_K];
+} agis_run_params;
+
+/* Estimator output.  estimate = mean of the sample weights X (an unbiased
+ * estimate of C(G, P), embeddings); copies = estimate / |Aut(P)|;
+ * variance = population variance of X (Algorithm 1's sigma^2);
+ * eps_hat = Algorithm 1's estimated relative error at delta;
+ * seconds = wall time from the first GPU launch of the estimate (including
+ * the first-step table) to the result; step1_seconds = the first-step
+ * table build alone. */
+typedef struct {
+    double estimate;
+    double copies;
+    double variance;
+    double eps_hat;
+    uint64_t n;
+    uint64_t n_nonzero;
+    uint32_t aut;
+    int32_t converged;
+    double seconds;
+    double step1_seconds;
+    agis_plan plan;
+} agis_result;
+
+/* Per-sample record written by agis_dump_samples (176 bytes, host layout):
+ * v[i] = data vertex picked at step i, num[i]/den[i] = the integer factor
+ * of step i (|S| / 1 for uniform steps, Q / q(v) for weighted ones),
+ * x = the sample weight (0 when the sample failed), steps = steps that
+ * picked a vertex, fail_step = -1 on success, else the step whose
+ * candidate set (or total weight) was empty.  Unused entries are 0. */
+typedef struct {
+    uint32_t v[AGIS_MAX_K];
+    uint64_t num[AGIS_MAX_K];
+    uint64_t den[AGIS_MAX_K];
+    double x;
+    int32_t steps;
+    int32_t fail_step;
+} agis_record;
+
+/* Creates a context on GPU `device` that enqueues work on `hip_stream`
+ * (a hipStream_t, borrowed; 0 = null stream).  *out receives the handle. */
+int agis_create(agis_ctx** out, int device, void* hip_stream);
+void agis_destroy(agis_ctx* ctx);
+const char* agis_last_error(const agis_ctx* ctx);
+
+/* Registers a symmetric CSR graph (Sec. 6.1: the graph is held in CSR).
+ * off: device uint64[n + 1], off[0] = 0, off[n] = nnz, non-decreasing;
+ * nbr: device uint32[nnz], each row strictly ascending, ids < n, no
+ * self-loops, and x in row v iff v in row x.  Both are BORROWED: they must
+ * stay valid and unchanged until agis_graph_destroy.  With
+ * AGIS_CSR_VALIDATE every property is checked on the GPU and a violation
+ * returns AGIS_E_INVALID_CSR.  n must be < 2^32. */
+int agis_load_csr(agis_ctx* ctx, const uint64_t* off, const uint32_t* nbr, uint64_t n, uint64_t nnz,
+                  uint32_t flags, agis_graph** out);
+void agis_graph_destroy(agis_graph* g);
+
+/* Builds the per-vertex proposal tables (Sec. 4.4): degree d(v), the
+ * neighbour-degree sum S2(v) = sum_{x in N(v)} d(x), and the clustering
+ * coefficient C_v estimated from d(v) trials (exact_cv = 0; each trial
+ * draws an ordered pair of distinct neighbours from Philox key cv_seed) or
+ * counted exactly (exact_cv = 1).  Stored in Q16 log2 form with log2 C_v
+ * clamped below at lc_min_q16 (log2 of the paper's small nonzero constant;
+ * -655360 = log2 2^-10).  The tables are owned by the library. */
+int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_seed, int32_t lc_min_q16,
+                               int32_t exact_cv, agis_tables** out);
+void agis_tables_destroy(agis_tables* t);
+
+/* Copies the tables into caller device buffers (each of n entries; any may
+ * be NULL): deg uint32, s2 uint64, hits uint64, trials uint64, la int32
+ * (Q16 log2 of S2/d), lc int32 (Q16 log2 of C_v, clamped). */
+int agis_tables_export(agis_ctx* ctx, const agis_tables* t, uint32_t* deg, uint64_t* s2, uint64_t* hits,
+                       uint64_t* trials, int32_t* la, int32_t* lc);
+
+/* Pattern compiler alone (host only, no GPU needed): matching order by
+ * Algorithm 2 when order == NULL (host uint8[k] otherwise), auxiliary
+ * arrays and decisions for params->mode / beta (params may be NULL:
+ * SWITCH, beta = 4/5). */
+int agis_compile_pattern(const agis_pattern* p, const uint8_t* order, const agis_run_params* params,
+                         agis_plan* out);
+
+/* Estimates C(G, P) (Algorithm 3 samples, Algorithm 1 statistics).
+ * order: host uint8[k] or NULL for Algorithm 2.  With params->eps > 0 the
+ * run stops at the first check where eps_hat <= eps (and n >= min_samples),
+ * or returns AGIS_E_NOT_CONVERGED after n_samples samples (result filled);
+ * with eps <= 0 exactly n_samples samples are drawn.  Samples use indices
+ * 0, 1, 2, ... under `seed`. */
+int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                  const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
+                  agis_result* out);
+
+/* Runs the samples whose indices are listed in idx (device uint64[m]) and
+ * writes one agis_record per index into out (device, m records). */
+int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                      const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
+                      uint64_t m, agis_record* out);
+
+/* Host copies of the library's Q16 tables (4096 entries each), its Philox
+ * block function and its bounded draw -- for host-side tests. */
+int agis_fixed_point_tables(int32_t* logtab, uint32_t* exp2tab);
+int agis_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGIS_H */

@@ -1,0 +1,255 @@
+"""Python binding of libagis.so (the C-ABI in include/agis.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library.  The functions keep the C names (``agis_create``,
+``agis_load_csr``, ...) and take plain integers for device pointers and
+streams; PyTorch is used by callers only to own device memory and streams.
+
+The binding refuses to work without the built library: there is no CPU
+fallback.  Build it with ``python -m paper_2601_01388_amd.build``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libagis.so")
+
+MAX_K = 8
+
+AGIS_OK = 0
+AGIS_E_INVALID_ARG = -1
+AGIS_E_INVALID_CSR = -2
+AGIS_E_PATTERN = -3
+AGIS_E_ORDER = -4
+AGIS_E_OOM = -5
+AGIS_E_HIP = -6
+AGIS_E_NOT_CONVERGED = -7
+AGIS_E_UNSUPPORTED = -8
+
+AGIS_MODE_UNIFORM = 0
+AGIS_MODE_SWITCH = 1
+AGIS_MODE_ALWAYS = 2
+AGIS_MODE_LEARNED = 3
+MODE_BY_NAME = {"uniform": 0, "switch": 1, "always": 2, "learned": 3}
+
+AGIS_CSR_VALIDATE = 1
+LC_MIN_DEFAULT = -10 * 65536
+
+_ERRNAMES = {
+    -1: "AGIS_E_INVALID_ARG", -2: "AGIS_E_INVALID_CSR", -3: "AGIS_E_PATTERN", -4: "AGIS_E_ORDER",
+    -5: "AGIS_E_OOM", -6: "AGIS_E_HIP", -7: "AGIS_E_NOT_CONVERGED", -8: "AGIS_E_UNSUPPORTED",
+}
+
+
+class AgisError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class agis_pattern(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("adj", ctypes.c_uint8 * MAX_K)]
+
+
+class agis_plan(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_uint32), ("aut", ctypes.c_uint32),
+        ("order", ctypes.c_uint8 * MAX_K), ("bmask", ctypes.c_uint8 * MAX_K), ("b", ctypes.c_uint8 * MAX_K),
+        ("f1", ctypes.c_uint8 * MAX_K), ("i1", ctypes.c_uint8 * MAX_K), ("ie", ctypes.c_uint8 * MAX_K),
+        ("f2", ctypes.c_uint8 * MAX_K), ("decision", ctypes.c_uint8 * MAX_K),
+        ("cert_num", ctypes.c_int32 * MAX_K), ("cert_den", ctypes.c_int32 * MAX_K),
+    ]
+
+
+class agis_run_params(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32), ("beta_num", ctypes.c_int32), ("beta_den", ctypes.c_int32),
+        ("pattern_id", ctypes.c_uint32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+        ("check_every", ctypes.c_uint64), ("min_samples", ctypes.c_uint64),
+        ("learned", ctypes.c_void_p * MAX_K),
+    ]
+
+
+class agis_result(ctypes.Structure):
+    _fields_ = [
+        ("estimate", ctypes.c_double), ("copies", ctypes.c_double), ("variance", ctypes.c_double),
+        ("eps_hat", ctypes.c_double), ("n", ctypes.c_uint64), ("n_nonzero", ctypes.c_uint64),
+        ("aut", ctypes.c_uint32), ("converged", ctypes.c_int32), ("seconds", ctypes.c_double),
+        ("step1_seconds", ctypes.c_double), ("plan", agis_plan),
+    ]
+
+
+RECORD_DTYPE = np.dtype([
+    ("v", np.uint32, (MAX_K,)), ("num", np.uint64, (MAX_K,)), ("den", np.uint64, (MAX_K,)),
+    ("x", np.float64), ("steps", np.int32), ("fail_step", np.int32),
+])
+RECORD_BYTES = RECORD_DTYPE.itemsize  # 176
+
+# (name, restype, argtypes) of every symbol include/agis.h declares
+_P = ctypes.c_void_p
+_SIGNATURES = [
+    ("agis_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, _P]),
+    ("agis_destroy", None, [_P]),
+    ("agis_last_error", ctypes.c_char_p, [_P]),
+    ("agis_load_csr", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.POINTER(ctypes.c_void_p)]),
+    ("agis_graph_destroy", None, [_P]),
+    ("agis_build_proposal_tables", ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_void_p)]),
+    ("agis_tables_destroy", None, [_P]),
+    ("agis_tables_export", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    ("agis_compile_pattern", ctypes.c_int, [ctypes.POINTER(agis_pattern), _P, ctypes.POINTER(agis_run_params),
+                                            ctypes.POINTER(agis_plan)]),
+    ("agis_estimate", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.POINTER(agis_run_params), ctypes.POINTER(agis_result)]),
+    ("agis_dump_samples", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
+                                         ctypes.POINTER(agis_run_params), _P, ctypes.c_uint64, _P]),
+    ("agis_fixed_point_tables", ctypes.c_int, [_P, _P]),
+    ("agis_philox4x32_10", ctypes.c_int, [_P, _P, _P]),
+]
+EXPORTED = [s[0] for s in _SIGNATURES]
+
+_lib = None
+
+
+def lib():
+    """Loads libagis.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_01388_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(ctx, rc: int, allow=()):
+    if rc != AGIS_OK and rc not in allow:
+        msg = lib().agis_last_error(ctx).decode() if ctx else ""
+        raise AgisError(rc, msg)
+    return rc
+
+
+# ---------------------------------------------------------------- C names
+
+def agis_create(device: int = 0, stream: int = 0):
+    h = ctypes.c_void_p()
+    _check(None, lib().agis_create(ctypes.byref(h), device, stream))
+    return h
+
+
+def agis_destroy(ctx):
+    lib().agis_destroy(ctx)
+
+
+def agis_last_error(ctx) -> str:
+    return lib().agis_last_error(ctx).decode()
+
+
+def agis_load_csr(ctx, off_ptr: int, nbr_ptr: int, n: int, nnz: int, flags: int = AGIS_CSR_VALIDATE):
+    h = ctypes.c_void_p()
+    _check(ctx, lib().agis_load_csr(ctx, off_ptr, nbr_ptr, n, nnz, flags, ctypes.byref(h)))
+    return h
+
+
+def agis_graph_destroy(g):
+    lib().agis_graph_destroy(g)
+
+
+def agis_build_proposal_tables(ctx, g, cv_seed: int = 0, lc_min_q16: int = LC_MIN_DEFAULT, exact_cv: bool = False):
+    h = ctypes.c_void_p()
+    _check(ctx, lib().agis_build_proposal_tables(ctx, g, cv_seed, lc_min_q16, 1 if exact_cv else 0, ctypes.byref(h)))
+    return h
+
+
+def agis_tables_destroy(t):
+    lib().agis_tables_destroy(t)
+
+
+def agis_tables_export(ctx, t, deg=0, s2=0, hits=0, trials=0, la=0, lc=0):
+    _check(ctx, lib().agis_tables_export(ctx, t, deg or None, s2 or None, hits or None, trials or None, la or None,
+                                         lc or None))
+
+
+def make_pattern(k: int, adj) -> agis_pattern:
+    p = agis_pattern()
+    p.k = k
+    for i, a in enumerate(adj):
+        p.adj[i] = a
+    return p
+
+
+def make_params(mode="switch", beta=(4, 5), pattern_id=0, eps=0.0, delta=0.05, check_every=0, min_samples=0,
+                learned=None) -> agis_run_params:
+    pr = agis_run_params()
+    pr.mode = MODE_BY_NAME[mode] if isinstance(mode, str) else int(mode)
+    pr.beta_num, pr.beta_den = beta
+    pr.pattern_id = pattern_id
+    pr.eps = eps
+    pr.delta = delta
+    pr.check_every = check_every
+    pr.min_samples = min_samples
+    if learned:
+        for i, ptr in learned.items():
+            pr.learned[i] = ptr
+    return pr
+
+
+def _order_arg(order):
+    if order is None:
+        return None, None
+    buf = (ctypes.c_uint8 * MAX_K)(*list(order))
+    return buf, ctypes.cast(buf, ctypes.c_void_p)
+
+
+def agis_compile_pattern(pattern: agis_pattern, order=None, params: agis_run_params = None) -> agis_plan:
+    out = agis_plan()
+    keep, ptr = _order_arg(order)
+    rc = lib().agis_compile_pattern(ctypes.byref(pattern), ptr, ctypes.byref(params) if params else None,
+                                    ctypes.byref(out))
+    if rc != AGIS_OK:
+        raise AgisError(rc, "pattern compile failed")
+    del keep
+    return out
+
+
+def agis_estimate(ctx, g, t, pattern: agis_pattern, n_samples: int, seed: int, params: agis_run_params,
+                  order=None) -> agis_result:
+    out = agis_result()
+    keep, ptr = _order_arg(order)
+    _check(ctx, lib().agis_estimate(ctx, g, t, ctypes.byref(pattern), ptr, n_samples, seed, ctypes.byref(params),
+                                    ctypes.byref(out)), allow=(AGIS_E_NOT_CONVERGED,))
+    del keep
+    return out
+
+
+def agis_dump_samples(ctx, g, t, pattern: agis_pattern, seed: int, params: agis_run_params, idx_ptr: int, m: int,
+                      out_ptr: int, order=None):
+    keep, ptr = _order_arg(order)
+    _check(ctx, lib().agis_dump_samples(ctx, g, t, ctypes.byref(pattern), ptr, seed, ctypes.byref(params), idx_ptr,
+                                        m, out_ptr))
+    del keep
+
+
+def agis_fixed_point_tables():
+    lt = np.zeros(4096, dtype=np.int32)
+    et = np.zeros(4096, dtype=np.uint32)
+    _check(None, lib().agis_fixed_point_tables(lt.ctypes.data, et.ctypes.data))
+    return lt, et
+
+
+def agis_philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    _check(None, lib().agis_philox4x32_10(c.ctypes.data, k.ctypes.data, o.ctypes.data))
+    return [int(x) for x in o]

@@ -1,0 +1,155 @@
+// Shared host/device definitions of the AGIS library: the random stream,
+// the Q16 log2 encoding of proposal weights, and the plain structs that the
+// kernels take by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define AGIS_HD __host__ __device__ __forceinline__
+
+namespace agis {
+
+constexpr int kMaxK = 8;
+constexpr int32_t kCertainZero = INT32_MIN;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11): ten
+// rounds of two 32x32->64 multiplies with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+struct U32x4 {
+    uint32_t x, y, z, w;
+};
+
+AGIS_HD void mulhilo32(uint32_t a, uint32_t b, uint32_t& hi, uint32_t& lo) {
+#ifdef __HIP_DEVICE_COMPILE__
+    lo = a * b;
+    hi = __umulhi(a, b);
+#else
+    uint64_t p = (uint64_t)a * (uint64_t)b;
+    hi = (uint32_t)(p >> 32);
+    lo = (uint32_t)p;
+#endif
+}
+
+AGIS_HD U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0, lo0, hi1, lo1;
+        mulhilo32(0xD2511F53u, c.x, hi0, lo0);
+        mulhilo32(0xCD9E8D57u, c.z, hi1, lo1);
+        U32x4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 64-bit word number `attempt` of stream (key; c0, c1, c2, tag): the Philox
+// counter is (c0, c1, c2, attempt << 4 | tag) and the word is out.y:out.x.
+AGIS_HD uint64_t stream_word(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag,
+                             uint32_t attempt) {
+    U32x4 c{c0, c1, c2, (attempt << 4) | (tag & 0xFu)};
+    U32x4 o = philox4x32_10(c, k0, k1);
+    return ((uint64_t)o.y << 32) | (uint64_t)o.x;
+}
+
+AGIS_HD uint64_t mul64hi(uint64_t a, uint64_t b) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * (unsigned __int128)b) >> 64);
+#endif
+}
+
+// Uniform integer in [0, range) (range >= 1) by Lemire's multiply-shift with
+// rejection (ACM TOMACS 2019): accept word x when the low half of x*range is
+// at least 2^64 mod range, else take the next attempt of the same stream.
+AGIS_HD uint64_t bounded_draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag,
+                              uint64_t range) {
+    for (uint32_t attempt = 0;; ++attempt) {
+        uint64_t x = stream_word(k0, k1, c0, c1, c2, tag, attempt);
+        uint64_t lo = x * range;
+        // the threshold (2^64 mod range) is below range, so only a low half
+        // under range needs the (slow) modulo
+        if (lo >= range || lo >= (0ull - range) % range) return mul64hi(x, range);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Q16 log2 encoding.  log2fx(x) = (msb(x) << 16) + LOG[next 12 bits of x],
+// LOG[j] = round(2^16 log2(1 + j/4096)).  A candidate with log weight l,
+// when the largest log weight is lmax, gets the integer weight
+// max(1, EXP[(d & 0xffff) >> 4] >> (d >> 16)) with d = lmax - l and
+// EXP[j] = round(2^31 2^(-j/4096)); shifts of 32 or more give the floor 1.
+// ---------------------------------------------------------------------------
+AGIS_HD int32_t log2fx(uint64_t x, const int32_t* logtab) {
+    int p = 63 - __builtin_clzll(x);
+    uint32_t m = p >= 12 ? (uint32_t)((x >> (p - 12)) & 0xFFFu) : (uint32_t)((x << (12 - p)) & 0xFFFu);
+    return (int32_t)(p << 16) + logtab[m];
+}
+
+AGIS_HD uint32_t weight_from_log(int32_t lmax, int32_t l, const uint32_t* exp2tab) {
+    uint32_t delta = (uint32_t)(lmax - l);
+    uint32_t sh = delta >> 16;
+    uint32_t q = sh >= 32u ? 0u : (exp2tab[(delta & 0xFFFFu) >> 4] >> sh);
+    return q < 1u ? 1u : q;
+}
+
+// ---------------------------------------------------------------------------
+// Structs passed to kernels by value.
+// ---------------------------------------------------------------------------
+struct DevGraph {
+    const uint64_t* off;
+    const uint32_t* nbr;
+    uint64_t n;
+    uint64_t nnz;
+};
+
+// Per-vertex record: x = degree, y = LA (Q16 log2 of S2/d), z = LC (Q16
+// log2 of C_v, clamped), w = unused.
+struct DevTables {
+    const uint4* rec;
+};
+
+struct DevPlan {
+    uint32_t k;
+    uint32_t pattern_id;
+    uint8_t bmask[kMaxK];
+    uint8_t b[kMaxK];
+    uint8_t f1[kMaxK];
+    uint8_t ie[kMaxK];
+    uint8_t f2[kMaxK];
+    uint8_t weighted[kMaxK];  // 1: draw from integer weights; 0: uniform draw
+    const int32_t* lt[kMaxK]; // learned log weights per step, or nullptr
+};
+
+struct Step1 {
+    const uint32_t* q1;   // integer weight of every vertex
+    const uint64_t* pre;  // inclusive prefix of q1
+    uint64_t total;
+};
+
+// Welford/Chan accumulator of the sample weights of one workgroup.
+struct Partial {
+    double n;
+    double mean;
+    double m2;
+    double nonzero;
+};
+
+struct Record {
+    uint32_t v[kMaxK];
+    uint64_t num[kMaxK];
+    uint64_t den[kMaxK];
+    double x;
+    int32_t steps;
+    int32_t fail_step;
+};
+
+}  // namespace agis

@@ -1,0 +1,82 @@
+// Internal interfaces between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "agis.h"
+#include "agis_common.h"
+
+struct agis_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int num_cus = 256;
+    // reusable device buffers
+    agis::DevPlan* d_plan = nullptr;
+    agis::Partial* d_partials = nullptr;
+    size_t partials_cap = 0;
+    void* d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    void* d_small = nullptr;  // 4 KiB of flags / reduction cells
+    uint64_t* d_blocksums = nullptr;
+    size_t blocksums_cap = 0;
+};
+
+struct agis_graph {
+    agis_ctx* ctx = nullptr;
+    agis::DevGraph g{};
+    uint32_t max_deg = 0;
+};
+
+struct agis_tables {
+    agis_ctx* ctx = nullptr;
+    const agis_graph* graph = nullptr;
+    uint4* rec = nullptr;      // {deg, LA, LC, 0}
+    uint64_t* s2 = nullptr;
+    uint64_t* hits = nullptr;
+    uint64_t* trials = nullptr;
+};
+
+namespace agis {
+
+int compile_plan(const agis_pattern* p, const uint8_t* order, int mode, int beta_num, int beta_den,
+                 agis_plan* out, std::string* err);
+
+// Host copies of the Q16 tables (generated on first use) and their upload
+// into the device constant tables of this library.
+const int32_t* host_logtab();
+const uint32_t* host_exp2tab();
+hipError_t upload_fixed_point_tables(hipStream_t stream);
+
+// Kernels launchers (all asynchronous on `stream`).
+// Row checks (offsets monotone and within nnz) must pass before the edge
+// checks run: the edge checks index rows through the offsets.
+hipError_t launch_validate_rows(const DevGraph& g, uint32_t* d_flags, hipStream_t stream);
+hipError_t launch_validate_edges(const DevGraph& g, uint32_t* d_flags, hipStream_t stream);
+hipError_t launch_max_degree(const DevGraph& g, uint32_t* d_max, hipStream_t stream);
+hipError_t launch_build_tables(const DevGraph& g, uint4* rec, uint64_t* s2, uint64_t* hits, uint64_t* trials,
+                               uint32_t k0, uint32_t k1, int32_t lc_min, int exact, hipStream_t stream);
+hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg, int32_t* la, int32_t* lc,
+                                hipStream_t stream);
+
+// First-step table for step 0 of `plan` (host copy `hp`): q1, inclusive
+// prefix pre, total copied into *total (synchronises the stream).
+hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
+                       uint32_t* q1, uint64_t* pre, uint64_t* total);
+
+struct SampleLaunch {
+    int blocks = 0;
+    int threads = 256;
+    uint64_t cap = 0;  // scratch entries per wave
+};
+
+SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t count, std::string* err, int* rc);
+
+hipError_t launch_sample(const SampleLaunch& L, const DevGraph& g, const DevTables& t, const DevPlan* d_plan,
+                         const Step1& s1, uint32_t k0, uint32_t k1, uint64_t start, uint64_t count,
+                         const uint64_t* idx, Record* dump, void* scratch, Partial* partials, hipStream_t stream);
+
+}  // namespace agis

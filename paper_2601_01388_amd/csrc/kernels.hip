@@ -1,0 +1,768 @@
+// gfx950 kernels of the AGIS library: CSR validation, per-vertex proposal
+// tables (Sec. 4.4), the first-step proposal over all vertices, and the
+// sampling kernel (Algorithm 3) with its estimator partials (Algorithm 1).
+//
+// Execution model of the sampler: one 64-lane wavefront owns one sample at
+// a time.  Control flow is wave-uniform (every lane holds the same matched
+// prefix, factors and weight); the lanes cooperate on the data-parallel
+// parts of a step: the 64-ary searches of the first step, the probes of
+// already-matched vertices, and the chunked walk over the shortest
+// backward neighbour list that builds the candidate set, its integer
+// weights and the prefix pick.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "agis_internal.h"
+
+namespace agis {
+
+__constant__ int32_t c_logtab[4096];
+__constant__ uint32_t c_exp2tab[4096];
+
+namespace {
+std::vector<int32_t> g_logtab;
+std::vector<uint32_t> g_exp2tab;
+
+void ensure_host_tables() {
+    if (!g_logtab.empty()) return;
+    g_logtab.resize(4096);
+    g_exp2tab.resize(4096);
+    for (int j = 0; j < 4096; ++j) {
+        const double frac = (double)j / 4096.0;
+        g_logtab[j] = (int32_t)std::llround(65536.0 * std::log2(1.0 + frac));
+        g_exp2tab[j] = (uint32_t)std::llround(2147483648.0 * std::exp2(-frac));
+    }
+}
+}  // namespace
+
+const int32_t* host_logtab() {
+    ensure_host_tables();
+    return g_logtab.data();
+}
+
+const uint32_t* host_exp2tab() {
+    ensure_host_tables();
+    return g_exp2tab.data();
+}
+
+hipError_t upload_fixed_point_tables(hipStream_t stream) {
+    ensure_host_tables();
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_logtab), g_logtab.data(), 4096 * sizeof(int32_t), 0,
+                                          hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_exp2tab), g_exp2tab.data(), 4096 * sizeof(uint32_t), 0,
+                               hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(stream);
+}
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+    uint32_t lo = readlane_u32((uint32_t)v, l);
+    uint32_t hi = readlane_u32((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        int32_t w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint64_t w = __shfl_up(v, d, kWave);
+        if (lane >= d) v += w;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// lower bound of x in a sorted list: first position with list[pos] >= x
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ list, uint32_t len, uint32_t x) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (list[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool contains_u32(const uint32_t* __restrict__ list, uint32_t len, uint32_t x) {
+    uint32_t p = lower_bound_u32(list, len, x);
+    return p < len && list[p] == x;
+}
+
+// Row of edge slot e: the vertex v with off[v] <= e < off[v + 1].
+__device__ __forceinline__ uint32_t row_of_slot(const uint64_t* __restrict__ off, uint64_t n, uint64_t e) {
+    uint64_t lo = 0, hi = n;  // first v with off[v + 1] > e
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (off[mid + 1] > e)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return (uint32_t)lo;
+}
+
+// Wave-cooperative 64-ary search: first index p in [0, n) with a[p] > r,
+// given a non-decreasing and a[n - 1] > r.  Every lane returns the answer.
+__device__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r) {
+    const int lane = lane_id();
+    uint64_t lo = 0, hi = n - 1;  // answer in [lo, hi], a[hi] > r
+    while (hi - lo + 1 > (uint64_t)kWave) {
+        const uint64_t step = (hi - lo + kWave) >> 6;
+        const uint64_t p = lo + (uint64_t)lane * step;
+        const bool valid = p <= hi;
+        const bool pred = valid && a[p] > r;
+        const uint64_t m = __ballot(pred);
+        if (m == 0) {
+            const uint64_t vm = __ballot(valid);
+            const int last = 63 - __clzll(vm);
+            lo = lo + (uint64_t)last * step + 1;
+        } else {
+            const int f = __ffsll((unsigned long long)m) - 1;
+            const uint64_t nh = lo + (uint64_t)f * step;
+            if (f > 0) lo = lo + (uint64_t)(f - 1) * step + 1;
+            hi = nh;
+        }
+    }
+    const uint64_t p = lo + (uint64_t)lane;
+    const bool pred = p <= hi && a[p] > r;
+    const uint64_t m = __ballot(pred);
+    return lo + (uint64_t)(__ffsll((unsigned long long)m) - 1);
+}
+
+__device__ __forceinline__ int32_t approx_log_weight(uint4 rec, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2) {
+    const uint32_t d = rec.x;
+    if (d < b + f1) return kCertainZero;
+    int32_t l = 0;
+    for (uint32_t t = 0; t < f1; ++t) l += log2fx((uint64_t)(d - b - t), c_logtab);
+    l += (int32_t)ie * (int32_t)rec.z;
+    l += (int32_t)f2 * (int32_t)rec.y;
+    return l;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// CSR validation and max degree
+// ---------------------------------------------------------------------------
+__global__ void k_validate_rows(DevGraph g, uint32_t* flags) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    if (g.off[v + 1] < g.off[v] || g.off[v + 1] > g.nnz) atomicOr(flags, 1u);
+}
+
+__global__ void k_validate_edges(DevGraph g, uint32_t* flags) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.nnz) return;
+    const uint32_t v = row_of_slot(g.off, g.n, e);
+    if (v >= g.n) {
+        atomicOr(flags, 1u);
+        return;
+    }
+    // offsets were checked (monotone, within nnz) by k_validate_rows first
+    const uint32_t x = g.nbr[e];
+    uint32_t f = 0;
+    if ((uint64_t)x >= g.n) {
+        atomicOr(flags, 2u);
+        return;
+    }
+    if (x == v) f |= 4u;
+    if (e + 1 < g.off[v + 1] && g.nbr[e + 1] <= x) f |= 8u;
+    const uint64_t o = g.off[x];
+    const uint64_t d = g.off[x + 1] - o;
+    if (d > 0xFFFFFFFFull || !contains_u32(g.nbr + o, (uint32_t)d, v)) f |= 16u;
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_max_degree(DevGraph g, uint32_t* out) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t d = v < g.n ? (uint32_t)(g.off[v + 1] - g.off[v]) : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t w = __shfl_xor(d, o, kWave);
+        d = w > d ? w : d;
+    }
+    if (lane_id() == 0 && d) atomicMax(out, d);
+}
+
+static unsigned grid_for(uint64_t n, unsigned threads) { return (unsigned)((n + threads - 1) / threads); }
+
+hipError_t launch_validate_rows(const DevGraph& g, uint32_t* d_flags, hipStream_t stream) {
+    if (g.n) hipLaunchKernelGGL(k_validate_rows, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_edges(const DevGraph& g, uint32_t* d_flags, hipStream_t stream) {
+    if (g.nnz) hipLaunchKernelGGL(k_validate_edges, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_degree(const DevGraph& g, uint32_t* d_max, hipStream_t stream) {
+    if (g.n) hipLaunchKernelGGL(k_max_degree, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, d_max);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-vertex proposal tables (Sec. 4.4)
+// ---------------------------------------------------------------------------
+__global__ void k_tables_init(DevGraph g, uint4* rec, uint64_t* s2, uint64_t* hits) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    rec[v] = make_uint4((uint32_t)(g.off[v + 1] - g.off[v]), 0u, 0u, 0u);
+    s2[v] = 0;
+    hits[v] = 0;
+}
+
+// One thread per edge slot (v, x): adds d(x) to S2(v) and, for the sampled
+// clustering coefficient, runs trial t = slot - off[v] of vertex v: an
+// ordered pair (a, b) of distinct neighbour positions from Philox key
+// cv_seed, counter (v, t, 0, tag 0 / tag 1), a hit when the two neighbours
+// are adjacent.  For the exact coefficient, counts the neighbours z > x of v
+// that are adjacent to x (each edge among N(v) once).
+__global__ void k_tables_edges(DevGraph g, const uint4* rec, uint64_t* s2, uint64_t* hits, uint32_t k0, uint32_t k1,
+                               int exact) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.nnz) return;
+    const uint32_t v = row_of_slot(g.off, g.n, e);
+    const uint32_t x = g.nbr[e];
+    const uint64_t ov = g.off[v];
+    const uint32_t d = rec[v].x;
+    atomicAdd((unsigned long long*)&s2[v], (unsigned long long)rec[x].x);
+    if (d < 2) return;
+    const uint32_t* row = g.nbr + ov;
+    uint32_t h = 0;
+    if (!exact) {
+        const uint32_t t = (uint32_t)(e - ov);
+        const uint64_t a = bounded_draw(k0, k1, v, t, 0, 0, d);
+        uint64_t b = bounded_draw(k0, k1, v, t, 0, 1, d - 1);
+        if (b >= a) ++b;
+        const uint32_t y = row[a], z = row[b];
+        const uint64_t oy = g.off[y];
+        h = contains_u32(g.nbr + oy, (uint32_t)(g.off[y + 1] - oy), z) ? 1u : 0u;
+    } else {
+        const uint64_t ox = g.off[x];
+        const uint32_t dx = (uint32_t)(g.off[x + 1] - ox);
+        for (uint32_t p = lower_bound_u32(row, d, x + 1); p < d; ++p)
+            if (contains_u32(g.nbr + ox, dx, row[p])) ++h;
+    }
+    if (h) atomicAdd((unsigned long long*)&hits[v], (unsigned long long)h);
+}
+
+__global__ void k_tables_finalize(DevGraph g, uint4* rec, const uint64_t* s2, const uint64_t* hits, uint64_t* trials,
+                                  int32_t lc_min, int exact) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    uint4 r = rec[v];
+    const uint64_t d = r.x;
+    const uint64_t t = d < 2 ? 0 : (exact ? d * (d - 1) / 2 : d);
+    trials[v] = t;
+    const int32_t la = d >= 1 ? log2fx(s2[v], c_logtab) - log2fx(d, c_logtab) : 0;
+    int32_t lc = lc_min;
+    const uint64_t h = hits[v];
+    if (d >= 2 && h > 0) {
+        const int32_t c = log2fx(h, c_logtab) - log2fx(t, c_logtab);
+        lc = c > lc_min ? c : lc_min;
+    }
+    r.y = (uint32_t)la;
+    r.z = (uint32_t)lc;
+    rec[v] = r;
+}
+
+hipError_t launch_build_tables(const DevGraph& g, uint4* rec, uint64_t* s2, uint64_t* hits, uint64_t* trials,
+                               uint32_t k0, uint32_t k1, int32_t lc_min, int exact, hipStream_t stream) {
+    if (!g.n) return hipSuccess;
+    hipLaunchKernelGGL(k_tables_init, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, rec, s2, hits);
+    if (g.nnz)
+        hipLaunchKernelGGL(k_tables_edges, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, rec, s2, hits, k0,
+                           k1, exact);
+    hipLaunchKernelGGL(k_tables_finalize, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, rec, s2, hits, trials,
+                       lc_min, exact);
+    return hipGetLastError();
+}
+
+__global__ void k_tables_export(const uint4* rec, uint64_t n, uint32_t* deg, int32_t* la, int32_t* lc) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const uint4 r = rec[v];
+    if (deg) deg[v] = r.x;
+    if (la) la[v] = (int32_t)r.y;
+    if (lc) lc[v] = (int32_t)r.z;
+}
+
+hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg, int32_t* la, int32_t* lc,
+                                hipStream_t stream) {
+    if (n && (deg || la || lc))
+        hipLaunchKernelGGL(k_tables_export, dim3(grid_for(n, 256)), dim3(256), 0, stream, t.rec, n, deg, la, lc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// First-step proposal over all vertices (the step-1 "cumulative
+// distribution" of the paper): log weights, their maximum, integer weights
+// and an inclusive 64-bit prefix, in three passes.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int32_t step0_log(const uint4* rec, const DevPlan& P, uint64_t v) {
+    const uint4 r = rec[v];
+    if (r.x < (uint32_t)P.f1[0]) return kCertainZero;
+    if (P.lt[0]) return P.lt[0][v];
+    return approx_log_weight(r, 0, P.f1[0], P.ie[0], P.f2[0]);
+}
+}  // namespace
+
+__global__ void k_step1_max(const uint4* rec, DevPlan P, uint64_t n, int32_t* lmax) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t l = kCertainZero;
+    if (v < n) l = step0_log(rec, P, v);
+    l = wave_max_i32(l);
+    if (lane_id() == 0 && l != kCertainZero) atomicMax(lmax, l);
+}
+
+__device__ __forceinline__ uint32_t step0_weight(const uint4* rec, const DevPlan& P, uint64_t v, int32_t lmax) {
+    const int32_t l = step0_log(rec, P, v);
+    return l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_step1_tilesum(const uint4* rec, DevPlan P, uint64_t n,
+                                                                 const int32_t* lmax_p, uint64_t* tile_sums) {
+    const int32_t lmax = *lmax_p;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t v = base + (uint64_t)j * kScanThreads + threadIdx.x;
+        if (v < n) s += step0_weight(rec, P, v, lmax);
+    }
+    s = wave_sum_u64(s);
+    __shared__ uint64_t ws[kScanThreads / kWave];
+    if (lane_id() == 0) ws[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) t += ws[w];
+        tile_sums[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the tile sums in place by one workgroup.
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint64_t* tile_sums, uint64_t ntiles) {
+    __shared__ uint64_t part[1024];
+    const uint64_t per = (ntiles + 1023) / 1024;
+    const uint64_t b = threadIdx.x * per;
+    uint64_t s = 0;
+    for (uint64_t j = 0; j < per && b + j < ntiles; ++j) s += tile_sums[b + j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t run = 0;
+        for (int j = 0; j < 1024; ++j) {
+            uint64_t t = part[j];
+            part[j] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    uint64_t run = part[threadIdx.x];
+    for (uint64_t j = 0; j < per && b + j < ntiles; ++j) {
+        uint64_t t = tile_sums[b + j];
+        tile_sums[b + j] = run;
+        run += t;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_step1_final(const uint4* rec, DevPlan P, uint64_t n,
+                                                               const int32_t* lmax_p, const uint64_t* tile_offs,
+                                                               uint32_t* q1, uint64_t* pre) {
+    const int32_t lmax = *lmax_p;
+    // thread t owns items [t*kScanItems, (t+1)*kScanItems) of the tile
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t q[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t v = base + j;
+        q[j] = v < n ? step0_weight(rec, P, v, lmax) : 0u;
+        s += q[j];
+    }
+    // exclusive scan of thread sums across the workgroup
+    uint64_t incl = wave_incl_scan_u64(s);
+    __shared__ uint64_t wsum[kScanThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (int j = 0; j < w; ++j) wbase += wsum[j];
+    uint64_t run = tile_offs[blockIdx.x] + wbase + incl - s;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t v = base + j;
+        if (v < n) {
+            run += q[j];
+            q1[v] = q[j];
+            pre[v] = run;
+        }
+    }
+}
+
+hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp, uint32_t* q1,
+                       uint64_t* pre, uint64_t* total) {
+    const uint64_t n = g.g.n;
+    hipStream_t st = ctx->stream;
+    int32_t* d_lmax = (int32_t*)ctx->d_small;
+    const int32_t init = kCertainZero;
+    hipError_t e = hipMemcpyAsync(d_lmax, &init, sizeof(init), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ctx->blocksums_cap < ntiles) {
+        if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
+        ctx->d_blocksums = nullptr;
+        e = hipMalloc(&ctx->d_blocksums, ntiles * sizeof(uint64_t));
+        if (e != hipSuccess) return e;
+        ctx->blocksums_cap = ntiles;
+    }
+    hipLaunchKernelGGL(k_step1_max, dim3(grid_for(n, 256)), dim3(256), 0, st, t.rec, hp, n, d_lmax);
+    hipLaunchKernelGGL(k_step1_tilesum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, t.rec, hp, n, d_lmax,
+                       ctx->d_blocksums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, ctx->d_blocksums, ntiles);
+    hipLaunchKernelGGL(k_step1_final, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, t.rec, hp, n, d_lmax,
+                       ctx->d_blocksums, q1, pre);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(total, pre + (n - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+// ---------------------------------------------------------------------------
+// Sampling kernel
+// ---------------------------------------------------------------------------
+namespace {
+
+// In-order sample: returns its weight X; lane 0 writes the record when
+// rec != nullptr.  `my_tau` of lane j holds the data vertex matched at step
+// j (wave-uniform by construction).  sv/sl: this wave's scratch for the
+// candidate vertices and their log weights (capacity >= max degree).
+__device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P, const Step1& s1,
+                             uint32_t k0, uint32_t k1, uint64_t s, uint32_t* __restrict__ sv,
+                             int32_t* __restrict__ sl, Record* __restrict__ rec) {
+    const int lane = lane_id();
+    const uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = P->pattern_id;
+    const uint32_t k = P->k;
+    uint32_t my_tau = 0;
+    double x = 1.0;
+    int fail = -1;
+    uint32_t i = 0;
+    for (; i < k; ++i) {
+        uint64_t num, den;
+        uint32_t v;
+        if (i == 0) {
+            if (P->weighted[0]) {
+                if (s1.total == 0) {
+                    fail = 0;
+                    break;
+                }
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, s1.total);
+                v = (uint32_t)wave_first_greater(s1.pre, g.n, r);
+                num = s1.total;
+                den = s1.q1[v];
+            } else {
+                if (g.nnz == 0) {
+                    fail = 0;
+                    break;
+                }
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, g.nnz);
+                v = (uint32_t)wave_first_greater(g.off + 1, g.n, r);
+                num = g.nnz;
+                den = g.off[v + 1] - g.off[v];
+            }
+            x = (double)num / (double)den;
+        } else {
+            const uint32_t bm = P->bmask[i];
+            const bool weighted = P->weighted[i] != 0;
+            if (!weighted && __builtin_popcount(bm) == 1) {
+                // Uniform draw from N(w) minus the matched vertices, without
+                // materialising the set: probe each matched vertex in N(w)
+                // and skip the positions found.
+                const uint32_t w = readlane_u32(my_tau, __builtin_ctz(bm));
+                const uint64_t o = g.off[w];
+                const uint32_t d = (uint32_t)(g.off[w + 1] - o);
+                const uint32_t* list = g.nbr + o;
+                uint32_t pos = 0xFFFFFFFFu;
+                bool found = false;
+                if ((uint32_t)lane < i) {
+                    pos = lower_bound_u32(list, d, my_tau);
+                    found = pos < d && list[pos] == my_tau;
+                }
+                const uint32_t ex = (uint32_t)__popcll(__ballot(found));
+                const uint64_t m = (uint64_t)d - ex;
+                if (m == 0) {
+                    fail = (int)i;
+                    break;
+                }
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, m);
+                uint64_t idx = r;
+                for (;;) {
+                    const uint64_t c = (uint64_t)__popcll(__ballot(found && (uint64_t)pos <= idx));
+                    if (r + c == idx) break;
+                    idx = r + c;
+                }
+                v = list[idx];
+                num = m;
+                den = 1;
+            } else {
+                // Candidate set: walk the shortest backward list in chunks of
+                // 64, keep elements present in every other backward list.
+                uint64_t my_o = 0;
+                uint32_t my_d = 0xFFFFFFFFu;
+                if ((uint32_t)lane < i && (bm >> lane & 1u)) {
+                    my_o = g.off[my_tau];
+                    my_d = (uint32_t)(g.off[my_tau + 1] - my_o);
+                }
+                // base = smallest degree, ties to the smallest position
+                uint64_t key = ((uint64_t)my_d << 8) | (uint64_t)lane;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    uint64_t w2 = __shfl_xor(key, o, kWave);
+                    key = w2 < key ? w2 : key;
+                }
+                const int jb = (int)(key & 0xFF);
+                const uint64_t ob = readlane_u64(my_o, jb);
+                const uint32_t db = readlane_u32(my_d, jb);
+                const uint32_t others = bm & ~(1u << jb);
+                const uint32_t b = P->b[i], f1 = P->f1[i], ie = P->ie[i], f2 = P->f2[i];
+                const int32_t* lt = P->lt[i];
+                uint64_t cnt = 0;
+                int32_t lmax_l = kCertainZero;
+                for (uint32_t c = 0; c < db; c += kWave) {
+                    const uint32_t pidx = c + (uint32_t)lane;
+                    const bool valid = pidx < db;
+                    const uint32_t xv = valid ? g.nbr[ob + pidx] : 0u;
+                    bool member = valid;
+                    for (uint32_t bits = others; bits; bits &= bits - 1) {
+                        const int j = __builtin_ctz(bits);
+                        const uint64_t oj = readlane_u64(my_o, j);
+                        const uint32_t dj = readlane_u32(my_d, j);
+                        if (member) member = contains_u32(g.nbr + oj, dj, xv);
+                    }
+                    int32_t l = kCertainZero;
+                    if (weighted && member) {
+                        const uint4 r = t.rec[xv];
+                        if (r.x >= b + f1) l = lt ? lt[xv] : approx_log_weight(r, b, f1, ie, f2);
+                        if (l != kCertainZero && l > lmax_l) lmax_l = l;
+                    }
+                    bool in_tau = false;
+                    for (uint32_t j = 0; j < i; ++j) in_tau |= (xv == readlane_u32(my_tau, (int)j));
+                    const bool keep = member && !in_tau;
+                    const uint64_t km = __ballot(keep);
+                    if (keep) {
+                        const uint64_t p = cnt + (uint64_t)__popcll(km & lanemask_lt());
+                        sv[p] = xv;
+                        sl[p] = l;
+                    }
+                    cnt += (uint64_t)__popcll(km);
+                }
+                __threadfence_block();
+                if (!weighted) {
+                    if (cnt == 0) {
+                        fail = (int)i;
+                        break;
+                    }
+                    const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, cnt);
+                    v = sv[r];
+                    num = cnt;
+                    den = 1;
+                } else {
+                    const int32_t lmax = wave_max_i32(lmax_l);
+                    uint64_t qs = 0;
+                    for (uint64_t c = (uint64_t)lane; c < cnt; c += kWave) {
+                        const int32_t l = sl[c];
+                        qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+                    }
+                    const uint64_t Q = wave_sum_u64(qs);
+                    if (Q == 0) {
+                        fail = (int)i;
+                        break;
+                    }
+                    const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
+                    uint64_t run = 0;
+                    v = 0;
+                    den = 0;
+                    for (uint64_t c0i = 0; c0i < cnt; c0i += kWave) {
+                        const uint64_t c = c0i + (uint64_t)lane;
+                        uint32_t q = 0;
+                        if (c < cnt) {
+                            const int32_t l = sl[c];
+                            q = l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+                        }
+                        const uint64_t incl = wave_incl_scan_u64((uint64_t)q);
+                        const uint64_t tot = readlane_u64(incl, kWave - 1);
+                        if (run + tot > r) {
+                            const uint64_t hm = __ballot(run + incl > r);
+                            const int L = __ffsll((unsigned long long)hm) - 1;
+                            v = sv[c0i + (uint64_t)L];
+                            den = readlane_u32(q, L);
+                            break;
+                        }
+                        run += tot;
+                    }
+                    num = Q;
+                }
+            }
+            x = x * ((double)num / (double)den);
+        }
+        if ((uint32_t)lane == i) my_tau = v;
+        if (rec && lane == 0) {
+            rec->v[i] = v;
+            rec->num[i] = num;
+            rec->den[i] = den;
+        }
+    }
+    if (fail >= 0) x = 0.0;
+    if (rec && lane == 0) {
+        for (uint32_t j = i; j < (uint32_t)kMaxK; ++j) {
+            rec->v[j] = 0;
+            rec->num[j] = 0;
+            rec->den[j] = 0;
+        }
+        rec->x = x;
+        rec->steps = (int32_t)i;
+        rec->fail_step = fail;
+    }
+    return x;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_sample(DevGraph g, DevTables t, const DevPlan* __restrict__ P, Step1 s1,
+                                                 uint32_t k0, uint32_t k1, uint64_t start, uint64_t count,
+                                                 const uint64_t* __restrict__ idx, Record* __restrict__ dump,
+                                                 uint32_t* __restrict__ scratch, uint64_t cap,
+                                                 Partial* __restrict__ partials) {
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const uint64_t gw = (uint64_t)blockIdx.x * wpb + wib;
+    const uint64_t nw = (uint64_t)gridDim.x * wpb;
+    uint32_t* sv = scratch + gw * cap * 2;
+    int32_t* sl = (int32_t*)(sv + cap);
+    double wn = 0.0, wmean = 0.0, wm2 = 0.0, wnz = 0.0;
+    for (uint64_t j = gw; j < count; j += nw) {
+        const uint64_t s = idx ? idx[j] : start + j;
+        const double xv = sample_one(g, t, P, s1, k0, k1, s, sv, sl, dump ? dump + j : nullptr);
+        wn += 1.0;
+        const double d = xv - wmean;
+        wmean += d / wn;
+        wm2 += d * (xv - wmean);
+        wnz += xv != 0.0 ? 1.0 : 0.0;
+    }
+    __shared__ Partial sp[1024 / kWave];
+    if (lane == 0) sp[wib] = Partial{wn, wmean, wm2, wnz};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Partial a = sp[0];
+        for (int w = 1; w < wpb; ++w) {
+            const Partial b = sp[w];
+            if (b.n == 0.0) continue;
+            if (a.n == 0.0) {
+                a = b;
+                continue;
+            }
+            const double n = a.n + b.n;
+            const double delta = b.mean - a.mean;
+            a.mean = a.mean + delta * (b.n / n);
+            a.m2 = a.m2 + b.m2 + delta * delta * (a.n * b.n / n);
+            a.n = n;
+            a.nonzero += b.nonzero;
+        }
+        partials[blockIdx.x] = a;
+    }
+}
+
+SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t count, std::string* err, int* rc) {
+    SampleLaunch L;
+    L.threads = 256;
+    L.cap = (uint64_t)g.max_deg + 1;
+    const uint64_t per_wave = L.cap * 2 * sizeof(uint32_t);
+    const uint64_t budget = 8ull << 30;  // scratch budget
+    uint64_t waves = (uint64_t)ctx->num_cus * 32;  // 8 waves per SIMD
+    if (waves * per_wave > budget) waves = budget / per_wave;
+    if (waves < 4) {
+        *err = "maximum degree too large for the sampler scratch budget";
+        *rc = AGIS_E_UNSUPPORTED;
+        return L;
+    }
+    const uint64_t need = (count + 3) / 4 * 4;
+    if (waves > need) waves = need < 4 ? 4 : need;
+    L.blocks = (int)(waves / 4);
+    const uint64_t bytes = (uint64_t)L.blocks * 4 * per_wave;
+    if (ctx->scratch_bytes < bytes) {
+        if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+        ctx->d_scratch = nullptr;
+        ctx->scratch_bytes = 0;
+        if (hipMalloc(&ctx->d_scratch, bytes) != hipSuccess) {
+            *err = "could not allocate sampler scratch";
+            *rc = AGIS_E_OOM;
+            return L;
+        }
+        ctx->scratch_bytes = bytes;
+    }
+    if (ctx->partials_cap < (size_t)L.blocks) {
+        if (ctx->d_partials) (void)hipFree(ctx->d_partials);
+        ctx->d_partials = nullptr;
+        ctx->partials_cap = 0;
+        if (hipMalloc(&ctx->d_partials, (size_t)L.blocks * sizeof(Partial)) != hipSuccess) {
+            *err = "could not allocate partials";
+            *rc = AGIS_E_OOM;
+            return L;
+        }
+        ctx->partials_cap = (size_t)L.blocks;
+    }
+    *rc = AGIS_OK;
+    return L;
+}
+
+hipError_t launch_sample(const SampleLaunch& L, const DevGraph& g, const DevTables& t, const DevPlan* d_plan,
+                         const Step1& s1, uint32_t k0, uint32_t k1, uint64_t start, uint64_t count, const uint64_t* idx,
+                         Record* dump, void* scratch, Partial* partials, hipStream_t stream) {
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)L.blocks), dim3((unsigned)L.threads), 0, stream, g, t, d_plan, s1, k0,
+                       k1, start, count, idx, dump, (uint32_t*)scratch, L.cap, partials);
+    return hipGetLastError();
+}
+
+}  // namespace agis
