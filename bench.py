@@ -1,0 +1,267 @@
+"""Benchmark of the AGIS sampling estimator on one MI355X.
+
+Workload: R-MAT scale 20 (2^20 vertices, edge factor 16, a=.57 b=.19 c=.19
+d=.05, symmetrised, deduplicated, no self-loops; ~15.7M undirected edges),
+patterns 5-clique, 5-cycle, house and 4-star, f_approx with the paper's
+switching rule (beta = 4/5).  One step = one estimate per pattern over a
+fixed batch of samples (first-step table build included, as the paper
+counts it in mining time).  ``value`` is samples per second over the timed
+steps.  Also reported: time to +-1% relative error at 95% confidence
+(Algorithm 1) per pattern and proposal mode, the roofline of the sampling
+kernel (random-gather bound: HBM), and the CPU oracle timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PATTERNS = ["5-clique", "5-cycle", "house", "4-star"]
+HBM_PEAK_GBS = 8000.0
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sample_rmat20_counters.json")
+KERNEL_SOURCES = ["paper_2601_01388_amd/csrc/kernels.hip", "paper_2601_01388_amd/csrc/agis_common.h"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(g, plan, recs) -> float:
+    """Mean algorithmic HBM bytes per sample of the given records.
+
+    Per sample: 16 B for the first draw (a prefix-table or offsets entry,
+    +4 B for the weight of a weighted first step); for every later step that
+    was reached, either the O(1) uniform single-backward draw -- 16 B of
+    offsets, 4 B for the picked neighbour and 4*ceil(log2(d+1)) B per probe
+    of an already matched vertex -- or, otherwise, the backward lists read
+    in full (16 + 4 d(v_j) B each, merge model of the intersection) plus a
+    16 B per-vertex record for every member of the intersection when the
+    step draws from weights."""
+    off = g.off
+    deg = np.diff(off).astype(np.int64)
+    k = plan.k
+    total = 0.0
+    for r in recs:
+        steps = int(r["steps"])
+        reached = steps + (1 if int(r["fail_step"]) >= 0 else 0)
+        tau = [int(x) for x in r["v"][:steps]]
+        b = 16.0 + (4.0 if plan.decision[0] and plan.f1[0] > 0 else 0.0)
+        for i in range(1, min(reached, k)):
+            bm = plan.bmask[i]
+            weighted = plan.decision[i] and plan.f1[i] > 0
+            js = [j for j in range(i) if bm >> j & 1]
+            if not weighted and len(js) == 1:
+                d = deg[tau[js[0]]]
+                b += 20.0 + i * 4.0 * math.ceil(math.log2(d + 1))
+            else:
+                b += sum(16.0 + 4.0 * deg[tau[j]] for j in js)
+                if weighted:
+                    lists = [g.nbr[off[tau[j]]:off[tau[j] + 1]] for j in js]
+                    inter = lists[0]
+                    for other in lists[1:]:
+                        inter = np.intersect1d(inter, other, assume_unique=True)
+                    b += 16.0 * inter.size
+        total += b
+    return total / max(len(recs), 1)
+
+
+def cpu_baseline(g, seconds_target: float):
+    """The oracle (single thread) on a bounded sample of the same workload:
+    the same patterns and mode, equal sample counts per pattern."""
+    import oracle
+    from oracle.pattern import compile_pattern
+    import synth
+    log("cpu baseline: oracle tables (setup, untimed)")
+    t = oracle.Tables(g, cv_seed=1)
+    samplers = []
+    for name in PATTERNS:
+        p = synth.named_pattern(name)
+        samplers.append(oracle.Sampler(g, t, compile_pattern(p.k, p.edges, mode="switch"), seed=7))
+    # calibrate on a few samples, then size the timed sample
+    per = []
+    for s in samplers:
+        t0 = time.perf_counter()
+        s.run(0, 200)
+        per.append((time.perf_counter() - t0) / 200)
+    n_each = max(200, int(seconds_target / max(sum(per), 1e-9)))
+    log(f"cpu baseline: {n_each} samples per pattern")
+    t0 = time.perf_counter()
+    for s in samplers:
+        s.run(0, n_each)
+    el = time.perf_counter() - t0
+    return {
+        "value": len(PATTERNS) * n_each / el,
+        "unit": "samples/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {n_each} sample indices of each of {', '.join(PATTERNS)} (f_approx+switch, seed 7) "
+                  f"on the same R-MAT-20 graph, single-threaded C oracle, {el:.1f} s",
+        "host": platform.processor() or platform.machine(),
+        "host_threads_available": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--samples", type=int, default=1 << 22, help="samples per pattern per step")
+    ap.add_argument("--eps-budget", type=int, default=10 ** 8, help="sample budget of each run to +-1%%")
+    ap.add_argument("--skip-eps", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--bytes-records", type=int, default=1500)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(samples are independent: more GPUs would split the sample index range)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2601_01388_amd.session import Session
+
+    log("generating R-MAT scale 20")
+    g = synth.rmat(20, 16, seed=20)
+    sess = Session(0)
+    G = sess.graph(g.off, g.nbr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = sess.tables(G, cv_seed=1)
+    torch.cuda.synchronize()
+    tables_s = time.perf_counter() - t0
+    log(f"graph n={g.n} nnz={g.nnz} dmax={int(np.diff(g.off).max())}; tables {tables_s * 1e3:.1f} ms")
+
+    pats = [synth.named_pattern(n) for n in PATTERNS]
+
+    def step(seed):
+        res = []
+        for pid, p in enumerate(pats):
+            res.append(sess.estimate(G, T, p, args.samples, seed, mode="switch", pattern_id=pid))
+        return res
+
+    for w in range(args.warmup):
+        step(1000 + w)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for k in range(args.steps):
+        results.append(step(7 + k))
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total_samples = args.steps * len(pats) * args.samples
+    value = total_samples / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    kern_s = sum(r.sample_kernel_seconds for rs in results for r in rs)
+    launches = sum(r.sample_launches for rs in results for r in rs)
+    per_pattern = {}
+    for pid, name in enumerate(PATTERNS):
+        ks = sum(rs[pid].sample_kernel_seconds for rs in results)
+        per_pattern[name] = {
+            "samples_per_s_kernel": args.steps * args.samples / ks,
+            "estimate": results[-1][pid].estimate,
+            "rel_var": results[-1][pid].variance / max(results[-1][pid].estimate ** 2, 1e-300),
+            "step1_ms": 1e3 * results[-1][pid].step1_seconds,
+        }
+    log(f"timed: {value:.4g} samples/s, {ms_per_step:.1f} ms/step")
+
+    # algorithmic bytes per sample, from dumped records of the timed stream
+    log("algorithmic bytes from sampled records")
+    bytes_per_sample = {}
+    rng = np.random.Generator(np.random.PCG64(3))
+    idx = np.sort(rng.integers(0, args.samples, size=args.bytes_records, dtype=np.uint64))
+    for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
+        recs = sess.dump(G, T, p, 7, idx, mode="switch", pattern_id=pid)
+        bytes_per_sample[name] = algorithmic_bytes(g, results[0][pid].plan, recs)
+    # dominant kernel: the sampling kernel; bytes per launch = samples per
+    # launch x mean bytes per sample (equal sample counts per pattern)
+    mean_bytes = float(np.mean([bytes_per_sample[n] for n in PATTERNS]))
+    avg_launch_s = kern_s / launches
+    achieved_gbs = mean_bytes * args.samples / avg_launch_s / 1e9
+    traffic = None
+    if os.path.exists(COUNTERS_FILE):
+        c = json.load(open(COUNTERS_FILE))
+        if c.get("kernel_source_sha") == kernel_source_hash() and c.get("samples_per_launch") == args.samples:
+            traffic = c.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_sample", "avg_launch_ms": 1e3 * avg_launch_s,
+                "algorithmic_bytes_per_sample": bytes_per_sample}
+
+    # time to +-1% (95% CI) per pattern and proposal mode
+    eps_table = {}
+    if not args.skip_eps:
+        for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
+            for mode in ("switch", "uniform"):
+                r = sess.estimate(G, T, p, args.eps_budget, 11, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
+                                  check_every=1 << 16, min_samples=1 << 14)
+                need = r.n * (r.eps_hat / 0.01) ** 2 if math.isfinite(r.eps_hat) else None
+                eps_table[f"{name}/{'f_approx' if mode == 'switch' else 'f_uniform'}"] = {
+                    "seconds": r.seconds, "converged": bool(r.converged), "samples": r.n, "estimate": r.estimate,
+                    "eps_hat": r.eps_hat, "rel_var": r.variance / max(r.estimate ** 2, 1e-300),
+                    "samples_needed": need,
+                }
+                log(f"+-1% {name} {mode}: {r.seconds:.3f} s, n={r.n}, converged={bool(r.converged)}")
+
+    cpu = None
+    if not args.skip_cpu:
+        cpu = cpu_baseline(g, args.cpu_seconds)
+        log(f"cpu baseline {cpu['value']:.4g} samples/s")
+
+    out = {
+        "metric": "time to ±1% rel. err (95% CI) + samples/s: learned vs f_approx vs uniform",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "R-MAT scale 20 (ef 16, a=.57 b=.19 c=.19), patterns 5-clique/5-cycle/house/4-star, "
+                        "f_approx with switching (beta=4/5)",
+            "samples_per_pattern_per_step": args.samples,
+            "graph": {"n": g.n, "nnz": g.nnz, "seed": 20},
+            "tables_ms": 1e3 * tables_s,
+        },
+        "per_pattern": per_pattern,
+        "time_to_1pct": eps_table,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    T.close()
+    G.close()
+    sess.close()
+
+
+if __name__ == "__main__":
+    main()

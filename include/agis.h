@@ -128,7 +128,9 @@ typedef struct {
  * eps_hat = Algorithm 1's estimated relative error at delta;
  * seconds = wall time from the first GPU launch of the estimate (including
  * the first-step table) to the result; step1_seconds = the first-step
- * table build alone. */
+ * table build alone; sample_kernel_seconds = GPU time of the sampling
+ * kernel launches (HIP events on the context's stream) over
+ * sample_launches launches. */
 typedef struct {
     double estimate;
     double copies;
@@ -140,6 +142,8 @@ typedef struct {
     int32_t converged;
     double seconds;
     double step1_seconds;
+    double sample_kernel_seconds;
+    uint64_t sample_launches;
     agis_plan plan;
 } agis_result;
 

@@ -80,7 +80,8 @@ class agis_result(ctypes.Structure):
         ("estimate", ctypes.c_double), ("copies", ctypes.c_double), ("variance", ctypes.c_double),
         ("eps_hat", ctypes.c_double), ("n", ctypes.c_uint64), ("n_nonzero", ctypes.c_uint64),
         ("aut", ctypes.c_uint32), ("converged", ctypes.c_int32), ("seconds", ctypes.c_double),
-        ("step1_seconds", ctypes.c_double), ("plan", agis_plan),
+        ("step1_seconds", ctypes.c_double), ("sample_kernel_seconds", ctypes.c_double),
+        ("sample_launches", ctypes.c_uint64), ("plan", agis_plan),
     ]
 
 

@@ -23,6 +23,8 @@ struct agis_ctx {
     void* d_small = nullptr;  // 4 KiB of flags / reduction cells
     uint64_t* d_blocksums = nullptr;
     size_t blocksums_cap = 0;
+    hipEvent_t ev_start = nullptr;  // brackets each sampling launch
+    hipEvent_t ev_stop = nullptr;
 };
 
 struct agis_graph {

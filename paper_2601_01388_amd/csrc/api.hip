@@ -160,6 +160,8 @@ int agis_create(agis_ctx** out, int device, void* hip_stream) {
     }
     if (e == hipSuccess) e = hipMalloc(&ctx->d_plan, sizeof(DevPlan));
     if (e == hipSuccess) e = hipMalloc(&ctx->d_small, 4096);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&ctx->ev_stop);
     if (e == hipSuccess) e = agis::upload_fixed_point_tables(ctx->stream);
     if (e != hipSuccess) {
         agis_destroy(ctx);
@@ -177,6 +179,8 @@ void agis_destroy(agis_ctx* ctx) {
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
     if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
+    if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
+    if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
     delete ctx;
 }
 
@@ -308,6 +312,8 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     Acc acc;
     bool converged = false;
     uint64_t done = 0;
+    double kernel_seconds = 0.0;
+    uint64_t launches = 0;
     if (n_samples > 0) {
         agis::SampleLaunch L = agis::plan_sample_launch(ctx, *g, batch < n_samples ? batch : n_samples, &ctx->err, &rc);
         if (rc != AGIS_OK) return rc;
@@ -315,15 +321,21 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
         const agis::DevTables dt{t->rec};
         while (done < n_samples) {
             const uint64_t cnt = (n_samples - done) < batch ? (n_samples - done) : batch;
+            AGIS_HIP(ctx, hipEventRecord(ctx->ev_start, ctx->stream), "record event");
             AGIS_HIP(ctx,
                      agis::launch_sample(L, g->g, dt, ctx->d_plan, prep.s1, (uint32_t)seed, (uint32_t)(seed >> 32),
                                          done, cnt, nullptr, nullptr, ctx->d_scratch, ctx->d_partials, ctx->stream),
                      "launch sampler");
+            AGIS_HIP(ctx, hipEventRecord(ctx->ev_stop, ctx->stream), "record event");
             AGIS_HIP(ctx,
                      hipMemcpyAsync(parts.data(), ctx->d_partials, parts.size() * sizeof(Partial),
                                     hipMemcpyDeviceToHost, ctx->stream),
                      "read partials");
             AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "sampler");
+            float ms = 0.0f;
+            AGIS_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop), "event time");
+            kernel_seconds += 1e-3 * (double)ms;
+            ++launches;
             for (const Partial& q : parts) acc.merge(q);
             done += cnt;
             if (to_eps && done >= pp->min_samples && eps_hat_of(acc, z) <= pp->eps) {
@@ -343,6 +355,8 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     out->converged = converged ? 1 : 0;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     out->step1_seconds = prep.step1_seconds;
+    out->sample_kernel_seconds = kernel_seconds;
+    out->sample_launches = launches;
     out->plan = prep.plan;
     if (to_eps && !converged) return fail(ctx, AGIS_E_NOT_CONVERGED, "sample budget reached before eps");
     return AGIS_OK;
