@@ -126,6 +126,7 @@ struct DevPlan {
     uint8_t ie[kMaxK];
     uint8_t f2[kMaxK];
     uint8_t weighted[kMaxK];  // 1: draw from integer weights; 0: uniform draw
+    uint8_t reuse[kMaxK];     // 1: intersect the previous step's candidate set (see sample_one)
     const int32_t* lt[kMaxK]; // learned log weights per step, or nullptr
 };
 

@@ -121,6 +121,12 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
             hp.lt[i] = params->learned[i];
         }
     }
+    // A step builds its candidate set in the wave's scratch unless it is a
+    // uniform draw with one backward vertex.  When step i-1 did and its
+    // backward set is contained in step i's, step i starts from that set.
+    auto general = [&](uint32_t i) { return hp.weighted[i] || __builtin_popcount(hp.bmask[i]) > 1; };
+    for (uint32_t i = 2; i < hp.k; ++i)
+        hp.reuse[i] = (general(i) && general(i - 1) && (hp.bmask[i - 1] & ~hp.bmask[i]) == 0) ? 1 : 0;
     if (hp.weighted[0] && g->g.n > 0) {
         const auto t0 = std::chrono::steady_clock::now();
         AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");

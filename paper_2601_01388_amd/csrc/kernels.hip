@@ -163,6 +163,61 @@ __device__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t 
     return lo + (uint64_t)(__ffsll((unsigned long long)m) - 1);
 }
 
+// Wave-cooperative: first position p in [lo, hi) with list[p] > key, or hi
+// when there is none (list ascending).
+__device__ uint32_t wave_first_greater_u32(const uint32_t* __restrict__ list, uint32_t lo, uint32_t hi, uint32_t key) {
+    const int lane = lane_id();
+    while (hi - lo > (uint32_t)kWave) {  // answer in [lo, hi]
+        const uint32_t step = (hi - lo + kWave - 1) >> 6;
+        const uint32_t p = lo + (uint32_t)lane * step;
+        const bool valid = p < hi;
+        const uint64_t m = __ballot(valid && list[p] > key);
+        if (m == 0) {
+            const int last = 63 - __clzll(__ballot(valid));
+            lo = lo + (uint32_t)last * step + 1;
+        } else {
+            const int f = __ffsll((unsigned long long)m) - 1;
+            const uint32_t nh = lo + (uint32_t)f * step;
+            if (f > 0) lo = lo + (uint32_t)(f - 1) * step + 1;
+            hi = nh;
+        }
+    }
+    const uint32_t p = lo + (uint32_t)lane;
+    const uint64_t m = __ballot(p < hi && list[p] > key);
+    return m ? lo + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
+}
+
+// One backward list co-iterated with a chunk of ascending base elements
+// (this lane's element xv, the chunk's largest xlast).  Elements of `list`
+// before `pos` are below every element of the chunk, so membership of xv
+// is decided inside the window [pos, end) of elements <= xlast.  A window of
+// at most 64 elements comes from one coalesced load and is searched with
+// register shuffles; a longer one is bounded by a 64-ary wave search and
+// searched per lane.  Clears `member` when xv is absent; returns end, the
+// window start of the next chunk.
+__device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict__ list, uint32_t pos, uint32_t len,
+                                                      uint32_t xv, uint32_t xlast, bool& member) {
+    const int lane = lane_id();
+    const uint32_t p = pos + (uint32_t)lane;
+    const uint32_t val = p < len ? list[p] : 0xFFFFFFFFu;  // ids are < n <= 2^32 - 1
+    const uint64_t gt = __ballot(val > xlast);
+    if (gt != 0) {
+        // the 64 loaded values ascend across lanes: lower bound of xv by shuffles
+        int lo = 0;
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+            const uint32_t pv = __shfl(val, lo + s - 1, kWave);
+            if (pv < xv) lo += s;
+        }
+        const uint32_t cand = __shfl(val, lo, kWave);
+        member = member && cand == xv;
+        return pos + (uint32_t)(__ffsll((unsigned long long)gt) - 1);
+    }
+    const uint32_t end = wave_first_greater_u32(list, pos + kWave, len, xlast);
+    if (member) member = contains_u32(list + pos, end - pos, xv);
+    return end;
+}
+
 __device__ __forceinline__ int32_t approx_log_weight(uint4 rec, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2) {
     const uint32_t d = rec.x;
     if (d < b + f1) return kCertainZero;
@@ -485,6 +540,7 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
     const uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = P->pattern_id;
     const uint32_t k = P->k;
     uint32_t my_tau = 0;
+    uint64_t scnt = 0;  // size of the candidate set the scratch holds
     double x = 1.0;
     int fail = -1;
     uint32_t i = 0;
@@ -546,39 +602,76 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
                 num = m;
                 den = 1;
             } else {
-                // Candidate set: walk the shortest backward list in chunks of
-                // 64, keep elements present in every other backward list.
+                // Candidate set I = intersection of the backward lists, S = I
+                // minus the matched vertices, in ascending id order.  The
+                // walk goes over a base list in chunks of 64; every other
+                // list is co-iterated through a window that only moves
+                // forward (see co_iterate_member).  When the previous step
+                // built its candidate set in the scratch and its backward
+                // set is contained in this one (every step of a clique),
+                // that set (already free of the earlier matched vertices) is
+                // the base and only the new backward lists are intersected.
+                const bool reuse = P->reuse[i] != 0;
+                const uint32_t lists = reuse ? (bm & ~P->bmask[i - 1]) : bm;
                 uint64_t my_o = 0;
                 uint32_t my_d = 0xFFFFFFFFu;
-                if ((uint32_t)lane < i && (bm >> lane & 1u)) {
+                if ((uint32_t)lane < i && (lists >> lane & 1u)) {
                     my_o = g.off[my_tau];
                     my_d = (uint32_t)(g.off[my_tau + 1] - my_o);
                 }
-                // base = smallest degree, ties to the smallest position
-                uint64_t key = ((uint64_t)my_d << 8) | (uint64_t)lane;
+                const uint32_t* base;
+                uint32_t db;
+                uint32_t others;
+                if (reuse) {
+                    base = sv;
+                    db = (uint32_t)scnt;
+                    others = lists;
+                } else {
+                    // base = smallest degree, ties to the smallest position
+                    uint64_t key = ((uint64_t)my_d << 8) | (uint64_t)lane;
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    uint64_t w2 = __shfl_xor(key, o, kWave);
-                    key = w2 < key ? w2 : key;
+                    for (int o = 32; o > 0; o >>= 1) {
+                        uint64_t w2 = __shfl_xor(key, o, kWave);
+                        key = w2 < key ? w2 : key;
+                    }
+                    const int jb = (int)(key & 0xFF);
+                    base = g.nbr + readlane_u64(my_o, jb);
+                    db = readlane_u32(my_d, jb);
+                    others = lists & ~(1u << jb);
                 }
-                const int jb = (int)(key & 0xFF);
-                const uint64_t ob = readlane_u64(my_o, jb);
-                const uint32_t db = readlane_u32(my_d, jb);
-                const uint32_t others = bm & ~(1u << jb);
                 const uint32_t b = P->b[i], f1 = P->f1[i], ie = P->ie[i], f2 = P->f2[i];
                 const int32_t* lt = P->lt[i];
-                uint64_t cnt = 0;
+                const uint32_t vprev = readlane_u32(my_tau, (int)i - 1);
                 int32_t lmax_l = kCertainZero;
+                if (weighted && reuse && (uint32_t)lane + 1 < i) {
+                    // matched vertices were dropped from the reused set; the
+                    // normalising maximum still covers those lying in I
+                    bool in_all = true;
+                    for (uint32_t bits = bm; bits && in_all; bits &= bits - 1) {
+                        const uint32_t w = readlane_u32(my_tau, __builtin_ctz(bits));
+                        const uint64_t o = g.off[w];
+                        in_all = contains_u32(g.nbr + o, (uint32_t)(g.off[w + 1] - o), my_tau);
+                    }
+                    if (in_all) {
+                        const uint4 r = t.rec[my_tau];
+                        if (r.x >= b + f1) lmax_l = lt ? lt[my_tau] : approx_log_weight(r, b, f1, ie, f2);
+                    }
+                }
+                uint32_t my_pos = 0;  // lane j: window start in backward list j
+                uint64_t cnt = 0;
                 for (uint32_t c = 0; c < db; c += kWave) {
-                    const uint32_t pidx = c + (uint32_t)lane;
-                    const bool valid = pidx < db;
-                    const uint32_t xv = valid ? g.nbr[ob + pidx] : 0u;
+                    const uint32_t nvalid = (db - c) < (uint32_t)kWave ? (db - c) : (uint32_t)kWave;
+                    const bool valid = (uint32_t)lane < nvalid;
+                    const uint32_t xv = valid ? base[c + (uint32_t)lane] : 0xFFFFFFFFu;
+                    const uint32_t xlast = readlane_u32(xv, (int)nvalid - 1);
                     bool member = valid;
                     for (uint32_t bits = others; bits; bits &= bits - 1) {
                         const int j = __builtin_ctz(bits);
-                        const uint64_t oj = readlane_u64(my_o, j);
+                        const uint32_t* lj = g.nbr + readlane_u64(my_o, j);
                         const uint32_t dj = readlane_u32(my_d, j);
-                        if (member) member = contains_u32(g.nbr + oj, dj, xv);
+                        const uint32_t pos = readlane_u32(my_pos, j);
+                        const uint32_t end = co_iterate_member(lj, pos, dj, xv, xlast, member);
+                        if (lane == j) my_pos = end;
                     }
                     int32_t l = kCertainZero;
                     if (weighted && member) {
@@ -587,9 +680,15 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
                         if (l != kCertainZero && l > lmax_l) lmax_l = l;
                     }
                     bool in_tau = false;
-                    for (uint32_t j = 0; j < i; ++j) in_tau |= (xv == readlane_u32(my_tau, (int)j));
+                    if (reuse) {
+                        in_tau = xv == vprev;
+                    } else {
+                        for (uint32_t j = 0; j < i; ++j) in_tau |= (xv == readlane_u32(my_tau, (int)j));
+                    }
                     const bool keep = member && !in_tau;
                     const uint64_t km = __ballot(keep);
+                    // in-place compaction is safe when base == sv: every write
+                    // position is below the chunk already held in registers
                     if (keep) {
                         const uint64_t p = cnt + (uint64_t)__popcll(km & lanemask_lt());
                         sv[p] = xv;
@@ -597,6 +696,7 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
                     }
                     cnt += (uint64_t)__popcll(km);
                 }
+                scnt = cnt;
                 __threadfence_block();
                 if (!weighted) {
                     if (cnt == 0) {
