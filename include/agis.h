@@ -108,13 +108,22 @@ typedef struct {
  * check_every: samples between convergence checks (0 = 65536).
  * min_samples: no convergence is declared before this many samples.
  * pattern_id: enters the random stream of every sample (Philox counter).
+ * flags: AGIS_RUN_ROWTAB_* -- whether a weighted step with a single matched
+ *   neighbour draws through per-row pick tables built for this estimate
+ *   (same samples either way; AUTO builds them for runs of >= 65536
+ *   samples when they fit in memory).
  * learned: for AGIS_MODE_LEARNED, per step a device int32[n] table of Q16
  *   log2 weights (NULL for steps that are not weighted); ignored otherwise. */
+#define AGIS_RUN_ROWTAB_AUTO 0u
+#define AGIS_RUN_ROWTAB_ON 1u
+#define AGIS_RUN_ROWTAB_OFF 2u
 typedef struct {
     int32_t mode;
     int32_t beta_num;
     int32_t beta_den;
     uint32_t pattern_id;
+    uint32_t flags;
+    uint32_t reserved;
     double eps;
     double delta;
     uint64_t check_every;
@@ -127,8 +136,9 @@ typedef struct {
  * variance = population variance of X (Algorithm 1's sigma^2);
  * eps_hat = Algorithm 1's estimated relative error at delta;
  * seconds = wall time from the first GPU launch of the estimate (including
- * the first-step table) to the result; step1_seconds = the first-step
- * table build alone; sample_kernel_seconds = GPU time of the sampling
+ * the per-estimate tables) to the result; tables_seconds = building the
+ * per-estimate proposal tables (the first-step distribution over all
+ * vertices and any per-row pick tables); sample_kernel_seconds = GPU time of the sampling
  * kernel launches (HIP events on the context's stream) over
  * sample_launches launches. */
 typedef struct {
@@ -141,7 +151,7 @@ typedef struct {
     uint32_t aut;
     int32_t converged;
     double seconds;
-    double step1_seconds;
+    double tables_seconds;
     double sample_kernel_seconds;
     uint64_t sample_launches;
     agis_plan plan;

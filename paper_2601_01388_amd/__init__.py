@@ -38,6 +38,10 @@ AGIS_MODE_LEARNED = 3
 MODE_BY_NAME = {"uniform": 0, "switch": 1, "always": 2, "learned": 3}
 
 AGIS_CSR_VALIDATE = 1
+AGIS_RUN_ROWTAB_AUTO = 0
+AGIS_RUN_ROWTAB_ON = 1
+AGIS_RUN_ROWTAB_OFF = 2
+ROWTAB_BY_NAME = {"auto": 0, "on": 1, "off": 2}
 LC_MIN_DEFAULT = -10 * 65536
 
 _ERRNAMES = {
@@ -69,7 +73,8 @@ class agis_plan(ctypes.Structure):
 class agis_run_params(ctypes.Structure):
     _fields_ = [
         ("mode", ctypes.c_int32), ("beta_num", ctypes.c_int32), ("beta_den", ctypes.c_int32),
-        ("pattern_id", ctypes.c_uint32), ("eps", ctypes.c_double), ("delta", ctypes.c_double),
+        ("pattern_id", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("eps", ctypes.c_double), ("delta", ctypes.c_double),
         ("check_every", ctypes.c_uint64), ("min_samples", ctypes.c_uint64),
         ("learned", ctypes.c_void_p * MAX_K),
     ]
@@ -80,7 +85,7 @@ class agis_result(ctypes.Structure):
         ("estimate", ctypes.c_double), ("copies", ctypes.c_double), ("variance", ctypes.c_double),
         ("eps_hat", ctypes.c_double), ("n", ctypes.c_uint64), ("n_nonzero", ctypes.c_uint64),
         ("aut", ctypes.c_uint32), ("converged", ctypes.c_int32), ("seconds", ctypes.c_double),
-        ("step1_seconds", ctypes.c_double), ("sample_kernel_seconds", ctypes.c_double),
+        ("tables_seconds", ctypes.c_double), ("sample_kernel_seconds", ctypes.c_double),
         ("sample_launches", ctypes.c_uint64), ("plan", agis_plan),
     ]
 
@@ -190,9 +195,10 @@ def make_pattern(k: int, adj) -> agis_pattern:
 
 
 def make_params(mode="switch", beta=(4, 5), pattern_id=0, eps=0.0, delta=0.05, check_every=0, min_samples=0,
-                learned=None) -> agis_run_params:
+                learned=None, rowtab="auto") -> agis_run_params:
     pr = agis_run_params()
     pr.mode = MODE_BY_NAME[mode] if isinstance(mode, str) else int(mode)
+    pr.flags = ROWTAB_BY_NAME[rowtab] if isinstance(rowtab, str) else int(rowtab)
     pr.beta_num, pr.beta_den = beta
     pr.pattern_id = pattern_id
     pr.eps = eps

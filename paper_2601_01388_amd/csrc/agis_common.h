@@ -128,6 +128,9 @@ struct DevPlan {
     uint8_t weighted[kMaxK];  // 1: draw from integer weights; 0: uniform draw
     uint8_t reuse[kMaxK];     // 1: intersect the previous step's candidate set (see sample_one)
     const int32_t* lt[kMaxK]; // learned log weights per step, or nullptr
+    // per-row inclusive prefixes of a weighted single-backward step's integer
+    // weights (one entry per CSR slot), or nullptr
+    const uint64_t* rowpre[kMaxK];
 };
 
 struct Step1 {

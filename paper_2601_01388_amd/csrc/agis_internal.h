@@ -23,6 +23,9 @@ struct agis_ctx {
     void* d_small = nullptr;  // 4 KiB of flags / reduction cells
     uint64_t* d_blocksums = nullptr;
     size_t blocksums_cap = 0;
+    double* d_xout = nullptr;  // per-sample weights of the current launch
+    uint64_t xout_cap = 0;
+    int sample_blocks_per_cu = 0;
     hipEvent_t ev_start = nullptr;  // brackets each sampling launch
     hipEvent_t ev_stop = nullptr;
 };
@@ -69,16 +72,36 @@ hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg,
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
                        uint32_t* q1, uint64_t* pre, uint64_t* total);
 
+// Per-row pick table (one inclusive u64 prefix over all CSR slots, read per row
+// relative to the entry before the row) of a weighted
+// step with one backward vertex and signature (b, f1, ie, f2) or learned
+// log weights lt.
+// rowmax: n int32 of scratch for the row maxima.
+hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const uint4* rec, uint32_t b, uint32_t f1, uint32_t ie,
+                         uint32_t f2, const int32_t* lt, uint64_t* pre, int32_t* rowmax);
+
 struct SampleLaunch {
     int blocks = 0;
     int threads = 256;
-    uint64_t cap = 0;  // scratch entries per wave
+    uint64_t cap = 0;    // scratch entries per wave
+    uint32_t grab = 1;   // sample slots a wave takes per queue access
+    uint64_t tiles = 0;  // reduction tiles of the weight buffer
 };
 
+// Sizes the persistent grid (resident waves only) and the buffers for a
+// launch of `count` samples.
 SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t count, std::string* err, int* rc);
 
-hipError_t launch_sample(const SampleLaunch& L, const DevGraph& g, const DevTables& t, const DevPlan* d_plan,
+// Samples slots [0, count) (sample index start + slot, or idx[slot]) into
+// ctx->d_xout; dump != nullptr also writes one record per slot.
+// `before`/`after` (may be null) are recorded around the sampling kernel alone.
+hipError_t launch_sample(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t,
                          const Step1& s1, uint32_t k0, uint32_t k1, uint64_t start, uint64_t count,
-                         const uint64_t* idx, Record* dump, void* scratch, Partial* partials, hipStream_t stream);
+                         const uint64_t* idx, Record* dump, hipEvent_t before, hipEvent_t after);
+
+// Per-tile (n, mean, M2, nonzero) of ctx->d_xout[0, count) into ctx->d_partials,
+// one tile per kReduceTileSamples consecutive weights.
+constexpr uint64_t kReduceTileSamples = 2048;
+hipError_t launch_reduce(agis_ctx* ctx, const SampleLaunch& L, uint64_t count);
 
 }  // namespace agis

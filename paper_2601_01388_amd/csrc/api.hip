@@ -93,17 +93,28 @@ struct Prepared {
     agis::Step1 s1{nullptr, nullptr, 0};
     uint32_t* q1 = nullptr;
     uint64_t* pre = nullptr;
-    double step1_seconds = 0;
+    std::vector<uint64_t*> rowtabs;
+    int32_t* rowmax = nullptr;
+    double tables_seconds = 0;
     ~Prepared() {
         if (q1) (void)hipFree(q1);
         if (pre) (void)hipFree(pre);
+        if (rowmax) (void)hipFree(rowmax);
+        for (uint64_t* r : rowtabs) (void)hipFree(r);
     }
 };
 
+// Per-row pick tables are built for runs of at least this many samples
+// (AUTO): their build streams every CSR slot once, which a short run does
+// not amortise.
+constexpr uint64_t kRowtabMinSamples = 65536;
+constexpr uint64_t kRowtabBudgetBytes = 32ull << 30;
+
 int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p, const uint8_t* order,
-            const agis_run_params* params, Prepared* out) {
+            const agis_run_params* params, uint64_t n_samples, Prepared* out) {
     int rc = agis::compile_plan(p, order, params->mode, params->beta_num, params->beta_den, &out->plan, &ctx->err);
     if (rc != AGIS_OK) return rc;
+    if (params->flags > AGIS_RUN_ROWTAB_OFF) return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
     DevPlan& hp = out->hp;
     std::memset(&hp, 0, sizeof(hp));
     hp.k = out->plan.k;
@@ -121,23 +132,58 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
             hp.lt[i] = params->learned[i];
         }
     }
-    // A step builds its candidate set in the wave's scratch unless it is a
-    // uniform draw with one backward vertex.  When step i-1 did and its
-    // backward set is contained in step i's, step i starts from that set.
-    auto general = [&](uint32_t i) { return hp.weighted[i] || __builtin_popcount(hp.bmask[i]) > 1; };
+    const auto t0 = std::chrono::steady_clock::now();
+    // per-row pick tables for weighted steps with one backward vertex
+    bool want_rows = params->flags == AGIS_RUN_ROWTAB_ON ||
+                     (params->flags == AGIS_RUN_ROWTAB_AUTO && n_samples >= kRowtabMinSamples);
+    int32_t* rowmax = nullptr;
+    if (want_rows && g->g.nnz > 0) {
+        struct Key {
+            uint32_t f1, ie, f2;
+            const int32_t* lt;
+            uint64_t* buf;
+        };
+        std::vector<Key> built;
+        for (uint32_t i = 1; i < hp.k; ++i) {
+            if (!hp.weighted[i] || __builtin_popcount(hp.bmask[i]) != 1) continue;
+            uint64_t* buf = nullptr;
+            for (const Key& k : built)
+                if (k.f1 == hp.f1[i] && k.ie == hp.ie[i] && k.f2 == hp.f2[i] && k.lt == hp.lt[i]) buf = k.buf;
+            if (!buf) {
+                if ((built.size() + 1) * g->g.nnz * sizeof(uint64_t) > kRowtabBudgetBytes) continue;
+                AGIS_HIP(ctx, hipMalloc(&buf, g->g.nnz * sizeof(uint64_t)), "allocate row pick table");
+                out->rowtabs.push_back(buf);
+                if (!rowmax) {
+                    AGIS_HIP(ctx, hipMalloc(&rowmax, g->g.n * sizeof(int32_t)), "allocate row maxima");
+                    out->rowmax = rowmax;
+                }
+                AGIS_HIP(ctx,
+                         agis::launch_rowtab(ctx, g->g, t->rec, 1, hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf, rowmax),
+                         "row pick table");
+                built.push_back(Key{hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
+            }
+            hp.rowpre[i] = buf;
+        }
+    }
+    // A step builds its candidate set in the wave's scratch unless it draws
+    // uniformly from one backward list or through a row table.  When step
+    // i-1 did and its backward set is contained in step i's, step i starts
+    // from that set.
+    auto general = [&](uint32_t i) {
+        return (hp.weighted[i] && hp.rowpre[i] == nullptr) || __builtin_popcount(hp.bmask[i]) > 1;
+    };
     for (uint32_t i = 2; i < hp.k; ++i)
         hp.reuse[i] = (general(i) && general(i - 1) && (hp.bmask[i - 1] & ~hp.bmask[i]) == 0) ? 1 : 0;
     if (hp.weighted[0] && g->g.n > 0) {
-        const auto t0 = std::chrono::steady_clock::now();
         AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");
         AGIS_HIP(ctx, hipMalloc(&out->pre, g->g.n * sizeof(uint64_t)), "allocate first-step prefix");
         uint64_t total = 0;
         AGIS_HIP(ctx, agis::build_step1(ctx, *g, *t, hp, out->q1, out->pre, &total), "first-step table");
         out->s1 = agis::Step1{out->q1, out->pre, total};
-        out->step1_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_plan, &hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream), "upload plan");
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "upload plan");
+    out->tables_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return AGIS_OK;
 }
 
@@ -184,6 +230,7 @@ void agis_destroy(agis_ctx* ctx) {
     if (ctx->d_small) (void)hipFree(ctx->d_small);
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+    if (ctx->d_xout) (void)hipFree(ctx->d_xout);
     if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
     if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
     if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
@@ -310,7 +357,7 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
     const auto t0 = std::chrono::steady_clock::now();
     Prepared prep;
-    rc = prepare(ctx, g, t, p, order, pp, &prep);
+    rc = prepare(ctx, g, t, p, order, pp, n_samples, &prep);
     if (rc != AGIS_OK) return rc;
     const bool to_eps = pp->eps > 0;
     const uint64_t batch = to_eps ? (pp->check_every ? pp->check_every : 65536) : n_samples;
@@ -323,16 +370,16 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     if (n_samples > 0) {
         agis::SampleLaunch L = agis::plan_sample_launch(ctx, *g, batch < n_samples ? batch : n_samples, &ctx->err, &rc);
         if (rc != AGIS_OK) return rc;
-        std::vector<Partial> parts((size_t)L.blocks);
+        std::vector<Partial> parts;
         const agis::DevTables dt{t->rec};
         while (done < n_samples) {
             const uint64_t cnt = (n_samples - done) < batch ? (n_samples - done) : batch;
-            AGIS_HIP(ctx, hipEventRecord(ctx->ev_start, ctx->stream), "record event");
             AGIS_HIP(ctx,
-                     agis::launch_sample(L, g->g, dt, ctx->d_plan, prep.s1, (uint32_t)seed, (uint32_t)(seed >> 32),
-                                         done, cnt, nullptr, nullptr, ctx->d_scratch, ctx->d_partials, ctx->stream),
+                     agis::launch_sample(ctx, L, g->g, dt, prep.s1, (uint32_t)seed, (uint32_t)(seed >> 32), done, cnt,
+                                         nullptr, nullptr, ctx->ev_start, ctx->ev_stop),
                      "launch sampler");
-            AGIS_HIP(ctx, hipEventRecord(ctx->ev_stop, ctx->stream), "record event");
+            AGIS_HIP(ctx, agis::launch_reduce(ctx, L, cnt), "launch reduction");
+            parts.resize((size_t)((cnt + agis::kReduceTileSamples - 1) / agis::kReduceTileSamples));
             AGIS_HIP(ctx,
                      hipMemcpyAsync(parts.data(), ctx->d_partials, parts.size() * sizeof(Partial),
                                     hipMemcpyDeviceToHost, ctx->stream),
@@ -360,7 +407,7 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     out->aut = prep.plan.aut;
     out->converged = converged ? 1 : 0;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    out->step1_seconds = prep.step1_seconds;
+    out->tables_seconds = prep.tables_seconds;
     out->sample_kernel_seconds = kernel_seconds;
     out->sample_launches = launches;
     out->plan = prep.plan;
@@ -379,15 +426,15 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     const agis_run_params* pp = params ? params : &dp;
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
     Prepared prep;
-    rc = prepare(ctx, g, t, p, order, pp, &prep);
+    rc = prepare(ctx, g, t, p, order, pp, m, &prep);
     if (rc != AGIS_OK) return rc;
     if (m == 0) return AGIS_OK;
     agis::SampleLaunch L = agis::plan_sample_launch(ctx, *g, m, &ctx->err, &rc);
     if (rc != AGIS_OK) return rc;
     const agis::DevTables dt{t->rec};
     AGIS_HIP(ctx,
-             agis::launch_sample(L, g->g, dt, ctx->d_plan, prep.s1, (uint32_t)seed, (uint32_t)(seed >> 32), 0, m, idx,
-                                 (agis::Record*)out, ctx->d_scratch, ctx->d_partials, ctx->stream),
+             agis::launch_sample(ctx, L, g->g, dt, prep.s1, (uint32_t)seed, (uint32_t)(seed >> 32), 0, m, idx,
+                                 (agis::Record*)out, nullptr, nullptr),
              "launch sampler");
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "sampler");
     return AGIS_OK;

@@ -104,6 +104,35 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// Segments of equal keys in a wave whose keys do not decrease across lanes:
+// head = first lane of this lane's segment, tail = this lane ends it.
+__device__ __forceinline__ void wave_segments(uint32_t key, int& head, bool& tail) {
+    const int lane = lane_id();
+    const uint32_t prev = __shfl_up(key, 1, kWave);
+    const uint64_t heads = __ballot(lane == 0 || prev != key);
+    head = 63 - __clzll(heads & ((2ull << lane) - 1ull));
+    const uint32_t next = __shfl_down(key, 1, kWave);
+    tail = lane == kWave - 1 || next != key;
+}
+
+// Inclusive sum of v over this lane's segment so far.
+__device__ __forceinline__ uint64_t wave_segmented_sum_u64(uint64_t v, int head) {
+    const uint64_t incl = wave_incl_scan_u64(v);
+    const uint64_t before = __shfl(incl, head > 0 ? head - 1 : 0, kWave);
+    return head > 0 ? incl - before : incl;
+}
+
+// Inclusive max of v over this lane's segment so far.
+__device__ __forceinline__ int32_t wave_segmented_max_i32(int32_t v, int head) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t w = __shfl_up(v, d, kWave);
+        if (lane - d >= head && w > v) v = w;
+    }
+    return v;
+}
+
 // lower bound of x in a sorted list: first position with list[pos] >= x
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ list, uint32_t len, uint32_t x) {
     uint32_t lo = 0, hi = len;
@@ -137,14 +166,16 @@ __device__ __forceinline__ uint32_t row_of_slot(const uint64_t* __restrict__ off
 
 // Wave-cooperative 64-ary search: first index p in [0, n) with a[p] > r,
 // given a non-decreasing and a[n - 1] > r.  Every lane returns the answer.
-__device__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r) {
+// Comparisons are of a[p] - base (modulo 2^64), so a prefix may be read
+// relative to the entry before its segment.
+__device__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r, uint64_t base = 0) {
     const int lane = lane_id();
-    uint64_t lo = 0, hi = n - 1;  // answer in [lo, hi], a[hi] > r
+    uint64_t lo = 0, hi = n - 1;  // answer in [lo, hi], a[hi] - base > r
     while (hi - lo + 1 > (uint64_t)kWave) {
         const uint64_t step = (hi - lo + kWave) >> 6;
         const uint64_t p = lo + (uint64_t)lane * step;
         const bool valid = p <= hi;
-        const bool pred = valid && a[p] > r;
+        const bool pred = valid && a[p] - base > r;
         const uint64_t m = __ballot(pred);
         if (m == 0) {
             const uint64_t vm = __ballot(valid);
@@ -158,7 +189,7 @@ __device__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t 
         }
     }
     const uint64_t p = lo + (uint64_t)lane;
-    const bool pred = p <= hi && a[p] > r;
+    const bool pred = p <= hi && a[p] - base > r;
     const uint64_t m = __ballot(pred);
     return lo + (uint64_t)(__ffsll((unsigned long long)m) - 1);
 }
@@ -307,33 +338,44 @@ __global__ void k_tables_init(DevGraph g, uint4* rec, uint64_t* s2, uint64_t* hi
 // cv_seed, counter (v, t, 0, tag 0 / tag 1), a hit when the two neighbours
 // are adjacent.  For the exact coefficient, counts the neighbours z > x of v
 // that are adjacent to x (each edge among N(v) once).
-__global__ void k_tables_edges(DevGraph g, const uint4* rec, uint64_t* s2, uint64_t* hits, uint32_t k0, uint32_t k1,
-                               int exact) {
+__global__ __launch_bounds__(256) void k_tables_edges(DevGraph g, const uint4* rec, uint64_t* s2, uint64_t* hits,
+                                                       uint32_t k0, uint32_t k1, int exact) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.nnz) return;
-    const uint32_t v = row_of_slot(g.off, g.n, e);
-    const uint32_t x = g.nbr[e];
-    const uint64_t ov = g.off[v];
-    const uint32_t d = rec[v].x;
-    atomicAdd((unsigned long long*)&s2[v], (unsigned long long)rec[x].x);
-    if (d < 2) return;
-    const uint32_t* row = g.nbr + ov;
-    uint32_t h = 0;
-    if (!exact) {
-        const uint32_t t = (uint32_t)(e - ov);
-        const uint64_t a = bounded_draw(k0, k1, v, t, 0, 0, d);
-        uint64_t b = bounded_draw(k0, k1, v, t, 0, 1, d - 1);
-        if (b >= a) ++b;
-        const uint32_t y = row[a], z = row[b];
-        const uint64_t oy = g.off[y];
-        h = contains_u32(g.nbr + oy, (uint32_t)(g.off[y + 1] - oy), z) ? 1u : 0u;
-    } else {
-        const uint64_t ox = g.off[x];
-        const uint32_t dx = (uint32_t)(g.off[x + 1] - ox);
-        for (uint32_t p = lower_bound_u32(row, d, x + 1); p < d; ++p)
-            if (contains_u32(g.nbr + ox, dx, row[p])) ++h;
+    const bool active = e < g.nnz;
+    uint32_t v = 0xFFFFFFFFu;
+    uint64_t dx = 0, h = 0;
+    if (active) {
+        v = row_of_slot(g.off, g.n, e);
+        const uint32_t x = g.nbr[e];
+        const uint64_t ov = g.off[v];
+        const uint32_t d = rec[v].x;
+        dx = rec[x].x;
+        const uint32_t* row = g.nbr + ov;
+        if (d >= 2 && !exact) {
+            const uint32_t t = (uint32_t)(e - ov);
+            const uint64_t a = bounded_draw(k0, k1, v, t, 0, 0, d);
+            uint64_t b = bounded_draw(k0, k1, v, t, 0, 1, d - 1);
+            if (b >= a) ++b;
+            const uint32_t y = row[a], z = row[b];
+            const uint64_t oy = g.off[y];
+            h = contains_u32(g.nbr + oy, (uint32_t)(g.off[y + 1] - oy), z) ? 1u : 0u;
+        } else if (d >= 2) {
+            const uint64_t ox = g.off[x];
+            const uint32_t dxx = (uint32_t)(g.off[x + 1] - ox);
+            for (uint32_t p = lower_bound_u32(row, d, x + 1); p < d; ++p)
+                if (contains_u32(g.nbr + ox, dxx, row[p])) ++h;
+        }
     }
-    if (h) atomicAdd((unsigned long long*)&hits[v], (unsigned long long)h);
+    // consecutive slots mostly share a row: one atomic per row segment of the wave
+    int head;
+    bool tail;
+    wave_segments(v, head, tail);
+    const uint64_t sdx = wave_segmented_sum_u64(dx, head);
+    const uint64_t sh = wave_segmented_sum_u64(h, head);
+    if (active && tail) {
+        atomicAdd((unsigned long long*)&s2[v], (unsigned long long)sdx);
+        if (sh) atomicAdd((unsigned long long*)&hits[v], (unsigned long long)sh);
+    }
 }
 
 __global__ void k_tables_finalize(DevGraph g, uint4* rec, const uint64_t* s2, const uint64_t* hits, uint64_t* trials,
@@ -525,6 +567,123 @@ hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t,
 }
 
 // ---------------------------------------------------------------------------
+// Per-row pick tables of a weighted step with one backward vertex w: its
+// candidates are N(w) minus matched vertices, and the normalising maximum is
+// taken over N(w), so every slot's integer weight depends on its row alone.
+// The table is one inclusive 64-bit prefix over all CSR slots of these
+// weights; a row's own prefix is read relative to the entry before the row
+// (differences are exact modulo 2^64).  Built flat over slots, so hub rows
+// spread over many waves: (1) log weight per slot, parked with its row id
+// in the output, and wave-combined atomic row maxima; (2) tile sums of the
+// integer weights; (3) scan of the tile sums; (4) the prefix.
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_rowtab_log(DevGraph g, const uint4* __restrict__ rec, uint32_t b,
+                                                     uint32_t f1, uint32_t ie, uint32_t f2,
+                                                     const int32_t* __restrict__ lt, uint64_t* __restrict__ park,
+                                                     int32_t* __restrict__ rowmax) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = e < g.nnz;
+    uint32_t w = 0xFFFFFFFFu;
+    int32_t l = kCertainZero;
+    if (active) {
+        w = row_of_slot(g.off, g.n, e);
+        const uint32_t x = g.nbr[e];
+        const uint4 r = rec[x];
+        if (r.x >= b + f1) l = lt ? lt[x] : approx_log_weight(r, b, f1, ie, f2);
+        park[e] = ((uint64_t)w << 32) | (uint64_t)(uint32_t)l;
+    }
+    int head;
+    bool tail;
+    wave_segments(w, head, tail);
+    const int32_t m = wave_segmented_max_i32(l, head);
+    if (active && tail && m != kCertainZero) atomicMax(&rowmax[w], m);
+}
+
+__device__ __forceinline__ uint32_t rowtab_weight(uint64_t parked, const int32_t* __restrict__ rowmax) {
+    const int32_t l = (int32_t)(uint32_t)parked;
+    return l == kCertainZero ? 0u : weight_from_log(rowmax[(uint32_t)(parked >> 32)], l, c_exp2tab);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_rowtab_tilesum(const uint64_t* __restrict__ park, uint64_t nnz,
+                                                                  const int32_t* __restrict__ rowmax,
+                                                                  uint64_t* __restrict__ tile_sums) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t e = base + (uint64_t)j * kScanThreads + threadIdx.x;
+        if (e < nnz) s += rowtab_weight(park[e], rowmax);
+    }
+    s = wave_sum_u64(s);
+    __shared__ uint64_t ws[kScanThreads / kWave];
+    if (lane_id() == 0) ws[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) t += ws[w];
+        tile_sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_rowtab_final(uint64_t* __restrict__ pre, uint64_t nnz,
+                                                                const int32_t* __restrict__ rowmax,
+                                                                const uint64_t* __restrict__ tile_offs) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t q[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t e = base + j;
+        q[j] = e < nnz ? rowtab_weight(pre[e], rowmax) : 0u;
+        s += q[j];
+    }
+    const uint64_t incl = wave_incl_scan_u64(s);
+    __shared__ uint64_t wsum[kScanThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (int j = 0; j < w; ++j) wbase += wsum[j];
+    uint64_t run = tile_offs[blockIdx.x] + wbase + incl - s;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t e = base + j;
+        if (e < nnz) {
+            run += q[j];
+            pre[e] = run;
+        }
+    }
+}
+
+hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const uint4* rec, uint32_t b, uint32_t f1, uint32_t ie,
+                         uint32_t f2, const int32_t* lt, uint64_t* pre, int32_t* rowmax) {
+    if (!g.n || !g.nnz) return hipSuccess;
+    hipStream_t st = ctx->stream;
+    const uint64_t ntiles = (g.nnz + kScanTile - 1) / kScanTile;
+    if (ctx->blocksums_cap < ntiles) {
+        if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
+        ctx->d_blocksums = nullptr;
+        ctx->blocksums_cap = 0;
+        hipError_t e = hipMalloc(&ctx->d_blocksums, ntiles * sizeof(uint64_t));
+        if (e != hipSuccess) return e;
+        ctx->blocksums_cap = ntiles;
+    }
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(g.n, 256)), dim3(256), 0, st, rowmax, g.n, kCertainZero);
+    hipLaunchKernelGGL(k_rowtab_log, dim3(grid_for(g.nnz, 256)), dim3(256), 0, st, g, rec, b, f1, ie, f2, lt, pre,
+                       rowmax);
+    hipLaunchKernelGGL(k_rowtab_tilesum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, pre, g.nnz, rowmax,
+                       ctx->d_blocksums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, ctx->d_blocksums, ntiles);
+    hipLaunchKernelGGL(k_rowtab_final, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, pre, g.nnz, rowmax,
+                       ctx->d_blocksums);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Sampling kernel
 // ---------------------------------------------------------------------------
 namespace {
@@ -571,7 +730,59 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
         } else {
             const uint32_t bm = P->bmask[i];
             const bool weighted = P->weighted[i] != 0;
-            if (!weighted && __builtin_popcount(bm) == 1) {
+            if (weighted && P->rowpre[i] != nullptr) {
+                // Weighted draw from S = N(w) minus the matched vertices
+                // through the row's prefix of integer weights: subtract the
+                // weights of matched vertices found in N(w), then search the
+                // prefix segment by segment between their positions.
+                const uint32_t w = readlane_u32(my_tau, __builtin_ctz(bm));
+                const uint64_t o = g.off[w];
+                const uint32_t d = (uint32_t)(g.off[w + 1] - o);
+                const uint32_t* list = g.nbr + o;
+                const uint64_t* pre = P->rowpre[i] + o;  // global prefix; row-relative below
+                const uint64_t base = o > 0 ? P->rowpre[i][o - 1] : 0ull;
+                uint32_t pos = 0xFFFFFFFFu;
+                bool found = false;
+                uint64_t qx = 0;
+                if ((uint32_t)lane < i) {
+                    pos = lower_bound_u32(list, d, my_tau);
+                    found = pos < d && list[pos] == my_tau;
+                    if (found) qx = pre[pos] - (pos > 0 ? pre[pos - 1] : base);
+                }
+                const uint64_t qrow = d ? pre[d - 1] - base : 0ull;
+                const uint64_t Q = qrow - wave_sum_u64(qx);
+                if (Q == 0) {
+                    fail = (int)i;
+                    break;
+                }
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
+                uint64_t shift = 0;  // weights of the matched vertices passed so far
+                uint32_t seg = 0;    // start of the current segment
+                uint64_t left = __ballot(found);
+                uint64_t ans = ~0ull;
+                while (left) {
+                    uint64_t key = (left >> lane & 1ull) ? (((uint64_t)pos << 8) | (uint64_t)lane) : ~0ull;
+#pragma unroll
+                    for (int of = 32; of > 0; of >>= 1) {
+                        const uint64_t k2 = __shfl_xor(key, of, kWave);
+                        key = k2 < key ? k2 : key;
+                    }
+                    const int L = (int)(key & 0xFF);
+                    const uint32_t e = (uint32_t)(key >> 8);
+                    const uint64_t before = e > 0 ? pre[e - 1] - base : 0ull;
+                    if (before - shift > r) {
+                        ans = seg + wave_first_greater(pre + seg, e - seg, r + shift, base);
+                        break;
+                    }
+                    shift += readlane_u64(qx, L);
+                    seg = e + 1;
+                    left &= ~(1ull << L);
+                }
+                if (ans == ~0ull) ans = seg + wave_first_greater(pre + seg, d - seg, r + shift, base);
+                v = list[ans];
+                num = Q;
+                den = pre[ans] - (ans > 0 ? pre[ans - 1] : base);
+            } else if (!weighted && __builtin_popcount(bm) == 1) {
                 // Uniform draw from N(w) minus the matched vertices, without
                 // materialising the set: probe each matched vertex in N(w)
                 // and skip the positions found.
@@ -769,48 +980,91 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
 
 }  // namespace
 
+__device__ __forceinline__ Partial chan_merge(Partial a, const Partial& b) {
+    if (b.n == 0.0) return a;
+    if (a.n == 0.0) return b;
+    const double n = a.n + b.n;
+    const double delta = b.mean - a.mean;
+    a.mean = a.mean + delta * (b.n / n);
+    a.m2 = a.m2 + b.m2 + delta * delta * (a.n * b.n / n);
+    a.n = n;
+    a.nonzero += b.nonzero;
+    return a;
+}
+
+// Persistent sampler: each wave repeatedly takes the next `grab` sample
+// slots from a device-wide counter (so heavy and light samples balance),
+// runs them one at a time and stores each weight at its slot.  A sample's
+// result does not depend on which wave runs it.
 __global__ __launch_bounds__(256) void k_sample(DevGraph g, DevTables t, const DevPlan* __restrict__ P, Step1 s1,
                                                  uint32_t k0, uint32_t k1, uint64_t start, uint64_t count,
                                                  const uint64_t* __restrict__ idx, Record* __restrict__ dump,
                                                  uint32_t* __restrict__ scratch, uint64_t cap,
-                                                 Partial* __restrict__ partials) {
+                                                 unsigned long long* __restrict__ queue, uint32_t grab,
+                                                 double* __restrict__ xout) {
     const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    const int wpb = blockDim.x / kWave;
-    const uint64_t gw = (uint64_t)blockIdx.x * wpb + wib;
-    const uint64_t nw = (uint64_t)gridDim.x * wpb;
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     uint32_t* sv = scratch + gw * cap * 2;
     int32_t* sl = (int32_t*)(sv + cap);
-    double wn = 0.0, wmean = 0.0, wm2 = 0.0, wnz = 0.0;
-    for (uint64_t j = gw; j < count; j += nw) {
-        const uint64_t s = idx ? idx[j] : start + j;
-        const double xv = sample_one(g, t, P, s1, k0, k1, s, sv, sl, dump ? dump + j : nullptr);
-        wn += 1.0;
-        const double d = xv - wmean;
-        wmean += d / wn;
-        wm2 += d * (xv - wmean);
-        wnz += xv != 0.0 ? 1.0 : 0.0;
+    // the next grab is requested before the current one is processed, so the
+    // atomic's round trip overlaps sampling work
+    unsigned long long cur = 0;
+    if (lane == 0) cur = atomicAdd(queue, (unsigned long long)grab);
+    cur = __shfl(cur, 0, kWave);
+    while (cur < count) {
+        unsigned long long next = 0;
+        if (lane == 0) next = atomicAdd(queue, (unsigned long long)grab);
+        const uint64_t j1 = (cur + grab) < count ? (cur + grab) : count;
+        for (uint64_t j = cur; j < j1; ++j) {
+            const uint64_t s = idx ? idx[j] : start + j;
+            const double xv = sample_one(g, t, P, s1, k0, k1, s, sv, sl, dump ? dump + j : nullptr);
+            if (lane == 0) xout[j] = xv;
+        }
+        cur = __shfl(next, 0, kWave);
     }
-    __shared__ Partial sp[1024 / kWave];
-    if (lane == 0) sp[wib] = Partial{wn, wmean, wm2, wnz};
+}
+
+// Estimator statistics of a batch of weights in a fixed order: each tile
+// of kReduceTile consecutive weights gives one (n, mean, M2, nonzero);
+// threads run Welford over 8 consecutive weights, then merge pairwise in a
+// fixed tree.  The result depends only on the weights, not on the launch
+// that produced them.
+constexpr int kReducePer = 8;
+constexpr int kReduceThreads = 256;
+constexpr int kReduceTile = kReducePer * kReduceThreads;
+static_assert(kReduceTile == kReduceTileSamples, "tile size");
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_x(const double* __restrict__ xs, uint64_t count,
+                                                              Partial* __restrict__ tiles) {
+    const uint64_t base = (uint64_t)blockIdx.x * kReduceTile + (uint64_t)threadIdx.x * kReducePer;
+    Partial a{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < kReducePer; ++j) {
+        const uint64_t p = base + j;
+        if (p >= count) break;
+        const double x = xs[p];
+        a.n += 1.0;
+        const double d = x - a.mean;
+        a.mean += d / a.n;
+        a.m2 += d * (x - a.mean);
+        a.nonzero += x != 0.0 ? 1.0 : 0.0;
+    }
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        Partial b;
+        b.n = __shfl_xor(a.n, o, kWave);
+        b.mean = __shfl_xor(a.mean, o, kWave);
+        b.m2 = __shfl_xor(a.m2, o, kWave);
+        b.nonzero = __shfl_xor(a.nonzero, o, kWave);
+        if ((lane & o) == 0) a = chan_merge(a, b);  // lower lane keeps (lower, upper)
+    }
+    __shared__ Partial wp[kReduceThreads / kWave];
+    if (lane == 0) wp[threadIdx.x / kWave] = a;
     __syncthreads();
     if (threadIdx.x == 0) {
-        Partial a = sp[0];
-        for (int w = 1; w < wpb; ++w) {
-            const Partial b = sp[w];
-            if (b.n == 0.0) continue;
-            if (a.n == 0.0) {
-                a = b;
-                continue;
-            }
-            const double n = a.n + b.n;
-            const double delta = b.mean - a.mean;
-            a.mean = a.mean + delta * (b.n / n);
-            a.m2 = a.m2 + b.m2 + delta * delta * (a.n * b.n / n);
-            a.n = n;
-            a.nonzero += b.nonzero;
-        }
-        partials[blockIdx.x] = a;
+        Partial r = wp[0];
+        for (int w = 1; w < kReduceThreads / kWave; ++w) r = chan_merge(r, wp[w]);
+        tiles[blockIdx.x] = r;
     }
 }
 
@@ -820,7 +1074,16 @@ SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t cou
     L.cap = (uint64_t)g.max_deg + 1;
     const uint64_t per_wave = L.cap * 2 * sizeof(uint32_t);
     const uint64_t budget = 8ull << 30;  // scratch budget
-    uint64_t waves = (uint64_t)ctx->num_cus * 32;  // 8 waves per SIMD
+    if (ctx->sample_blocks_per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sample), L.threads, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 4;
+        ctx->sample_blocks_per_cu = nb;
+    }
+    // as many waves as can be resident at once: a persistent grid
+    uint64_t waves = (uint64_t)ctx->num_cus * (uint64_t)ctx->sample_blocks_per_cu * 4;
     if (waves * per_wave > budget) waves = budget / per_wave;
     if (waves < 4) {
         *err = "maximum degree too large for the sampler scratch budget";
@@ -830,6 +1093,8 @@ SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t cou
     const uint64_t need = (count + 3) / 4 * 4;
     if (waves > need) waves = need < 4 ? 4 : need;
     L.blocks = (int)(waves / 4);
+    const uint64_t per = count / (waves * 32);
+    L.grab = (uint32_t)(per < 1 ? 1 : (per > 8 ? 8 : per));
     const uint64_t bytes = (uint64_t)L.blocks * 4 * per_wave;
     if (ctx->scratch_bytes < bytes) {
         if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
@@ -842,26 +1107,53 @@ SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t cou
         }
         ctx->scratch_bytes = bytes;
     }
-    if (ctx->partials_cap < (size_t)L.blocks) {
+    const uint64_t tiles = (count + kReduceTile - 1) / kReduceTile;
+    if (ctx->partials_cap < (size_t)tiles) {
         if (ctx->d_partials) (void)hipFree(ctx->d_partials);
         ctx->d_partials = nullptr;
         ctx->partials_cap = 0;
-        if (hipMalloc(&ctx->d_partials, (size_t)L.blocks * sizeof(Partial)) != hipSuccess) {
+        if (hipMalloc(&ctx->d_partials, (size_t)tiles * sizeof(Partial)) != hipSuccess) {
             *err = "could not allocate partials";
             *rc = AGIS_E_OOM;
             return L;
         }
-        ctx->partials_cap = (size_t)L.blocks;
+        ctx->partials_cap = (size_t)tiles;
     }
+    if (ctx->xout_cap < count) {
+        if (ctx->d_xout) (void)hipFree(ctx->d_xout);
+        ctx->d_xout = nullptr;
+        ctx->xout_cap = 0;
+        if (hipMalloc(&ctx->d_xout, (size_t)count * sizeof(double)) != hipSuccess) {
+            *err = "could not allocate the sample-weight buffer";
+            *rc = AGIS_E_OOM;
+            return L;
+        }
+        ctx->xout_cap = count;
+    }
+    L.tiles = tiles;
     *rc = AGIS_OK;
     return L;
 }
 
-hipError_t launch_sample(const SampleLaunch& L, const DevGraph& g, const DevTables& t, const DevPlan* d_plan,
+hipError_t launch_sample(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t,
                          const Step1& s1, uint32_t k0, uint32_t k1, uint64_t start, uint64_t count, const uint64_t* idx,
-                         Record* dump, void* scratch, Partial* partials, hipStream_t stream) {
-    hipLaunchKernelGGL(k_sample, dim3((unsigned)L.blocks), dim3((unsigned)L.threads), 0, stream, g, t, d_plan, s1, k0,
-                       k1, start, count, idx, dump, (uint32_t*)scratch, L.cap, partials);
+                         Record* dump, hipEvent_t before, hipEvent_t after) {
+    unsigned long long* queue = (unsigned long long*)((char*)ctx->d_small + 64);
+    hipError_t e = hipMemsetAsync(queue, 0, sizeof(unsigned long long), ctx->stream);
+    if (e != hipSuccess) return e;
+    if (before && (e = hipEventRecord(before, ctx->stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)L.blocks), dim3((unsigned)L.threads), 0, ctx->stream, g, t,
+                       ctx->d_plan, s1, k0, k1, start, count, idx, dump, (uint32_t*)ctx->d_scratch, L.cap, queue,
+                       L.grab, ctx->d_xout);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (after && (e = hipEventRecord(after, ctx->stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t launch_reduce(agis_ctx* ctx, const SampleLaunch& L, uint64_t count) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_x, dim3((unsigned)L.tiles), dim3(kReduceThreads), 0, ctx->stream, ctx->d_xout, count,
+                       ctx->d_partials);
     return hipGetLastError();
 }
 

@@ -120,14 +120,15 @@ def c1_state(sess, c1):
     return G, T, OT
 
 
+@pytest.mark.parametrize("rowtab", ["off", "on"])
 @pytest.mark.parametrize("name", C1_PATTERNS)
 @pytest.mark.parametrize("mode", MODES)
-def test_records_parity_c1(sess, c1, c1_state, name, mode):
+def test_records_parity_c1(sess, c1, c1_state, name, mode, rowtab):
     G, T, OT = c1_state
     p = synth.named_pattern(name)
     idx = _indices(3000, rng_seed=sum(name.encode()))
-    say(f"records chung-lu {name} {mode} m={idx.size}")
-    got = sess.dump(G, T, p, SEED, idx, mode=mode, pattern_id=5)
+    say(f"records chung-lu {name} {mode} rowtab={rowtab} m={idx.size}")
+    got = sess.dump(G, T, p, SEED, idx, mode=mode, pattern_id=5, rowtab=rowtab)
     c = compile_pattern(p.k, p.edges, mode=mode)
     ref = oracle.Sampler(c1, OT, c, seed=SEED, pattern_id=5).records(idx)
     _compare_records(got, ref, f"{name}/{mode}")
@@ -147,7 +148,7 @@ def test_records_shape_invariance(sess, c1, c1_state):
     assert np.array_equal(np.ascontiguousarray(a[::-1]).view(np.uint8), c.view(np.uint8))
 
 
-@pytest.mark.parametrize("name", ["triangle", "4-cycle", "4-clique"])
+@pytest.mark.parametrize("name", ["triangle", "4-cycle", "4-clique", "house"])
 @pytest.mark.parametrize("mode", MODES)
 def test_estimate_parity_c1(sess, c1, c1_state, name, mode):
     G, T, OT = c1_state
@@ -155,6 +156,8 @@ def test_estimate_parity_c1(sess, c1, c1_state, name, mode):
     n = 200_000
     say(f"estimate chung-lu {name} {mode} n={n}")
     r = sess.estimate(G, T, p, n, SEED, mode=mode)
+    r2 = sess.estimate(G, T, p, n, SEED, mode=mode, rowtab="off", check_every=12345, eps=1e-30)
+    assert r2.n == n and r2.estimate == pytest.approx(r.estimate, rel=1e-12)
     c = compile_pattern(p.k, p.edges, mode=mode)
     st, _, _ = oracle.Sampler(c1, OT, c, seed=SEED).run(0, n)
     assert r.n == st.n and r.n_nonzero == st.nonzero
@@ -275,10 +278,11 @@ def test_rmat20_full_size_sampled_parity(sess, rmat20):
     for name in C2_PATTERNS:
         p = synth.named_pattern(name)
         for mode in ("switch", "uniform"):
-            say(f"R-MAT-20 records {name} {mode}")
-            got = sess.dump(G, T, p, SEED, idx, mode=mode)
             ref = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode=mode), seed=SEED).records(idx)
-            _compare_records(got, ref, f"rmat20/{name}/{mode}")
+            for rowtab in ("off", "on"):
+                say(f"R-MAT-20 records {name} {mode} rowtab={rowtab}")
+                got = sess.dump(G, T, p, SEED, idx, mode=mode, rowtab=rowtab)
+                _compare_records(got, ref, f"rmat20/{name}/{mode}/{rowtab}")
     # 4-star has a closed form: k! * sum C(d, 4)
     say("R-MAT-20 4-star closed form")
     r = sess.estimate(G, T, synth.named_pattern("4-star"), 100_000, SEED, mode="switch")
