@@ -132,6 +132,11 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--bytes-records", type=int, default=1500)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-pilot", type=int, default=1 << 18)
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--batch-budget-scale", type=float, default=1.0,
+                    help="multiplier on the 32-pattern set's budgets (log-uniform in [1e6, 1e9])")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -155,6 +160,13 @@ def main():
     log(f"graph n={g.n} nnz={g.nnz} dmax={int(np.diff(g.off).max())}; tables {tables_s * 1e3:.1f} ms")
 
     pats = [synth.named_pattern(n) for n in PATTERNS]
+    tuning = None
+    if not args.no_tune:
+        log("autotuning the sampler launch on the four patterns")
+        tun = sess.autotune(G, T, pats, args.tune_pilot, mode="switch")
+        tuning = {"variant": tun.variant, "grab": tun.grab, "pilot_kernel_s": tun.seconds,
+                  "default_kernel_s": tun.default_seconds}
+        log(f"tuned: variant {tun.variant} grab {tun.grab} ({tun.default_seconds:.3f} s -> {tun.seconds:.3f} s)")
 
     def step(seed):
         res = []
@@ -227,6 +239,32 @@ def main():
                 }
                 log(f"+-1% {name} {mode}: {r.seconds:.3f} s, n={r.n}, converged={bool(r.converged)}")
 
+    # 32 connected patterns of 4-7 vertices (seed 3) with uneven budgets,
+    # all run to +-1% in one batch of rounds (each a persistent launch)
+    batch = None
+    if not args.skip_batch:
+        pset = synth.random_pattern_set(32, seed=3)
+        bpats = [p for p, _ in pset]
+        budgets = [max(1, int(b * args.batch_budget_scale)) for _, b in pset]
+        log(f"32-pattern batch to +-1%, total budget {sum(budgets):.3g} samples")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sess.estimate_batch(G, T, bpats, budgets, 13, mode="switch", eps=0.01, delta=0.05,
+                                  check_every=1 << 16, min_samples=1 << 14)
+        torch.cuda.synchronize()
+        bt = time.perf_counter() - t0
+        batch = {
+            "patterns": 32, "seconds": bt, "samples": int(sum(r.n for r in res)),
+            "converged": int(sum(r.converged for r in res)),
+            "samples_per_s": sum(r.n for r in res) / bt,
+            "budget_total": int(sum(budgets)),
+            "per_pattern": [{"k": p.k, "edges": len(p.edges), "budget": b, "samples": r.n,
+                             "converged": bool(r.converged), "seconds": r.seconds,
+                             "rel_var": r.variance / max(r.estimate ** 2, 1e-300)}
+                            for p, b, r in zip(bpats, budgets, res)],
+        }
+        log(f"batch: {bt:.2f} s, {batch['converged']}/32 converged, {batch['samples']:.3g} samples")
+
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(g, args.cpu_seconds)
@@ -252,7 +290,9 @@ def main():
             "graph": {"n": g.n, "nnz": g.nnz, "seed": 20},
             "tables_ms": 1e3 * tables_s,
         },
+        "tuning": tuning,
         "per_pattern": per_pattern,
+        "batch_32_patterns": batch,
         "time_to_1pct": eps_table,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -223,6 +223,53 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
                   const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
                   agis_result* out);
 
+/* Estimates C(G, P) for n_patterns (1..64) patterns at once, the way the
+ * paper runs independent samplers in parallel (Sec. 6.1), with uneven
+ * sample budgets: budgets[i] host uint64 per pattern.  Each round is one
+ * persistent launch over all still-active patterns (replayed from a
+ * captured HIP graph unless disabled by agis_set_launch): waves take
+ * sample slots from a shared queue, so heavy and light patterns balance.
+ * Pattern i uses Algorithm 2's order and pattern id params->pattern_id + i;
+ * with params->eps > 0 each pattern stops at its own convergence (checks
+ * every check_every of its samples) or at its budget, otherwise it runs
+ * exactly its budget.  Every per-pattern result equals what agis_estimate
+ * gives for that pattern alone (same samples, same stopping point;
+ * estimates to relative 1e-9).  out: host agis_result[n_patterns].
+ * Learned mode is not accepted here (its tables are per pattern).
+ * Returns AGIS_E_NOT_CONVERGED (results filled) if any pattern did not
+ * converge within its budget. */
+int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint32_t n_patterns,
+                        const agis_pattern* patterns, const uint64_t* budgets, uint64_t seed,
+                        const agis_run_params* params, agis_result* out);
+
+/* Launch shape of the sampler for later calls on this context (results do
+ * not depend on it): use_graphs = replay rounds from a captured HIP graph;
+ * blocks_per_cu = resident 256-thread workgroups per compute unit (0 = as
+ * many as fit); grab = sample slots a wave takes from the queue at a time
+ * (0 = chosen from the round size, at most 1024); variant = register
+ * budget of the sampling kernel (0 = compiler's choice, 1 = at most 5
+ * waves' worth per SIMD lane set, 2 = 6). */
+int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant);
+
+/* Launch configuration chosen by agis_autotune. */
+typedef struct {
+    int32_t use_graphs;
+    int32_t blocks_per_cu;
+    uint32_t grab;
+    int32_t variant;
+    double seconds;          /* sampling-kernel time of the chosen configuration's pilot */
+    double default_seconds;  /* the same pilot under the default configuration */
+} agis_tuning;
+
+/* Times pilot batches (pilot_samples samples of each of the n_patterns
+ * patterns, fixed budgets, params' mode and beta) under each candidate
+ * launch configuration -- kernel register-budget variant x queue grab --
+ * and applies the fastest to the context (as agis_set_launch would).
+ * Results of later calls do not depend on the choice. */
+int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint32_t n_patterns,
+                  const agis_pattern* patterns, uint64_t pilot_samples, const agis_run_params* params,
+                  agis_tuning* out);
+
 /* Runs the samples whose indices are listed in idx (device uint64[m]) and
  * writes one agis_record per index into out (device, m records). */
 int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,

@@ -80,6 +80,11 @@ class agis_run_params(ctypes.Structure):
     ]
 
 
+class agis_tuning(ctypes.Structure):
+    _fields_ = [("use_graphs", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("grab", ctypes.c_uint32),
+                ("variant", ctypes.c_int32), ("seconds", ctypes.c_double), ("default_seconds", ctypes.c_double)]
+
+
 class agis_result(ctypes.Structure):
     _fields_ = [
         ("estimate", ctypes.c_double), ("copies", ctypes.c_double), ("variance", ctypes.c_double),
@@ -115,6 +120,11 @@ _SIGNATURES = [
                                      ctypes.c_uint64, ctypes.POINTER(agis_run_params), ctypes.POINTER(agis_result)]),
     ("agis_dump_samples", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
                                          ctypes.POINTER(agis_run_params), _P, ctypes.c_uint64, _P]),
+    ("agis_estimate_batch", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, _P, ctypes.c_uint64,
+                                           ctypes.POINTER(agis_run_params), _P]),
+    ("agis_set_launch", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32]),
+    ("agis_autotune", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, ctypes.c_uint64,
+                                     ctypes.POINTER(agis_run_params), ctypes.POINTER(agis_tuning)]),
     ("agis_fixed_point_tables", ctypes.c_int, [_P, _P]),
     ("agis_philox4x32_10", ctypes.c_int, [_P, _P, _P]),
 ]
@@ -245,6 +255,31 @@ def agis_dump_samples(ctx, g, t, pattern: agis_pattern, seed: int, params: agis_
     _check(ctx, lib().agis_dump_samples(ctx, g, t, ctypes.byref(pattern), ptr, seed, ctypes.byref(params), idx_ptr,
                                         m, out_ptr))
     del keep
+
+
+def agis_estimate_batch(ctx, g, t, patterns, budgets, seed: int, params: agis_run_params):
+    """patterns: list of agis_pattern; budgets: list of ints.  Returns a
+    list of agis_result (NOT_CONVERGED is reported in each result)."""
+    n = len(patterns)
+    arr = (agis_pattern * n)(*patterns)
+    bud = (ctypes.c_uint64 * n)(*budgets)
+    out = (agis_result * n)()
+    _check(ctx, lib().agis_estimate_batch(ctx, g, t, n, ctypes.cast(arr, _P), ctypes.cast(bud, _P), seed,
+                                          ctypes.byref(params), ctypes.cast(out, _P)), allow=(AGIS_E_NOT_CONVERGED,))
+    return list(out)
+
+
+def agis_set_launch(ctx, use_graphs: bool = True, blocks_per_cu: int = 0, grab: int = 0, variant: int = 0):
+    _check(ctx, lib().agis_set_launch(ctx, 1 if use_graphs else 0, blocks_per_cu, grab, variant))
+
+
+def agis_autotune(ctx, g, t, patterns, pilot_samples: int, params: agis_run_params) -> agis_tuning:
+    n = len(patterns)
+    arr = (agis_pattern * n)(*patterns)
+    out = agis_tuning()
+    _check(ctx, lib().agis_autotune(ctx, g, t, n, ctypes.cast(arr, _P), pilot_samples, ctypes.byref(params),
+                                    ctypes.byref(out)))
+    return out
 
 
 def agis_fixed_point_tables():

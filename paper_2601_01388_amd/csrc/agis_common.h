@@ -131,12 +131,55 @@ struct DevPlan {
     // per-row inclusive prefixes of a weighted single-backward step's integer
     // weights (one entry per CSR slot), or nullptr
     const uint64_t* rowpre[kMaxK];
+    // first-step table of a weighted first step: integer weight of every
+    // vertex, its inclusive prefix and the total
+    const uint32_t* s1_q;
+    const uint64_t* s1_pre;
+    uint64_t s1_total;
 };
 
-struct Step1 {
-    const uint32_t* q1;   // integer weight of every vertex
-    const uint64_t* pre;  // inclusive prefix of q1
-    uint64_t total;
+// One launch ("round") of the sampler covers up to kMaxSegs segments: the
+// slots [base, base + count) run samples start .. start + count - 1 of
+// plan `plan`; the segment's weights are reduced in tiles numbered from
+// tile_base.
+constexpr uint32_t kMaxSegs = 64;
+
+struct Segment {
+    uint32_t plan;
+    uint32_t ntiles;
+    uint64_t start;
+    uint64_t base;
+    uint64_t count;
+    uint64_t tile_base;
+};
+
+struct RoundDesc {
+    uint64_t total;  // slots in the round
+    uint32_t nseg;
+    uint32_t k0, k1;  // Philox key (the sampling seed)
+    uint32_t pad;
+    Segment seg[kMaxSegs];
+};
+
+struct Record;
+
+// Everything the sampling and reduction kernels of one round read, held in
+// device memory (one pointer argument: the fields are fetched through the
+// scalar cache where used instead of occupying registers for the whole
+// kernel, and a captured graph stays valid while only the contents change).
+struct LaunchDesc {
+    DevGraph g;
+    DevTables t;
+    const DevPlan* plans;
+    const uint64_t* idx;       // non-null: the single segment's sample indices
+    Record* dump;              // non-null: one record per slot
+    uint32_t* scratch;         // per wave: cap vertices + cap log weights
+    uint64_t cap;
+    unsigned long long* queue; // next free slot
+    double* xout;              // weight per slot
+    uint32_t grab;
+    uint32_t pad;
+    RoundDesc round;
 };
 
 // Welford/Chan accumulator of the sample weights of one workgroup.

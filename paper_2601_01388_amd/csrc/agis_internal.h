@@ -15,7 +15,6 @@ struct agis_ctx {
     std::string err;
     int num_cus = 256;
     // reusable device buffers
-    agis::DevPlan* d_plan = nullptr;
     agis::Partial* d_partials = nullptr;
     size_t partials_cap = 0;
     void* d_scratch = nullptr;
@@ -23,9 +22,24 @@ struct agis_ctx {
     void* d_small = nullptr;  // 4 KiB of flags / reduction cells
     uint64_t* d_blocksums = nullptr;
     size_t blocksums_cap = 0;
-    double* d_xout = nullptr;  // per-sample weights of the current launch
+    double* d_xout = nullptr;  // per-sample weights of the current round
     uint64_t xout_cap = 0;
-    int sample_blocks_per_cu = 0;
+    agis::DevPlan* d_plans = nullptr;    // kMaxSegs plans
+    agis::LaunchDesc* d_launch = nullptr;  // the current round
+    int sample_blocks_per_cu[3] = {0, 0, 0};  // resident blocks per CU of each kernel variant
+    // launch tuning (0 = default): resident blocks per CU, slots per grab
+    int tune_blocks_per_cu = 0;
+    uint32_t tune_grab = 0;
+    int use_graphs = 1;
+    int tune_variant = 0;  // sampling-kernel register budget (see sample_kernel)
+    // captured round (k_zero, k_sample, k_reduce_x) replayed on graph_stream;
+    // valid while the key below matches
+    hipStream_t graph_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hipEvent_t ev_in = nullptr;
+    hipEvent_t ev_out = nullptr;
     hipEvent_t ev_start = nullptr;  // brackets each sampling launch
     hipEvent_t ev_stop = nullptr;
 };
@@ -67,8 +81,8 @@ hipError_t launch_build_tables(const DevGraph& g, uint4* rec, uint64_t* s2, uint
 hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg, int32_t* la, int32_t* lc,
                                 hipStream_t stream);
 
-// First-step table for step 0 of `plan` (host copy `hp`): q1, inclusive
-// prefix pre, total copied into *total (synchronises the stream).
+// First-step table for step 0 of the plan `hp`: q1, inclusive prefix pre,
+// total copied into *total (synchronises the stream).
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
                        uint32_t* q1, uint64_t* pre, uint64_t* total);
 
@@ -83,25 +97,36 @@ hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const uint4* rec, uin
 struct SampleLaunch {
     int blocks = 0;
     int threads = 256;
-    uint64_t cap = 0;    // scratch entries per wave
-    uint32_t grab = 1;   // sample slots a wave takes per queue access
-    uint64_t tiles = 0;  // reduction tiles of the weight buffer
+    uint64_t cap = 0;        // scratch entries per wave
+    uint32_t grab = 1;       // sample slots a wave takes per queue access
+    uint64_t max_slots = 0;  // largest round
+    uint64_t max_tiles = 0;  // reduction tiles of the largest round
+    bool dump = false;       // launch the record-writing variant
+    int variant = 0;         // register-budget variant
 };
 
-// Sizes the persistent grid (resident waves only) and the buffers for a
-// launch of `count` samples.
-SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t count, std::string* err, int* rc);
+// The sampling kernel for (record-writing?, register-budget variant 0..2).
+const void* sample_kernel(bool dump, int variant);
 
-// Samples slots [0, count) (sample index start + slot, or idx[slot]) into
-// ctx->d_xout; dump != nullptr also writes one record per slot.
-// `before`/`after` (may be null) are recorded around the sampling kernel alone.
-hipError_t launch_sample(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t,
-                         const Step1& s1, uint32_t k0, uint32_t k1, uint64_t start, uint64_t count,
-                         const uint64_t* idx, Record* dump, hipEvent_t before, hipEvent_t after);
+// Sizes the persistent grid (resident waves only) and the buffers for
+// rounds of at most max_slots samples over at most max_segs segments.
+int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, uint32_t max_segs, SampleLaunch* L,
+                       std::string* err);
 
-// Per-tile (n, mean, M2, nonzero) of ctx->d_xout[0, count) into ctx->d_partials,
-// one tile per kReduceTileSamples consecutive weights.
+// One round as described by ctx->d_launch (plans in ctx->d_plans): clears
+// the work queue (a kernel, so the sequence can be captured in a graph),
+// samples every slot into ctx->d_xout (slot weights), reduces each
+// segment's weights into tiles of kReduceTileSamples in ctx->d_partials.
+// With D.idx the single segment's samples are idx[0..count); with D.dump
+// one record per slot.  `before`/`after` (may be null) are recorded
+// around the sampling kernel alone.
 constexpr uint64_t kReduceTileSamples = 2048;
-hipError_t launch_reduce(agis_ctx* ctx, const SampleLaunch& L, uint64_t count);
+hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L, hipEvent_t before,
+                        hipEvent_t after);
+
+// Host-side fill of the launch descriptor's buffers and shape (the round
+// part is filled by the caller); upload it to ctx->d_launch before a round.
+void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t, const uint64_t* idx,
+                 Record* dump, LaunchDesc* D);
 
 }  // namespace agis

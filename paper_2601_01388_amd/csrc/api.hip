@@ -1,6 +1,7 @@
 // C-ABI entry points of the AGIS library (declared in include/agis.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -90,7 +91,6 @@ agis_run_params default_params() {
 struct Prepared {
     agis_plan plan;
     DevPlan hp;
-    agis::Step1 s1{nullptr, nullptr, 0};
     uint32_t* q1 = nullptr;
     uint64_t* pre = nullptr;
     std::vector<uint64_t*> rowtabs;
@@ -179,12 +179,177 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         AGIS_HIP(ctx, hipMalloc(&out->pre, g->g.n * sizeof(uint64_t)), "allocate first-step prefix");
         uint64_t total = 0;
         AGIS_HIP(ctx, agis::build_step1(ctx, *g, *t, hp, out->q1, out->pre, &total), "first-step table");
-        out->s1 = agis::Step1{out->q1, out->pre, total};
+        hp.s1_q = out->q1;
+        hp.s1_pre = out->pre;
+        hp.s1_total = total;
     }
-    AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_plan, &hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream), "upload plan");
-    AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "upload plan");
+    AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "proposal tables");
     out->tables_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return AGIS_OK;
+}
+
+// State of one pattern inside a run of rounds.
+struct PatternRun {
+    Prepared prep;
+    uint64_t budget = 0;
+    uint64_t done = 0;
+    Acc acc;
+    bool active = true;
+    bool converged = false;
+    double seconds = 0;  // from the start of the run until this pattern stopped
+    double kernel_seconds = 0;
+    uint64_t launches = 0;
+};
+
+// Rounds of at most this many samples bound the weight buffer (8 B each).
+constexpr uint64_t kMaxRoundSlots = 1ull << 24;
+
+int replay_or_launch(agis_ctx* ctx, const agis::SampleLaunch& L, const agis_graph* g, const agis_tables* t,
+                     float* ms) {
+    if (!ctx->use_graphs) {
+        AGIS_HIP(ctx, agis::launch_round(ctx, ctx->stream, L, ctx->ev_start, ctx->ev_stop), "launch round");
+        AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "round");
+        AGIS_HIP(ctx, hipEventElapsedTime(ms, ctx->ev_start, ctx->ev_stop), "event time");
+        return AGIS_OK;
+    }
+    // kernel arguments and grids of the captured sequence: the descriptor's
+    // contents may change between replays, its address and the grids not
+    const uint64_t key[8] = {(uint64_t)(uintptr_t)ctx->d_launch, (uint64_t)L.blocks, (uint64_t)L.threads,
+                             L.max_tiles, (uint64_t)(uintptr_t)ctx->d_partials, (uint64_t)(uintptr_t)ctx->d_small,
+                             (uint64_t)L.variant, 0};
+    if (!ctx->graph_exec || std::memcmp(key, ctx->graph_key, sizeof(key)) != 0) {
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->graph_exec = nullptr;
+        ctx->graph = nullptr;
+        AGIS_HIP(ctx, hipStreamBeginCapture(ctx->graph_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t e = agis::launch_round(ctx, ctx->graph_stream, L, nullptr, nullptr);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(ctx->graph_stream, &gr);
+        if (e != hipSuccess) return hip_fail(ctx, e, "capture round");
+        if (e2 != hipSuccess) return hip_fail(ctx, e2, "end capture");
+        ctx->graph = gr;
+        AGIS_HIP(ctx, hipGraphInstantiate(&ctx->graph_exec, gr, nullptr, nullptr, 0), "instantiate round graph");
+        std::memcpy(ctx->graph_key, key, sizeof(key));
+    }
+    // order the replay after the caller's stream, and the caller's stream after it
+    AGIS_HIP(ctx, hipEventRecord(ctx->ev_in, ctx->stream), "record event");
+    AGIS_HIP(ctx, hipStreamWaitEvent(ctx->graph_stream, ctx->ev_in, 0), "wait event");
+    AGIS_HIP(ctx, hipEventRecord(ctx->ev_start, ctx->graph_stream), "record event");
+    AGIS_HIP(ctx, hipGraphLaunch(ctx->graph_exec, ctx->graph_stream), "replay round graph");
+    AGIS_HIP(ctx, hipEventRecord(ctx->ev_stop, ctx->graph_stream), "record event");
+    AGIS_HIP(ctx, hipEventRecord(ctx->ev_out, ctx->graph_stream), "record event");
+    AGIS_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_out, 0), "wait event");
+    AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "round");
+    AGIS_HIP(ctx, hipEventElapsedTime(ms, ctx->ev_start, ctx->ev_stop), "event time");
+    return AGIS_OK;
+}
+
+// Runs the patterns' samples in rounds.  to_eps: every active pattern gets
+// check_every samples per round and stops once Algorithm 1's eps_hat <= eps
+// (with at least min_samples) or at its budget; otherwise each pattern runs
+// exactly its budget, rounds filled in pattern order.  Samples of a pattern
+// use indices 0, 1, 2, ... in order, so the stopping point of each pattern
+// depends only on its own samples.
+int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::vector<PatternRun>& runs,
+               const agis_run_params* pp, uint64_t seed) {
+    const bool to_eps = pp->eps > 0;
+    const uint64_t check = pp->check_every ? pp->check_every : 65536;
+    const double z = normal_quantile(1.0 - (to_eps ? pp->delta : 0.05) / 2.0);
+    const uint32_t npat = (uint32_t)runs.size();
+    std::vector<DevPlan> plans(npat);
+    for (uint32_t p = 0; p < npat; ++p) plans[p] = runs[p].prep.hp;
+    AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_plans, plans.data(), npat * sizeof(DevPlan), hipMemcpyHostToDevice, ctx->stream),
+             "upload plans");
+    uint64_t max_slots = 0, total_budget = 0;
+    for (const PatternRun& r : runs) {
+        total_budget += r.budget;
+        max_slots += to_eps ? std::min(check, r.budget) : r.budget;
+    }
+    max_slots = std::min(max_slots, kMaxRoundSlots);
+    if (max_slots == 0) return AGIS_OK;
+    agis::SampleLaunch L;
+    int rc = agis::plan_sample_launch(ctx, *g, max_slots, npat, &L, &ctx->err);
+    if (rc != AGIS_OK) return rc;
+    agis::LaunchDesc ld;
+    std::memset(&ld, 0, sizeof(ld));
+    agis::fill_launch(ctx, L, g->g, agis::DevTables{t->rec}, nullptr, nullptr, &ld);
+    agis::RoundDesc& rd = ld.round;
+    std::vector<Partial> parts;
+    std::vector<uint32_t> members;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        std::memset(&rd, 0, sizeof(rd));
+        rd.k0 = (uint32_t)seed;
+        rd.k1 = (uint32_t)(seed >> 32);
+        members.clear();
+        uint64_t used = 0, tiles = 0;
+        for (uint32_t p = 0; p < npat && used < max_slots; ++p) {
+            PatternRun& r = runs[p];
+            if (!r.active) continue;
+            uint64_t cnt = r.budget - r.done;
+            if (to_eps) cnt = std::min(cnt, check);
+            cnt = std::min(cnt, max_slots - used);
+            if (cnt == 0) continue;
+            agis::Segment& S = rd.seg[rd.nseg++];
+            S.plan = p;
+            S.start = r.done;
+            S.base = used;
+            S.count = cnt;
+            S.ntiles = (uint32_t)((cnt + agis::kReduceTileSamples - 1) / agis::kReduceTileSamples);
+            S.tile_base = tiles;
+            used += cnt;
+            tiles += S.ntiles;
+            members.push_back(p);
+        }
+        if (rd.nseg == 0) break;
+        rd.total = used;
+        AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_launch, &ld, sizeof(ld), hipMemcpyHostToDevice, ctx->stream),
+                 "upload round");
+        float ms = 0.0f;
+        rc = replay_or_launch(ctx, L, g, t, &ms);
+        if (rc != AGIS_OK) return rc;
+        parts.resize((size_t)tiles);
+        AGIS_HIP(ctx,
+                 hipMemcpyAsync(parts.data(), ctx->d_partials, tiles * sizeof(Partial), hipMemcpyDeviceToHost,
+                                ctx->stream),
+                 "read partials");
+        AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "read partials");
+        const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (uint32_t q = 0; q < rd.nseg; ++q) {
+            PatternRun& r = runs[rd.seg[q].plan];
+            for (uint32_t k = 0; k < rd.seg[q].ntiles; ++k) r.acc.merge(parts[rd.seg[q].tile_base + k]);
+            r.done += rd.seg[q].count;
+            r.kernel_seconds += 1e-3 * (double)ms * (double)rd.seg[q].count / (double)used;
+            r.launches += 1;
+            if (to_eps && r.done >= pp->min_samples && eps_hat_of(r.acc, z) <= pp->eps) {
+                r.converged = true;
+                r.active = false;
+            }
+            if (r.done >= r.budget) r.active = false;
+            if (!r.active) r.seconds = now;
+        }
+    }
+    (void)total_budget;
+    return AGIS_OK;
+}
+
+void fill_result(const PatternRun& r, double z, double extra_seconds, agis_result* out) {
+    std::memset(out, 0, sizeof(*out));
+    const Acc& acc = r.acc;
+    out->estimate = acc.mean;
+    out->copies = r.prep.plan.aut ? acc.mean / (double)r.prep.plan.aut : 0.0;
+    out->variance = acc.n > 0 ? acc.m2 / acc.n : 0.0;
+    out->eps_hat = eps_hat_of(acc, z);
+    out->n = (uint64_t)acc.n;
+    out->n_nonzero = (uint64_t)acc.nonzero;
+    out->aut = r.prep.plan.aut;
+    out->converged = r.converged ? 1 : 0;
+    out->seconds = r.seconds + extra_seconds;
+    out->tables_seconds = r.prep.tables_seconds;
+    out->sample_kernel_seconds = r.kernel_seconds;
+    out->sample_launches = r.launches;
+    out->plan = r.prep.plan;
 }
 
 int check_handles(const agis_ctx* ctx, const agis_graph* g, const agis_tables* t) {
@@ -210,8 +375,12 @@ int agis_create(agis_ctx** out, int device, void* hip_stream) {
         e = hipGetDeviceProperties(&prop, device);
         if (e == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
     }
-    if (e == hipSuccess) e = hipMalloc(&ctx->d_plan, sizeof(DevPlan));
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_plans, agis::kMaxSegs * sizeof(DevPlan));
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_launch, sizeof(agis::LaunchDesc));
     if (e == hipSuccess) e = hipMalloc(&ctx->d_small, 4096);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&ctx->ev_stop);
     if (e == hipSuccess) e = agis::upload_fixed_point_tables(ctx->stream);
@@ -226,7 +395,13 @@ int agis_create(agis_ctx** out, int device, void* hip_stream) {
 void agis_destroy(agis_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    if (ctx->d_plan) (void)hipFree(ctx->d_plan);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->d_plans) (void)hipFree(ctx->d_plans);
+    if (ctx->d_launch) (void)hipFree(ctx->d_launch);
     if (ctx->d_small) (void)hipFree(ctx->d_small);
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
@@ -356,62 +531,51 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     if (pp->eps > 0 && !(pp->delta > 0 && pp->delta < 1)) return fail(ctx, AGIS_E_INVALID_ARG, "delta must be in (0, 1)");
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
     const auto t0 = std::chrono::steady_clock::now();
-    Prepared prep;
-    rc = prepare(ctx, g, t, p, order, pp, n_samples, &prep);
+    std::vector<PatternRun> runs(1);
+    rc = prepare(ctx, g, t, p, order, pp, n_samples, &runs[0].prep);
     if (rc != AGIS_OK) return rc;
-    const bool to_eps = pp->eps > 0;
-    const uint64_t batch = to_eps ? (pp->check_every ? pp->check_every : 65536) : n_samples;
-    const double z = normal_quantile(1.0 - (to_eps ? pp->delta : 0.05) / 2.0);
-    Acc acc;
-    bool converged = false;
-    uint64_t done = 0;
-    double kernel_seconds = 0.0;
-    uint64_t launches = 0;
-    if (n_samples > 0) {
-        agis::SampleLaunch L = agis::plan_sample_launch(ctx, *g, batch < n_samples ? batch : n_samples, &ctx->err, &rc);
+    runs[0].budget = n_samples;
+    const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rc = run_rounds(ctx, g, t, runs, pp, seed);
+    if (rc != AGIS_OK) return rc;
+    const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
+    fill_result(runs[0], z, setup, out);
+    if (pp->eps > 0 && !runs[0].converged) return fail(ctx, AGIS_E_NOT_CONVERGED, "sample budget reached before eps");
+    return AGIS_OK;
+}
+
+int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint32_t n_patterns,
+                        const agis_pattern* patterns, const uint64_t* budgets, uint64_t seed,
+                        const agis_run_params* params, agis_result* out) {
+    int rc = check_handles(ctx, g, t);
+    if (rc != AGIS_OK) return ctx ? fail(ctx, rc, "bad handle") : rc;
+    if (n_patterns == 0 || n_patterns > agis::kMaxSegs) return fail(ctx, AGIS_E_INVALID_ARG, "1..64 patterns per batch");
+    if (!patterns || !budgets || !out) return fail(ctx, AGIS_E_INVALID_ARG, "null pattern, budget or result array");
+    const agis_run_params dp = default_params();
+    const agis_run_params* pp = params ? params : &dp;
+    if (pp->eps > 0 && !(pp->delta > 0 && pp->delta < 1)) return fail(ctx, AGIS_E_INVALID_ARG, "delta must be in (0, 1)");
+    if (pp->mode == AGIS_MODE_LEARNED) return fail(ctx, AGIS_E_INVALID_ARG, "learned tables are per pattern: use agis_estimate");
+    AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<PatternRun> runs(n_patterns);
+    for (uint32_t i = 0; i < n_patterns; ++i) {
+        agis_run_params pi = *pp;
+        pi.pattern_id = pp->pattern_id + i;
+        rc = prepare(ctx, g, t, &patterns[i], nullptr, &pi, budgets[i], &runs[i].prep);
         if (rc != AGIS_OK) return rc;
-        std::vector<Partial> parts;
-        const agis::DevTables dt{t->rec};
-        while (done < n_samples) {
-            const uint64_t cnt = (n_samples - done) < batch ? (n_samples - done) : batch;
-            AGIS_HIP(ctx,
-                     agis::launch_sample(ctx, L, g->g, dt, prep.s1, (uint32_t)seed, (uint32_t)(seed >> 32), done, cnt,
-                                         nullptr, nullptr, ctx->ev_start, ctx->ev_stop),
-                     "launch sampler");
-            AGIS_HIP(ctx, agis::launch_reduce(ctx, L, cnt), "launch reduction");
-            parts.resize((size_t)((cnt + agis::kReduceTileSamples - 1) / agis::kReduceTileSamples));
-            AGIS_HIP(ctx,
-                     hipMemcpyAsync(parts.data(), ctx->d_partials, parts.size() * sizeof(Partial),
-                                    hipMemcpyDeviceToHost, ctx->stream),
-                     "read partials");
-            AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "sampler");
-            float ms = 0.0f;
-            AGIS_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop), "event time");
-            kernel_seconds += 1e-3 * (double)ms;
-            ++launches;
-            for (const Partial& q : parts) acc.merge(q);
-            done += cnt;
-            if (to_eps && done >= pp->min_samples && eps_hat_of(acc, z) <= pp->eps) {
-                converged = true;
-                break;
-            }
-        }
+        runs[i].budget = budgets[i];
+        runs[i].active = budgets[i] > 0;
     }
-    std::memset(out, 0, sizeof(*out));
-    out->estimate = acc.mean;
-    out->copies = prep.plan.aut ? acc.mean / (double)prep.plan.aut : 0.0;
-    out->variance = acc.n > 0 ? acc.m2 / acc.n : 0.0;
-    out->eps_hat = eps_hat_of(acc, z);
-    out->n = (uint64_t)acc.n;
-    out->n_nonzero = (uint64_t)acc.nonzero;
-    out->aut = prep.plan.aut;
-    out->converged = converged ? 1 : 0;
-    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    out->tables_seconds = prep.tables_seconds;
-    out->sample_kernel_seconds = kernel_seconds;
-    out->sample_launches = launches;
-    out->plan = prep.plan;
-    if (to_eps && !converged) return fail(ctx, AGIS_E_NOT_CONVERGED, "sample budget reached before eps");
+    const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rc = run_rounds(ctx, g, t, runs, pp, seed);
+    if (rc != AGIS_OK) return rc;
+    const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
+    bool all = true;
+    for (uint32_t i = 0; i < n_patterns; ++i) {
+        fill_result(runs[i], z, setup, &out[i]);
+        all = all && runs[i].converged;
+    }
+    if (pp->eps > 0 && !all) return fail(ctx, AGIS_E_NOT_CONVERGED, "a pattern reached its budget before eps");
     return AGIS_OK;
 }
 
@@ -429,15 +593,90 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     rc = prepare(ctx, g, t, p, order, pp, m, &prep);
     if (rc != AGIS_OK) return rc;
     if (m == 0) return AGIS_OK;
-    agis::SampleLaunch L = agis::plan_sample_launch(ctx, *g, m, &ctx->err, &rc);
+    if (m > kMaxRoundSlots) return fail(ctx, AGIS_E_INVALID_ARG, "at most 2^24 records per call");
+    agis::SampleLaunch L;
+    rc = agis::plan_sample_launch(ctx, *g, m, 1, &L, &ctx->err);
     if (rc != AGIS_OK) return rc;
-    const agis::DevTables dt{t->rec};
-    AGIS_HIP(ctx,
-             agis::launch_sample(ctx, L, g->g, dt, prep.s1, (uint32_t)seed, (uint32_t)(seed >> 32), 0, m, idx,
-                                 (agis::Record*)out, nullptr, nullptr),
-             "launch sampler");
+    L.dump = true;
+    agis::LaunchDesc ld;
+    std::memset(&ld, 0, sizeof(ld));
+    agis::fill_launch(ctx, L, g->g, agis::DevTables{t->rec}, idx, (agis::Record*)out, &ld);
+    agis::RoundDesc& rd = ld.round;
+    rd.total = m;
+    rd.nseg = 1;
+    rd.k0 = (uint32_t)seed;
+    rd.k1 = (uint32_t)(seed >> 32);
+    rd.seg[0].count = m;
+    rd.seg[0].ntiles = (uint32_t)((m + agis::kReduceTileSamples - 1) / agis::kReduceTileSamples);
+    AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_plans, &prep.hp, sizeof(DevPlan), hipMemcpyHostToDevice, ctx->stream),
+             "upload plan");
+    AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_launch, &ld, sizeof(ld), hipMemcpyHostToDevice, ctx->stream), "upload round");
+    AGIS_HIP(ctx, agis::launch_round(ctx, ctx->stream, L, nullptr, nullptr), "launch sampler");
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "sampler");
     return AGIS_OK;
+}
+
+int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant) {
+    if (!ctx || blocks_per_cu < 0 || grab > 1024 || variant < 0 || variant > 2) return AGIS_E_INVALID_ARG;
+    ctx->use_graphs = use_graphs ? 1 : 0;
+    ctx->tune_blocks_per_cu = blocks_per_cu;
+    ctx->tune_grab = grab;
+    ctx->tune_variant = variant;
+    return AGIS_OK;
+}
+
+int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint32_t n_patterns,
+                  const agis_pattern* patterns, uint64_t pilot_samples, const agis_run_params* params,
+                  agis_tuning* out) {
+    int rc = check_handles(ctx, g, t);
+    if (rc != AGIS_OK) return ctx ? fail(ctx, rc, "bad handle") : rc;
+    if (!patterns || !out || n_patterns == 0 || n_patterns > agis::kMaxSegs || pilot_samples == 0)
+        return fail(ctx, AGIS_E_INVALID_ARG, "1..64 patterns and a nonzero pilot size");
+    agis_run_params pp = params ? *params : default_params();
+    pp.eps = 0.0;  // pilots run fixed budgets
+    if (pp.mode == AGIS_MODE_LEARNED) pp.mode = AGIS_MODE_SWITCH;
+    std::vector<uint64_t> budgets(n_patterns, pilot_samples);
+    std::vector<agis_result> res(n_patterns);
+    const int saved_graphs = ctx->use_graphs, saved_blocks = ctx->tune_blocks_per_cu, saved_variant = ctx->tune_variant;
+    const uint32_t saved_grab = ctx->tune_grab;
+    struct Cand {
+        int variant;
+        uint32_t grab;
+    };
+    const Cand cands[] = {{0, 0}, {1, 0}, {2, 0}, {0, 1}, {1, 1}, {2, 1}, {0, 4}, {1, 4}, {2, 4}};
+    double best = INFINITY, first = 0.0;
+    Cand best_c = cands[0];
+    for (const Cand& c : cands) {
+        ctx->use_graphs = 1;
+        ctx->tune_blocks_per_cu = 0;
+        ctx->tune_variant = c.variant;
+        ctx->tune_grab = c.grab;
+        double secs = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {  // first repetition warms caches and captures the graph
+            rc = agis_estimate_batch(ctx, g, t, n_patterns, patterns, budgets.data(), 0x5eed, &pp, res.data());
+            if (rc != AGIS_OK) break;
+            if (rep == 1)
+                for (const agis_result& r : res) secs += r.sample_kernel_seconds;
+        }
+        if (rc != AGIS_OK) break;
+        if (&c == &cands[0]) first = secs;
+        if (secs < best) {
+            best = secs;
+            best_c = c;
+        }
+    }
+    ctx->use_graphs = saved_graphs;
+    ctx->tune_blocks_per_cu = saved_blocks;
+    ctx->tune_variant = saved_variant;
+    ctx->tune_grab = saved_grab;
+    if (rc != AGIS_OK) return rc;
+    out->use_graphs = 1;
+    out->blocks_per_cu = 0;
+    out->grab = best_c.grab;
+    out->variant = best_c.variant;
+    out->seconds = best;
+    out->default_seconds = first;
+    return agis_set_launch(ctx, 1, 0, best_c.grab, best_c.variant);
 }
 
 int agis_fixed_point_tables(int32_t* logtab, uint32_t* exp2tab) {

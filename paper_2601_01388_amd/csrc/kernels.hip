@@ -168,7 +168,7 @@ __device__ __forceinline__ uint32_t row_of_slot(const uint64_t* __restrict__ off
 // given a non-decreasing and a[n - 1] > r.  Every lane returns the answer.
 // Comparisons are of a[p] - base (modulo 2^64), so a prefix may be read
 // relative to the entry before its segment.
-__device__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r, uint64_t base = 0) {
+__device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r, uint64_t base = 0) {
     const int lane = lane_id();
     uint64_t lo = 0, hi = n - 1;  // answer in [lo, hi], a[hi] - base > r
     while (hi - lo + 1 > (uint64_t)kWave) {
@@ -196,7 +196,7 @@ __device__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t 
 
 // Wave-cooperative: first position p in [lo, hi) with list[p] > key, or hi
 // when there is none (list ascending).
-__device__ uint32_t wave_first_greater_u32(const uint32_t* __restrict__ list, uint32_t lo, uint32_t hi, uint32_t key) {
+__device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __restrict__ list, uint32_t lo, uint32_t hi, uint32_t key) {
     const int lane = lane_id();
     while (hi - lo > (uint32_t)kWave) {  // answer in [lo, hi]
         const uint32_t step = (hi - lo + kWave - 1) >> 6;
@@ -692,7 +692,8 @@ namespace {
 // rec != nullptr.  `my_tau` of lane j holds the data vertex matched at step
 // j (wave-uniform by construction).  sv/sl: this wave's scratch for the
 // candidate vertices and their log weights (capacity >= max degree).
-__device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P, const Step1& s1,
+template <bool kDump>
+__device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P,
                              uint32_t k0, uint32_t k1, uint64_t s, uint32_t* __restrict__ sv,
                              int32_t* __restrict__ sl, Record* __restrict__ rec) {
     const int lane = lane_id();
@@ -708,14 +709,14 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
         uint32_t v;
         if (i == 0) {
             if (P->weighted[0]) {
-                if (s1.total == 0) {
+                if (P->s1_total == 0) {
                     fail = 0;
                     break;
                 }
-                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, s1.total);
-                v = (uint32_t)wave_first_greater(s1.pre, g.n, r);
-                num = s1.total;
-                den = s1.q1[v];
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, P->s1_total);
+                v = (uint32_t)wave_first_greater(P->s1_pre, g.n, r);
+                num = P->s1_total;
+                den = P->s1_q[v];
             } else {
                 if (g.nnz == 0) {
                     fail = 0;
@@ -958,14 +959,14 @@ __device__ double sample_one(const DevGraph& g, const DevTables& t, const DevPla
             x = x * ((double)num / (double)den);
         }
         if ((uint32_t)lane == i) my_tau = v;
-        if (rec && lane == 0) {
+        if (kDump && lane == 0) {
             rec->v[i] = v;
             rec->num[i] = num;
             rec->den[i] = den;
         }
     }
     if (fail >= 0) x = 0.0;
-    if (rec && lane == 0) {
+    if (kDump && lane == 0) {
         for (uint32_t j = i; j < (uint32_t)kMaxK; ++j) {
             rec->v[j] = 0;
             rec->num[j] = 0;
@@ -992,56 +993,78 @@ __device__ __forceinline__ Partial chan_merge(Partial a, const Partial& b) {
     return a;
 }
 
-// Persistent sampler: each wave repeatedly takes the next `grab` sample
-// slots from a device-wide counter (so heavy and light samples balance),
-// runs them one at a time and stores each weight at its slot.  A sample's
-// result does not depend on which wave runs it.
-__global__ __launch_bounds__(256) void k_sample(DevGraph g, DevTables t, const DevPlan* __restrict__ P, Step1 s1,
-                                                 uint32_t k0, uint32_t k1, uint64_t start, uint64_t count,
-                                                 const uint64_t* __restrict__ idx, Record* __restrict__ dump,
-                                                 uint32_t* __restrict__ scratch, uint64_t cap,
-                                                 unsigned long long* __restrict__ queue, uint32_t grab,
-                                                 double* __restrict__ xout) {
+// Persistent sampler over one round: slots [0, total) are the concatenated
+// segments of the round (pattern plan, first sample index, slot range).
+// Each wave repeatedly takes the next `grab` slots from a device-wide
+// counter (so heavy and light samples balance across waves), runs them one
+// at a time and stores each weight at its slot.  The next grab is requested
+// before the current one is processed, so the atomic's round trip overlaps
+// sampling work.  A sample's result does not depend on which wave runs it.
+// kDump: the record-writing variant (index lists and records), compiled
+// apart so the production kernel carries none of that state.  kWavesPerEU:
+// register budget of the variant -- at least that many waves per SIMD must
+// fit (4 leaves the compiler its own choice here; 5 and 6 trade a few
+// spills for more resident waves); the autotuner picks the fastest.
+template <bool kDump, int kWavesPerEU>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU)))
+void k_sample(const LaunchDesc* __restrict__ D) {
     const int lane = lane_id();
     const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    uint32_t* sv = scratch + gw * cap * 2;
+    const uint64_t cap = D->cap;
+    uint32_t* sv = D->scratch + gw * cap * 2;
     int32_t* sl = (int32_t*)(sv + cap);
-    // the next grab is requested before the current one is processed, so the
-    // atomic's round trip overlaps sampling work
+    const RoundDesc* __restrict__ round = &D->round;
+    const uint64_t total = round->total;
+    const uint32_t grab = D->grab;
+    uint32_t sg = 0;  // segment of the current slot (slots a wave takes only increase)
     unsigned long long cur = 0;
-    if (lane == 0) cur = atomicAdd(queue, (unsigned long long)grab);
+    if (lane == 0) cur = atomicAdd(D->queue, (unsigned long long)grab);
     cur = __shfl(cur, 0, kWave);
-    while (cur < count) {
+    while (cur < total) {
         unsigned long long next = 0;
-        if (lane == 0) next = atomicAdd(queue, (unsigned long long)grab);
-        const uint64_t j1 = (cur + grab) < count ? (cur + grab) : count;
+        if (lane == 0) next = atomicAdd(D->queue, (unsigned long long)grab);
+        const uint64_t j1 = (cur + grab) < total ? (cur + grab) : total;
         for (uint64_t j = cur; j < j1; ++j) {
-            const uint64_t s = idx ? idx[j] : start + j;
-            const double xv = sample_one(g, t, P, s1, k0, k1, s, sv, sl, dump ? dump + j : nullptr);
-            if (lane == 0) xout[j] = xv;
+            while (sg + 1 < round->nseg && j >= round->seg[sg].base + round->seg[sg].count) ++sg;
+            const Segment& S = round->seg[sg];
+            const uint64_t off = j - S.base;
+            const uint64_t sidx = kDump ? D->idx[off] : S.start + off;
+            Record* rec = kDump ? D->dump + j : nullptr;
+            const double xv =
+                sample_one<kDump>(D->g, D->t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec);
+            if (lane == 0) D->xout[j] = xv;
         }
         cur = __shfl(next, 0, kWave);
     }
 }
 
-// Estimator statistics of a batch of weights in a fixed order: each tile
-// of kReduceTile consecutive weights gives one (n, mean, M2, nonzero);
-// threads run Welford over 8 consecutive weights, then merge pairwise in a
-// fixed tree.  The result depends only on the weights, not on the launch
-// that produced them.
+// Estimator statistics of a round's weights in a fixed order: each segment
+// is cut into tiles of kReduceTile consecutive slots; threads run Welford
+// over 8 consecutive weights, then merge pairwise in a fixed tree.  The
+// result depends only on the weights and the segment lengths, not on the
+// launch that produced the weights.
 constexpr int kReducePer = 8;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceTile = kReducePer * kReduceThreads;
 static_assert(kReduceTile == kReduceTileSamples, "tile size");
 
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_x(const double* __restrict__ xs, uint64_t count,
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_x(const LaunchDesc* __restrict__ D,
                                                               Partial* __restrict__ tiles) {
-    const uint64_t base = (uint64_t)blockIdx.x * kReduceTile + (uint64_t)threadIdx.x * kReducePer;
+    const RoundDesc* __restrict__ round = &D->round;
+    const double* __restrict__ xs = D->xout;
+    const uint32_t nseg = round->nseg;
+    if (nseg == 0 || blockIdx.x >= round->seg[nseg - 1].tile_base + round->seg[nseg - 1].ntiles) return;
+    uint32_t sg = 0;
+    while (sg + 1 < nseg && blockIdx.x >= round->seg[sg + 1].tile_base) ++sg;
+    const Segment& S = round->seg[sg];
+    const uint64_t t0 = (uint64_t)(blockIdx.x - S.tile_base) * kReduceTile;
+    const uint64_t lim = S.count;
+    const uint64_t first = t0 + (uint64_t)threadIdx.x * kReducePer;
     Partial a{0.0, 0.0, 0.0, 0.0};
     for (int j = 0; j < kReducePer; ++j) {
-        const uint64_t p = base + j;
-        if (p >= count) break;
-        const double x = xs[p];
+        const uint64_t p = first + j;
+        if (p >= lim) break;
+        const double x = xs[S.base + p];
         a.n += 1.0;
         const double d = x - a.mean;
         a.mean += d / a.n;
@@ -1068,91 +1091,121 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_x(const double* __res
     }
 }
 
-SampleLaunch plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t count, std::string* err, int* rc) {
-    SampleLaunch L;
-    L.threads = 256;
-    L.cap = (uint64_t)g.max_deg + 1;
-    const uint64_t per_wave = L.cap * 2 * sizeof(uint32_t);
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+const void* sample_kernel(bool dump, int variant) {
+    switch (variant) {
+        case 1:
+            return dump ? reinterpret_cast<const void*>(k_sample<true, 5>) : reinterpret_cast<const void*>(k_sample<false, 5>);
+        case 2:
+            return dump ? reinterpret_cast<const void*>(k_sample<true, 6>) : reinterpret_cast<const void*>(k_sample<false, 6>);
+        default:
+            return dump ? reinterpret_cast<const void*>(k_sample<true, 4>) : reinterpret_cast<const void*>(k_sample<false, 4>);
+    }
+}
+
+int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, uint32_t max_segs, SampleLaunch* L,
+                       std::string* err) {
+    L->threads = 256;
+    L->cap = (uint64_t)g.max_deg + 1;
+    const uint64_t per_wave = L->cap * 2 * sizeof(uint32_t);
     const uint64_t budget = 8ull << 30;  // scratch budget
-    if (ctx->sample_blocks_per_cu == 0) {
+    L->variant = ctx->tune_variant;
+    int& cached = ctx->sample_blocks_per_cu[L->variant];
+    if (cached == 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sample), L.threads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel(false, ctx->tune_variant), L->threads, 0) !=
                 hipSuccess ||
             nb < 1)
             nb = 4;
-        ctx->sample_blocks_per_cu = nb;
+        cached = nb;
     }
-    // as many waves as can be resident at once: a persistent grid
-    uint64_t waves = (uint64_t)ctx->num_cus * (uint64_t)ctx->sample_blocks_per_cu * 4;
+    // as many waves as can be resident at once (a persistent grid), scaled
+    // by the tuning fraction
+    uint64_t blocks_per_cu = (uint64_t)cached;
+    if (ctx->tune_blocks_per_cu > 0 && (uint64_t)ctx->tune_blocks_per_cu < blocks_per_cu)
+        blocks_per_cu = (uint64_t)ctx->tune_blocks_per_cu;
+    uint64_t waves = (uint64_t)ctx->num_cus * blocks_per_cu * 4;
     if (waves * per_wave > budget) waves = budget / per_wave;
     if (waves < 4) {
         *err = "maximum degree too large for the sampler scratch budget";
-        *rc = AGIS_E_UNSUPPORTED;
-        return L;
+        return AGIS_E_UNSUPPORTED;
     }
-    const uint64_t need = (count + 3) / 4 * 4;
+    const uint64_t need = (max_slots + 3) / 4 * 4;
     if (waves > need) waves = need < 4 ? 4 : need;
-    L.blocks = (int)(waves / 4);
-    const uint64_t per = count / (waves * 32);
-    L.grab = (uint32_t)(per < 1 ? 1 : (per > 8 ? 8 : per));
-    const uint64_t bytes = (uint64_t)L.blocks * 4 * per_wave;
+    L->blocks = (int)(waves / 4);
+    if (ctx->tune_grab > 0) {
+        L->grab = ctx->tune_grab;
+    } else {
+        const uint64_t per = max_slots / (waves * 32);
+        L->grab = (uint32_t)(per < 1 ? 1 : (per > 8 ? 8 : per));
+    }
+    const uint64_t bytes = (uint64_t)L->blocks * 4 * per_wave;
     if (ctx->scratch_bytes < bytes) {
         if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
         ctx->d_scratch = nullptr;
         ctx->scratch_bytes = 0;
         if (hipMalloc(&ctx->d_scratch, bytes) != hipSuccess) {
             *err = "could not allocate sampler scratch";
-            *rc = AGIS_E_OOM;
-            return L;
+            return AGIS_E_OOM;
         }
         ctx->scratch_bytes = bytes;
     }
-    const uint64_t tiles = (count + kReduceTile - 1) / kReduceTile;
-    if (ctx->partials_cap < (size_t)tiles) {
+    L->max_tiles = (max_slots + kReduceTile - 1) / kReduceTile + max_segs;
+    if (ctx->partials_cap < (size_t)L->max_tiles) {
         if (ctx->d_partials) (void)hipFree(ctx->d_partials);
         ctx->d_partials = nullptr;
         ctx->partials_cap = 0;
-        if (hipMalloc(&ctx->d_partials, (size_t)tiles * sizeof(Partial)) != hipSuccess) {
+        if (hipMalloc(&ctx->d_partials, (size_t)L->max_tiles * sizeof(Partial)) != hipSuccess) {
             *err = "could not allocate partials";
-            *rc = AGIS_E_OOM;
-            return L;
+            return AGIS_E_OOM;
         }
-        ctx->partials_cap = (size_t)tiles;
+        ctx->partials_cap = (size_t)L->max_tiles;
     }
-    if (ctx->xout_cap < count) {
+    if (ctx->xout_cap < max_slots) {
         if (ctx->d_xout) (void)hipFree(ctx->d_xout);
         ctx->d_xout = nullptr;
         ctx->xout_cap = 0;
-        if (hipMalloc(&ctx->d_xout, (size_t)count * sizeof(double)) != hipSuccess) {
+        if (hipMalloc(&ctx->d_xout, (size_t)max_slots * sizeof(double)) != hipSuccess) {
             *err = "could not allocate the sample-weight buffer";
-            *rc = AGIS_E_OOM;
-            return L;
+            return AGIS_E_OOM;
         }
-        ctx->xout_cap = count;
+        ctx->xout_cap = max_slots;
     }
-    L.tiles = tiles;
-    *rc = AGIS_OK;
-    return L;
+    L->max_slots = max_slots;
+    return AGIS_OK;
 }
 
-hipError_t launch_sample(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t,
-                         const Step1& s1, uint32_t k0, uint32_t k1, uint64_t start, uint64_t count, const uint64_t* idx,
-                         Record* dump, hipEvent_t before, hipEvent_t after) {
+void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t, const uint64_t* idx,
+                 Record* dump, LaunchDesc* D) {
+    D->g = g;
+    D->t = t;
+    D->plans = ctx->d_plans;
+    D->idx = idx;
+    D->dump = dump;
+    D->scratch = (uint32_t*)ctx->d_scratch;
+    D->cap = L.cap;
+    D->queue = (unsigned long long*)((char*)ctx->d_small + 64);
+    D->xout = ctx->d_xout;
+    D->grab = L.grab;
+    D->pad = 0;
+}
+
+hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L, hipEvent_t before,
+                        hipEvent_t after) {
     unsigned long long* queue = (unsigned long long*)((char*)ctx->d_small + 64);
-    hipError_t e = hipMemsetAsync(queue, 0, sizeof(unsigned long long), ctx->stream);
+    hipError_t e;
+    // the queue is cleared by a kernel (the sequence may be captured in a graph)
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, queue);
+    if (before && (e = hipEventRecord(before, stream)) != hipSuccess) return e;
+    const LaunchDesc* desc = ctx->d_launch;
+    void* args[] = {(void*)&desc};
+    e = hipLaunchKernel(sample_kernel(L.dump, L.variant), dim3((unsigned)L.blocks), dim3((unsigned)L.threads), args, 0,
+                        stream);
     if (e != hipSuccess) return e;
-    if (before && (e = hipEventRecord(before, ctx->stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sample, dim3((unsigned)L.blocks), dim3((unsigned)L.threads), 0, ctx->stream, g, t,
-                       ctx->d_plan, s1, k0, k1, start, count, idx, dump, (uint32_t*)ctx->d_scratch, L.cap, queue,
-                       L.grab, ctx->d_xout);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (after && (e = hipEventRecord(after, ctx->stream)) != hipSuccess) return e;
-    return hipSuccess;
-}
-
-hipError_t launch_reduce(agis_ctx* ctx, const SampleLaunch& L, uint64_t count) {
-    if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_x, dim3((unsigned)L.tiles), dim3(kReduceThreads), 0, ctx->stream, ctx->d_xout, count,
+    if (after && (e = hipEventRecord(after, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_x, dim3((unsigned)L.max_tiles), dim3(kReduceThreads), 0, stream, ctx->d_launch,
                        ctx->d_partials);
     return hipGetLastError();
 }

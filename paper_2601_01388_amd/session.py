@@ -9,8 +9,10 @@ import ctypes
 import numpy as np
 
 from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, agis_build_proposal_tables,
-               agis_create, agis_destroy, agis_dump_samples, agis_estimate, agis_graph_destroy, agis_load_csr,
-               agis_tables_destroy, agis_tables_export, make_params, make_pattern, lib)
+               agis_autotune, agis_create, agis_destroy, agis_dump_samples, agis_estimate, agis_estimate_batch,
+               agis_graph_destroy,
+               agis_load_csr, agis_set_launch, agis_tables_destroy, agis_tables_export, make_params, make_pattern,
+               lib)
 
 
 def _torch():
@@ -88,6 +90,18 @@ class Session:
     def estimate(self, graph: Graph, tables: Tables, pattern, n_samples: int, seed: int, order=None, **kw):
         p = make_pattern(pattern.k, pattern.adj8())
         return agis_estimate(self.ctx, graph.handle, tables.handle, p, n_samples, seed, make_params(**kw), order=order)
+
+    def estimate_batch(self, graph: Graph, tables: Tables, patterns, budgets, seed: int, **kw):
+        ps = [make_pattern(p.k, p.adj8()) for p in patterns]
+        return agis_estimate_batch(self.ctx, graph.handle, tables.handle, ps, [int(b) for b in budgets], seed,
+                                   make_params(**kw))
+
+    def autotune(self, graph: Graph, tables: Tables, patterns, pilot_samples: int, **kw):
+        ps = [make_pattern(p.k, p.adj8()) for p in patterns]
+        return agis_autotune(self.ctx, graph.handle, tables.handle, ps, pilot_samples, make_params(**kw))
+
+    def set_launch(self, use_graphs=True, blocks_per_cu=0, grab=0, variant=0):
+        agis_set_launch(self.ctx, use_graphs, blocks_per_cu, grab, variant)
 
     def dump(self, graph: Graph, tables: Tables, pattern, seed: int, indices, order=None, **kw) -> np.ndarray:
         torch = _torch()

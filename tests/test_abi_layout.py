@@ -16,6 +16,7 @@ STRUCTS = {
     "agis_plan": A.agis_plan,
     "agis_run_params": A.agis_run_params,
     "agis_result": A.agis_result,
+    "agis_tuning": A.agis_tuning,
 }
 
 
