@@ -133,11 +133,25 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--bytes-records", type=int, default=1500)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run 3 plain device copies of this many bytes (counter calibration) and exit")
     ap.add_argument("--tune-pilot", type=int, default=1 << 18)
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-budget-scale", type=float, default=1.0,
                     help="multiplier on the 32-pattern set's budgets (log-uniform in [1e6, 1e9])")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling hardware byte counters
+        import torch
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -214,15 +228,21 @@ def main():
     mean_bytes = float(np.mean([bytes_per_sample[n] for n in PATTERNS]))
     avg_launch_s = kern_s / launches
     achieved_gbs = mean_bytes * args.samples / avg_launch_s / 1e9
+    # HBM traffic per launch from the committed FETCH_SIZE / WRITE_SIZE
+    # counter runs (calibrated on a plain copy), valid only while the kernel
+    # sources are the ones the counters were taken with; the counters give
+    # bytes per sample (mean over the four patterns), scaled to this launch
     traffic = None
     if os.path.exists(COUNTERS_FILE):
         c = json.load(open(COUNTERS_FILE))
-        if c.get("kernel_source_sha") == kernel_source_hash() and c.get("samples_per_launch") == args.samples:
-            traffic = c.get("hbm_bytes_per_launch")
+        if c.get("kernel_source_sha") == kernel_source_hash():
+            traffic = c["hbm_bytes_per_sample_mean"] * args.samples
     roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_sample", "avg_launch_ms": 1e3 * avg_launch_s,
-                "algorithmic_bytes_per_sample": bytes_per_sample}
+                "algorithmic_bytes_per_launch": mean_bytes * args.samples,
+                "algorithmic_bytes_per_sample": bytes_per_sample,
+                "traffic_gbs": (traffic / avg_launch_s / 1e9) if traffic else None}
 
     # time to +-1% (95% CI) per pattern and proposal mode
     eps_table = {}
