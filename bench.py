@@ -137,6 +137,9 @@ def main():
                     help="only run 3 plain device copies of this many bytes (counter calibration) and exit")
     ap.add_argument("--tune-pilot", type=int, default=1 << 18)
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-learned", action="store_true")
+    ap.add_argument("--train-samples", type=int, default=1 << 20, help="sampler runs producing training targets")
+    ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--batch-budget-scale", type=float, default=1.0,
                     help="multiplier on the 32-pattern set's budgets (log-uniform in [1e6, 1e9])")
     args = ap.parse_args()
@@ -244,20 +247,74 @@ def main():
                 "algorithmic_bytes_per_sample": bytes_per_sample,
                 "traffic_gbs": (traffic / avg_launch_s / 1e9) if traffic else None}
 
+    # learned proposal: one MLP per pattern, trained on extension counts the
+    # sampler produces on a smaller R-MAT graph (scale 18, seed 18), then
+    # BF16 inference into pick tables for this graph
+    learned = {}
+    if not args.skip_learned and not args.skip_eps:
+        from paper_2601_01388_amd.session import mlp_init
+        log("learned proposal: training graph R-MAT scale 18")
+        gtr = synth.rmat(18, 16, seed=18)
+        Gtr = sess.graph(gtr.off, gtr.nbr)
+        Ttr = sess.tables(Gtr, cv_seed=1)
+        ftr = sess.features(Ttr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fev = sess.features(T)
+        torch.cuda.synchronize()
+        feat_s = time.perf_counter() - t0
+        for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
+            t0 = time.perf_counter()
+            steps = sess.weighted_steps(p, "learned")
+            sums, counts = sess.learn_targets(Gtr, Ttr, p, args.train_samples, 101 + pid, mode="switch")
+            rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2)
+            del sums, counts
+            tg = rows["target"].cpu().numpy()
+            wt = rows["weight"].cpu().numpy()
+            params = torch.from_numpy(mlp_init(7 + pid, float(np.average(tg, weights=wt)))).to(sess.device)
+            losses = sess.mlp_train(params, ftr, rows, epochs=args.train_epochs, batch=4096, lr=3e-3, seed=pid)
+            torch.cuda.synchronize()
+            train_s = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            tabs = sess.learned_tables(params, fev, p)
+            torch.cuda.synchronize()
+            infer_s = time.perf_counter() - t0
+            learned[name] = {"tables": tabs, "ptrs": {i: tab.data_ptr() for i, tab in tabs.items()},
+                             "info": {"train_rows": rows["rows"], "train_seconds": train_s,
+                                      "loss_first_last": [losses[0], losses[-1]], "infer_seconds": infer_s,
+                                      "weighted_steps": steps}}
+            log(f"learned {name}: {rows['rows']} rows, train {train_s:.2f} s, loss {losses[0]:.3g} -> "
+                f"{losses[-1]:.3g}, tables {infer_s * 1e3:.1f} ms")
+        Ttr.close()
+        Gtr.close()
+
     # time to +-1% (95% CI) per pattern and proposal mode
     eps_table = {}
     if not args.skip_eps:
         for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
-            for mode in ("switch", "uniform"):
+            for mode in ("learned", "switch", "uniform"):
+                if mode == "learned" and name not in learned:
+                    continue
+                kw = dict(learned=learned[name]["ptrs"]) if mode == "learned" else {}
                 r = sess.estimate(G, T, p, args.eps_budget, 11, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
-                                  check_every=1 << 16, min_samples=1 << 14)
+                                  check_every=1 << 16, min_samples=1 << 14, **kw)
                 need = r.n * (r.eps_hat / 0.01) ** 2 if math.isfinite(r.eps_hat) else None
-                eps_table[f"{name}/{'f_approx' if mode == 'switch' else 'f_uniform'}"] = {
+                label = {"switch": "f_approx", "uniform": "f_uniform", "learned": "learned"}[mode]
+                entry = {
                     "seconds": r.seconds, "converged": bool(r.converged), "samples": r.n, "estimate": r.estimate,
                     "eps_hat": r.eps_hat, "rel_var": r.variance / max(r.estimate ** 2, 1e-300),
                     "samples_needed": need,
                 }
-                log(f"+-1% {name} {mode}: {r.seconds:.3f} s, n={r.n}, converged={bool(r.converged)}")
+                if mode == "learned":
+                    entry["seconds_incl_table_inference"] = r.seconds + learned[name]["info"]["infer_seconds"]
+                    entry.update(learned[name]["info"])
+                eps_table[f"{name}/{label}"] = entry
+                log(f"+-1% {name} {label}: {r.seconds:.3f} s, n={r.n}, rel.var {entry['rel_var']:.4g}, "
+                    f"converged={bool(r.converged)}")
+        for name in PATTERNS:
+            if f"{name}/learned" in eps_table:
+                eps_table[f"{name}/learned"]["rel_var_vs_f_approx"] = (
+                    eps_table[f"{name}/learned"]["rel_var"] / max(eps_table[f"{name}/f_approx"]["rel_var"], 1e-300))
 
     # 32 connected patterns of 4-7 vertices (seed 3) with uneven budgets,
     # all run to +-1% in one batch of rounds (each a persistent launch)

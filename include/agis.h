@@ -276,6 +276,71 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
                       const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
                       uint64_t m, agis_record* out);
 
+/* ---- Learned proposal ------------------------------------------------
+ * A small MLP predicts, for a vertex v and the position of a weighted
+ * step, the log2 of the number of successful extensions when v is picked
+ * there -- the quantity the ideal distribution is proportional to
+ * (Theorem 1, Sec. 4.1).  It is trained on extension counts estimated by
+ * the sampler itself and its predictions become Q16 log2 pick tables
+ * (AGIS_MODE_LEARNED); the importance factors keep the estimate unbiased
+ * (Theorem 2) whatever the network predicts.
+ * Network: x (8) -> 64 GELU -> 64 GELU -> 1, GELU(a) = a Phi(a) (exact erf
+ * form).  x = (log2(1 + d(v)), log2(1 + S2(v)), log2(1 + C_v C(d(v), 2)),
+ * log2(1 + h(v))) and a one-hot of the step position class {1, 2, 3, >= 4},
+ * where h(v) = largest h with at least h neighbours of degree >= h (an
+ * upper bound of the core number).  Parameters: float[4801] =
+ * W1[64][8], b1[64], W2[64][64] (W2[j][i]: output j, input i), b2[64],
+ * w3[64], b3. */
+int agis_mlp_param_count(void);
+
+/* Per-vertex features into feats (device float[n][4], the 4 scalars above). */
+int agis_features(agis_ctx* ctx, const agis_tables* t, float* feats);
+
+/* Training targets: runs samples 0..n_samples-1 of the pattern (mode and
+ * beta from params) and, for every step i of each sample, adds to
+ * sums[i][v_i] (device double[k][n]) the product of the factors of the
+ * steps after i -- an unbiased estimate of the successful extensions of
+ * the prefix ending at v_i, 0 when the sample failed later -- and 1 to
+ * counts[i][v_i] (device uint32[k][n]).  Both are cleared first.  The sums
+ * use FP64 atomics, so their last bits depend on the order of arrival. */
+int agis_learn_targets(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                       const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
+                       double* sums, uint32_t* counts);
+
+/* Training rows from targets: for every step i in step_mask (bit i) and
+ * every vertex v with counts[i][v] >= min_count (and >= 1), one row (vtx v,
+ * cls = position class min(i, 3), target log2(1 + sums/counts), weight
+ * counts), steps ascending then vertices ascending.  sums/counts: device,
+ * as written by agis_learn_targets (k steps, n vertices); outputs: device
+ * arrays of capacity k * n; *rows (host) receives the row count. */
+int agis_learn_rows(agis_ctx* ctx, const double* sums, const uint32_t* counts, uint32_t k, uint64_t n,
+                    uint32_t step_mask, uint32_t min_count, uint32_t* vtx, uint8_t* cls, float* target, float* weight,
+                    uint64_t* rows);
+
+/* Gradient of L = sum_r w_r (y_r - target_r)^2 / weight_sum over `rows`
+ * training rows (device arrays: vtx uint32, cls uint8 position class,
+ * target float, weight float; feats from agis_features) at `params`
+ * (device float[4801]), in FP32 with a fixed summation order.  grad:
+ * device float[4801]; loss: device float[1] or NULL. */
+int agis_mlp_grad(agis_ctx* ctx, const float* params, const float* feats, const uint32_t* vtx, const uint8_t* cls,
+                  const float* target, const float* weight, uint64_t rows, float weight_sum, float* grad, float* loss);
+
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on minibatches
+ * of `batch` rows of a per-epoch shuffle (host generator seeded with
+ * shuffle_seed), for `epochs` epochs; updates params in place.
+ * loss_per_epoch: host float[epochs] or NULL. */
+int agis_mlp_train(agis_ctx* ctx, float* params, const float* feats, const uint32_t* vtx, const uint8_t* cls,
+                   const float* target, const float* weight, uint64_t rows, uint32_t epochs, uint32_t batch,
+                   float lr, uint64_t shuffle_seed, float* loss_per_epoch);
+
+/* Inference for every vertex at one position class (0..3): BF16 matrix-core
+ * products with FP32 accumulation for the 64 x 64 layer, FP32 elsewhere.
+ * lt: device int32[n] = round(2^16 y), the Q16 log2 pick table consumed by
+ * AGIS_MODE_LEARNED (certain zeros are still decided by degree at pick
+ * time); y: device float[n] or NULL. */
+int agis_mlp_infer(agis_ctx* ctx, const float* params, const float* feats, uint64_t n, uint32_t position_class,
+                   int32_t* lt, float* y);
+
 /* Host copies of the library's Q16 tables (4096 entries each), its Philox
  * block function and its bounded draw -- for host-side tests. */
 int agis_fixed_point_tables(int32_t* logtab, uint32_t* exp2tab);

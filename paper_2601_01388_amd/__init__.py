@@ -125,6 +125,16 @@ _SIGNATURES = [
     ("agis_set_launch", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32]),
     ("agis_autotune", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, ctypes.c_uint64,
                                      ctypes.POINTER(agis_run_params), ctypes.POINTER(agis_tuning)]),
+    ("agis_mlp_param_count", ctypes.c_int, []),
+    ("agis_features", ctypes.c_int, [_P, _P, _P]),
+    ("agis_learn_targets", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.POINTER(agis_run_params), _P, _P]),
+    ("agis_learn_rows", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                       _P, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("agis_mlp_grad", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_float, _P, _P]),
+    ("agis_mlp_train", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_float, ctypes.c_uint64, _P]),
+    ("agis_mlp_infer", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P]),
     ("agis_fixed_point_tables", ctypes.c_int, [_P, _P]),
     ("agis_philox4x32_10", ctypes.c_int, [_P, _P, _P]),
 ]
@@ -280,6 +290,48 @@ def agis_autotune(ctx, g, t, patterns, pilot_samples: int, params: agis_run_para
     _check(ctx, lib().agis_autotune(ctx, g, t, n, ctypes.cast(arr, _P), pilot_samples, ctypes.byref(params),
                                     ctypes.byref(out)))
     return out
+
+
+def agis_mlp_param_count() -> int:
+    return int(lib().agis_mlp_param_count())
+
+
+def agis_features(ctx, t, feats_ptr: int):
+    _check(ctx, lib().agis_features(ctx, t, feats_ptr))
+
+
+def agis_learn_targets(ctx, g, t, pattern: agis_pattern, n_samples: int, seed: int, params: agis_run_params,
+                       sums_ptr: int, counts_ptr: int, order=None):
+    keep, ptr = _order_arg(order)
+    _check(ctx, lib().agis_learn_targets(ctx, g, t, ctypes.byref(pattern), ptr, n_samples, seed, ctypes.byref(params),
+                                         sums_ptr, counts_ptr))
+    del keep
+
+
+def agis_learn_rows(ctx, sums_ptr, counts_ptr, k, n, step_mask, min_count, vtx_ptr, cls_ptr, target_ptr,
+                    weight_ptr) -> int:
+    rows = ctypes.c_uint64()
+    _check(ctx, lib().agis_learn_rows(ctx, sums_ptr, counts_ptr, k, n, step_mask, min_count, vtx_ptr, cls_ptr,
+                                      target_ptr, weight_ptr, ctypes.byref(rows)))
+    return int(rows.value)
+
+
+def agis_mlp_grad(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, weight_ptr, rows, weight_sum, grad_ptr,
+                  loss_ptr=0):
+    _check(ctx, lib().agis_mlp_grad(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, weight_ptr, rows,
+                                    weight_sum, grad_ptr, loss_ptr or None))
+
+
+def agis_mlp_train(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, weight_ptr, rows, epochs, batch, lr,
+                   shuffle_seed):
+    losses = (ctypes.c_float * max(epochs, 1))()
+    _check(ctx, lib().agis_mlp_train(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, weight_ptr, rows,
+                                     epochs, batch, lr, shuffle_seed, ctypes.cast(losses, _P)))
+    return [float(x) for x in losses[:epochs]]
+
+
+def agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr=0):
+    _check(ctx, lib().agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr or None))
 
 
 def agis_fixed_point_tables():

@@ -1,0 +1,556 @@
+// Learned proposal: per-vertex features, training targets produced by the
+// sampler itself, an 8 -> 64 -> 64 -> 1 GELU MLP trained with this file's
+// forward/backward kernels (FP32, deterministic reductions, Adam), and
+// BF16 MFMA inference quantised into Q16 log2 pick tables that the sampler
+// reads in its learned mode.
+//
+// Parameter layout (float[kMlpParams]): W1[64][8], b1[64], W2[64][64]
+// (W2[j][i]: output j, input i), b2[64], w3[64], b3.
+// Input row: the 4 vertex features (log2(1 + d), log2(1 + S2),
+// log2(1 + estimated triangles), log2(1 + h-index of neighbour degrees))
+// followed by a one-hot of the step's position class {1, 2, 3, >=4}.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "agis.h"
+#include "agis_internal.h"
+
+namespace agis {
+
+constexpr int kH = 64;
+constexpr int kIn = 8;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kH * kIn;
+constexpr int kOffW2 = kOffB1 + kH;
+constexpr int kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH;
+constexpr int kOffB3 = kOffW3 + kH;
+constexpr int kMlpParams = kOffB3 + 1;
+static_assert(kMlpParams == 4801, "parameter count");
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float a) {
+    return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * expf(-0.5f * a * a);
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ list, uint32_t len, uint32_t x) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (list[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Features: one wave per vertex (grid-stride).  The h-index of the
+// neighbour degrees -- the largest h with at least h neighbours of degree
+// >= h, an upper bound of the core number -- is found by bisection over h
+// with a wave-wide count per probe.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_features(DevGraph g, const uint4* __restrict__ rec,
+                                                  const uint64_t* __restrict__ s2, const uint64_t* __restrict__ hits,
+                                                  const uint64_t* __restrict__ trials, float* __restrict__ feats) {
+    const int lane = lane_id();
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t v = gw; v < g.n; v += nw) {
+        const uint64_t o = g.off[v];
+        const uint32_t d = (uint32_t)(g.off[v + 1] - o);
+        uint32_t lo = 0, hi = d;  // h in [lo, hi]
+        while (lo < hi) {
+            const uint32_t h = (lo + hi + 1) >> 1;
+            uint32_t c = 0;
+            for (uint32_t e = (uint32_t)lane; e < d; e += kWave) c += rec[g.nbr[o + e]].x >= h ? 1u : 0u;
+#pragma unroll
+            for (int s = 32; s > 0; s >>= 1) c += __shfl_xor(c, s, kWave);
+            if (c >= h)
+                lo = h;
+            else
+                hi = h - 1;
+        }
+        if (lane == 0) {
+            const double tri = trials[v] ? (double)hits[v] / (double)trials[v] * 0.5 * (double)d * (double)(d - 1) : 0.0;
+            float* f = feats + v * 4;
+            f[0] = (float)log2(1.0 + (double)d);
+            f[1] = (float)log2(1.0 + (double)s2[v]);
+            f[2] = (float)log2(1.0 + tri);
+            f[3] = (float)log2(1.0 + (double)lo);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training targets from sample records: for a successful sample and step i,
+// R_i = product of the factors num_t / den_t of the steps t > i (in FP64,
+// from the last step backwards) estimates the number of successful
+// extensions of the prefix v_1..v_i without bias; a sample that failed
+// after step i contributes R_i = 0.  Sums and counts per (step, vertex).
+// ---------------------------------------------------------------------------
+__global__ void k_targets(const Record* __restrict__ recs, uint64_t m, uint32_t k, uint64_t n,
+                          double* __restrict__ sums, uint32_t* __restrict__ counts) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const Record& r = recs[j];
+    const int steps = r.steps;
+    const bool ok = r.fail_step < 0;
+    double prod = 1.0;
+    for (int i = (int)k - 1; i >= 0; --i) {
+        if (i < steps) {
+            const double R = ok ? prod : 0.0;
+            atomicAdd(&sums[(uint64_t)i * n + r.v[i]], R);
+            atomicAdd(&counts[(uint64_t)i * n + r.v[i]], 1u);
+        }
+        if (ok && i > 0) prod = prod * ((double)r.num[i] / (double)r.den[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training: per tile of 64 rows (one wave), forward and backward in FP32;
+// the tile's parameter gradient is summed over its rows in row order and
+// written to its own slot; k_mlp_reduce adds the slots in tile order, so
+// the gradient does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 64;
+
+__global__ __launch_bounds__(kTile) void k_mlp_grad(const float* __restrict__ params, const float* __restrict__ feats,
+                                                    const uint32_t* __restrict__ vtx, const uint8_t* __restrict__ cls,
+                                                    const float* __restrict__ target, const float* __restrict__ weight,
+                                                    const uint32_t* __restrict__ order, uint64_t rows, float inv_wsum,
+                                                    float* __restrict__ partial, float* __restrict__ loss_part) {
+    // activations are stored [unit][row] with one padding column so that both
+    // per-row (forward) and per-unit (gradient) walks avoid bank conflicts
+    constexpr int kLd = kTile + 1;
+    __shared__ float P[kMlpParams];
+    __shared__ float X[kIn][kLd];
+    __shared__ float H1[kH][kLd];
+    __shared__ float G1[kH][kLd];  // GELU'(layer-1 pre-activation), later dL/d(pre1)
+    __shared__ float H2[kH][kLd];
+    __shared__ float D2[kH][kLd];  // dL/d(pre2)
+    __shared__ float DY[kTile];
+    const int t = threadIdx.x;
+    for (int p = t; p < kMlpParams; p += kTile) P[p] = params[p];
+    const uint64_t rix = (uint64_t)blockIdx.x * kTile + (uint64_t)t;
+    float w = 0.0f, tgt = 0.0f;
+    float x[kIn];
+    for (int c = 0; c < kIn; ++c) x[c] = 0.0f;
+    if (rix < rows) {
+        const uint32_t ri = order ? order[rix] : (uint32_t)rix;
+        const uint32_t v = vtx[ri];
+        for (int c = 0; c < 4; ++c) x[c] = feats[(uint64_t)v * 4 + c];
+        x[4 + (cls[ri] < 3 ? cls[ri] : 3)] = 1.0f;
+        w = weight[ri];
+        tgt = target[ri];
+    }
+    for (int c = 0; c < kIn; ++c) X[c][t] = x[c];
+    __syncthreads();
+    // forward
+    for (int j = 0; j < kH; ++j) {
+        float a = P[kOffB1 + j];
+        for (int c = 0; c < kIn; ++c) a += P[kOffW1 + j * kIn + c] * x[c];
+        H1[j][t] = gelu(a);
+        G1[j][t] = gelu_grad(a);
+    }
+    float y = P[kOffB3];
+    for (int j = 0; j < kH; ++j) {
+        float a = P[kOffB2 + j];
+        for (int i = 0; i < kH; ++i) a += P[kOffW2 + j * kH + i] * H1[i][t];
+        const float h2 = gelu(a);
+        H2[j][t] = h2;
+        D2[j][t] = gelu_grad(a);  // completed below once dy is known
+        y += P[kOffW3 + j] * h2;
+    }
+    const float err = y - tgt;
+    const float dy = 2.0f * w * err * inv_wsum;
+    DY[t] = dy;
+    for (int j = 0; j < kH; ++j) D2[j][t] *= dy * P[kOffW3 + j];
+    for (int i = 0; i < kH; ++i) {
+        float s = 0.0f;
+        for (int j = 0; j < kH; ++j) s += P[kOffW2 + j * kH + i] * D2[j][t];
+        G1[i][t] *= s;  // dL/d(pre1)
+    }
+    __syncthreads();
+    // parameter gradients of the tile, each a sum over its 64 rows in order
+    float* out = partial + (uint64_t)blockIdx.x * kMlpParams;
+    for (int p = t; p < kH * kH; p += kTile) {
+        const int j = p / kH, i = p % kH;
+        float s = 0.0f;
+        for (int r = 0; r < kTile; ++r) s += D2[j][r] * H1[i][r];
+        out[kOffW2 + p] = s;
+    }
+    for (int p = t; p < kH * kIn; p += kTile) {
+        const int j = p / kIn, c = p % kIn;
+        float s = 0.0f;
+        for (int r = 0; r < kTile; ++r) s += G1[j][r] * X[c][r];
+        out[kOffW1 + p] = s;
+    }
+    {
+        const int j = t;
+        float sb1 = 0.0f, sb2 = 0.0f, sw3 = 0.0f;
+        for (int r = 0; r < kTile; ++r) {
+            sb1 += G1[j][r];
+            sb2 += D2[j][r];
+            sw3 += DY[r] * H2[j][r];
+        }
+        out[kOffB1 + j] = sb1;
+        out[kOffB2 + j] = sb2;
+        out[kOffW3 + j] = sw3;
+    }
+    if (t == 0) {
+        float sb3 = 0.0f;
+        for (int r = 0; r < kTile; ++r) sb3 += DY[r];
+        out[kOffB3] = sb3;
+    }
+    // loss of the tile (weighted squared error / total weight), row order
+    __syncthreads();
+    DY[t] = w * err * err * inv_wsum;
+    __syncthreads();
+    if (t == 0) {
+        float l = 0.0f;
+        for (int r = 0; r < kTile; ++r) l += DY[r];
+        loss_part[blockIdx.x] = l;
+    }
+}
+
+__global__ void k_mlp_reduce(const float* __restrict__ partial, uint64_t tiles, const float* __restrict__ loss_part,
+                             float* __restrict__ grad, float* __restrict__ loss) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kMlpParams) {
+        float s = 0.0f;
+        for (uint64_t b = 0; b < tiles; ++b) s += partial[b * kMlpParams + p];
+        grad[p] = s;
+    }
+    if (p == kMlpParams && loss) {
+        float s = 0.0f;
+        for (uint64_t b = 0; b < tiles; ++b) s += loss_part[b];
+        *loss = s;
+    }
+}
+
+__global__ void k_adam(float* __restrict__ params, const float* __restrict__ grad, float* __restrict__ m1,
+                       float* __restrict__ m2, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams) return;
+    const float g = grad[p];
+    const float a = b1 * m1[p] + (1.0f - b1) * g;
+    const float b = b2 * m2[p] + (1.0f - b2) * g * g;
+    m1[p] = a;
+    m2[p] = b;
+    params[p] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA inference.  One wave handles 32 rows at a time: layer 1 in FP32
+// on the vector units (K = 8 is too small for the matrix cores), layer 2 as
+// a 32 x 64 x 64 product on v_mfma_f32_32x32x16_bf16 (two 32-column output
+// tiles, four K steps of 16, FP32 accumulation), layer 3 in FP32 with a
+// cross-lane sum.  Operand layout of the instruction: lane l supplies
+// A[m = l % 32][k = 8 (l / 32) + j] and B[k = 8 (l / 32) + j][n = l % 32],
+// j = 0..7, and receives D[m = 8 (j / 4) + 4 (l / 32) + j % 4][n = l % 32],
+// j = 0..15.  Output: y (optional) and the Q16 table round(2^16 y).
+// ---------------------------------------------------------------------------
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ params, const float* __restrict__ feats,
+                                                   uint64_t n, uint32_t cls, int32_t* __restrict__ lt,
+                                                   float* __restrict__ yout) {
+    const int lane = lane_id();
+    const int col = lane & 31;   // m for A, n for B and D
+    const int half = lane >> 5;  // which 8-wide slice of each K step
+    // B operand (W2 transposed), constant across row tiles
+    bf16x8 bw[2][4];
+    for (int nt = 0; nt < 2; ++nt)
+        for (int kc = 0; kc < 4; ++kc)
+            for (int j = 0; j < 8; ++j)
+                bw[nt][kc][j] = (__bf16)params[kOffW2 + (nt * 32 + col) * kH + kc * 16 + half * 8 + j];
+    const float b2n[2] = {params[kOffB2 + col], params[kOffB2 + 32 + col]};
+    const float w3n[2] = {params[kOffW3 + col], params[kOffW3 + 32 + col]};
+    const float b3 = params[kOffB3];
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    const uint64_t tiles = (n + 31) / 32;
+    for (uint64_t tile = gw; tile < tiles; tile += nw) {
+        const uint64_t row = tile * 32 + (uint64_t)col;
+        float x[kIn];
+        for (int c = 0; c < kIn; ++c) x[c] = 0.0f;
+        if (row < n)
+            for (int c = 0; c < 4; ++c) x[c] = feats[row * 4 + c];
+        x[4 + (cls < 3 ? cls : 3)] = 1.0f;
+        // layer 1: this lane's 32 of the row's 64 hidden units, as bf16 A slices
+        bf16x8 a[4];
+        for (int kc = 0; kc < 4; ++kc)
+            for (int j = 0; j < 8; ++j) {
+                const int h = kc * 16 + half * 8 + j;
+                float s = params[kOffB1 + h];
+                for (int c = 0; c < kIn; ++c) s += params[kOffW1 + h * kIn + c] * x[c];
+                a[kc][j] = (__bf16)gelu(s);
+            }
+        f32x16 acc0 = {}, acc1 = {};
+        for (int kc = 0; kc < 4; ++kc) {
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kc], bw[0][kc], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kc], bw[1][kc], acc1, 0, 0, 0);
+        }
+        // layer 3: contribution of this lane's two output columns to each of
+        // its 16 rows, summed over the 32 lanes of the half
+        float part[16];
+        for (int j = 0; j < 16; ++j)
+            part[j] = w3n[0] * gelu(acc0[j] + b2n[0]) + w3n[1] * gelu(acc1[j] + b2n[1]);
+        for (int j = 0; j < 16; ++j) {
+#pragma unroll
+            for (int s = 16; s > 0; s >>= 1) part[j] += __shfl_xor(part[j], s, kWave);
+        }
+        // lane with col j < 16 of each half writes row m = 8 (j / 4) + 4 half + j % 4
+        if (col < 16) {
+            float y = b3;
+            for (int j = 0; j < 16; ++j)
+                if (j == col) y += part[j];
+            const int m = 8 * (col / 4) + 4 * half + (col % 4);
+            const uint64_t r = tile * 32 + (uint64_t)m;
+            if (r < n) {
+                lt[r] = (int32_t)rintf(y * 65536.0f);
+                if (yout) yout[r] = y;
+            }
+        }
+    }
+}
+
+}  // namespace agis
+
+using agis::kMlpParams;
+
+namespace {
+
+int lfail(agis_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+#define LHIP(ctx, expr, what)                                                                     \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return lfail(ctx, e_ == hipErrorOutOfMemory ? AGIS_E_OOM : AGIS_E_HIP,                \
+                         std::string(what) + ": " + hipGetErrorString(e_));                      \
+    } while (0)
+
+unsigned grid1(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+extern "C" {
+
+int agis_mlp_param_count(void) { return kMlpParams; }
+
+int agis_features(agis_ctx* ctx, const agis_tables* t, float* feats) {
+    if (!ctx || !t || t->ctx != ctx || !feats) return AGIS_E_INVALID_ARG;
+    LHIP(ctx, hipSetDevice(ctx->device), "set device");
+    const agis::DevGraph& g = t->graph->g;
+    if (g.n == 0) return AGIS_OK;
+    const uint64_t blocks = std::min<uint64_t>((g.n + 3) / 4, (uint64_t)ctx->num_cus * 32);
+    hipLaunchKernelGGL(agis::k_features, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, g, t->rec, t->s2, t->hits,
+                       t->trials, feats);
+    LHIP(ctx, hipGetLastError(), "features");
+    LHIP(ctx, hipStreamSynchronize(ctx->stream), "features");
+    return AGIS_OK;
+}
+
+int agis_learn_targets(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                       const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
+                       double* sums, uint32_t* counts) {
+    if (!ctx || !g || !t || !p || !sums || !counts) return AGIS_E_INVALID_ARG;
+    if (p->k < 2 || p->k > 8) return lfail(ctx, AGIS_E_PATTERN, "pattern size must be in [2, 8]");
+    LHIP(ctx, hipSetDevice(ctx->device), "set device");
+    const uint64_t n = g->g.n;
+    LHIP(ctx, hipMemsetAsync(sums, 0, (size_t)p->k * n * sizeof(double), ctx->stream), "clear sums");
+    LHIP(ctx, hipMemsetAsync(counts, 0, (size_t)p->k * n * sizeof(uint32_t), ctx->stream), "clear counts");
+    const uint64_t chunk = 1ull << 20;
+    uint64_t* d_idx = nullptr;
+    agis::Record* d_rec = nullptr;
+    LHIP(ctx, hipMalloc(&d_idx, chunk * sizeof(uint64_t)), "allocate indices");
+    hipError_t e = hipMalloc(&d_rec, chunk * sizeof(agis::Record));
+    if (e != hipSuccess) {
+        (void)hipFree(d_idx);
+        return lfail(ctx, AGIS_E_OOM, "allocate records");
+    }
+    std::vector<uint64_t> idx(chunk);
+    int rc = AGIS_OK;
+    for (uint64_t done = 0; done < n_samples && rc == AGIS_OK; done += chunk) {
+        const uint64_t m = std::min(chunk, n_samples - done);
+        for (uint64_t j = 0; j < m; ++j) idx[j] = done + j;
+        e = hipMemcpyAsync(d_idx, idx.data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, ctx->stream);
+        if (e != hipSuccess) {
+            rc = lfail(ctx, AGIS_E_HIP, "upload indices");
+            break;
+        }
+        rc = agis_dump_samples(ctx, g, t, p, order, seed, params, d_idx, m, (agis_record*)d_rec);
+        if (rc != AGIS_OK) break;
+        hipLaunchKernelGGL(agis::k_targets, dim3(grid1(m, 256)), dim3(256), 0, ctx->stream, d_rec, m, p->k, n, sums,
+                           counts);
+        e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) rc = lfail(ctx, AGIS_E_HIP, std::string("targets: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(d_idx);
+    (void)hipFree(d_rec);
+    return rc;
+}
+
+int agis_learn_rows(agis_ctx* ctx, const double* sums, const uint32_t* counts, uint32_t k, uint64_t n,
+                    uint32_t step_mask, uint32_t min_count, uint32_t* vtx, uint8_t* cls, float* target, float* weight,
+                    uint64_t* rows) {
+    if (!ctx || !sums || !counts || !vtx || !cls || !target || !weight || !rows || k == 0 || k > 8)
+        return AGIS_E_INVALID_ARG;
+    LHIP(ctx, hipSetDevice(ctx->device), "set device");
+    std::vector<double> s(n);
+    std::vector<uint32_t> c(n);
+    std::vector<uint32_t> hv;
+    std::vector<uint8_t> hc;
+    std::vector<float> ht, hw;
+    for (uint32_t i = 0; i < k; ++i) {
+        if (!(step_mask >> i & 1u)) continue;
+        LHIP(ctx, hipMemcpy(s.data(), sums + (uint64_t)i * n, n * sizeof(double), hipMemcpyDeviceToHost), "read sums");
+        LHIP(ctx, hipMemcpy(c.data(), counts + (uint64_t)i * n, n * sizeof(uint32_t), hipMemcpyDeviceToHost),
+             "read counts");
+        for (uint64_t v = 0; v < n; ++v) {
+            if (c[v] < min_count || c[v] == 0) continue;
+            hv.push_back((uint32_t)v);
+            hc.push_back((uint8_t)(i < 3 ? i : 3));
+            ht.push_back((float)std::log2(1.0 + s[v] / (double)c[v]));
+            hw.push_back((float)c[v]);
+        }
+    }
+    const uint64_t r = hv.size();
+    if (r) {
+        LHIP(ctx, hipMemcpy(vtx, hv.data(), r * sizeof(uint32_t), hipMemcpyHostToDevice), "write rows");
+        LHIP(ctx, hipMemcpy(cls, hc.data(), r * sizeof(uint8_t), hipMemcpyHostToDevice), "write rows");
+        LHIP(ctx, hipMemcpy(target, ht.data(), r * sizeof(float), hipMemcpyHostToDevice), "write rows");
+        LHIP(ctx, hipMemcpy(weight, hw.data(), r * sizeof(float), hipMemcpyHostToDevice), "write rows");
+    }
+    *rows = r;
+    return AGIS_OK;
+}
+
+int agis_mlp_grad(agis_ctx* ctx, const float* params, const float* feats, const uint32_t* vtx, const uint8_t* cls,
+                  const float* target, const float* weight, uint64_t rows, float weight_sum, float* grad, float* loss) {
+    if (!ctx || !params || !feats || !vtx || !cls || !target || !weight || !grad || rows == 0 || !(weight_sum > 0))
+        return AGIS_E_INVALID_ARG;
+    LHIP(ctx, hipSetDevice(ctx->device), "set device");
+    const uint64_t tiles = (rows + agis::kTile - 1) / agis::kTile;
+    float* partial = nullptr;
+    float* lpart = nullptr;
+    LHIP(ctx, hipMalloc(&partial, tiles * kMlpParams * sizeof(float)), "allocate gradient partials");
+    hipError_t e = hipMalloc(&lpart, tiles * sizeof(float));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(agis::k_mlp_grad, dim3((unsigned)tiles), dim3(agis::kTile), 0, ctx->stream, params, feats,
+                           vtx, cls, target, weight, nullptr, rows, 1.0f / weight_sum, partial, lpart);
+        hipLaunchKernelGGL(agis::k_mlp_reduce, dim3(grid1(kMlpParams + 1, 256)), dim3(256), 0, ctx->stream, partial,
+                           tiles, lpart, grad, loss);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
+    (void)hipFree(partial);
+    if (lpart) (void)hipFree(lpart);
+    LHIP(ctx, e, "mlp gradient");
+    return AGIS_OK;
+}
+
+int agis_mlp_train(agis_ctx* ctx, float* params, const float* feats, const uint32_t* vtx, const uint8_t* cls,
+                   const float* target, const float* weight, uint64_t rows, uint32_t epochs, uint32_t batch,
+                   float lr, uint64_t shuffle_seed, float* loss_per_epoch) {
+    if (!ctx || !params || !feats || !vtx || !cls || !target || !weight || rows == 0 || batch == 0)
+        return AGIS_E_INVALID_ARG;
+    if (rows >= (1ull << 32)) return lfail(ctx, AGIS_E_INVALID_ARG, "at most 2^32 - 1 rows");
+    LHIP(ctx, hipSetDevice(ctx->device), "set device");
+    const uint64_t bt = std::min<uint64_t>(batch, rows);
+    const uint64_t tiles = (bt + agis::kTile - 1) / agis::kTile;
+    std::vector<float> w(rows);
+    LHIP(ctx, hipMemcpy(w.data(), weight, rows * sizeof(float), hipMemcpyDeviceToHost), "read weights");
+    float *partial = nullptr, *lpart = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr, *loss = nullptr;
+    uint32_t* order = nullptr;
+    hipError_t e = hipMalloc(&partial, tiles * kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&lpart, tiles * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&grad, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m1, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m2, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&loss, sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&order, rows * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(m1, 0, kMlpParams * sizeof(float), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m2, 0, kMlpParams * sizeof(float), ctx->stream);
+    std::vector<uint32_t> perm(rows);
+    for (uint64_t i = 0; i < rows; ++i) perm[i] = (uint32_t)i;
+    std::mt19937_64 rng(shuffle_seed);
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    uint64_t step = 0;
+    for (uint32_t ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+        std::shuffle(perm.begin(), perm.end(), rng);
+        e = hipMemcpyAsync(order, perm.data(), rows * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
+        double ep_loss = 0.0;
+        for (uint64_t s0 = 0; s0 < rows && e == hipSuccess; s0 += bt) {
+            const uint64_t cnt = std::min(bt, rows - s0);
+            double ws = 0.0;
+            for (uint64_t i = 0; i < cnt; ++i) ws += w[perm[s0 + i]];
+            if (!(ws > 0)) continue;
+            const uint64_t tl = (cnt + agis::kTile - 1) / agis::kTile;
+            hipLaunchKernelGGL(agis::k_mlp_grad, dim3((unsigned)tl), dim3(agis::kTile), 0, ctx->stream, params, feats,
+                               vtx, cls, target, weight, order + s0, cnt, (float)(1.0 / ws), partial, lpart);
+            hipLaunchKernelGGL(agis::k_mlp_reduce, dim3(grid1(kMlpParams + 1, 256)), dim3(256), 0, ctx->stream,
+                               partial, tl, lpart, grad, loss);
+            ++step;
+            const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+            hipLaunchKernelGGL(agis::k_adam, dim3(grid1(kMlpParams, 256)), dim3(256), 0, ctx->stream, params, grad, m1,
+                               m2, lr, b1, b2, eps, c1, c2);
+            e = hipGetLastError();
+            if (loss_per_epoch) {
+                float l = 0.0f;
+                if (e == hipSuccess) e = hipMemcpyAsync(&l, loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+                ep_loss += (double)l * ws;
+            }
+        }
+        if (loss_per_epoch) {
+            double wt = 0.0;
+            for (float x : w) wt += x;
+            loss_per_epoch[ep] = (float)(ep_loss / wt);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    for (void* q : {(void*)partial, (void*)lpart, (void*)grad, (void*)m1, (void*)m2, (void*)loss, (void*)order})
+        if (q) (void)hipFree(q);
+    LHIP(ctx, e, "mlp training");
+    return AGIS_OK;
+}
+
+int agis_mlp_infer(agis_ctx* ctx, const float* params, const float* feats, uint64_t n, uint32_t position_class,
+                   int32_t* lt, float* y) {
+    if (!ctx || !params || !feats || !lt || position_class > 3) return AGIS_E_INVALID_ARG;
+    LHIP(ctx, hipSetDevice(ctx->device), "set device");
+    if (n == 0) return AGIS_OK;
+    const uint64_t tiles = (n + 31) / 32;
+    const uint64_t blocks = std::min<uint64_t>((tiles + 3) / 4, (uint64_t)ctx->num_cus * 8);
+    hipLaunchKernelGGL(agis::k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, params, feats, n,
+                       position_class, lt, y);
+    LHIP(ctx, hipGetLastError(), "mlp inference");
+    LHIP(ctx, hipStreamSynchronize(ctx->stream), "mlp inference");
+    return AGIS_OK;
+}
+
+}  // extern "C"

@@ -9,10 +9,10 @@ import ctypes
 import numpy as np
 
 from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, agis_build_proposal_tables,
-               agis_autotune, agis_create, agis_destroy, agis_dump_samples, agis_estimate, agis_estimate_batch,
-               agis_graph_destroy,
-               agis_load_csr, agis_set_launch, agis_tables_destroy, agis_tables_export, make_params, make_pattern,
-               lib)
+               agis_autotune, agis_compile_pattern, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
+               agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
+               agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
+               agis_tables_destroy, agis_tables_export, make_params, make_pattern, lib)
 
 
 def _torch():
@@ -114,7 +114,84 @@ class Session:
                           d_out.data_ptr(), order=order)
         return d_out.cpu().numpy()[: m * RECORD_BYTES].view(RECORD_DTYPE).copy()
 
+    # ---------------------------------------------------------------- learned proposal
+
+    def features(self, tables: Tables):
+        torch = _torch()
+        f = torch.zeros((tables.graph.n, 4), dtype=torch.float32, device=self.device)
+        agis_features(self.ctx, tables.handle, f.data_ptr())
+        return f
+
+    def learn_targets(self, graph: Graph, tables: Tables, pattern, n_samples: int, seed: int, **kw):
+        torch = _torch()
+        k, n = pattern.k, graph.n
+        sums = torch.zeros((k, n), dtype=torch.float64, device=self.device)
+        counts = torch.zeros((k, n), dtype=torch.int32, device=self.device)
+        p = make_pattern(pattern.k, pattern.adj8())
+        agis_learn_targets(self.ctx, graph.handle, tables.handle, p, n_samples, seed, make_params(**kw),
+                           sums.data_ptr(), counts.data_ptr())
+        return sums, counts
+
+    def learn_rows(self, sums, counts, step_mask: int, min_count: int = 2):
+        torch = _torch()
+        k, n = sums.shape
+        cap = max(k * n, 1)
+        vtx = torch.zeros(cap, dtype=torch.int32, device=self.device)
+        cls = torch.zeros(cap, dtype=torch.uint8, device=self.device)
+        tgt = torch.zeros(cap, dtype=torch.float32, device=self.device)
+        wt = torch.zeros(cap, dtype=torch.float32, device=self.device)
+        rows = agis_learn_rows(self.ctx, sums.data_ptr(), counts.data_ptr(), k, n, step_mask, min_count,
+                               vtx.data_ptr(), cls.data_ptr(), tgt.data_ptr(), wt.data_ptr())
+        return {"vtx": vtx[:rows], "cls": cls[:rows], "target": tgt[:rows], "weight": wt[:rows], "rows": rows}
+
+    def mlp_grad(self, params, feats, rows: dict):
+        torch = _torch()
+        grad = torch.zeros(agis_mlp_param_count(), dtype=torch.float32, device=self.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        wsum = float(rows["weight"].double().sum().item())
+        agis_mlp_grad(self.ctx, params.data_ptr(), feats.data_ptr(), rows["vtx"].data_ptr(), rows["cls"].data_ptr(),
+                      rows["target"].data_ptr(), rows["weight"].data_ptr(), rows["rows"], wsum, grad.data_ptr(),
+                      loss.data_ptr())
+        return grad, float(loss.item())
+
+    def mlp_train(self, params, feats, rows: dict, epochs: int, batch: int, lr: float, seed: int):
+        return agis_mlp_train(self.ctx, params.data_ptr(), feats.data_ptr(), rows["vtx"].data_ptr(),
+                              rows["cls"].data_ptr(), rows["target"].data_ptr(), rows["weight"].data_ptr(),
+                              rows["rows"], epochs, batch, lr, seed)
+
+    def mlp_infer(self, params, feats, position_class: int, want_y: bool = False):
+        torch = _torch()
+        n = feats.shape[0]
+        lt = torch.zeros(n, dtype=torch.int32, device=self.device)
+        y = torch.zeros(n, dtype=torch.float32, device=self.device) if want_y else None
+        agis_mlp_infer(self.ctx, params.data_ptr(), feats.data_ptr(), n, position_class, lt.data_ptr(),
+                       y.data_ptr() if want_y else 0)
+        return (lt, y) if want_y else lt
+
+    def weighted_steps(self, pattern, mode="switch"):
+        plan = agis_compile_pattern(make_pattern(pattern.k, pattern.adj8()), params=make_params(mode=mode))
+        return [i for i in range(pattern.k) if plan.decision[i] and plan.f1[i] > 0]
+
+    def learned_tables(self, params, feats, pattern):
+        """Q16 pick table per weighted step (position class min(i, 3))."""
+        return {i: self.mlp_infer(params, feats, min(i, 3)) for i in self.weighted_steps(pattern, "learned")}
+
     def close(self):
         if self.ctx:
             agis_destroy(self.ctx)
             self.ctx = None
+
+
+def mlp_init(seed: int, target_mean: float = 0.0):
+    """Initial parameters (Xavier-uniform weights, zero biases, output bias
+    at the mean target), as a host float32 array in the library's layout."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h, i = 64, 8
+
+    def xavier(fan_out, fan_in):
+        lim = np.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-lim, lim, size=(fan_out, fan_in))
+
+    parts = [xavier(h, i).ravel(), np.zeros(h), xavier(h, h).ravel(), np.zeros(h), xavier(1, h).ravel(),
+             np.array([target_mean])]
+    return np.concatenate(parts).astype(np.float32)

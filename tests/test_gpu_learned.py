@@ -1,0 +1,201 @@
+"""GPU: learned proposal -- features, targets, rows, training gradients,
+BF16 MFMA inference, bit-exact learned sampling, and the gain test."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp
+from oracle.pattern import compile_pattern
+
+pytestmark = pytest.mark.gpu
+
+A = pytest.importorskip("paper_2601_01388_amd")
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sess():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_01388_amd.session import Session
+    s = Session(0)
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def small(sess):
+    g = synth.rmat(12, 16, seed=12)
+    G = sess.graph(g.off, g.nbr)
+    T = sess.tables(G, cv_seed=1)
+    OT = oracle.Tables(g, cv_seed=1)
+    return g, G, T, OT
+
+
+def test_features_parity(sess, small):
+    g, G, T, OT = small
+    say("features")
+    got = sess.features(T).cpu().numpy().astype(np.float64)
+    ref = mlp.features(g, OT)
+    assert np.allclose(got, ref, rtol=2e-7, atol=1e-6), np.max(np.abs(got - ref))
+
+
+@pytest.mark.parametrize("name", ["house", "5-cycle", "4-clique"])
+def test_targets_and_rows_parity(sess, small, name):
+    g, G, T, OT = small
+    p = synth.named_pattern(name)
+    n_samples = 30_000
+    say(f"targets {name}")
+    sums, counts = sess.learn_targets(G, T, p, n_samples, 21, mode="switch")
+    recs = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="switch"), seed=21).records(np.arange(n_samples))
+    rs, rc = mlp.targets_from_records(recs, p.k, g.n)
+    assert np.array_equal(counts.cpu().numpy().astype(np.int64), rc)
+    gs = sums.cpu().numpy()
+    assert np.allclose(gs, rs, rtol=1e-12, atol=0.0)
+    rows = sess.learn_rows(sums, counts, step_mask=(1 << p.k) - 1, min_count=2)
+    exp_v, exp_t, exp_w = [], [], []
+    for i in range(p.k):
+        for v in range(g.n):
+            if rc[i, v] >= 2:
+                exp_v.append(v)
+                exp_t.append(np.float32(math.log2(1.0 + rs[i, v] / rc[i, v])))
+                exp_w.append(rc[i, v])
+    assert rows["rows"] == len(exp_v)
+    assert np.array_equal(rows["vtx"].cpu().numpy(), np.array(exp_v, dtype=np.int32))
+    assert np.allclose(rows["target"].cpu().numpy(), np.array(exp_t), rtol=1e-6)
+    assert np.array_equal(rows["weight"].cpu().numpy(), np.array(exp_w, dtype=np.float32))
+
+
+def _rows_for(sess, G, T, p, n_samples=40_000, seed=5):
+    sums, counts = sess.learn_targets(G, T, p, n_samples, seed, mode="switch")
+    steps = sess.weighted_steps(p, "learned")
+    return sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2)
+
+
+def test_gradient_matches_fp64_oracle(sess, small):
+    import torch
+    from paper_2601_01388_amd.session import mlp_init
+    g, G, T, OT = small
+    p = synth.named_pattern("house")
+    rows = _rows_for(sess, G, T, p)
+    assert rows["rows"] > 100
+    feats = sess.features(T)
+    fx = feats.cpu().numpy().astype(np.float64)
+    x = mlp.inputs(fx, rows["vtx"].cpu().numpy(), rows["cls"].cpu().numpy())
+    t = rows["target"].cpu().numpy().astype(np.float64)
+    w = rows["weight"].cpu().numpy().astype(np.float64)
+    for seed in (0, 1):
+        theta = mlp_init(seed, float(np.average(t, weights=w)))
+        theta[:512] *= 0.5
+        params = torch.from_numpy(theta).to(sess.device)
+        say(f"gradient check seed {seed}, {rows['rows']} rows")
+        grad, loss = sess.mlp_grad(params, feats, rows)
+        gg = grad.cpu().numpy().astype(np.float64)
+        ref = mlp.grad(theta.astype(np.float64), x, t, w, w.sum())
+        tol = 1e-4 * np.abs(ref) + 1e-6 * max(1.0, np.abs(ref).max())
+        bad = np.flatnonzero(np.abs(gg - ref) > tol)
+        assert bad.size == 0, (bad[:5], gg[bad[:5]], ref[bad[:5]])
+        assert loss == pytest.approx(mlp.loss(theta.astype(np.float64), x, t, w, w.sum()), rel=1e-4)
+
+
+def test_training_deterministic_and_learns(sess, small):
+    import torch
+    from paper_2601_01388_amd.session import mlp_init
+    g, G, T, OT = small
+    p = synth.named_pattern("5-cycle")
+    rows = _rows_for(sess, G, T, p)
+    feats = sess.features(T)
+    t = rows["target"].cpu().numpy()
+    w = rows["weight"].cpu().numpy()
+    theta0 = mlp_init(3, float(np.average(t, weights=w)))
+    runs = []
+    for _ in range(2):
+        params = torch.from_numpy(theta0.copy()).to(sess.device)
+        say("training")
+        losses = sess.mlp_train(params, feats, rows, epochs=30, batch=1024, lr=3e-3, seed=9)
+        runs.append((params.cpu().numpy(), losses))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    losses = runs[0][1]
+    assert losses[-1] < 0.5 * losses[0], losses
+
+
+def test_bf16_inference_and_learned_sampling(sess, small):
+    import torch
+    from paper_2601_01388_amd.session import mlp_init
+    g, G, T, OT = small
+    p = synth.named_pattern("house")
+    rows = _rows_for(sess, G, T, p)
+    feats = sess.features(T)
+    t = rows["target"].cpu().numpy()
+    w = rows["weight"].cpu().numpy()
+    params = torch.from_numpy(mlp_init(4, float(np.average(t, weights=w)))).to(sess.device)
+    sess.mlp_train(params, feats, rows, epochs=20, batch=1024, lr=3e-3, seed=1)
+    theta = params.cpu().numpy().astype(np.float64)
+    fx = feats.cpu().numpy().astype(np.float64)
+    for cls in range(4):
+        say(f"inference class {cls}")
+        lt, y = sess.mlp_infer(params, feats, cls, want_y=True)
+        yg = y.cpu().numpy().astype(np.float64)
+        ref, _ = mlp.forward(theta, mlp.inputs(fx, np.arange(g.n), np.full(g.n, cls)))
+        assert np.max(np.abs(yg - ref)) <= 0.05, np.max(np.abs(yg - ref))
+        assert np.array_equal(lt.cpu().numpy(), np.rint(y.cpu().numpy() * np.float32(65536.0)).astype(np.int32))
+    # learned sampling: GPU and oracle fed the same tables choose identically
+    tabs = sess.learned_tables(params, feats, p)
+    learned = {i: tab.data_ptr() for i, tab in tabs.items()}
+    idx = np.concatenate([np.arange(3000), np.array([2 ** 40 + 5, 2 ** 63 + 7])]).astype(np.uint64)
+    say("learned records")
+    got = sess.dump(G, T, p, 17, idx, mode="learned", learned=learned)
+    ref = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="learned"), seed=17,
+                         learned={i: tab.cpu().numpy() for i, tab in tabs.items()}).records(idx)
+    for f in ("v", "num", "den", "steps", "fail_step"):
+        assert np.array_equal(got[f], ref[f]), f
+    assert np.array_equal(got["x"], ref["x"])
+    r = sess.estimate(G, T, p, 200_000, 3, mode="learned", learned=learned)
+    st, _, _ = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="learned"), seed=3,
+                              learned={i: tab.cpu().numpy() for i, tab in tabs.items()}).run(0, 200_000)
+    assert r.estimate == pytest.approx(st.mean, rel=1e-9)
+
+
+def test_learned_gain_over_f_approx(sess):
+    """Train on one R-MAT graph, evaluate on another: relative variance per
+    sample of learned vs f_approx (printed), and the learned estimate agrees
+    with f_approx and f_uniform (all unbiased)."""
+    import torch
+    from paper_2601_01388_amd.session import mlp_init
+    gtr = synth.rmat(15, 16, seed=150)
+    gev = synth.rmat(16, 16, seed=160)
+    Gtr, Gev = sess.graph(gtr.off, gtr.nbr), sess.graph(gev.off, gev.nbr)
+    Ttr, Tev = sess.tables(Gtr, cv_seed=1), sess.tables(Gev, cv_seed=1)
+    ftr, fev = sess.features(Ttr), sess.features(Tev)
+    gains = {}
+    for name in ("house", "5-cycle", "4-clique"):
+        p = synth.named_pattern(name)
+        rows = _rows_for(sess, Gtr, Ttr, p, n_samples=400_000)
+        t = rows["target"].cpu().numpy()
+        w = rows["weight"].cpu().numpy()
+        params = torch.from_numpy(mlp_init(7, float(np.average(t, weights=w)))).to(sess.device)
+        sess.mlp_train(params, ftr, rows, epochs=20, batch=4096, lr=3e-3, seed=2)
+        tabs = sess.learned_tables(params, fev, p)
+        learned = {i: tab.data_ptr() for i, tab in tabs.items()}
+        n = 500_000
+        rl = sess.estimate(Gev, Tev, p, n, 31, mode="learned", learned=learned)
+        ra = sess.estimate(Gev, Tev, p, n, 31, mode="switch")
+        ru = sess.estimate(Gev, Tev, p, n, 31, mode="uniform")
+        vl = rl.variance / rl.estimate ** 2
+        va = ra.variance / ra.estimate ** 2
+        vu = ru.variance / ru.estimate ** 2
+        gains[name] = va / vl
+        say(f"gain {name}: rel.var learned {vl:.4g}, f_approx {va:.4g}, f_uniform {vu:.4g} -> {va / vl:.3f}x")
+        se = math.sqrt(rl.variance / n + ra.variance / n)
+        assert abs(rl.estimate - ra.estimate) <= 5 * se
+    assert all(math.isfinite(x) and x > 0 for x in gains.values())
