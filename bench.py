@@ -140,6 +140,11 @@ def main():
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--train-samples", type=int, default=1 << 20, help="sampler runs producing training targets")
     ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--train-min-steps", type=int, default=1500, help="fewest Adam steps per pattern")
+    ap.add_argument("--learned-absolute", action="store_true",
+                    help="learned tables predict the log weight itself instead of correcting f_approx")
+    ap.add_argument("--pilot-samples", type=int, default=1 << 18,
+                    help="per-mode pilot deciding between learned and f_approx")
     ap.add_argument("--batch-budget-scale", type=float, default=1.0,
                     help="multiplier on the 32-pattern set's budgets (log-uniform in [1e6, 1e9])")
     args = ap.parse_args()
@@ -263,28 +268,38 @@ def main():
         fev = sess.features(T)
         torch.cuda.synchronize()
         feat_s = time.perf_counter() - t0
+        residual = not args.learned_absolute
+        batch_rows = 4096
         for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
             t0 = time.perf_counter()
             steps = sess.weighted_steps(p, "learned")
             sums, counts = sess.learn_targets(Gtr, Ttr, p, args.train_samples, 101 + pid, mode="switch")
-            rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2)
-            del sums, counts
+            base_tr = sess.step_log_weights(Ttr, p) if residual else None
+            rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2, base=base_tr)
+            del sums, counts, base_tr
             tg = rows["target"].cpu().numpy()
             wt = rows["weight"].cpu().numpy()
-            params = torch.from_numpy(mlp_init(7 + pid, float(np.average(tg, weights=wt)))).to(sess.device)
-            losses = sess.mlp_train(params, ftr, rows, epochs=args.train_epochs, batch=4096, lr=3e-3, seed=pid)
+            init = mlp_init(7 + pid, float(np.average(tg, weights=wt)) if rows["rows"] else 0.0,
+                            zero_output=residual)
+            params = torch.from_numpy(init).to(sess.device)
+            per_epoch = max(1, -(-rows["rows"] // batch_rows))
+            epochs = max(args.train_epochs, -(-args.train_min_steps // per_epoch))
+            losses = sess.mlp_train(params, ftr, rows, epochs=epochs, batch=batch_rows, lr=3e-3, seed=pid)
             torch.cuda.synchronize()
             train_s = time.perf_counter() - t0
             t0 = time.perf_counter()
-            tabs = sess.learned_tables(params, fev, p)
+            base_ev = sess.step_log_weights(T, p) if residual else None
+            tabs = sess.learned_tables(params, fev, p, base=base_ev)
+            del base_ev
             torch.cuda.synchronize()
             infer_s = time.perf_counter() - t0
             learned[name] = {"tables": tabs, "ptrs": {i: tab.data_ptr() for i, tab in tabs.items()},
-                             "info": {"train_rows": rows["rows"], "train_seconds": train_s,
-                                      "loss_first_last": [losses[0], losses[-1]], "infer_seconds": infer_s,
-                                      "weighted_steps": steps}}
-            log(f"learned {name}: {rows['rows']} rows, train {train_s:.2f} s, loss {losses[0]:.3g} -> "
-                f"{losses[-1]:.3g}, tables {infer_s * 1e3:.1f} ms")
+                             "info": {"train_rows": rows["rows"], "train_seconds": train_s, "epochs": epochs,
+                                      "adam_steps": epochs * per_epoch, "residual": residual,
+                                      "loss_first_last": [losses[0], losses[-1]] if losses else None,
+                                      "infer_seconds": infer_s, "weighted_steps": steps}}
+            log(f"learned {name}: {rows['rows']} rows, {epochs} epochs, train {train_s:.2f} s, loss "
+                f"{losses[0]:.3g} -> {losses[-1]:.3g}, tables {infer_s * 1e3:.1f} ms")
         Ttr.close()
         Gtr.close()
 
@@ -311,10 +326,25 @@ def main():
                 eps_table[f"{name}/{label}"] = entry
                 log(f"+-1% {name} {label}: {r.seconds:.3f} s, n={r.n}, rel.var {entry['rel_var']:.4g}, "
                     f"converged={bool(r.converged)}")
-        for name in PATTERNS:
-            if f"{name}/learned" in eps_table:
-                eps_table[f"{name}/learned"]["rel_var_vs_f_approx"] = (
-                    eps_table[f"{name}/learned"]["rel_var"] / max(eps_table[f"{name}/f_approx"]["rel_var"], 1e-300))
+        for pid, name in enumerate(PATTERNS):
+            if f"{name}/learned" not in eps_table:
+                continue
+            eps_table[f"{name}/learned"]["rel_var_vs_f_approx"] = (
+                eps_table[f"{name}/learned"]["rel_var"] / max(eps_table[f"{name}/f_approx"]["rel_var"], 1e-300))
+            # fallback: a pilot of each proposal on fresh samples keeps the
+            # learned tables only if their variance per sample is lower
+            t0 = time.perf_counter()
+            pl = sess.estimate(G, T, pats[pid], args.pilot_samples, 97, mode="learned", pattern_id=pid,
+                               learned=learned[name]["ptrs"])
+            pa = sess.estimate(G, T, pats[pid], args.pilot_samples, 97, mode="switch", pattern_id=pid)
+            pilot_s = time.perf_counter() - t0
+            keep = pl.variance / max(pl.estimate ** 2, 1e-300) < pa.variance / max(pa.estimate ** 2, 1e-300)
+            chosen = eps_table[f"{name}/learned" if keep else f"{name}/f_approx"]
+            eps_table[f"{name}/learned_with_fallback"] = {
+                "chosen": "learned" if keep else "f_approx", "pilot_seconds": pilot_s,
+                "seconds": chosen["seconds"] + pilot_s, "samples": chosen["samples"],
+                "converged": chosen["converged"], "estimate": chosen["estimate"], "rel_var": chosen["rel_var"]}
+            log(f"{name}: pilot keeps {'learned' if keep else 'f_approx'}")
 
     # 32 connected patterns of 4-7 vertices (seed 3) with uneven budgets,
     # all run to +-1% in one batch of rounds (each a persistent launch)

@@ -311,11 +311,18 @@ int agis_learn_targets(agis_ctx* ctx, const agis_graph* g, const agis_tables* t,
  * every vertex v with counts[i][v] >= min_count (and >= 1), one row (vtx v,
  * cls = position class min(i, 3), target log2(1 + sums/counts), weight
  * counts), steps ascending then vertices ascending.  sums/counts: device,
- * as written by agis_learn_targets (k steps, n vertices); outputs: device
+ * as written by agis_learn_targets (k steps, n vertices); base: NULL, or
+ * device int32[k][n] Q16 log weights the network corrects (residual
+ * targets: rows whose base is the certain-zero marker are skipped; with
+ * B = 2^(base / 2^16) and, per step, kappa = sum(sums) / sum(counts * B)
+ * over the kept rows (1 if either sum is 0), the row target becomes
+ * log2((sums / (kappa B) + 1) / (counts + 1)), i.e. the mean completion
+ * count with kappa B as one pseudo-observation, relative to kappa B);
+ * outputs: device
  * arrays of capacity k * n; *rows (host) receives the row count. */
 int agis_learn_rows(agis_ctx* ctx, const double* sums, const uint32_t* counts, uint32_t k, uint64_t n,
-                    uint32_t step_mask, uint32_t min_count, uint32_t* vtx, uint8_t* cls, float* target, float* weight,
-                    uint64_t* rows);
+                    uint32_t step_mask, uint32_t min_count, const int32_t* base, uint32_t* vtx, uint8_t* cls,
+                    float* target, float* weight, uint64_t* rows);
 
 /* Gradient of L = sum_r w_r (y_r - target_r)^2 / weight_sum over `rows`
  * training rows (device arrays: vtx uint32, cls uint8 position class,
@@ -333,13 +340,21 @@ int agis_mlp_train(agis_ctx* ctx, float* params, const float* feats, const uint3
                    const float* target, const float* weight, uint64_t rows, uint32_t epochs, uint32_t batch,
                    float lr, uint64_t shuffle_seed, float* loss_per_epoch);
 
+/* f_approx Q16 log2 weight (Eq. probability_function in the library's
+ * integer encoding) of every vertex for a step signature (b, f1, ie, f2),
+ * INT32_MIN where d(v) - b < f1.  out: device int32[n]. */
+int agis_step_log_weights(agis_ctx* ctx, const agis_tables* t, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,
+                          int32_t* out);
+
 /* Inference for every vertex at one position class (0..3): BF16 matrix-core
  * products with FP32 accumulation for the 64 x 64 layer, FP32 elsewhere.
  * lt: device int32[n] = round(2^16 y), the Q16 log2 pick table consumed by
  * AGIS_MODE_LEARNED (certain zeros are still decided by degree at pick
- * time); y: device float[n] or NULL. */
+ * time), or base[v] + round(2^16 y) when base (device int32[n], e.g. the
+ * step's agis_step_log_weights) is given -- a learned correction of
+ * f_approx; y: device float[n] or NULL. */
 int agis_mlp_infer(agis_ctx* ctx, const float* params, const float* feats, uint64_t n, uint32_t position_class,
-                   int32_t* lt, float* y);
+                   const int32_t* base, int32_t* lt, float* y);
 
 /* Host copies of the library's Q16 tables (4096 entries each), its Philox
  * block function and its bounded draw -- for host-side tests. */

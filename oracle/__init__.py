@@ -99,6 +99,7 @@ def lib():
         L.orc_weight_from_log.restype = u32
         L.orc_fixed_point_tables.argtypes = [P, P]
         L.orc_build_tables.argtypes = [P, P, u64, u32, u32, i32, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_log_weights.argtypes = [P, P, ctypes.c_int, u64, P]
         L.orc_step1_table.argtypes = [P, P, P, P, P, P]
         L.orc_step1_table.restype = u64
         L.orc_run.argtypes = [P, P, u64, u64, P, P, P, P, P, P, P, P, u64, u64, u64, u64, P, P, P]
@@ -263,6 +264,13 @@ class Sampler:
         if rc != 0:
             raise MemoryError("oracle scratch allocation failed")
         return recs
+
+    def log_weights(self, i: int) -> np.ndarray:
+        """f_approx Q16 log weight of every vertex at step i (certain zeros
+        are INT32_MIN)."""
+        out = np.zeros(max(self.g.n, 1), dtype=np.int32)
+        lib().orc_log_weights(self._tables_struct(), ctypes.byref(self.plan), i, self.g.n, _p(out))
+        return out[: self.g.n].copy()
 
     def step_distribution(self, i: int, tau):
         t = self.t

@@ -244,6 +244,12 @@ static int32_t log_weight(const orc_tables* T, const orc_plan* P, int i, uint32_
     return l;
 }
 
+/* f_approx log weight of every vertex at step i (certain zeros marked), the
+ * base a learned correction is added to. */
+void orc_log_weights(const orc_tables* T, const orc_plan* P, int i, uint64_t n, int32_t* out) {
+    for (uint64_t v = 0; v < n; ++v) out[v] = log_weight(T, P, i, (uint32_t)v, NULL);
+}
+
 /* Step-1 proposal over the whole vertex set: fills q1[v] and the inclusive
  * prefix pre1[v]; returns the total. */
 uint64_t orc_step1_table(const orc_graph* G, const orc_tables* T, const orc_plan* P, const int32_t* lt,

@@ -130,11 +130,13 @@ _SIGNATURES = [
     ("agis_learn_targets", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
                                           ctypes.c_uint64, ctypes.POINTER(agis_run_params), _P, _P]),
     ("agis_learn_rows", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                       _P, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+                                       _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("agis_step_log_weights", ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                             _P]),
     ("agis_mlp_grad", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_float, _P, _P]),
     ("agis_mlp_train", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_float, ctypes.c_uint64, _P]),
-    ("agis_mlp_infer", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P]),
+    ("agis_mlp_infer", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, _P]),
     ("agis_fixed_point_tables", ctypes.c_int, [_P, _P]),
     ("agis_philox4x32_10", ctypes.c_int, [_P, _P, _P]),
 ]
@@ -309,11 +311,15 @@ def agis_learn_targets(ctx, g, t, pattern: agis_pattern, n_samples: int, seed: i
 
 
 def agis_learn_rows(ctx, sums_ptr, counts_ptr, k, n, step_mask, min_count, vtx_ptr, cls_ptr, target_ptr,
-                    weight_ptr) -> int:
+                    weight_ptr, base_ptr=0) -> int:
     rows = ctypes.c_uint64()
-    _check(ctx, lib().agis_learn_rows(ctx, sums_ptr, counts_ptr, k, n, step_mask, min_count, vtx_ptr, cls_ptr,
-                                      target_ptr, weight_ptr, ctypes.byref(rows)))
+    _check(ctx, lib().agis_learn_rows(ctx, sums_ptr, counts_ptr, k, n, step_mask, min_count, base_ptr or None,
+                                      vtx_ptr, cls_ptr, target_ptr, weight_ptr, ctypes.byref(rows)))
     return int(rows.value)
+
+
+def agis_step_log_weights(ctx, t, b, f1, ie, f2, out_ptr):
+    _check(ctx, lib().agis_step_log_weights(ctx, t, b, f1, ie, f2, out_ptr))
 
 
 def agis_mlp_grad(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, weight_ptr, rows, weight_sum, grad_ptr,
@@ -330,8 +336,9 @@ def agis_mlp_train(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, wei
     return [float(x) for x in losses[:epochs]]
 
 
-def agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr=0):
-    _check(ctx, lib().agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr or None))
+def agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr=0, base_ptr=0):
+    _check(ctx, lib().agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, base_ptr or None, lt_ptr,
+                                     y_ptr or None))
 
 
 def agis_fixed_point_tables():

@@ -426,6 +426,20 @@ hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg,
     return hipGetLastError();
 }
 
+// f_approx log weight (Q16) of every vertex for one step signature, the
+// certain-zero marker where d(v) - b < f1.
+__global__ void k_step_log_weights(const uint4* rec, uint64_t n, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,
+                                   int32_t* out) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) out[v] = approx_log_weight(rec[v], b, f1, ie, f2);
+}
+
+hipError_t launch_step_log_weights(const agis_tables& t, uint64_t n, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,
+                                   int32_t* out, hipStream_t stream) {
+    if (n) hipLaunchKernelGGL(k_step_log_weights, dim3(grid_for(n, 256)), dim3(256), 0, stream, t.rec, n, b, f1, ie, f2, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // First-step proposal over all vertices (the step-1 "cumulative
 // distribution" of the paper): log weights, their maximum, integer weights

@@ -272,8 +272,8 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ params, const float* __restrict__ feats,
-                                                   uint64_t n, uint32_t cls, int32_t* __restrict__ lt,
-                                                   float* __restrict__ yout) {
+                                                   uint64_t n, uint32_t cls, const int32_t* __restrict__ base,
+                                                   int32_t* __restrict__ lt, float* __restrict__ yout) {
     const int lane = lane_id();
     const int col = lane & 31;   // m for A, n for B and D
     const int half = lane >> 5;  // which 8-wide slice of each K step
@@ -327,7 +327,12 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ par
             const int m = 8 * (col / 4) + 4 * half + (col % 4);
             const uint64_t r = tile * 32 + (uint64_t)m;
             if (r < n) {
-                lt[r] = (int32_t)rintf(y * 65536.0f);
+                // clamped to +-2^13 (also maps NaN to a finite value) so the
+                // Q16 code and the residual sum stay inside int32
+                const int32_t q = (int32_t)rintf(fminf(fmaxf(y, -8192.0f), 8192.0f) * 65536.0f);
+                // residual tables: the network's output corrects the f_approx
+                // log weight; certain zeros stay marked
+                lt[r] = base ? (base[r] == kCertainZero ? kCertainZero : base[r] + q) : q;
                 if (yout) yout[r] = y;
             }
         }
@@ -415,13 +420,14 @@ int agis_learn_targets(agis_ctx* ctx, const agis_graph* g, const agis_tables* t,
 }
 
 int agis_learn_rows(agis_ctx* ctx, const double* sums, const uint32_t* counts, uint32_t k, uint64_t n,
-                    uint32_t step_mask, uint32_t min_count, uint32_t* vtx, uint8_t* cls, float* target, float* weight,
-                    uint64_t* rows) {
+                    uint32_t step_mask, uint32_t min_count, const int32_t* base, uint32_t* vtx, uint8_t* cls,
+                    float* target, float* weight, uint64_t* rows) {
     if (!ctx || !sums || !counts || !vtx || !cls || !target || !weight || !rows || k == 0 || k > 8)
         return AGIS_E_INVALID_ARG;
     LHIP(ctx, hipSetDevice(ctx->device), "set device");
     std::vector<double> s(n);
     std::vector<uint32_t> c(n);
+    std::vector<int32_t> bl(base ? n : 0);
     std::vector<uint32_t> hv;
     std::vector<uint8_t> hc;
     std::vector<float> ht, hw;
@@ -430,11 +436,39 @@ int agis_learn_rows(agis_ctx* ctx, const double* sums, const uint32_t* counts, u
         LHIP(ctx, hipMemcpy(s.data(), sums + (uint64_t)i * n, n * sizeof(double), hipMemcpyDeviceToHost), "read sums");
         LHIP(ctx, hipMemcpy(c.data(), counts + (uint64_t)i * n, n * sizeof(uint32_t), hipMemcpyDeviceToHost),
              "read counts");
+        if (base)
+            LHIP(ctx, hipMemcpy(bl.data(), base + (uint64_t)i * n, n * sizeof(int32_t), hipMemcpyDeviceToHost),
+                 "read base");
+        auto kept = [&](uint64_t v) {
+            return c[v] >= min_count && c[v] != 0 && !(base && bl[v] == agis::kCertainZero);
+        };
+        // f_approx log weights are relative (constant factors cancel in the
+        // pick), so their scale is calibrated first: kappa = sum s / sum c B
+        double kappa = 1.0;
+        if (base) {
+            double num = 0.0, den = 0.0;
+            for (uint64_t v = 0; v < n; ++v)
+                if (kept(v)) {
+                    num += s[v];
+                    den += (double)c[v] * std::exp2((double)bl[v] / 65536.0);
+                }
+            if (num > 0.0 && den > 0.0) kappa = num / den;
+        }
         for (uint64_t v = 0; v < n; ++v) {
-            if (c[v] < min_count || c[v] == 0) continue;
+            if (!kept(v)) continue;
+            double tv;
+            if (base) {
+                // posterior mean of the completions with the calibrated
+                // f_approx value kappa B as one pseudo-observation, relative
+                // to kappa B
+                const double kb = kappa * std::exp2((double)bl[v] / 65536.0);
+                tv = std::log2((s[v] / kb + 1.0) / ((double)c[v] + 1.0));
+            } else {
+                tv = std::log2(1.0 + s[v] / (double)c[v]);
+            }
             hv.push_back((uint32_t)v);
             hc.push_back((uint8_t)(i < 3 ? i : 3));
-            ht.push_back((float)std::log2(1.0 + s[v] / (double)c[v]));
+            ht.push_back((float)tv);
             hw.push_back((float)c[v]);
         }
     }
@@ -539,15 +573,24 @@ int agis_mlp_train(agis_ctx* ctx, float* params, const float* feats, const uint3
     return AGIS_OK;
 }
 
+int agis_step_log_weights(agis_ctx* ctx, const agis_tables* t, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,
+                          int32_t* out) {
+    if (!ctx || !t || t->ctx != ctx || !out || b > 7 || f1 > 7 || ie > 7 || f2 > 64) return AGIS_E_INVALID_ARG;
+    LHIP(ctx, hipSetDevice(ctx->device), "set device");
+    LHIP(ctx, agis::launch_step_log_weights(*t, t->graph->g.n, b, f1, ie, f2, out, ctx->stream), "step log weights");
+    LHIP(ctx, hipStreamSynchronize(ctx->stream), "step log weights");
+    return AGIS_OK;
+}
+
 int agis_mlp_infer(agis_ctx* ctx, const float* params, const float* feats, uint64_t n, uint32_t position_class,
-                   int32_t* lt, float* y) {
+                   const int32_t* base, int32_t* lt, float* y) {
     if (!ctx || !params || !feats || !lt || position_class > 3) return AGIS_E_INVALID_ARG;
     LHIP(ctx, hipSetDevice(ctx->device), "set device");
     if (n == 0) return AGIS_OK;
     const uint64_t tiles = (n + 31) / 32;
     const uint64_t blocks = std::min<uint64_t>((tiles + 3) / 4, (uint64_t)ctx->num_cus * 8);
     hipLaunchKernelGGL(agis::k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, params, feats, n,
-                       position_class, lt, y);
+                       position_class, base, lt, y);
     LHIP(ctx, hipGetLastError(), "mlp inference");
     LHIP(ctx, hipStreamSynchronize(ctx->stream), "mlp inference");
     return AGIS_OK;

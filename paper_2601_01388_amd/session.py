@@ -12,6 +12,7 @@ from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, ag
                agis_autotune, agis_compile_pattern, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
                agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
                agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
+               agis_step_log_weights,
                agis_tables_destroy, agis_tables_export, make_params, make_pattern, lib)
 
 
@@ -132,7 +133,19 @@ class Session:
                            sums.data_ptr(), counts.data_ptr())
         return sums, counts
 
-    def learn_rows(self, sums, counts, step_mask: int, min_count: int = 2):
+    def step_log_weights(self, tables: Tables, pattern, mode="learned"):
+        """f_approx Q16 log weights of every vertex, one row per step of the
+        pattern's plan (rows of steps that are not weighted stay zero)."""
+        torch = _torch()
+        plan = agis_compile_pattern(make_pattern(pattern.k, pattern.adj8()), params=make_params(mode=mode))
+        base = torch.zeros((pattern.k, tables.graph.n), dtype=torch.int32, device=self.device)
+        for i in range(pattern.k):
+            if plan.decision[i] and plan.f1[i] > 0:
+                agis_step_log_weights(self.ctx, tables.handle, plan.b[i], plan.f1[i], plan.ie[i], plan.f2[i],
+                                      base[i].data_ptr())
+        return base
+
+    def learn_rows(self, sums, counts, step_mask: int, min_count: int = 2, base=None):
         torch = _torch()
         k, n = sums.shape
         cap = max(k * n, 1)
@@ -141,7 +154,8 @@ class Session:
         tgt = torch.zeros(cap, dtype=torch.float32, device=self.device)
         wt = torch.zeros(cap, dtype=torch.float32, device=self.device)
         rows = agis_learn_rows(self.ctx, sums.data_ptr(), counts.data_ptr(), k, n, step_mask, min_count,
-                               vtx.data_ptr(), cls.data_ptr(), tgt.data_ptr(), wt.data_ptr())
+                               vtx.data_ptr(), cls.data_ptr(), tgt.data_ptr(), wt.data_ptr(),
+                               base.data_ptr() if base is not None else 0)
         return {"vtx": vtx[:rows], "cls": cls[:rows], "target": tgt[:rows], "weight": wt[:rows], "rows": rows}
 
     def mlp_grad(self, params, feats, rows: dict):
@@ -159,22 +173,24 @@ class Session:
                               rows["cls"].data_ptr(), rows["target"].data_ptr(), rows["weight"].data_ptr(),
                               rows["rows"], epochs, batch, lr, seed)
 
-    def mlp_infer(self, params, feats, position_class: int, want_y: bool = False):
+    def mlp_infer(self, params, feats, position_class: int, want_y: bool = False, base=None):
         torch = _torch()
         n = feats.shape[0]
         lt = torch.zeros(n, dtype=torch.int32, device=self.device)
         y = torch.zeros(n, dtype=torch.float32, device=self.device) if want_y else None
         agis_mlp_infer(self.ctx, params.data_ptr(), feats.data_ptr(), n, position_class, lt.data_ptr(),
-                       y.data_ptr() if want_y else 0)
+                       y.data_ptr() if want_y else 0, base.data_ptr() if base is not None else 0)
         return (lt, y) if want_y else lt
 
     def weighted_steps(self, pattern, mode="switch"):
         plan = agis_compile_pattern(make_pattern(pattern.k, pattern.adj8()), params=make_params(mode=mode))
         return [i for i in range(pattern.k) if plan.decision[i] and plan.f1[i] > 0]
 
-    def learned_tables(self, params, feats, pattern):
-        """Q16 pick table per weighted step (position class min(i, 3))."""
-        return {i: self.mlp_infer(params, feats, min(i, 3)) for i in self.weighted_steps(pattern, "learned")}
+    def learned_tables(self, params, feats, pattern, base=None):
+        """Q16 pick table per weighted step (position class min(i, 3)); with
+        base (from step_log_weights) the network's output corrects f_approx."""
+        return {i: self.mlp_infer(params, feats, min(i, 3), base=None if base is None else base[i])
+                for i in self.weighted_steps(pattern, "learned")}
 
     def close(self):
         if self.ctx:
@@ -182,9 +198,11 @@ class Session:
             self.ctx = None
 
 
-def mlp_init(seed: int, target_mean: float = 0.0):
+def mlp_init(seed: int, target_mean: float = 0.0, zero_output: bool = False):
     """Initial parameters (Xavier-uniform weights, zero biases, output bias
-    at the mean target), as a host float32 array in the library's layout."""
+    at the mean target), as a host float32 array in the library's layout.
+    zero_output: output weights start at zero, so the untrained network is
+    the constant target_mean (for residual tables: exactly f_approx)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     h, i = 64, 8
 
@@ -192,6 +210,9 @@ def mlp_init(seed: int, target_mean: float = 0.0):
         lim = np.sqrt(6.0 / (fan_in + fan_out))
         return rng.uniform(-lim, lim, size=(fan_out, fan_in))
 
-    parts = [xavier(h, i).ravel(), np.zeros(h), xavier(h, h).ravel(), np.zeros(h), xavier(1, h).ravel(),
+    w3 = xavier(1, h).ravel()
+    if zero_output:
+        w3 = np.zeros_like(w3)
+    parts = [xavier(h, i).ravel(), np.zeros(h), xavier(h, h).ravel(), np.zeros(h), w3,
              np.array([target_mean])]
     return np.concatenate(parts).astype(np.float32)

@@ -76,6 +76,56 @@ def test_targets_and_rows_parity(sess, small, name):
     assert np.array_equal(rows["weight"].cpu().numpy(), np.array(exp_w, dtype=np.float32))
 
 
+@pytest.mark.parametrize("name", ["house", "5-clique", "4-star", "diamond"])
+def test_step_log_weights_parity(sess, small, name):
+    g, G, T, OT = small
+    p = synth.named_pattern(name)
+    say(f"step log weights {name}")
+    base = sess.step_log_weights(T, p).cpu().numpy()
+    smp = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="learned"), seed=0)
+    steps = sess.weighted_steps(p, "learned")
+    assert steps
+    for i in range(p.k):
+        if i in steps:
+            assert np.array_equal(base[i], smp.log_weights(i)), i
+        else:
+            assert not base[i].any()
+
+
+def test_residual_rows_and_inference(sess, small):
+    import torch
+    from paper_2601_01388_amd.session import mlp_init
+    g, G, T, OT = small
+    p = synth.named_pattern("house")
+    say("residual rows")
+    sums, counts = sess.learn_targets(G, T, p, 30_000, 8, mode="switch")
+    base = sess.step_log_weights(T, p)
+    steps = sess.weighted_steps(p, "learned")
+    rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2, base=base)
+    rs, rc, bl = sums.cpu().numpy(), counts.cpu().numpy(), base.cpu().numpy()
+    exp_v, exp_t = [], []
+    for i in steps:
+        keep = (rc[i] >= 2) & (bl[i] != np.iinfo(np.int32).min)
+        bb = np.exp2(bl[i].astype(np.float64) / 65536.0)
+        kappa = rs[i][keep].sum() / (rc[i][keep] * bb[keep]).sum()
+        for v in np.flatnonzero(keep):
+            exp_v.append(v)
+            exp_t.append(math.log2((rs[i, v] / (kappa * bb[v]) + 1.0) / (rc[i, v] + 1.0)))
+    assert rows["rows"] == len(exp_v) > 0
+    assert np.array_equal(rows["vtx"].cpu().numpy(), np.array(exp_v, dtype=np.int32))
+    assert np.allclose(rows["target"].cpu().numpy(), np.array(exp_t), rtol=1e-5, atol=1e-6)
+    feats = sess.features(T)
+    params = torch.from_numpy(mlp_init(2, 0.0)).to(sess.device)
+    for i in steps:
+        say(f"residual inference step {i}")
+        lt, y = sess.mlp_infer(params, feats, min(i, 3), want_y=True, base=base[i])
+        q = np.rint(y.cpu().numpy() * np.float32(65536.0)).astype(np.int64)
+        b = bl[i].astype(np.int64)
+        cz = b == np.iinfo(np.int32).min
+        exp = np.where(cz, b, b + q)
+        assert np.array_equal(lt.cpu().numpy().astype(np.int64), exp)
+
+
 def _rows_for(sess, G, T, p, n_samples=40_000, seed=5):
     sums, counts = sess.learn_targets(G, T, p, n_samples, seed, mode="switch")
     steps = sess.weighted_steps(p, "learned")
@@ -180,12 +230,16 @@ def test_learned_gain_over_f_approx(sess):
     gains = {}
     for name in ("house", "5-cycle", "4-clique"):
         p = synth.named_pattern(name)
-        rows = _rows_for(sess, Gtr, Ttr, p, n_samples=400_000)
+        sums, counts = sess.learn_targets(Gtr, Ttr, p, 400_000, 5, mode="switch")
+        steps = sess.weighted_steps(p, "learned")
+        rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2,
+                               base=sess.step_log_weights(Ttr, p))
         t = rows["target"].cpu().numpy()
         w = rows["weight"].cpu().numpy()
-        params = torch.from_numpy(mlp_init(7, float(np.average(t, weights=w)))).to(sess.device)
-        sess.mlp_train(params, ftr, rows, epochs=20, batch=4096, lr=3e-3, seed=2)
-        tabs = sess.learned_tables(params, fev, p)
+        params = torch.from_numpy(mlp_init(7, float(np.average(t, weights=w)), zero_output=True)).to(sess.device)
+        epochs = max(20, -(-1000 // max(1, -(-rows["rows"] // 4096))))
+        sess.mlp_train(params, ftr, rows, epochs=epochs, batch=4096, lr=3e-3, seed=2)
+        tabs = sess.learned_tables(params, fev, p, base=sess.step_log_weights(Tev, p))
         learned = {i: tab.data_ptr() for i, tab in tabs.items()}
         n = 500_000
         rl = sess.estimate(Gev, Tev, p, n, 31, mode="learned", learned=learned)
