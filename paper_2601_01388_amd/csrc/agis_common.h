@@ -128,6 +128,10 @@ struct DevPlan {
     uint8_t weighted[kMaxK];  // 1: draw from integer weights; 0: uniform draw
     uint8_t reuse[kMaxK];     // 1: intersect the previous step's candidate set (see sample_one)
     const int32_t* lt[kMaxK]; // learned log weights per step, or nullptr
+    // per-vertex Q16 log weight of a weighted step that builds its candidate
+    // set (certain zeros folded in), or nullptr: then the weight is computed
+    // from the vertex record (and lt)
+    const int32_t* sw[kMaxK];
     // per-row inclusive prefixes of a weighted single-backward step's integer
     // weights (one entry per CSR slot), or nullptr
     const uint64_t* rowpre[kMaxK];

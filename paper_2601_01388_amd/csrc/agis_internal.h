@@ -78,8 +78,10 @@ hipError_t launch_validate_edges(const DevGraph& g, uint32_t* d_flags, hipStream
 hipError_t launch_max_degree(const DevGraph& g, uint32_t* d_max, hipStream_t stream);
 hipError_t launch_build_tables(const DevGraph& g, uint4* rec, uint64_t* s2, uint64_t* hits, uint64_t* trials,
                                uint32_t k0, uint32_t k1, int32_t lc_min, int exact, hipStream_t stream);
+// out[v] = certain-zero marker if d(v) < b + f1, else lt[v] (lt given) or the
+// f_approx log weight of signature (b, f1, ie, f2).
 hipError_t launch_step_log_weights(const agis_tables& t, uint64_t n, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,
-                                   int32_t* out, hipStream_t stream);
+                                   const int32_t* lt, int32_t* out, hipStream_t stream);
 hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg, int32_t* la, int32_t* lc,
                                 hipStream_t stream);
 

@@ -104,6 +104,26 @@ struct Prepared {
     }
 };
 
+// Per-vertex log weights of the weighted steps that build candidate sets,
+// shared by the patterns of one call: one table per (b, f1, ie, f2, learned
+// table).  A candidate's weight is then one 4-byte read instead of a 16-byte
+// record and the arithmetic.  Steps beyond the budget use the records.
+struct StepTables {
+    struct Entry {
+        uint32_t b, f1, ie, f2;
+        const int32_t* lt;
+        int32_t* buf;
+    };
+    std::vector<Entry> e;
+    StepTables() = default;
+    StepTables(const StepTables&) = delete;
+    StepTables& operator=(const StepTables&) = delete;
+    ~StepTables() {
+        for (Entry& x : e) (void)hipFree(x.buf);
+    }
+};
+constexpr uint64_t kStepTableBudgetBytes = 16ull << 30;
+
 // Per-row pick tables are built for runs of at least this many samples
 // (AUTO): their build streams every CSR slot once, which a short run does
 // not amortise.
@@ -111,7 +131,7 @@ constexpr uint64_t kRowtabMinSamples = 65536;
 constexpr uint64_t kRowtabBudgetBytes = 32ull << 30;
 
 int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p, const uint8_t* order,
-            const agis_run_params* params, uint64_t n_samples, Prepared* out) {
+            const agis_run_params* params, uint64_t n_samples, StepTables* st, Prepared* out) {
     int rc = agis::compile_plan(p, order, params->mode, params->beta_num, params->beta_den, &out->plan, &ctx->err);
     if (rc != AGIS_OK) return rc;
     if (params->flags > AGIS_RUN_ROWTAB_OFF) return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
@@ -174,6 +194,23 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     };
     for (uint32_t i = 2; i < hp.k; ++i)
         hp.reuse[i] = (general(i) && general(i - 1) && (hp.bmask[i - 1] & ~hp.bmask[i]) == 0) ? 1 : 0;
+    for (uint32_t i = 1; i < hp.k && g->g.n > 0; ++i) {
+        if (!hp.weighted[i] || hp.rowpre[i] != nullptr) continue;
+        int32_t* buf = nullptr;
+        for (const StepTables::Entry& e : st->e)
+            if (e.b == hp.b[i] && e.f1 == hp.f1[i] && e.ie == hp.ie[i] && e.f2 == hp.f2[i] && e.lt == hp.lt[i])
+                buf = e.buf;
+        if (!buf) {
+            if ((st->e.size() + 1) * g->g.n * sizeof(int32_t) > kStepTableBudgetBytes) continue;
+            AGIS_HIP(ctx, hipMalloc(&buf, g->g.n * sizeof(int32_t)), "allocate step weight table");
+            st->e.push_back(StepTables::Entry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
+            AGIS_HIP(ctx,
+                     agis::launch_step_log_weights(*t, g->g.n, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
+                                                   ctx->stream),
+                     "step weight table");
+        }
+        hp.sw[i] = buf;
+    }
     if (hp.weighted[0] && g->g.n > 0) {
         AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");
         AGIS_HIP(ctx, hipMalloc(&out->pre, g->g.n * sizeof(uint64_t)), "allocate first-step prefix");
@@ -531,8 +568,9 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     if (pp->eps > 0 && !(pp->delta > 0 && pp->delta < 1)) return fail(ctx, AGIS_E_INVALID_ARG, "delta must be in (0, 1)");
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
     const auto t0 = std::chrono::steady_clock::now();
+    StepTables st;
     std::vector<PatternRun> runs(1);
-    rc = prepare(ctx, g, t, p, order, pp, n_samples, &runs[0].prep);
+    rc = prepare(ctx, g, t, p, order, pp, n_samples, &st, &runs[0].prep);
     if (rc != AGIS_OK) return rc;
     runs[0].budget = n_samples;
     const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -557,11 +595,12 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
     if (pp->mode == AGIS_MODE_LEARNED) return fail(ctx, AGIS_E_INVALID_ARG, "learned tables are per pattern: use agis_estimate");
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
     const auto t0 = std::chrono::steady_clock::now();
+    StepTables st;
     std::vector<PatternRun> runs(n_patterns);
     for (uint32_t i = 0; i < n_patterns; ++i) {
         agis_run_params pi = *pp;
         pi.pattern_id = pp->pattern_id + i;
-        rc = prepare(ctx, g, t, &patterns[i], nullptr, &pi, budgets[i], &runs[i].prep);
+        rc = prepare(ctx, g, t, &patterns[i], nullptr, &pi, budgets[i], &st, &runs[i].prep);
         if (rc != AGIS_OK) return rc;
         runs[i].budget = budgets[i];
         runs[i].active = budgets[i] > 0;
@@ -589,8 +628,9 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     const agis_run_params dp = default_params();
     const agis_run_params* pp = params ? params : &dp;
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
+    StepTables st;
     Prepared prep;
-    rc = prepare(ctx, g, t, p, order, pp, m, &prep);
+    rc = prepare(ctx, g, t, p, order, pp, m, &st, &prep);
     if (rc != AGIS_OK) return rc;
     if (m == 0) return AGIS_OK;
     if (m > kMaxRoundSlots) return fail(ctx, AGIS_E_INVALID_ARG, "at most 2^24 records per call");

@@ -426,17 +426,22 @@ hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg,
     return hipGetLastError();
 }
 
-// f_approx log weight (Q16) of every vertex for one step signature, the
-// certain-zero marker where d(v) - b < f1.
+// Log weight (Q16) of every vertex for one step signature: the certain-zero
+// marker where d(v) - b < f1, else the learned value lt[v] or the f_approx
+// value.
 __global__ void k_step_log_weights(const uint4* rec, uint64_t n, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,
-                                   int32_t* out) {
+                                   const int32_t* lt, int32_t* out) {
     const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) out[v] = approx_log_weight(rec[v], b, f1, ie, f2);
+    if (v >= n) return;
+    const uint4 r = rec[v];
+    out[v] = r.x < b + f1 ? kCertainZero : (lt ? lt[v] : approx_log_weight(r, b, f1, ie, f2));
 }
 
 hipError_t launch_step_log_weights(const agis_tables& t, uint64_t n, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,
-                                   int32_t* out, hipStream_t stream) {
-    if (n) hipLaunchKernelGGL(k_step_log_weights, dim3(grid_for(n, 256)), dim3(256), 0, stream, t.rec, n, b, f1, ie, f2, out);
+                                   const int32_t* lt, int32_t* out, hipStream_t stream) {
+    if (n)
+        hipLaunchKernelGGL(k_step_log_weights, dim3(grid_for(n, 256)), dim3(256), 0, stream, t.rec, n, b, f1, ie, f2,
+                           lt, out);
     return hipGetLastError();
 }
 
@@ -702,6 +707,16 @@ hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const uint4* rec, uin
 // ---------------------------------------------------------------------------
 namespace {
 
+// Log weight of candidate v at a weighted step: one 4-byte read of the
+// step's table when it was built, else from the 16-byte vertex record.
+__device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int32_t* sw, const int32_t* lt, uint32_t v,
+                                                   uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2) {
+    if (sw) return sw[v];
+    const uint4 r = t.rec[v];
+    if (r.x < b + f1) return kCertainZero;
+    return lt ? lt[v] : approx_log_weight(r, b, f1, ie, f2);
+}
+
 // In-order sample: returns its weight X; lane 0 writes the record when
 // rec != nullptr.  `my_tau` of lane j holds the data vertex matched at step
 // j (wave-uniform by construction).  sv/sl: this wave's scratch for the
@@ -867,6 +882,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 }
                 const uint32_t b = P->b[i], f1 = P->f1[i], ie = P->ie[i], f2 = P->f2[i];
                 const int32_t* lt = P->lt[i];
+                const int32_t* sw = P->sw[i];
                 const uint32_t vprev = readlane_u32(my_tau, (int)i - 1);
                 int32_t lmax_l = kCertainZero;
                 if (weighted && reuse && (uint32_t)lane + 1 < i) {
@@ -878,10 +894,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         const uint64_t o = g.off[w];
                         in_all = contains_u32(g.nbr + o, (uint32_t)(g.off[w + 1] - o), my_tau);
                     }
-                    if (in_all) {
-                        const uint4 r = t.rec[my_tau];
-                        if (r.x >= b + f1) lmax_l = lt ? lt[my_tau] : approx_log_weight(r, b, f1, ie, f2);
-                    }
+                    if (in_all) lmax_l = step_log_weight(t, sw, lt, my_tau, b, f1, ie, f2);
                 }
                 uint32_t my_pos = 0;  // lane j: window start in backward list j
                 uint64_t cnt = 0;
@@ -901,8 +914,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     }
                     int32_t l = kCertainZero;
                     if (weighted && member) {
-                        const uint4 r = t.rec[xv];
-                        if (r.x >= b + f1) l = lt ? lt[xv] : approx_log_weight(r, b, f1, ie, f2);
+                        l = step_log_weight(t, sw, lt, xv, b, f1, ie, f2);
                         if (l != kCertainZero && l > lmax_l) lmax_l = l;
                     }
                     bool in_tau = false;

@@ -577,7 +577,7 @@ int agis_step_log_weights(agis_ctx* ctx, const agis_tables* t, uint32_t b, uint3
                           int32_t* out) {
     if (!ctx || !t || t->ctx != ctx || !out || b > 7 || f1 > 7 || ie > 7 || f2 > 64) return AGIS_E_INVALID_ARG;
     LHIP(ctx, hipSetDevice(ctx->device), "set device");
-    LHIP(ctx, agis::launch_step_log_weights(*t, t->graph->g.n, b, f1, ie, f2, out, ctx->stream), "step log weights");
+    LHIP(ctx, agis::launch_step_log_weights(*t, t->graph->g.n, b, f1, ie, f2, nullptr, out, ctx->stream), "step log weights");
     LHIP(ctx, hipStreamSynchronize(ctx->stream), "step log weights");
     return AGIS_OK;
 }
