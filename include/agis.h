@@ -247,8 +247,8 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
  * blocks_per_cu = resident 256-thread workgroups per compute unit (0 = as
  * many as fit); grab = sample slots a wave takes from the queue at a time
  * (0 = chosen from the round size, at most 1024); variant = register
- * budget of the sampling kernel (0 = compiler's choice, 1 = at most 5
- * waves' worth per SIMD lane set, 2 = 6). */
+ * budget of the sampling kernel (0 = compiler's choice; 1 and 2 = small
+ * enough for 7 and 8 resident waves per SIMD, spilling the rest). */
 int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant);
 
 /* Launch configuration chosen by agis_autotune. */

@@ -104,9 +104,27 @@ AGIS_HD uint32_t weight_from_log(int32_t lmax, int32_t l, const uint32_t* exp2ta
 // ---------------------------------------------------------------------------
 // Structs passed to kernels by value.
 // ---------------------------------------------------------------------------
+
+// Buffers behind the pointers below are always global memory.  In device
+// code the pointers carry that address space, so loads through them are
+// global loads (scalar base + 32-bit vector offset) rather than FLAT loads,
+// which take 64-bit vector addresses and share the wait counter of scalar
+// and LDS accesses.  Host code sees ordinary pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AGIS_GMEM __attribute__((address_space(1)))
+#else
+#define AGIS_GMEM
+#endif
+
+// Host code stores ordinary pointers into these fields through gmem().
+template <typename T>
+AGIS_HD AGIS_GMEM T* gmem(T* p) {
+    return (AGIS_GMEM T*)p;
+}
+
 struct DevGraph {
-    const uint64_t* off;
-    const uint32_t* nbr;
+    AGIS_GMEM const uint64_t* off;
+    AGIS_GMEM const uint32_t* nbr;
     uint64_t n;
     uint64_t nnz;
 };
@@ -114,7 +132,7 @@ struct DevGraph {
 // Per-vertex record: x = degree, y = LA (Q16 log2 of S2/d), z = LC (Q16
 // log2 of C_v, clamped), w = unused.
 struct DevTables {
-    const uint4* rec;
+    AGIS_GMEM const uint4* rec;
 };
 
 struct DevPlan {
@@ -127,18 +145,18 @@ struct DevPlan {
     uint8_t f2[kMaxK];
     uint8_t weighted[kMaxK];  // 1: draw from integer weights; 0: uniform draw
     uint8_t reuse[kMaxK];     // 1: intersect the previous step's candidate set (see sample_one)
-    const int32_t* lt[kMaxK]; // learned log weights per step, or nullptr
+    AGIS_GMEM const int32_t* lt[kMaxK];  // learned log weights per step, or nullptr
     // per-vertex Q16 log weight of a weighted step that builds its candidate
     // set (certain zeros folded in), or nullptr: then the weight is computed
     // from the vertex record (and lt)
-    const int32_t* sw[kMaxK];
+    AGIS_GMEM const int32_t* sw[kMaxK];
     // per-row inclusive prefixes of a weighted single-backward step's integer
     // weights (one entry per CSR slot), or nullptr
-    const uint64_t* rowpre[kMaxK];
+    AGIS_GMEM const uint64_t* rowpre[kMaxK];
     // first-step table of a weighted first step: integer weight of every
     // vertex, its inclusive prefix and the total
-    const uint32_t* s1_q;
-    const uint64_t* s1_pre;
+    AGIS_GMEM const uint32_t* s1_q;
+    AGIS_GMEM const uint64_t* s1_pre;
     uint64_t s1_total;
 };
 
@@ -174,13 +192,13 @@ struct Record;
 struct LaunchDesc {
     DevGraph g;
     DevTables t;
-    const DevPlan* plans;
-    const uint64_t* idx;       // non-null: the single segment's sample indices
-    Record* dump;              // non-null: one record per slot
-    uint32_t* scratch;         // per wave: cap vertices + cap log weights
+    AGIS_GMEM const DevPlan* plans;
+    AGIS_GMEM const uint64_t* idx;        // non-null: the single segment's sample indices
+    AGIS_GMEM Record* dump;               // non-null: one record per slot
+    AGIS_GMEM uint32_t* scratch;          // per wave: cap vertices + cap log weights
     uint64_t cap;
-    unsigned long long* queue; // next free slot
-    double* xout;              // weight per slot
+    AGIS_GMEM unsigned long long* queue;  // next free slot
+    AGIS_GMEM double* xout;               // weight per slot
     uint32_t grab;
     uint32_t pad;
     RoundDesc round;

@@ -149,7 +149,7 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         hp.weighted[i] = (out->plan.decision[i] && out->plan.f1[i] > 0) ? 1 : 0;
         if (params->mode == AGIS_MODE_LEARNED && hp.weighted[i]) {
             if (!params->learned[i]) return fail(ctx, AGIS_E_INVALID_ARG, "learned mode needs a table for every weighted step");
-            hp.lt[i] = params->learned[i];
+            hp.lt[i] = agis::gmem(params->learned[i]);
         }
     }
     const auto t0 = std::chrono::steady_clock::now();
@@ -182,7 +182,7 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
                          "row pick table");
                 built.push_back(Key{hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
             }
-            hp.rowpre[i] = buf;
+            hp.rowpre[i] = agis::gmem((const uint64_t*)buf);
         }
     }
     // A step builds its candidate set in the wave's scratch unless it draws
@@ -209,15 +209,15 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
                                                    ctx->stream),
                      "step weight table");
         }
-        hp.sw[i] = buf;
+        hp.sw[i] = agis::gmem((const int32_t*)buf);
     }
     if (hp.weighted[0] && g->g.n > 0) {
         AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");
         AGIS_HIP(ctx, hipMalloc(&out->pre, g->g.n * sizeof(uint64_t)), "allocate first-step prefix");
         uint64_t total = 0;
         AGIS_HIP(ctx, agis::build_step1(ctx, *g, *t, hp, out->q1, out->pre, &total), "first-step table");
-        hp.s1_q = out->q1;
-        hp.s1_pre = out->pre;
+        hp.s1_q = agis::gmem((const uint32_t*)out->q1);
+        hp.s1_pre = agis::gmem((const uint64_t*)out->pre);
         hp.s1_total = total;
     }
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "proposal tables");
@@ -310,7 +310,7 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
     if (rc != AGIS_OK) return rc;
     agis::LaunchDesc ld;
     std::memset(&ld, 0, sizeof(ld));
-    agis::fill_launch(ctx, L, g->g, agis::DevTables{t->rec}, nullptr, nullptr, &ld);
+    agis::fill_launch(ctx, L, g->g, agis::DevTables{agis::gmem((const uint4*)t->rec)}, nullptr, nullptr, &ld);
     agis::RoundDesc& rd = ld.round;
     std::vector<Partial> parts;
     std::vector<uint32_t> members;
@@ -466,7 +466,7 @@ int agis_load_csr(agis_ctx* ctx, const uint64_t* off, const uint32_t* nbr, uint6
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "read offsets");
     if (ends[0] != 0 || ends[1] != nnz) return fail(ctx, AGIS_E_INVALID_CSR, "off[0] must be 0 and off[n] must be nnz");
     if (nnz & 1ull) return fail(ctx, AGIS_E_INVALID_CSR, "nnz of a symmetric graph must be even");
-    agis::DevGraph dg{off, nbr, n, nnz};
+    agis::DevGraph dg{agis::gmem(off), agis::gmem(nbr), n, nnz};
     uint32_t* d_cells = (uint32_t*)ctx->d_small;
     uint32_t cells[2] = {0, 0};
     AGIS_HIP(ctx, hipMemsetAsync(d_cells, 0, 2 * sizeof(uint32_t), ctx->stream), "clear flags");
@@ -640,7 +640,7 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     L.dump = true;
     agis::LaunchDesc ld;
     std::memset(&ld, 0, sizeof(ld));
-    agis::fill_launch(ctx, L, g->g, agis::DevTables{t->rec}, idx, (agis::Record*)out, &ld);
+    agis::fill_launch(ctx, L, g->g, agis::DevTables{agis::gmem((const uint4*)t->rec)}, idx, (agis::Record*)out, &ld);
     agis::RoundDesc& rd = ld.round;
     rd.total = m;
     rd.nseg = 1;

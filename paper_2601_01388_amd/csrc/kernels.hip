@@ -77,6 +77,17 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// A wave-uniform value moved to a scalar register (the compiler cannot
+// always prove uniformity, and a uniform value in a vector register costs
+// 64 lanes of register file).
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    return ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32) | uniform_u32((uint32_t)v);
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -769,8 +780,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint64_t o = g.off[w];
                 const uint32_t d = (uint32_t)(g.off[w + 1] - o);
                 const uint32_t* list = g.nbr + o;
-                const uint64_t* pre = P->rowpre[i] + o;  // global prefix; row-relative below
-                const uint64_t base = o > 0 ? P->rowpre[i][o - 1] : 0ull;
+                const AGIS_GMEM uint64_t* rp = P->rowpre[i];
+                const uint64_t* pre = rp + o;  // global prefix; row-relative below
+                const uint64_t base = o > 0 ? rp[o - 1] : 0ull;
                 uint32_t pos = 0xFFFFFFFFu;
                 bool found = false;
                 uint64_t qx = 0;
@@ -881,8 +893,8 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     others = lists & ~(1u << jb);
                 }
                 const uint32_t b = P->b[i], f1 = P->f1[i], ie = P->ie[i], f2 = P->f2[i];
-                const int32_t* lt = P->lt[i];
-                const int32_t* sw = P->sw[i];
+                const AGIS_GMEM int32_t* lt = P->lt[i];
+                const AGIS_GMEM int32_t* sw = P->sw[i];
                 const uint32_t vprev = readlane_u32(my_tau, (int)i - 1);
                 int32_t lmax_l = kCertainZero;
                 if (weighted && reuse && (uint32_t)lane + 1 < i) {
@@ -946,13 +958,13 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     num = cnt;
                     den = 1;
                 } else {
-                    const int32_t lmax = wave_max_i32(lmax_l);
+                    const int32_t lmax = (int32_t)uniform_u32((uint32_t)wave_max_i32(lmax_l));
                     uint64_t qs = 0;
                     for (uint64_t c = (uint64_t)lane; c < cnt; c += kWave) {
                         const int32_t l = sl[c];
                         qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
                     }
-                    const uint64_t Q = wave_sum_u64(qs);
+                    const uint64_t Q = uniform_u64(wave_sum_u64(qs));
                     if (Q == 0) {
                         fail = (int)i;
                         break;
@@ -982,8 +994,11 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     num = Q;
                 }
             }
+            num = uniform_u64(num);
+            den = uniform_u64(den);
             x = x * ((double)num / (double)den);
         }
+        v = uniform_u32(v);
         if ((uint32_t)lane == i) my_tau = v;
         if (kDump && lane == 0) {
             rec->v[i] = v;
@@ -1029,23 +1044,27 @@ __device__ __forceinline__ Partial chan_merge(Partial a, const Partial& b) {
 // kDump: the record-writing variant (index lists and records), compiled
 // apart so the production kernel carries none of that state.  kWavesPerEU:
 // register budget of the variant -- at least that many waves per SIMD must
-// fit (4 leaves the compiler its own choice here; 5 and 6 trade a few
-// spills for more resident waves); the autotuner picks the fastest.
+// fit (4 leaves the compiler its own choice, 80 registers and 6 waves here;
+// 7 and 8 trade spills for more resident waves); the autotuner picks the
+// fastest.
 template <bool kDump, int kWavesPerEU>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU)))
 void k_sample(const LaunchDesc* __restrict__ D) {
     const int lane = lane_id();
-    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + uniform_u32(threadIdx.x / kWave);
     const uint64_t cap = D->cap;
     uint32_t* sv = D->scratch + gw * cap * 2;
     int32_t* sl = (int32_t*)(sv + cap);
     const RoundDesc* __restrict__ round = &D->round;
     const uint64_t total = round->total;
     const uint32_t grab = D->grab;
+    const DevGraph g = D->g;
+    const DevTables t = D->t;
+    AGIS_GMEM double* xout = D->xout;
     uint32_t sg = 0;  // segment of the current slot (slots a wave takes only increase)
     unsigned long long cur = 0;
     if (lane == 0) cur = atomicAdd(D->queue, (unsigned long long)grab);
-    cur = __shfl(cur, 0, kWave);
+    cur = uniform_u64(cur);
     while (cur < total) {
         unsigned long long next = 0;
         if (lane == 0) next = atomicAdd(D->queue, (unsigned long long)grab);
@@ -1056,11 +1075,10 @@ void k_sample(const LaunchDesc* __restrict__ D) {
             const uint64_t off = j - S.base;
             const uint64_t sidx = kDump ? D->idx[off] : S.start + off;
             Record* rec = kDump ? D->dump + j : nullptr;
-            const double xv =
-                sample_one<kDump>(D->g, D->t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec);
-            if (lane == 0) D->xout[j] = xv;
+            const double xv = sample_one<kDump>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec);
+            if (lane == 0) xout[j] = xv;
         }
-        cur = __shfl(next, 0, kWave);
+        cur = uniform_u64(next);
     }
 }
 
@@ -1122,9 +1140,9 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 const void* sample_kernel(bool dump, int variant) {
     switch (variant) {
         case 1:
-            return dump ? reinterpret_cast<const void*>(k_sample<true, 5>) : reinterpret_cast<const void*>(k_sample<false, 5>);
+            return dump ? reinterpret_cast<const void*>(k_sample<true, 7>) : reinterpret_cast<const void*>(k_sample<false, 7>);
         case 2:
-            return dump ? reinterpret_cast<const void*>(k_sample<true, 6>) : reinterpret_cast<const void*>(k_sample<false, 6>);
+            return dump ? reinterpret_cast<const void*>(k_sample<true, 8>) : reinterpret_cast<const void*>(k_sample<false, 8>);
         default:
             return dump ? reinterpret_cast<const void*>(k_sample<true, 4>) : reinterpret_cast<const void*>(k_sample<false, 4>);
     }
@@ -1206,13 +1224,13 @@ void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const 
                  Record* dump, LaunchDesc* D) {
     D->g = g;
     D->t = t;
-    D->plans = ctx->d_plans;
-    D->idx = idx;
-    D->dump = dump;
-    D->scratch = (uint32_t*)ctx->d_scratch;
+    D->plans = gmem((const DevPlan*)ctx->d_plans);
+    D->idx = gmem(idx);
+    D->dump = gmem(dump);
+    D->scratch = gmem((uint32_t*)ctx->d_scratch);
     D->cap = L.cap;
-    D->queue = (unsigned long long*)((char*)ctx->d_small + 64);
-    D->xout = ctx->d_xout;
+    D->queue = gmem((unsigned long long*)((char*)ctx->d_small + 64));
+    D->xout = gmem(ctx->d_xout);
     D->grab = L.grab;
     D->pad = 0;
 }
