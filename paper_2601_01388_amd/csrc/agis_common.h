@@ -112,14 +112,20 @@ AGIS_HD uint32_t weight_from_log(int32_t lmax, int32_t l, const uint32_t* exp2ta
 // and LDS accesses.  Host code sees ordinary pointers of the same size.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define AGIS_GMEM __attribute__((address_space(1)))
+#define AGIS_CMEM __attribute__((address_space(4)))
 #else
 #define AGIS_GMEM
+#define AGIS_CMEM
 #endif
 
 // Host code stores ordinary pointers into these fields through gmem().
 template <typename T>
 AGIS_HD AGIS_GMEM T* gmem(T* p) {
     return (AGIS_GMEM T*)p;
+}
+template <typename T>
+AGIS_HD AGIS_CMEM T* cmem(T* p) {
+    return (AGIS_CMEM T*)p;
 }
 
 struct DevGraph {
@@ -192,7 +198,7 @@ struct Record;
 struct LaunchDesc {
     DevGraph g;
     DevTables t;
-    AGIS_GMEM const DevPlan* plans;
+    AGIS_CMEM const DevPlan* plans;  // read-only while a round runs: scalar loads
     AGIS_GMEM const uint64_t* idx;        // non-null: the single segment's sample indices
     AGIS_GMEM Record* dump;               // non-null: one record per slot
     AGIS_GMEM uint32_t* scratch;          // per wave: cap vertices + cap log weights

@@ -771,6 +771,11 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
         } else {
             const uint32_t bm = P->bmask[i];
             const bool weighted = P->weighted[i] != 0;
+            // At the last step only the size of a uniform draw's candidate
+            // set enters X (no later step reads the vertex): the production
+            // kernel counts the set and skips the draw; the record-writing
+            // variant still picks the vertex.
+            const bool count_only = !kDump && !weighted && i + 1 == k;
             if (weighted && P->rowpre[i] != nullptr) {
                 // Weighted draw from S = N(w) minus the matched vertices
                 // through the row's prefix of integer weights: subtract the
@@ -844,14 +849,17 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     fail = (int)i;
                     break;
                 }
-                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, m);
-                uint64_t idx = r;
-                for (;;) {
-                    const uint64_t c = (uint64_t)__popcll(__ballot(found && (uint64_t)pos <= idx));
-                    if (r + c == idx) break;
-                    idx = r + c;
+                v = 0;
+                if (!count_only) {
+                    const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, m);
+                    uint64_t idx = r;
+                    for (;;) {
+                        const uint64_t c = (uint64_t)__popcll(__ballot(found && (uint64_t)pos <= idx));
+                        if (r + c == idx) break;
+                        idx = r + c;
+                    }
+                    v = list[idx];
                 }
-                v = list[idx];
                 num = m;
                 den = 1;
             } else {
@@ -939,7 +947,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     const uint64_t km = __ballot(keep);
                     // in-place compaction is safe when base == sv: every write
                     // position is below the chunk already held in registers
-                    if (keep) {
+                    if (keep && !count_only) {
                         const uint64_t p = cnt + (uint64_t)__popcll(km & lanemask_lt());
                         sv[p] = xv;
                         sl[p] = l;
@@ -953,8 +961,8 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         fail = (int)i;
                         break;
                     }
-                    const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, cnt);
-                    v = sv[r];
+                    v = 0;
+                    if (!count_only) v = sv[bounded_draw(k0, k1, c0, c1, c2, i, cnt)];
                     num = cnt;
                     den = 1;
                 } else {
@@ -1224,7 +1232,7 @@ void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const 
                  Record* dump, LaunchDesc* D) {
     D->g = g;
     D->t = t;
-    D->plans = gmem((const DevPlan*)ctx->d_plans);
+    D->plans = cmem((const DevPlan*)ctx->d_plans);
     D->idx = gmem(idx);
     D->dump = gmem(dump);
     D->scratch = gmem((uint32_t*)ctx->d_scratch);
