@@ -232,19 +232,48 @@ __device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __res
 // One backward list co-iterated with a chunk of ascending base elements
 // (this lane's element xv, the chunk's largest xlast).  Elements of `list`
 // before `pos` are below every element of the chunk, so membership of xv
-// is decided inside the window [pos, end) of elements <= xlast.  A window of
-// at most 64 elements comes from one coalesced load and is searched with
-// register shuffles; a longer one is bounded by a 64-ary wave search and
-// searched per lane.  Clears `member` when xv is absent; returns end, the
-// window start of the next chunk.
+// is decided inside the window [pos, end) of elements <= xlast.  The window
+// is streamed in coalesced 64-element pieces, each searched for every
+// lane's xv with register shuffles, until a piece holds an element above
+// xlast: the bytes read are the window itself, as in a merge.  When the
+// window is expected to be far longer than the chunk (the list is much
+// longer than what is left of the base: left = base elements from this
+// chunk on), it is bounded by a 64-ary wave search instead and searched
+// per lane.  Clears `member` when xv is absent; returns end, the window
+// start of the next chunk.
+constexpr uint32_t kStreamMaxWindow = 2048;
+
 __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict__ list, uint32_t pos, uint32_t len,
-                                                      uint32_t xv, uint32_t xlast, bool& member) {
+                                                      uint32_t xv, uint32_t xlast, uint32_t left, bool& member) {
     const int lane = lane_id();
+    const uint64_t expect = (uint64_t)(len - pos) * kWave / (left ? left : 1u);
+    if (expect <= kStreamMaxWindow) {
+        bool hit = false;
+        for (;;) {
+            const uint32_t p = pos + (uint32_t)lane;
+            const uint32_t val = p < len ? list[p] : 0xFFFFFFFFu;  // ids are < n <= 2^32 - 1
+            int lo = 0;
+#pragma unroll
+            for (int s = 32; s > 0; s >>= 1) {
+                const uint32_t pv = __shfl(val, lo + s - 1, kWave);
+                if (pv < xv) lo += s;
+            }
+            // every lane takes part in each shuffle (a lane outside the
+            // exec mask would not supply its value to the others)
+            const uint32_t cand = __shfl(val, lo, kWave);
+            hit = hit || cand == xv;
+            const uint64_t gt = __ballot(val > xlast);
+            if (gt != 0) {
+                member = member && hit;
+                return pos + (uint32_t)(__ffsll((unsigned long long)gt) - 1);
+            }
+            pos += kWave;
+        }
+    }
     const uint32_t p = pos + (uint32_t)lane;
-    const uint32_t val = p < len ? list[p] : 0xFFFFFFFFu;  // ids are < n <= 2^32 - 1
+    const uint32_t val = p < len ? list[p] : 0xFFFFFFFFu;
     const uint64_t gt = __ballot(val > xlast);
     if (gt != 0) {
-        // the 64 loaded values ascend across lanes: lower bound of xv by shuffles
         int lo = 0;
 #pragma unroll
         for (int s = 32; s > 0; s >>= 1) {
@@ -929,7 +958,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         const uint32_t* lj = g.nbr + readlane_u64(my_o, j);
                         const uint32_t dj = readlane_u32(my_d, j);
                         const uint32_t pos = readlane_u32(my_pos, j);
-                        const uint32_t end = co_iterate_member(lj, pos, dj, xv, xlast, member);
+                        const uint32_t end = co_iterate_member(lj, pos, dj, xv, xlast, db - c, member);
                         if (lane == j) my_pos = end;
                     }
                     int32_t l = kCertainZero;
