@@ -243,45 +243,68 @@ __device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __res
 // start of the next chunk.
 constexpr uint32_t kStreamMaxWindow = 2048;
 
+// Whether this lane's xv occurs among the 64 ascending values held one per
+// lane (val): a binary search by shuffles.  Every lane must take part (a
+// lane outside the exec mask would not supply its value to the others).
+__device__ __forceinline__ bool piece_contains(uint32_t val, uint32_t xv) {
+    int lo = 0;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+        const uint32_t pv = __shfl(val, lo + s - 1, kWave);
+        if (pv < xv) lo += s;
+    }
+    const uint32_t cand = __shfl(val, lo, kWave);
+    return cand == xv;
+}
+
 __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict__ list, uint32_t pos, uint32_t len,
                                                       uint32_t xv, uint32_t xlast, uint32_t left, bool& member) {
     const int lane = lane_id();
     const uint64_t expect = (uint64_t)(len - pos) * kWave / (left ? left : 1u);
     if (expect <= kStreamMaxWindow) {
+        // up to 4 pieces are loaded together (sized by the expected window)
+        // so their latencies overlap; pieces past the window are reused by
+        // the next chunk through the cache
+        const uint32_t np = expect <= 64 ? 1u : expect <= 128 ? 2u : expect <= 192 ? 3u : 4u;
+        constexpr uint32_t kNone = 0xFFFFFFFFu;  // ids are < n <= 2^32 - 1
         bool hit = false;
         for (;;) {
             const uint32_t p = pos + (uint32_t)lane;
-            const uint32_t val = p < len ? list[p] : 0xFFFFFFFFu;  // ids are < n <= 2^32 - 1
-            int lo = 0;
-#pragma unroll
-            for (int s = 32; s > 0; s >>= 1) {
-                const uint32_t pv = __shfl(val, lo + s - 1, kWave);
-                if (pv < xv) lo += s;
+            const uint32_t v0 = p < len ? list[p] : kNone;
+            const uint32_t v1 = (np > 1 && p + 64 < len) ? list[p + 64] : kNone;
+            const uint32_t v2 = (np > 2 && p + 128 < len) ? list[p + 128] : kNone;
+            const uint32_t v3 = (np > 3 && p + 192 < len) ? list[p + 192] : kNone;
+            uint64_t gt = __ballot(v0 > xlast);
+            hit = piece_contains(v0, xv) || hit;
+            uint32_t at = 0;
+            if (gt == 0 && np > 1) {
+                at = 64;
+                gt = __ballot(v1 > xlast);
+                hit = piece_contains(v1, xv) || hit;
+                if (gt == 0 && np > 2) {
+                    at = 128;
+                    gt = __ballot(v2 > xlast);
+                    hit = piece_contains(v2, xv) || hit;
+                    if (gt == 0 && np > 3) {
+                        at = 192;
+                        gt = __ballot(v3 > xlast);
+                        hit = piece_contains(v3, xv) || hit;
+                    }
+                }
             }
-            // every lane takes part in each shuffle (a lane outside the
-            // exec mask would not supply its value to the others)
-            const uint32_t cand = __shfl(val, lo, kWave);
-            hit = hit || cand == xv;
-            const uint64_t gt = __ballot(val > xlast);
             if (gt != 0) {
                 member = member && hit;
-                return pos + (uint32_t)(__ffsll((unsigned long long)gt) - 1);
+                return pos + at + (uint32_t)(__ffsll((unsigned long long)gt) - 1);
             }
-            pos += kWave;
+            pos += np * kWave;
         }
     }
     const uint32_t p = pos + (uint32_t)lane;
     const uint32_t val = p < len ? list[p] : 0xFFFFFFFFu;
     const uint64_t gt = __ballot(val > xlast);
     if (gt != 0) {
-        int lo = 0;
-#pragma unroll
-        for (int s = 32; s > 0; s >>= 1) {
-            const uint32_t pv = __shfl(val, lo + s - 1, kWave);
-            if (pv < xv) lo += s;
-        }
-        const uint32_t cand = __shfl(val, lo, kWave);
-        member = member && cand == xv;
+        const bool in = piece_contains(val, xv);
+        member = member && in;
         return pos + (uint32_t)(__ffsll((unsigned long long)gt) - 1);
     }
     const uint32_t end = wave_first_greater_u32(list, pos + kWave, len, xlast);
