@@ -262,41 +262,64 @@ __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict
     const int lane = lane_id();
     const uint64_t expect = (uint64_t)(len - pos) * kWave / (left ? left : 1u);
     if (expect <= kStreamMaxWindow) {
-        // up to 4 pieces are loaded together (sized by the expected window)
-        // so their latencies overlap; pieces past the window are reused by
-        // the next chunk through the cache
-        const uint32_t np = expect <= 64 ? 1u : expect <= 128 ? 2u : expect <= 192 ? 3u : 4u;
+        // Blocks of 256 elements, 4 consecutive ones per lane from one
+        // 16-byte load (blocks are aligned to 16 bytes in memory, so the
+        // first may start up to 3 elements before pos; elements before pos
+        // are below the chunk and never match).  A lane finds the lane whose
+        // quad may hold its xv by a shuffle search over the quads' first
+        // elements, then compares with that quad: 10 shuffles per 256
+        // elements.  Reads stay inside [0, len) of the list.
         constexpr uint32_t kNone = 0xFFFFFFFFu;  // ids are < n <= 2^32 - 1
+        const int64_t mis = (int64_t)(((uintptr_t)list >> 2) & 3u);
+        int64_t qs = (int64_t)(((uint64_t)pos + (uint64_t)mis) & ~3ull) - mis;  // block start, >= pos - 3
         bool hit = false;
         for (;;) {
-            const uint32_t p = pos + (uint32_t)lane;
-            const uint32_t v0 = p < len ? list[p] : kNone;
-            const uint32_t v1 = (np > 1 && p + 64 < len) ? list[p + 64] : kNone;
-            const uint32_t v2 = (np > 2 && p + 128 < len) ? list[p + 128] : kNone;
-            const uint32_t v3 = (np > 3 && p + 192 < len) ? list[p + 192] : kNone;
-            uint64_t gt = __ballot(v0 > xlast);
-            hit = piece_contains(v0, xv) || hit;
-            uint32_t at = 0;
-            if (gt == 0 && np > 1) {
-                at = 64;
-                gt = __ballot(v1 > xlast);
-                hit = piece_contains(v1, xv) || hit;
-                if (gt == 0 && np > 2) {
-                    at = 128;
-                    gt = __ballot(v2 > xlast);
-                    hit = piece_contains(v2, xv) || hit;
-                    if (gt == 0 && np > 3) {
-                        at = 192;
-                        gt = __ballot(v3 > xlast);
-                        hit = piece_contains(v3, xv) || hit;
-                    }
-                }
+            const int64_t e = qs + 4 * (int64_t)lane;
+            uint32_t v0, v1, v2, v3;
+            if (e >= 0 && e + 3 < (int64_t)len) {
+                const uint4 q = *reinterpret_cast<const uint4*>(list + e);
+                v0 = q.x;
+                v1 = q.y;
+                v2 = q.z;
+                v3 = q.w;
+            } else {
+                v0 = e < 0 ? 0u : (e < (int64_t)len ? list[e] : kNone);
+                v1 = e + 1 < 0 ? 0u : (e + 1 < (int64_t)len ? list[e + 1] : kNone);
+                v2 = e + 2 < 0 ? 0u : (e + 2 < (int64_t)len ? list[e + 2] : kNone);
+                v3 = e + 3 < (int64_t)len ? list[e + 3] : kNone;
             }
-            if (gt != 0) {
+            // window end: first element at or after pos above xlast
+            const int64_t dp = (int64_t)pos - e;  // elements of this quad before pos
+            const uint64_t m0 = __ballot(dp <= 0 && v0 > xlast);
+            const uint64_t m1 = __ballot(dp <= 1 && v1 > xlast);
+            const uint64_t m2 = __ballot(dp <= 2 && v2 > xlast);
+            const uint64_t m3 = __ballot(dp <= 3 && v3 > xlast);
+            // membership of xv
+            int lo = 0;
+#pragma unroll
+            for (int s = 32; s > 0; s >>= 1) {
+                const uint32_t pv = __shfl(v0, lo + s, kWave);
+                if (pv <= xv) lo += s;
+            }
+            const uint32_t a0 = __shfl(v0, lo, kWave);
+            const uint32_t a1 = __shfl(v1, lo, kWave);
+            const uint32_t a2 = __shfl(v2, lo, kWave);
+            const uint32_t a3 = __shfl(v3, lo, kWave);
+            // only elements at or after pos count (this also excludes the
+            // zero fill before the list's start)
+            const int64_t dl = (int64_t)pos - (qs + 4 * (int64_t)lo);
+            hit = hit || (a0 == xv && dl <= 0) || (a1 == xv && dl <= 1) || (a2 == xv && dl <= 2) ||
+                  (a3 == xv && dl <= 3);
+            if ((m0 | m1 | m2 | m3) != 0) {
+                int64_t endi = INT64_MAX;
+                if (m0) endi = qs + 4 * (__ffsll((unsigned long long)m0) - 1);
+                if (m1) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m1) - 1) + 1);
+                if (m2) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m2) - 1) + 2);
+                if (m3) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m3) - 1) + 3);
                 member = member && hit;
-                return pos + at + (uint32_t)(__ffsll((unsigned long long)gt) - 1);
+                return (uint32_t)endi;
             }
-            pos += np * kWave;
+            qs += 4 * kWave;
         }
     }
     const uint32_t p = pos + (uint32_t)lane;
@@ -970,10 +993,26 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 }
                 uint32_t my_pos = 0;  // lane j: window start in backward list j
                 uint64_t cnt = 0;
+                // Software pipeline over the chunks: the next chunk's base
+                // elements are loaded one chunk ahead, and a chunk's weights
+                // (gathered from the step table) are stored and folded into
+                // the maximum during the next chunk, so base, window and
+                // weight loads of neighbouring chunks are in flight together.
+                // In-place compaction stays safe when base == sv: every store
+                // lands below the chunk being read, and the prefetched chunk
+                // lies above both.
+                constexpr uint32_t kNone = 0xFFFFFFFFu;
+                uint32_t xv_next = (uint32_t)lane < db ? base[lane] : kNone;
+                int32_t pend_l = kCertainZero;  // previous chunk: gathered log weight,
+                uint32_t pend_p = 0;            // its scratch slot,
+                bool pend_member = false;       // whether it is in I,
+                bool pend_keep = false;         // whether it is stored
                 for (uint32_t c = 0; c < db; c += kWave) {
                     const uint32_t nvalid = (db - c) < (uint32_t)kWave ? (db - c) : (uint32_t)kWave;
                     const bool valid = (uint32_t)lane < nvalid;
-                    const uint32_t xv = valid ? base[c + (uint32_t)lane] : 0xFFFFFFFFu;
+                    const uint32_t xv = xv_next;
+                    const uint32_t nx = c + (uint32_t)kWave + (uint32_t)lane;
+                    xv_next = nx < db ? base[nx] : kNone;
                     const uint32_t xlast = readlane_u32(xv, (int)nvalid - 1);
                     bool member = valid;
                     for (uint32_t bits = others; bits; bits &= bits - 1) {
@@ -984,11 +1023,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         const uint32_t end = co_iterate_member(lj, pos, dj, xv, xlast, db - c, member);
                         if (lane == j) my_pos = end;
                     }
+                    if (pend_member && pend_l != kCertainZero && pend_l > lmax_l) lmax_l = pend_l;
+                    if (pend_keep) sl[pend_p] = pend_l;
                     int32_t l = kCertainZero;
-                    if (weighted && member) {
-                        l = step_log_weight(t, sw, lt, xv, b, f1, ie, f2);
-                        if (l != kCertainZero && l > lmax_l) lmax_l = l;
-                    }
+                    if (weighted && member) l = step_log_weight(t, sw, lt, xv, b, f1, ie, f2);
                     bool in_tau = false;
                     if (reuse) {
                         in_tau = xv == vprev;
@@ -997,15 +1035,19 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     }
                     const bool keep = member && !in_tau;
                     const uint64_t km = __ballot(keep);
-                    // in-place compaction is safe when base == sv: every write
-                    // position is below the chunk already held in registers
+                    uint32_t p = 0;
                     if (keep && !count_only) {
-                        const uint64_t p = cnt + (uint64_t)__popcll(km & lanemask_lt());
+                        p = (uint32_t)cnt + (uint32_t)__popcll(km & lanemask_lt());
                         sv[p] = xv;
-                        sl[p] = l;
                     }
+                    pend_member = weighted && member;
+                    pend_keep = weighted && keep;
+                    pend_p = p;
+                    pend_l = l;
                     cnt += (uint64_t)__popcll(km);
                 }
+                if (pend_member && pend_l != kCertainZero && pend_l > lmax_l) lmax_l = pend_l;
+                if (pend_keep) sl[pend_p] = pend_l;
                 scnt = cnt;
                 __threadfence_block();
                 if (!weighted) {
