@@ -260,8 +260,8 @@ __device__ __forceinline__ bool piece_contains(uint32_t val, uint32_t xv) {
 __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict__ list, uint32_t pos, uint32_t len,
                                                       uint32_t xv, uint32_t xlast, uint32_t left, bool& member) {
     const int lane = lane_id();
-    const uint64_t expect = (uint64_t)(len - pos) * kWave / (left ? left : 1u);
-    if (expect <= kStreamMaxWindow) {
+    // expected window (len - pos) * 64 / left <= kStreamMaxWindow, without a division
+    if ((uint64_t)(len - pos) * kWave <= (uint64_t)kStreamMaxWindow * (left ? left : 1u)) {
         // Blocks of 256 elements, 4 consecutive ones per lane from one
         // 16-byte load (blocks are aligned to 16 bytes in memory, so the
         // first may start up to 3 elements before pos; elements before pos
