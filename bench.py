@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--tune-pilot", type=int, default=1 << 18)
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
+    ap.add_argument("--skip-ablation", action="store_true")
+    ap.add_argument("--ablation-samples", type=int, default=1 << 20,
+                    help="samples per configuration of the term-ablation and beta sweeps")
     ap.add_argument("--train-samples", type=int, default=1 << 20, help="sampler runs producing training targets")
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--train-min-steps", type=int, default=1500, help="fewest Adam steps per pattern")
@@ -307,14 +310,15 @@ def main():
     eps_table = {}
     if not args.skip_eps:
         for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
-            for mode in ("learned", "switch", "uniform"):
+            for mode in ("learned", "switch", "always", "uniform"):
                 if mode == "learned" and name not in learned:
                     continue
                 kw = dict(learned=learned[name]["ptrs"]) if mode == "learned" else {}
                 r = sess.estimate(G, T, p, args.eps_budget, 11, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
                                   check_every=1 << 16, min_samples=1 << 14, **kw)
                 need = r.n * (r.eps_hat / 0.01) ** 2 if math.isfinite(r.eps_hat) else None
-                label = {"switch": "f_approx", "uniform": "f_uniform", "learned": "learned"}[mode]
+                label = {"switch": "f_approx", "always": "f_approx_always", "uniform": "f_uniform",
+                         "learned": "learned"}[mode]
                 entry = {
                     "seconds": r.seconds, "converged": bool(r.converged), "samples": r.n, "estimate": r.estimate,
                     "eps_hat": r.eps_hat, "rel_var": r.variance / max(r.estimate ** 2, 1e-300),
@@ -345,6 +349,43 @@ def main():
                 "seconds": chosen["seconds"] + pilot_s, "samples": chosen["samples"],
                 "converged": chosen["converged"], "estimate": chosen["estimate"], "rel_var": chosen["rel_var"]}
             log(f"{name}: pilot keeps {'learned' if keep else 'f_approx'}")
+
+    # incremental terms of f_approx (T[F1]; T[F1] T[I1]; all three) and the
+    # switching threshold beta, as in the paper's analysis of the
+    # approximation and of beta: variance per sample and the samples
+    # Algorithm 1 needs for +-1% at 95% (z^2 rel.var / eps^2)
+    ablation = None
+    if not args.skip_ablation:
+        z2 = 1.959963984540054 ** 2
+        ablation = {"samples": args.ablation_samples, "terms": {}, "beta": {}}
+        t0 = time.perf_counter()
+        for name in ["4-clique", "4-path", "5-clique", "5-cycle", "house"]:
+            p = synth.named_pattern(name)
+            row = {}
+            for terms in ("f1", "f1_i1", "all"):
+                r = sess.estimate(G, T, p, args.ablation_samples, 17, mode="switch", terms=terms)
+                rv = r.variance / max(r.estimate ** 2, 1e-300)
+                row[terms] = {"rel_var": rv, "samples_needed": z2 * rv / 1e-4, "estimate": r.estimate,
+                              "seconds_per_sample": r.seconds / r.n}
+            ablation["terms"][name] = row
+        betas = [("-inf", (-1, 0)), ("1/2", (1, 2)), ("4/5", (4, 5)), ("5/6", (5, 6)), ("1", (1, 1)),
+                 ("+inf", (1, 0))]
+        for name in ["house", "5-cycle", "6-cycle", "chordal-7-cycle"]:
+            p = synth.named_pattern(name)
+            row = {}
+            for label, beta in betas:
+                r = sess.estimate(G, T, p, args.ablation_samples, 19, mode="switch", beta=beta)
+                rv = r.variance / max(r.estimate ** 2, 1e-300)
+                row[label] = {"rel_var": rv, "samples_needed": z2 * rv / 1e-4, "estimate": r.estimate,
+                              "seconds_per_sample": r.seconds / r.n,
+                              "uniform_steps": int(sum(1 for i in range(p.k) if not r.plan.decision[i]))}
+            ablation["beta"][name] = row
+        ablation["seconds"] = time.perf_counter() - t0
+        log(f"term ablation and beta sweep: {ablation['seconds']:.1f} s")
+        for name, row in ablation["terms"].items():
+            log("  terms " + name + ": " + ", ".join(f"{k} {v['rel_var']:.3g}" for k, v in row.items()))
+        for name, row in ablation["beta"].items():
+            log("  beta " + name + ": " + ", ".join(f"{k} {v['rel_var']:.3g}" for k, v in row.items()))
 
     # 32 connected patterns of 4-7 vertices (seed 3) with uneven budgets,
     # all run to +-1% in one batch of rounds (each a persistent launch)
@@ -400,6 +441,7 @@ def main():
         "tuning": tuning,
         "per_pattern": per_pattern,
         "batch_32_patterns": batch,
+        "term_ablation_and_beta": ablation,
         "time_to_1pct": eps_table,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -112,18 +112,27 @@ typedef struct {
  *   neighbour draws through per-row pick tables built for this estimate
  *   (same samples either way; AUTO builds them for runs of >= 65536
  *   samples when they fit in memory).
+ * terms: which factors of f_approx (Eq. probability_function) enter the
+ *   weights -- AGIS_TERMS_ALL (T[F1] T[I1] T[F2], the method), or the
+ *   incremental versions of the paper's analysis of the approximation
+ *   (Sec. 7, analysis of the approximate distribution): AGIS_TERMS_F1
+ *   (T[F1] only) and AGIS_TERMS_F1_I1 (T[F1] T[I1]).  The decision function
+ *   and the reported plan are unchanged.
  * learned: for AGIS_MODE_LEARNED, per step a device int32[n] table of Q16
  *   log2 weights (NULL for steps that are not weighted); ignored otherwise. */
 #define AGIS_RUN_ROWTAB_AUTO 0u
 #define AGIS_RUN_ROWTAB_ON 1u
 #define AGIS_RUN_ROWTAB_OFF 2u
+#define AGIS_TERMS_ALL 0u
+#define AGIS_TERMS_F1 1u
+#define AGIS_TERMS_F1_I1 2u
 typedef struct {
     int32_t mode;
     int32_t beta_num;
     int32_t beta_den;
     uint32_t pattern_id;
     uint32_t flags;
-    uint32_t reserved;
+    uint32_t terms;
     double eps;
     double delta;
     uint64_t check_every;

@@ -182,15 +182,23 @@ class Tables:
         return np.where(t > 0, self.hits.astype(np.float64) / np.maximum(t, 1), 0.0)
 
 
-def make_plan(compiled: dict, pattern_id: int = 0) -> Plan:
+TERMS = ("all", "f1", "f1_i1")
+
+
+def make_plan(compiled: dict, pattern_id: int = 0, terms: str = "all") -> Plan:
+    """terms: the factors of f_approx kept in the weights -- all three, or
+    the incremental versions of the paper's analysis of the approximation
+    (T[F1] only; T[F1] T[I1]).  Dropping T[I1] or T[F2] sets its exponent
+    (ie or f2) to zero."""
+    assert terms in TERMS
     P = Plan()
     P.k = compiled["k"]
     P.pattern_id = pattern_id
     for i, s in enumerate(compiled["steps"]):
         P.bmask[i] = s["bmask"]
         P.f1[i] = s["f1"]
-        P.ie[i] = s["ie"]
-        P.f2[i] = s["f2"]
+        P.ie[i] = 0 if terms == "f1" else s["ie"]
+        P.f2[i] = s["f2"] if terms == "all" else 0
         P.decision[i] = s["decision"]
     return P
 
@@ -198,13 +206,14 @@ def make_plan(compiled: dict, pattern_id: int = 0) -> Plan:
 class Sampler:
     """Algorithm 3 over one graph/pattern; all state on the host."""
 
-    def __init__(self, g, tables: Tables, compiled: dict, seed: int, pattern_id: int = 0, learned=None):
+    def __init__(self, g, tables: Tables, compiled: dict, seed: int, pattern_id: int = 0, learned=None,
+                 terms: str = "all"):
         self.g = g
         self.off = np.ascontiguousarray(g.off, dtype=np.uint64)
         self.nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
         self.t = tables
         self.compiled = compiled
-        self.plan = make_plan(compiled, pattern_id)
+        self.plan = make_plan(compiled, pattern_id, terms)
         self.seed = seed
         self._learned = learned
         k = compiled["k"]

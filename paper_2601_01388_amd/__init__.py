@@ -42,6 +42,10 @@ AGIS_RUN_ROWTAB_AUTO = 0
 AGIS_RUN_ROWTAB_ON = 1
 AGIS_RUN_ROWTAB_OFF = 2
 ROWTAB_BY_NAME = {"auto": 0, "on": 1, "off": 2}
+AGIS_TERMS_ALL = 0
+AGIS_TERMS_F1 = 1
+AGIS_TERMS_F1_I1 = 2
+TERMS_BY_NAME = {"all": 0, "f1": 1, "f1_i1": 2}
 LC_MIN_DEFAULT = -10 * 65536
 
 _ERRNAMES = {
@@ -73,7 +77,7 @@ class agis_plan(ctypes.Structure):
 class agis_run_params(ctypes.Structure):
     _fields_ = [
         ("mode", ctypes.c_int32), ("beta_num", ctypes.c_int32), ("beta_den", ctypes.c_int32),
-        ("pattern_id", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("pattern_id", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("terms", ctypes.c_uint32),
         ("eps", ctypes.c_double), ("delta", ctypes.c_double),
         ("check_every", ctypes.c_uint64), ("min_samples", ctypes.c_uint64),
         ("learned", ctypes.c_void_p * MAX_K),
@@ -217,10 +221,11 @@ def make_pattern(k: int, adj) -> agis_pattern:
 
 
 def make_params(mode="switch", beta=(4, 5), pattern_id=0, eps=0.0, delta=0.05, check_every=0, min_samples=0,
-                learned=None, rowtab="auto") -> agis_run_params:
+                learned=None, rowtab="auto", terms="all") -> agis_run_params:
     pr = agis_run_params()
     pr.mode = MODE_BY_NAME[mode] if isinstance(mode, str) else int(mode)
     pr.flags = ROWTAB_BY_NAME[rowtab] if isinstance(rowtab, str) else int(rowtab)
+    pr.terms = TERMS_BY_NAME[terms] if isinstance(terms, str) else int(terms)
     pr.beta_num, pr.beta_den = beta
     pr.pattern_id = pattern_id
     pr.eps = eps

@@ -135,6 +135,7 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     int rc = agis::compile_plan(p, order, params->mode, params->beta_num, params->beta_den, &out->plan, &ctx->err);
     if (rc != AGIS_OK) return rc;
     if (params->flags > AGIS_RUN_ROWTAB_OFF) return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
+    if (params->terms > AGIS_TERMS_F1_I1) return fail(ctx, AGIS_E_INVALID_ARG, "unknown term set");
     DevPlan& hp = out->hp;
     std::memset(&hp, 0, sizeof(hp));
     hp.k = out->plan.k;
@@ -143,8 +144,9 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         hp.bmask[i] = out->plan.bmask[i];
         hp.b[i] = out->plan.b[i];
         hp.f1[i] = out->plan.f1[i];
-        hp.ie[i] = out->plan.ie[i];
-        hp.f2[i] = out->plan.f2[i];
+        // the term ablation drops T[I1] (exponent ie) and T[F2] (exponent f2)
+        hp.ie[i] = params->terms == AGIS_TERMS_F1 ? 0 : out->plan.ie[i];
+        hp.f2[i] = params->terms == AGIS_TERMS_ALL ? out->plan.f2[i] : 0;
         // |F1| = 0 makes every weight C(d - b, 0) = 1: a uniform draw.
         hp.weighted[i] = (out->plan.decision[i] && out->plan.f1[i] > 0) ? 1 : 0;
         if (params->mode == AGIS_MODE_LEARNED && hp.weighted[i]) {

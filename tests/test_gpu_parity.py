@@ -134,6 +134,20 @@ def test_records_parity_c1(sess, c1, c1_state, name, mode, rowtab):
     _compare_records(got, ref, f"{name}/{mode}")
 
 
+@pytest.mark.parametrize("rowtab", ["off", "on"])
+@pytest.mark.parametrize("terms", ["f1", "f1_i1"])
+@pytest.mark.parametrize("name", ["house", "4-clique", "5-cycle", "diamond"])
+def test_records_parity_term_ablation(sess, c1, c1_state, name, terms, rowtab):
+    G, T, OT = c1_state
+    p = synth.named_pattern(name)
+    idx = _indices(2000, rng_seed=7 + sum(name.encode()))
+    say(f"records chung-lu {name} terms={terms} rowtab={rowtab} m={idx.size}")
+    got = sess.dump(G, T, p, SEED, idx, mode="always", pattern_id=2, rowtab=rowtab, terms=terms)
+    c = compile_pattern(p.k, p.edges, mode="always")
+    ref = oracle.Sampler(c1, OT, c, seed=SEED, pattern_id=2, terms=terms).records(idx)
+    _compare_records(got, ref, f"{name}/{terms}")
+
+
 def test_records_shape_invariance(sess, c1, c1_state):
     """The same sample index gives the same record whatever the launch."""
     G, T, OT = c1_state

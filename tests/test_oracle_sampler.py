@@ -153,6 +153,45 @@ def test_unbiased_exact_enumeration(gi, name):
             assert len(succ) == len(r["success"]) == exact
 
 
+@pytest.mark.parametrize("terms", ["f1", "f1_i1"])
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "house", "5-cycle", "diamond"])
+def test_unbiased_exact_enumeration_term_ablation(name, terms):
+    """Theorem 2 holds for any proposal that only zeroes certain zeros: the
+    incremental versions of f_approx are still unbiased."""
+    for gi in (0, 3):
+        g = SMALL_GRAPHS[gi]
+        p = synth.named_pattern(name)
+        exact = judges.brute_force(g, p.k, p.edges)
+        c = compile_pattern(p.k, p.edges, mode="always")
+        s = oracle.Sampler(g, oracle.Tables(g, cv_seed=5), c, seed=3, terms=terms)
+        r = enumerate_tree(s)
+        assert r["p_total"] == 1 and r["ex"] == exact
+
+
+def test_term_ablation_drops_the_right_factor():
+    """Step 1 of the diamond has signature (b, f1, ie, f2) = (0, 3, 2, 0) and
+    of the house (0, 3, 1, 2): T[F1] is d(d-1)(d-2) / 3! (its log is the sum
+    of the three log2fx terms; the 3! cancels), T[I1] adds ie*LC and T[F2]
+    adds f2*LA (Eq. probability_function).  The ablated versions keep
+    exactly the leading factors."""
+    g = synth.chung_lu(n=60, m=300, seed=4)
+    t = oracle.Tables(g, cv_seed=2)
+    d = np.diff(g.off).astype(np.int64)
+    f1_part = np.array([sum(oracle.log2fx(int(x) - j) for j in range(3)) if x >= 3 else 0 for x in d])
+    cz = d < 3
+    for name, ie, f2 in (("diamond", 2, 0), ("house", 1, 2)):
+        p = synth.named_pattern(name)
+        c = compile_pattern(p.k, p.edges, mode="always")
+        st = c["steps"][0]
+        assert (st["b"], st["f1"], st["ie"], st["f2"]) == (0, 3, ie, f2)
+        lw = {terms: oracle.Sampler(g, t, c, seed=0, terms=terms).log_weights(0) for terms in oracle.TERMS}
+        for terms, expect in (("f1", f1_part), ("f1_i1", f1_part + ie * t.lc),
+                              ("all", f1_part + ie * t.lc + f2 * t.la)):
+            got = lw[terms]
+            assert np.all(got[cz] == np.iinfo(np.int32).min)
+            assert np.array_equal(got[~cz], expect[~cz].astype(np.int32)), terms
+
+
 def test_kstar_first_step_is_ideal_zero_variance():
     # Sec. 3.2: drawing the centre with probability proportional to C(d, k)
     # makes every sample return k! * sum_v C(d(v), k) (zero variance).
