@@ -244,16 +244,21 @@ def main():
     # sources are the ones the counters were taken with; the counters give
     # bytes per sample (mean over the four patterns), scaled to this launch
     traffic = None
+    l2_hit = None
     if os.path.exists(COUNTERS_FILE):
         c = json.load(open(COUNTERS_FILE))
         if c.get("kernel_source_sha") == kernel_source_hash():
             traffic = c["hbm_bytes_per_sample_mean"] * args.samples
+            rates = [v.get("l2_hit_rate") for v in c["per_pattern"].values()]
+            if all(r is not None for r in rates):
+                l2_hit = {k: v["l2_hit_rate"] for k, v in c["per_pattern"].items()}
     roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_sample", "avg_launch_ms": 1e3 * avg_launch_s,
                 "algorithmic_bytes_per_launch": mean_bytes * args.samples,
                 "algorithmic_bytes_per_sample": bytes_per_sample,
-                "traffic_gbs": (traffic / avg_launch_s / 1e9) if traffic else None}
+                "traffic_gbs": (traffic / avg_launch_s / 1e9) if traffic else None,
+                "l2_hit_rate": l2_hit}
 
     # learned proposal: one MLP per pattern, trained on extension counts the
     # sampler produces on a smaller R-MAT graph (scale 18, seed 18), then
