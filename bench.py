@@ -121,6 +121,112 @@ def cpu_baseline(g, seconds_target: float):
     }
 
 
+def bpats_budgets(args):
+    import synth
+    pset = synth.random_pattern_set(32, seed=3)
+    return [p for p, _ in pset], [max(1, int(b * args.large_budget_scale)) for _, b in pset]
+
+
+def large_legs(args, sess, G20, T20, pats_budgets, log):
+    import torch
+    import synth
+    from paper_2601_01388_amd.session import mlp_init
+    bpats, budgets = pats_budgets
+    out = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    off, nbr = synth.graphs.rmat_device(24, 16, seed=24, device=str(sess.device))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    G = sess.graph(off, nbr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = sess.tables(G, cv_seed=1)
+    torch.cuda.synchronize()
+    tables_s = time.perf_counter() - t0
+    dmax = int((off[1:] - off[:-1]).max().item())
+    out["graph"] = {"scale": 24, "seed": 24, "generator": "torch GPU Philox stream", "n": G.n, "nnz": G.nnz,
+                    "dmax": dmax, "generate_s": gen_s, "tables_ms": 1e3 * tables_s}
+    log(f"R-MAT scale 24: n={G.n} nnz={G.nnz} dmax={dmax}; generated in {gen_s:.1f} s, tables {1e3 * tables_s:.1f} ms")
+    log(f"32-pattern batch on scale 24 to +-1%, total budget {sum(budgets):.3g} samples")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = sess.estimate_batch(G, T, bpats, budgets, 13, mode="switch", eps=0.01, delta=0.05,
+                              check_every=1 << 16, min_samples=1 << 14)
+    torch.cuda.synchronize()
+    bt = time.perf_counter() - t0
+    out["batch_32_patterns"] = {
+        "budget_scale": args.large_budget_scale, "seconds": bt, "samples": int(sum(r.n for r in res)), "converged": int(sum(r.converged for r in res)),
+        "samples_per_s": sum(r.n for r in res) / bt, "budget_total": int(sum(budgets)),
+        "per_pattern": [{"k": p.k, "edges": len(p.edges), "budget": b, "samples": r.n,
+                         "converged": bool(r.converged), "seconds": r.seconds,
+                         "rel_var": r.variance / max(r.estimate ** 2, 1e-300)}
+                        for p, b, r in zip(bpats, budgets, res)]}
+    log(f"scale-24 batch: {bt:.2f} s, {out['batch_32_patterns']['converged']}/32 converged, "
+        f"{out['batch_32_patterns']['samples']:.3g} samples")
+    # learned proposal per pattern: trained on scale-20 targets, evaluated here
+    f20 = sess.features(T20)
+    f24 = sess.features(T)
+    rows_out = []
+    ratios = []
+    fb_ratios = []
+    t0 = time.perf_counter()
+    for pid, p in enumerate(bpats):
+        steps = sess.weighted_steps(p, "learned")
+        if not steps:
+            rows_out.append({"k": p.k, "edges": len(p.edges), "weighted_steps": 0})
+            continue
+        sums, counts = sess.learn_targets(G20, T20, p, 1 << 19, 301 + pid, mode="switch")
+        rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2,
+                               base=sess.step_log_weights(T20, p))
+        del sums, counts
+        if rows["rows"] == 0:
+            rows_out.append({"k": p.k, "edges": len(p.edges), "weighted_steps": len(steps), "train_rows": 0})
+            continue
+        tg = rows["target"].cpu().numpy()
+        wt = rows["weight"].cpu().numpy()
+        params = torch.from_numpy(mlp_init(11 + pid, float(np.average(tg, weights=wt)), zero_output=True)).to(
+            sess.device)
+        per_epoch = max(1, -(-rows["rows"] // 4096))
+        sess.mlp_train(params, f20, rows, epochs=max(20, -(-1500 // per_epoch)), batch=4096, lr=3e-3, seed=pid)
+        tabs = sess.learned_tables(params, f24, p, base=sess.step_log_weights(T, p))
+        ptrs = {i: tab.data_ptr() for i, tab in tabs.items()}
+        rl = sess.estimate(G, T, p, args.large_eval_samples, 41, mode="learned", learned=ptrs, pattern_id=pid)
+        ra = sess.estimate(G, T, p, args.large_eval_samples, 41, mode="switch", pattern_id=pid)
+        vl = rl.variance / max(rl.estimate ** 2, 1e-300)
+        va = ra.variance / max(ra.estimate ** 2, 1e-300)
+        # fallback: pilots of each mode on other samples keep the learned
+        # tables only where their variance per sample is lower
+        pl = sess.estimate(G, T, p, args.pilot_samples, 43, mode="learned", learned=ptrs, pattern_id=pid)
+        pa = sess.estimate(G, T, p, args.pilot_samples, 43, mode="switch", pattern_id=pid)
+        keep = pl.variance / max(pl.estimate ** 2, 1e-300) < pa.variance / max(pa.estimate ** 2, 1e-300)
+        entry = {"k": p.k, "edges": len(p.edges), "weighted_steps": len(steps), "train_rows": rows["rows"],
+                 "rel_var_learned": vl, "rel_var_f_approx": va, "estimate_learned": rl.estimate,
+                 "estimate_f_approx": ra.estimate, "pilot_keeps_learned": bool(keep)}
+        if va > 0 and vl > 0:
+            entry["learned_over_f_approx"] = vl / va
+            ratios.append(vl / va)
+            fb_ratios.append(vl / va if keep else 1.0)
+        rows_out.append(entry)
+        del tabs, params, rows
+    learned_s = time.perf_counter() - t0
+    geo = float(np.exp(np.mean(np.log(ratios)))) if ratios else None
+    geo_fb = float(np.exp(np.mean(np.log(fb_ratios)))) if fb_ratios else None
+    out["learned_32_patterns"] = {"train_graph": "R-MAT scale 20 (the bench graph)", "eval_samples": args.large_eval_samples,
+                                  "pilot_samples": args.pilot_samples, "seconds": learned_s,
+                                  "geomean_rel_var_learned_over_f_approx": geo,
+                                  "geomean_rel_var_with_fallback_over_f_approx": geo_fb,
+                                  "patterns_better": int(sum(r < 1 for r in ratios)), "patterns_compared": len(ratios),
+                                  "per_pattern": rows_out}
+    log(f"learned on scale 24: geomean variance ratio learned/f_approx {geo} ({geo_fb} with the pilot fallback), "
+        f"{out['learned_32_patterns']['patterns_better']}/{len(ratios)} better, {learned_s:.1f} s")
+    T.close()
+    G.close()
+    del off, nbr
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +245,12 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-ablation", action="store_true")
+    ap.add_argument("--skip-large", action="store_true",
+                    help="skip the R-MAT scale 24 legs (32-pattern batch; learned proposal trained on scale 20)")
+    ap.add_argument("--large-budget-scale", type=float, default=0.1,
+                    help="multiplier on the 32-pattern budgets on R-MAT scale 24 (1.0 = the full budgets)")
+    ap.add_argument("--large-eval-samples", type=int, default=1 << 20,
+                    help="samples per pattern and mode for the learned-vs-f_approx variance on scale 24")
     ap.add_argument("--ablation-samples", type=int, default=1 << 20,
                     help="samples per configuration of the term-ablation and beta sweeps")
     ap.add_argument("--train-samples", type=int, default=1 << 20, help="sampler runs producing training targets")
@@ -418,6 +530,13 @@ def main():
         }
         log(f"batch: {bt:.2f} s, {batch['converged']}/32 converged, {batch['samples']:.3g} samples")
 
+    # R-MAT scale 24 (generated on the GPU): the 32-pattern batch run to
+    # +-1%, and the learned proposal trained on extension counts of the
+    # scale-20 graph, evaluated against f_approx for variance per sample
+    large = None
+    if not args.skip_large:
+        large = large_legs(args, sess, G, T, bpats_budgets(args), log)
+
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(g, args.cpu_seconds)
@@ -446,6 +565,7 @@ def main():
         "tuning": tuning,
         "per_pattern": per_pattern,
         "batch_32_patterns": batch,
+        "rmat24": large,
         "term_ablation_and_beta": ablation,
         "time_to_1pct": eps_table,
         "roofline": roofline,

@@ -24,15 +24,25 @@ def _torch():
 
 
 class Graph:
-    def __init__(self, sess, off: np.ndarray, nbr: np.ndarray, validate: bool = True):
+    """A CSR graph on the device: host numpy arrays (uint64 off, uint32 nbr)
+    are copied; device tensors (int64 off, int32 nbr on the session's GPU)
+    are used in place."""
+
+    def __init__(self, sess, off, nbr, validate: bool = True):
         torch = _torch()
         self.sess = sess
         self.n = int(off.shape[0] - 1)
         self.nnz = int(nbr.shape[0])
         dev = sess.device
-        self.d_off = torch.from_numpy(np.ascontiguousarray(off, dtype=np.uint64).view(np.int64)).to(dev)
-        nb = np.ascontiguousarray(nbr, dtype=np.uint32).view(np.int32)
-        self.d_nbr = torch.from_numpy(nb if nb.size else np.zeros(1, dtype=np.int32)).to(dev)
+        if isinstance(off, torch.Tensor):
+            if off.dtype != torch.int64 or nbr.dtype != torch.int32 or off.device != dev or nbr.device != dev:
+                raise ValueError("device CSR must be int64 offsets and int32 neighbours on the session's GPU")
+            self.d_off = off.contiguous()
+            self.d_nbr = nbr.contiguous() if self.nnz else torch.zeros(1, dtype=torch.int32, device=dev)
+        else:
+            self.d_off = torch.from_numpy(np.ascontiguousarray(off, dtype=np.uint64).view(np.int64)).to(dev)
+            nb = np.ascontiguousarray(nbr, dtype=np.uint32).view(np.int32)
+            self.d_nbr = torch.from_numpy(nb if nb.size else np.zeros(1, dtype=np.int32)).to(dev)
         self.handle = agis_load_csr(sess.ctx, self.d_off.data_ptr(), self.d_nbr.data_ptr(), self.n, self.nnz,
                                     AGIS_CSR_VALIDATE if validate else 0)
 

@@ -136,6 +136,48 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
     return CSR(off=off, nbr=cols, name=f"rmat{scale}_ef{edge_factor}_s{seed}")
 
 
+def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                seed: int = 24, device: str = "cuda"):
+    """The same R-MAT recipe as ``rmat``, drawn on a GPU with torch's
+    counter-based generator (a different stream from ``rmat``'s, so a
+    different graph for the same seed): for scales whose host generation
+    takes minutes.  Returns (off int64[n+1], nbr int32[nnz]) device tensors
+    of the symmetrised, deduplicated, loop-free CSR (off holds uint64
+    values, nbr uint32 ids)."""
+    import torch
+    n = 1 << scale
+    total = edge_factor * n
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    ab, abc = a + b, a + b + c
+    keys = []
+    chunk = 1 << 26
+    done = 0
+    while done < total:
+        cnt = min(chunk, total - done)
+        u = torch.zeros(cnt, dtype=torch.int64, device=device)
+        v = torch.zeros(cnt, dtype=torch.int64, device=device)
+        for _ in range(scale):
+            r = torch.rand(cnt, generator=gen, device=device, dtype=torch.float64)
+            u = (u << 1) | (r >= ab).to(torch.int64)
+            v = (v << 1) | (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64)
+            del r
+        keep = u != v
+        u, v = u[keep], v[keep]
+        keys.append(torch.unique(torch.cat([u * n + v, v * n + u])))
+        del u, v, keep
+        done += cnt
+    key = torch.unique(torch.cat(keys)) if len(keys) > 1 else keys[0]
+    del keys
+    rows = torch.div(key, n, rounding_mode="floor")
+    nbr = (key - rows * n).to(torch.int32)
+    counts = torch.bincount(rows, minlength=n)
+    del key, rows
+    off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    off[1:] = torch.cumsum(counts, 0)
+    return off, nbr
+
+
 def tiny_graph(n: int, p: float, seed: int) -> CSR:
     """Erdos-Renyi G(n, p) for brute-force checks on a handful of vertices."""
     rng = np.random.Generator(np.random.PCG64(seed))
