@@ -100,6 +100,7 @@ def lib():
         L.orc_fixed_point_tables.argtypes = [P, P]
         L.orc_build_tables.argtypes = [P, P, u64, u32, u32, i32, ctypes.c_int, P, P, P, P, P, P]
         L.orc_log_weights.argtypes = [P, P, ctypes.c_int, u64, P]
+        L.orc_tables_at.argtypes = [P, P, P, u64, u32, u32, i32, ctypes.c_int, P, P, P, P, P, P]
         L.orc_step1_table.argtypes = [P, P, P, P, P, P]
         L.orc_step1_table.restype = u64
         L.orc_run.argtypes = [P, P, u64, u64, P, P, P, P, P, P, P, P, u64, u64, u64, u64, P, P, P]
@@ -183,6 +184,21 @@ class Tables:
 
 
 TERMS = ("all", "f1", "f1_i1")
+
+
+def tables_at(g, vertices, cv_seed: int = 0, lc_min: int = LC_MIN_DEFAULT, exact_cv: bool = False) -> dict:
+    """Table entries (deg, s2, hits, trials, la, lc) of the listed vertices
+    only, by the same definitions as Tables."""
+    vs = np.ascontiguousarray(vertices, dtype=np.uint64)
+    m = vs.size
+    out = {"deg": np.zeros(m, np.uint32), "s2": np.zeros(m, np.uint64), "hits": np.zeros(m, np.uint64),
+           "trials": np.zeros(m, np.uint64), "la": np.zeros(m, np.int32), "lc": np.zeros(m, np.int32)}
+    off = np.ascontiguousarray(g.off, dtype=np.uint64)
+    nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
+    lib().orc_tables_at(_p(off), _p(nbr), _p(vs), m, cv_seed & 0xFFFFFFFF, cv_seed >> 32, lc_min, int(exact_cv),
+                        _p(out["deg"]), _p(out["s2"]), _p(out["hits"]), _p(out["trials"]), _p(out["la"]),
+                        _p(out["lc"]))
+    return out
 
 
 def make_plan(compiled: dict, pattern_id: int = 0, terms: str = "all") -> Plan:

@@ -159,54 +159,71 @@ static int contains(const uint32_t* list, uint64_t len, uint32_t x) {
     return lo < len && list[lo] == x;
 }
 
-/* Fills deg, s2, hits, trials, la, lc for every vertex.
+/* Table entries of vertex v (Sec. 4.4): degree, S2 = sum of the neighbour
+ * degrees, the C_v trials (hits out of trials) and the Q16 logs LA and LC.
  * exact_cv = 1: hits = number of edges among N(v), trials = C(d, 2).
  * exact_cv = 0: d(v) sampled ordered pairs of distinct neighbours. */
+static void tables_of_vertex(const uint64_t* off, const uint32_t* nbr, uint64_t v, const uint32_t key[2],
+                             int32_t lc_min, int exact_cv, uint32_t* deg_v, uint64_t* s2_v, uint64_t* hits_v,
+                             uint64_t* trials_v, int32_t* la_v, int32_t* lc_v) {
+    uint64_t d = off[v + 1] - off[v];
+    const uint32_t* row = nbr + off[v];
+    uint64_t s = 0;
+    for (uint64_t e = 0; e < d; ++e) s += off[row[e] + 1] - off[row[e]];
+    uint64_t h = 0, t = 0;
+    if (d >= 2) {
+        if (exact_cv) {
+            for (uint64_t a = 0; a < d; ++a) {
+                const uint32_t* ra = nbr + off[row[a]];
+                uint64_t da = off[row[a] + 1] - off[row[a]];
+                for (uint64_t b = a + 1; b < d; ++b)
+                    if (contains(ra, da, row[b])) ++h;
+            }
+            t = d * (d - 1) / 2;
+        } else {
+            for (uint64_t trial = 0; trial < d; ++trial) {
+                uint64_t a = orc_bounded(key, (uint32_t)v, (uint32_t)trial, 0, 0, d);
+                uint64_t b = orc_bounded(key, (uint32_t)v, (uint32_t)trial, 0, 1, d - 1);
+                if (b >= a) ++b;
+                uint32_t x = row[a], y = row[b];
+                if (contains(nbr + off[x], off[x + 1] - off[x], y)) ++h;
+            }
+            t = d;
+        }
+    }
+    *deg_v = (uint32_t)d;
+    *s2_v = s;
+    *hits_v = h;
+    *trials_v = t;
+    *la_v = d >= 1 ? orc_log2fx(s) - orc_log2fx(d) : 0;
+    if (d < 2 || h == 0) {
+        *lc_v = lc_min;
+    } else {
+        int32_t c = orc_log2fx(h) - orc_log2fx(t);
+        *lc_v = c > lc_min ? c : lc_min;
+    }
+}
+
+/* Fills deg, s2, hits, trials, la, lc for every vertex. */
 void orc_build_tables(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint32_t cv_seed_lo,
                       uint32_t cv_seed_hi, int32_t lc_min, int exact_cv, uint32_t* deg, uint64_t* s2,
                       uint64_t* hits, uint64_t* trials, int32_t* la, int32_t* lc) {
     init_fixed_point();
     uint32_t key[2] = {cv_seed_lo, cv_seed_hi};
-    for (uint64_t v = 0; v < n; ++v) deg[v] = (uint32_t)(off[v + 1] - off[v]);
-    for (uint64_t v = 0; v < n; ++v) {
-        uint64_t s = 0;
-        for (uint64_t e = off[v]; e < off[v + 1]; ++e) s += deg[nbr[e]];
-        s2[v] = s;
-    }
-    for (uint64_t v = 0; v < n; ++v) {
-        uint64_t d = deg[v];
-        const uint32_t* row = nbr + off[v];
-        uint64_t h = 0, t = 0;
-        if (d >= 2) {
-            if (exact_cv) {
-                for (uint64_t a = 0; a < d; ++a) {
-                    const uint32_t* ra = nbr + off[row[a]];
-                    uint64_t da = deg[row[a]];
-                    for (uint64_t b = a + 1; b < d; ++b)
-                        if (contains(ra, da, row[b])) ++h;
-                }
-                t = d * (d - 1) / 2;
-            } else {
-                for (uint64_t trial = 0; trial < d; ++trial) {
-                    uint64_t a = orc_bounded(key, (uint32_t)v, (uint32_t)trial, 0, 0, d);
-                    uint64_t b = orc_bounded(key, (uint32_t)v, (uint32_t)trial, 0, 1, d - 1);
-                    if (b >= a) ++b;
-                    uint32_t x = row[a], y = row[b];
-                    if (contains(nbr + off[x], deg[x], y)) ++h;
-                }
-                t = d;
-            }
-        }
-        hits[v] = h;
-        trials[v] = t;
-        la[v] = d >= 1 ? orc_log2fx(s2[v]) - orc_log2fx(d) : 0;
-        if (d < 2 || h == 0) {
-            lc[v] = lc_min;
-        } else {
-            int32_t c = orc_log2fx(h) - orc_log2fx(t);
-            lc[v] = c > lc_min ? c : lc_min;
-        }
-    }
+    for (uint64_t v = 0; v < n; ++v)
+        tables_of_vertex(off, nbr, v, key, lc_min, exact_cv, &deg[v], &s2[v], &hits[v], &trials[v], &la[v], &lc[v]);
+}
+
+/* The same entries for the listed vertices only (entry j for vs[j]), for
+ * graphs whose whole table takes the oracle too long. */
+void orc_tables_at(const uint64_t* off, const uint32_t* nbr, const uint64_t* vs, uint64_t count, uint32_t cv_seed_lo,
+                   uint32_t cv_seed_hi, int32_t lc_min, int exact_cv, uint32_t* deg, uint64_t* s2, uint64_t* hits,
+                   uint64_t* trials, int32_t* la, int32_t* lc) {
+    init_fixed_point();
+    uint32_t key[2] = {cv_seed_lo, cv_seed_hi};
+    for (uint64_t j = 0; j < count; ++j)
+        tables_of_vertex(off, nbr, vs[j], key, lc_min, exact_cv, &deg[j], &s2[j], &hits[j], &trials[j], &la[j],
+                         &lc[j]);
 }
 
 /* ------------------------------------------------------------------ */

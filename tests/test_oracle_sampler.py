@@ -95,6 +95,16 @@ def test_sampled_cv_is_unbiased():
     assert np.all(np.abs(mean - ex[sel]) < 5 * se + 1e-9)
 
 
+@pytest.mark.parametrize("exact_cv", [False, True])
+def test_tables_at_matches_full_tables(exact_cv):
+    g = synth.chung_lu(n=500, m=3000, seed=8)
+    t = oracle.Tables(g, cv_seed=11, exact_cv=exact_cv)
+    vs = np.array([0, 1, 7, 250, 499, 3, 3], dtype=np.uint64)
+    a = oracle.tables_at(g, vs, cv_seed=11, exact_cv=exact_cv)
+    for k in ("deg", "s2", "hits", "trials", "la", "lc"):
+        assert np.array_equal(a[k], getattr(t, k)[vs.astype(np.int64)]), k
+
+
 def test_lc_clamp_and_la():
     g = synth.star_graph(5)  # centre has C_v = 0, leaves have degree 1
     t = oracle.Tables(g, cv_seed=1)
