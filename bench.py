@@ -245,6 +245,9 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-ablation", action="store_true")
+    ap.add_argument("--skip-conc", action="store_true")
+    ap.add_argument("--conc-budget", type=int, default=20_000_000,
+                    help="sample budget per pattern of the concentration runs (to +-1%%)")
     ap.add_argument("--skip-large", action="store_true",
                     help="skip the R-MAT scale 24 legs (32-pattern batch; learned proposal trained on scale 20)")
     ap.add_argument("--large-budget-scale", type=float, default=0.1,
@@ -530,6 +533,30 @@ def main():
         }
         log(f"batch: {bt:.2f} s, {batch['converged']}/32 converged, {batch['samples']:.3g} samples")
 
+    # concentrations of all connected 4- and 5-vertex patterns (6 and 21),
+    # each pattern run to +-1% inside batched launches, as in the paper's
+    # comparison with MCMC estimators
+    concentration = None
+    if not args.skip_conc:
+        concentration = {}
+        for k in (4, 5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = sess.concentrations(G, T, k, args.conc_budget, 23, mode="switch", eps=0.01, delta=0.05,
+                                      check_every=1 << 16, min_samples=1 << 14)
+            torch.cuda.synchronize()
+            ct = time.perf_counter() - t0
+            res = out["results"]
+            concentration[f"k{k}"] = {
+                "patterns": len(res), "seconds": ct, "budget_per_pattern": args.conc_budget,
+                "converged": int(sum(r.converged for r in res)), "samples": int(sum(r.n for r in res)),
+                "per_pattern": [{"edges": [list(e) for e in p.edges], "copies": r.copies, "eps_hat": r.eps_hat,
+                                 "conc_edge": float(ce), "conc_induced": float(ci), "induced": float(ind)}
+                                for p, r, ce, ci, ind in zip(out["patterns"], res, out["conc_edge"],
+                                                              out["conc_induced"], out["induced"])]}
+            log(f"concentrations k={k}: {len(res)} patterns, {concentration[f'k{k}']['converged']} converged, "
+                f"{ct:.2f} s")
+
     # R-MAT scale 24 (generated on the GPU): the 32-pattern batch run to
     # +-1%, and the learned proposal trained on extension counts of the
     # scale-20 graph, evaluated against f_approx for variance per sample
@@ -566,6 +593,7 @@ def main():
         "per_pattern": per_pattern,
         "batch_32_patterns": batch,
         "rmat24": large,
+        "concentrations": concentration,
         "term_ablation_and_beta": ablation,
         "time_to_1pct": eps_table,
         "roofline": roofline,

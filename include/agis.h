@@ -279,6 +279,21 @@ int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint
                   const agis_pattern* patterns, uint64_t pilot_samples, const agis_run_params* params,
                   agis_tuning* out);
 
+/* Concentrations of the connected k-vertex patterns (2 <= k <= 6), the
+ * quantity the paper compares with MCMC estimators (Sec. 7, comparison
+ * with MCMC): each pattern's count divided by the total over all
+ * patterns of its size.  Host arrays of n_patterns entries; patterns must
+ * be pairwise non-isomorphic, connected, of one size, and hold every
+ * connected graph of that size with more edges than one of them (all of
+ * them, normally).  copies: edge-induced counts (agis_result.copies).
+ * Outputs (each may be NULL): conc_edge = copies / sum(copies); induced =
+ * vertex-induced counts, from copies(H) = sum_G s(H, G) induced(G) over
+ * the patterns G with at least H's edges, s(H, G) = the copies of H as a
+ * spanning subgraph of G (solved from the most edges down); conc_induced =
+ * induced / sum(induced).  No GPU work; no context. */
+int agis_concentrations(uint32_t n_patterns, const agis_pattern* patterns, const double* copies, double* conc_edge,
+                        double* induced, double* conc_induced);
+
 /* Runs the samples whose indices are listed in idx (device uint64[m]) and
  * writes one agis_record per index into out (device, m records). */
 int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,

@@ -141,6 +141,7 @@ _SIGNATURES = [
     ("agis_mlp_train", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_float, ctypes.c_uint64, _P]),
     ("agis_mlp_infer", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, _P]),
+    ("agis_concentrations", ctypes.c_int, [ctypes.c_uint32, _P, _P, _P, _P, _P]),
     ("agis_fixed_point_tables", ctypes.c_int, [_P, _P]),
     ("agis_philox4x32_10", ctypes.c_int, [_P, _P, _P]),
 ]
@@ -344,6 +345,19 @@ def agis_mlp_train(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, wei
 def agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr=0, base_ptr=0):
     _check(ctx, lib().agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, base_ptr or None, lt_ptr,
                                      y_ptr or None))
+
+
+def agis_concentrations(patterns, copies):
+    """(conc_edge, induced, conc_induced) as numpy arrays."""
+    n = len(patterns)
+    arr = (agis_pattern * n)(*patterns)
+    c = np.ascontiguousarray(copies, dtype=np.float64)
+    ce = np.zeros(n)
+    ind = np.zeros(n)
+    ci = np.zeros(n)
+    _check(None, lib().agis_concentrations(n, ctypes.cast(arr, _P), c.ctypes.data, ce.ctypes.data, ind.ctypes.data,
+                                           ci.ctypes.data))
+    return ce, ind, ci
 
 
 def agis_fixed_point_tables():

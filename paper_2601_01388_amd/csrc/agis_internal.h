@@ -64,6 +64,11 @@ namespace agis {
 int compile_plan(const agis_pattern* p, const uint8_t* order, int mode, int beta_num, int beta_den,
                  agis_plan* out, std::string* err);
 
+// Edge-induced and vertex-induced concentrations from copy counts of every
+// connected k-pattern (see agis_concentrations).
+int concentrations(uint32_t n, const agis_pattern* patterns, const double* copies, double* conc_edge, double* induced,
+                   double* conc_induced, std::string* err);
+
 // Host copies of the Q16 tables (generated on first use) and their upload
 // into the device constant tables of this library.
 const int32_t* host_logtab();

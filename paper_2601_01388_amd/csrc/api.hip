@@ -559,6 +559,12 @@ int agis_compile_pattern(const agis_pattern* p, const uint8_t* order, const agis
     return agis::compile_plan(p, order, pp->mode, pp->beta_num, pp->beta_den, out, &err);
 }
 
+int agis_concentrations(uint32_t n_patterns, const agis_pattern* patterns, const double* copies, double* conc_edge,
+                        double* induced, double* conc_induced) {
+    std::string err;
+    return agis::concentrations(n_patterns, patterns, copies, conc_edge, induced, conc_induced, &err);
+}
+
 int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
                   const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
                   agis_result* out) {

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "agis.h"
 #include "agis_internal.h"
@@ -237,6 +238,134 @@ int compile_plan(const agis_pattern* p, const uint8_t* order_in, int mode, int b
             d = (int64_t)s.cert_num * beta_den >= (int64_t)beta_num * s.cert_den ? 1 : 0;
         }
         out->decision[i] = (uint8_t)d;
+    }
+    return AGIS_OK;
+}
+
+namespace {
+
+// Canonical code of a graph on k <= 6 vertices given as a bitmask over the
+// vertex pairs (a, b), a < b, in lexicographic order: the smallest pair mask
+// over all relabellings.
+uint32_t pair_index(int a, int b, int k) {
+    // index of (a, b), a < b, among the pairs of k vertices in lexicographic order
+    return (uint32_t)(a * (2 * k - a - 1) / 2 + (b - a - 1));
+}
+
+uint32_t canonical_code(uint32_t mask, int k) {
+    int perm[8];
+    for (int i = 0; i < k; ++i) perm[i] = i;
+    uint32_t best = 0xFFFFFFFFu;
+    do {
+        uint32_t m = 0;
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b)
+                if (mask >> pair_index(a, b, k) & 1u) {
+                    const int x = std::min(perm[a], perm[b]), y = std::max(perm[a], perm[b]);
+                    m |= 1u << pair_index(x, y, k);
+                }
+        best = std::min(best, m);
+    } while (std::next_permutation(perm, perm + k));
+    return best;
+}
+
+bool mask_connected(uint32_t mask, int k) {
+    agis_pattern p{};
+    p.k = (uint32_t)k;
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b)
+            if (mask >> pair_index(a, b, k) & 1u) {
+                p.adj[a] |= (uint8_t)(1u << b);
+                p.adj[b] |= (uint8_t)(1u << a);
+            }
+    return connected(p);
+}
+
+}  // namespace
+
+int concentrations(uint32_t n, const agis_pattern* patterns, const double* copies, double* conc_edge, double* induced,
+                   double* conc_induced, std::string* err) {
+    if (n == 0 || !patterns || !copies) {
+        *err = "null or empty pattern set";
+        return AGIS_E_INVALID_ARG;
+    }
+    const int k = (int)patterns[0].k;
+    if (k < 2 || k > 6) {
+        *err = "concentrations need 2 <= k <= 6";
+        return AGIS_E_INVALID_ARG;
+    }
+    std::vector<uint32_t> mask(n), code(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const agis_pattern& p = patterns[i];
+        if ((int)p.k != k || !connected(p)) {
+            *err = "every pattern must be connected and of the same size";
+            return AGIS_E_PATTERN;
+        }
+        uint32_t m = 0;
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b)
+                if (p.adj[a] >> b & 1u) m |= 1u << pair_index(a, b, k);
+        mask[i] = m;
+        code[i] = canonical_code(m, k);
+        for (uint32_t j = 0; j < i; ++j)
+            if (code[j] == code[i]) {
+                *err = "patterns must be pairwise non-isomorphic";
+                return AGIS_E_INVALID_ARG;
+            }
+    }
+    auto index_of = [&](uint32_t c) -> int {
+        for (uint32_t j = 0; j < n; ++j)
+            if (code[j] == c) return (int)j;
+        return -1;
+    };
+    // s[h][g]: copies of pattern h as a spanning subgraph of pattern g (edge
+    // subsets of g isomorphic to h); the set must contain every connected
+    // graph that is such a subgraph's supergraph on the same vertices, i.e. be
+    // closed under adding edges
+    const uint32_t npairs = (uint32_t)(k * (k - 1) / 2);
+    for (uint32_t i = 0; i < n; ++i)
+        for (uint32_t e = 0; e < npairs; ++e)
+            if (!(mask[i] >> e & 1u) && index_of(canonical_code(mask[i] | (1u << e), k)) < 0) {
+                *err = "the pattern set must hold every connected graph of its size with more edges";
+                return AGIS_E_INVALID_ARG;
+            }
+    std::vector<double> s((size_t)n * n, 0.0);
+    for (uint32_t g = 0; g < n; ++g) {
+        // enumerate the edge subsets of pattern g
+        std::vector<int> bits;
+        for (uint32_t e = 0; e < npairs; ++e)
+            if (mask[g] >> e & 1u) bits.push_back((int)e);
+        for (uint32_t sub = 1; sub < (1u << bits.size()); ++sub) {
+            uint32_t m = 0;
+            for (size_t j = 0; j < bits.size(); ++j)
+                if (sub >> j & 1u) m |= 1u << bits[j];
+            if (!mask_connected(m, k)) continue;
+            const int h = index_of(canonical_code(m, k));
+            if (h >= 0) s[(size_t)h * n + g] += 1.0;
+        }
+    }
+    // copies(h) = sum_g s[h][g] induced(g): solve from the most edges down
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(),
+              [&](uint32_t a, uint32_t b) { return __builtin_popcount(mask[a]) > __builtin_popcount(mask[b]); });
+    std::vector<double> ind(n, 0.0);
+    for (uint32_t oi = 0; oi < n; ++oi) {
+        const uint32_t h = order[oi];
+        double v = copies[h];
+        for (uint32_t g = 0; g < n; ++g)
+            if (g != h) v -= s[(size_t)h * n + g] * ind[g];
+        ind[h] = v / s[(size_t)h * n + h];
+    }
+    double se = 0.0, si = 0.0;
+    for (uint32_t i = 0; i < n; ++i) {
+        se += copies[i];
+        si += ind[i];
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        if (conc_edge) conc_edge[i] = se != 0.0 ? copies[i] / se : 0.0;
+        if (induced) induced[i] = ind[i];
+        if (conc_induced) conc_induced[i] = si != 0.0 ? ind[i] / si : 0.0;
     }
     return AGIS_OK;
 }

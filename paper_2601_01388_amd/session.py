@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, agis_build_proposal_tables,
-               agis_autotune, agis_compile_pattern, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
+               agis_autotune, agis_compile_pattern, agis_concentrations, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
                agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
                agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
                agis_step_log_weights,
@@ -110,6 +110,21 @@ class Session:
     def autotune(self, graph: Graph, tables: Tables, patterns, pilot_samples: int, **kw):
         ps = [make_pattern(p.k, p.adj8()) for p in patterns]
         return agis_autotune(self.ctx, graph.handle, tables.handle, ps, pilot_samples, make_params(**kw))
+
+    def concentrations(self, graph: Graph, tables: Tables, k: int, budget: int, seed: int, **kw):
+        """Estimates every connected k-vertex pattern (batched launches of at
+        most 64 patterns) and returns their concentrations: edge-induced
+        (copies / total) and vertex-induced (agis_concentrations)."""
+        import synth
+        pats = synth.patterns.connected_patterns(k)
+        res = []
+        for lo in range(0, len(pats), 64):
+            chunk = pats[lo:lo + 64]
+            kw2 = dict(kw)
+            kw2["pattern_id"] = kw.get("pattern_id", 0) + lo
+            res += self.estimate_batch(graph, tables, chunk, [budget] * len(chunk), seed, **kw2)
+        ce, ind, ci = agis_concentrations([make_pattern(p.k, p.adj8()) for p in pats], [r.copies for r in res])
+        return {"patterns": pats, "results": res, "conc_edge": ce, "induced": ind, "conc_induced": ci}
 
     def set_launch(self, use_graphs=True, blocks_per_cu=0, grab=0, variant=0):
         agis_set_launch(self.ctx, use_graphs, blocks_per_cu, grab, variant)

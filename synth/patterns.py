@@ -149,3 +149,28 @@ def random_pattern_set(count: int = 32, seed: int = 3, kmin: int = 4, kmax: int 
         budget = int(round(10 ** (lo + (hi - lo) * rng.random())))
         out.append((_mk(k, have, f"rand{len(out):02d}_k{k}"), budget))
     return out
+
+
+def connected_patterns(k: int):
+    """Every connected graph on k vertices (2 <= k <= 6) up to isomorphism,
+    one representative each, ordered by edge count and then by canonical
+    code: 1, 2, 6, 21 and 112 patterns for k = 2..6."""
+    if not (2 <= k <= 6):
+        raise ValueError("connected_patterns supports 2 <= k <= 6")
+    pairs = list(itertools.combinations(range(k), 2))
+    seen = {}
+    for mask in range(1 << len(pairs)):
+        edges = {pairs[j] for j in range(len(pairs)) if mask >> j & 1}
+        if len(edges) < k - 1:
+            continue
+        p = _mk(k, edges, "")
+        if not p.is_connected():
+            continue
+        code = _canonical(k, edges)
+        if code not in seen:
+            seen[code] = edges
+    out = []
+    for code in sorted(seen, key=lambda c: (len(seen[c]), c)):
+        out.append(_mk(k, seen[code], f"k{k}_{len(out):02d}"))
+    return out
+

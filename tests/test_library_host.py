@@ -6,10 +6,12 @@ import os
 import re
 from fractions import Fraction
 
+import numpy as np
 import pytest
 
 import oracle
 import synth
+from oracle import judges
 from oracle.pattern import compile_pattern
 from test_oracle_primitives import _kat
 
@@ -116,3 +118,29 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower() or f == "__init__.py" and "oracle" not in text, f
                 assert "import oracle" not in text and "from oracle" not in text
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_library_concentrations_match_oracle(k):
+    """agis_concentrations (host code of the library) against the oracle's
+    inversion on exact copy counts."""
+    from oracle import concentration as conc
+    from oracle.pattern import automorphisms
+    pats = synth.patterns.connected_patterns(k)
+    tup = [(p.k, list(p.edges)) for p in pats]
+    g = synth.graphs.tiny_graph(8, 0.5, 77)
+    copies = [judges.brute_force(g, p.k, p.edges) // automorphisms(p.k, p.edges) for p in pats]
+    ce, ind, ci = A.agis_concentrations([A.make_pattern(p.k, p.adj8()) for p in pats], copies)
+    ref = conc.induced_from_copies(tup, copies)
+    assert np.allclose(ind, [float(x) for x in ref], rtol=1e-12, atol=1e-9)
+    assert np.allclose(ce, [float(x) for x in conc.normalise(copies)], rtol=1e-12)
+    assert np.allclose(ci, [float(x) for x in conc.normalise(ref)], rtol=1e-12)
+
+
+def test_library_concentrations_rejects_incomplete_sets():
+    pats = synth.patterns.connected_patterns(4)
+    ps = [A.make_pattern(p.k, p.adj8()) for p in pats]
+    with pytest.raises(A.AgisError):
+        A.agis_concentrations(ps[:-1], [1.0] * 5)  # the 4-clique is missing
+    with pytest.raises(A.AgisError):
+        A.agis_concentrations(ps + [ps[0]], [1.0] * 7)  # duplicate

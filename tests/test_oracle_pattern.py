@@ -139,3 +139,34 @@ def test_mode_overrides():
     assert all(s["decision"] == 0 for s in compile_pattern(p.k, p.edges, mode="uniform")["steps"])
     assert all(s["decision"] == 1 for s in compile_pattern(p.k, p.edges, mode="always")["steps"])
     assert all(s["decision"] == 0 for s in compile_pattern(p.k, p.edges, beta=float("inf"))["steps"])
+
+
+# ------------------------------------------------------------ concentrations
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_induced_counts_by_inversion_match_direct_listing(k):
+    """Edge-induced copies (brute force) inverted through s(H, G) give the
+    vertex-induced counts found by listing every k-vertex set."""
+    from oracle import concentration as conc
+    pats = [(p.k, list(p.edges)) for p in synth.patterns.connected_patterns(k)]
+    for seed in range(3):
+        g = synth.graphs.tiny_graph(8, 0.45, 30 + seed)
+        copies = [judges.brute_force(g, kk, e) // automorphisms(kk, e) for kk, e in pats]
+        inv = conc.induced_from_copies(pats, copies)
+        direct = conc.induced_direct(g, pats)
+        assert [int(x) for x in inv] == direct and all(x.denominator == 1 for x in inv)
+
+
+def test_concentrations_on_complete_graph():
+    from oracle import concentration as conc
+    pats = [(p.k, list(p.edges)) for p in synth.patterns.connected_patterns(4)]
+    g = synth.complete_graph(6)
+    copies = [judges.brute_force(g, kk, e) // automorphisms(kk, e) for kk, e in pats]
+    ind = conc.induced_from_copies(pats, copies)
+    # every 4-set of K6 induces K4: C(6, 4) = 15 of them, nothing else
+    assert ind[-1] == 15 and all(x == 0 for x in ind[:-1])
+    assert conc.normalise(ind)[-1] == 1
+    # spanning copies of the 4-path in K4: 4!/2 = 12
+    path4 = next(i for i, (kk, e) in enumerate(pats) if len(e) == 3 and max(
+        sum(1 for ed in e if v in ed) for v in range(4)) == 2)
+    assert conc.spanning_copies(pats[path4], pats[-1]) == 12
