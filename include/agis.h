@@ -279,6 +279,18 @@ int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint
                   const agis_pattern* patterns, uint64_t pilot_samples, const agis_run_params* params,
                   agis_tuning* out);
 
+/* The first-step proposal of an estimate (Algorithm 3, first step; Sec.
+ * 5.3 for the uniform case) as integer weights: vertex v is drawn with
+ * probability q1[v] / *total.  A weighted first step gives the Q16-encoded
+ * f_approx (or learned, or term-ablated) weights the sampler draws from;
+ * a uniform one (edge-uniform) gives q1[v] = d(v), *total = nnz.  With the
+ * exact rooted counts n_(v) of small graphs this yields the divergence of
+ * each proposal from the ideal f_ideal(v | ()) = n_(v) / C(G, P), the
+ * paper's analysis of the approximate distribution.  q1: device
+ * uint32[n]; total: host. */
+int agis_step1_weights(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                       const uint8_t* order, const agis_run_params* params, uint32_t* q1, uint64_t* total);
+
 /* Concentrations of the connected k-vertex patterns (2 <= k <= 6), the
  * quantity the paper compares with MCMC estimators (Sec. 7, comparison
  * with MCMC): each pattern's count divided by the total over all

@@ -115,6 +115,8 @@ def lib():
         L.orc_count_embeddings.argtypes = [P, P, u64, u64, P, P, u32]
         L.orc_count_embeddings.restype = u64
         L.orc_count_cliques.argtypes = [P, P, u64, u64, u32]
+        L.orc_rooted_counts.argtypes = [P, P, u64, u64, P, P, u32, P]
+        L.orc_rooted_counts.restype = u64
         L.orc_count_cliques.restype = u64
         _lib = L
     return _lib

@@ -667,6 +667,23 @@ uint64_t orc_count_embeddings(const uint64_t* off, const uint32_t* nbr, uint64_t
     return bt_count(&G, adjmask, order, k, 0, m);
 }
 
+/* n_(v) for every v: the embeddings whose first matched pattern vertex
+ * (order[0]) maps to v -- the normaliser of the ideal first-step
+ * distribution f_ideal(v | ()) (Sec. 3 and the analysis of the approximate
+ * distribution).  out[v] for v < n; returns their sum. */
+uint64_t orc_rooted_counts(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint64_t nnz,
+                           const uint8_t* adjmask, const uint8_t* order, uint32_t k, uint64_t* out) {
+    orc_graph G = {n, nnz, off, nbr};
+    uint32_t m[ORC_MAXK];
+    uint64_t total = 0;
+    for (uint64_t v = 0; v < n; ++v) {
+        m[0] = (uint32_t)v;
+        out[v] = (k <= 1) ? (k == 1) : bt_count(&G, adjmask, order, k, 1, m);
+        total += out[v];
+    }
+    return total;
+}
+
 /* Number of k-cliques (copies) by ordered listing over the degree-oriented
  * graph: an edge points from the endpoint with smaller (degree, id) to the
  * larger one; each clique is counted once at its smallest vertex. */

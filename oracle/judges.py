@@ -47,6 +47,21 @@ def backtrack(g, k, edges, order=None) -> int:
     return int(lib().orc_count_embeddings(_p(off), _p(nbr), g.n, g.nnz, _p(adjm), _p(ordm), k))
 
 
+def rooted_counts(g, k, edges, order) -> np.ndarray:
+    """n_(v): embeddings with pattern vertex order[0] mapped to v, per v."""
+    adjm = np.zeros(8, dtype=np.uint8)
+    for a, b in edges:
+        adjm[a] |= 1 << b
+        adjm[b] |= 1 << a
+    ordm = np.zeros(8, dtype=np.uint8)
+    ordm[:k] = order
+    off = np.ascontiguousarray(g.off, dtype=np.uint64)
+    nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
+    out = np.zeros(max(g.n, 1), dtype=np.uint64)
+    lib().orc_rooted_counts(_p(off), _p(nbr), g.n, g.nnz, _p(adjm), _p(ordm), k, _p(out))
+    return out[: g.n]
+
+
 def clique_embeddings(g, k) -> int:
     off = np.ascontiguousarray(g.off, dtype=np.uint64)
     nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)

@@ -142,6 +142,8 @@ _SIGNATURES = [
                                       ctypes.c_float, ctypes.c_uint64, _P]),
     ("agis_mlp_infer", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, _P]),
     ("agis_concentrations", ctypes.c_int, [ctypes.c_uint32, _P, _P, _P, _P, _P]),
+    ("agis_step1_weights", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P,
+                                          ctypes.POINTER(agis_run_params), _P, ctypes.POINTER(ctypes.c_uint64)]),
     ("agis_fixed_point_tables", ctypes.c_int, [_P, _P]),
     ("agis_philox4x32_10", ctypes.c_int, [_P, _P, _P]),
 ]
@@ -345,6 +347,14 @@ def agis_mlp_train(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, wei
 def agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr=0, base_ptr=0):
     _check(ctx, lib().agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, base_ptr or None, lt_ptr,
                                      y_ptr or None))
+
+
+def agis_step1_weights(ctx, g, t, pattern: agis_pattern, params: agis_run_params, q1_ptr, order=None) -> int:
+    buf, optr = _order_arg(order)
+    total = ctypes.c_uint64()
+    _check(ctx, lib().agis_step1_weights(ctx, g, t, ctypes.byref(pattern), optr, ctypes.byref(params), q1_ptr,
+                                         ctypes.byref(total)))
+    return int(total.value)
 
 
 def agis_concentrations(patterns, copies):

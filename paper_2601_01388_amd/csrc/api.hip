@@ -559,6 +559,33 @@ int agis_compile_pattern(const agis_pattern* p, const uint8_t* order, const agis
     return agis::compile_plan(p, order, pp->mode, pp->beta_num, pp->beta_den, out, &err);
 }
 
+int agis_step1_weights(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                       const uint8_t* order, const agis_run_params* params, uint32_t* q1, uint64_t* total) {
+    int rc = check_handles(ctx, g, t);
+    if (rc != AGIS_OK) return ctx ? fail(ctx, rc, "bad handle") : rc;
+    if (!p || !q1 || !total) return fail(ctx, AGIS_E_INVALID_ARG, "null pattern, weights or total");
+    const agis_run_params dp = default_params();
+    const agis_run_params* pp = params ? params : &dp;
+    AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
+    StepTables st;
+    Prepared prep;
+    rc = prepare(ctx, g, t, p, order, pp, 0, &st, &prep);
+    if (rc != AGIS_OK) return rc;
+    const uint64_t n = g->g.n;
+    if (prep.hp.weighted[0]) {
+        if (n)
+            AGIS_HIP(ctx, hipMemcpyAsync(q1, prep.q1, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream),
+                     "copy first-step weights");
+        *total = prep.hp.s1_total;
+    } else {
+        // edge-uniform first step: P(v) = d(v) / nnz
+        AGIS_HIP(ctx, agis::launch_export_tables(*t, n, q1, nullptr, nullptr, ctx->stream), "degrees");
+        *total = g->g.nnz;
+    }
+    AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "first-step weights");
+    return AGIS_OK;
+}
+
 int agis_concentrations(uint32_t n_patterns, const agis_pattern* patterns, const double* copies, double* conc_edge,
                         double* induced, double* conc_induced) {
     std::string err;

@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, agis_build_proposal_tables,
-               agis_autotune, agis_compile_pattern, agis_concentrations, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
+               agis_autotune, agis_compile_pattern, agis_concentrations, agis_step1_weights, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
                agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
                agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
                agis_step_log_weights,
@@ -110,6 +110,14 @@ class Session:
     def autotune(self, graph: Graph, tables: Tables, patterns, pilot_samples: int, **kw):
         ps = [make_pattern(p.k, p.adj8()) for p in patterns]
         return agis_autotune(self.ctx, graph.handle, tables.handle, ps, pilot_samples, make_params(**kw))
+
+    def step1_weights(self, graph: Graph, tables: Tables, pattern, order=None, **kw):
+        """(q1 int64 host array, total): the first-step proposal q1[v] / total."""
+        torch = _torch()
+        q1 = torch.zeros(max(graph.n, 1), dtype=torch.int32, device=self.device)
+        total = agis_step1_weights(self.ctx, graph.handle, tables.handle, make_pattern(pattern.k, pattern.adj8()),
+                                   make_params(**kw), q1.data_ptr(), order=order)
+        return q1.cpu().numpy()[: graph.n].view(np.uint32).astype(np.int64), total
 
     def concentrations(self, graph: Graph, tables: Tables, k: int, budget: int, seed: int, **kw):
         """Estimates every connected k-vertex pattern (batched launches of at

@@ -148,6 +148,22 @@ def test_records_parity_term_ablation(sess, c1, c1_state, name, terms, rowtab):
     _compare_records(got, ref, f"{name}/{terms}")
 
 
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "house", "4-cycle", "5-cycle"])
+def test_step1_weights_parity(sess, c1, c1_state, name):
+    """The first-step proposal the library exports equals the oracle's."""
+    G, T, OT = c1_state
+    p = synth.named_pattern(name)
+    d = np.diff(c1.off).astype(np.int64)
+    for mode in MODES:
+        for terms in ("all", "f1", "f1_i1"):
+            q1, total = sess.step1_weights(G, T, p, mode=mode, terms=terms)
+            s = oracle.Sampler(c1, OT, compile_pattern(p.k, p.edges, mode=mode), seed=0, terms=terms)
+            if s.Q1:
+                assert total == s.Q1 and np.array_equal(q1, s.q1.astype(np.int64)), (mode, terms)
+            else:  # edge-uniform first step
+                assert total == c1.nnz and np.array_equal(q1, d), (mode, terms)
+
+
 def test_records_shape_invariance(sess, c1, c1_state):
     """The same sample index gives the same record whatever the launch."""
     G, T, OT = c1_state

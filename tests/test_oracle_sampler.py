@@ -416,3 +416,58 @@ def test_run_to_eps_stop_depends_only_on_prefix():
     # and the batch before it had not converged
     st3, _, _ = oracle.Sampler(g, t, c, seed=8).run(0, st.n - 256)
     assert st.n - 256 < 512 or eps_hat(st3.n, st3.mean, st3.m2, 0.05) > 0.05
+
+
+# ------------------------------------------------------------ ideal first step and KL divergence
+
+def _kl(ideal, q, total):
+    """KL(f_ideal || f) with f(v) = q[v] / total; f must cover the ideal's support."""
+    p = ideal.astype(np.float64) / ideal.sum()
+    f = q.astype(np.float64) / float(total)
+    m = p > 0
+    assert np.all(f[m] > 0)
+    return float(np.sum(p[m] * np.log(p[m] / f[m])))
+
+
+def test_rooted_counts_closed_forms():
+    g = synth.chung_lu(n=80, m=400, seed=6)
+    d = np.diff(g.off).astype(np.int64)
+    t = oracle.Tables(g, exact_cv=True)
+    tri = synth.named_pattern("triangle")
+    r = judges.rooted_counts(g, 3, tri.edges, [0, 1, 2])
+    assert np.array_equal(r, 2 * t.hits.astype(np.int64))  # ordered pairs of adjacent neighbours
+    star = synth.patterns.star(3)
+    r = judges.rooted_counts(g, 4, star.edges, [0, 1, 2, 3])  # centre first
+    assert np.array_equal(r, d * (d - 1) * (d - 2))
+    for name in ("4-clique", "house", "4-path"):
+        p = synth.named_pattern(name)
+        c = compile_pattern(p.k, p.edges)
+        r = judges.rooted_counts(g, p.k, p.edges, c["order"])
+        assert int(r.sum()) == judges.backtrack(g, p.k, p.edges)
+
+
+def test_first_step_kl_divergence_from_ideal():
+    """The paper's analysis of the approximate distribution, on a skewed
+    synthetic graph: the triangle's and the k-star's first steps are ideal
+    up to the Q16 encoding (and the triangle's clamp of C_v); every f_approx is closer to f_ideal than the
+    edge-uniform step; T[I1] is what makes the 4-clique close and T[F2] the
+    4-path."""
+    g = synth.chung_lu(n=300, m=1500, seed=4)
+    d = np.diff(g.off).astype(np.int64)
+    t = oracle.Tables(g, exact_cv=True)
+    kl = {}
+    for name in ("triangle", "3-star", "4-clique", "4-path", "diamond", "house"):
+        p = synth.named_pattern(name)
+        c = compile_pattern(p.k, p.edges, mode="always")
+        ideal = judges.rooted_counts(g, p.k, p.edges, c["order"])
+        kl[name] = {"uniform": _kl(ideal, d, int(d.sum()))}
+        for terms in oracle.TERMS:
+            s = oracle.Sampler(g, t, c, seed=0, terms=terms)
+            kl[name][terms] = _kl(ideal, s.q1, s.Q1)
+    print(kl)
+    # triangle: the c_min clamp gives triangle-free vertices a small weight
+    assert kl["triangle"]["all"] < 1e-4 and kl["3-star"]["all"] < 1e-6
+    for name in kl:
+        assert kl[name]["all"] < kl[name]["uniform"], name
+    assert kl["4-clique"]["f1_i1"] < 0.5 * kl["4-clique"]["f1"]
+    assert kl["4-path"]["all"] < 0.5 * kl["4-path"]["f1_i1"]
