@@ -198,6 +198,29 @@ int agis_load_csr(agis_ctx* ctx, const uint64_t* off, const uint32_t* nbr, uint6
                   uint32_t flags, agis_graph** out);
 void agis_graph_destroy(agis_graph* g);
 
+/* Degree orientation for clique patterns (Sec. 6.1, orientation
+ * optimisation): a new graph, owned by the library, whose rows hold only
+ * the neighbours w of v with (d(w), w) > (d(v), v) -- edges from the
+ * higher-degree end are dropped, ties broken by id -- in ascending id order.
+ * It must be destroyed before g.  On an oriented graph:
+ *  - agis_build_proposal_tables counts out-degrees, and C_v over pairs of
+ *    out-neighbours, deciding adjacency in g;
+ *  - agis_estimate / _batch / dump / learn accept clique patterns only
+ *    (AGIS_E_UNSUPPORTED otherwise).  Each k-clique is reached by exactly
+ *    one trajectory (its vertices in increasing order); the f_approx weight
+ *    of a candidate counts the remaining clique vertices among its
+ *    out-neighbours (|B| enters as 0), and agis_result.estimate = k! x the
+ *    sample mean (embeddings), copies = the mean (cliques), variance scaled
+ *    alike. */
+int agis_orient(agis_ctx* ctx, const agis_graph* g, agis_graph** out);
+
+/* The CSR of a graph: n, nnz and device pointers to its offsets and
+ * neighbours (the caller's for agis_load_csr, the library's for
+ * agis_orient; valid until the graph is destroyed).  Any output may be
+ * NULL. */
+int agis_graph_export(agis_ctx* ctx, const agis_graph* g, uint64_t* n, uint64_t* nnz, const uint64_t** off,
+                      const uint32_t** nbr);
+
 /* Builds the per-vertex proposal tables (Sec. 4.4): degree d(v), the
  * neighbour-degree sum S2(v) = sum_{x in N(v)} d(x), and the clustering
  * coefficient C_v estimated from d(v) trials (exact_cv = 0; each trial

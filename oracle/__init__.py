@@ -52,6 +52,7 @@ class Plan(ctypes.Structure):
         ("ie", ctypes.c_uint8 * MAXK),
         ("f2", ctypes.c_uint8 * MAXK),
         ("decision", ctypes.c_uint8 * MAXK),
+        ("oriented", ctypes.c_uint8),
     ]
 
 
@@ -99,6 +100,9 @@ def lib():
         L.orc_weight_from_log.restype = u32
         L.orc_fixed_point_tables.argtypes = [P, P]
         L.orc_build_tables.argtypes = [P, P, u64, u32, u32, i32, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_build_tables_oriented.argtypes = [P, P, u64, P, P, u32, u32, i32, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_orient.argtypes = [P, P, u64, P, P]
+        L.orc_orient.restype = u64
         L.orc_log_weights.argtypes = [P, P, ctypes.c_int, u64, P]
         L.orc_tables_at.argtypes = [P, P, P, u64, u32, u32, i32, ctypes.c_int, P, P, P, P, P, P]
         L.orc_step1_table.argtypes = [P, P, P, P, P, P]
@@ -161,7 +165,10 @@ def fixed_point_tables():
 class Tables:
     """Per-vertex proposal tables of Sec. 4.4 (host arrays)."""
 
-    def __init__(self, g, cv_seed: int = 0, lc_min: int = LC_MIN_DEFAULT, exact_cv: bool = False):
+    def __init__(self, g, cv_seed: int = 0, lc_min: int = LC_MIN_DEFAULT, exact_cv: bool = False,
+                 adjacency=None):
+        """adjacency: for an oriented g, the undirected graph that decides
+        whether two out-neighbours are adjacent (C_v over out-neighbours)."""
         n = g.n
         self.n = n
         self.deg = np.zeros(n, dtype=np.uint32)
@@ -175,9 +182,16 @@ class Tables:
         self.exact_cv = exact_cv
         off = np.ascontiguousarray(g.off, dtype=np.uint64)
         nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
-        lib().orc_build_tables(_p(off), _p(nbr), n, cv_seed & 0xFFFFFFFF, cv_seed >> 32, lc_min,
-                               1 if exact_cv else 0, _p(self.deg), _p(self.s2), _p(self.hits),
-                               _p(self.trials), _p(self.la), _p(self.lc))
+        if adjacency is None:
+            lib().orc_build_tables(_p(off), _p(nbr), n, cv_seed & 0xFFFFFFFF, cv_seed >> 32, lc_min,
+                                   1 if exact_cv else 0, _p(self.deg), _p(self.s2), _p(self.hits),
+                                   _p(self.trials), _p(self.la), _p(self.lc))
+        else:
+            aoff = np.ascontiguousarray(adjacency.off, dtype=np.uint64)
+            anbr = np.ascontiguousarray(adjacency.nbr, dtype=np.uint32)
+            lib().orc_build_tables_oriented(_p(off), _p(nbr), n, _p(aoff), _p(anbr), cv_seed & 0xFFFFFFFF,
+                                            cv_seed >> 32, lc_min, 1 if exact_cv else 0, _p(self.deg), _p(self.s2),
+                                            _p(self.hits), _p(self.trials), _p(self.la), _p(self.lc))
 
     def cv(self) -> np.ndarray:
         """Clustering coefficient hits / trials (0 where undefined)."""
@@ -203,7 +217,19 @@ def tables_at(g, vertices, cv_seed: int = 0, lc_min: int = LC_MIN_DEFAULT, exact
     return out
 
 
-def make_plan(compiled: dict, pattern_id: int = 0, terms: str = "all") -> Plan:
+def orient(g):
+    """The degree orientation of a symmetric CSR: v -> w kept iff
+    (d(v), v) < (d(w), w).  Returns a CSR of out-neighbour lists."""
+    from synth.graphs import CSR
+    off = np.ascontiguousarray(g.off, dtype=np.uint64)
+    nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
+    oo = np.zeros(g.n + 1, dtype=np.uint64)
+    on = np.zeros(max(g.nnz // 2, 1), dtype=np.uint32)
+    m = int(lib().orc_orient(_p(off), _p(nbr), g.n, _p(oo), _p(on)))
+    return CSR(off=oo, nbr=on[:m].copy(), name=(g.name or "") + "_oriented")
+
+
+def make_plan(compiled: dict, pattern_id: int = 0, terms: str = "all", oriented: bool = False) -> Plan:
     """terms: the factors of f_approx kept in the weights -- all three, or
     the incremental versions of the paper's analysis of the approximation
     (T[F1] only; T[F1] T[I1]).  Dropping T[I1] or T[F2] sets its exponent
@@ -218,6 +244,7 @@ def make_plan(compiled: dict, pattern_id: int = 0, terms: str = "all") -> Plan:
         P.ie[i] = 0 if terms == "f1" else s["ie"]
         P.f2[i] = s["f2"] if terms == "all" else 0
         P.decision[i] = s["decision"]
+    P.oriented = 1 if oriented else 0
     return P
 
 
@@ -225,13 +252,16 @@ class Sampler:
     """Algorithm 3 over one graph/pattern; all state on the host."""
 
     def __init__(self, g, tables: Tables, compiled: dict, seed: int, pattern_id: int = 0, learned=None,
-                 terms: str = "all"):
+                 terms: str = "all", oriented: bool = False):
+        """oriented: g is the degree orientation of a graph (orient) and the
+        pattern a clique; each clique is one trajectory, so the mean of X
+        counts cliques (k! embeddings each)."""
         self.g = g
         self.off = np.ascontiguousarray(g.off, dtype=np.uint64)
         self.nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
         self.t = tables
         self.compiled = compiled
-        self.plan = make_plan(compiled, pattern_id, terms)
+        self.plan = make_plan(compiled, pattern_id, terms, oriented)
         self.seed = seed
         self._learned = learned
         k = compiled["k"]

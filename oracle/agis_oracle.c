@@ -163,9 +163,9 @@ static int contains(const uint32_t* list, uint64_t len, uint32_t x) {
  * degrees, the C_v trials (hits out of trials) and the Q16 logs LA and LC.
  * exact_cv = 1: hits = number of edges among N(v), trials = C(d, 2).
  * exact_cv = 0: d(v) sampled ordered pairs of distinct neighbours. */
-static void tables_of_vertex(const uint64_t* off, const uint32_t* nbr, uint64_t v, const uint32_t key[2],
-                             int32_t lc_min, int exact_cv, uint32_t* deg_v, uint64_t* s2_v, uint64_t* hits_v,
-                             uint64_t* trials_v, int32_t* la_v, int32_t* lc_v) {
+static void tables_of_vertex(const uint64_t* off, const uint32_t* nbr, const uint64_t* aoff, const uint32_t* anbr,
+                             uint64_t v, const uint32_t key[2], int32_t lc_min, int exact_cv, uint32_t* deg_v,
+                             uint64_t* s2_v, uint64_t* hits_v, uint64_t* trials_v, int32_t* la_v, int32_t* lc_v) {
     uint64_t d = off[v + 1] - off[v];
     const uint32_t* row = nbr + off[v];
     uint64_t s = 0;
@@ -174,8 +174,8 @@ static void tables_of_vertex(const uint64_t* off, const uint32_t* nbr, uint64_t 
     if (d >= 2) {
         if (exact_cv) {
             for (uint64_t a = 0; a < d; ++a) {
-                const uint32_t* ra = nbr + off[row[a]];
-                uint64_t da = off[row[a] + 1] - off[row[a]];
+                const uint32_t* ra = anbr + aoff[row[a]];
+                uint64_t da = aoff[row[a] + 1] - aoff[row[a]];
                 for (uint64_t b = a + 1; b < d; ++b)
                     if (contains(ra, da, row[b])) ++h;
             }
@@ -186,7 +186,7 @@ static void tables_of_vertex(const uint64_t* off, const uint32_t* nbr, uint64_t 
                 uint64_t b = orc_bounded(key, (uint32_t)v, (uint32_t)trial, 0, 1, d - 1);
                 if (b >= a) ++b;
                 uint32_t x = row[a], y = row[b];
-                if (contains(nbr + off[x], off[x + 1] - off[x], y)) ++h;
+                if (contains(anbr + aoff[x], aoff[x + 1] - aoff[x], y)) ++h;
             }
             t = d;
         }
@@ -195,7 +195,9 @@ static void tables_of_vertex(const uint64_t* off, const uint32_t* nbr, uint64_t 
     *s2_v = s;
     *hits_v = h;
     *trials_v = t;
-    *la_v = d >= 1 ? orc_log2fx(s) - orc_log2fx(d) : 0;
+    /* log2(S2 / d) is undefined at S2 = 0, which only an oriented graph has
+     * (out-neighbours without out-neighbours): 0 there, as for d = 0 */
+    *la_v = (d >= 1 && s > 0) ? orc_log2fx(s) - orc_log2fx(d) : 0;
     if (d < 2 || h == 0) {
         *lc_v = lc_min;
     } else {
@@ -211,7 +213,40 @@ void orc_build_tables(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint
     init_fixed_point();
     uint32_t key[2] = {cv_seed_lo, cv_seed_hi};
     for (uint64_t v = 0; v < n; ++v)
-        tables_of_vertex(off, nbr, v, key, lc_min, exact_cv, &deg[v], &s2[v], &hits[v], &trials[v], &la[v], &lc[v]);
+        tables_of_vertex(off, nbr, off, nbr, v, key, lc_min, exact_cv, &deg[v], &s2[v], &hits[v], &trials[v], &la[v],
+                         &lc[v]);
+}
+
+/* The same for an oriented graph (off, nbr: out-neighbours), with the
+ * adjacency of two out-neighbours decided in the undirected graph (aoff,
+ * anbr). */
+void orc_build_tables_oriented(const uint64_t* off, const uint32_t* nbr, uint64_t n, const uint64_t* aoff,
+                               const uint32_t* anbr, uint32_t cv_seed_lo, uint32_t cv_seed_hi, int32_t lc_min,
+                               int exact_cv, uint32_t* deg, uint64_t* s2, uint64_t* hits, uint64_t* trials, int32_t* la,
+                               int32_t* lc) {
+    init_fixed_point();
+    uint32_t key[2] = {cv_seed_lo, cv_seed_hi};
+    for (uint64_t v = 0; v < n; ++v)
+        tables_of_vertex(off, nbr, aoff, anbr, v, key, lc_min, exact_cv, &deg[v], &s2[v], &hits[v], &trials[v],
+                         &la[v], &lc[v]);
+}
+
+/* Degree orientation (the DAG of the clique optimisation): keep v -> w iff
+ * (d(v), v) < (d(w), w).  off_out: n + 1 entries; nbr_out: capacity nnz / 2;
+ * rows stay in ascending id order.  Returns the number of kept edges. */
+uint64_t orc_orient(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint64_t* off_out, uint32_t* nbr_out) {
+    uint64_t p = 0;
+    off_out[0] = 0;
+    for (uint64_t v = 0; v < n; ++v) {
+        uint64_t dv = off[v + 1] - off[v];
+        for (uint64_t e = off[v]; e < off[v + 1]; ++e) {
+            uint32_t w = nbr[e];
+            uint64_t dw = off[w + 1] - off[w];
+            if (dv < dw || (dv == dw && v < w)) nbr_out[p++] = w;
+        }
+        off_out[v + 1] = p;
+    }
+    return p;
 }
 
 /* The same entries for the listed vertices only (entry j for vs[j]), for
@@ -222,8 +257,8 @@ void orc_tables_at(const uint64_t* off, const uint32_t* nbr, const uint64_t* vs,
     init_fixed_point();
     uint32_t key[2] = {cv_seed_lo, cv_seed_hi};
     for (uint64_t j = 0; j < count; ++j)
-        tables_of_vertex(off, nbr, vs[j], key, lc_min, exact_cv, &deg[j], &s2[j], &hits[j], &trials[j], &la[j],
-                         &lc[j]);
+        tables_of_vertex(off, nbr, off, nbr, vs[j], key, lc_min, exact_cv, &deg[j], &s2[j], &hits[j], &trials[j],
+                         &la[j], &lc[j]);
 }
 
 /* ------------------------------------------------------------------ */
@@ -238,6 +273,7 @@ typedef struct {
     uint8_t ie[ORC_MAXK];       /* |I_effective| */
     uint8_t f2[ORC_MAXK];       /* |F2| */
     uint8_t decision[ORC_MAXK]; /* D(i): 1 = f_approx / learned, 0 = f_uniform */
+    uint8_t oriented;           /* 1: sampling a clique on the degree-oriented graph */
 } orc_plan;
 
 /* A step draws from weights when it is an f_approx step with forward
@@ -249,7 +285,9 @@ static int step_weighted(const orc_plan* P, int i) { return P->decision[i] && P-
  * cannot extend to an embedding because d(v) - |B| < |F1|.
  * lt: learned log-weight table for this step (NULL = f_approx). */
 static int32_t log_weight(const orc_tables* T, const orc_plan* P, int i, uint32_t v, const int32_t* lt) {
-    uint32_t b = (uint32_t)__builtin_popcount(P->bmask[i]);
+    /* on the oriented graph no backward vertex is an out-neighbour of v:
+     * all d(v) out-neighbours are open to the later clique vertices */
+    uint32_t b = P->oriented ? 0u : (uint32_t)__builtin_popcount(P->bmask[i]);
     uint32_t d = T->deg[v];
     uint32_t f1 = P->f1[i];
     if (d < b + f1) return ORC_CERTAIN_ZERO;
@@ -579,7 +617,7 @@ uint64_t orc_step_distribution_literal(const uint64_t* off, const uint32_t* nbr,
                                        double* out_w) {
     orc_graph G; orc_tables T; orc_sampler S;
     if (make_sampler(&S, &G, &T, P, off, nbr, n, nnz, deg, s2, NULL, NULL, NULL, NULL, NULL, 0, 0)) return 0;
-    uint32_t b = (uint32_t)__builtin_popcount(P->bmask[i]);
+    uint32_t b = P->oriented ? 0u : (uint32_t)__builtin_popcount(P->bmask[i]);
     uint64_t m = 0;
     if (i == 0) {
         for (uint64_t v = 0; v < n; ++v) {

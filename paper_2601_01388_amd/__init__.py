@@ -114,6 +114,9 @@ _SIGNATURES = [
     ("agis_load_csr", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.POINTER(ctypes.c_void_p)]),
     ("agis_graph_destroy", None, [_P]),
+    ("agis_orient", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_void_p)]),
+    ("agis_graph_export", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     ("agis_build_proposal_tables", ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                                   ctypes.POINTER(ctypes.c_void_p)]),
     ("agis_tables_destroy", None, [_P]),
@@ -355,6 +358,23 @@ def agis_step1_weights(ctx, g, t, pattern: agis_pattern, params: agis_run_params
     _check(ctx, lib().agis_step1_weights(ctx, g, t, ctypes.byref(pattern), optr, ctypes.byref(params), q1_ptr,
                                          ctypes.byref(total)))
     return int(total.value)
+
+
+def agis_orient(ctx, g):
+    h = ctypes.c_void_p()
+    _check(ctx, lib().agis_orient(ctx, g, ctypes.byref(h)))
+    return h.value
+
+
+def agis_graph_export(ctx, g):
+    """(n, nnz, off_ptr, nbr_ptr) of a graph (device pointers)."""
+    n = ctypes.c_uint64()
+    nnz = ctypes.c_uint64()
+    off = ctypes.c_void_p()
+    nbr = ctypes.c_void_p()
+    _check(ctx, lib().agis_graph_export(ctx, g, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(off),
+                                        ctypes.byref(nbr)))
+    return int(n.value), int(nnz.value), off.value, nbr.value
 
 
 def agis_concentrations(patterns, copies):

@@ -48,6 +48,11 @@ struct agis_graph {
     agis_ctx* ctx = nullptr;
     agis::DevGraph g{};
     uint32_t max_deg = 0;
+    // a degree-oriented graph (agis_orient) owns its CSR and keeps the
+    // undirected graph it came from (adjacency tests of its tables)
+    const agis_graph* parent = nullptr;
+    uint64_t* own_off = nullptr;
+    uint32_t* own_nbr = nullptr;
 };
 
 struct agis_tables {
@@ -81,8 +86,15 @@ hipError_t upload_fixed_point_tables(hipStream_t stream);
 hipError_t launch_validate_rows(const DevGraph& g, uint32_t* d_flags, hipStream_t stream);
 hipError_t launch_validate_edges(const DevGraph& g, uint32_t* d_flags, hipStream_t stream);
 hipError_t launch_max_degree(const DevGraph& g, uint32_t* d_max, hipStream_t stream);
-hipError_t launch_build_tables(const DevGraph& g, uint4* rec, uint64_t* s2, uint64_t* hits, uint64_t* trials,
-                               uint32_t k0, uint32_t k1, int32_t lc_min, int exact, hipStream_t stream);
+// adj: the graph whose lists decide whether two neighbours are adjacent (g
+// itself, or the undirected graph of an oriented g)
+hipError_t launch_build_tables(const DevGraph& g, const DevGraph& adj, uint4* rec, uint64_t* s2, uint64_t* hits,
+                               uint64_t* trials, uint32_t k0, uint32_t k1, int32_t lc_min, int exact,
+                               hipStream_t stream);
+// Degree orientation: out-degrees into outdeg (n entries of scratch), the
+// offsets into off_out (n + 1), then the neighbours into nbr_out.
+hipError_t launch_orient_offsets(agis_ctx* ctx, const DevGraph& g, uint32_t* outdeg, uint64_t* off_out);
+hipError_t launch_orient_fill(const DevGraph& g, const uint64_t* off_out, uint32_t* nbr_out, hipStream_t stream);
 // out[v] = certain-zero marker if d(v) < b + f1, else lt[v] (lt given) or the
 // f_approx log weight of signature (b, f1, ie, f2).
 hipError_t launch_step_log_weights(const agis_tables& t, uint64_t n, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2,

@@ -91,6 +91,7 @@ agis_run_params default_params() {
 struct Prepared {
     agis_plan plan;
     DevPlan hp;
+    double scale = 1.0;  // embeddings per unit of the sample mean (k! on an oriented graph)
     uint32_t* q1 = nullptr;
     uint64_t* pre = nullptr;
     std::vector<uint64_t*> rowtabs;
@@ -134,6 +135,19 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
             const agis_run_params* params, uint64_t n_samples, StepTables* st, Prepared* out) {
     int rc = agis::compile_plan(p, order, params->mode, params->beta_num, params->beta_den, &out->plan, &ctx->err);
     if (rc != AGIS_OK) return rc;
+    // On a degree-oriented graph (agis_orient) a k-clique is found exactly
+    // once, as the increasing sequence of its vertices: only cliques are
+    // sampled there, the weights count the later vertices among the out-
+    // neighbours (no backward vertex is an out-neighbour: |B| enters as 0),
+    // and the mean counts cliques, k! embeddings each.
+    const bool oriented = g->parent != nullptr;
+    out->scale = 1.0;
+    if (oriented) {
+        for (uint32_t u = 0; u < p->k; ++u)
+            if (p->adj[u] != (uint8_t)(((1u << p->k) - 1u) & ~(1u << u)))
+                return fail(ctx, AGIS_E_UNSUPPORTED, "an oriented graph samples clique patterns only");
+        for (uint32_t j = 2; j <= p->k; ++j) out->scale *= (double)j;
+    }
     if (params->flags > AGIS_RUN_ROWTAB_OFF) return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
     if (params->terms > AGIS_TERMS_F1_I1) return fail(ctx, AGIS_E_INVALID_ARG, "unknown term set");
     DevPlan& hp = out->hp;
@@ -142,7 +156,7 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     hp.pattern_id = params->pattern_id;
     for (uint32_t i = 0; i < hp.k; ++i) {
         hp.bmask[i] = out->plan.bmask[i];
-        hp.b[i] = out->plan.b[i];
+        hp.b[i] = oriented ? 0 : out->plan.b[i];
         hp.f1[i] = out->plan.f1[i];
         // the term ablation drops T[I1] (exponent ie) and T[F2] (exponent f2)
         hp.ie[i] = params->terms == AGIS_TERMS_F1 ? 0 : out->plan.ie[i];
@@ -161,7 +175,7 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     int32_t* rowmax = nullptr;
     if (want_rows && g->g.nnz > 0) {
         struct Key {
-            uint32_t f1, ie, f2;
+            uint32_t b, f1, ie, f2;
             const int32_t* lt;
             uint64_t* buf;
         };
@@ -170,7 +184,9 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
             if (!hp.weighted[i] || __builtin_popcount(hp.bmask[i]) != 1) continue;
             uint64_t* buf = nullptr;
             for (const Key& k : built)
-                if (k.f1 == hp.f1[i] && k.ie == hp.ie[i] && k.f2 == hp.f2[i] && k.lt == hp.lt[i]) buf = k.buf;
+                if (k.b == hp.b[i] && k.f1 == hp.f1[i] && k.ie == hp.ie[i] && k.f2 == hp.f2[i] &&
+                    k.lt == (const int32_t*)hp.lt[i])
+                    buf = k.buf;
             if (!buf) {
                 if ((built.size() + 1) * g->g.nnz * sizeof(uint64_t) > kRowtabBudgetBytes) continue;
                 AGIS_HIP(ctx, hipMalloc(&buf, g->g.nnz * sizeof(uint64_t)), "allocate row pick table");
@@ -180,9 +196,10 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
                     out->rowmax = rowmax;
                 }
                 AGIS_HIP(ctx,
-                         agis::launch_rowtab(ctx, g->g, t->rec, 1, hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf, rowmax),
+                         agis::launch_rowtab(ctx, g->g, t->rec, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
+                                             rowmax),
                          "row pick table");
-                built.push_back(Key{hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
+                built.push_back(Key{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], (const int32_t*)hp.lt[i], buf});
             }
             hp.rowpre[i] = agis::gmem((const uint64_t*)buf);
         }
@@ -376,9 +393,10 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
 void fill_result(const PatternRun& r, double z, double extra_seconds, agis_result* out) {
     std::memset(out, 0, sizeof(*out));
     const Acc& acc = r.acc;
-    out->estimate = acc.mean;
-    out->copies = r.prep.plan.aut ? acc.mean / (double)r.prep.plan.aut : 0.0;
-    out->variance = acc.n > 0 ? acc.m2 / acc.n : 0.0;
+    const double sc = r.prep.scale;
+    out->estimate = acc.mean * sc;
+    out->copies = r.prep.plan.aut ? acc.mean * sc / (double)r.prep.plan.aut : 0.0;
+    out->variance = acc.n > 0 ? acc.m2 / acc.n * sc * sc : 0.0;
     out->eps_hat = eps_hat_of(acc, z);
     out->n = (uint64_t)acc.n;
     out->n_nonzero = (uint64_t)acc.nonzero;
@@ -500,7 +518,58 @@ int agis_load_csr(agis_ctx* ctx, const uint64_t* off, const uint32_t* nbr, uint6
     return AGIS_OK;
 }
 
-void agis_graph_destroy(agis_graph* g) { delete g; }
+void agis_graph_destroy(agis_graph* g) {
+    if (!g) return;
+    if (g->own_off) (void)hipFree(g->own_off);
+    if (g->own_nbr) (void)hipFree(g->own_nbr);
+    delete g;
+}
+
+int agis_orient(agis_ctx* ctx, const agis_graph* g, agis_graph** out) {
+    if (!ctx || !g || !out || g->ctx != ctx) return AGIS_E_INVALID_ARG;
+    *out = nullptr;
+    if (g->parent) return fail(ctx, AGIS_E_INVALID_ARG, "the graph is already oriented");
+    AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
+    const uint64_t n = g->g.n;
+    agis_graph* o = new (std::nothrow) agis_graph();
+    if (!o) return fail(ctx, AGIS_E_OOM, "host allocation");
+    o->ctx = ctx;
+    o->parent = g;
+    uint32_t* outdeg = nullptr;
+    hipError_t e = hipMalloc(&outdeg, n * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&o->own_off, (n + 1) * sizeof(uint64_t));
+    if (e == hipSuccess) e = agis::launch_orient_offsets(ctx, g->g, outdeg, o->own_off);
+    uint64_t nnz = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&nnz, o->own_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMalloc(&o->own_nbr, (nnz ? nnz : 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = agis::launch_orient_fill(g->g, o->own_off, o->own_nbr, ctx->stream);
+    uint32_t* d_max = (uint32_t*)ctx->d_small;
+    uint32_t maxd = 0;
+    o->g = agis::DevGraph{agis::gmem((const uint64_t*)o->own_off), agis::gmem((const uint32_t*)o->own_nbr), n, nnz};
+    if (e == hipSuccess) e = hipMemsetAsync(d_max, 0, sizeof(uint32_t), ctx->stream);
+    if (e == hipSuccess) e = agis::launch_max_degree(o->g, d_max, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&maxd, d_max, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (outdeg) (void)hipFree(outdeg);
+    if (e != hipSuccess) {
+        agis_graph_destroy(o);
+        return hip_fail(ctx, e, "orient graph");
+    }
+    o->max_deg = maxd;
+    *out = o;
+    return AGIS_OK;
+}
+
+int agis_graph_export(agis_ctx* ctx, const agis_graph* g, uint64_t* n, uint64_t* nnz, const uint64_t** off,
+                      const uint32_t** nbr) {
+    if (!ctx || !g || g->ctx != ctx) return AGIS_E_INVALID_ARG;
+    if (n) *n = g->g.n;
+    if (nnz) *nnz = g->g.nnz;
+    if (off) *off = (const uint64_t*)g->g.off;
+    if (nbr) *nbr = (const uint32_t*)g->g.nbr;
+    return AGIS_OK;
+}
 
 int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_seed, int32_t lc_min_q16,
                                int32_t exact_cv, agis_tables** out) {
@@ -518,8 +587,9 @@ int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_s
     if (e == hipSuccess) e = hipMalloc(&t->hits, n * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc(&t->trials, n * sizeof(uint64_t));
     if (e == hipSuccess)
-        e = agis::launch_build_tables(g->g, t->rec, t->s2, t->hits, t->trials, (uint32_t)cv_seed,
-                                      (uint32_t)(cv_seed >> 32), lc_min_q16, exact_cv ? 1 : 0, ctx->stream);
+        e = agis::launch_build_tables(g->g, g->parent ? g->parent->g : g->g, t->rec, t->s2, t->hits, t->trials,
+                                      (uint32_t)cv_seed, (uint32_t)(cv_seed >> 32), lc_min_q16, exact_cv ? 1 : 0,
+                                      ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         agis_tables_destroy(t);

@@ -424,8 +424,8 @@ __global__ void k_tables_init(DevGraph g, uint4* rec, uint64_t* s2, uint64_t* hi
 // cv_seed, counter (v, t, 0, tag 0 / tag 1), a hit when the two neighbours
 // are adjacent.  For the exact coefficient, counts the neighbours z > x of v
 // that are adjacent to x (each edge among N(v) once).
-__global__ __launch_bounds__(256) void k_tables_edges(DevGraph g, const uint4* rec, uint64_t* s2, uint64_t* hits,
-                                                       uint32_t k0, uint32_t k1, int exact) {
+__global__ __launch_bounds__(256) void k_tables_edges(DevGraph g, DevGraph adj, const uint4* rec, uint64_t* s2,
+                                                       uint64_t* hits, uint32_t k0, uint32_t k1, int exact) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = e < g.nnz;
     uint32_t v = 0xFFFFFFFFu;
@@ -443,13 +443,13 @@ __global__ __launch_bounds__(256) void k_tables_edges(DevGraph g, const uint4* r
             uint64_t b = bounded_draw(k0, k1, v, t, 0, 1, d - 1);
             if (b >= a) ++b;
             const uint32_t y = row[a], z = row[b];
-            const uint64_t oy = g.off[y];
-            h = contains_u32(g.nbr + oy, (uint32_t)(g.off[y + 1] - oy), z) ? 1u : 0u;
+            const uint64_t oy = adj.off[y];
+            h = contains_u32(adj.nbr + oy, (uint32_t)(adj.off[y + 1] - oy), z) ? 1u : 0u;
         } else if (d >= 2) {
-            const uint64_t ox = g.off[x];
-            const uint32_t dxx = (uint32_t)(g.off[x + 1] - ox);
+            const uint64_t ox = adj.off[x];
+            const uint32_t dxx = (uint32_t)(adj.off[x + 1] - ox);
             for (uint32_t p = lower_bound_u32(row, d, x + 1); p < d; ++p)
-                if (contains_u32(g.nbr + ox, dxx, row[p])) ++h;
+                if (contains_u32(adj.nbr + ox, dxx, row[p])) ++h;
         }
     }
     // consecutive slots mostly share a row: one atomic per row segment of the wave
@@ -472,7 +472,9 @@ __global__ void k_tables_finalize(DevGraph g, uint4* rec, const uint64_t* s2, co
     const uint64_t d = r.x;
     const uint64_t t = d < 2 ? 0 : (exact ? d * (d - 1) / 2 : d);
     trials[v] = t;
-    const int32_t la = d >= 1 ? log2fx(s2[v], c_logtab) - log2fx(d, c_logtab) : 0;
+    // S2 = 0 happens only on an oriented graph (out-neighbours without
+    // out-neighbours); LA is then 0, as for d = 0 (cliques never use it)
+    const int32_t la = (d >= 1 && s2[v] > 0) ? log2fx(s2[v], c_logtab) - log2fx(d, c_logtab) : 0;
     int32_t lc = lc_min;
     const uint64_t h = hits[v];
     if (d >= 2 && h > 0) {
@@ -484,13 +486,14 @@ __global__ void k_tables_finalize(DevGraph g, uint4* rec, const uint64_t* s2, co
     rec[v] = r;
 }
 
-hipError_t launch_build_tables(const DevGraph& g, uint4* rec, uint64_t* s2, uint64_t* hits, uint64_t* trials,
-                               uint32_t k0, uint32_t k1, int32_t lc_min, int exact, hipStream_t stream) {
+hipError_t launch_build_tables(const DevGraph& g, const DevGraph& adj, uint4* rec, uint64_t* s2, uint64_t* hits,
+                               uint64_t* trials, uint32_t k0, uint32_t k1, int32_t lc_min, int exact,
+                               hipStream_t stream) {
     if (!g.n) return hipSuccess;
     hipLaunchKernelGGL(k_tables_init, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, rec, s2, hits);
     if (g.nnz)
-        hipLaunchKernelGGL(k_tables_edges, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, rec, s2, hits, k0,
-                           k1, exact);
+        hipLaunchKernelGGL(k_tables_edges, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, adj, rec, s2, hits,
+                           k0, k1, exact);
     hipLaunchKernelGGL(k_tables_finalize, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, rec, s2, hits, trials,
                        lc_min, exact);
     return hipGetLastError();
@@ -640,6 +643,110 @@ __global__ __launch_bounds__(kScanThreads) void k_step1_final(const uint4* rec, 
             pre[v] = run;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Degree orientation (the DAG the paper uses for clique patterns): the edge
+// {v, w} is kept as v -> w iff (d(v), v) < (d(w), w), i.e. edges from the
+// higher-degree end are dropped.  Rows stay in ascending id order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t orient_key(const DevGraph& g, uint32_t v) {
+    return ((g.off[v + 1] - g.off[v]) << 32) | (uint64_t)v;
+}
+
+__global__ void k_orient_count(DevGraph g, uint32_t* outdeg) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const uint64_t kv = orient_key(g, (uint32_t)v);
+    uint32_t c = 0;
+    for (uint64_t e = g.off[v]; e < g.off[v + 1]; ++e) c += orient_key(g, g.nbr[e]) > kv ? 1u : 0u;
+    outdeg[v] = c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_u32_tilesum(const uint32_t* in, uint64_t n, uint64_t* tile_sums) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t v = base + (uint64_t)j * kScanThreads + threadIdx.x;
+        if (v < n) s += in[v];
+    }
+    s = wave_sum_u64(s);
+    __shared__ uint64_t ws[kScanThreads / kWave];
+    if (lane_id() == 0) ws[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) t += ws[w];
+        tile_sums[blockIdx.x] = t;
+    }
+}
+
+// out[v + 1] = in[0] + ... + in[v] (out[0] is set by the caller)
+__global__ __launch_bounds__(kScanThreads) void k_u32_final(const uint32_t* in, uint64_t n, const uint64_t* tile_offs,
+                                                             uint64_t* out) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t q[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t v = base + j;
+        q[j] = v < n ? in[v] : 0u;
+        s += q[j];
+    }
+    const uint64_t incl = wave_incl_scan_u64(s);
+    __shared__ uint64_t wsum[kScanThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (int j = 0; j < w; ++j) wbase += wsum[j];
+    uint64_t run = tile_offs[blockIdx.x] + wbase + incl - s;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t v = base + j;
+        if (v < n) {
+            run += q[j];
+            out[v + 1] = run;
+        }
+    }
+}
+
+__global__ void k_orient_fill(DevGraph g, const uint64_t* off_out, uint32_t* nbr_out) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const uint64_t kv = orient_key(g, (uint32_t)v);
+    uint64_t p = off_out[v];
+    for (uint64_t e = g.off[v]; e < g.off[v + 1]; ++e) {
+        const uint32_t w = g.nbr[e];
+        if (orient_key(g, w) > kv) nbr_out[p++] = w;
+    }
+}
+
+hipError_t launch_orient_offsets(agis_ctx* ctx, const DevGraph& g, uint32_t* outdeg, uint64_t* off_out) {
+    hipStream_t st = ctx->stream;
+    const uint64_t n = g.n;
+    const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ctx->blocksums_cap < ntiles) {
+        if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
+        ctx->d_blocksums = nullptr;
+        ctx->blocksums_cap = 0;
+        hipError_t e = hipMalloc(&ctx->d_blocksums, ntiles * sizeof(uint64_t));
+        if (e != hipSuccess) return e;
+        ctx->blocksums_cap = ntiles;
+    }
+    hipError_t e = hipMemsetAsync(off_out, 0, sizeof(uint64_t), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_orient_count, dim3(grid_for(n, 256)), dim3(256), 0, st, g, outdeg);
+    hipLaunchKernelGGL(k_u32_tilesum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, outdeg, n, ctx->d_blocksums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, ctx->d_blocksums, ntiles);
+    hipLaunchKernelGGL(k_u32_final, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, outdeg, n, ctx->d_blocksums,
+                       off_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_orient_fill(const DevGraph& g, const uint64_t* off_out, uint32_t* nbr_out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, off_out, nbr_out);
+    return hipGetLastError();
 }
 
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp, uint32_t* q1,

@@ -9,7 +9,8 @@ import ctypes
 import numpy as np
 
 from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, agis_build_proposal_tables,
-               agis_autotune, agis_compile_pattern, agis_concentrations, agis_step1_weights, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
+               agis_autotune, agis_compile_pattern, agis_concentrations, agis_step1_weights, agis_orient,
+               agis_graph_export, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
                agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
                agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
                agis_step_log_weights,
@@ -45,6 +46,39 @@ class Graph:
             self.d_nbr = torch.from_numpy(nb if nb.size else np.zeros(1, dtype=np.int32)).to(dev)
         self.handle = agis_load_csr(sess.ctx, self.d_off.data_ptr(), self.d_nbr.data_ptr(), self.n, self.nnz,
                                     AGIS_CSR_VALIDATE if validate else 0)
+
+    def close(self):
+        if self.handle:
+            agis_graph_destroy(self.handle)
+            self.handle = None
+
+
+class _DeviceArray:
+    """A library-owned device buffer seen by torch (no copy)."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 3}
+
+
+class OrientedGraph:
+    """The degree orientation of a Graph (agis_orient), owned by the library;
+    keeps its undirected graph alive."""
+
+    def __init__(self, sess, graph: Graph):
+        self.sess = sess
+        self.parent = graph
+        self.handle = agis_orient(sess.ctx, graph.handle)
+        self.n, self.nnz, self._off, self._nbr = agis_graph_export(sess.ctx, self.handle)
+
+    def csr(self):
+        """(off uint64, nbr uint32) host copies of the oriented CSR."""
+        torch = _torch()
+        off = torch.as_tensor(_DeviceArray(self._off, self.n + 1, "<i8"), device=self.sess.device)
+        o = off.cpu().numpy().view(np.uint64).copy()
+        if not self.nnz:
+            return o, np.zeros(0, dtype=np.uint32)
+        nbr = torch.as_tensor(_DeviceArray(self._nbr, self.nnz, "<i4"), device=self.sess.device)
+        return o, nbr.cpu().numpy().view(np.uint32).copy()
 
     def close(self):
         if self.handle:
@@ -94,6 +128,9 @@ class Session:
 
     def graph(self, off, nbr, validate=True) -> Graph:
         return Graph(self, off, nbr, validate)
+
+    def orient(self, graph: Graph) -> OrientedGraph:
+        return OrientedGraph(self, graph)
 
     def tables(self, graph: Graph, cv_seed=0, lc_min=LC_MIN_DEFAULT, exact_cv=False) -> Tables:
         return Tables(self, graph, cv_seed, lc_min, exact_cv)

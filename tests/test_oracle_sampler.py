@@ -1,6 +1,7 @@
 """Pins of the oracle's tables, sampler and estimator against the paper's
 theorems, worked examples and closed forms."""
 
+import itertools
 import math
 from fractions import Fraction
 
@@ -471,3 +472,53 @@ def test_first_step_kl_divergence_from_ideal():
         assert kl[name]["all"] < kl[name]["uniform"], name
     assert kl["4-clique"]["f1_i1"] < 0.5 * kl["4-clique"]["f1"]
     assert kl["4-path"]["all"] < 0.5 * kl["4-path"]["f1_i1"]
+
+
+# ------------------------------------------------------------ degree orientation for cliques
+
+def test_orientation_keeps_each_edge_once_in_degree_order():
+    g = synth.chung_lu(n=300, m=1500, seed=3)
+    o = oracle.orient(g)
+    d = np.diff(g.off).astype(np.int64)
+    assert o.n == g.n and o.nnz * 2 == g.nnz
+    key = lambda v: (int(d[v]), int(v))
+    seen = set()
+    for v in range(o.n):
+        row = o.nbr[int(o.off[v]):int(o.off[v + 1])]
+        assert np.all(np.diff(row.astype(np.int64)) > 0)
+        for w in row.tolist():
+            assert key(v) < key(w)  # acyclic: every edge goes up the (degree, id) order
+            seen.add((min(v, w), max(v, w)))
+    und = {(v, int(w)) for v in range(g.n) for w in g.nbr[int(g.off[v]):int(g.off[v + 1])] if v < int(w)}
+    assert seen == und
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_oriented_clique_sampler_is_unbiased_exactly(k):
+    """Theorem 2 on the DAG: each k-clique is one trajectory, so E[X] is the
+    clique count (exact rationals over the whole sampling tree)."""
+    p = synth.patterns.clique(k)
+    for gi in (0, 1, 3, 4):
+        g = SMALL_GRAPHS[gi]
+        cliques = judges.brute_force(g, k, p.edges) // math.factorial(k)
+        o = oracle.orient(g)
+        for mode in MODES:
+            c = compile_pattern(p.k, p.edges, mode=mode)
+            for exact_cv in (True, False):
+                t = oracle.Tables(o, cv_seed=4, exact_cv=exact_cv, adjacency=g)
+                r = enumerate_tree(oracle.Sampler(o, t, c, seed=1, oriented=True))
+                assert r["p_total"] == 1 and r["ex"] == cliques, (gi, mode, exact_cv)
+
+
+def test_oriented_tables_count_out_neighbours():
+    g = synth.chung_lu(n=200, m=1200, seed=9)
+    o = oracle.orient(g)
+    t = oracle.Tables(o, exact_cv=True, adjacency=g)
+    adj = g.adjacency_sets()
+    dout = np.diff(o.off).astype(np.int64)
+    assert np.array_equal(t.deg.astype(np.int64), dout)
+    for v in range(0, g.n, 7):
+        out = o.nbr[int(o.off[v]):int(o.off[v + 1])].tolist()
+        pairs = sum(1 for a, b in itertools.combinations(out, 2) if b in adj[a])
+        assert int(t.hits[v]) == pairs
+        assert int(t.trials[v]) == len(out) * (len(out) - 1) // 2
