@@ -246,6 +246,7 @@ def main():
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-ablation", action="store_true")
     ap.add_argument("--skip-conc", action="store_true")
+    ap.add_argument("--skip-oriented", action="store_true")
     ap.add_argument("--conc-budget", type=int, default=20_000_000,
                     help="sample budget per pattern of the concentration runs (to +-1%%)")
     ap.add_argument("--skip-large", action="store_true",
@@ -533,6 +534,34 @@ def main():
         }
         log(f"batch: {bt:.2f} s, {batch['converged']}/32 converged, {batch['samples']:.3g} samples")
 
+    # cliques on the degree-oriented graph (each clique one trajectory) vs
+    # the symmetric graph: samples/s, variance per sample, time to +-1%
+    oriented = None
+    if not args.skip_oriented:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        O = sess.orient(G)
+        TO = sess.tables(O, cv_seed=1)
+        torch.cuda.synchronize()
+        oriented = {"orient_and_tables_ms": 1e3 * (time.perf_counter() - t0), "nnz": O.nnz, "patterns": {}}
+        for k in (4, 5):
+            p = synth.patterns.clique(k)
+            row = {}
+            for label, (gg, tt) in (("oriented", (O, TO)), ("symmetric", (G, T))):
+                r = sess.estimate(gg, tt, p, args.samples, 29, mode="switch", pattern_id=k)
+                e = sess.estimate(gg, tt, p, args.eps_budget, 31, mode="switch", pattern_id=k, eps=0.01, delta=0.05,
+                                  check_every=1 << 16, min_samples=1 << 14)
+                row[label] = {"samples_per_s_kernel": r.n / max(r.sample_kernel_seconds, 1e-12),
+                              "rel_var": r.variance / max(r.estimate ** 2, 1e-300), "estimate": r.estimate,
+                              "time_to_1pct_s": e.seconds, "samples_to_1pct": e.n, "converged": bool(e.converged)}
+            oriented["patterns"][f"{k}-clique"] = row
+            log(f"{k}-clique oriented: {row['oriented']['samples_per_s_kernel']:.3g} samples/s, rel.var "
+                f"{row['oriented']['rel_var']:.3g}, +-1% in {row['oriented']['time_to_1pct_s']:.4f} s; symmetric: "
+                f"{row['symmetric']['samples_per_s_kernel']:.3g} samples/s, rel.var {row['symmetric']['rel_var']:.3g}, "
+                f"+-1% in {row['symmetric']['time_to_1pct_s']:.4f} s")
+        TO.close()
+        O.close()
+
     # concentrations of all connected 4- and 5-vertex patterns (6 and 21),
     # each pattern run to +-1% inside batched launches, as in the paper's
     # comparison with MCMC estimators
@@ -594,6 +623,7 @@ def main():
         "batch_32_patterns": batch,
         "rmat24": large,
         "concentrations": concentration,
+        "cliques_oriented": oriented,
         "term_ablation_and_beta": ablation,
         "time_to_1pct": eps_table,
         "roofline": roofline,
