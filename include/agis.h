@@ -115,7 +115,7 @@ typedef struct {
  * terms: which factors of f_approx (Eq. probability_function) enter the
  *   weights -- AGIS_TERMS_ALL (T[F1] T[I1] T[F2], the method), or the
  *   incremental versions of the paper's analysis of the approximation
- *   (Sec. 7, analysis of the approximate distribution): AGIS_TERMS_F1
+ *   (Sec. 6.2, analysis of the approximate distribution): AGIS_TERMS_F1
  *   (T[F1] only) and AGIS_TERMS_F1_I1 (T[F1] T[I1]).  The decision function
  *   and the reported plan are unchanged.
  * learned: for AGIS_MODE_LEARNED, per step a device int32[n] table of Q16
@@ -187,7 +187,7 @@ int agis_create(agis_ctx** out, int device, void* hip_stream);
 void agis_destroy(agis_ctx* ctx);
 const char* agis_last_error(const agis_ctx* ctx);
 
-/* Registers a symmetric CSR graph (Sec. 6.1: the graph is held in CSR).
+/* Registers a symmetric CSR graph (Sec. 5.4: the graph is held in CSR).
  * off: device uint64[n + 1], off[0] = 0, off[n] = nnz, non-decreasing;
  * nbr: device uint32[nnz], each row strictly ascending, ids < n, no
  * self-loops, and x in row v iff v in row x.  Both are BORROWED: they must
@@ -198,7 +198,7 @@ int agis_load_csr(agis_ctx* ctx, const uint64_t* off, const uint32_t* nbr, uint6
                   uint32_t flags, agis_graph** out);
 void agis_graph_destroy(agis_graph* g);
 
-/* Degree orientation for clique patterns (Sec. 6.1, orientation
+/* Degree orientation for clique patterns (Sec. 5.4, orientation
  * optimisation): a new graph, owned by the library, whose rows hold only
  * the neighbours w of v with (d(w), w) > (d(v), v) -- edges from the
  * higher-degree end are dropped, ties broken by id -- in ascending id order.
@@ -256,7 +256,7 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
                   agis_result* out);
 
 /* Estimates C(G, P) for n_patterns (1..64) patterns at once, the way the
- * paper runs independent samplers in parallel (Sec. 6.1), with uneven
+ * paper runs independent samplers in parallel (Sec. 5.4), with uneven
  * sample budgets: budgets[i] host uint64 per pattern.  Each round is one
  * persistent launch over all still-active patterns (replayed from a
  * captured HIP graph unless disabled by agis_set_launch): waves take
@@ -315,7 +315,7 @@ int agis_step1_weights(agis_ctx* ctx, const agis_graph* g, const agis_tables* t,
                        const uint8_t* order, const agis_run_params* params, uint32_t* q1, uint64_t* total);
 
 /* Concentrations of the connected k-vertex patterns (2 <= k <= 6), the
- * quantity the paper compares with MCMC estimators (Sec. 7, comparison
+ * quantity the paper compares with MCMC estimators (Sec. 6.3, comparison
  * with MCMC): each pattern's count divided by the total over all
  * patterns of its size.  Host arrays of n_patterns entries; patterns must
  * be pairwise non-isomorphic, connected, of one size, and hold every

@@ -3,7 +3,7 @@ infrastructure only).
 
 The paper compares its counts with MCMC estimators of the concentration
 of a pattern: its count divided by the total count of all connected
-patterns of the same size (Sec. 7, comparison with MCMC).  The sampler
+patterns of the same size (Sec. 6.3, comparison with MCMC).  The sampler
 counts edge-induced copies (embeddings / |Aut|).  Vertex-induced counts
 follow from them: every k-vertex set that induces a connected graph G
 contains s(H, G) copies of H, where s(H, G) is the number of spanning
