@@ -243,6 +243,12 @@ __device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __res
 // start of the next chunk.
 constexpr uint32_t kStreamMaxWindow = 2048;
 
+// The value `v` held by lane `src` (0..63), as seen by this lane: one
+// ds_bpermute.  Every lane of the wave must execute it.
+__device__ __forceinline__ uint32_t bperm(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+
 // Whether this lane's xv occurs among the 64 ascending values held one per
 // lane (val): a binary search by shuffles.  Every lane must take part (a
 // lane outside the exec mask would not supply its value to the others).
@@ -250,18 +256,19 @@ __device__ __forceinline__ bool piece_contains(uint32_t val, uint32_t xv) {
     int lo = 0;
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) {
-        const uint32_t pv = __shfl(val, lo + s - 1, kWave);
-        if (pv < xv) lo += s;
+        const uint32_t pv = bperm(val, lo + s - 1);
+        lo += pv < xv ? s : 0;
     }
-    const uint32_t cand = __shfl(val, lo, kWave);
+    const uint32_t cand = bperm(val, lo);
     return cand == xv;
 }
 
 __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict__ list, uint32_t pos, uint32_t len,
                                                       uint32_t xv, uint32_t xlast, uint32_t left, bool& member) {
     const int lane = lane_id();
-    // expected window (len - pos) * 64 / left <= kStreamMaxWindow, without a division
-    if ((uint64_t)(len - pos) * kWave <= (uint64_t)kStreamMaxWindow * (left ? left : 1u)) {
+    // expected window (len - pos) * 64 / left <= kStreamMaxWindow, without a
+    // division; the streaming path takes positions as 32-bit signed values
+    if (len < 0x7FFFFF00u && (uint64_t)(len - pos) * kWave <= (uint64_t)kStreamMaxWindow * (left ? left : 1u)) {
         // Blocks of 256 elements, 4 consecutive ones per lane from one
         // 16-byte load (blocks are aligned to 16 bytes in memory, so the
         // first may start up to 3 elements before pos; elements before pos
@@ -270,48 +277,55 @@ __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict
         // elements, then compares with that quad: 10 shuffles per 256
         // elements.  Reads stay inside [0, len) of the list.
         constexpr uint32_t kNone = 0xFFFFFFFFu;  // ids are < n <= 2^32 - 1
-        const int64_t mis = (int64_t)(((uintptr_t)list >> 2) & 3u);
-        int64_t qs = (int64_t)(((uint64_t)pos + (uint64_t)mis) & ~3ull) - mis;  // block start, >= pos - 3
+        // positions as 32-bit signed values (the caller keeps len < 2^31)
+        const int32_t mis = (int32_t)(((uintptr_t)list >> 2) & 3u);
+        const int32_t ilen = (int32_t)len;
+        const int32_t ipos = (int32_t)pos;
+        int32_t qs = ((ipos + mis) & ~3) - mis;  // block start, >= pos - 3
         bool hit = false;
         for (;;) {
-            const int64_t e = qs + 4 * (int64_t)lane;
+            const int32_t e = qs + 4 * lane;
             uint32_t v0, v1, v2, v3;
-            if (e >= 0 && e + 3 < (int64_t)len) {
+            if (qs >= 0 && qs + 4 * kWave <= ilen) {
+                // the whole block lies in the list (wave-uniform test)
                 const uint4 q = *reinterpret_cast<const uint4*>(list + e);
                 v0 = q.x;
                 v1 = q.y;
                 v2 = q.z;
                 v3 = q.w;
             } else {
-                v0 = e < 0 ? 0u : (e < (int64_t)len ? list[e] : kNone);
-                v1 = e + 1 < 0 ? 0u : (e + 1 < (int64_t)len ? list[e + 1] : kNone);
-                v2 = e + 2 < 0 ? 0u : (e + 2 < (int64_t)len ? list[e + 2] : kNone);
-                v3 = e + 3 < (int64_t)len ? list[e + 3] : kNone;
+                // a block at either end of the list: per element, zero
+                // before the list's start (never counted: before pos), none
+                // after its end
+                v0 = e < 0 ? 0u : (e < ilen ? list[e] : kNone);
+                v1 = e + 1 < 0 ? 0u : (e + 1 < ilen ? list[e + 1] : kNone);
+                v2 = e + 2 < 0 ? 0u : (e + 2 < ilen ? list[e + 2] : kNone);
+                v3 = e + 3 < ilen ? list[e + 3] : kNone;
             }
             // window end: first element at or after pos above xlast
-            const int64_t dp = (int64_t)pos - e;  // elements of this quad before pos
-            const uint64_t m0 = __ballot(dp <= 0 && v0 > xlast);
-            const uint64_t m1 = __ballot(dp <= 1 && v1 > xlast);
-            const uint64_t m2 = __ballot(dp <= 2 && v2 > xlast);
-            const uint64_t m3 = __ballot(dp <= 3 && v3 > xlast);
-            // membership of xv
+            const int32_t dp = ipos - e;  // elements of this quad before pos
+            const uint64_t m0 = __ballot((dp <= 0) & (v0 > xlast));
+            const uint64_t m1 = __ballot((dp <= 1) & (v1 > xlast));
+            const uint64_t m2 = __ballot((dp <= 2) & (v2 > xlast));
+            const uint64_t m3 = __ballot((dp <= 3) & (v3 > xlast));
+            // membership of xv: the lane whose quad may hold it, then its quad
             int lo = 0;
 #pragma unroll
             for (int s = 32; s > 0; s >>= 1) {
-                const uint32_t pv = __shfl(v0, lo + s, kWave);
-                if (pv <= xv) lo += s;
+                const uint32_t pv = bperm(v0, lo + s);
+                lo += pv <= xv ? s : 0;
             }
-            const uint32_t a0 = __shfl(v0, lo, kWave);
-            const uint32_t a1 = __shfl(v1, lo, kWave);
-            const uint32_t a2 = __shfl(v2, lo, kWave);
-            const uint32_t a3 = __shfl(v3, lo, kWave);
+            const uint32_t a0 = bperm(v0, lo);
+            const uint32_t a1 = bperm(v1, lo);
+            const uint32_t a2 = bperm(v2, lo);
+            const uint32_t a3 = bperm(v3, lo);
             // only elements at or after pos count (this also excludes the
             // zero fill before the list's start)
-            const int64_t dl = (int64_t)pos - (qs + 4 * (int64_t)lo);
-            hit = hit || (a0 == xv && dl <= 0) || (a1 == xv && dl <= 1) || (a2 == xv && dl <= 2) ||
-                  (a3 == xv && dl <= 3);
+            const int32_t dl = ipos - (qs + 4 * lo);
+            hit = hit | ((a0 == xv) & (dl <= 0)) | ((a1 == xv) & (dl <= 1)) | ((a2 == xv) & (dl <= 2)) |
+                  ((a3 == xv) & (dl <= 3));
             if ((m0 | m1 | m2 | m3) != 0) {
-                int64_t endi = INT64_MAX;
+                int32_t endi = INT32_MAX;
                 if (m0) endi = qs + 4 * (__ffsll((unsigned long long)m0) - 1);
                 if (m1) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m1) - 1) + 1);
                 if (m2) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m2) - 1) + 2);
