@@ -936,6 +936,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
     const uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = P->pattern_id;
     const uint32_t k = P->k;
     uint32_t my_tau = 0;
+    // lane j: the row its vertex was drawn from at a single-backward step and
+    // its position there (a later probe of the same row needs no search)
+    uint32_t my_row = 0xFFFFFFFFu, my_rpos = 0;
     uint64_t scnt = 0;  // size of the candidate set the scratch holds
     double x = 1.0;
     int fail = -1;
@@ -943,6 +946,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
     for (; i < k; ++i) {
         uint64_t num, den;
         uint32_t v;
+        uint32_t drawn_row = 0xFFFFFFFFu, drawn_pos = 0;
         if (i == 0) {
             if (P->weighted[0]) {
                 if (P->s1_total == 0) {
@@ -987,9 +991,15 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 uint32_t pos = 0xFFFFFFFFu;
                 bool found = false;
                 uint64_t qx = 0;
-                if ((uint32_t)lane < i) {
-                    pos = lower_bound_u32(list, d, my_tau);
-                    found = pos < d && list[pos] == my_tau;
+                // w itself is matched but never in its own list (no loops)
+                if ((uint32_t)lane < i && my_tau != w) {
+                    if (my_row == w) {
+                        pos = my_rpos;
+                        found = true;
+                    } else {
+                        pos = lower_bound_u32(list, d, my_tau);
+                        found = pos < d && list[pos] == my_tau;
+                    }
                     if (found) qx = pre[pos] - (pos > 0 ? pre[pos - 1] : base);
                 }
                 const uint64_t qrow = d ? pre[d - 1] - base : 0ull;
@@ -1023,6 +1033,8 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 }
                 if (ans == ~0ull) ans = seg + wave_first_greater(pre + seg, d - seg, r + shift, base);
                 v = list[ans];
+                drawn_row = w;
+                drawn_pos = (uint32_t)ans;
                 num = Q;
                 den = pre[ans] - (ans > 0 ? pre[ans - 1] : base);
             } else if (!weighted && __builtin_popcount(bm) == 1) {
@@ -1035,9 +1047,14 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint32_t* list = g.nbr + o;
                 uint32_t pos = 0xFFFFFFFFu;
                 bool found = false;
-                if ((uint32_t)lane < i) {
-                    pos = lower_bound_u32(list, d, my_tau);
-                    found = pos < d && list[pos] == my_tau;
+                if ((uint32_t)lane < i && my_tau != w) {  // w is never in its own list
+                    if (my_row == w) {
+                        pos = my_rpos;
+                        found = true;
+                    } else {
+                        pos = lower_bound_u32(list, d, my_tau);
+                        found = pos < d && list[pos] == my_tau;
+                    }
                 }
                 const uint32_t ex = (uint32_t)__popcll(__ballot(found));
                 const uint64_t m = (uint64_t)d - ex;
@@ -1055,6 +1072,8 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         idx = r + c;
                     }
                     v = list[idx];
+                    drawn_row = w;
+                    drawn_pos = (uint32_t)idx;
                 }
                 num = m;
                 den = 1;
@@ -1222,7 +1241,11 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
             x = x * ((double)num / (double)den);
         }
         v = uniform_u32(v);
-        if ((uint32_t)lane == i) my_tau = v;
+        if ((uint32_t)lane == i) {
+            my_tau = v;
+            my_row = drawn_row;
+            my_rpos = drawn_pos;
+        }
         if (kDump && lane == 0) {
             rec->v[i] = v;
             rec->num[i] = num;
