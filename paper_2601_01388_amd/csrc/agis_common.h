@@ -139,6 +139,12 @@ struct DevGraph {
 // log2 of C_v, clamped), w = unused.
 struct DevTables {
     AGIS_GMEM const uint4* rec;
+    // neighbourhood bitmaps of the highest-degree vertices: bit x of row
+    // hub_slot[v] is set iff x is a neighbour of v (hub_slot[v] < 0: none);
+    // a membership test against such a list is one probe
+    AGIS_GMEM const uint32_t* hub_bits;
+    AGIS_GMEM const int32_t* hub_slot;
+    uint64_t hub_words;  // 32-bit words per bitmap row
 };
 
 struct DevPlan {

@@ -62,6 +62,12 @@ struct agis_tables {
     uint64_t* s2 = nullptr;
     uint64_t* hits = nullptr;
     uint64_t* trials = nullptr;
+    // hub neighbourhood bitmaps (see DevTables)
+    uint32_t* hub_bits = nullptr;
+    int32_t* hub_slot = nullptr;
+    uint64_t hub_words = 0;
+    uint64_t hubs = 0;
+    uint32_t hub_min_degree = 0;
 };
 
 namespace agis {
@@ -91,6 +97,14 @@ hipError_t launch_max_degree(const DevGraph& g, uint32_t* d_max, hipStream_t str
 hipError_t launch_build_tables(const DevGraph& g, const DevGraph& adj, uint4* rec, uint64_t* s2, uint64_t* hits,
                                uint64_t* trials, uint32_t k0, uint32_t k1, int32_t lc_min, int exact,
                                hipStream_t stream);
+// Hub bitmaps: log2-degree histogram (64 buckets) of g; then, for vertices
+// of degree >= min_deg, their slots (hub_slot, -1 elsewhere; flags is n
+// entries of scratch), the count into *hubs; then the bits.
+hipError_t launch_degree_histogram(const DevGraph& g, uint32_t* hist, hipStream_t stream);
+hipError_t launch_hub_slots(agis_ctx* ctx, const DevGraph& g, uint32_t min_deg, uint32_t* flags, int32_t* hub_slot,
+                            uint64_t* d_count);
+hipError_t launch_hub_bits(const DevGraph& g, const int32_t* hub_slot, uint64_t words, uint32_t* bits,
+                           hipStream_t stream);
 // Degree orientation: out-degrees into outdeg (n entries of scratch), the
 // offsets into off_out (n + 1), then the neighbours into nbr_out.
 hipError_t launch_orient_offsets(agis_ctx* ctx, const DevGraph& g, uint32_t* outdeg, uint64_t* off_out);

@@ -131,6 +131,59 @@ constexpr uint64_t kStepTableBudgetBytes = 16ull << 30;
 constexpr uint64_t kRowtabMinSamples = 65536;
 constexpr uint64_t kRowtabBudgetBytes = 32ull << 30;
 
+// Neighbourhood bitmaps of the highest-degree vertices (degree >= 64, as
+// many as fit in kHubBitmapBudget, the degree threshold a power of two):
+// the sampler tests membership in such a list with one probe.
+constexpr uint64_t kHubBitmapBudget = 1ull << 30;
+
+hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t) {
+    const uint64_t n = g->g.n;
+    const uint64_t words = (n + 31) / 32;
+    const uint64_t max_hubs = kHubBitmapBudget / (words * sizeof(uint32_t));
+    if (n == 0 || max_hubs == 0) return hipSuccess;
+    uint32_t* d_hist = (uint32_t*)ctx->d_small;
+    uint32_t hist[64];
+    hipError_t e = agis::launch_degree_histogram(g->g, d_hist, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hist, d_hist, sizeof(hist), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    int b = 6;
+    for (;; ++b) {
+        uint64_t c = 0;
+        for (int j = b; j < 64; ++j) c += hist[j];
+        if (c <= max_hubs || b == 63) break;
+    }
+    uint64_t above = 0;
+    for (int j = b; j < 64; ++j) above += hist[j];
+    if (above == 0) return hipSuccess;
+    uint32_t* flags = nullptr;
+    uint64_t* prefix = nullptr;
+    e = hipMalloc(&flags, n * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&prefix, (n + 1) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&t->hub_slot, n * sizeof(int32_t));
+    if (e == hipSuccess) e = agis::launch_hub_slots(ctx, g->g, 1u << b, flags, t->hub_slot, prefix);
+    uint64_t hubs = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hubs, prefix + n, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMalloc(&t->hub_bits, hubs * words * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(t->hub_bits, 0, hubs * words * sizeof(uint32_t), ctx->stream);
+    if (e == hipSuccess) e = agis::launch_hub_bits(g->g, t->hub_slot, words, t->hub_bits, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (flags) (void)hipFree(flags);
+    if (prefix) (void)hipFree(prefix);
+    if (e == hipSuccess) {
+        t->hub_words = words;
+        t->hubs = hubs;
+        t->hub_min_degree = 1u << b;
+    }
+    return e;
+}
+
+agis::DevTables dev_tables(const agis_tables* t) {
+    return agis::DevTables{agis::gmem((const uint4*)t->rec), agis::gmem((const uint32_t*)t->hub_bits),
+                           agis::gmem((const int32_t*)t->hub_slot), t->hub_words};
+}
+
 int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p, const uint8_t* order,
             const agis_run_params* params, uint64_t n_samples, StepTables* st, Prepared* out) {
     int rc = agis::compile_plan(p, order, params->mode, params->beta_num, params->beta_den, &out->plan, &ctx->err);
@@ -329,7 +382,7 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
     if (rc != AGIS_OK) return rc;
     agis::LaunchDesc ld;
     std::memset(&ld, 0, sizeof(ld));
-    agis::fill_launch(ctx, L, g->g, agis::DevTables{agis::gmem((const uint4*)t->rec)}, nullptr, nullptr, &ld);
+    agis::fill_launch(ctx, L, g->g, dev_tables(t), nullptr, nullptr, &ld);
     agis::RoundDesc& rd = ld.round;
     std::vector<Partial> parts;
     std::vector<uint32_t> members;
@@ -591,6 +644,7 @@ int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_s
                                       (uint32_t)cv_seed, (uint32_t)(cv_seed >> 32), lc_min_q16, exact_cv ? 1 : 0,
                                       ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = build_hub_bitmaps(ctx, g, t);
     if (e != hipSuccess) {
         agis_tables_destroy(t);
         return hip_fail(ctx, e, "build proposal tables");
@@ -605,6 +659,8 @@ void agis_tables_destroy(agis_tables* t) {
     if (t->s2) (void)hipFree(t->s2);
     if (t->hits) (void)hipFree(t->hits);
     if (t->trials) (void)hipFree(t->trials);
+    if (t->hub_bits) (void)hipFree(t->hub_bits);
+    if (t->hub_slot) (void)hipFree(t->hub_slot);
     delete t;
 }
 
@@ -745,7 +801,7 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     L.dump = true;
     agis::LaunchDesc ld;
     std::memset(&ld, 0, sizeof(ld));
-    agis::fill_launch(ctx, L, g->g, agis::DevTables{agis::gmem((const uint4*)t->rec)}, idx, (agis::Record*)out, &ld);
+    agis::fill_launch(ctx, L, g->g, dev_tables(t), idx, (agis::Record*)out, &ld);
     agis::RoundDesc& rd = ld.round;
     rd.total = m;
     rd.nseg = 1;

@@ -758,6 +758,76 @@ hipError_t launch_orient_offsets(agis_ctx* ctx, const DevGraph& g, uint32_t* out
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Hub neighbourhood bitmaps
+// ---------------------------------------------------------------------------
+__global__ void k_degree_histogram(DevGraph g, uint32_t* hist) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const uint64_t d = g.off[v + 1] - g.off[v];
+    if (d) atomicAdd(&hist[63 - __builtin_clzll(d)], 1u);
+}
+
+hipError_t launch_degree_histogram(const DevGraph& g, uint32_t* hist, hipStream_t stream) {
+    hipError_t e = hipMemsetAsync(hist, 0, 64 * sizeof(uint32_t), stream);
+    if (e != hipSuccess) return e;
+    if (g.n) hipLaunchKernelGGL(k_degree_histogram, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, hist);
+    return hipGetLastError();
+}
+
+__global__ void k_hub_flags(DevGraph g, uint32_t min_deg, uint32_t* flags) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < g.n) flags[v] = (g.off[v + 1] - g.off[v]) >= min_deg ? 1u : 0u;
+}
+
+// hub_slot[v] = number of hubs before v for a hub, -1 otherwise; prefix[v + 1]
+// = inclusive count (from the scan)
+__global__ void k_hub_slot(const uint32_t* flags, const uint64_t* prefix, uint64_t n, int32_t* hub_slot) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) hub_slot[v] = flags[v] ? (int32_t)(prefix[v + 1] - 1) : -1;
+}
+
+hipError_t launch_hub_slots(agis_ctx* ctx, const DevGraph& g, uint32_t min_deg, uint32_t* flags, int32_t* hub_slot,
+                            uint64_t* d_count) {
+    hipStream_t st = ctx->stream;
+    const uint64_t n = g.n;
+    const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ctx->blocksums_cap < ntiles) {
+        if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
+        ctx->d_blocksums = nullptr;
+        ctx->blocksums_cap = 0;
+        hipError_t e = hipMalloc(&ctx->d_blocksums, ntiles * sizeof(uint64_t));
+        if (e != hipSuccess) return e;
+        ctx->blocksums_cap = ntiles;
+    }
+    // the inclusive prefix goes to d_count[0..n] (n + 1 entries of scratch)
+    hipError_t e = hipMemsetAsync(d_count, 0, sizeof(uint64_t), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hub_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, g, min_deg, flags);
+    hipLaunchKernelGGL(k_u32_tilesum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, flags, n, ctx->d_blocksums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, ctx->d_blocksums, ntiles);
+    hipLaunchKernelGGL(k_u32_final, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, flags, n, ctx->d_blocksums,
+                       d_count);
+    hipLaunchKernelGGL(k_hub_slot, dim3(grid_for(n, 256)), dim3(256), 0, st, flags, d_count, n, hub_slot);
+    return hipGetLastError();
+}
+
+__global__ void k_hub_bits(DevGraph g, const int32_t* hub_slot, uint64_t words, uint32_t* bits) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.nnz) return;
+    const uint32_t v = row_of_slot(g.off, g.n, e);
+    const int32_t slot = hub_slot[v];
+    if (slot < 0) return;
+    const uint32_t x = g.nbr[e];
+    atomicOr(&bits[(uint64_t)slot * words + (x >> 5)], 1u << (x & 31u));
+}
+
+hipError_t launch_hub_bits(const DevGraph& g, const int32_t* hub_slot, uint64_t words, uint32_t* bits,
+                           hipStream_t stream) {
+    if (g.nnz) hipLaunchKernelGGL(k_hub_bits, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, hub_slot, words, bits);
+    return hipGetLastError();
+}
+
 hipError_t launch_orient_fill(const DevGraph& g, const uint64_t* off_out, uint32_t* nbr_out, hipStream_t stream) {
     hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, off_out, nbr_out);
     return hipGetLastError();
@@ -1132,6 +1202,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     if (in_all) lmax_l = step_log_weight(t, sw, lt, my_tau, b, f1, ie, f2);
                 }
                 uint32_t my_pos = 0;  // lane j: window start in backward list j
+                // lane j: bitmap row of backward vertex j when it is a hub
+                int32_t my_slot = -1;
+                if (t.hub_slot && (uint32_t)lane < i && (others >> lane & 1u)) my_slot = t.hub_slot[my_tau];
                 uint64_t cnt = 0;
                 // Software pipeline over the chunks: the next chunk's base
                 // elements are loaded one chunk ahead, and a chunk's weights
@@ -1157,6 +1230,15 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     bool member = valid;
                     for (uint32_t bits = others; bits; bits &= bits - 1) {
                         const int j = __builtin_ctz(bits);
+                        const int32_t slot = (int32_t)readlane_u32((uint32_t)my_slot, j);
+                        if (slot >= 0) {
+                            // a hub's list: one bit probe per element
+                            if (member) {
+                                const uint32_t wd = t.hub_bits[(uint64_t)slot * t.hub_words + (xv >> 5)];
+                                member = (wd >> (xv & 31u)) & 1u;
+                            }
+                            continue;
+                        }
                         const uint32_t* lj = g.nbr + readlane_u64(my_o, j);
                         const uint32_t dj = readlane_u32(my_d, j);
                         const uint32_t pos = readlane_u32(my_pos, j);
