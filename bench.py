@@ -305,9 +305,10 @@ def main():
     if not args.no_tune:
         log("autotuning the sampler launch on the four patterns")
         tun = sess.autotune(G, T, pats, args.tune_pilot, mode="switch")
-        tuning = {"variant": tun.variant, "grab": tun.grab, "pilot_kernel_s": tun.seconds,
+        tuning = {"variant": tun.variant, "grab": tun.grab, "hub_window": tun.hub_window, "pilot_kernel_s": tun.seconds,
                   "default_kernel_s": tun.default_seconds}
-        log(f"tuned: variant {tun.variant} grab {tun.grab} ({tun.default_seconds:.3f} s -> {tun.seconds:.3f} s)")
+        log(f"tuned: variant {tun.variant} grab {tun.grab} hub window {tun.hub_window} "
+            f"({tun.default_seconds:.3f} s -> {tun.seconds:.3f} s)")
 
     def step(seed):
         res = []

@@ -280,8 +280,13 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
  * many as fit); grab = sample slots a wave takes from the queue at a time
  * (0 = chosen from the round size, at most 1024); variant = register
  * budget of the sampling kernel (0 = compiler's choice; 1 and 2 = small
- * enough for 7 and 8 resident waves per SIMD, spilling the rest). */
-int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant);
+ * enough for 7 and 8 resident waves per SIMD, spilling the rest);
+ * hub_window: a high-degree vertex's neighbourhood bitmap (built with the
+ * tables) replaces the merge with its list when the list is at least
+ * hub_window / 64 times as long as the set it is intersected with (0 =
+ * whenever there is a bitmap). */
+int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant,
+                    uint32_t hub_window);
 
 /* Launch configuration chosen by agis_autotune. */
 typedef struct {
@@ -291,11 +296,14 @@ typedef struct {
     int32_t variant;
     double seconds;          /* sampling-kernel time of the chosen configuration's pilot */
     double default_seconds;  /* the same pilot under the default configuration */
+    uint32_t hub_window;
+    uint32_t reserved;
 } agis_tuning;
 
 /* Times pilot batches (pilot_samples samples of each of the n_patterns
  * patterns, fixed budgets, params' mode and beta) under each candidate
- * launch configuration -- kernel register-budget variant x queue grab --
+ * launch configuration -- kernel register-budget variant x queue grab,
+ * then the hub-bitmap window --
  * and applies the fastest to the context (as agis_set_launch would).
  * Results of later calls do not depend on the choice. */
 int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint32_t n_patterns,

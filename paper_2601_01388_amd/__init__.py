@@ -86,7 +86,8 @@ class agis_run_params(ctypes.Structure):
 
 class agis_tuning(ctypes.Structure):
     _fields_ = [("use_graphs", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("grab", ctypes.c_uint32),
-                ("variant", ctypes.c_int32), ("seconds", ctypes.c_double), ("default_seconds", ctypes.c_double)]
+                ("variant", ctypes.c_int32), ("seconds", ctypes.c_double), ("default_seconds", ctypes.c_double),
+                ("hub_window", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class agis_result(ctypes.Structure):
@@ -129,7 +130,8 @@ _SIGNATURES = [
                                          ctypes.POINTER(agis_run_params), _P, ctypes.c_uint64, _P]),
     ("agis_estimate_batch", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, _P, ctypes.c_uint64,
                                            ctypes.POINTER(agis_run_params), _P]),
-    ("agis_set_launch", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32]),
+    ("agis_set_launch", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
+                                       ctypes.c_uint32]),
     ("agis_autotune", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, ctypes.c_uint64,
                                      ctypes.POINTER(agis_run_params), ctypes.POINTER(agis_tuning)]),
     ("agis_mlp_param_count", ctypes.c_int, []),
@@ -292,8 +294,9 @@ def agis_estimate_batch(ctx, g, t, patterns, budgets, seed: int, params: agis_ru
     return list(out)
 
 
-def agis_set_launch(ctx, use_graphs: bool = True, blocks_per_cu: int = 0, grab: int = 0, variant: int = 0):
-    _check(ctx, lib().agis_set_launch(ctx, 1 if use_graphs else 0, blocks_per_cu, grab, variant))
+def agis_set_launch(ctx, use_graphs: bool = True, blocks_per_cu: int = 0, grab: int = 0, variant: int = 0,
+                    hub_window: int = 0):
+    _check(ctx, lib().agis_set_launch(ctx, 1 if use_graphs else 0, blocks_per_cu, grab, variant, hub_window))
 
 
 def agis_autotune(ctx, g, t, patterns, pilot_samples: int, params: agis_run_params) -> agis_tuning:

@@ -212,7 +212,9 @@ struct LaunchDesc {
     AGIS_GMEM unsigned long long* queue;  // next free slot
     AGIS_GMEM double* xout;               // weight per slot
     uint32_t grab;
-    uint32_t pad;
+    // a hub's bitmap replaces the merge with its list when the list is at
+    // least hub_window / 64 times as long as the base it is intersected with
+    uint32_t hub_window;
     RoundDesc round;
 };
 

@@ -32,6 +32,7 @@ struct agis_ctx {
     uint32_t tune_grab = 0;
     int use_graphs = 1;
     int tune_variant = 0;  // sampling-kernel register budget (see sample_kernel)
+    uint32_t tune_hub_window = 0;  // see LaunchDesc::hub_window
     // captured round (k_zero, k_sample, k_reduce_x) replayed on graph_stream;
     // valid while the key below matches
     hipStream_t graph_stream = nullptr;
@@ -138,6 +139,7 @@ struct SampleLaunch {
     uint64_t max_tiles = 0;  // reduction tiles of the largest round
     bool dump = false;       // launch the record-writing variant
     int variant = 0;         // register-budget variant
+    uint32_t hub_window = 0; // see LaunchDesc::hub_window
 };
 
 // The sampling kernel for (record-writing?, register-budget variant 0..2).

@@ -817,12 +817,14 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     return AGIS_OK;
 }
 
-int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant) {
+int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant,
+                    uint32_t hub_window) {
     if (!ctx || blocks_per_cu < 0 || grab > 1024 || variant < 0 || variant > 2) return AGIS_E_INVALID_ARG;
     ctx->use_graphs = use_graphs ? 1 : 0;
     ctx->tune_blocks_per_cu = blocks_per_cu;
     ctx->tune_grab = grab;
     ctx->tune_variant = variant;
+    ctx->tune_hub_window = hub_window;
     return AGIS_OK;
 }
 
@@ -839,45 +841,61 @@ int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint
     std::vector<uint64_t> budgets(n_patterns, pilot_samples);
     std::vector<agis_result> res(n_patterns);
     const int saved_graphs = ctx->use_graphs, saved_blocks = ctx->tune_blocks_per_cu, saved_variant = ctx->tune_variant;
-    const uint32_t saved_grab = ctx->tune_grab;
+    const uint32_t saved_grab = ctx->tune_grab, saved_window = ctx->tune_hub_window;
     struct Cand {
         int variant;
         uint32_t grab;
+        uint32_t window;
     };
-    const Cand cands[] = {{0, 0}, {1, 0}, {2, 0}, {0, 1}, {1, 1}, {2, 1}, {0, 4}, {1, 4}, {2, 4}};
+    // first the register budget x queue grab, then the hub-bitmap window
+    // with the best of those
+    Cand cands[9 + 3] = {{0, 0, 0}, {1, 0, 0}, {2, 0, 0}, {0, 1, 0}, {1, 1, 0},
+                         {2, 1, 0}, {0, 4, 0}, {1, 4, 0}, {2, 4, 0}};
     double best = INFINITY, first = 0.0;
     Cand best_c = cands[0];
-    for (const Cand& c : cands) {
+    auto time_config = [&](const Cand& c, double* secs) -> int {
         ctx->use_graphs = 1;
         ctx->tune_blocks_per_cu = 0;
         ctx->tune_variant = c.variant;
         ctx->tune_grab = c.grab;
-        double secs = 0.0;
+        ctx->tune_hub_window = c.window;
+        *secs = 0.0;
         for (int rep = 0; rep < 2; ++rep) {  // first repetition warms caches and captures the graph
-            rc = agis_estimate_batch(ctx, g, t, n_patterns, patterns, budgets.data(), 0x5eed, &pp, res.data());
-            if (rc != AGIS_OK) break;
+            const int r = agis_estimate_batch(ctx, g, t, n_patterns, patterns, budgets.data(), 0x5eed, &pp, res.data());
+            if (r != AGIS_OK) return r;
             if (rep == 1)
-                for (const agis_result& r : res) secs += r.sample_kernel_seconds;
+                for (const agis_result& x : res) *secs += x.sample_kernel_seconds;
         }
+        return AGIS_OK;
+    };
+    for (int ci = 0; ci < 12 && rc == AGIS_OK; ++ci) {
+        if (ci == 9) {
+            const uint32_t windows[3] = {256, 1024, 4096};
+            for (int w = 0; w < 3; ++w) cands[9 + w] = Cand{best_c.variant, best_c.grab, windows[w]};
+        }
+        double secs = 0.0;
+        rc = time_config(cands[ci], &secs);
         if (rc != AGIS_OK) break;
-        if (&c == &cands[0]) first = secs;
+        if (ci == 0) first = secs;
         if (secs < best) {
             best = secs;
-            best_c = c;
+            best_c = cands[ci];
         }
     }
     ctx->use_graphs = saved_graphs;
     ctx->tune_blocks_per_cu = saved_blocks;
     ctx->tune_variant = saved_variant;
     ctx->tune_grab = saved_grab;
+    ctx->tune_hub_window = saved_window;
     if (rc != AGIS_OK) return rc;
     out->use_graphs = 1;
     out->blocks_per_cu = 0;
     out->grab = best_c.grab;
     out->variant = best_c.variant;
+    out->hub_window = best_c.window;
     out->seconds = best;
     out->default_seconds = first;
-    return agis_set_launch(ctx, 1, 0, best_c.grab, best_c.variant);
+    return agis_set_launch(ctx, 1, 0, best_c.grab, best_c.variant, best_c.window);
 }
 
 int agis_fixed_point_tables(int32_t* logtab, uint32_t* exp2tab) {

@@ -1001,7 +1001,7 @@ __device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int
 template <bool kDump>
 __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P,
                              uint32_t k0, uint32_t k1, uint64_t s, uint32_t* __restrict__ sv,
-                             int32_t* __restrict__ sl, Record* __restrict__ rec) {
+                             int32_t* __restrict__ sl, Record* __restrict__ rec, uint32_t hub_window) {
     const int lane = lane_id();
     const uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = P->pattern_id;
     const uint32_t k = P->k;
@@ -1204,7 +1204,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 uint32_t my_pos = 0;  // lane j: window start in backward list j
                 // lane j: bitmap row of backward vertex j when it is a hub
                 int32_t my_slot = -1;
-                if (t.hub_slot && (uint32_t)lane < i && (others >> lane & 1u)) my_slot = t.hub_slot[my_tau];
+                if (t.hub_slot && (uint32_t)lane < i && (others >> lane & 1u) &&
+                    (uint64_t)my_d * kWave >= (uint64_t)hub_window * db)
+                    my_slot = t.hub_slot[my_tau];
                 uint64_t cnt = 0;
                 // Software pipeline over the chunks: the next chunk's base
                 // elements are loaded one chunk ahead, and a chunk's weights
@@ -1388,6 +1390,7 @@ void k_sample(const LaunchDesc* __restrict__ D) {
     const uint32_t grab = D->grab;
     const DevGraph g = D->g;
     const DevTables t = D->t;
+    const uint32_t hub_window = D->hub_window;
     AGIS_GMEM double* xout = D->xout;
     uint32_t sg = 0;  // segment of the current slot (slots a wave takes only increase)
     unsigned long long cur = 0;
@@ -1403,7 +1406,8 @@ void k_sample(const LaunchDesc* __restrict__ D) {
             const uint64_t off = j - S.base;
             const uint64_t sidx = kDump ? D->idx[off] : S.start + off;
             Record* rec = kDump ? D->dump + j : nullptr;
-            const double xv = sample_one<kDump>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec);
+            const double xv =
+                sample_one<kDump>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec, hub_window);
             if (lane == 0) xout[j] = xv;
         }
         cur = uniform_u64(next);
@@ -1491,6 +1495,7 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
         budget = q < (8ull << 30) ? (8ull << 30) : (q > (64ull << 30) ? (64ull << 30) : q);
     }
     L->variant = ctx->tune_variant;
+    L->hub_window = ctx->tune_hub_window;
     int& cached = ctx->sample_blocks_per_cu[L->variant];
     if (cached == 0) {
         int nb = 0;
@@ -1568,7 +1573,7 @@ void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const 
     D->queue = gmem((unsigned long long*)((char*)ctx->d_small + 64));
     D->xout = gmem(ctx->d_xout);
     D->grab = L.grab;
-    D->pad = 0;
+    D->hub_window = L.hub_window;
 }
 
 hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L, hipEvent_t before,

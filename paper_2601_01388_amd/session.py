@@ -171,8 +171,8 @@ class Session:
         ce, ind, ci = agis_concentrations([make_pattern(p.k, p.adj8()) for p in pats], [r.copies for r in res])
         return {"patterns": pats, "results": res, "conc_edge": ce, "induced": ind, "conc_induced": ci}
 
-    def set_launch(self, use_graphs=True, blocks_per_cu=0, grab=0, variant=0):
-        agis_set_launch(self.ctx, use_graphs, blocks_per_cu, grab, variant)
+    def set_launch(self, use_graphs=True, blocks_per_cu=0, grab=0, variant=0, hub_window=0):
+        agis_set_launch(self.ctx, use_graphs, blocks_per_cu, grab, variant, hub_window)
 
     def dump(self, graph: Graph, tables: Tables, pattern, seed: int, indices, order=None, **kw) -> np.ndarray:
         torch = _torch()

@@ -101,7 +101,8 @@ def test_graph_replay_equals_direct_launches(sess, c1_state):
         assert other.n == 10_000
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 0), (2, 3, 0), (0, 16, 1), (0, 1, 2), (3, 0, 1), (0, 0, 2)])
+@pytest.mark.parametrize("shape", [(1, 1, 0), (2, 3, 0), (0, 16, 1), (0, 1, 2), (3, 0, 1), (0, 0, 2), (0, 0, 0, 1024),
+                                   (0, 4, 1, 1 << 30)])
 def test_launch_shape_invariance(sess, c1_state, shape):
     g, G, T, OT = c1_state
     p = synth.named_pattern("5-cycle")
@@ -109,7 +110,8 @@ def test_launch_shape_invariance(sess, c1_state, shape):
     ref = sess.estimate(G, T, p, 300_000, 9)
     refrec = sess.dump(G, T, p, 9, np.arange(2000, dtype=np.uint64))
     say(f"launch shape {shape}")
-    sess.set_launch(use_graphs=True, blocks_per_cu=shape[0], grab=shape[1], variant=shape[2])
+    sess.set_launch(use_graphs=True, blocks_per_cu=shape[0], grab=shape[1], variant=shape[2],
+                    hub_window=shape[3] if len(shape) > 3 else 0)
     got = sess.estimate(G, T, p, 300_000, 9)
     rec = sess.dump(G, T, p, 9, np.arange(2000, dtype=np.uint64))
     sess.set_launch(use_graphs=True)
