@@ -189,7 +189,7 @@ def large_legs(args, sess, G20, T20, pats_budgets, log):
             sess.device)
         per_epoch = max(1, -(-rows["rows"] // 4096))
         sess.mlp_train(params, f20, rows, epochs=max(20, -(-1500 // per_epoch)), batch=4096, lr=3e-3, seed=pid)
-        tabs = sess.learned_tables(params, f24, p, base=sess.step_log_weights(T, p))
+        tabs = sess.learned_tables(params, f24, p, base=sess.step_log_weights(T, p), rows=rows)
         ptrs = {i: tab.data_ptr() for i, tab in tabs.items()}
         rl = sess.estimate(G, T, p, args.large_eval_samples, 41, mode="learned", learned=ptrs, pattern_id=pid)
         ra = sess.estimate(G, T, p, args.large_eval_samples, 41, mode="switch", pattern_id=pid)
@@ -414,7 +414,7 @@ def main():
             train_s = time.perf_counter() - t0
             t0 = time.perf_counter()
             base_ev = sess.step_log_weights(T, p) if residual else None
-            tabs = sess.learned_tables(params, fev, p, base=base_ev)
+            tabs = sess.learned_tables(params, fev, p, base=base_ev, rows=rows)
             del base_ev
             torch.cuda.synchronize()
             infer_s = time.perf_counter() - t0
@@ -580,7 +580,7 @@ def main():
             concentration[f"k{k}"] = {
                 "patterns": len(res), "seconds": ct, "budget_per_pattern": args.conc_budget,
                 "converged": int(sum(r.converged for r in res)), "samples": int(sum(r.n for r in res)),
-                "per_pattern": [{"edges": [list(e) for e in p.edges], "copies": r.copies, "eps_hat": r.eps_hat,
+                "per_pattern": [{"edges": [list(e) for e in p[1]], "copies": r.copies, "eps_hat": r.eps_hat,
                                  "conc_edge": float(ce), "conc_induced": float(ci), "induced": float(ind)}
                                 for p, r, ce, ci, ind in zip(out["patterns"], res, out["conc_edge"],
                                                               out["conc_induced"], out["induced"])]}

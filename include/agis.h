@@ -322,6 +322,12 @@ int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint
 int agis_step1_weights(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
                        const uint8_t* order, const agis_run_params* params, uint32_t* q1, uint64_t* total);
 
+/* Every connected graph on k vertices (2 <= k <= 6) up to isomorphism --
+ * 1, 2, 6, 21 and 112 of them -- ordered by edge count, then by canonical
+ * adjacency code; the set agis_concentrations takes.  *count receives the
+ * number; out (host, cap entries) receives the patterns unless NULL. */
+int agis_connected_patterns(uint32_t k, agis_pattern* out, uint32_t cap, uint32_t* count);
+
 /* Concentrations of the connected k-vertex patterns (2 <= k <= 6), the
  * quantity the paper compares with MCMC estimators (Sec. 6.3, comparison
  * with MCMC): each pattern's count divided by the total over all
@@ -419,9 +425,12 @@ int agis_step_log_weights(agis_ctx* ctx, const agis_tables* t, uint32_t b, uint3
  * AGIS_MODE_LEARNED (certain zeros are still decided by degree at pick
  * time), or base[v] + round(2^16 y) when base (device int32[n], e.g. the
  * step's agis_step_log_weights) is given -- a learned correction of
- * f_approx; y: device float[n] or NULL. */
+ * f_approx; the output is first clamped to [y_min, y_max] (e.g. the range
+ * of the training targets, against extrapolation to unseen degrees;
+ * -INFINITY and INFINITY for none); y: device float[n] (the unclamped
+ * output) or NULL. */
 int agis_mlp_infer(agis_ctx* ctx, const float* params, const float* feats, uint64_t n, uint32_t position_class,
-                   const int32_t* base, int32_t* lt, float* y);
+                   const int32_t* base, float y_min, float y_max, int32_t* lt, float* y);
 
 /* Host copies of the library's Q16 tables (4096 entries each), its Philox
  * block function and its bounded draw -- for host-side tests. */

@@ -145,8 +145,10 @@ _SIGNATURES = [
     ("agis_mlp_grad", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_float, _P, _P]),
     ("agis_mlp_train", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_float, ctypes.c_uint64, _P]),
-    ("agis_mlp_infer", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, _P]),
+    ("agis_mlp_infer", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_float,
+                                      ctypes.c_float, _P, _P]),
     ("agis_concentrations", ctypes.c_int, [ctypes.c_uint32, _P, _P, _P, _P, _P]),
+    ("agis_connected_patterns", ctypes.c_int, [ctypes.c_uint32, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
     ("agis_step1_weights", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P,
                                           ctypes.POINTER(agis_run_params), _P, ctypes.POINTER(ctypes.c_uint64)]),
     ("agis_fixed_point_tables", ctypes.c_int, [_P, _P]),
@@ -350,9 +352,10 @@ def agis_mlp_train(ctx, params_ptr, feats_ptr, vtx_ptr, cls_ptr, target_ptr, wei
     return [float(x) for x in losses[:epochs]]
 
 
-def agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr=0, base_ptr=0):
-    _check(ctx, lib().agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, base_ptr or None, lt_ptr,
-                                     y_ptr or None))
+def agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, lt_ptr, y_ptr=0, base_ptr=0,
+                   y_min=float("-inf"), y_max=float("inf")):
+    _check(ctx, lib().agis_mlp_infer(ctx, params_ptr, feats_ptr, n, position_class, base_ptr or None, y_min, y_max,
+                                     lt_ptr, y_ptr or None))
 
 
 def agis_step1_weights(ctx, g, t, pattern: agis_pattern, params: agis_run_params, q1_ptr, order=None) -> int:
@@ -378,6 +381,15 @@ def agis_graph_export(ctx, g):
     _check(ctx, lib().agis_graph_export(ctx, g, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(off),
                                         ctypes.byref(nbr)))
     return int(n.value), int(nnz.value), off.value, nbr.value
+
+
+def agis_connected_patterns(k: int) -> list:
+    """Every connected k-vertex pattern up to isomorphism, as agis_pattern."""
+    cnt = ctypes.c_uint32()
+    _check(None, lib().agis_connected_patterns(k, None, 0, ctypes.byref(cnt)))
+    arr = (agis_pattern * max(cnt.value, 1))()
+    _check(None, lib().agis_connected_patterns(k, ctypes.cast(arr, _P), cnt.value, ctypes.byref(cnt)))
+    return [arr[i] for i in range(cnt.value)]
 
 
 def agis_concentrations(patterns, copies):

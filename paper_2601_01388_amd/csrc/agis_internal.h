@@ -76,6 +76,10 @@ namespace agis {
 int compile_plan(const agis_pattern* p, const uint8_t* order, int mode, int beta_num, int beta_den,
                  agis_plan* out, std::string* err);
 
+// Every connected graph on k vertices up to isomorphism (see
+// agis_connected_patterns).
+int connected_patterns(uint32_t k, agis_pattern* out, uint32_t cap, uint32_t* count, std::string* err);
+
 // Edge-induced and vertex-induced concentrations from copy counts of every
 // connected k-pattern (see agis_concentrations).
 int concentrations(uint32_t n, const agis_pattern* patterns, const double* copies, double* conc_edge, double* induced,

@@ -712,6 +712,12 @@ int agis_step1_weights(agis_ctx* ctx, const agis_graph* g, const agis_tables* t,
     return AGIS_OK;
 }
 
+int agis_connected_patterns(uint32_t k, agis_pattern* out, uint32_t cap, uint32_t* count) {
+    if (!count) return AGIS_E_INVALID_ARG;
+    std::string err;
+    return agis::connected_patterns(k, out, cap, count, &err);
+}
+
 int agis_concentrations(uint32_t n_patterns, const agis_pattern* patterns, const double* copies, double* conc_edge,
                         double* induced, double* conc_induced) {
     std::string err;

@@ -273,7 +273,8 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ params, const float* __restrict__ feats,
                                                    uint64_t n, uint32_t cls, const int32_t* __restrict__ base,
-                                                   int32_t* __restrict__ lt, float* __restrict__ yout) {
+                                                   float y_min, float y_max, int32_t* __restrict__ lt,
+                                                   float* __restrict__ yout) {
     const int lane = lane_id();
     const int col = lane & 31;   // m for A, n for B and D
     const int half = lane >> 5;  // which 8-wide slice of each K step
@@ -327,9 +328,11 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ par
             const int m = 8 * (col / 4) + 4 * half + (col % 4);
             const uint64_t r = tile * 32 + (uint64_t)m;
             if (r < n) {
-                // clamped to +-2^13 (also maps NaN to a finite value) so the
-                // Q16 code and the residual sum stay inside int32
-                const int32_t q = (int32_t)rintf(fminf(fmaxf(y, -8192.0f), 8192.0f) * 65536.0f);
+                // clamped to [y_min, y_max] and to +-2^13 (also maps NaN to a
+                // finite value) so the Q16 code and the residual sum stay
+                // inside int32
+                const float yc = fminf(fmaxf(fminf(fmaxf(y, y_min), y_max), -8192.0f), 8192.0f);
+                const int32_t q = (int32_t)rintf(yc * 65536.0f);
                 // residual tables: the network's output corrects the f_approx
                 // log weight; certain zeros stay marked
                 lt[r] = base ? (base[r] == kCertainZero ? kCertainZero : base[r] + q) : q;
@@ -583,14 +586,14 @@ int agis_step_log_weights(agis_ctx* ctx, const agis_tables* t, uint32_t b, uint3
 }
 
 int agis_mlp_infer(agis_ctx* ctx, const float* params, const float* feats, uint64_t n, uint32_t position_class,
-                   const int32_t* base, int32_t* lt, float* y) {
-    if (!ctx || !params || !feats || !lt || position_class > 3) return AGIS_E_INVALID_ARG;
+                   const int32_t* base, float y_min, float y_max, int32_t* lt, float* y) {
+    if (!ctx || !params || !feats || !lt || position_class > 3 || !(y_min <= y_max)) return AGIS_E_INVALID_ARG;
     LHIP(ctx, hipSetDevice(ctx->device), "set device");
     if (n == 0) return AGIS_OK;
     const uint64_t tiles = (n + 31) / 32;
     const uint64_t blocks = std::min<uint64_t>((tiles + 3) / 4, (uint64_t)ctx->num_cus * 8);
     hipLaunchKernelGGL(agis::k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, params, feats, n,
-                       position_class, base, lt, y);
+                       position_class, base, y_min, y_max, lt, y);
     LHIP(ctx, hipGetLastError(), "mlp inference");
     LHIP(ctx, hipStreamSynchronize(ctx->stream), "mlp inference");
     return AGIS_OK;

@@ -283,6 +283,43 @@ bool mask_connected(uint32_t mask, int k) {
 
 }  // namespace
 
+int connected_patterns(uint32_t k, agis_pattern* out, uint32_t cap, uint32_t* count, std::string* err) {
+    if (k < 2 || k > 6) {
+        *err = "connected patterns are enumerated for 2 <= k <= 6";
+        return AGIS_E_INVALID_ARG;
+    }
+    const int kk = (int)k;
+    const uint32_t npairs = (uint32_t)(kk * (kk - 1) / 2);
+    std::vector<uint32_t> codes;
+    for (uint32_t m = 0; m < (1u << npairs); ++m) {
+        if ((uint32_t)__builtin_popcount(m) < k - 1 || !mask_connected(m, kk)) continue;
+        const uint32_t c = canonical_code(m, kk);
+        if (c == m) codes.push_back(c);  // each class once, at its canonical mask
+    }
+    std::sort(codes.begin(), codes.end(), [](uint32_t a, uint32_t b) {
+        const int pa = __builtin_popcount(a), pb = __builtin_popcount(b);
+        return pa != pb ? pa < pb : a < b;
+    });
+    *count = (uint32_t)codes.size();
+    if (!out) return AGIS_OK;
+    if (cap < codes.size()) {
+        *err = "output array too small";
+        return AGIS_E_INVALID_ARG;
+    }
+    for (size_t i = 0; i < codes.size(); ++i) {
+        agis_pattern p{};
+        p.k = k;
+        for (int a = 0; a < kk; ++a)
+            for (int b = a + 1; b < kk; ++b)
+                if (codes[i] >> pair_index(a, b, kk) & 1u) {
+                    p.adj[a] |= (uint8_t)(1u << b);
+                    p.adj[b] |= (uint8_t)(1u << a);
+                }
+        out[i] = p;
+    }
+    return AGIS_OK;
+}
+
 int concentrations(uint32_t n, const agis_pattern* patterns, const double* copies, double* conc_edge, double* induced,
                    double* conc_induced, std::string* err) {
     if (n == 0 || !patterns || !copies) {

@@ -9,7 +9,8 @@ import ctypes
 import numpy as np
 
 from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, agis_build_proposal_tables,
-               agis_autotune, agis_compile_pattern, agis_concentrations, agis_step1_weights, agis_orient,
+               agis_autotune, agis_compile_pattern, agis_concentrations, agis_connected_patterns, agis_step1_weights,
+               agis_orient,
                agis_graph_export, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
                agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
                agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
@@ -157,19 +158,19 @@ class Session:
         return q1.cpu().numpy()[: graph.n].view(np.uint32).astype(np.int64), total
 
     def concentrations(self, graph: Graph, tables: Tables, k: int, budget: int, seed: int, **kw):
-        """Estimates every connected k-vertex pattern (batched launches of at
-        most 64 patterns) and returns their concentrations: edge-induced
-        (copies / total) and vertex-induced (agis_concentrations)."""
-        import synth
-        pats = synth.patterns.connected_patterns(k)
+        """Estimates every connected k-vertex pattern (agis_connected_patterns;
+        batched launches of at most 64 patterns) and returns their
+        concentrations: edge-induced (copies / total) and vertex-induced
+        (agis_concentrations).  patterns: (k, edges) per pattern."""
+        pats = agis_connected_patterns(k)
         res = []
         for lo in range(0, len(pats), 64):
             chunk = pats[lo:lo + 64]
-            kw2 = dict(kw)
-            kw2["pattern_id"] = kw.get("pattern_id", 0) + lo
-            res += self.estimate_batch(graph, tables, chunk, [budget] * len(chunk), seed, **kw2)
-        ce, ind, ci = agis_concentrations([make_pattern(p.k, p.adj8()) for p in pats], [r.copies for r in res])
-        return {"patterns": pats, "results": res, "conc_edge": ce, "induced": ind, "conc_induced": ci}
+            res += agis_estimate_batch(self.ctx, graph.handle, tables.handle, chunk, [int(budget)] * len(chunk), seed,
+                                       make_params(**dict(kw, pattern_id=kw.get("pattern_id", 0) + lo)))
+        ce, ind, ci = agis_concentrations(pats, [r.copies for r in res])
+        edges = [(p.k, [(a, b) for a in range(p.k) for b in range(a + 1, p.k) if p.adj[a] >> b & 1]) for p in pats]
+        return {"patterns": edges, "results": res, "conc_edge": ce, "induced": ind, "conc_induced": ci}
 
     def set_launch(self, use_graphs=True, blocks_per_cu=0, grab=0, variant=0, hub_window=0):
         agis_set_launch(self.ctx, use_graphs, blocks_per_cu, grab, variant, hub_window)
@@ -243,24 +244,37 @@ class Session:
                               rows["cls"].data_ptr(), rows["target"].data_ptr(), rows["weight"].data_ptr(),
                               rows["rows"], epochs, batch, lr, seed)
 
-    def mlp_infer(self, params, feats, position_class: int, want_y: bool = False, base=None):
+    def mlp_infer(self, params, feats, position_class: int, want_y: bool = False, base=None, y_range=None):
         torch = _torch()
         n = feats.shape[0]
         lt = torch.zeros(n, dtype=torch.int32, device=self.device)
         y = torch.zeros(n, dtype=torch.float32, device=self.device) if want_y else None
+        lo, hi = y_range if y_range is not None else (float("-inf"), float("inf"))
         agis_mlp_infer(self.ctx, params.data_ptr(), feats.data_ptr(), n, position_class, lt.data_ptr(),
-                       y.data_ptr() if want_y else 0, base.data_ptr() if base is not None else 0)
+                       y.data_ptr() if want_y else 0, base.data_ptr() if base is not None else 0, lo, hi)
         return (lt, y) if want_y else lt
 
     def weighted_steps(self, pattern, mode="switch"):
         plan = agis_compile_pattern(make_pattern(pattern.k, pattern.adj8()), params=make_params(mode=mode))
         return [i for i in range(pattern.k) if plan.decision[i] and plan.f1[i] > 0]
 
-    def learned_tables(self, params, feats, pattern, base=None):
+    def learned_tables(self, params, feats, pattern, base=None, rows=None):
         """Q16 pick table per weighted step (position class min(i, 3)); with
-        base (from step_log_weights) the network's output corrects f_approx."""
-        return {i: self.mlp_infer(params, feats, min(i, 3), base=None if base is None else base[i])
-                for i in self.weighted_steps(pattern, "learned")}
+        base (from step_log_weights) the network's output corrects f_approx;
+        with rows (the training rows) the output is clamped, per class, to
+        the range of the training targets."""
+        ranges = {}
+        if rows is not None and rows["rows"]:
+            cls = rows["cls"].cpu().numpy()
+            tg = rows["target"].cpu().numpy()
+            for c in np.unique(cls):
+                ranges[int(c)] = (float(tg[cls == c].min()), float(tg[cls == c].max()))
+        out = {}
+        for i in self.weighted_steps(pattern, "learned"):
+            c = min(i, 3)
+            out[i] = self.mlp_infer(params, feats, c, base=None if base is None else base[i],
+                                    y_range=ranges.get(c) if rows is not None else None)
+        return out
 
     def close(self):
         if self.ctx:

@@ -124,6 +124,12 @@ def test_residual_rows_and_inference(sess, small):
         cz = b == np.iinfo(np.int32).min
         exp = np.where(cz, b, b + q)
         assert np.array_equal(lt.cpu().numpy().astype(np.int64), exp)
+        # clamped to a range: the same with y limited to it
+        yy = y.cpu().numpy()
+        lo, hi = float(np.quantile(yy, 0.2)), float(np.quantile(yy, 0.8))
+        ltc = sess.mlp_infer(params, feats, min(i, 3), base=base[i], y_range=(lo, hi))
+        qc = np.rint(np.clip(yy, np.float32(lo), np.float32(hi)) * np.float32(65536.0)).astype(np.int64)
+        assert np.array_equal(ltc.cpu().numpy().astype(np.int64), np.where(cz, b, b + qc))
 
 
 def _rows_for(sess, G, T, p, n_samples=40_000, seed=5):

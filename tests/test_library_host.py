@@ -144,3 +144,26 @@ def test_library_concentrations_rejects_incomplete_sets():
         A.agis_concentrations(ps[:-1], [1.0] * 5)  # the 4-clique is missing
     with pytest.raises(A.AgisError):
         A.agis_concentrations(ps + [ps[0]], [1.0] * 7)  # duplicate
+
+
+def test_library_connected_patterns_are_the_isomorphism_classes():
+    """agis_connected_patterns against an independent enumeration (the
+    oracle's canonical forms of every connected graph on k vertices)."""
+    from oracle import concentration as conc
+    import itertools
+    for k, count in ((2, 1), (3, 2), (4, 6), (5, 21)):
+        got = A.agis_connected_patterns(k)
+        assert len(got) == count
+        codes = set()
+        for p in got:
+            edges = [(a, b) for a in range(k) for b in range(a + 1, k) if p.adj[a] >> b & 1]
+            codes.add(conc._canon(k, edges))
+        ref = set()
+        pairs = list(itertools.combinations(range(k), 2))
+        for m in range(1 << len(pairs)):
+            e = [pairs[j] for j in range(len(pairs)) if m >> j & 1]
+            if synth.Pattern(k=k, edges=tuple(e)).is_connected():
+                ref.add(conc._canon(k, e))
+        assert codes == ref
+        sizes = [sum(bin(p.adj[a]).count("1") for a in range(k)) // 2 for p in got]
+        assert sizes == sorted(sizes)
