@@ -629,6 +629,13 @@ def main():
         "time_to_1pct": eps_table,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "paper_context": {
+            "hardware": "AMD Ryzen Threadripper PRO 7985WX, 48 cores (C++/OpenMP, one sampler per thread)",
+            "graphs": "real graphs (LiveJournal to GSH-2015), eps = 0.1, delta = 0.01",
+            "geomean_speedup_vs_scalegpm": 28.5,
+            "geomean_speedup_vs_peregrine": 63108,
+            "note": "context only: the paper reports no samples/s and no GPU figure",
+        },
     }
     print(json.dumps(out), flush=True)
     T.close()
