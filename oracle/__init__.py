@@ -264,7 +264,6 @@ class Sampler:
         self.plan = make_plan(compiled, pattern_id, terms, oriented)
         self.seed = seed
         self._learned = learned
-        k = compiled["k"]
         if learned is not None:
             self._lt_arrays = [None if learned.get(i) is None else np.ascontiguousarray(learned[i], dtype=np.int32)
                                for i in range(MAXK)]
@@ -282,7 +281,6 @@ class Sampler:
                 lt0 = _p(self._lt_arrays[0])
             self.Q1 = int(lib().orc_step1_table(self._graph_struct(), self._tables_struct(), ctypes.byref(self.plan),
                                                lt0, _p(self.q1), _p(self.pre1)))
-        del k
 
     def _graph_struct(self):
         class G(ctypes.Structure):
