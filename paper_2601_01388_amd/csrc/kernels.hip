@@ -761,11 +761,18 @@ hipError_t launch_orient_offsets(agis_ctx* ctx, const DevGraph& g, uint32_t* out
 // ---------------------------------------------------------------------------
 // Hub neighbourhood bitmaps
 // ---------------------------------------------------------------------------
-__global__ void k_degree_histogram(DevGraph g, uint32_t* hist) {
+// per-block histogram in LDS, then one global atomic per nonzero bucket
+__global__ __launch_bounds__(256) void k_degree_histogram(DevGraph g, uint32_t* hist) {
+    __shared__ uint32_t h[64];
+    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __syncthreads();
     const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.n) return;
-    const uint64_t d = g.off[v + 1] - g.off[v];
-    if (d) atomicAdd(&hist[63 - __builtin_clzll(d)], 1u);
+    if (v < g.n) {
+        const uint64_t d = g.off[v + 1] - g.off[v];
+        if (d) atomicAdd(&h[63 - __builtin_clzll(d)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
 hipError_t launch_degree_histogram(const DevGraph& g, uint32_t* hist, hipStream_t stream) {

@@ -62,40 +62,152 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Features: one wave per vertex (grid-stride).  The h-index of the
-// neighbour degrees -- the largest h with at least h neighbours of degree
-// >= h, an upper bound of the core number -- is found by bisection over h
-// with a wave-wide count per probe.
+// Features.  The h-index of the neighbour degrees -- the largest h with at
+// least h neighbours of degree >= h, an upper bound of the core number --
+// is found per vertex from a histogram of the neighbour degrees capped at
+// the vertex's own degree d (h <= d).
+//
+// k_features: each wave takes 64 consecutive vertices.  The neighbour lists
+// of those with d <= kLaneDeg are gathered by the whole wave as one
+// concatenated list (element e belongs to the lane whose exclusive prefix
+// of degrees is the last one <= e), so the loads are independent; each such
+// lane then scans its histogram column from h = d down.  Vertices of larger
+// degree go to a list for k_features_big.
+//
+// k_features_big: one workgroup per listed vertex narrows [lo, hi] (lo
+// always feasible) by 256-bucket histograms of the degrees >= lo: bucket b
+// holds degrees in [lo + b w, lo + (b + 1) w) with w a power of two, the
+// last bucket also everything above; suffix sums give the count of degrees
+// >= lo + b w, and the feasible thresholds form a prefix of the buckets.
+// Three passes cover any degree below 2^24.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_features(DevGraph g, const uint4* __restrict__ rec,
-                                                  const uint64_t* __restrict__ s2, const uint64_t* __restrict__ hits,
-                                                  const uint64_t* __restrict__ trials, float* __restrict__ feats) {
+constexpr uint32_t kLaneDeg = 32;
+constexpr int kFeatThreads = 256;
+constexpr int kFeatWaves = kFeatThreads / kWave;
+
+__device__ __forceinline__ void write_features(float* __restrict__ feats, uint64_t v, uint32_t d, uint64_t s2,
+                                               uint64_t hits, uint64_t trials, uint32_t hidx) {
+    const double tri = trials ? (double)hits / (double)trials * 0.5 * (double)d * (double)(d - 1) : 0.0;
+    float* f = feats + v * 4;
+    f[0] = (float)log2(1.0 + (double)d);
+    f[1] = (float)log2(1.0 + (double)s2);
+    f[2] = (float)log2(1.0 + tri);
+    f[3] = (float)log2(1.0 + (double)hidx);
+}
+
+__global__ __launch_bounds__(kFeatThreads) void k_features(DevGraph g, const uint4* __restrict__ rec,
+                                                           const uint64_t* __restrict__ s2,
+                                                           const uint64_t* __restrict__ hits,
+                                                           const uint64_t* __restrict__ trials,
+                                                           float* __restrict__ feats, uint32_t* __restrict__ big,
+                                                           uint32_t* __restrict__ nbig) {
+    // histogram bin b of lane l of wave w: hist[w][b][l], bins 0..kLaneDeg
+    __shared__ uint32_t hist[kFeatWaves][kLaneDeg + 1][kWave];
+    __shared__ uint32_t s_excl[kFeatWaves][kWave];
+    __shared__ uint32_t s_deg[kFeatWaves][kWave];
+    __shared__ uint64_t s_off[kFeatWaves][kWave];
     const int lane = lane_id();
-    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
-    for (uint64_t v = gw; v < g.n; v += nw) {
+    const int wib = (int)threadIdx.x / kWave;
+    const uint64_t groups = (g.n + kWave - 1) / kWave;
+    // all waves of a workgroup run the same iterations (workgroup barriers)
+    for (uint64_t gb = (uint64_t)blockIdx.x * kFeatWaves; gb < groups; gb += (uint64_t)gridDim.x * kFeatWaves) {
+        const uint64_t v = (gb + (uint64_t)wib) * kWave + (uint64_t)lane;
+        const bool have = v < g.n;
+        uint64_t o = 0;
+        uint32_t d = 0;
+        if (have) {
+            o = g.off[v];
+            d = (uint32_t)(g.off[v + 1] - o);
+        }
+        const bool small = have && d <= kLaneDeg;
+        const uint32_t ds = small ? d : 0u;
+        uint32_t incl = ds;
+#pragma unroll
+        for (int sh = 1; sh < kWave; sh <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, sh, kWave);
+            if (lane >= sh) incl += t;
+        }
+        const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        s_excl[wib][lane] = incl - ds;
+        s_deg[wib][lane] = d;
+        s_off[wib][lane] = o;
+        for (uint32_t b = 0; b <= kLaneDeg; ++b) hist[wib][b][lane] = 0;
+        __syncthreads();
+        for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
+            // owner: the last lane whose exclusive prefix is <= e
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                if (s_excl[wib][lo + step] <= e) lo += step;
+            const uint32_t od = s_deg[wib][lo];
+            const uint32_t nd = rec[g.nbr[s_off[wib][lo] + (e - s_excl[wib][lo])]].x;
+            atomicAdd(&hist[wib][nd < od ? nd : od][lo], 1u);
+        }
+        __syncthreads();
+        if (small) {
+            uint32_t h = d, at_least = 0;
+            for (; h > 0; --h) {
+                at_least += hist[wib][h][lane];
+                if (at_least >= h) break;
+            }
+            write_features(feats, v, d, s2[v], hits[v], trials[v], h);
+        }
+        const uint64_t bm = __ballot(have && !small);
+        if (bm) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(nbig, (uint32_t)__popcll(bm));
+            base = (uint32_t)__shfl((int)base, 0, kWave);
+            if (have && !small) big[base + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)v;
+        }
+        __syncthreads();  // the LDS of this iteration is rewritten by the next
+    }
+}
+
+__global__ __launch_bounds__(kFeatThreads) void k_features_big(DevGraph g, const uint4* __restrict__ rec,
+                                                               const uint64_t* __restrict__ s2,
+                                                               const uint64_t* __restrict__ hits,
+                                                               const uint64_t* __restrict__ trials,
+                                                               float* __restrict__ feats,
+                                                               const uint32_t* __restrict__ big,
+                                                               const uint32_t* __restrict__ nbig) {
+    __shared__ uint32_t cnt[kFeatThreads];
+    const uint32_t m = *nbig;
+    const int t = (int)threadIdx.x;
+    for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
+        const uint64_t v = big[i];
         const uint64_t o = g.off[v];
         const uint32_t d = (uint32_t)(g.off[v + 1] - o);
-        uint32_t lo = 0, hi = d;  // h in [lo, hi]
+        uint32_t lo = 0, hi = d;  // the h-index is in [lo, hi]; lo is feasible
         while (lo < hi) {
-            const uint32_t h = (lo + hi + 1) >> 1;
-            uint32_t c = 0;
-            for (uint32_t e = (uint32_t)lane; e < d; e += kWave) c += rec[g.nbr[o + e]].x >= h ? 1u : 0u;
-#pragma unroll
-            for (int s = 32; s > 0; s >>= 1) c += __shfl_xor(c, s, kWave);
-            if (c >= h)
-                lo = h;
-            else
-                hi = h - 1;
+            const uint64_t span = (uint64_t)hi - lo + 1;
+            uint32_t sh = 0;
+            while (((uint64_t)kFeatThreads << sh) < (uint64_t)span) ++sh;
+            cnt[t] = 0;
+            __syncthreads();
+            for (uint32_t e = (uint32_t)t; e < d; e += kFeatThreads) {
+                const uint32_t x = rec[g.nbr[o + e]].x;
+                if (x >= lo) {
+                    const uint32_t b = (x - lo) >> sh;
+                    atomicAdd(&cnt[b < (uint32_t)kFeatThreads ? b : (uint32_t)kFeatThreads - 1u], 1u);
+                }
+            }
+            __syncthreads();
+            // suffix sums: cnt[b] becomes the number of degrees >= lo + b w
+            for (int step = 1; step < kFeatThreads; step <<= 1) {
+                const uint32_t add = t + step < kFeatThreads ? cnt[t + step] : 0u;
+                __syncthreads();
+                cnt[t] += add;
+                __syncthreads();
+            }
+            const uint64_t thr = (uint64_t)lo + ((uint64_t)t << sh);
+            const int ok = thr <= hi && (uint64_t)cnt[t] >= thr;
+            const int nok = __syncthreads_count(ok);
+            const uint32_t nlo = lo + ((uint32_t)(nok - 1) << sh);
+            hi = (uint32_t)min<uint64_t>((uint64_t)hi, (uint64_t)nlo + (1ull << sh) - 1ull);
+            lo = nlo;
         }
-        if (lane == 0) {
-            const double tri = trials[v] ? (double)hits[v] / (double)trials[v] * 0.5 * (double)d * (double)(d - 1) : 0.0;
-            float* f = feats + v * 4;
-            f[0] = (float)log2(1.0 + (double)d);
-            f[1] = (float)log2(1.0 + (double)s2[v]);
-            f[2] = (float)log2(1.0 + tri);
-            f[3] = (float)log2(1.0 + (double)lo);
-        }
+        if (t == 0) write_features(feats, v, d, s2[v], hits[v], trials[v], lo);
+        __syncthreads();
     }
 }
 
@@ -125,18 +237,28 @@ __global__ void k_targets(const Record* __restrict__ recs, uint64_t m, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Training: per tile of 64 rows (one wave), forward and backward in FP32;
-// the tile's parameter gradient is summed over its rows in row order and
-// written to its own slot; k_mlp_reduce adds the slots in tile order, so
-// the gradient does not depend on scheduling.
+// Training: per tile of 64 rows, forward and backward in FP32 by a workgroup
+// of four waves: lane r of every wave holds row r, and wave q computes the
+// hidden units 16 q .. 16 q + 15 of both layers.  The tile's parameter
+// gradient is summed over its rows in row order and written to its own
+// slot; k_mlp_reduce adds the slots in tile order, so the gradient does not
+// depend on scheduling.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 64;
+constexpr int kGradWaves = 4;
+constexpr int kGradThreads = kTile * kGradWaves;
+constexpr int kUnitsPerWave = kH / kGradWaves;
+static_assert(kH == kTile, "the bias and w3 sums give unit r to lane r");
 
-__global__ __launch_bounds__(kTile) void k_mlp_grad(const float* __restrict__ params, const float* __restrict__ feats,
-                                                    const uint32_t* __restrict__ vtx, const uint8_t* __restrict__ cls,
-                                                    const float* __restrict__ target, const float* __restrict__ weight,
-                                                    const uint32_t* __restrict__ order, uint64_t rows, float inv_wsum,
-                                                    float* __restrict__ partial, float* __restrict__ loss_part) {
+__global__ __launch_bounds__(kGradThreads) void k_mlp_grad(const float* __restrict__ params,
+                                                           const float* __restrict__ feats,
+                                                           const uint32_t* __restrict__ vtx,
+                                                           const uint8_t* __restrict__ cls,
+                                                           const float* __restrict__ target,
+                                                           const float* __restrict__ weight,
+                                                           const uint32_t* __restrict__ order, uint64_t rows,
+                                                           float inv_wsum, float* __restrict__ partial,
+                                                           float* __restrict__ loss_part) {
     // activations are stored [unit][row] with one padding column so that both
     // per-row (forward) and per-unit (gradient) walks avoid bank conflicts
     constexpr int kLd = kTile + 1;
@@ -146,10 +268,15 @@ __global__ __launch_bounds__(kTile) void k_mlp_grad(const float* __restrict__ pa
     __shared__ float G1[kH][kLd];  // GELU'(layer-1 pre-activation), later dL/d(pre1)
     __shared__ float H2[kH][kLd];
     __shared__ float D2[kH][kLd];  // dL/d(pre2)
+    __shared__ float YP[kGradWaves][kTile];
     __shared__ float DY[kTile];
+    __shared__ float LS[kTile];
     const int t = threadIdx.x;
-    for (int p = t; p < kMlpParams; p += kTile) P[p] = params[p];
-    const uint64_t rix = (uint64_t)blockIdx.x * kTile + (uint64_t)t;
+    const int r = t % kTile;
+    const int q = t / kTile;  // wave-uniform
+    const int j0 = q * kUnitsPerWave;
+    for (int p = t; p < kMlpParams; p += kGradThreads) P[p] = params[p];
+    const uint64_t rix = (uint64_t)blockIdx.x * kTile + (uint64_t)r;
     float w = 0.0f, tgt = 0.0f;
     float x[kIn];
     for (int c = 0; c < kIn; ++c) x[c] = 0.0f;
@@ -161,101 +288,103 @@ __global__ __launch_bounds__(kTile) void k_mlp_grad(const float* __restrict__ pa
         w = weight[ri];
         tgt = target[ri];
     }
-    for (int c = 0; c < kIn; ++c) X[c][t] = x[c];
+    if (q == 0)
+        for (int c = 0; c < kIn; ++c) X[c][r] = x[c];
     __syncthreads();
-    // forward
-    for (int j = 0; j < kH; ++j) {
+    // forward, layer 1 (this wave's units)
+    for (int j = j0; j < j0 + kUnitsPerWave; ++j) {
         float a = P[kOffB1 + j];
         for (int c = 0; c < kIn; ++c) a += P[kOffW1 + j * kIn + c] * x[c];
-        H1[j][t] = gelu(a);
-        G1[j][t] = gelu_grad(a);
+        H1[j][r] = gelu(a);
+        G1[j][r] = gelu_grad(a);
     }
-    float y = P[kOffB3];
-    for (int j = 0; j < kH; ++j) {
+    __syncthreads();
+    // layer 2 and this wave's share of the output
+    float yp = 0.0f;
+    for (int j = j0; j < j0 + kUnitsPerWave; ++j) {
         float a = P[kOffB2 + j];
-        for (int i = 0; i < kH; ++i) a += P[kOffW2 + j * kH + i] * H1[i][t];
+        for (int i = 0; i < kH; ++i) a += P[kOffW2 + j * kH + i] * H1[i][r];
         const float h2 = gelu(a);
-        H2[j][t] = h2;
-        D2[j][t] = gelu_grad(a);  // completed below once dy is known
-        y += P[kOffW3 + j] * h2;
+        H2[j][r] = h2;
+        D2[j][r] = gelu_grad(a);  // completed below once dy is known
+        yp += P[kOffW3 + j] * h2;
     }
+    YP[q][r] = yp;
+    __syncthreads();
+    float y = P[kOffB3];
+    for (int qq = 0; qq < kGradWaves; ++qq) y += YP[qq][r];
     const float err = y - tgt;
     const float dy = 2.0f * w * err * inv_wsum;
-    DY[t] = dy;
-    for (int j = 0; j < kH; ++j) D2[j][t] *= dy * P[kOffW3 + j];
-    for (int i = 0; i < kH; ++i) {
-        float s = 0.0f;
-        for (int j = 0; j < kH; ++j) s += P[kOffW2 + j * kH + i] * D2[j][t];
-        G1[i][t] *= s;  // dL/d(pre1)
+    if (q == 0) {
+        DY[r] = dy;
+        LS[r] = w * err * err * inv_wsum;  // loss of the row (weighted squared error / total weight)
+    }
+    for (int j = j0; j < j0 + kUnitsPerWave; ++j) D2[j][r] *= dy * P[kOffW3 + j];
+    __syncthreads();
+    // back to layer 1 (this wave's units)
+    for (int i = j0; i < j0 + kUnitsPerWave; ++i) {
+        float sacc = 0.0f;
+        for (int j = 0; j < kH; ++j) sacc += P[kOffW2 + j * kH + i] * D2[j][r];
+        G1[i][r] *= sacc;  // dL/d(pre1)
     }
     __syncthreads();
     // parameter gradients of the tile, each a sum over its 64 rows in order
     float* out = partial + (uint64_t)blockIdx.x * kMlpParams;
-    for (int p = t; p < kH * kH; p += kTile) {
+    for (int p = t; p < kH * kH; p += kGradThreads) {
         const int j = p / kH, i = p % kH;
-        float s = 0.0f;
-        for (int r = 0; r < kTile; ++r) s += D2[j][r] * H1[i][r];
-        out[kOffW2 + p] = s;
+        float sacc = 0.0f;
+        for (int rr = 0; rr < kTile; ++rr) sacc += D2[j][rr] * H1[i][rr];
+        out[kOffW2 + p] = sacc;
     }
-    for (int p = t; p < kH * kIn; p += kTile) {
+    for (int p = t; p < kH * kIn; p += kGradThreads) {
         const int j = p / kIn, c = p % kIn;
-        float s = 0.0f;
-        for (int r = 0; r < kTile; ++r) s += G1[j][r] * X[c][r];
-        out[kOffW1 + p] = s;
+        float sacc = 0.0f;
+        for (int rr = 0; rr < kTile; ++rr) sacc += G1[j][rr] * X[c][rr];
+        out[kOffW1 + p] = sacc;
     }
-    {
-        const int j = t;
-        float sb1 = 0.0f, sb2 = 0.0f, sw3 = 0.0f;
-        for (int r = 0; r < kTile; ++r) {
-            sb1 += G1[j][r];
-            sb2 += D2[j][r];
-            sw3 += DY[r] * H2[j][r];
-        }
-        out[kOffB1 + j] = sb1;
-        out[kOffB2 + j] = sb2;
-        out[kOffW3 + j] = sw3;
-    }
-    if (t == 0) {
-        float sb3 = 0.0f;
-        for (int r = 0; r < kTile; ++r) sb3 += DY[r];
-        out[kOffB3] = sb3;
-    }
-    // loss of the tile (weighted squared error / total weight), row order
-    __syncthreads();
-    DY[t] = w * err * err * inv_wsum;
-    __syncthreads();
-    if (t == 0) {
-        float l = 0.0f;
-        for (int r = 0; r < kTile; ++r) l += DY[r];
-        loss_part[blockIdx.x] = l;
+    if (q < 3) {
+        // wave 0: b1, wave 1: b2, wave 2: w3 (unit r)
+        float sacc = 0.0f;
+        for (int rr = 0; rr < kTile; ++rr)
+            sacc += q == 0 ? G1[r][rr] : q == 1 ? D2[r][rr] : DY[rr] * H2[r][rr];
+        out[(q == 0 ? kOffB1 : q == 1 ? kOffB2 : kOffW3) + r] = sacc;
+    } else if (r < 2) {
+        // wave 3: b3 and the tile's loss
+        float sacc = 0.0f;
+        for (int rr = 0; rr < kTile; ++rr) sacc += r == 0 ? DY[rr] : LS[rr];
+        if (r == 0)
+            out[kOffB3] = sacc;
+        else
+            loss_part[blockIdx.x] = sacc;
     }
 }
 
+// Sum of the tiles' gradient slots in tile order; with m1 set, also the
+// Adam update of the parameters (bias corrections c1 = 1 - b1^t, c2 =
+// 1 - b2^t).
 __global__ void k_mlp_reduce(const float* __restrict__ partial, uint64_t tiles, const float* __restrict__ loss_part,
-                             float* __restrict__ grad, float* __restrict__ loss) {
+                             float* __restrict__ grad, float* __restrict__ loss, float* __restrict__ params,
+                             float* __restrict__ m1, float* __restrict__ m2, float lr, float b1, float b2, float eps,
+                             float c1, float c2) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < kMlpParams) {
         float s = 0.0f;
+#pragma unroll 8
         for (uint64_t b = 0; b < tiles; ++b) s += partial[b * kMlpParams + p];
-        grad[p] = s;
+        if (grad) grad[p] = s;
+        if (m1) {
+            const float a = b1 * m1[p] + (1.0f - b1) * s;
+            const float bb = b2 * m2[p] + (1.0f - b2) * s * s;
+            m1[p] = a;
+            m2[p] = bb;
+            params[p] -= lr * (a / c1) / (sqrtf(bb / c2) + eps);
+        }
     }
     if (p == kMlpParams && loss) {
         float s = 0.0f;
         for (uint64_t b = 0; b < tiles; ++b) s += loss_part[b];
         *loss = s;
     }
-}
-
-__global__ void k_adam(float* __restrict__ params, const float* __restrict__ grad, float* __restrict__ m1,
-                       float* __restrict__ m2, float lr, float b1, float b2, float eps, float c1, float c2) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kMlpParams) return;
-    const float g = grad[p];
-    const float a = b1 * m1[p] + (1.0f - b1) * g;
-    const float b = b2 * m2[p] + (1.0f - b2) * g * g;
-    m1[p] = a;
-    m2[p] = b;
-    params[p] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,38 +407,54 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ par
     const int lane = lane_id();
     const int col = lane & 31;   // m for A, n for B and D
     const int half = lane >> 5;  // which 8-wide slice of each K step
-    // B operand (W2 transposed), constant across row tiles
-    bf16x8 bw[2][4];
-    for (int nt = 0; nt < 2; ++nt)
-        for (int kc = 0; kc < 4; ++kc)
-            for (int j = 0; j < 8; ++j)
-                bw[nt][kc][j] = (__bf16)params[kOffW2 + (nt * 32 + col) * kH + kc * 16 + half * 8 + j];
+    // B operand (W2 transposed) in LDS, in the order lanes read it: slice
+    // (nt, kc) of lane l is s_w2[(nt * 4 + kc) * 64 + l]
+    __shared__ bf16x8 s_w2[2 * 4 * kWave];
+    for (int i = (int)threadIdx.x; i < 2 * 4 * kWave; i += (int)blockDim.x) {
+        const int l = i % kWave, nt = i / (4 * kWave), kc = (i / kWave) % 4;
+        bf16x8 v;
+        for (int j = 0; j < 8; ++j)
+            v[j] = (__bf16)params[kOffW2 + (nt * 32 + (l & 31)) * kH + kc * 16 + (l >> 5) * 8 + j];
+        s_w2[i] = v;
+    }
     const float b2n[2] = {params[kOffB2 + col], params[kOffB2 + 32 + col]};
     const float w3n[2] = {params[kOffW3 + col], params[kOffW3 + 32 + col]};
     const float b3 = params[kOffB3];
+    // layer 1 weights in LDS, per hidden unit: the bias plus the weight of
+    // this position class's one-hot input, then the four feature weights
+    __shared__ float s_l1[kH * 5];
+    const uint32_t cc = cls < 3 ? cls : 3;
+    for (int h = (int)threadIdx.x; h < kH; h += (int)blockDim.x) {
+        s_l1[h * 5] = params[kOffB1 + h] + params[kOffW1 + h * kIn + 4 + (int)cc];
+        for (int c = 0; c < 4; ++c) s_l1[h * 5 + 1 + c] = params[kOffW1 + h * kIn + c];
+    }
+    __syncthreads();
     const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
     const uint64_t tiles = (n + 31) / 32;
     for (uint64_t tile = gw; tile < tiles; tile += nw) {
         const uint64_t row = tile * 32 + (uint64_t)col;
-        float x[kIn];
-        for (int c = 0; c < kIn; ++c) x[c] = 0.0f;
+        float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (row < n)
             for (int c = 0; c < 4; ++c) x[c] = feats[row * 4 + c];
-        x[4 + (cls < 3 ? cls : 3)] = 1.0f;
-        // layer 1: this lane's 32 of the row's 64 hidden units, as bf16 A slices
+        // layer 1: this lane's 32 of the row's 64 hidden units, as bf16 A
+        // slices.  The weights are read from LDS in every tile: an opaque
+        // zero offset keeps the compiler from hoisting all 160 of them into
+        // registers, which would cut occupancy.
+        int w0 = half * 8 * 5;
+        asm volatile("" : "+v"(w0));
         bf16x8 a[4];
         for (int kc = 0; kc < 4; ++kc)
             for (int j = 0; j < 8; ++j) {
-                const int h = kc * 16 + half * 8 + j;
-                float s = params[kOffB1 + h];
-                for (int c = 0; c < kIn; ++c) s += params[kOffW1 + h * kIn + c] * x[c];
+                const float* wl = s_l1 + w0 + (kc * 16 + j) * 5;
+                float s = wl[0];
+                for (int c = 0; c < 4; ++c) s += wl[1 + c] * x[c];
                 a[kc][j] = (__bf16)gelu(s);
             }
         f32x16 acc0 = {}, acc1 = {};
         for (int kc = 0; kc < 4; ++kc) {
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kc], bw[0][kc], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kc], bw[1][kc], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kc], s_w2[kc * kWave + lane], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kc], s_w2[(4 + kc) * kWave + lane], acc1, 0, 0, 0);
         }
         // layer 3: contribution of this lane's two output columns to each of
         // its 16 rows, summed over the 32 lanes of the half
@@ -374,11 +519,28 @@ int agis_features(agis_ctx* ctx, const agis_tables* t, float* feats) {
     LHIP(ctx, hipSetDevice(ctx->device), "set device");
     const agis::DevGraph& g = t->graph->g;
     if (g.n == 0) return AGIS_OK;
-    const uint64_t blocks = std::min<uint64_t>((g.n + 3) / 4, (uint64_t)ctx->num_cus * 32);
-    hipLaunchKernelGGL(agis::k_features, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, g, t->rec, t->s2, t->hits,
-                       t->trials, feats);
-    LHIP(ctx, hipGetLastError(), "features");
-    LHIP(ctx, hipStreamSynchronize(ctx->stream), "features");
+    if (g.n > UINT32_MAX) return lfail(ctx, AGIS_E_INVALID_ARG, "features: more than 2^32 - 1 vertices");
+    // list of the vertices of degree above the per-lane limit, and its length
+    uint32_t* big = nullptr;
+    LHIP(ctx, hipMalloc(&big, (size_t)(g.n + 1) * sizeof(uint32_t)), "allocate feature list");
+    uint32_t* nbig = big + g.n;
+    hipError_t e = hipMemsetAsync(nbig, 0, sizeof(uint32_t), ctx->stream);
+    const uint64_t groups = (g.n + 63) / 64;
+    const uint64_t blocks = std::min<uint64_t>((groups + agis::kFeatWaves - 1) / agis::kFeatWaves,
+                                               (uint64_t)ctx->num_cus * 8);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(agis::k_features, dim3((unsigned)blocks), dim3(agis::kFeatThreads), 0, ctx->stream, g,
+                           t->rec, t->s2, t->hits, t->trials, feats, big, nbig);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(agis::k_features_big, dim3((unsigned)ctx->num_cus * 4), dim3(agis::kFeatThreads), 0,
+                           ctx->stream, g, t->rec, t->s2, t->hits, t->trials, feats, big, nbig);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(big);
+    LHIP(ctx, e, "features");
     return AGIS_OK;
 }
 
@@ -497,10 +659,10 @@ int agis_mlp_grad(agis_ctx* ctx, const float* params, const float* feats, const 
     LHIP(ctx, hipMalloc(&partial, tiles * kMlpParams * sizeof(float)), "allocate gradient partials");
     hipError_t e = hipMalloc(&lpart, tiles * sizeof(float));
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(agis::k_mlp_grad, dim3((unsigned)tiles), dim3(agis::kTile), 0, ctx->stream, params, feats,
-                           vtx, cls, target, weight, nullptr, rows, 1.0f / weight_sum, partial, lpart);
+        hipLaunchKernelGGL(agis::k_mlp_grad, dim3((unsigned)tiles), dim3(agis::kGradThreads), 0, ctx->stream, params,
+                           feats, vtx, cls, target, weight, nullptr, rows, 1.0f / weight_sum, partial, lpart);
         hipLaunchKernelGGL(agis::k_mlp_reduce, dim3(grid1(kMlpParams + 1, 256)), dim3(256), 0, ctx->stream, partial,
-                           tiles, lpart, grad, loss);
+                           tiles, lpart, grad, loss, nullptr, nullptr, nullptr, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     }
@@ -521,11 +683,10 @@ int agis_mlp_train(agis_ctx* ctx, float* params, const float* feats, const uint3
     const uint64_t tiles = (bt + agis::kTile - 1) / agis::kTile;
     std::vector<float> w(rows);
     LHIP(ctx, hipMemcpy(w.data(), weight, rows * sizeof(float), hipMemcpyDeviceToHost), "read weights");
-    float *partial = nullptr, *lpart = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr, *loss = nullptr;
+    float *partial = nullptr, *lpart = nullptr, *m1 = nullptr, *m2 = nullptr, *loss = nullptr;
     uint32_t* order = nullptr;
     hipError_t e = hipMalloc(&partial, tiles * kMlpParams * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&lpart, tiles * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&grad, kMlpParams * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&m1, kMlpParams * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&m2, kMlpParams * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&loss, sizeof(float));
@@ -547,14 +708,13 @@ int agis_mlp_train(agis_ctx* ctx, float* params, const float* feats, const uint3
             for (uint64_t i = 0; i < cnt; ++i) ws += w[perm[s0 + i]];
             if (!(ws > 0)) continue;
             const uint64_t tl = (cnt + agis::kTile - 1) / agis::kTile;
-            hipLaunchKernelGGL(agis::k_mlp_grad, dim3((unsigned)tl), dim3(agis::kTile), 0, ctx->stream, params, feats,
-                               vtx, cls, target, weight, order + s0, cnt, (float)(1.0 / ws), partial, lpart);
-            hipLaunchKernelGGL(agis::k_mlp_reduce, dim3(grid1(kMlpParams + 1, 256)), dim3(256), 0, ctx->stream,
-                               partial, tl, lpart, grad, loss);
+            hipLaunchKernelGGL(agis::k_mlp_grad, dim3((unsigned)tl), dim3(agis::kGradThreads), 0, ctx->stream, params,
+                               feats, vtx, cls, target, weight, order + s0, cnt, (float)(1.0 / ws), partial, lpart);
             ++step;
             const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
-            hipLaunchKernelGGL(agis::k_adam, dim3(grid1(kMlpParams, 256)), dim3(256), 0, ctx->stream, params, grad, m1,
-                               m2, lr, b1, b2, eps, c1, c2);
+            hipLaunchKernelGGL(agis::k_mlp_reduce, dim3(grid1(kMlpParams + 1, 256)), dim3(256), 0, ctx->stream,
+                               partial, tl, lpart, nullptr, loss_per_epoch ? loss : nullptr, params, m1, m2, lr, b1,
+                               b2, eps, c1, c2);
             e = hipGetLastError();
             if (loss_per_epoch) {
                 float l = 0.0f;
@@ -570,7 +730,7 @@ int agis_mlp_train(agis_ctx* ctx, float* params, const float* feats, const uint3
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    for (void* q : {(void*)partial, (void*)lpart, (void*)grad, (void*)m1, (void*)m2, (void*)loss, (void*)order})
+    for (void* q : {(void*)partial, (void*)lpart, (void*)m1, (void*)m2, (void*)loss, (void*)order})
         if (q) (void)hipFree(q);
     LHIP(ctx, e, "mlp training");
     return AGIS_OK;
