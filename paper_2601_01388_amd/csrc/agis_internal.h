@@ -126,13 +126,11 @@ hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg,
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
                        uint32_t* q1, uint64_t* pre, uint64_t* total);
 
-// Per-row pick table (one inclusive u64 prefix over all CSR slots, read per row
-// relative to the entry before the row) of a weighted
-// step with one backward vertex and signature (b, f1, ie, f2) or learned
-// log weights lt.
-// rowmax: n int32 of scratch for the row maxima.
-hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const uint4* rec, uint32_t b, uint32_t f1, uint32_t ie,
-                         uint32_t f2, const int32_t* lt, uint64_t* pre, int32_t* rowmax);
+// Per-row pick table (per CSR slot, the inclusive u64 prefix of the integer
+// weights within the slot's row) of a weighted step with one backward vertex
+// whose per-vertex log weights (launch_step_log_weights) are sw.
+// lists: 2 n + 2 uint32 of scratch (the lists of longer rows and their lengths).
+hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const int32_t* sw, uint64_t* pre, uint32_t* lists);
 
 struct SampleLaunch {
     int blocks = 0;

@@ -94,33 +94,40 @@ struct Prepared {
     double scale = 1.0;  // embeddings per unit of the sample mean (k! on an oriented graph)
     uint32_t* q1 = nullptr;
     uint64_t* pre = nullptr;
-    std::vector<uint64_t*> rowtabs;
-    int32_t* rowmax = nullptr;
     double tables_seconds = 0;
     ~Prepared() {
         if (q1) (void)hipFree(q1);
         if (pre) (void)hipFree(pre);
-        if (rowmax) (void)hipFree(rowmax);
-        for (uint64_t* r : rowtabs) (void)hipFree(r);
     }
 };
 
-// Per-vertex log weights of the weighted steps that build candidate sets,
-// shared by the patterns of one call: one table per (b, f1, ie, f2, learned
-// table).  A candidate's weight is then one 4-byte read instead of a 16-byte
-// record and the arithmetic.  Steps beyond the budget use the records.
+// Tables shared by the patterns of one call, one per (b, f1, ie, f2,
+// learned table):
+//  - per-vertex log weights of the weighted steps that build candidate
+//    sets: a candidate's weight is then one 4-byte read instead of a 16-byte
+//    record and the arithmetic (steps beyond the budget use the records);
+//  - per-row pick tables of the weighted steps with one backward vertex.
 struct StepTables {
     struct Entry {
         uint32_t b, f1, ie, f2;
         const int32_t* lt;
         int32_t* buf;
     };
+    struct RowEntry {
+        uint32_t b, f1, ie, f2;
+        const int32_t* lt;
+        uint64_t* buf;
+    };
     std::vector<Entry> e;
+    std::vector<RowEntry> rows;
+    uint32_t* long_rows = nullptr;  // scratch of the row-table build (lists of longer rows)
     StepTables() = default;
     StepTables(const StepTables&) = delete;
     StepTables& operator=(const StepTables&) = delete;
     ~StepTables() {
         for (Entry& x : e) (void)hipFree(x.buf);
+        for (RowEntry& x : rows) (void)hipFree(x.buf);
+        if (long_rows) (void)hipFree(long_rows);
     }
 };
 constexpr uint64_t kStepTableBudgetBytes = 16ull << 30;
@@ -129,7 +136,7 @@ constexpr uint64_t kStepTableBudgetBytes = 16ull << 30;
 // (AUTO): their build streams every CSR slot once, which a short run does
 // not amortise.
 constexpr uint64_t kRowtabMinSamples = 65536;
-constexpr uint64_t kRowtabBudgetBytes = 32ull << 30;
+constexpr uint64_t kRowtabBudgetBytes = 48ull << 30;
 
 // Neighbourhood bitmaps of the highest-degree vertices (degree >= 64, as
 // many as fit in kHubBitmapBudget, the degree threshold a power of two):
@@ -222,37 +229,49 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         }
     }
     const auto t0 = std::chrono::steady_clock::now();
+    // per-vertex log weights of step i (shared by the call), nullptr beyond
+    // the budget
+    int step_rc = AGIS_OK;
+    auto step_table = [&](uint32_t i) -> const int32_t* {
+        for (const StepTables::Entry& e : st->e)
+            if (e.b == hp.b[i] && e.f1 == hp.f1[i] && e.ie == hp.ie[i] && e.f2 == hp.f2[i] && e.lt == hp.lt[i])
+                return e.buf;
+        if ((st->e.size() + 1) * g->g.n * sizeof(int32_t) > kStepTableBudgetBytes) return nullptr;
+        int32_t* buf = nullptr;
+        hipError_t e = hipMalloc(&buf, g->g.n * sizeof(int32_t));
+        if (e == hipSuccess) {
+            st->e.push_back(StepTables::Entry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
+            e = agis::launch_step_log_weights(*t, g->g.n, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
+                                              ctx->stream);
+        }
+        if (e != hipSuccess) {
+            step_rc = fail(ctx, e == hipErrorOutOfMemory ? AGIS_E_OOM : AGIS_E_HIP,
+                           std::string("step weight table: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        return buf;
+    };
     // per-row pick tables for weighted steps with one backward vertex
     bool want_rows = params->flags == AGIS_RUN_ROWTAB_ON ||
                      (params->flags == AGIS_RUN_ROWTAB_AUTO && n_samples >= kRowtabMinSamples);
-    int32_t* rowmax = nullptr;
     if (want_rows && g->g.nnz > 0) {
-        struct Key {
-            uint32_t b, f1, ie, f2;
-            const int32_t* lt;
-            uint64_t* buf;
-        };
-        std::vector<Key> built;
         for (uint32_t i = 1; i < hp.k; ++i) {
             if (!hp.weighted[i] || __builtin_popcount(hp.bmask[i]) != 1) continue;
+            const int32_t* lt = (const int32_t*)hp.lt[i];
             uint64_t* buf = nullptr;
-            for (const Key& k : built)
-                if (k.b == hp.b[i] && k.f1 == hp.f1[i] && k.ie == hp.ie[i] && k.f2 == hp.f2[i] &&
-                    k.lt == (const int32_t*)hp.lt[i])
-                    buf = k.buf;
+            for (const StepTables::RowEntry& r : st->rows)
+                if (r.b == hp.b[i] && r.f1 == hp.f1[i] && r.ie == hp.ie[i] && r.f2 == hp.f2[i] && r.lt == lt)
+                    buf = r.buf;
             if (!buf) {
-                if ((built.size() + 1) * g->g.nnz * sizeof(uint64_t) > kRowtabBudgetBytes) continue;
+                if ((st->rows.size() + 1) * g->g.nnz * sizeof(uint64_t) > kRowtabBudgetBytes) continue;
+                const int32_t* sw = step_table(i);
+                if (step_rc != AGIS_OK) return step_rc;
+                if (!sw) continue;
+                if (!st->long_rows)
+                    AGIS_HIP(ctx, hipMalloc(&st->long_rows, (2 * g->g.n + 2) * sizeof(uint32_t)), "allocate row lists");
                 AGIS_HIP(ctx, hipMalloc(&buf, g->g.nnz * sizeof(uint64_t)), "allocate row pick table");
-                out->rowtabs.push_back(buf);
-                if (!rowmax) {
-                    AGIS_HIP(ctx, hipMalloc(&rowmax, g->g.n * sizeof(int32_t)), "allocate row maxima");
-                    out->rowmax = rowmax;
-                }
-                AGIS_HIP(ctx,
-                         agis::launch_rowtab(ctx, g->g, t->rec, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
-                                             rowmax),
-                         "row pick table");
-                built.push_back(Key{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], (const int32_t*)hp.lt[i], buf});
+                st->rows.push_back(StepTables::RowEntry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], lt, buf});
+                AGIS_HIP(ctx, agis::launch_rowtab(ctx, g->g, sw, buf, st->long_rows), "row pick table");
             }
             hp.rowpre[i] = agis::gmem((const uint64_t*)buf);
         }
@@ -268,20 +287,9 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         hp.reuse[i] = (general(i) && general(i - 1) && (hp.bmask[i - 1] & ~hp.bmask[i]) == 0) ? 1 : 0;
     for (uint32_t i = 1; i < hp.k && g->g.n > 0; ++i) {
         if (!hp.weighted[i] || hp.rowpre[i] != nullptr) continue;
-        int32_t* buf = nullptr;
-        for (const StepTables::Entry& e : st->e)
-            if (e.b == hp.b[i] && e.f1 == hp.f1[i] && e.ie == hp.ie[i] && e.f2 == hp.f2[i] && e.lt == hp.lt[i])
-                buf = e.buf;
-        if (!buf) {
-            if ((st->e.size() + 1) * g->g.n * sizeof(int32_t) > kStepTableBudgetBytes) continue;
-            AGIS_HIP(ctx, hipMalloc(&buf, g->g.n * sizeof(int32_t)), "allocate step weight table");
-            st->e.push_back(StepTables::Entry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
-            AGIS_HIP(ctx,
-                     agis::launch_step_log_weights(*t, g->g.n, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
-                                                   ctx->stream),
-                     "step weight table");
-        }
-        hp.sw[i] = agis::gmem((const int32_t*)buf);
+        const int32_t* buf = step_table(i);
+        if (step_rc != AGIS_OK) return step_rc;
+        if (buf) hp.sw[i] = agis::gmem(buf);
     }
     if (hp.weighted[0] && g->g.n > 0) {
         AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");

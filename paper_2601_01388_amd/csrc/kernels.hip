@@ -177,16 +177,14 @@ __device__ __forceinline__ uint32_t row_of_slot(const uint64_t* __restrict__ off
 
 // Wave-cooperative 64-ary search: first index p in [0, n) with a[p] > r,
 // given a non-decreasing and a[n - 1] > r.  Every lane returns the answer.
-// Comparisons are of a[p] - base (modulo 2^64), so a prefix may be read
-// relative to the entry before its segment.
-__device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r, uint64_t base = 0) {
+__device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r) {
     const int lane = lane_id();
-    uint64_t lo = 0, hi = n - 1;  // answer in [lo, hi], a[hi] - base > r
+    uint64_t lo = 0, hi = n - 1;  // answer in [lo, hi], a[hi] > r
     while (hi - lo + 1 > (uint64_t)kWave) {
         const uint64_t step = (hi - lo + kWave) >> 6;
         const uint64_t p = lo + (uint64_t)lane * step;
         const bool valid = p <= hi;
-        const bool pred = valid && a[p] - base > r;
+        const bool pred = valid && a[p] > r;
         const uint64_t m = __ballot(pred);
         if (m == 0) {
             const uint64_t vm = __ballot(valid);
@@ -200,7 +198,7 @@ __device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restric
         }
     }
     const uint64_t p = lo + (uint64_t)lane;
-    const bool pred = p <= hi && a[p] - base > r;
+    const bool pred = p <= hi && a[p] > r;
     const uint64_t m = __ballot(pred);
     return lo + (uint64_t)(__ffsll((unsigned long long)m) - 1);
 }
@@ -873,116 +871,215 @@ hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t,
 // Per-row pick tables of a weighted step with one backward vertex w: its
 // candidates are N(w) minus matched vertices, and the normalising maximum is
 // taken over N(w), so every slot's integer weight depends on its row alone.
-// The table is one inclusive 64-bit prefix over all CSR slots of these
-// weights; a row's own prefix is read relative to the entry before the row
-// (differences are exact modulo 2^64).  Built flat over slots, so hub rows
-// spread over many waves: (1) log weight per slot, parked with its row id
-// in the output, and wave-combined atomic row maxima; (2) tile sums of the
-// integer weights; (3) scan of the tile sums; (4) the prefix.
+// The table holds, per CSR slot, the inclusive prefix of these weights
+// within the slot's row (64-bit).  The log weights come from the step's
+// per-vertex table sw (4 bytes per neighbour instead of its 16-byte record);
+// these gathers, one cache line per slot, dominate the traffic.  Three
+// kernels by row length, none with workgroup barriers on the common path:
+//  - k_rowtab_short: one lane per row of degree <= kRowtabLane, the row's
+//    log weights held in registers; longer rows are listed;
+//  - k_rowtab_mid: one wave per listed row of degree <= kRowtabWaveRow, the
+//    row's log weights in registers (slot u * 64 + lane in lane's entry u),
+//    a wave scan per 64 slots;
+//  - k_rowtab_long: one workgroup per longer row, which parks each slot's
+//    log weight in the low half of its table entry, takes the row maximum,
+//    then overwrites the entries with the prefix, 4096 slots per piece.
 // ---------------------------------------------------------------------------
 __global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_rowtab_log(DevGraph g, const uint4* __restrict__ rec, uint32_t b,
-                                                     uint32_t f1, uint32_t ie, uint32_t f2,
-                                                     const int32_t* __restrict__ lt, uint64_t* __restrict__ park,
-                                                     int32_t* __restrict__ rowmax) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = e < g.nnz;
-    uint32_t w = 0xFFFFFFFFu;
-    int32_t l = kCertainZero;
-    if (active) {
-        w = row_of_slot(g.off, g.n, e);
-        const uint32_t x = g.nbr[e];
-        const uint4 r = rec[x];
-        if (r.x >= b + f1) l = lt ? lt[x] : approx_log_weight(r, b, f1, ie, f2);
-        park[e] = ((uint64_t)w << 32) | (uint64_t)(uint32_t)l;
-    }
-    int head;
-    bool tail;
-    wave_segments(w, head, tail);
-    const int32_t m = wave_segmented_max_i32(l, head);
-    if (active && tail && m != kCertainZero) atomicMax(&rowmax[w], m);
+constexpr uint32_t kRowtabLane = 16;
+constexpr uint32_t kRowtabPerLane = 16;
+constexpr uint32_t kRowtabWaveRow = kWave * kRowtabPerLane;
+constexpr int kRowtabThreads = 256;
+constexpr int kRowtabWaves = kRowtabThreads / kWave;
+constexpr int kRowtabBigItems = 16;
+constexpr int kRowtabUnroll = 8;
+
+__device__ __forceinline__ uint32_t rowtab_q(int32_t lmax, int32_t l) {
+    return l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
 }
 
-__device__ __forceinline__ uint32_t rowtab_weight(uint64_t parked, const int32_t* __restrict__ rowmax) {
-    const int32_t l = (int32_t)(uint32_t)parked;
-    return l == kCertainZero ? 0u : weight_from_log(rowmax[(uint32_t)(parked >> 32)], l, c_exp2tab);
+// Appends the rows of this wave whose `take` is set to list (length in *len).
+__device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t* __restrict__ list,
+                                            uint32_t* __restrict__ len) {
+    const uint64_t bm = __ballot(take);
+    if (!bm) return;
+    uint32_t at = 0;
+    if (lane_id() == 0) at = atomicAdd(len, (uint32_t)__popcll(bm));
+    at = (uint32_t)__shfl((int)at, 0, kWave);
+    if (take) list[at + (uint32_t)__popcll(bm & lanemask_lt())] = v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_rowtab_tilesum(const uint64_t* __restrict__ park, uint64_t nnz,
-                                                                  const int32_t* __restrict__ rowmax,
-                                                                  uint64_t* __restrict__ tile_sums) {
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-    uint64_t s = 0;
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint64_t e = base + (uint64_t)j * kScanThreads + threadIdx.x;
-        if (e < nnz) s += rowtab_weight(park[e], rowmax);
-    }
-    s = wave_sum_u64(s);
-    __shared__ uint64_t ws[kScanThreads / kWave];
-    if (lane_id() == 0) ws[threadIdx.x / kWave] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int w = 0; w < kScanThreads / kWave; ++w) t += ws[w];
-        tile_sums[blockIdx.x] = t;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_rowtab_final(uint64_t* __restrict__ pre, uint64_t nnz,
-                                                                const int32_t* __restrict__ rowmax,
-                                                                const uint64_t* __restrict__ tile_offs) {
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-    uint32_t q[kScanItems];
-    uint64_t s = 0;
+__global__ __launch_bounds__(kRowtabThreads) void k_rowtab_short(DevGraph g, const int32_t* __restrict__ sw,
+                                                                  uint64_t* __restrict__ pre,
+                                                                  uint32_t* __restrict__ mid,
+                                                                  uint32_t* __restrict__ long_rows,
+                                                                  uint32_t* __restrict__ counts) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // whole waves iterate together (the lists are appended wave by wave)
+    const uint64_t n_up = (g.n + kWave - 1) / kWave * kWave;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_up; v += stride) {
+        const bool have = v < g.n;
+        uint64_t o = 0;
+        uint32_t d = 0;
+        if (have) {
+            o = g.off[v];
+            d = (uint32_t)(g.off[v + 1] - o);
+        }
+        if (have && d <= kRowtabLane) {
+            uint32_t x[kRowtabLane];
+            int32_t l[kRowtabLane];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint64_t e = base + j;
-        q[j] = e < nnz ? rowtab_weight(pre[e], rowmax) : 0u;
-        s += q[j];
-    }
-    const uint64_t incl = wave_incl_scan_u64(s);
-    __shared__ uint64_t wsum[kScanThreads / kWave];
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == kWave - 1) wsum[w] = incl;
-    __syncthreads();
-    uint64_t wbase = 0;
-    for (int j = 0; j < w; ++j) wbase += wsum[j];
-    uint64_t run = tile_offs[blockIdx.x] + wbase + incl - s;
+            for (uint32_t j = 0; j < kRowtabLane; ++j) x[j] = j < d ? g.nbr[o + j] : 0u;
+            int32_t lmax = kCertainZero;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint64_t e = base + j;
-        if (e < nnz) {
-            run += q[j];
-            pre[e] = run;
+            for (uint32_t j = 0; j < kRowtabLane; ++j) {
+                l[j] = j < d ? sw[x[j]] : kCertainZero;
+                lmax = l[j] > lmax ? l[j] : lmax;
+            }
+            uint64_t run = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < kRowtabLane; ++j)
+                if (j < d) {
+                    run += rowtab_q(lmax, l[j]);
+                    pre[o + j] = run;
+                }
+        }
+        wave_append(have && d > kRowtabLane && d <= kRowtabWaveRow, (uint32_t)v, mid, counts);
+        wave_append(have && d > kRowtabWaveRow, (uint32_t)v, long_rows, counts + 1);
+    }
+}
+
+__global__ __launch_bounds__(kRowtabThreads) void k_rowtab_mid(DevGraph g, const int32_t* __restrict__ sw,
+                                                                uint64_t* __restrict__ pre,
+                                                                const uint32_t* __restrict__ mid,
+                                                                const uint32_t* __restrict__ counts) {
+    const int lane = lane_id();
+    const uint32_t m = counts[0];
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t i = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < m; i += nw) {
+        const uint64_t v = mid[i];
+        const uint64_t o = g.off[v];
+        const uint32_t d = (uint32_t)(g.off[v + 1] - o);
+        // slot u * 64 + lane of the row in x[u], l[u]
+        uint32_t x[kRowtabPerLane];
+        int32_t l[kRowtabPerLane];
+#pragma unroll
+        for (uint32_t u = 0; u < kRowtabPerLane; ++u) {
+            const uint32_t e = u * kWave + (uint32_t)lane;
+            x[u] = e < d ? g.nbr[o + e] : 0u;
+        }
+        int32_t lm = kCertainZero;
+#pragma unroll
+        for (uint32_t u = 0; u < kRowtabPerLane; ++u) {
+            l[u] = u * kWave + (uint32_t)lane < d ? sw[x[u]] : kCertainZero;
+            lm = l[u] > lm ? l[u] : lm;
+        }
+        const int32_t lmax = wave_max_i32(lm);
+        uint64_t carry = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kRowtabPerLane; ++u) {
+            if (u * kWave >= d) break;
+            const uint32_t e = u * kWave + (uint32_t)lane;
+            const uint64_t q = e < d ? (uint64_t)rowtab_q(lmax, l[u]) : 0ull;
+            const uint64_t inc = wave_incl_scan_u64(q);
+            if (e < d) pre[o + e] = carry + inc;
+            carry += __shfl(inc, kWave - 1, kWave);
         }
     }
 }
 
-hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const uint4* rec, uint32_t b, uint32_t f1, uint32_t ie,
-                         uint32_t f2, const int32_t* lt, uint64_t* pre, int32_t* rowmax) {
+__global__ __launch_bounds__(kRowtabThreads) void k_rowtab_long(DevGraph g, const int32_t* __restrict__ sw,
+                                                                 uint64_t* __restrict__ pre,
+                                                                 const uint32_t* __restrict__ long_rows,
+                                                                 const uint32_t* __restrict__ counts) {
+    __shared__ int32_t s_wmax[kRowtabWaves];
+    __shared__ uint64_t s_wsum[kRowtabWaves];
+    int32_t* park = reinterpret_cast<int32_t*>(pre);  // low half of entry e: park[2 e]
+    const uint32_t m = counts[1];
+    const int t = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int wib = t / kWave;
+    constexpr uint32_t kPiece = kRowtabThreads * kRowtabBigItems;
+    for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
+        const uint64_t v = long_rows[i];
+        const uint64_t o = g.off[v];
+        const uint32_t d = (uint32_t)(g.off[v + 1] - o);
+        int32_t lm = kCertainZero;
+        for (uint32_t e0 = 0; e0 < d; e0 += kRowtabThreads * kRowtabUnroll) {
+            uint32_t x[kRowtabUnroll];
+            int32_t l[kRowtabUnroll];
+#pragma unroll
+            for (int u = 0; u < kRowtabUnroll; ++u) {
+                const uint32_t e = e0 + (uint32_t)(u * kRowtabThreads + t);
+                x[u] = e < d ? g.nbr[o + e] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowtabUnroll; ++u)
+                l[u] = e0 + (uint32_t)(u * kRowtabThreads + t) < d ? sw[x[u]] : kCertainZero;
+#pragma unroll
+            for (int u = 0; u < kRowtabUnroll; ++u) {
+                const uint32_t e = e0 + (uint32_t)(u * kRowtabThreads + t);
+                if (e < d) park[2 * (o + e)] = l[u];
+                lm = l[u] > lm ? l[u] : lm;
+            }
+        }
+        lm = wave_max_i32(lm);
+        if (lane == 0) s_wmax[wib] = lm;
+        __syncthreads();
+        int32_t lmax = s_wmax[0];
+        for (int w = 1; w < kRowtabWaves; ++w) lmax = s_wmax[w] > lmax ? s_wmax[w] : lmax;
+        // pieces of kPiece slots, kRowtabBigItems consecutive ones per thread
+        uint64_t carry = 0;
+        for (uint32_t p0 = 0; p0 < d; p0 += kPiece) {
+            const uint32_t e0 = p0 + (uint32_t)t * kRowtabBigItems;
+            uint64_t q[kRowtabBigItems];
+            uint64_t s = 0;
+#pragma unroll
+            for (int j = 0; j < kRowtabBigItems; ++j) {
+                q[j] = e0 + j < d ? rowtab_q(lmax, park[2 * (o + e0 + j)]) : 0ull;
+                s += q[j];
+            }
+            const uint64_t inc = wave_incl_scan_u64(s);
+            if (lane == kWave - 1) s_wsum[wib] = inc;
+            __syncthreads();
+            uint64_t run = carry + inc - s;
+            uint64_t piece = 0;
+            for (int w = 0; w < kRowtabWaves; ++w) {
+                if (w < wib) run += s_wsum[w];
+                piece += s_wsum[w];
+            }
+#pragma unroll
+            for (int j = 0; j < kRowtabBigItems; ++j) {
+                run += q[j];
+                if (e0 + j < d) pre[o + e0 + j] = run;
+            }
+            carry += piece;
+            __syncthreads();  // s_wsum (and s_wmax) are rewritten next
+        }
+    }
+}
+
+hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const int32_t* sw, uint64_t* pre, uint32_t* lists) {
     if (!g.n || !g.nnz) return hipSuccess;
     hipStream_t st = ctx->stream;
-    const uint64_t ntiles = (g.nnz + kScanTile - 1) / kScanTile;
-    if (ctx->blocksums_cap < ntiles) {
-        if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
-        ctx->d_blocksums = nullptr;
-        ctx->blocksums_cap = 0;
-        hipError_t e = hipMalloc(&ctx->d_blocksums, ntiles * sizeof(uint64_t));
-        if (e != hipSuccess) return e;
-        ctx->blocksums_cap = ntiles;
-    }
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(g.n, 256)), dim3(256), 0, st, rowmax, g.n, kCertainZero);
-    hipLaunchKernelGGL(k_rowtab_log, dim3(grid_for(g.nnz, 256)), dim3(256), 0, st, g, rec, b, f1, ie, f2, lt, pre,
-                       rowmax);
-    hipLaunchKernelGGL(k_rowtab_tilesum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, pre, g.nnz, rowmax,
-                       ctx->d_blocksums);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, ctx->d_blocksums, ntiles);
-    hipLaunchKernelGGL(k_rowtab_final, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, pre, g.nnz, rowmax,
-                       ctx->d_blocksums);
+    // lists: the mid-length rows from the front, the long rows from n on
+    // (a row is in at most one), their two lengths at 2 n
+    uint32_t* mid = lists;
+    uint32_t* long_rows = lists + g.n;
+    uint32_t* counts = lists + 2 * g.n;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t*>(counts), 2, 0);
+    const uint64_t waves = (g.n + kWave - 1) / kWave;
+    const uint64_t blocks = std::min<uint64_t>((waves + kRowtabWaves - 1) / kRowtabWaves, (uint64_t)ctx->num_cus * 8);
+    hipLaunchKernelGGL(k_rowtab_short, dim3((unsigned)blocks), dim3(kRowtabThreads), 0, st, g, sw, pre, mid,
+                       long_rows, counts);
+    hipLaunchKernelGGL(k_rowtab_mid, dim3((unsigned)ctx->num_cus * 8), dim3(kRowtabThreads), 0, st, g, sw, pre, mid,
+                       counts);
+    hipLaunchKernelGGL(k_rowtab_long, dim3((unsigned)ctx->num_cus * 8), dim3(kRowtabThreads), 0, st, g, sw, pre,
+                       long_rows, counts);
     return hipGetLastError();
 }
 
@@ -1062,9 +1159,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint64_t o = g.off[w];
                 const uint32_t d = (uint32_t)(g.off[w + 1] - o);
                 const uint32_t* list = g.nbr + o;
-                const AGIS_GMEM uint64_t* rp = P->rowpre[i];
-                const uint64_t* pre = rp + o;  // global prefix; row-relative below
-                const uint64_t base = o > 0 ? rp[o - 1] : 0ull;
+                const uint64_t* pre = P->rowpre[i] + o;  // the row's own inclusive prefix
                 uint32_t pos = 0xFFFFFFFFu;
                 bool found = false;
                 uint64_t qx = 0;
@@ -1077,9 +1172,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         pos = lower_bound_u32(list, d, my_tau);
                         found = pos < d && list[pos] == my_tau;
                     }
-                    if (found) qx = pre[pos] - (pos > 0 ? pre[pos - 1] : base);
+                    if (found) qx = pre[pos] - (pos > 0 ? pre[pos - 1] : 0ull);
                 }
-                const uint64_t qrow = d ? pre[d - 1] - base : 0ull;
+                const uint64_t qrow = d ? pre[d - 1] : 0ull;
                 const uint64_t Q = qrow - wave_sum_u64(qx);
                 if (Q == 0) {
                     fail = (int)i;
@@ -1099,21 +1194,21 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     }
                     const int L = (int)(key & 0xFF);
                     const uint32_t e = (uint32_t)(key >> 8);
-                    const uint64_t before = e > 0 ? pre[e - 1] - base : 0ull;
+                    const uint64_t before = e > 0 ? pre[e - 1] : 0ull;
                     if (before - shift > r) {
-                        ans = seg + wave_first_greater(pre + seg, e - seg, r + shift, base);
+                        ans = seg + wave_first_greater(pre + seg, e - seg, r + shift);
                         break;
                     }
                     shift += readlane_u64(qx, L);
                     seg = e + 1;
                     left &= ~(1ull << L);
                 }
-                if (ans == ~0ull) ans = seg + wave_first_greater(pre + seg, d - seg, r + shift, base);
+                if (ans == ~0ull) ans = seg + wave_first_greater(pre + seg, d - seg, r + shift);
                 v = list[ans];
                 drawn_row = w;
                 drawn_pos = (uint32_t)ans;
                 num = Q;
-                den = pre[ans] - (ans > 0 ? pre[ans - 1] : base);
+                den = pre[ans] - (ans > 0 ? pre[ans - 1] : 0ull);
             } else if (!weighted && __builtin_popcount(bm) == 1) {
                 // Uniform draw from N(w) minus the matched vertices, without
                 // materialising the set: probe each matched vertex in N(w)
