@@ -85,6 +85,16 @@ def algorithmic_bytes(g, plan, recs) -> float:
     return total / max(len(recs), 1)
 
 
+def is_clique(p) -> bool:
+    return len(p.edges) == p.k * (p.k - 1) // 2
+
+
+class HostCSR:
+    def __init__(self, off, nbr):
+        self.off = off
+        self.nbr = nbr
+
+
 def cpu_baseline(g, seconds_target: float):
     """The oracle (single thread) on a bounded sample of the same workload:
     the same patterns and mode, equal sample counts per pattern."""
@@ -93,10 +103,18 @@ def cpu_baseline(g, seconds_target: float):
     import synth
     log("cpu baseline: oracle tables (setup, untimed)")
     t = oracle.Tables(g, cv_seed=1)
+    og = ot = None
     samplers = []
     for name in PATTERNS:
         p = synth.named_pattern(name)
-        samplers.append(oracle.Sampler(g, t, compile_pattern(p.k, p.edges, mode="switch"), seed=7))
+        cp = compile_pattern(p.k, p.edges, mode="switch")
+        if is_clique(p):
+            if og is None:
+                og = oracle.orient(g)
+                ot = oracle.Tables(og, cv_seed=1, adjacency=g)
+            samplers.append(oracle.Sampler(og, ot, cp, seed=7, oriented=True))
+        else:
+            samplers.append(oracle.Sampler(g, t, cp, seed=7))
     # calibrate on a few samples, then size the timed sample
     per = []
     for s in samplers:
@@ -114,8 +132,9 @@ def cpu_baseline(g, seconds_target: float):
         "unit": "samples/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"first {n_each} sample indices of each of {', '.join(PATTERNS)} (f_approx+switch, seed 7) "
-                  f"on the same R-MAT-20 graph, single-threaded C oracle, {el:.1f} s",
+        "sample": f"first {n_each} sample indices of each of {', '.join(PATTERNS)} (f_approx+switch, seed 7, "
+                  f"cliques on the degree-oriented graph) on the same R-MAT-20 graph, single-threaded C oracle, "
+                  f"{el:.1f} s",
         "host": platform.processor() or platform.machine(),
         "host_threads_available": os.cpu_count(),
     }
@@ -301,32 +320,76 @@ def main():
     log(f"graph n={g.n} nnz={g.nnz} dmax={int(np.diff(g.off).max())}; tables {tables_s * 1e3:.1f} ms")
 
     pats = [synth.named_pattern(n) for n in PATTERNS]
+    # cliques run on the degree-oriented graph, as the method does for them
+    # (Sec. 5.4); it is built once per graph with its tables, like the
+    # symmetric graph's tables (preprocessing, outside the timed steps)
+    O = TO = None
+    orient_s = 0.0
+    if any(is_clique(p) for p in pats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        O = sess.orient(G)
+        TO = sess.tables(O, cv_seed=1)
+        torch.cuda.synchronize()
+        orient_s = time.perf_counter() - t0
+        log(f"degree-oriented graph for the cliques: nnz={O.nnz}, orientation and tables {orient_s * 1e3:.1f} ms")
+
+    def graph_of(p):
+        return (O, TO) if is_clique(p) else (G, T)
+
     tuning = None
     if not args.no_tune:
-        log("autotuning the sampler launch on the four patterns")
-        tun = sess.autotune(G, T, pats, args.tune_pilot, mode="switch")
+        # tuned on the patterns that run on the symmetric graph (the
+        # launch shape is one per context)
+        tpats = [p for p in pats if not is_clique(p)] or pats
+        log(f"autotuning the sampler launch on {len(tpats)} patterns")
+        tun = sess.autotune(G, T, tpats, args.tune_pilot, mode="switch")
         tuning = {"variant": tun.variant, "grab": tun.grab, "hub_window": tun.hub_window, "pilot_kernel_s": tun.seconds,
                   "default_kernel_s": tun.default_seconds}
         log(f"tuned: variant {tun.variant} grab {tun.grab} hub window {tun.hub_window} "
             f"({tun.default_seconds:.3f} s -> {tun.seconds:.3f} s)")
 
-    def step(seed):
+    def step(seed, walls=None):
         res = []
         for pid, p in enumerate(pats):
-            res.append(sess.estimate(G, T, p, args.samples, seed, mode="switch", pattern_id=pid))
+            t1 = time.perf_counter()
+            gg, tt = graph_of(p)
+            res.append(sess.estimate(gg, tt, p, args.samples, seed, mode="switch", pattern_id=pid))
+            if walls is not None:
+                walls[pid] += time.perf_counter() - t1
         return res
 
+    # the timed steps' clique estimates on the symmetric graph instead, for
+    # comparison (not the headline): their wall time replaces the oriented
+    # ones' (run first, so that the timed launches are the last ones)
+    sym_s = 0.0
+    if O is not None:
+        for pid, p in enumerate(pats):
+            if is_clique(p):
+                sess.estimate(G, T, p, args.samples, 999, mode="switch", pattern_id=pid)  # warmup
+        for k in range(args.steps):
+            for pid, p in enumerate(pats):
+                if is_clique(p):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    sess.estimate(G, T, p, args.samples, 7 + k, mode="switch", pattern_id=pid)
+                    sym_s += time.perf_counter() - t1
     for w in range(args.warmup):
         step(1000 + w)
         log(f"warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
+    walls = [0.0] * len(pats)
     for k in range(args.steps):
-        results.append(step(7 + k))
+        results.append(step(7 + k, walls))
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    value_symmetric = None
+    if O is not None:
+        clique_s = sum(w for w, p in zip(walls, pats) if is_clique(p))
+        value_symmetric = args.steps * len(pats) * args.samples / (elapsed - clique_s + sym_s)
     total_samples = args.steps * len(pats) * args.samples
     value = total_samples / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
@@ -336,21 +399,30 @@ def main():
     for pid, name in enumerate(PATTERNS):
         ks = sum(rs[pid].sample_kernel_seconds for rs in results)
         per_pattern[name] = {
+            "graph": "degree-oriented" if is_clique(pats[pid]) else "symmetric",
             "samples_per_s_kernel": args.steps * args.samples / ks,
             "estimate": results[-1][pid].estimate,
             "rel_var": results[-1][pid].variance / max(results[-1][pid].estimate ** 2, 1e-300),
             "tables_ms": 1e3 * results[-1][pid].tables_seconds,
         }
-    log(f"timed: {value:.4g} samples/s, {ms_per_step:.1f} ms/step")
+    log(f"timed: {value:.4g} samples/s, {ms_per_step:.1f} ms/step"
+        + (f"; cliques on the symmetric graph instead: {value_symmetric:.4g} samples/s" if value_symmetric else ""))
 
     # algorithmic bytes per sample, from dumped records of the timed stream
     log("algorithmic bytes from sampled records")
     bytes_per_sample = {}
     rng = np.random.Generator(np.random.PCG64(3))
     idx = np.sort(rng.integers(0, args.samples, size=args.bytes_records, dtype=np.uint64))
+    host_dag = None
     for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
-        recs = sess.dump(G, T, p, 7, idx, mode="switch", pattern_id=pid)
-        bytes_per_sample[name] = algorithmic_bytes(g, results[0][pid].plan, recs)
+        gg, tt = graph_of(p)
+        recs = sess.dump(gg, tt, p, 7, idx, mode="switch", pattern_id=pid)
+        hg = g
+        if gg is O:
+            if host_dag is None:
+                host_dag = HostCSR(*O.csr())
+            hg = host_dag
+        bytes_per_sample[name] = algorithmic_bytes(hg, results[0][pid].plan, recs)
     # dominant kernel: the sampling kernel; bytes per launch = samples per
     # launch x mean bytes per sample (equal sample counts per pattern)
     mean_bytes = float(np.mean([bytes_per_sample[n] for n in PATTERNS]))
@@ -602,6 +674,7 @@ def main():
     out = {
         "metric": "time to ±1% rel. err (95% CI) + samples/s: learned vs f_approx vs uniform",
         "value": value,
+        "value_cliques_on_symmetric_graph": value_symmetric,
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -614,7 +687,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "R-MAT scale 20 (ef 16, a=.57 b=.19 c=.19), patterns 5-clique/5-cycle/house/4-star, "
-                        "f_approx with switching (beta=4/5)",
+                        "f_approx with switching (beta=4/5); the clique on the degree-oriented graph (Sec. 5.4)",
+            "orientation_and_tables_ms": 1e3 * orient_s,
             "samples_per_pattern_per_step": args.samples,
             "graph": {"n": g.n, "nnz": g.nnz, "seed": 20},
             "tables_ms": 1e3 * tables_s,
