@@ -178,6 +178,14 @@ struct DevPlan {
 // tile_base.
 constexpr uint32_t kMaxSegs = 64;
 
+// Slot-queue counters of a round: kQueues of them, kQueueStride 64-bit
+// entries (256 bytes) apart, from byte kQueueOffset of the context's small
+// device buffer; kNoSlot marks an empty part.
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kQueueStride = 32;
+constexpr uint32_t kQueueOffset = 2048;
+constexpr uint64_t kNoSlot = ~0ull;
+
 struct Segment {
     uint32_t plan;
     uint32_t ntiles;
@@ -209,7 +217,7 @@ struct LaunchDesc {
     AGIS_GMEM Record* dump;               // non-null: one record per slot
     AGIS_GMEM uint32_t* scratch;          // per wave: cap vertices + cap log weights
     uint64_t cap;
-    AGIS_GMEM unsigned long long* queue;  // next free slot
+    AGIS_GMEM unsigned long long* queue;  // kQueues counters, kQueueStride apart
     AGIS_GMEM double* xout;               // weight per slot
     uint32_t grab;
     // a hub's bitmap replaces the merge with its list when the list is at

@@ -1468,8 +1468,8 @@ __device__ __forceinline__ Partial chan_merge(Partial a, const Partial& b) {
 
 // Persistent sampler over one round: slots [0, total) are the concatenated
 // segments of the round (pattern plan, first sample index, slot range).
-// Each wave repeatedly takes the next `grab` slots from a device-wide
-// counter (so heavy and light samples balance across waves), runs them one
+// Each wave repeatedly takes the next `grab` slots from device-wide
+// counters (so heavy and light samples balance across waves), runs them one
 // at a time and stores each weight at its slot.  The next grab is requested
 // before the current one is processed, so the atomic's round trip overlaps
 // sampling work.  A sample's result does not depend on which wave runs it.
@@ -1494,14 +1494,34 @@ void k_sample(const LaunchDesc* __restrict__ D) {
     const DevTables t = D->t;
     const uint32_t hub_window = D->hub_window;
     AGIS_GMEM double* xout = D->xout;
-    uint32_t sg = 0;  // segment of the current slot (slots a wave takes only increase)
-    unsigned long long cur = 0;
-    if (lane == 0) cur = atomicAdd(D->queue, (unsigned long long)grab);
-    cur = uniform_u64(cur);
-    while (cur < total) {
-        unsigned long long next = 0;
-        if (lane == 0) next = atomicAdd(D->queue, (unsigned long long)grab);
-        const uint64_t j1 = (cur + grab) < total ? (cur + grab) : total;
+    // The slots are split into kQueues contiguous parts, each with its own
+    // counter (atomics on one address are serialised: with cheap samples a
+    // single counter bounds the launch).  A wave starts on part
+    // blockIdx % kQueues and, when that part runs out, moves on to the next
+    // part, until it has found every part empty.
+    uint32_t q = blockIdx.x % kQueues;
+    uint64_t lo = total * q / kQueues, hi = total * (q + 1) / kQueues;
+    auto take = [&]() -> uint64_t {
+        unsigned long long o = 0;
+        if (lane == 0) o = atomicAdd(D->queue + (uint64_t)q * kQueueStride, (unsigned long long)grab);
+        o = uniform_u64(o);
+        return o < hi - lo ? lo + o : kNoSlot;
+    };
+    uint32_t sg = 0;  // segment of the current slot (within a part, slots only increase)
+    uint32_t unvisited = kQueues - 1;
+    uint64_t cur = take();
+    for (;;) {
+        while (cur == kNoSlot && unvisited > 0) {
+            --unvisited;
+            q = (q + 1) % kQueues;
+            lo = total * q / kQueues;
+            hi = total * (q + 1) / kQueues;
+            sg = 0;
+            cur = take();
+        }
+        if (cur == kNoSlot) break;
+        const uint64_t next = take();  // requested before the current grab runs
+        const uint64_t j1 = (cur + grab) < hi ? (cur + grab) : hi;
         for (uint64_t j = cur; j < j1; ++j) {
             while (sg + 1 < round->nseg && j >= round->seg[sg].base + round->seg[sg].count) ++sg;
             const Segment& S = round->seg[sg];
@@ -1569,7 +1589,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_x(const LaunchDesc* _
     }
 }
 
-__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+__global__ void k_zero_queues(unsigned long long* p) {
+    if (threadIdx.x < kQueues) p[threadIdx.x * kQueueStride] = 0ull;
+}
 
 const void* sample_kernel(bool dump, int variant) {
     switch (variant) {
@@ -1672,7 +1694,7 @@ void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const 
     D->dump = gmem(dump);
     D->scratch = gmem((uint32_t*)ctx->d_scratch);
     D->cap = L.cap;
-    D->queue = gmem((unsigned long long*)((char*)ctx->d_small + 64));
+    D->queue = gmem((unsigned long long*)((char*)ctx->d_small + kQueueOffset));
     D->xout = gmem(ctx->d_xout);
     D->grab = L.grab;
     D->hub_window = L.hub_window;
@@ -1680,10 +1702,10 @@ void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const 
 
 hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L, hipEvent_t before,
                         hipEvent_t after) {
-    unsigned long long* queue = (unsigned long long*)((char*)ctx->d_small + 64);
+    unsigned long long* queue = (unsigned long long*)((char*)ctx->d_small + kQueueOffset);
     hipError_t e;
-    // the queue is cleared by a kernel (the sequence may be captured in a graph)
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, queue);
+    // the counters are cleared by a kernel (the sequence may be captured in a graph)
+    hipLaunchKernelGGL(k_zero_queues, dim3(1), dim3(64), 0, stream, queue);
     if (before && (e = hipEventRecord(before, stream)) != hipSuccess) return e;
     const LaunchDesc* desc = ctx->d_launch;
     void* args[] = {(void*)&desc};
