@@ -104,3 +104,46 @@ def test_oriented_rejects_non_cliques(sess, c1):
     with pytest.raises(A.AgisError) as e:
         sess.estimate(O, T, synth.named_pattern("house"), 1000, 1)
     assert e.value.code == A.AGIS_E_UNSUPPORTED
+
+
+def test_oriented_rmat20_full_size_sampled_parity(sess):
+    """The bench's clique workload at full size: R-MAT scale 20 oriented on
+    the GPU, its CSR and tables compared whole with the oracle's, records of
+    the 4- and 5-clique compared on indices sampled from [0, 10^8), and the
+    oriented 5-clique estimate against the symmetric graph's."""
+    g = synth.rmat(20, 16, seed=20)
+    say(f"R-MAT-20 orient n={g.n} nnz={g.nnz}")
+    G = sess.graph(g.off, g.nbr)
+    O = sess.orient(G)
+    T = sess.tables(O, cv_seed=1)
+    o = oracle.orient(g)
+    off, nbr = O.csr()
+    assert np.array_equal(off, o.off) and np.array_equal(nbr, o.nbr)
+    say("R-MAT-20 oriented tables compare")
+    OT = oracle.Tables(o, cv_seed=1, adjacency=g)
+    got = T.export()
+    for k in ("deg", "s2", "hits", "trials", "la", "lc"):
+        assert np.array_equal(got[k], getattr(OT, k)), k
+    rng = np.random.Generator(np.random.PCG64(21))
+    idx = np.sort(rng.integers(0, 10 ** 8, size=400, dtype=np.uint64))
+    for k in (4, 5):
+        p = synth.patterns.clique(k)
+        ref = oracle.Sampler(o, OT, compile_pattern(p.k, p.edges, mode="switch"), seed=7,
+                             oriented=True).records(idx)
+        for rowtab in ("off", "on"):
+            say(f"R-MAT-20 oriented records {k}-clique rowtab={rowtab}")
+            rec = sess.dump(O, T, p, 7, idx, mode="switch", rowtab=rowtab)
+            for f in ("v", "num", "den", "steps", "fail_step"):
+                assert np.array_equal(rec[f], ref[f]), (k, rowtab, f)
+            assert np.array_equal(rec["x"], ref["x"]), (k, rowtab)
+    say("R-MAT-20 5-clique: oriented vs symmetric estimate")
+    p = synth.patterns.clique(5)
+    TS = sess.tables(G, cv_seed=1)
+    ro = sess.estimate(O, T, p, 1 << 22, 7, mode="switch")
+    rs = sess.estimate(G, TS, p, 1 << 22, 8, mode="switch")
+    se = math.sqrt(ro.variance / ro.n + rs.variance / rs.n)  # both in embeddings
+    assert abs(ro.estimate - rs.estimate) <= 5 * se, (ro.estimate, rs.estimate, se)
+    TS.close()
+    T.close()
+    O.close()
+    G.close()
