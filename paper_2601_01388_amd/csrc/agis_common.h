@@ -145,6 +145,12 @@ struct DevTables {
     AGIS_GMEM const uint32_t* hub_bits;
     AGIS_GMEM const int32_t* hub_slot;
     uint64_t hub_words;  // 32-bit words per bitmap row
+    // common-neighbour counts of the "pair hubs" (the highest-degree hubs):
+    // pair_count[pair_slot[a] * pairs + pair_slot[b]] = |N(a) cap N(b)|
+    // (pair_slot < 0: not a pair hub; pairs = 0: no table)
+    AGIS_GMEM const int32_t* pair_slot;
+    AGIS_GMEM const uint32_t* pair_count;
+    uint64_t pairs;
 };
 
 struct DevPlan {

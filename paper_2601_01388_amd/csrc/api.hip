@@ -142,6 +142,11 @@ constexpr uint64_t kRowtabBudgetBytes = 48ull << 30;
 // many as fit in kHubBitmapBudget, the degree threshold a power of two):
 // the sampler tests membership in such a list with one probe.
 constexpr uint64_t kHubBitmapBudget = 1ull << 30;
+// Common-neighbour counts of every pair among at most this many hubs
+// (the highest degrees): a uniform last step whose candidates are the
+// common neighbours of two such hubs only counts them, so the count is one
+// table read (4 MiB of table for 1024 hubs).
+constexpr uint64_t kPairHubs = 1024;
 
 hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t) {
     const uint64_t n = g->g.n;
@@ -176,19 +181,48 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
     if (e == hipSuccess) e = hipMemsetAsync(t->hub_bits, 0, hubs * words * sizeof(uint32_t), ctx->stream);
     if (e == hipSuccess) e = agis::launch_hub_bits(g->g, t->hub_slot, words, t->hub_bits, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (flags) (void)hipFree(flags);
-    if (prefix) (void)hipFree(prefix);
     if (e == hipSuccess) {
         t->hub_words = words;
         t->hubs = hubs;
         t->hub_min_degree = 1u << b;
     }
+    // pair hubs: the hubs of degree >= 2^p, p >= b the smallest with at most
+    // kPairHubs of them
+    int pb = b;
+    for (;; ++pb) {
+        uint64_t c = 0;
+        for (int j = pb; j < 64; ++j) c += hist[j];
+        if (c <= kPairHubs || pb == 63) break;
+    }
+    uint64_t H = 0;
+    uint32_t* pair_hub = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&t->pair_slot, n * sizeof(int32_t));
+    if (e == hipSuccess) e = agis::launch_hub_slots(ctx, g->g, 1u << pb, flags, t->pair_slot, prefix);
+    if (e == hipSuccess) e = hipMemcpyAsync(&H, prefix + n, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && H >= 2) {
+        e = hipMalloc(&pair_hub, H * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&t->pair_count, H * H * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = agis::launch_pair_counts(ctx, g->g, t->hub_slot, t->hub_bits, words, t->pair_slot, H, pair_hub,
+                                         t->pair_count);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess) {
+            t->pairs = H;
+            t->pair_min_degree = 1u << pb;
+        }
+    }
+    if (pair_hub) (void)hipFree(pair_hub);
+    if (flags) (void)hipFree(flags);
+    if (prefix) (void)hipFree(prefix);
     return e;
 }
 
 agis::DevTables dev_tables(const agis_tables* t) {
-    return agis::DevTables{agis::gmem((const uint4*)t->rec), agis::gmem((const uint32_t*)t->hub_bits),
-                           agis::gmem((const int32_t*)t->hub_slot), t->hub_words};
+    return agis::DevTables{agis::gmem((const uint4*)t->rec),        agis::gmem((const uint32_t*)t->hub_bits),
+                           agis::gmem((const int32_t*)t->hub_slot),    t->hub_words,
+                           agis::gmem((const int32_t*)t->pair_slot),   agis::gmem((const uint32_t*)t->pair_count),
+                           t->pair_count ? t->pairs : 0};
 }
 
 int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p, const uint8_t* order,
@@ -669,6 +703,8 @@ void agis_tables_destroy(agis_tables* t) {
     if (t->trials) (void)hipFree(t->trials);
     if (t->hub_bits) (void)hipFree(t->hub_bits);
     if (t->hub_slot) (void)hipFree(t->hub_slot);
+    if (t->pair_slot) (void)hipFree(t->pair_slot);
+    if (t->pair_count) (void)hipFree(t->pair_count);
     delete t;
 }
 

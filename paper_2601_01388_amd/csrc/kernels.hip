@@ -833,6 +833,59 @@ hipError_t launch_hub_bits(const DevGraph& g, const int32_t* hub_slot, uint64_t 
     return hipGetLastError();
 }
 
+// Pair hubs in slot order, then one wave per pair (a, b), a < b: the
+// shorter of the two lists is walked and each element probed in the other
+// vertex's bitmap (every pair hub has one); both orders of the pair get
+// the count, the diagonal 0.
+__global__ void k_pair_hubs(const int32_t* __restrict__ pair_slot, uint64_t n, uint32_t* __restrict__ pair_hub) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && pair_slot[v] >= 0) pair_hub[pair_slot[v]] = (uint32_t)v;
+}
+
+__global__ __launch_bounds__(256) void k_pair_counts(DevGraph g, const int32_t* __restrict__ hub_slot,
+                                                      const uint32_t* __restrict__ hub_bits, uint64_t hub_words,
+                                                      const uint32_t* __restrict__ pair_hub, uint64_t H,
+                                                      uint32_t* __restrict__ pair_count) {
+    const int lane = lane_id();
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t pr = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; pr < H * H; pr += nw) {
+        const uint64_t a = pr / H, b = pr % H;
+        if (a > b) continue;  // wave-uniform
+        if (a == b) {
+            if (lane == 0) pair_count[pr] = 0u;
+            continue;
+        }
+        const uint32_t va = pair_hub[a], vb = pair_hub[b];
+        const uint64_t oa = g.off[va], ob = g.off[vb];
+        const uint64_t da = g.off[va + 1] - oa, db = g.off[vb + 1] - ob;
+        // walk the shorter list, probe the other's bitmap
+        const bool walk_a = da <= db;
+        const uint64_t o = walk_a ? oa : ob, d = walk_a ? da : db;
+        const uint32_t* bits = hub_bits + (uint64_t)hub_slot[walk_a ? vb : va] * hub_words;
+        uint32_t c = 0;
+        for (uint64_t e = (uint64_t)lane; e < d; e += kWave) {
+            const uint32_t x = g.nbr[o + e];
+            c += (bits[x >> 5] >> (x & 31u)) & 1u;
+        }
+        c = (uint32_t)wave_sum_u64(c);
+        if (lane == 0) {
+            pair_count[a * H + b] = c;
+            pair_count[b * H + a] = c;
+        }
+    }
+}
+
+hipError_t launch_pair_counts(agis_ctx* ctx, const DevGraph& g, const int32_t* hub_slot, const uint32_t* hub_bits,
+                              uint64_t hub_words, const int32_t* pair_slot, uint64_t H, uint32_t* pair_hub,
+                              uint32_t* pair_count) {
+    hipLaunchKernelGGL(k_pair_hubs, dim3(grid_for(g.n, 256)), dim3(256), 0, ctx->stream, pair_slot, g.n, pair_hub);
+    const uint64_t waves = H * H;
+    const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, (uint64_t)ctx->num_cus * 8);
+    hipLaunchKernelGGL(k_pair_counts, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, g, hub_slot, hub_bits,
+                       hub_words, pair_hub, H, pair_count);
+    return hipGetLastError();
+}
+
 hipError_t launch_orient_fill(const DevGraph& g, const uint64_t* off_out, uint32_t* nbr_out, hipStream_t stream) {
     hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, off_out, nbr_out);
     return hipGetLastError();
@@ -1088,6 +1141,30 @@ hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const int32_t* sw, ui
 // ---------------------------------------------------------------------------
 namespace {
 
+// |S| of a last step whose candidates are the common neighbours of the two
+// matched vertices a and b (bm) minus the matched vertices, when a and b
+// are both pair hubs: the table's |N(a) cap N(b)| less the other matched
+// vertices found in both bitmaps (a and b lie in neither of their own
+// lists).  Returns false, and leaves `out`, when either is not a pair hub.
+__device__ __forceinline__ bool pair_hub_count(const DevTables& t, uint32_t my_tau, uint32_t bm, uint32_t i,
+                                               uint64_t& out) {
+    const int lane = lane_id();
+    const uint32_t a = readlane_u32(my_tau, __builtin_ctz(bm));
+    const uint32_t b = readlane_u32(my_tau, 31 - __builtin_clz(bm));
+    const int32_t sa = t.pair_slot[a], sb = t.pair_slot[b];
+    if (sa < 0 || sb < 0) return false;
+    const uint32_t c = t.pair_count[(uint64_t)sa * t.pairs + (uint64_t)sb];
+    bool both = false;
+    if ((uint32_t)lane < i && my_tau != a && my_tau != b) {
+        const auto ba = t.hub_bits + (uint64_t)t.hub_slot[a] * t.hub_words;
+        const auto bb = t.hub_bits + (uint64_t)t.hub_slot[b] * t.hub_words;
+        const uint32_t w = my_tau >> 5, m = 1u << (my_tau & 31u);
+        both = (ba[w] & m) != 0 && (bb[w] & m) != 0;
+    }
+    out = (uint64_t)c - (uint64_t)__popcll(__ballot(both));
+    return true;
+}
+
 // Log weight of candidate v at a weighted step: one 4-byte read of the
 // step's table when it was built, else from the 16-byte vertex record.
 __device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int32_t* sw, const int32_t* lt, uint32_t v,
@@ -1248,6 +1325,17 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     drawn_pos = (uint32_t)idx;
                 }
                 num = m;
+                den = 1;
+            } else if (count_only && t.pairs != 0 && __builtin_popcount(bm) == 2 &&
+                       pair_hub_count(t, my_tau, bm, i, num)) {
+                // only the number of common neighbours of two pair hubs
+                // enters X: one table read, less the matched vertices in
+                // both lists
+                if (num == 0) {
+                    fail = (int)i;
+                    break;
+                }
+                v = 0;
                 den = 1;
             } else {
                 // Candidate set I = intersection of the backward lists, S = I

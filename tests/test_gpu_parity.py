@@ -318,3 +318,23 @@ def test_rmat20_full_size_sampled_parity(sess, rmat20):
     r = sess.estimate(G, T, synth.named_pattern("4-star"), 100_000, SEED, mode="switch")
     exact = judges.star_embeddings(g, 4)
     assert abs(r.estimate / exact - 1) < 0.01
+
+
+def test_rmat20_estimates_match_oracle(sess, rmat20):
+    """The production sampler (count-only last steps, the pair-hub count
+    table for common neighbours of two top hubs) against the oracle's mean
+    over the same sample indices of the full-size graph."""
+    g = rmat20
+    G = sess.graph(g.off, g.nbr)
+    T = sess.tables(G, cv_seed=CV_SEED)
+    OT = oracle.Tables(g, cv_seed=CV_SEED)
+    n = 20_000
+    for name in ("5-cycle", "house", "4-cycle", "triangle"):
+        p = synth.named_pattern(name)
+        say(f"R-MAT-20 estimate {name}")
+        r = sess.estimate(G, T, p, n, SEED, mode="switch")
+        st, _, _ = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="switch"), seed=SEED).run(0, n)
+        assert r.n == n
+        assert abs(r.estimate - st.mean) <= 1e-9 * abs(st.mean), (name, r.estimate, st.mean)
+    T.close()
+    G.close()
