@@ -142,11 +142,14 @@ constexpr uint64_t kRowtabBudgetBytes = 48ull << 30;
 // many as fit in kHubBitmapBudget, the degree threshold a power of two):
 // the sampler tests membership in such a list with one probe.
 constexpr uint64_t kHubBitmapBudget = 1ull << 30;
-// Common-neighbour counts of every pair among at most this many hubs
-// (the highest degrees): a uniform last step whose candidates are the
-// common neighbours of two such hubs only counts them, so the count is one
-// table read (4 MiB of table for 1024 hubs).
-constexpr uint64_t kPairHubs = 1024;
+// Common-neighbour counts of every pair among the highest-degree hubs: a
+// uniform last step whose candidates are the common neighbours of two such
+// hubs only counts them, so the count is one table read.  The pair hubs are
+// those of degree >= 2^p for the smallest p with at most kPairHubs of them
+// (a table of at most 64 MiB) and an estimated build work of at most
+// kPairWork list elements (the shorter list of every pair is walked).
+constexpr uint64_t kPairHubs = 4096;
+constexpr double kPairWork = 8.0e9;
 
 hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t) {
     const uint64_t n = g->g.n;
@@ -186,13 +189,18 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
         t->hubs = hubs;
         t->hub_min_degree = 1u << b;
     }
-    // pair hubs: the hubs of degree >= 2^p, p >= b the smallest with at most
-    // kPairHubs of them
+    // pair hubs: the hubs of degree >= 2^p, p >= b the smallest within both
+    // limits; the work bound takes every degree of bucket j as 2^(j+1) and
+    // the hubs in decreasing degree (a pair costs the later one's degree)
     int pb = b;
     for (;; ++pb) {
         uint64_t c = 0;
-        for (int j = pb; j < 64; ++j) c += hist[j];
-        if (c <= kPairHubs || pb == 63) break;
+        double work = 0.0;
+        for (int j = 63; j >= pb; --j) {
+            work += (double)hist[j] * ((double)c + 0.5 * (double)hist[j]) * std::ldexp(1.0, j + 1);
+            c += hist[j];
+        }
+        if ((c <= kPairHubs && work <= kPairWork) || pb == 63) break;
     }
     uint64_t H = 0;
     uint32_t* pair_hub = nullptr;
