@@ -26,7 +26,7 @@ struct agis_ctx {
     uint64_t xout_cap = 0;
     agis::DevPlan* d_plans = nullptr;    // kMaxSegs plans
     agis::LaunchDesc* d_launch = nullptr;  // the current round
-    int sample_blocks_per_cu[3] = {0, 0, 0};  // resident blocks per CU of each kernel variant
+    int sample_blocks_per_cu[6] = {0, 0, 0, 0, 0, 0};  // resident blocks per CU of each kernel (variant, pairs)
     // launch tuning (0 = default): resident blocks per CU, slots per grab
     int tune_blocks_per_cu = 0;
     uint32_t tune_grab = 0;
@@ -152,10 +152,15 @@ struct SampleLaunch {
     bool dump = false;       // launch the record-writing variant
     int variant = 0;         // register-budget variant
     uint32_t hub_window = 0; // see LaunchDesc::hub_window
+    // the kernel with the pair-hub paths (set by the caller before
+    // plan_sample_launch: some plan has an unweighted step over exactly two
+    // backward lists and the tables hold the pair-hub table)
+    bool pairs = false;
 };
 
-// The sampling kernel for (record-writing?, register-budget variant 0..2).
-const void* sample_kernel(bool dump, int variant);
+// The sampling kernel for (record-writing?, register-budget variant 0..2,
+// pair-hub paths?).
+const void* sample_kernel(bool dump, int variant, bool pairs);
 
 // Sizes the persistent grid (resident waves only) and the buffers for
 // rounds of at most max_slots samples over at most max_segs segments.

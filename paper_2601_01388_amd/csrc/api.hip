@@ -360,6 +360,15 @@ struct PatternRun {
     uint64_t launches = 0;
 };
 
+// Whether a plan has a step the pair-hub paths serve (an unweighted step
+// over exactly two backward lists) and the tables have the pair-hub table.
+bool uses_pair_hubs(const DevPlan& hp, const agis_tables* t) {
+    if (!t->pair_count || t->pairs == 0) return false;
+    for (uint32_t i = 2; i < hp.k; ++i)
+        if (!hp.weighted[i] && __builtin_popcount(hp.bmask[i]) == 2) return true;
+    return false;
+}
+
 // Rounds of at most this many samples bound the weight buffer (8 B each).
 constexpr uint64_t kMaxRoundSlots = 1ull << 24;
 
@@ -375,7 +384,7 @@ int replay_or_launch(agis_ctx* ctx, const agis::SampleLaunch& L, const agis_grap
     // contents may change between replays, its address and the grids not
     const uint64_t key[8] = {(uint64_t)(uintptr_t)ctx->d_launch, (uint64_t)L.blocks, (uint64_t)L.threads,
                              L.max_tiles, (uint64_t)(uintptr_t)ctx->d_partials, (uint64_t)(uintptr_t)ctx->d_small,
-                             (uint64_t)L.variant, 0};
+                             (uint64_t)L.variant, (uint64_t)L.pairs};
     if (!ctx->graph_exec || std::memcmp(key, ctx->graph_key, sizeof(key)) != 0) {
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
         if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -428,6 +437,7 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
     max_slots = std::min(max_slots, kMaxRoundSlots);
     if (max_slots == 0) return AGIS_OK;
     agis::SampleLaunch L;
+    for (const PatternRun& r : runs) L.pairs = L.pairs || uses_pair_hubs(r.prep.hp, t);
     int rc = agis::plan_sample_launch(ctx, *g, max_slots, npat, &L, &ctx->err);
     if (rc != AGIS_OK) return rc;
     agis::LaunchDesc ld;
@@ -854,6 +864,7 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     if (m == 0) return AGIS_OK;
     if (m > kMaxRoundSlots) return fail(ctx, AGIS_E_INVALID_ARG, "at most 2^24 records per call");
     agis::SampleLaunch L;
+    L.pairs = uses_pair_hubs(prep.hp, t);
     rc = agis::plan_sample_launch(ctx, *g, m, 1, &L, &ctx->err);
     if (rc != AGIS_OK) return rc;
     L.dump = true;

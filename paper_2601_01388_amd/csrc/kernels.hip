@@ -1179,7 +1179,7 @@ __device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int
 // rec != nullptr.  `my_tau` of lane j holds the data vertex matched at step
 // j (wave-uniform by construction).  sv/sl: this wave's scratch for the
 // candidate vertices and their log weights (capacity >= max degree).
-template <bool kDump>
+template <bool kDump, bool kPairs>
 __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P,
                              uint32_t k0, uint32_t k1, uint64_t s, uint32_t* __restrict__ sv,
                              int32_t* __restrict__ sl, Record* __restrict__ rec, uint32_t hub_window) {
@@ -1326,7 +1326,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 }
                 num = m;
                 den = 1;
-            } else if (count_only && t.pairs != 0 && __builtin_popcount(bm) == 2 &&
+            } else if (kPairs && count_only && t.pairs != 0 && __builtin_popcount(bm) == 2 &&
                        pair_hub_count(t, my_tau, bm, i, num)) {
                 // only the number of common neighbours of two pair hubs
                 // enters X: one table read, less the matched vertices in
@@ -1397,6 +1397,19 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 if (t.hub_slot && (uint32_t)lane < i && (others >> lane & 1u) &&
                     (uint64_t)my_d * kWave >= (uint64_t)hub_window * db)
                     my_slot = t.hub_slot[my_tau];
+                // A uniform step over the common neighbours of two pair hubs,
+                // whose set no later step reuses: |S| comes from the pair-hub
+                // table, so the vertex is drawn first and the walk stops once
+                // the drawn rank has been stored.
+                uint64_t pick = ~0ull, m_pair = 0;
+                if (kPairs && !weighted && !count_only && !reuse && t.pairs != 0 && __builtin_popcount(bm) == 2 &&
+                    (i + 1 == k || P->reuse[i + 1] == 0) && pair_hub_count(t, my_tau, bm, i, m_pair)) {
+                    if (m_pair == 0) {
+                        fail = (int)i;
+                        break;
+                    }
+                    pick = bounded_draw(k0, k1, c0, c1, c2, i, m_pair);
+                }
                 uint64_t cnt = 0;
                 // Software pipeline over the chunks: the next chunk's base
                 // elements are loaded one chunk ahead, and a chunk's weights
@@ -1459,6 +1472,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     pend_p = p;
                     pend_l = l;
                     cnt += (uint64_t)__popcll(km);
+                    if (cnt > pick) break;
                 }
                 if (pend_member && pend_l != kCertainZero && pend_l > lmax_l) lmax_l = pend_l;
                 if (pend_keep) sl[pend_p] = pend_l;
@@ -1470,8 +1484,13 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         break;
                     }
                     v = 0;
-                    if (!count_only) v = sv[bounded_draw(k0, k1, c0, c1, c2, i, cnt)];
-                    num = cnt;
+                    if (pick != ~0ull) {
+                        v = sv[pick];
+                        num = m_pair;
+                    } else {
+                        if (!count_only) v = sv[bounded_draw(k0, k1, c0, c1, c2, i, cnt)];
+                        num = cnt;
+                    }
                     den = 1;
                 } else {
                     const int32_t lmax = (int32_t)uniform_u32((uint32_t)wave_max_i32(lmax_l));
@@ -1567,7 +1586,7 @@ __device__ __forceinline__ Partial chan_merge(Partial a, const Partial& b) {
 // fit (4 leaves the compiler its own choice, 80 registers and 6 waves here;
 // 7 and 8 trade spills for more resident waves); the autotuner picks the
 // fastest.
-template <bool kDump, int kWavesPerEU>
+template <bool kDump, int kWavesPerEU, bool kPairs>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU)))
 void k_sample(const LaunchDesc* __restrict__ D) {
     const int lane = lane_id();
@@ -1617,7 +1636,7 @@ void k_sample(const LaunchDesc* __restrict__ D) {
             const uint64_t sidx = kDump ? D->idx[off] : S.start + off;
             Record* rec = kDump ? D->dump + j : nullptr;
             const double xv =
-                sample_one<kDump>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec, hub_window);
+                sample_one<kDump, kPairs>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec, hub_window);
             if (lane == 0) xout[j] = xv;
         }
         cur = uniform_u64(next);
@@ -1681,14 +1700,20 @@ __global__ void k_zero_queues(unsigned long long* p) {
     if (threadIdx.x < kQueues) p[threadIdx.x * kQueueStride] = 0ull;
 }
 
-const void* sample_kernel(bool dump, int variant) {
+template <int kW, bool kPairs>
+const void* sample_kernel_of(bool dump) {
+    return dump ? reinterpret_cast<const void*>(k_sample<true, kW, kPairs>)
+                : reinterpret_cast<const void*>(k_sample<false, kW, kPairs>);
+}
+
+const void* sample_kernel(bool dump, int variant, bool pairs) {
     switch (variant) {
         case 1:
-            return dump ? reinterpret_cast<const void*>(k_sample<true, 7>) : reinterpret_cast<const void*>(k_sample<false, 7>);
+            return pairs ? sample_kernel_of<7, true>(dump) : sample_kernel_of<7, false>(dump);
         case 2:
-            return dump ? reinterpret_cast<const void*>(k_sample<true, 8>) : reinterpret_cast<const void*>(k_sample<false, 8>);
+            return pairs ? sample_kernel_of<8, true>(dump) : sample_kernel_of<8, false>(dump);
         default:
-            return dump ? reinterpret_cast<const void*>(k_sample<true, 4>) : reinterpret_cast<const void*>(k_sample<false, 4>);
+            return pairs ? sample_kernel_of<4, true>(dump) : sample_kernel_of<4, false>(dump);
     }
 }
 
@@ -1708,10 +1733,11 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
     }
     L->variant = ctx->tune_variant;
     L->hub_window = ctx->tune_hub_window;
-    int& cached = ctx->sample_blocks_per_cu[L->variant];
+    int& cached = ctx->sample_blocks_per_cu[L->variant * 2 + (L->pairs ? 1 : 0)];
     if (cached == 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel(false, ctx->tune_variant), L->threads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel(false, L->variant, L->pairs), L->threads,
+                                                         0) !=
                 hipSuccess ||
             nb < 1)
             nb = 4;
@@ -1797,7 +1823,7 @@ hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L
     if (before && (e = hipEventRecord(before, stream)) != hipSuccess) return e;
     const LaunchDesc* desc = ctx->d_launch;
     void* args[] = {(void*)&desc};
-    e = hipLaunchKernel(sample_kernel(L.dump, L.variant), dim3((unsigned)L.blocks), dim3((unsigned)L.threads), args, 0,
+    e = hipLaunchKernel(sample_kernel(L.dump, L.variant, L.pairs), dim3((unsigned)L.blocks), dim3((unsigned)L.threads), args, 0,
                         stream);
     if (e != hipSuccess) return e;
     if ((e = hipGetLastError()) != hipSuccess) return e;
