@@ -1165,6 +1165,42 @@ __device__ __forceinline__ bool pair_hub_count(const DevTables& t, uint32_t my_t
     return true;
 }
 
+// The element of rank r (ascending, 0-based) of S = (N(a) cap N(b)) minus
+// the matched vertices, |S| = m, for two pair hubs a and b (bm): the shorter
+// list is walked 64 elements at a time, each probed in the other's bitmap,
+// from its start when r lies in the lower half of S and from its end
+// otherwise (ranks then counted from the top).
+__device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const DevTables& t, uint32_t my_tau, uint32_t bm,
+                                                    uint32_t i, uint64_t r, uint64_t m) {
+    const int lane = lane_id();
+    const uint32_t a = readlane_u32(my_tau, __builtin_ctz(bm));
+    const uint32_t b = readlane_u32(my_tau, 31 - __builtin_clz(bm));
+    const uint64_t oa = g.off[a], ob = g.off[b];
+    const uint64_t da = g.off[a + 1] - oa, db = g.off[b + 1] - ob;
+    const bool walk_a = da <= db;
+    const uint32_t* list = g.nbr + (walk_a ? oa : ob);
+    const uint64_t d = walk_a ? da : db;
+    const auto row = t.hub_bits + (uint64_t)t.hub_slot[walk_a ? b : a] * t.hub_words;
+    const bool forward = r < m - r;
+    const uint64_t target = forward ? r : m - 1 - r;
+    uint64_t seen = 0;
+    for (uint64_t c = 0; c < d; c += kWave) {
+        const uint64_t e = c + (uint64_t)lane;
+        const bool valid = e < d;
+        const uint32_t x = valid ? list[forward ? e : d - 1 - e] : 0u;
+        bool keep = valid && ((row[x >> 5] >> (x & 31u)) & 1u) != 0;
+        for (uint32_t j = 0; j < i; ++j) keep = keep && x != readlane_u32(my_tau, (int)j);
+        uint64_t bal = __ballot(keep);
+        const uint64_t n = (uint64_t)__popcll(bal);
+        if (seen + n > target) {
+            for (uint64_t q = target - seen; q > 0; --q) bal &= bal - 1;
+            return readlane_u32(x, __builtin_ctzll(bal));
+        }
+        seen += n;
+    }
+    return 0u;  // not reached: S holds m elements
+}
+
 // Log weight of candidate v at a weighted step: one 4-byte read of the
 // step's table when it was built, else from the 16-byte vertex record.
 __device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int32_t* sw, const int32_t* lt, uint32_t v,
@@ -1337,6 +1373,19 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 }
                 v = 0;
                 den = 1;
+            } else if (kPairs && !weighted && !count_only && P->reuse[i] == 0 && t.pairs != 0 &&
+                       __builtin_popcount(bm) == 2 && (i + 1 == k || P->reuse[i + 1] == 0) &&
+                       pair_hub_count(t, my_tau, bm, i, num)) {
+                // A uniform draw from the common neighbours of two pair hubs
+                // (a set no later step reuses): |S| from the table, then the
+                // drawn rank is found by walking from the nearer end.
+                if (num == 0) {
+                    fail = (int)i;
+                    break;
+                }
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, num);
+                v = pair_hub_select(g, t, my_tau, bm, i, r, num);
+                den = 1;
             } else {
                 // Candidate set I = intersection of the backward lists, S = I
                 // minus the matched vertices, in ascending id order.  The
@@ -1397,19 +1446,6 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 if (t.hub_slot && (uint32_t)lane < i && (others >> lane & 1u) &&
                     (uint64_t)my_d * kWave >= (uint64_t)hub_window * db)
                     my_slot = t.hub_slot[my_tau];
-                // A uniform step over the common neighbours of two pair hubs,
-                // whose set no later step reuses: |S| comes from the pair-hub
-                // table, so the vertex is drawn first and the walk stops once
-                // the drawn rank has been stored.
-                uint64_t pick = ~0ull, m_pair = 0;
-                if (kPairs && !weighted && !count_only && !reuse && t.pairs != 0 && __builtin_popcount(bm) == 2 &&
-                    (i + 1 == k || P->reuse[i + 1] == 0) && pair_hub_count(t, my_tau, bm, i, m_pair)) {
-                    if (m_pair == 0) {
-                        fail = (int)i;
-                        break;
-                    }
-                    pick = bounded_draw(k0, k1, c0, c1, c2, i, m_pair);
-                }
                 uint64_t cnt = 0;
                 // Software pipeline over the chunks: the next chunk's base
                 // elements are loaded one chunk ahead, and a chunk's weights
@@ -1472,7 +1508,6 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     pend_p = p;
                     pend_l = l;
                     cnt += (uint64_t)__popcll(km);
-                    if (cnt > pick) break;
                 }
                 if (pend_member && pend_l != kCertainZero && pend_l > lmax_l) lmax_l = pend_l;
                 if (pend_keep) sl[pend_p] = pend_l;
@@ -1484,13 +1519,8 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         break;
                     }
                     v = 0;
-                    if (pick != ~0ull) {
-                        v = sv[pick];
-                        num = m_pair;
-                    } else {
-                        if (!count_only) v = sv[bounded_draw(k0, k1, c0, c1, c2, i, cnt)];
-                        num = cnt;
-                    }
+                    if (!count_only) v = sv[bounded_draw(k0, k1, c0, c1, c2, i, cnt)];
+                    num = cnt;
                     den = 1;
                 } else {
                     const int32_t lmax = (int32_t)uniform_u32((uint32_t)wave_max_i32(lmax_l));
