@@ -85,6 +85,17 @@ def algorithmic_bytes(g, plan, recs) -> float:
     return total / max(len(recs), 1)
 
 
+def tune_batch(args, sess, G, T, pats, log):
+    """Autotunes the launch for a batch leg on pilots of its own patterns (the
+    launch shape that suits a batch of short to-eps rounds differs from the
+    one for long single-pattern estimates); returns what was chosen."""
+    if args.no_tune:
+        return None
+    tb = sess.autotune(G, T, pats, args.batch_tune_pilot, mode="switch")
+    log(f"batch tuning: variant {tb.variant} grab {tb.grab} hub window {tb.hub_window}")
+    return {"variant": tb.variant, "grab": tb.grab, "hub_window": tb.hub_window, "pilot_samples": args.batch_tune_pilot}
+
+
 def is_clique(p) -> bool:
     return len(p.edges) == p.k * (p.k - 1) // 2
 
@@ -146,7 +157,7 @@ def bpats_budgets(args):
     return [p for p, _ in pset], [max(1, int(b * args.large_budget_scale)) for _, b in pset]
 
 
-def large_legs(args, sess, G20, T20, pats_budgets, log):
+def large_legs(args, sess, G20, T20, pats_budgets, log, restore_tuning):
     import torch
     import synth
     from paper_2601_01388_amd.session import mlp_init
@@ -168,14 +179,16 @@ def large_legs(args, sess, G20, T20, pats_budgets, log):
                     "dmax": dmax, "generate_s": gen_s, "tables_ms": 1e3 * tables_s}
     log(f"R-MAT scale 24: n={G.n} nnz={G.nnz} dmax={dmax}; generated in {gen_s:.1f} s, tables {1e3 * tables_s:.1f} ms")
     log(f"32-pattern batch on scale 24 to +-1%, total budget {sum(budgets):.3g} samples")
+    btune = tune_batch(args, sess, G, T, bpats, log)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = sess.estimate_batch(G, T, bpats, budgets, 13, mode="switch", eps=0.01, delta=0.05,
                               check_every=1 << 16, min_samples=1 << 14)
     torch.cuda.synchronize()
     bt = time.perf_counter() - t0
+    restore_tuning()
     out["batch_32_patterns"] = {
-        "budget_scale": args.large_budget_scale, "seconds": bt, "samples": int(sum(r.n for r in res)), "converged": int(sum(r.converged for r in res)),
+        "tuning": btune, "budget_scale": args.large_budget_scale, "seconds": bt, "samples": int(sum(r.n for r in res)), "converged": int(sum(r.converged for r in res)),
         "samples_per_s": sum(r.n for r in res) / bt, "budget_total": int(sum(budgets)),
         "per_pattern": [{"k": p.k, "edges": len(p.edges), "budget": b, "samples": r.n,
                          "converged": bool(r.converged), "seconds": r.seconds,
@@ -260,7 +273,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run 3 plain device copies of this many bytes (counter calibration) and exit")
-    ap.add_argument("--tune-pilot", type=int, default=1 << 18)
+    ap.add_argument("--tune-pilot", type=int, default=1 << 20, help="pilot samples per pattern of the autotuner")
+    ap.add_argument("--batch-tune-pilot", type=int, default=1 << 15,
+                    help="pilot samples per pattern of the batch legs' autotuning")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-ablation", action="store_true")
@@ -348,6 +363,11 @@ def main():
                   "default_kernel_s": tun.default_seconds}
         log(f"tuned: variant {tun.variant} grab {tun.grab} hub window {tun.hub_window} "
             f"({tun.default_seconds:.3f} s -> {tun.seconds:.3f} s)")
+
+    def restore_tuning():
+        """Back to the headline's launch shape after a leg tuned its own."""
+        if tuning is not None:
+            sess.set_launch(True, 0, tuning["grab"], tuning["variant"], tuning["hub_window"])
 
     def step(seed, walls=None):
         res = []
@@ -589,14 +609,16 @@ def main():
         bpats = [p for p, _ in pset]
         budgets = [max(1, int(b * args.batch_budget_scale)) for _, b in pset]
         log(f"32-pattern batch to +-1%, total budget {sum(budgets):.3g} samples")
+        btune = tune_batch(args, sess, G, T, bpats, log)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = sess.estimate_batch(G, T, bpats, budgets, 13, mode="switch", eps=0.01, delta=0.05,
                                   check_every=1 << 16, min_samples=1 << 14)
         torch.cuda.synchronize()
         bt = time.perf_counter() - t0
+        restore_tuning()
         batch = {
-            "patterns": 32, "seconds": bt, "samples": int(sum(r.n for r in res)),
+            "patterns": 32, "tuning": btune, "seconds": bt, "samples": int(sum(r.n for r in res)),
             "converged": int(sum(r.converged for r in res)),
             "samples_per_s": sum(r.n for r in res) / bt,
             "budget_total": int(sum(budgets)),
@@ -664,7 +686,7 @@ def main():
     # scale-20 graph, evaluated against f_approx for variance per sample
     large = None
     if not args.skip_large:
-        large = large_legs(args, sess, G, T, bpats_budgets(args), log)
+        large = large_legs(args, sess, G, T, bpats_budgets(args), log, restore_tuning)
 
     cpu = None
     if not args.skip_cpu:
