@@ -146,10 +146,11 @@ constexpr uint64_t kHubBitmapBudget = 1ull << 30;
 // uniform last step whose candidates are the common neighbours of two such
 // hubs only counts them, so the count is one table read.  The pair hubs are
 // those of degree >= 2^p for the smallest p with at most kPairHubs of them
-// (a table of at most 64 MiB) and an estimated build work of at most
-// kPairWork list elements (the shorter list of every pair is walked).
-constexpr uint64_t kPairHubs = 4096;
-constexpr double kPairWork = 8.0e9;
+// (a table of at most 256 MiB) and an estimated build work of at most
+// kPairWork list elements (the shorter list of every pair is walked; about
+// 0.1 s at this bound).
+constexpr uint64_t kPairHubs = 8192;
+constexpr double kPairWork = 6.0e10;
 
 hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t) {
     const uint64_t n = g->g.n;
