@@ -147,3 +147,19 @@ def test_oriented_rmat20_full_size_sampled_parity(sess):
     T.close()
     O.close()
     G.close()
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_oriented_production_estimates_match_oracle(sess, c1, k):
+    """The production kernel on the DAG (count-only last step, pair-hub
+    table of out-neighbourhoods) against the oracle's mean over the same
+    sample indices: the estimate is k! times it."""
+    g, G, O, T, o, OT = c1
+    p = synth.patterns.clique(k)
+    n = 50_000
+    for mode in ("switch", "uniform"):
+        r = sess.estimate(O, T, p, n, 7, mode=mode)
+        st, _, _ = oracle.Sampler(o, OT, compile_pattern(p.k, p.edges, mode=mode), seed=7, oriented=True).run(0, n)
+        assert r.n == n
+        exact = math.factorial(k) * st.mean
+        assert abs(r.estimate - exact) <= 1e-9 * abs(exact), (mode, r.estimate, exact)
