@@ -227,7 +227,13 @@ int agis_graph_export(agis_ctx* ctx, const agis_graph* g, uint64_t* n, uint64_t*
  * draws an ordered pair of distinct neighbours from Philox key cv_seed) or
  * counted exactly (exact_cv = 1).  Stored in Q16 log2 form with log2 C_v
  * clamped below at lc_min_q16 (log2 of the paper's small nonzero constant;
- * -655360 = log2 2^-10).  The tables are owned by the library. */
+ * -655360 = log2 2^-10).  The tables are owned by the library.
+ * With them the library builds two search aids of the sampler (they change
+ * no sample): neighbourhood bitmaps of the highest-degree vertices (up to
+ * 1 GiB), and the common-neighbour counts of every pair among the hubs of
+ * highest degree (up to 8,192 of them, 256 MiB, within a bounded build
+ * work), which make a uniform step over the common neighbours of two such
+ * hubs a table read plus a partial walk. */
 int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_seed, int32_t lc_min_q16,
                                int32_t exact_cv, agis_tables** out);
 void agis_tables_destroy(agis_tables* t);
