@@ -172,8 +172,22 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
     uint64_t above = 0;
     for (int j = b; j < 64; ++j) above += hist[j];
     if (above == 0) return hipSuccess;
+    // Both aids are optional: where device memory runs short they are left
+    // out (the sampler then merges lists) instead of failing the tables.
     uint32_t* flags = nullptr;
     uint64_t* prefix = nullptr;
+    auto drop_out_of_memory = [&]() {
+        (void)hipGetLastError();
+        for (void* q : {(void*)flags, (void*)prefix, (void*)t->hub_slot, (void*)t->hub_bits, (void*)t->pair_slot,
+                        (void*)t->pair_count})
+            if (q) (void)hipFree(q);
+        t->hub_slot = nullptr;
+        t->hub_bits = nullptr;
+        t->pair_slot = nullptr;
+        t->pair_count = nullptr;
+        t->hub_words = t->hubs = t->pairs = 0;
+        return hipSuccess;
+    };
     e = hipMalloc(&flags, n * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&prefix, (n + 1) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc(&t->hub_slot, n * sizeof(int32_t));
@@ -182,6 +196,7 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
     if (e == hipSuccess) e = hipMemcpyAsync(&hubs, prefix + n, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e == hipSuccess) e = hipMalloc(&t->hub_bits, hubs * words * sizeof(uint32_t));
+    if (e == hipErrorOutOfMemory) return drop_out_of_memory();
     if (e == hipSuccess) e = hipMemsetAsync(t->hub_bits, 0, hubs * words * sizeof(uint32_t), ctx->stream);
     if (e == hipSuccess) e = agis::launch_hub_bits(g->g, t->hub_slot, words, t->hub_bits, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -205,14 +220,31 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
     }
     uint64_t H = 0;
     uint32_t* pair_hub = nullptr;
-    if (e == hipSuccess) e = hipMalloc(&t->pair_slot, n * sizeof(int32_t));
+    if (e == hipSuccess) {
+        e = hipMalloc(&t->pair_slot, n * sizeof(int32_t));
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            t->pair_slot = nullptr;
+            e = hipSuccess;
+            (void)hipFree(flags);
+            (void)hipFree(prefix);
+            return e;  // bitmaps without the pair-hub table
+        }
+    }
     if (e == hipSuccess) e = agis::launch_hub_slots(ctx, g->g, 1u << pb, flags, t->pair_slot, prefix);
     if (e == hipSuccess) e = hipMemcpyAsync(&H, prefix + n, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e == hipSuccess && H >= 2) {
         e = hipMalloc(&pair_hub, H * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&t->pair_count, H * H * sizeof(uint32_t));
-        if (e == hipSuccess)
+        if (e == hipErrorOutOfMemory) {
+            // no room for the pair-hub table: keep the bitmaps without it
+            (void)hipGetLastError();
+            if (t->pair_count) (void)hipFree(t->pair_count);
+            t->pair_count = nullptr;
+            H = 0;
+            e = hipSuccess;
+        } else if (e == hipSuccess)
             e = agis::launch_pair_counts(ctx, g->g, t->hub_slot, t->hub_bits, words, t->pair_slot, H, pair_hub,
                                          t->pair_count);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

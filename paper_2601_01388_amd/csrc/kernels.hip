@@ -133,17 +133,6 @@ __device__ __forceinline__ uint64_t wave_segmented_sum_u64(uint64_t v, int head)
     return head > 0 ? incl - before : incl;
 }
 
-// Inclusive max of v over this lane's segment so far.
-__device__ __forceinline__ int32_t wave_segmented_max_i32(int32_t v, int head) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int32_t w = __shfl_up(v, d, kWave);
-        if (lane - d >= head && w > v) v = w;
-    }
-    return v;
-}
-
 // lower bound of x in a sorted list: first position with list[pos] >= x
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ list, uint32_t len, uint32_t x) {
     uint32_t lo = 0, hi = len;
