@@ -338,3 +338,29 @@ def test_rmat20_estimates_match_oracle(sess, rmat20):
         assert abs(r.estimate - st.mean) <= 1e-9 * abs(st.mean), (name, r.estimate, st.mean)
     T.close()
     G.close()
+
+
+@pytest.mark.parametrize("n", [70, 130])
+def test_complete_graph_closed_forms_with_pair_hubs(sess, n):
+    """On K_n (n >= 65) every vertex has a neighbourhood bitmap and is a pair
+    hub, and every matched vertex lies in both lists of a two-list step, so
+    the pair-hub count and rank selection must subtract each of them.  Every
+    injective map is an embedding: each sample's X is n!/(n-k)! exactly,
+    in every mode, and the records equal the oracle's."""
+    g = synth.complete_graph(n)
+    G = sess.graph(g.off, g.nbr)
+    T = sess.tables(G, cv_seed=CV_SEED)
+    OT = oracle.Tables(g, cv_seed=CV_SEED)
+    idx = np.arange(2000, dtype=np.uint64)
+    for name in ("triangle", "4-cycle", "house", "5-cycle", "diamond"):
+        p = synth.named_pattern(name)
+        exact = float(math.perm(n, p.k))
+        for mode in ("switch", "uniform", "always"):
+            say(f"K_{n} {name} {mode}")
+            r = sess.estimate(G, T, p, 50_000, SEED, mode=mode)
+            assert r.estimate == pytest.approx(exact, rel=1e-12), (name, mode, r.estimate, exact)
+            got = sess.dump(G, T, p, SEED, idx, mode=mode)
+            ref = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode=mode), seed=SEED).records(idx)
+            _compare_records(got, ref, f"K{n}/{name}/{mode}")
+    T.close()
+    G.close()
