@@ -1418,9 +1418,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const AGIS_GMEM int32_t* sw = P->sw[i];
                 const uint32_t vprev = readlane_u32(my_tau, (int)i - 1);
                 int32_t lmax_l = kCertainZero;
-                if (weighted && reuse && (uint32_t)lane + 1 < i) {
+                if (weighted && reuse && (uint32_t)lane + 1 < i && !(bm >> lane & 1u)) {
                     // matched vertices were dropped from the reused set; the
-                    // normalising maximum still covers those lying in I
+                    // normalising maximum still covers those lying in I (a
+                    // backward vertex is not in its own list, so never in I)
                     bool in_all = true;
                     for (uint32_t bits = bm; bits && in_all; bits &= bits - 1) {
                         const uint32_t w = readlane_u32(my_tau, __builtin_ctz(bits));
