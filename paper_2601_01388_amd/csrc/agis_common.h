@@ -176,6 +176,13 @@ struct DevPlan {
     AGIS_GMEM const uint32_t* s1_q;
     AGIS_GMEM const uint64_t* s1_pre;
     uint64_t s1_total;
+    // guide of the prefix (or nullptr): s1_guide[b] = first v with
+    // s1_pre[v] > b << s1_shift, and s1_guide[last bucket + 1] = n - 1, so a
+    // draw r is searched for only between the guides of buckets r >> shift
+    // and the next
+    AGIS_GMEM const uint32_t* s1_guide;
+    uint32_t s1_shift;
+    uint32_t s1_pad;
 };
 
 // One launch ("round") of the sampler covers up to kMaxSegs segments: the

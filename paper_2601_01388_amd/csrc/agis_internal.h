@@ -136,6 +136,14 @@ hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg,
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
                        uint32_t* q1, uint64_t* pre, uint64_t* total);
 
+// Guide of an inclusive prefix pre[0..n) with total = pre[n - 1] > 0:
+// guide[b] = first v with pre[v] > b << shift for b < buckets =
+// ((total - 1) >> shift) + 1 <= 2^kGuideBits, guide[buckets] = n - 1.
+constexpr uint32_t kGuideBits = 16;
+uint32_t guide_shift(uint64_t total);
+hipError_t launch_prefix_guide(const uint64_t* pre, uint64_t n, uint64_t total, uint32_t shift, uint32_t* guide,
+                               hipStream_t stream);
+
 // Per-row pick table (per CSR slot, the inclusive u64 prefix of the integer
 // weights within the slot's row) of a weighted step with one backward vertex
 // whose per-vertex log weights (launch_step_log_weights) are sw.

@@ -94,10 +94,12 @@ struct Prepared {
     double scale = 1.0;  // embeddings per unit of the sample mean (k! on an oriented graph)
     uint32_t* q1 = nullptr;
     uint64_t* pre = nullptr;
+    uint32_t* guide = nullptr;
     double tables_seconds = 0;
     ~Prepared() {
         if (q1) (void)hipFree(q1);
         if (pre) (void)hipFree(pre);
+        if (guide) (void)hipFree(guide);
     }
 };
 
@@ -374,6 +376,15 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         hp.s1_q = agis::gmem((const uint32_t*)out->q1);
         hp.s1_pre = agis::gmem((const uint64_t*)out->pre);
         hp.s1_total = total;
+        if (total > 0) {
+            const uint32_t shift = agis::guide_shift(total);
+            const uint64_t buckets = ((total - 1) >> shift) + 1;
+            AGIS_HIP(ctx, hipMalloc(&out->guide, (buckets + 1) * sizeof(uint32_t)), "allocate first-step guide");
+            AGIS_HIP(ctx, agis::launch_prefix_guide(out->pre, g->g.n, total, shift, out->guide, ctx->stream),
+                     "first-step guide");
+            hp.s1_guide = agis::gmem((const uint32_t*)out->guide);
+            hp.s1_shift = shift;
+        }
     }
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "proposal tables");
     out->tables_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

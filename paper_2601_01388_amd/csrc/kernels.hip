@@ -909,6 +909,32 @@ hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t,
     return hipStreamSynchronize(st);
 }
 
+// Entry v owns the buckets b with pre[v - 1] <= b << shift < pre[v]
+// (pre[-1] = 0): it is the first entry above each of their lower bounds.
+__global__ void k_prefix_guide(const uint64_t* __restrict__ pre, uint64_t n, uint64_t buckets, uint32_t shift,
+                               uint32_t* __restrict__ guide) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const uint64_t lo = v ? pre[v - 1] : 0ull, hi = pre[v];
+    const uint64_t unit = 1ull << shift;
+    uint64_t b = (lo + unit - 1) >> shift;      // first b with b << shift >= lo
+    const uint64_t e = (hi + unit - 1) >> shift;  // first b with b << shift >= hi
+    for (; b < e && b < buckets; ++b) guide[b] = (uint32_t)v;
+    if (v == n - 1) guide[buckets] = (uint32_t)v;
+}
+
+uint32_t guide_shift(uint64_t total) {
+    const int bits = 64 - __builtin_clzll(total);
+    return bits > (int)kGuideBits ? (uint32_t)(bits - (int)kGuideBits) : 0u;
+}
+
+hipError_t launch_prefix_guide(const uint64_t* pre, uint64_t n, uint64_t total, uint32_t shift, uint32_t* guide,
+                               hipStream_t stream) {
+    const uint64_t buckets = ((total - 1) >> shift) + 1;
+    hipLaunchKernelGGL(k_prefix_guide, dim3(grid_for(n, 256)), dim3(256), 0, stream, pre, n, buckets, shift, guide);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Per-row pick tables of a weighted step with one backward vertex w: its
 // candidates are N(w) minus matched vertices, and the normalising maximum is
@@ -1230,7 +1256,14 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     break;
                 }
                 const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, P->s1_total);
-                v = (uint32_t)wave_first_greater(P->s1_pre, g.n, r);
+                if (P->s1_guide) {
+                    // the answer lies between the guides of r's bucket and the next
+                    const uint64_t bkt = r >> P->s1_shift;
+                    const uint32_t lo = P->s1_guide[bkt], hi = P->s1_guide[bkt + 1];
+                    v = lo + (uint32_t)wave_first_greater(P->s1_pre + lo, (uint64_t)(hi - lo) + 1, r);
+                } else {
+                    v = (uint32_t)wave_first_greater(P->s1_pre, g.n, r);
+                }
                 num = P->s1_total;
                 den = P->s1_q[v];
             } else {
