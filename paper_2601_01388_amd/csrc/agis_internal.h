@@ -72,6 +72,7 @@ struct agis_tables {
     // common-neighbour counts of the pair hubs (see DevTables)
     int32_t* pair_slot = nullptr;
     uint32_t* pair_count = nullptr;
+    uint32_t* pair_quart = nullptr;
     uint64_t pairs = 0;
     uint32_t pair_min_degree = 0;
 };
@@ -115,9 +116,11 @@ hipError_t launch_hub_slots(agis_ctx* ctx, const DevGraph& g, uint32_t min_deg, 
                             uint64_t* d_count);
 // pair_count[a * H + b] = |N(u_a) cap N(u_b)| for the H vertices with
 // pair_slot >= 0 (all of them hubs with bitmaps); the diagonal is 0.
+// pair_quart[(a * H + b) * 3 + j - 1] = common neighbours before position
+// j d / 4 of the walked list (the shorter of the two by (degree, id)).
 hipError_t launch_pair_counts(agis_ctx* ctx, const DevGraph& g, const int32_t* hub_slot, const uint32_t* hub_bits,
                               uint64_t hub_words, const int32_t* pair_slot, uint64_t H, uint32_t* pair_hub,
-                              uint32_t* pair_count);
+                              uint32_t* pair_count, uint32_t* pair_quart);
 hipError_t launch_hub_bits(const DevGraph& g, const int32_t* hub_slot, uint64_t words, uint32_t* bits,
                            hipStream_t stream);
 // Degree orientation: out-degrees into outdeg (n entries of scratch), the

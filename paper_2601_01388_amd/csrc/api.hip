@@ -181,12 +181,13 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
     auto drop_out_of_memory = [&]() {
         (void)hipGetLastError();
         for (void* q : {(void*)flags, (void*)prefix, (void*)t->hub_slot, (void*)t->hub_bits, (void*)t->pair_slot,
-                        (void*)t->pair_count})
+                        (void*)t->pair_count, (void*)t->pair_quart})
             if (q) (void)hipFree(q);
         t->hub_slot = nullptr;
         t->hub_bits = nullptr;
         t->pair_slot = nullptr;
         t->pair_count = nullptr;
+        t->pair_quart = nullptr;
         t->hub_words = t->hubs = t->pairs = 0;
         return hipSuccess;
     };
@@ -239,16 +240,19 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
     if (e == hipSuccess && H >= 2) {
         e = hipMalloc(&pair_hub, H * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&t->pair_count, H * H * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&t->pair_quart, H * H * 3 * sizeof(uint32_t));
         if (e == hipErrorOutOfMemory) {
             // no room for the pair-hub table: keep the bitmaps without it
             (void)hipGetLastError();
             if (t->pair_count) (void)hipFree(t->pair_count);
+            if (t->pair_quart) (void)hipFree(t->pair_quart);
             t->pair_count = nullptr;
+            t->pair_quart = nullptr;
             H = 0;
             e = hipSuccess;
         } else if (e == hipSuccess)
             e = agis::launch_pair_counts(ctx, g->g, t->hub_slot, t->hub_bits, words, t->pair_slot, H, pair_hub,
-                                         t->pair_count);
+                                         t->pair_count, t->pair_quart);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e == hipSuccess) {
             t->pairs = H;
@@ -265,7 +269,7 @@ agis::DevTables dev_tables(const agis_tables* t) {
     return agis::DevTables{agis::gmem((const uint4*)t->rec),        agis::gmem((const uint32_t*)t->hub_bits),
                            agis::gmem((const int32_t*)t->hub_slot),    t->hub_words,
                            agis::gmem((const int32_t*)t->pair_slot),   agis::gmem((const uint32_t*)t->pair_count),
-                           t->pair_count ? t->pairs : 0};
+                           t->pair_count ? t->pairs : 0,               agis::gmem((const uint32_t*)t->pair_quart)};
 }
 
 int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p, const uint8_t* order,
@@ -767,6 +771,7 @@ void agis_tables_destroy(agis_tables* t) {
     if (t->hub_slot) (void)hipFree(t->hub_slot);
     if (t->pair_slot) (void)hipFree(t->pair_slot);
     if (t->pair_count) (void)hipFree(t->pair_count);
+    if (t->pair_quart) (void)hipFree(t->pair_quart);
     delete t;
 }
 

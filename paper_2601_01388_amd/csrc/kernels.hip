@@ -834,44 +834,61 @@ __global__ void k_pair_hubs(const int32_t* __restrict__ pair_slot, uint64_t n, u
 __global__ __launch_bounds__(256) void k_pair_counts(DevGraph g, const int32_t* __restrict__ hub_slot,
                                                       const uint32_t* __restrict__ hub_bits, uint64_t hub_words,
                                                       const uint32_t* __restrict__ pair_hub, uint64_t H,
-                                                      uint32_t* __restrict__ pair_count) {
+                                                      uint32_t* __restrict__ pair_count,
+                                                      uint32_t* __restrict__ pair_quart) {
     const int lane = lane_id();
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
     for (uint64_t pr = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; pr < H * H; pr += nw) {
         const uint64_t a = pr / H, b = pr % H;
         if (a > b) continue;  // wave-uniform
         if (a == b) {
-            if (lane == 0) pair_count[pr] = 0u;
+            if (lane == 0) {
+                pair_count[pr] = 0u;
+                for (int j = 0; j < 3; ++j) pair_quart[pr * 3 + j] = 0u;
+            }
             continue;
         }
         const uint32_t va = pair_hub[a], vb = pair_hub[b];
         const uint64_t oa = g.off[va], ob = g.off[vb];
         const uint64_t da = g.off[va + 1] - oa, db = g.off[vb + 1] - ob;
-        // walk the shorter list, probe the other's bitmap
-        const bool walk_a = da <= db;
+        // walk the shorter list (by (degree, id)), probe the other's bitmap
+        const bool walk_a = da < db || (da == db && va < vb);
         const uint64_t o = walk_a ? oa : ob, d = walk_a ? da : db;
         const uint32_t* bits = hub_bits + (uint64_t)hub_slot[walk_a ? vb : va] * hub_words;
-        uint32_t c = 0;
+        const uint64_t p1 = d / 4, p2 = d / 2, p3 = 3 * d / 4;
+        uint32_t c = 0, c1 = 0, c2 = 0, c3 = 0;
         for (uint64_t e = (uint64_t)lane; e < d; e += kWave) {
             const uint32_t x = g.nbr[o + e];
-            c += (bits[x >> 5] >> (x & 31u)) & 1u;
+            const uint32_t m = (bits[x >> 5] >> (x & 31u)) & 1u;
+            c += m;
+            c1 += e < p1 ? m : 0u;
+            c2 += e < p2 ? m : 0u;
+            c3 += e < p3 ? m : 0u;
         }
         c = (uint32_t)wave_sum_u64(c);
+        c1 = (uint32_t)wave_sum_u64(c1);
+        c2 = (uint32_t)wave_sum_u64(c2);
+        c3 = (uint32_t)wave_sum_u64(c3);
         if (lane == 0) {
             pair_count[a * H + b] = c;
             pair_count[b * H + a] = c;
+            const uint32_t q[3] = {c1, c2, c3};
+            for (int j = 0; j < 3; ++j) {
+                pair_quart[(a * H + b) * 3 + j] = q[j];
+                pair_quart[(b * H + a) * 3 + j] = q[j];
+            }
         }
     }
 }
 
 hipError_t launch_pair_counts(agis_ctx* ctx, const DevGraph& g, const int32_t* hub_slot, const uint32_t* hub_bits,
                               uint64_t hub_words, const int32_t* pair_slot, uint64_t H, uint32_t* pair_hub,
-                              uint32_t* pair_count) {
+                              uint32_t* pair_count, uint32_t* pair_quart) {
     hipLaunchKernelGGL(k_pair_hubs, dim3(grid_for(g.n, 256)), dim3(256), 0, ctx->stream, pair_slot, g.n, pair_hub);
     const uint64_t waves = H * H;
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, (uint64_t)ctx->num_cus * 8);
     hipLaunchKernelGGL(k_pair_counts, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, g, hub_slot, hub_bits,
-                       hub_words, pair_hub, H, pair_count);
+                       hub_words, pair_hub, H, pair_count, pair_quart);
     return hipGetLastError();
 }
 
@@ -1181,10 +1198,13 @@ __device__ __forceinline__ bool pair_hub_count(const DevTables& t, uint32_t my_t
 }
 
 // The element of rank r (ascending, 0-based) of S = (N(a) cap N(b)) minus
-// the matched vertices, |S| = m, for two pair hubs a and b (bm): the shorter
-// list is walked 64 elements at a time, each probed in the other's bitmap,
-// from its start when r lies in the lower half of S and from its end
-// otherwise (ranks then counted from the top).
+// the matched vertices, |S| = m, for two pair hubs a and b (bm).  The
+// shorter list (by (degree, id)) is cut at positions d/4, d/2 and 3d/4;
+// the table holds how many common neighbours lie before each cut, less
+// here the matched ones (their ids are compared with the elements at the
+// cuts).  The quarter holding rank r is walked 64 elements at a time, each
+// probed in the other hub's bitmap, from its nearer end (ranks then counted
+// from that end).
 __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const DevTables& t, uint32_t my_tau, uint32_t bm,
                                                     uint32_t i, uint64_t r, uint64_t m) {
     const int lane = lane_id();
@@ -1192,28 +1212,50 @@ __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const Dev
     const uint32_t b = readlane_u32(my_tau, 31 - __builtin_clz(bm));
     const uint64_t oa = g.off[a], ob = g.off[b];
     const uint64_t da = g.off[a + 1] - oa, db = g.off[b + 1] - ob;
-    const bool walk_a = da <= db;
+    const bool walk_a = da < db || (da == db && a < b);
     const uint32_t* list = g.nbr + (walk_a ? oa : ob);
     const uint64_t d = walk_a ? da : db;
     const auto row = t.hub_bits + (uint64_t)t.hub_slot[walk_a ? b : a] * t.hub_words;
-    const bool forward = r < m - r;
-    const uint64_t target = forward ? r : m - 1 - r;
+    // matched vertices (other than a and b) that lie in both lists
+    bool both = false;
+    if ((uint32_t)lane < i && my_tau != a && my_tau != b) {
+        const auto ra = t.hub_bits + (uint64_t)t.hub_slot[a] * t.hub_words;
+        const auto rb = t.hub_bits + (uint64_t)t.hub_slot[b] * t.hub_words;
+        const uint32_t w = my_tau >> 5, mk = 1u << (my_tau & 31u);
+        both = (ra[w] & mk) != 0 && (rb[w] & mk) != 0;
+    }
+    // the cuts: positions and members of S before them
+    const uint64_t pos[5] = {0, d / 4, d / 2, 3 * d / 4, d};
+    uint64_t cnt[5];
+    cnt[0] = 0;
+    cnt[4] = m;
+    const auto q = t.pair_quart + ((uint64_t)t.pair_slot[a] * t.pairs + (uint64_t)t.pair_slot[b]) * 3;
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+        const uint32_t cut = list[pos[j]];
+        cnt[j] = (uint64_t)q[j - 1] - (uint64_t)__popcll(__ballot(both && my_tau < cut));
+    }
+    int s = 0;
+    while (s < 3 && cnt[s + 1] <= r) ++s;  // quarter s holds rank r
+    const bool forward = r - cnt[s] <= cnt[s + 1] - 1 - r;
+    const uint64_t target = forward ? r - cnt[s] : cnt[s + 1] - 1 - r;
+    const uint64_t from = pos[s], len = pos[s + 1] - pos[s];
     uint64_t seen = 0;
-    for (uint64_t c = 0; c < d; c += kWave) {
+    for (uint64_t c = 0; c < len; c += kWave) {
         const uint64_t e = c + (uint64_t)lane;
-        const bool valid = e < d;
-        const uint32_t x = valid ? list[forward ? e : d - 1 - e] : 0u;
+        const bool valid = e < len;
+        const uint32_t x = valid ? list[forward ? from + e : from + len - 1 - e] : 0u;
         bool keep = valid && ((row[x >> 5] >> (x & 31u)) & 1u) != 0;
         for (uint32_t j = 0; j < i; ++j) keep = keep && x != readlane_u32(my_tau, (int)j);
         uint64_t bal = __ballot(keep);
         const uint64_t n = (uint64_t)__popcll(bal);
         if (seen + n > target) {
-            for (uint64_t q = target - seen; q > 0; --q) bal &= bal - 1;
+            for (uint64_t k = target - seen; k > 0; --k) bal &= bal - 1;
             return readlane_u32(x, __builtin_ctzll(bal));
         }
         seen += n;
     }
-    return 0u;  // not reached: S holds m elements
+    return 0u;  // not reached: the quarter holds the rank
 }
 
 // Log weight of candidate v at a weighted step: one 4-byte read of the
