@@ -151,10 +151,13 @@ struct DevTables {
     AGIS_GMEM const int32_t* pair_slot;
     AGIS_GMEM const uint32_t* pair_count;
     uint64_t pairs;
-    // per pair, 3 entries: the common neighbours lying before positions
-    // d/4, d/2 and 3d/4 of the walked list (the shorter by (degree, id))
+    // per pair, kPairParts - 1 entries: the common neighbours lying before
+    // positions j d / kPairParts (j = 1 .. kPairParts - 1) of the walked list
+    // (the shorter of the two by (degree, id))
     AGIS_GMEM const uint32_t* pair_quart;
 };
+
+constexpr int kPairParts = 8;
 
 struct DevPlan {
     uint32_t k;

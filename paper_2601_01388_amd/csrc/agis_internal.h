@@ -116,8 +116,9 @@ hipError_t launch_hub_slots(agis_ctx* ctx, const DevGraph& g, uint32_t min_deg, 
                             uint64_t* d_count);
 // pair_count[a * H + b] = |N(u_a) cap N(u_b)| for the H vertices with
 // pair_slot >= 0 (all of them hubs with bitmaps); the diagonal is 0.
-// pair_quart[(a * H + b) * 3 + j - 1] = common neighbours before position
-// j d / 4 of the walked list (the shorter of the two by (degree, id)).
+// pair_quart[(a * H + b) * (kPairParts - 1) + j - 1] = common neighbours
+// before position j d / kPairParts of the walked list (the shorter of the
+// two by (degree, id)).
 hipError_t launch_pair_counts(agis_ctx* ctx, const DevGraph& g, const int32_t* hub_slot, const uint32_t* hub_bits,
                               uint64_t hub_words, const int32_t* pair_slot, uint64_t H, uint32_t* pair_hub,
                               uint32_t* pair_count, uint32_t* pair_quart);

@@ -240,7 +240,7 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
     if (e == hipSuccess && H >= 2) {
         e = hipMalloc(&pair_hub, H * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&t->pair_count, H * H * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc(&t->pair_quart, H * H * 3 * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&t->pair_quart, H * H * (agis::kPairParts - 1) * sizeof(uint32_t));
         if (e == hipErrorOutOfMemory) {
             // no room for the pair-hub table: keep the bitmaps without it
             (void)hipGetLastError();

@@ -844,7 +844,7 @@ __global__ __launch_bounds__(256) void k_pair_counts(DevGraph g, const int32_t* 
         if (a == b) {
             if (lane == 0) {
                 pair_count[pr] = 0u;
-                for (int j = 0; j < 3; ++j) pair_quart[pr * 3 + j] = 0u;
+                for (int j = 0; j < kPairParts - 1; ++j) pair_quart[pr * (kPairParts - 1) + j] = 0u;
             }
             continue;
         }
@@ -855,28 +855,32 @@ __global__ __launch_bounds__(256) void k_pair_counts(DevGraph g, const int32_t* 
         const bool walk_a = da < db || (da == db && va < vb);
         const uint64_t o = walk_a ? oa : ob, d = walk_a ? da : db;
         const uint32_t* bits = hub_bits + (uint64_t)hub_slot[walk_a ? vb : va] * hub_words;
-        const uint64_t p1 = d / 4, p2 = d / 2, p3 = 3 * d / 4;
-        uint32_t c = 0, c1 = 0, c2 = 0, c3 = 0;
+        // members per part: part j holds positions [j d / P, (j + 1) d / P)
+        uint32_t cp[kPairParts];
+#pragma unroll
+        for (int j = 0; j < kPairParts; ++j) cp[j] = 0u;
         for (uint64_t e = (uint64_t)lane; e < d; e += kWave) {
             const uint32_t x = g.nbr[o + e];
             const uint32_t m = (bits[x >> 5] >> (x & 31u)) & 1u;
-            c += m;
-            c1 += e < p1 ? m : 0u;
-            c2 += e < p2 ? m : 0u;
-            c3 += e < p3 ? m : 0u;
+            // the part of position e: the largest j with j d / P <= e
+            int part = (int)((e * kPairParts) / d);
+            while (part + 1 < kPairParts && (uint64_t)(part + 1) * d / kPairParts <= e) ++part;
+            while (part > 0 && (uint64_t)part * d / kPairParts > e) --part;
+#pragma unroll
+            for (int j = 0; j < kPairParts; ++j) cp[j] += j == part ? m : 0u;
         }
-        c = (uint32_t)wave_sum_u64(c);
-        c1 = (uint32_t)wave_sum_u64(c1);
-        c2 = (uint32_t)wave_sum_u64(c2);
-        c3 = (uint32_t)wave_sum_u64(c3);
-        if (lane == 0) {
-            pair_count[a * H + b] = c;
-            pair_count[b * H + a] = c;
-            const uint32_t q[3] = {c1, c2, c3};
-            for (int j = 0; j < 3; ++j) {
-                pair_quart[(a * H + b) * 3 + j] = q[j];
-                pair_quart[(b * H + a) * 3 + j] = q[j];
+        uint32_t run = 0;
+        for (int j = 0; j < kPairParts; ++j) {
+            const uint32_t sj = (uint32_t)wave_sum_u64(cp[j]);
+            if (lane == 0 && j > 0) {
+                pair_quart[(a * H + b) * (kPairParts - 1) + j - 1] = run;
+                pair_quart[(b * H + a) * (kPairParts - 1) + j - 1] = run;
             }
+            run += sj;
+        }
+        if (lane == 0) {
+            pair_count[a * H + b] = run;
+            pair_count[b * H + a] = run;
         }
     }
 }
@@ -1199,12 +1203,12 @@ __device__ __forceinline__ bool pair_hub_count(const DevTables& t, uint32_t my_t
 
 // The element of rank r (ascending, 0-based) of S = (N(a) cap N(b)) minus
 // the matched vertices, |S| = m, for two pair hubs a and b (bm).  The
-// shorter list (by (degree, id)) is cut at positions d/4, d/2 and 3d/4;
-// the table holds how many common neighbours lie before each cut, less
-// here the matched ones (their ids are compared with the elements at the
-// cuts).  The quarter holding rank r is walked 64 elements at a time, each
-// probed in the other hub's bitmap, from its nearer end (ranks then counted
-// from that end).
+// shorter list (by (degree, id)) is cut into kPairParts parts at positions
+// j d / kPairParts; the table holds how many common neighbours lie before
+// each cut, less here the matched ones (their ids are compared with the
+// elements at the cuts).  The part holding rank r is walked 64 elements at
+// a time, each probed in the other hub's bitmap, from its nearer end (ranks
+// then counted from that end).
 __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const DevTables& t, uint32_t my_tau, uint32_t bm,
                                                     uint32_t i, uint64_t r, uint64_t m) {
     const int lane = lane_id();
@@ -1224,22 +1228,31 @@ __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const Dev
         const uint32_t w = my_tau >> 5, mk = 1u << (my_tau & 31u);
         both = (ra[w] & mk) != 0 && (rb[w] & mk) != 0;
     }
-    // the cuts: positions and members of S before them
-    const uint64_t pos[5] = {0, d / 4, d / 2, 3 * d / 4, d};
-    uint64_t cnt[5];
-    cnt[0] = 0;
-    cnt[4] = m;
-    const auto q = t.pair_quart + ((uint64_t)t.pair_slot[a] * t.pairs + (uint64_t)t.pair_slot[b]) * 3;
+    // the cuts j d / P: members of S before each (the part holding rank r
+    // lies between the last cut at or below r and the next)
+    const auto q = t.pair_quart + ((uint64_t)t.pair_slot[a] * t.pairs + (uint64_t)t.pair_slot[b]) * (kPairParts - 1);
+    uint32_t cutv[kPairParts - 1], qv[kPairParts - 1];
 #pragma unroll
-    for (int j = 1; j < 4; ++j) {
-        const uint32_t cut = list[pos[j]];
-        cnt[j] = (uint64_t)q[j - 1] - (uint64_t)__popcll(__ballot(both && my_tau < cut));
+    for (int j = 1; j < kPairParts; ++j) {
+        cutv[j - 1] = list[(uint64_t)j * d / kPairParts];
+        qv[j - 1] = q[j - 1];
     }
     int s = 0;
-    while (s < 3 && cnt[s + 1] <= r) ++s;  // quarter s holds rank r
-    const bool forward = r - cnt[s] <= cnt[s + 1] - 1 - r;
-    const uint64_t target = forward ? r - cnt[s] : cnt[s + 1] - 1 - r;
-    const uint64_t from = pos[s], len = pos[s + 1] - pos[s];
+    uint64_t lo_cnt = 0, hi_cnt = m;
+#pragma unroll
+    for (int j = 1; j < kPairParts; ++j) {
+        const uint64_t cj = (uint64_t)qv[j - 1] - (uint64_t)__popcll(__ballot(both && my_tau < cutv[j - 1]));
+        if (cj <= r) {
+            s = j;
+            lo_cnt = cj;
+        } else {
+            hi_cnt = cj;
+            break;
+        }
+    }
+    const bool forward = r - lo_cnt <= hi_cnt - 1 - r;
+    const uint64_t target = forward ? r - lo_cnt : hi_cnt - 1 - r;
+    const uint64_t from = (uint64_t)s * d / kPairParts, len = (uint64_t)(s + 1) * d / kPairParts - from;
     uint64_t seen = 0;
     for (uint64_t c = 0; c < len; c += kWave) {
         const uint64_t e = c + (uint64_t)lane;
@@ -1255,7 +1268,7 @@ __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const Dev
         }
         seen += n;
     }
-    return 0u;  // not reached: the quarter holds the rank
+    return 0u;  // not reached: the part holds the rank
 }
 
 // Log weight of candidate v at a weighted step: one 4-byte read of the
