@@ -1602,24 +1602,46 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     den = 1;
                 } else {
                     const int32_t lmax = (int32_t)uniform_u32((uint32_t)wave_max_i32(lmax_l));
+                    // Lane l sums the weights of the consecutive candidates
+                    // [l B, (l + 1) B); one scan of the 64 sums then finds
+                    // the block holding the draw, and the wave searches that
+                    // block alone (candidate order is kept throughout).  For
+                    // large sets (B > 8) a lane's block is read in strides
+                    // of 64 instead (coalesced), and the blocks are 64 wide.
+                    const bool blocked = cnt <= (uint64_t)kWave * 8;
+                    const uint64_t B = blocked ? (cnt + kWave - 1) / kWave : cnt;
+                    const uint64_t b0 = (uint64_t)lane * B;
+                    const uint64_t b1 = b0 + B < cnt ? b0 + B : cnt;
                     uint64_t qs = 0;
-                    for (uint64_t c = (uint64_t)lane; c < cnt; c += kWave) {
-                        const int32_t l = sl[c];
-                        qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+                    if (blocked) {
+                        for (uint64_t c = b0; c < b1; ++c) {
+                            const int32_t l = sl[c];
+                            qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+                        }
+                    } else {
+                        for (uint64_t c = (uint64_t)lane; c < cnt; c += kWave) {
+                            const int32_t l = sl[c];
+                            qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+                        }
                     }
-                    const uint64_t Q = uniform_u64(wave_sum_u64(qs));
+                    const uint64_t lincl = blocked ? wave_incl_scan_u64(qs) : wave_sum_u64(qs);
+                    const uint64_t Q = uniform_u64(readlane_u64(lincl, kWave - 1));
                     if (Q == 0) {
                         fail = (int)i;
                         break;
                     }
                     const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
-                    uint64_t run = 0;
+                    // unblocked: one block [0, cnt) searched from the start
+                    const int LB = blocked ? __ffsll((unsigned long long)__ballot(lincl > r)) - 1 : 0;
+                    uint64_t run = blocked ? readlane_u64(lincl - qs, LB) : 0ull;
+                    const uint64_t bs = (uint64_t)LB * B;
+                    const uint64_t be = bs + B < cnt ? bs + B : cnt;
                     v = 0;
                     den = 0;
-                    for (uint64_t c0i = 0; c0i < cnt; c0i += kWave) {
+                    for (uint64_t c0i = bs; c0i < be; c0i += kWave) {
                         const uint64_t c = c0i + (uint64_t)lane;
                         uint32_t q = 0;
-                        if (c < cnt) {
+                        if (c < be) {
                             const int32_t l = sl[c];
                             q = l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
                         }
