@@ -308,10 +308,11 @@ typedef struct {
 
 /* Times pilot batches (pilot_samples samples of each of the n_patterns
  * patterns, fixed budgets, params' mode and beta) under each candidate
- * launch configuration -- kernel register-budget variant x queue grab,
- * then the hub-bitmap window --
- * and applies the fastest to the context (as agis_set_launch would).
- * Results of later calls do not depend on the choice. */
+ * launch configuration -- kernel register-budget variant (0, 1, 2) x queue
+ * grab (1, 2, 4 slots), then the hub-bitmap window (256, 1024, 4096) --
+ * and applies the fastest to the context (as agis_set_launch would); a
+ * candidate must beat the best so far by 2% to be taken.  Results of later
+ * calls do not depend on the choice. */
 int agis_autotune(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint32_t n_patterns,
                   const agis_pattern* patterns, uint64_t pilot_samples, const agis_run_params* params,
                   agis_tuning* out);
