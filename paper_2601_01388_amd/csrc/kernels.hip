@@ -272,29 +272,29 @@ __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict
         bool hit = false;
         for (;;) {
             const int32_t e = qs + 4 * lane;
+            // The block read as one ascending sequence: zero fill before the
+            // list's start, the list, none after its end.  Its elements
+            // before pos are at most the previous chunk's largest element,
+            // so below every xv of this chunk: they never match xv and never
+            // end the window.
             uint32_t v0, v1, v2, v3;
-            if (qs >= 0 && qs + 4 * kWave <= ilen) {
-                // the whole block lies in the list (wave-uniform test)
+            if (qs >= 0 && qs + 4 * kWave <= ilen) {  // the whole block is in the list
                 const uint4 q = *reinterpret_cast<const uint4*>(list + e);
                 v0 = q.x;
                 v1 = q.y;
                 v2 = q.z;
                 v3 = q.w;
             } else {
-                // a block at either end of the list: per element, zero
-                // before the list's start (never counted: before pos), none
-                // after its end
                 v0 = e < 0 ? 0u : (e < ilen ? list[e] : kNone);
                 v1 = e + 1 < 0 ? 0u : (e + 1 < ilen ? list[e + 1] : kNone);
                 v2 = e + 2 < 0 ? 0u : (e + 2 < ilen ? list[e + 2] : kNone);
                 v3 = e + 3 < ilen ? list[e + 3] : kNone;
             }
-            // window end: first element at or after pos above xlast
-            const int32_t dp = ipos - e;  // elements of this quad before pos
-            const uint64_t m0 = __ballot((dp <= 0) & (v0 > xlast));
-            const uint64_t m1 = __ballot((dp <= 1) & (v1 > xlast));
-            const uint64_t m2 = __ballot((dp <= 2) & (v2 > xlast));
-            const uint64_t m3 = __ballot((dp <= 3) & (v3 > xlast));
+            // the elements <= xlast form a prefix of the block
+            const uint64_t m0 = __ballot(v0 > xlast);
+            const uint64_t m1 = __ballot(v1 > xlast);
+            const uint64_t m2 = __ballot(v2 > xlast);
+            const uint64_t m3 = __ballot(v3 > xlast);
             // membership of xv: the lane whose quad may hold it, then its quad
             int lo = 0;
 #pragma unroll
@@ -306,19 +306,14 @@ __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict
             const uint32_t a1 = bperm(v1, lo);
             const uint32_t a2 = bperm(v2, lo);
             const uint32_t a3 = bperm(v3, lo);
-            // only elements at or after pos count (this also excludes the
-            // zero fill before the list's start)
-            const int32_t dl = ipos - (qs + 4 * lo);
-            hit = hit | ((a0 == xv) & (dl <= 0)) | ((a1 == xv) & (dl <= 1)) | ((a2 == xv) & (dl <= 2)) |
-                  ((a3 == xv) & (dl <= 3));
+            // the zero fill before the list's start (at most the first 3
+            // elements of the block) may equal xv = 0
+            const int32_t fill = -(qs + 4 * lo);
+            hit = hit | ((a0 == xv) & (fill <= 0)) | ((a1 == xv) & (fill <= 1)) | ((a2 == xv) & (fill <= 2)) |
+                  (a3 == xv);
             if ((m0 | m1 | m2 | m3) != 0) {
-                int32_t endi = INT32_MAX;
-                if (m0) endi = qs + 4 * (__ffsll((unsigned long long)m0) - 1);
-                if (m1) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m1) - 1) + 1);
-                if (m2) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m2) - 1) + 2);
-                if (m3) endi = min(endi, qs + 4 * (__ffsll((unsigned long long)m3) - 1) + 3);
                 member = member && hit;
-                return (uint32_t)endi;
+                return (uint32_t)(qs + __popcll(~m0) + __popcll(~m1) + __popcll(~m2) + __popcll(~m3));
             }
             qs += 4 * kWave;
         }
@@ -1499,7 +1494,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     const int jb = (int)(key & 0xFF);
                     base = g.nbr + readlane_u64(my_o, jb);
                     db = readlane_u32(my_d, jb);
-                    others = lists & ~(1u << jb);
+                    others = uniform_u32(lists & ~(1u << jb));
                 }
                 const uint32_t b = P->b[i], f1 = P->f1[i], ie = P->ie[i], f2 = P->f2[i];
                 const AGIS_GMEM int32_t* lt = P->lt[i];
