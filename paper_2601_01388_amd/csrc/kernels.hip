@@ -1525,22 +1525,32 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 // (gathered from the step table) are stored and folded into
                 // the maximum during the next chunk, so base, window and
                 // weight loads of neighbouring chunks are in flight together.
+                // Two register sets take turns (the loop runs chunks in
+                // pairs), so no value still in flight is copied from one
+                // chunk to the next: the copy would wait for its load.  A
+                // chunk's largest element (xlast) is read from the prefetch
+                // after the previous chunk's list loads, which the prefetch
+                // preceded, have been waited for.
                 // In-place compaction stays safe when base == sv: every store
                 // lands below the chunk being read, and the prefetched chunk
                 // lies above both.
                 constexpr uint32_t kNone = 0xFFFFFFFFu;
-                uint32_t xv_next = (uint32_t)lane < db ? base[lane] : kNone;
-                int32_t pend_l = kCertainZero;  // previous chunk: gathered log weight,
-                uint32_t pend_p = 0;            // its scratch slot,
-                bool pend_member = false;       // whether it is in I,
-                bool pend_keep = false;         // whether it is stored
-                for (uint32_t c = 0; c < db; c += kWave) {
+                uint32_t xa = (uint32_t)lane < db ? base[lane] : kNone, xb = kNone;
+                // (read unconditionally: every load issued so far is then
+                // known to have arrived before the loop)
+                uint32_t xlast_next = readlane_u32(xa, db == 0 ? 0 : (int)(db < (uint32_t)kWave ? db : (uint32_t)kWave) - 1);
+                // per set: a chunk's gathered log weight (kCertainZero when
+                // the candidate is not in I or the step is unweighted) and
+                // the scratch slot it is stored at (kNone: not stored)
+                int32_t la = kCertainZero, lb = kCertainZero;
+                uint32_t pa = kNone, pb = kNone;
+                auto chunk = [&](uint32_t c, uint32_t xv, uint32_t& x_next, int32_t& l_out, uint32_t& p_out,
+                                 int32_t l_prev, uint32_t p_prev) {
                     const uint32_t nvalid = (db - c) < (uint32_t)kWave ? (db - c) : (uint32_t)kWave;
                     const bool valid = (uint32_t)lane < nvalid;
-                    const uint32_t xv = xv_next;
+                    const uint32_t xlast = xlast_next;
                     const uint32_t nx = c + (uint32_t)kWave + (uint32_t)lane;
-                    xv_next = nx < db ? base[nx] : kNone;
-                    const uint32_t xlast = readlane_u32(xv, (int)nvalid - 1);
+                    x_next = nx < db ? base[nx] : kNone;
                     bool member = valid;
                     for (uint32_t bits = others; bits; bits &= bits - 1) {
                         const int j = __builtin_ctz(bits);
@@ -1548,8 +1558,14 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         if (slot >= 0) {
                             // a hub's list: one bit probe per element
                             if (member) {
-                                const uint32_t wd = t.hub_bits[(uint64_t)slot * t.hub_words + (xv >> 5)];
-                                member = (wd >> (xv & 31u)) & 1u;
+                                // xv passes through an empty asm statement, so
+                                // that the probe's address is not computed
+                                // ahead of the list loop (where it would wait
+                                // for the prefetch issued just before)
+                                uint32_t x = xv;
+                                asm volatile("" : "+v"(x));
+                                const uint32_t wd = t.hub_bits[(uint64_t)slot * t.hub_words + (x >> 5)];
+                                member = (wd >> (x & 31u)) & 1u;
                             }
                             continue;
                         }
@@ -1559,8 +1575,15 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         const uint32_t end = co_iterate_member(lj, pos, dj, xv, xlast, db - c, member);
                         if (lane == j) my_pos = end;
                     }
-                    if (pend_member && pend_l != kCertainZero && pend_l > lmax_l) lmax_l = pend_l;
-                    if (pend_keep) sl[pend_p] = pend_l;
+                    {
+                        // elements of the next chunk (none past the last)
+                        const uint32_t nn = db - c > (uint32_t)kWave ? db - c - (uint32_t)kWave : 1u;
+                        xlast_next = readlane_u32(x_next, (int)(nn < (uint32_t)kWave ? nn : (uint32_t)kWave) - 1);
+                    }
+                    // the previous chunk's weights (kCertainZero is the
+                    // identity of the maximum)
+                    lmax_l = l_prev > lmax_l ? l_prev : lmax_l;
+                    if (p_prev != kNone) sl[p_prev] = l_prev;
                     int32_t l = kCertainZero;
                     if (weighted && member) l = step_log_weight(t, sw, lt, xv, b, f1, ie, f2);
                     bool in_tau = false;
@@ -1571,19 +1594,27 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     }
                     const bool keep = member && !in_tau;
                     const uint64_t km = __ballot(keep);
-                    uint32_t p = 0;
+                    uint32_t p = kNone;
                     if (keep && !count_only) {
                         p = (uint32_t)cnt + (uint32_t)__popcll(km & lanemask_lt());
                         sv[p] = xv;
                     }
-                    pend_member = weighted && member;
-                    pend_keep = weighted && keep;
-                    pend_p = p;
-                    pend_l = l;
+                    l_out = l;
+                    p_out = weighted && keep ? p : kNone;
                     cnt += (uint64_t)__popcll(km);
+                };
+                for (uint32_t c = 0; c < db; c += 2 * (uint32_t)kWave) {
+                    chunk(c, xa, xb, la, pa, lb, pb);
+                    if (c + (uint32_t)kWave >= db) break;
+                    chunk(c + (uint32_t)kWave, xb, xa, lb, pb, la, pa);
                 }
-                if (pend_member && pend_l != kCertainZero && pend_l > lmax_l) lmax_l = pend_l;
-                if (pend_keep) sl[pend_p] = pend_l;
+                // The last chunk's weights.  The other set was taken up by
+                // that chunk already: storing it again writes the same value
+                // and the maximum is unchanged.
+                lmax_l = la > lmax_l ? la : lmax_l;
+                lmax_l = lb > lmax_l ? lb : lmax_l;
+                if (pa != kNone) sl[pa] = la;
+                if (pb != kNone) sl[pb] = lb;
                 scnt = cnt;
                 __threadfence_block();
                 if (!weighted) {
