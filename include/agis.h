@@ -285,8 +285,8 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
  * blocks_per_cu = resident 256-thread workgroups per compute unit (0 = as
  * many as fit); grab = sample slots a wave takes from the queue at a time
  * (0 = chosen from the round size, at most 1024); variant = register
- * budget of the sampling kernel (0 = compiler's choice; 1 and 2 = small
- * enough for 7 and 8 resident waves per SIMD, spilling the rest);
+ * budget of the sampling kernel (0, 1 and 2 = small enough for 6, 7 and 8
+ * resident waves per SIMD; the smaller budgets spill a few registers);
  * hub_window: a high-degree vertex's neighbourhood bitmap (built with the
  * tables) replaces the merge with its list when the list is at least
  * hub_window / 64 times as long as the set it is intersected with (0 =

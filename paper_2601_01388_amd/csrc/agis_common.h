@@ -95,9 +95,10 @@ AGIS_HD int32_t log2fx(uint64_t x, const int32_t* logtab) {
 }
 
 AGIS_HD uint32_t weight_from_log(int32_t lmax, int32_t l, const uint32_t* exp2tab) {
-    uint32_t delta = (uint32_t)(lmax - l);
-    uint32_t sh = delta >> 16;
-    uint32_t q = sh >= 32u ? 0u : (exp2tab[(delta & 0xFFFFu) >> 4] >> sh);
+    const uint32_t delta = (uint32_t)lmax - (uint32_t)l;
+    const uint32_t sh = delta >> 16;
+    const uint32_t e = exp2tab[(delta & 0xFFFFu) >> 4];  // in the table for any delta
+    const uint32_t q = sh >= 32u ? 0u : (e >> sh);
     return q < 1u ? 1u : q;
 }
 

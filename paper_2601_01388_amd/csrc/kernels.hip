@@ -20,6 +20,9 @@ namespace agis {
 
 __constant__ int32_t c_logtab[4096];
 __constant__ uint32_t c_exp2tab[4096];
+// the same table staged in LDS by the sampling kernel (each block fills its
+// copy once), for the weighted picks
+__shared__ uint32_t s_exp2tab[4096];
 
 namespace {
 std::vector<int32_t> g_logtab;
@@ -1280,6 +1283,9 @@ __device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int
 // rec != nullptr.  `my_tau` of lane j holds the data vertex matched at step
 // j (wave-uniform by construction).  sv/sl: this wave's scratch for the
 // candidate vertices and their log weights (capacity >= max degree).
+// candidates per lane up to which a weighted pick keeps them in registers
+constexpr int kPickBlock = 8;
+
 template <bool kDump, bool kPairs>
 __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P,
                              uint32_t k0, uint32_t k1, uint64_t s, uint32_t* __restrict__ sv,
@@ -1628,61 +1634,100 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     den = 1;
                 } else {
                     const int32_t lmax = (int32_t)uniform_u32((uint32_t)wave_max_i32(lmax_l));
-                    // Lane l sums the weights of the consecutive candidates
-                    // [l B, (l + 1) B); one scan of the 64 sums then finds
-                    // the block holding the draw, and the wave searches that
-                    // block alone (candidate order is kept throughout).  For
-                    // large sets (B > 8) a lane's block is read in strides
-                    // of 64 instead (coalesced), and the blocks are 64 wide.
-                    const bool blocked = cnt <= (uint64_t)kWave * 8;
-                    const uint64_t B = blocked ? (cnt + kWave - 1) / kWave : cnt;
-                    const uint64_t b0 = (uint64_t)lane * B;
-                    const uint64_t b1 = b0 + B < cnt ? b0 + B : cnt;
-                    uint64_t qs = 0;
-                    if (blocked) {
-                        for (uint64_t c = b0; c < b1; ++c) {
-                            const int32_t l = sl[c];
-                            qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+                    // Lane l takes the consecutive candidates [l B, (l + 1) B);
+                    // one scan of the 64 block sums then finds the block
+                    // holding the draw, and the wave searches that block
+                    // alone (candidate order is kept throughout).  Up to
+                    // kPickBlock candidates per lane, a lane keeps its block's
+                    // weights and vertices in registers (all its loads in
+                    // flight together) and the search reads them from the
+                    // chosen lane; for larger sets a lane's block is read in
+                    // strides of 64 (coalesced), and the blocks are 64 wide.
+                    if (cnt <= (uint64_t)kWave * kPickBlock) {
+                        const uint32_t B = (uint32_t)((cnt + kWave - 1) / kWave);
+                        const uint32_t b0 = (uint32_t)lane * B;
+                        uint32_t wk[kPickBlock], vk[kPickBlock];
+#pragma unroll
+                        for (int e = 0; e < kPickBlock; ++e) {
+                            const uint32_t c = b0 + (uint32_t)e;
+                            wk[e] = (uint32_t)kCertainZero;
+                            vk[e] = 0;
+                            if ((uint32_t)e < B && c < (uint32_t)cnt) {
+                                wk[e] = (uint32_t)sl[c];
+                                vk[e] = sv[c];
+                            }
                         }
-                    } else {
-                        for (uint64_t c = (uint64_t)lane; c < cnt; c += kWave) {
-                            const int32_t l = sl[c];
-                            qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
+                        uint64_t qs = 0;
+#pragma unroll
+                        for (int e = 0; e < kPickBlock; ++e) {
+                            // decoded unconditionally (defined for any l), so
+                            // that the table reads are issued together
+                            const int32_t l = (int32_t)wk[e];
+                            const uint32_t w = weight_from_log(lmax, l, s_exp2tab);
+                            wk[e] = l == kCertainZero ? 0u : w;
+                            qs += wk[e];
                         }
-                    }
-                    const uint64_t lincl = blocked ? wave_incl_scan_u64(qs) : wave_sum_u64(qs);
-                    const uint64_t Q = uniform_u64(readlane_u64(lincl, kWave - 1));
-                    if (Q == 0) {
-                        fail = (int)i;
-                        break;
-                    }
-                    const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
-                    // unblocked: one block [0, cnt) searched from the start
-                    const int LB = blocked ? __ffsll((unsigned long long)__ballot(lincl > r)) - 1 : 0;
-                    uint64_t run = blocked ? readlane_u64(lincl - qs, LB) : 0ull;
-                    const uint64_t bs = (uint64_t)LB * B;
-                    const uint64_t be = bs + B < cnt ? bs + B : cnt;
-                    v = 0;
-                    den = 0;
-                    for (uint64_t c0i = bs; c0i < be; c0i += kWave) {
-                        const uint64_t c = c0i + (uint64_t)lane;
-                        uint32_t q = 0;
-                        if (c < be) {
-                            const int32_t l = sl[c];
-                            q = l == kCertainZero ? 0u : weight_from_log(lmax, l, c_exp2tab);
-                        }
-                        const uint64_t incl = wave_incl_scan_u64((uint64_t)q);
-                        const uint64_t tot = readlane_u64(incl, kWave - 1);
-                        if (run + tot > r) {
-                            const uint64_t hm = __ballot(run + incl > r);
-                            const int L = __ffsll((unsigned long long)hm) - 1;
-                            v = sv[c0i + (uint64_t)L];
-                            den = readlane_u32(q, L);
+                        const uint64_t lincl = wave_incl_scan_u64(qs);
+                        const uint64_t Q = uniform_u64(readlane_u64(lincl, kWave - 1));
+                        if (Q == 0) {
+                            fail = (int)i;
                             break;
                         }
-                        run += tot;
+                        const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
+                        const int LB = __ffsll((unsigned long long)__ballot(lincl > r)) - 1;
+                        // weights before block LB: at most r, so the block's
+                        // zero weights are never chosen
+                        uint64_t run = readlane_u64(lincl - qs, LB);
+                        v = 0;
+                        den = 0;
+                        bool found = false;
+#pragma unroll
+                        for (int e = 0; e < kPickBlock; ++e) {
+                            const uint32_t w = readlane_u32(wk[e], LB);
+                            const uint32_t xe = readlane_u32(vk[e], LB);
+                            if (!found && run + w > r) {
+                                found = true;
+                                v = xe;
+                                den = w;
+                            }
+                            run += w;
+                        }
+                        num = Q;
+                    } else {
+                        uint64_t qs = 0;
+                        for (uint64_t c = (uint64_t)lane; c < cnt; c += kWave) {
+                            const int32_t l = sl[c];
+                            qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, s_exp2tab);
+                        }
+                        const uint64_t Q = uniform_u64(wave_sum_u64(qs));
+                        if (Q == 0) {
+                            fail = (int)i;
+                            break;
+                        }
+                        const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
+                        uint64_t run = 0;
+                        v = 0;
+                        den = 0;
+                        for (uint64_t c0i = 0; c0i < cnt; c0i += kWave) {
+                            const uint64_t c = c0i + (uint64_t)lane;
+                            uint32_t q = 0;
+                            if (c < cnt) {
+                                const int32_t l = sl[c];
+                                q = l == kCertainZero ? 0u : weight_from_log(lmax, l, s_exp2tab);
+                            }
+                            const uint64_t incl = wave_incl_scan_u64((uint64_t)q);
+                            const uint64_t tot = readlane_u64(incl, kWave - 1);
+                            if (run + tot > r) {
+                                const uint64_t hm = __ballot(run + incl > r);
+                                const int L = __ffsll((unsigned long long)hm) - 1;
+                                v = sv[c0i + (uint64_t)L];
+                                den = readlane_u32(q, L);
+                                break;
+                            }
+                            run += tot;
+                        }
+                        num = Q;
                     }
-                    num = Q;
                 }
             }
             num = uniform_u64(num);
@@ -1746,6 +1791,8 @@ template <bool kDump, int kWavesPerEU, bool kPairs>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU)))
 void k_sample(const LaunchDesc* __restrict__ D) {
     const int lane = lane_id();
+    for (uint32_t e = threadIdx.x; e < 4096u; e += blockDim.x) s_exp2tab[e] = c_exp2tab[e];
+    __syncthreads();
     const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + uniform_u32(threadIdx.x / kWave);
     const uint64_t cap = D->cap;
     uint32_t* sv = D->scratch + gw * cap * 2;
@@ -1869,7 +1916,7 @@ const void* sample_kernel(bool dump, int variant, bool pairs) {
         case 2:
             return pairs ? sample_kernel_of<8, true>(dump) : sample_kernel_of<8, false>(dump);
         default:
-            return pairs ? sample_kernel_of<4, true>(dump) : sample_kernel_of<4, false>(dump);
+            return pairs ? sample_kernel_of<6, true>(dump) : sample_kernel_of<6, false>(dump);
     }
 }
 
