@@ -253,6 +253,50 @@ __device__ __forceinline__ bool piece_contains(uint32_t val, uint32_t xv) {
     return cand == xv;
 }
 
+// Lower bounds of up to eight keys in one ascending list, searched
+// together: the wave splits into groups of G lanes (G = 16 for up to four
+// keys, else 8), group q searching for the key of lane q (if `need` there)
+// with G probes per level, each level cutting the interval (G + 1)-fold.
+// Lane q receives the first position whose element is not below its key
+// (d when there is none) and, in `found`, whether that element is the key.
+// Every lane must call it; nq (<= 8, wave-uniform) bounds the query lanes.
+__device__ __forceinline__ uint32_t wave_lower_bound_keys(const uint32_t* __restrict__ list, uint32_t d, uint32_t key,
+                                                          bool need, uint32_t nq, bool& found) {
+    const int lane = lane_id();
+    const int sh = nq <= 4 ? 4 : 3;
+    const uint32_t G = 1u << sh;
+    const int q = lane >> sh;
+    const uint32_t s = (uint32_t)lane & (G - 1u);
+    const uint32_t qkey = bperm(key, q);
+    const bool qneed = bperm(need ? 1u : 0u, q) != 0u;
+    const uint64_t gmask = ((G == 16u) ? 0xFFFFull : 0xFFull) << ((uint32_t)q * G);
+    uint32_t lo = 0, hi = qneed ? d : 0u;  // answer in [lo, hi]
+    uint32_t hival = 0;                    // the element at hi, once a probe has set hi
+    bool hset = false;
+    while (__ballot(lo < hi)) {
+        const bool active = lo < hi;  // uniform within a group
+        const uint64_t span = hi - lo;
+        const uint32_t p = lo + (uint32_t)(((uint64_t)(s + 1u) * span) / (G + 1u));
+        const uint32_t val = active ? list[p] : 0u;
+        // probes below the key form a prefix of the group's probes
+        const uint32_t c = (uint32_t)__popcll(__ballot(active && val < qkey) & gmask);
+        const uint32_t vc = bperm(val, (int)((uint32_t)q * G + (c < G ? c : G - 1u)));
+        if (active) {
+            const uint32_t nlo = c > 0u ? lo + (uint32_t)(((uint64_t)c * span) / (G + 1u)) + 1u : lo;
+            if (c < G) {
+                hi = lo + (uint32_t)(((uint64_t)(c + 1u) * span) / (G + 1u));
+                hival = vc;
+                hset = true;
+            }
+            lo = nlo;
+        }
+    }
+    // lane j < 64 / G takes the answer of group j (from its first lane)
+    const int src = (lane * (int)G) & (kWave - 1);
+    found = bperm((hset && lo < d && hival == qkey) ? 1u : 0u, src) != 0u;
+    return bperm(lo, src);
+}
+
 __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict__ list, uint32_t pos, uint32_t len,
                                                       uint32_t xv, uint32_t xlast, uint32_t left, bool& member) {
     const int lane = lane_id();
@@ -1354,17 +1398,23 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 uint32_t pos = 0xFFFFFFFFu;
                 bool found = false;
                 uint64_t qx = 0;
-                // w itself is matched but never in its own list (no loops)
-                if ((uint32_t)lane < i && my_tau != w) {
-                    if (my_row == w) {
-                        pos = my_rpos;
-                        found = true;
-                    } else {
-                        pos = lower_bound_u32(list, d, my_tau);
-                        found = pos < d && list[pos] == my_tau;
+                // w itself is matched but never in its own list (no loops);
+                // a vertex drawn from this row has its position already
+                const bool mine = (uint32_t)lane < i && my_tau != w;
+                const bool need = mine && my_row != w;
+                if (__ballot(need)) {
+                    bool f;
+                    const uint32_t pq = wave_lower_bound_keys(list, d, my_tau, need, i, f);
+                    if (need) {
+                        pos = pq;
+                        found = f;
                     }
-                    if (found) qx = pre[pos] - (pos > 0 ? pre[pos - 1] : 0ull);
                 }
+                if (mine && my_row == w) {
+                    pos = my_rpos;
+                    found = true;
+                }
+                if (found) qx = pre[pos] - (pos > 0 ? pre[pos - 1] : 0ull);
                 const uint64_t qrow = d ? pre[d - 1] : 0ull;
                 const uint64_t Q = qrow - wave_sum_u64(qx);
                 if (Q == 0) {
@@ -1410,14 +1460,19 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint32_t* list = g.nbr + o;
                 uint32_t pos = 0xFFFFFFFFu;
                 bool found = false;
-                if ((uint32_t)lane < i && my_tau != w) {  // w is never in its own list
-                    if (my_row == w) {
-                        pos = my_rpos;
-                        found = true;
-                    } else {
-                        pos = lower_bound_u32(list, d, my_tau);
-                        found = pos < d && list[pos] == my_tau;
+                const bool mine = (uint32_t)lane < i && my_tau != w;  // w is never in its own list
+                const bool need = mine && my_row != w;
+                if (__ballot(need)) {
+                    bool f;
+                    const uint32_t pq = wave_lower_bound_keys(list, d, my_tau, need, i, f);
+                    if (need) {
+                        pos = pq;
+                        found = f;
                     }
+                }
+                if (mine && my_row == w) {
+                    pos = my_rpos;
+                    found = true;
                 }
                 const uint32_t ex = (uint32_t)__popcll(__ballot(found));
                 const uint64_t m = (uint64_t)d - ex;
