@@ -265,6 +265,11 @@ __device__ __forceinline__ uint32_t wave_lower_bound_keys(const uint32_t* __rest
     const int lane = lane_id();
     const int sh = nq <= 4 ? 4 : 3;
     const uint32_t G = 1u << sh;
+    // x / (G + 1) for any 32-bit x as a multiply-high and a shift
+    // (multipliers ceil(2^36 / 17) and ceil(2^33 / 9))
+    const uint32_t mg = nq <= 4 ? 0xF0F0F0F1u : 0x38E38E39u;
+    const uint32_t ms = nq <= 4 ? 4u : 1u;
+    auto div = [&](uint32_t x) { return __umulhi(x, mg) >> ms; };
     const int q = lane >> sh;
     const uint32_t s = (uint32_t)lane & (G - 1u);
     const uint32_t qkey = bperm(key, q);
@@ -275,16 +280,20 @@ __device__ __forceinline__ uint32_t wave_lower_bound_keys(const uint32_t* __rest
     bool hset = false;
     while (__ballot(lo < hi)) {
         const bool active = lo < hi;  // uniform within a group
-        const uint64_t span = hi - lo;
-        const uint32_t p = lo + (uint32_t)(((uint64_t)(s + 1u) * span) / (G + 1u));
+        // probe t (1..G) at lo + floor(t span / (G + 1)), in 32 bits:
+        // span = a (G + 1) + b gives t a + floor(t b / (G + 1))
+        const uint32_t span = hi - lo;
+        const uint32_t a = div(span), b = span - a * (G + 1u);
+        auto at = [&](uint32_t t) { return lo + t * a + div(t * b); };
+        const uint32_t p = at(s + 1u);
         const uint32_t val = active ? list[p] : 0u;
         // probes below the key form a prefix of the group's probes
         const uint32_t c = (uint32_t)__popcll(__ballot(active && val < qkey) & gmask);
         const uint32_t vc = bperm(val, (int)((uint32_t)q * G + (c < G ? c : G - 1u)));
         if (active) {
-            const uint32_t nlo = c > 0u ? lo + (uint32_t)(((uint64_t)c * span) / (G + 1u)) + 1u : lo;
+            const uint32_t nlo = c > 0u ? at(c) + 1u : lo;
             if (c < G) {
-                hi = lo + (uint32_t)(((uint64_t)(c + 1u) * span) / (G + 1u));
+                hi = at(c + 1u);
                 hival = vc;
                 hset = true;
             }
