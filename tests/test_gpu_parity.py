@@ -135,6 +135,23 @@ def test_records_parity_c1(sess, c1, c1_state, name, mode, rowtab):
 
 
 @pytest.mark.parametrize("rowtab", ["off", "on"])
+@pytest.mark.parametrize("mode", ["uniform", "switch"])
+@pytest.mark.parametrize("k", [6, 7, 8])
+def test_records_parity_c1_long_paths(sess, c1, c1_state, k, mode, rowtab):
+    """Paths of 6 to 8 vertices: single-backward steps with five to seven
+    matched vertices, located in the row by the eight-lane search groups
+    (the bench patterns use the sixteen-lane ones)."""
+    G, T, OT = c1_state
+    p = synth.patterns.path(k)
+    idx = _indices(2000, rng_seed=100 + k)
+    say(f"records chung-lu path({k}) {mode} rowtab={rowtab} m={idx.size}")
+    got = sess.dump(G, T, p, SEED, idx, mode=mode, pattern_id=6, rowtab=rowtab)
+    c = compile_pattern(p.k, p.edges, mode=mode)
+    ref = oracle.Sampler(c1, OT, c, seed=SEED, pattern_id=6).records(idx)
+    _compare_records(got, ref, f"path({k})/{mode}")
+
+
+@pytest.mark.parametrize("rowtab", ["off", "on"])
 @pytest.mark.parametrize("terms", ["f1", "f1_i1"])
 @pytest.mark.parametrize("name", ["house", "4-clique", "5-cycle", "diamond"])
 def test_records_parity_term_ablation(sess, c1, c1_state, name, terms, rowtab):
