@@ -223,8 +223,8 @@ __device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __res
 // (this lane's element xv, the chunk's largest xlast).  Elements of `list`
 // before `pos` are below every element of the chunk, so membership of xv
 // is decided inside the window [pos, end) of elements <= xlast.  The window
-// is streamed in coalesced 64-element pieces, each searched for every
-// lane's xv with register shuffles, until a piece holds an element above
+// is streamed in coalesced 256-element blocks, each searched for every
+// lane's xv with register shuffles, until a block holds an element above
 // xlast: the bytes read are the window itself, as in a merge.  When the
 // window is expected to be far longer than the chunk (the list is much
 // longer than what is left of the base: left = base elements from this
