@@ -167,3 +167,19 @@ def test_library_connected_patterns_are_the_isomorphism_classes():
         assert codes == ref
         sizes = [sum(bin(p.adj[a]).count("1") for a in range(k)) // 2 for p in got]
         assert sizes == sorted(sizes)
+
+
+def test_sampler_division_multipliers_are_exact():
+    # The grouped position search divides by G + 1 (17 or 9) as a multiply-
+    # high by m and a right shift by s.  That equals floor(x / d) for every
+    # 32-bit x when m = ceil(2^(32+s) / d) and m d - 2^(32+s) <= 2^s
+    # (Granlund and Montgomery, PLDI 1994); checked here on the constants
+    # the kernel source holds, and on boundary values.
+    src = open(os.path.join(ROOT, "paper_2601_01388_amd", "csrc", "kernels.hip")).read()
+    mg = re.search(r"const uint32_t mg = nq <= 4 \? (0x[0-9A-Fa-f]+)u : (0x[0-9A-Fa-f]+)u;", src)
+    ms = re.search(r"const uint32_t ms = nq <= 4 \? (\d+)u : (\d+)u;", src)
+    assert mg and ms
+    for d, m, s in [(17, int(mg.group(1), 16), int(ms.group(1))), (9, int(mg.group(2), 16), int(ms.group(2)))]:
+        assert m == -(-(1 << (32 + s)) // d) and m * d - (1 << (32 + s)) <= (1 << s)
+        for x in [0, 1, d - 1, d, d + 1, (1 << 32) - 1, (1 << 32) - d, (1 << 31) + 5] + list(range(0, 5000)):
+            assert ((x * m) >> 32) >> s == x // d
