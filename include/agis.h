@@ -283,7 +283,7 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
 /* Launch shape of the sampler for later calls on this context (results do
  * not depend on it): use_graphs = replay rounds from a captured HIP graph;
  * blocks_per_cu = resident 256-thread workgroups per compute unit (0 = as
- * many as fit); grab = sample slots a wave takes from the queue at a time
+ * many as fit; each holds 16 KB of LDS, the weight decoder's table); grab = sample slots a wave takes from the queue at a time
  * (0 = chosen from the round size, at most 1024); variant = register
  * budget of the sampling kernel (0, 1 and 2 = small enough for 6, 7 and 8
  * resident waves per SIMD; the smaller budgets spill a few registers);
