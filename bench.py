@@ -1,16 +1,26 @@
 """Benchmark of the AGIS sampling estimator on one MI355X.
 
-Workload: R-MAT scale 20 (2^20 vertices, edge factor 16, a=.57 b=.19 c=.19
-d=.05, symmetrised, deduplicated, no self-loops; ~15.7M undirected edges),
+Headline workload (the R-MAT scale 20 configuration): R-MAT scale 20
+(2^20 vertices, edge factor 16, a=.57 b=.19 c=.19 d=.05, symmetrised,
+deduplicated, no self-loops; ~15.7M undirected edges) in symmetric CSR,
 patterns 5-clique, 5-cycle, house and 4-star, f_approx with the paper's
-switching rule (beta = 4/5).  One step = one estimate per pattern over a
-fixed batch of samples (first-step table build included, as the paper
-counts it in mining time).  ``value`` is samples per second over the timed
-steps.  Also reported: time to +-1% relative error at 95% confidence
-(Algorithm 1) per pattern and proposal mode, the roofline of the sampling
-kernel (random-gather bound: HBM), and the CPU oracle timed on the host.
+switching rule (beta = 4/5), 10^8 samples per pattern.  The 10^8 samples of
+each pattern are split into K consecutive index ranges; one step runs one
+range of every pattern (one estimate each, its per-estimate tables
+included, as the paper counts them in mining time), so the K steps together
+are one 10^8-sample estimate per pattern.  ``value`` is samples per second
+over the timed steps.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Also measured in the same run (the detail goes to a side file, a summary to
+stderr): the roofline of the sampling kernel (request bytes counted per
+sample by the metering kernel, against the HBM peak and against a measured
+random-gather ceiling), time to +-1% relative error at 95% confidence
+(Algorithm 1) per pattern for learned vs f_approx vs f_uniform, the batched
+32-pattern runs, the term ablation and beta sweep, cliques on the degree
+DAG, concentrations, the R-MAT scale 24 legs, and the CPU oracle timed on
+the host's cores.  The last stdout line is one compact JSON object.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--detail PATH]
 """
 
 from __future__ import annotations
@@ -30,9 +40,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PATTERNS = ["5-clique", "5-cycle", "house", "4-star"]
+C2_SAMPLES = 10 ** 8
 HBM_PEAK_GBS = 8000.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sample_rmat20_counters.json")
+GOLDEN_5CLIQUE = os.path.join(ROOT, "tests", "golden", "rmat20_clique_counts.txt")
 KERNEL_SOURCES = ["paper_2601_01388_amd/csrc/kernels.hip", "paper_2601_01388_amd/csrc/agis_common.h"]
+GATHER_SIZES = [4, 16, 64, 256, 1024]
 
 
 def log(msg):
@@ -44,6 +57,65 @@ def kernel_source_hash() -> str:
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def rel_var(r) -> float:
+    return r.variance / max(r.estimate ** 2, 1e-300)
+
+
+def merge_results(rs):
+    """(n, mean, population variance) of the union of several estimates'
+    samples (Chan et al.'s pairwise update, in the given order)."""
+    n, mean, m2 = 0.0, 0.0, 0.0
+    for r in rs:
+        nb, mb, m2b = float(r.n), r.estimate, r.variance * float(r.n)
+        if nb == 0:
+            continue
+        if n == 0:
+            n, mean, m2 = nb, mb, m2b
+            continue
+        tot = n + nb
+        d = mb - mean
+        mean += d * nb / tot
+        m2 += m2b + d * d * n * nb / tot
+        n = tot
+    return n, mean, (m2 / n if n else 0.0)
+
+
+def host_info() -> dict:
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"model": model or platform.processor() or platform.machine(), "nproc": avail,
+            "os_cpu_count": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def star_closed_form(g, leaves: int) -> int:
+    """k-star embeddings: k! * sum_v C(d(v), k) (the paper's k-star example)."""
+    d = np.diff(g.off).astype(np.int64)
+    return int(sum(math.perm(int(x), leaves) for x in d[d >= leaves]))
+
+
+def golden_cliques():
+    """Exact clique counts of the R-MAT scale 20 bench graph (embeddings),
+    written by tests/golden/make_rmat20_cliques.py from the oracle."""
+    out = {}
+    if os.path.exists(GOLDEN_5CLIQUE):
+        for line in open(GOLDEN_5CLIQUE):
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                out[int(k)] = int(v)
+    return out
 
 
 def algorithmic_bytes(g, plan, recs) -> float:
@@ -106,49 +178,320 @@ class HostCSR:
         self.nbr = nbr
 
 
-def cpu_baseline(g, seconds_target: float):
-    """The oracle (single thread) on a bounded sample of the same workload:
-    the same patterns and mode, equal sample counts per pattern."""
+def cpu_baseline(g, c1, seconds_target: float):
+    """The oracle on the host's cores (bounded samples of the bench's own
+    workloads): the R-MAT scale 20 headline (the four patterns in switch
+    mode on the symmetric graph, seed 7) single-threaded and with the OpenMP
+    flavour on every core (one sampler per thread, contiguous index blocks),
+    and the Chung-Lu C1 workload in full (triangle, 4-cycle, 4-clique x
+    uniform, switch, always, 10^6 samples each) on every core."""
     import oracle
     from oracle.pattern import compile_pattern
     import synth
-    log("cpu baseline: oracle tables (setup, untimed)")
-    t = oracle.Tables(g, cv_seed=1)
-    og = ot = None
-    samplers = []
-    for name in PATTERNS:
-        p = synth.named_pattern(name)
-        cp = compile_pattern(p.k, p.edges, mode="switch")
-        if is_clique(p):
-            if og is None:
-                og = oracle.orient(g)
-                ot = oracle.Tables(og, cv_seed=1, adjacency=g)
-            samplers.append(oracle.Sampler(og, ot, cp, seed=7, oriented=True))
-        else:
-            samplers.append(oracle.Sampler(g, t, cp, seed=7))
-    # calibrate on a few samples, then size the timed sample
+    info = host_info()
+    threads = int(info["omp_num_threads"] or 0) or info["nproc"]
+    log(f"cpu baseline: oracle tables of R-MAT-20 on {threads} threads (setup, untimed)")
+    t = oracle.Tables(g, cv_seed=1, threads=threads)
+    samplers = [oracle.Sampler(g, t, compile_pattern(p.k, p.edges, mode="switch"), seed=7, pattern_id=pid)
+                for pid, p in enumerate(synth.named_pattern(n) for n in PATTERNS)]
     per = []
     for s in samplers:
         t0 = time.perf_counter()
-        s.run(0, 200)
-        per.append((time.perf_counter() - t0) / 200)
-    n_each = max(200, int(seconds_target / max(sum(per), 1e-9)))
-    log(f"cpu baseline: {n_each} samples per pattern")
+        s.run(0, 100)
+        per.append((time.perf_counter() - t0) / 100)
+    n1 = max(100, int(0.35 * seconds_target / max(sum(per), 1e-9)))
     t0 = time.perf_counter()
     for s in samplers:
-        s.run(0, n_each)
-    el = time.perf_counter() - t0
+        s.run(0, n1)
+    el1 = time.perf_counter() - t0
+    nall = max(n1, int(0.35 * seconds_target * threads / max(sum(per), 1e-9)))
+    t0 = time.perf_counter()
+    used = threads
+    for s in samplers:
+        _, used = s.run_parallel(0, nall, threads=threads)
+    elall = time.perf_counter() - t0
+    # C1 in full on every core
+    tc = oracle.Tables(c1, cv_seed=1, threads=threads)
+    c1_runs = {}
+    t0 = time.perf_counter()
+    for pid, name in enumerate(("triangle", "4-cycle", "4-clique")):
+        p = synth.named_pattern(name)
+        for mode in ("uniform", "switch", "always"):
+            st, _ = oracle.Sampler(c1, tc, compile_pattern(p.k, p.edges, mode=mode), seed=7,
+                                   pattern_id=pid).run_parallel(0, 10 ** 6, threads=threads)
+            c1_runs[f"{name}/{mode}"] = {"mean": st.mean, "n": int(st.n)}
+    elc1 = time.perf_counter() - t0
     return {
-        "value": len(PATTERNS) * n_each / el,
+        "value": len(PATTERNS) * nall / elall,
         "unit": "samples/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": f"first {n_each} sample indices of each of {', '.join(PATTERNS)} (f_approx+switch, seed 7, "
-                  f"cliques on the degree-oriented graph) on the same R-MAT-20 graph, single-threaded C oracle, "
-                  f"{el:.1f} s",
-        "host": platform.processor() or platform.machine(),
-        "host_threads_available": os.cpu_count(),
+        "sample": (f"R-MAT-20 headline workload (5-clique, 5-cycle, house, 4-star; switch; seed 7): first {nall} "
+                   f"sample indices per pattern with the OpenMP oracle on {used} threads ({elall:.1f} s); "
+                   f"single-threaded: first {n1} per pattern ({el1:.1f} s)"),
+        "single_thread_value": len(PATTERNS) * n1 / el1,
+        "c1_full": {"samples": 9 * 10 ** 6, "seconds": elc1, "threads": used, "samples_per_s": 9e6 / elc1,
+                    "runs": c1_runs},
+        "host": info,
     }
+
+
+GATHER_BUFFERS = {"128MiB": 1 << 27, "8GiB": 1 << 33}
+
+
+def gather_ceiling(sess, waves_per_cu: int):
+    """Random-gather ceiling (agis_gather_bench) for segment sizes of 4 B to
+    1 KiB, as chains of dependent reads and as independent reads, at the
+    sampler's resident waves per compute unit, over two footprints: 128 MiB
+    (held by the 256 MB Infinity Cache) and 8 GiB (HBM)."""
+    import torch
+    out = {}
+    for label, nbytes in GATHER_BUFFERS.items():
+        buf = torch.arange(nbytes // 8, dtype=torch.int64, device=sess.device)
+        rows = {}
+        for S in GATHER_SIZES:
+            row = {}
+            for dep in (True, False):
+                sec, ub = sess.gather_bench(buf, S, dep, waves_per_cu=waves_per_cu, rounds=32, seed=S)
+                rounds = int(min(max(32 * 0.02 / max(sec, 1e-6), 32), 200000))
+                sec, ub = sess.gather_bench(buf, S, dep, waves_per_cu=waves_per_cu, rounds=rounds, seed=S + 1)
+                row["dependent_gbs" if dep else "independent_gbs"] = ub / sec / 1e9
+            rows[S] = row
+        out[label] = rows
+        del buf
+        torch.cuda.empty_cache()
+    return out
+
+
+def learned_four(args, sess, T, pats):
+    """One MLP per headline pattern, trained on extension counts the sampler
+    produces on R-MAT scale 18 (seed 18), BF16 inference into pick tables
+    for the bench graph (residual: a learned correction of f_approx)."""
+    import torch
+    import synth
+    from paper_2601_01388_amd.session import mlp_init
+    learned = {}
+    log("learned proposal: training graph R-MAT scale 18")
+    gtr = synth.rmat(18, 16, seed=18)
+    Gtr = sess.graph(gtr.off, gtr.nbr)
+    Ttr = sess.tables(Gtr, cv_seed=1)
+    ftr = sess.features(Ttr)
+    fev = sess.features(T)
+    residual = not args.learned_absolute
+    batch_rows = 4096
+    for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
+        t0 = time.perf_counter()
+        steps = sess.weighted_steps(p, "learned")
+        sums, counts = sess.learn_targets(Gtr, Ttr, p, args.train_samples, 101 + pid, mode="switch")
+        base_tr = sess.step_log_weights(Ttr, p) if residual else None
+        rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2, base=base_tr)
+        del sums, counts, base_tr
+        tg = rows["target"].cpu().numpy()
+        wt = rows["weight"].cpu().numpy()
+        init = mlp_init(7 + pid, float(np.average(tg, weights=wt)) if rows["rows"] else 0.0, zero_output=residual)
+        params = torch.from_numpy(init).to(sess.device)
+        per_epoch = max(1, -(-rows["rows"] // batch_rows))
+        epochs = max(args.train_epochs, -(-args.train_min_steps // per_epoch))
+        losses = sess.mlp_train(params, ftr, rows, epochs=epochs, batch=batch_rows, lr=3e-3, seed=pid)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        base_ev = sess.step_log_weights(T, p) if residual else None
+        tabs = sess.learned_tables(params, fev, p, base=base_ev, rows=rows)
+        del base_ev
+        torch.cuda.synchronize()
+        infer_s = time.perf_counter() - t0
+        learned[name] = {"tables": tabs, "ptrs": {i: tab.data_ptr() for i, tab in tabs.items()},
+                         "info": {"train_rows": rows["rows"], "train_seconds": train_s, "epochs": epochs,
+                                  "adam_steps": epochs * per_epoch, "residual": residual,
+                                  "loss_first_last": [losses[0], losses[-1]] if losses else None,
+                                  "infer_seconds": infer_s, "weighted_steps": steps}}
+        log(f"learned {name}: {rows['rows']} rows, {epochs} epochs, train {train_s:.2f} s, loss "
+            f"{losses[0]:.3g} -> {losses[-1]:.3g}, tables {infer_s * 1e3:.1f} ms")
+    Ttr.close()
+    Gtr.close()
+    return learned
+
+
+def time_to_eps(args, sess, G, T, pats, learned):
+    """Time to +-1% at 95% CI (Algorithm 1) per pattern and proposal; checks
+    every 4096 samples from 4096 on, so that the stop point reflects the
+    proposal rather than the check interval; budget --eps-budget."""
+    table = {}
+    ck = args.eps_check
+    for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
+        for mode in ("learned", "switch", "always", "uniform"):
+            if mode == "learned" and name not in learned:
+                continue
+            kw = dict(learned=learned[name]["ptrs"]) if mode == "learned" else {}
+            r = sess.estimate(G, T, p, args.eps_budget, 11, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
+                              check_every=ck, min_samples=ck, **kw)
+            need = r.n * (r.eps_hat / 0.01) ** 2 if math.isfinite(r.eps_hat) else None
+            label = {"switch": "f_approx", "always": "f_approx_always", "uniform": "f_uniform",
+                     "learned": "learned"}[mode]
+            entry = {"seconds": r.seconds, "converged": bool(r.converged), "samples": r.n, "estimate": r.estimate,
+                     "eps_hat": r.eps_hat, "rel_var": rel_var(r), "samples_needed": need,
+                     "stopped_at_first_check": r.n <= ck}
+            if mode == "learned":
+                entry["seconds_incl_table_inference"] = r.seconds + learned[name]["info"]["infer_seconds"]
+                entry.update({k: v for k, v in learned[name]["info"].items() if k != "weighted_steps"})
+            table[f"{name}/{label}"] = entry
+            log(f"+-1% {name} {label}: {r.seconds:.4f} s, n={r.n}, rel.var {entry['rel_var']:.4g}, "
+                f"converged={bool(r.converged)}")
+    for pid, name in enumerate(PATTERNS):
+        if f"{name}/learned" not in table:
+            continue
+        table[f"{name}/learned"]["rel_var_vs_f_approx"] = (
+            table[f"{name}/learned"]["rel_var"] / max(table[f"{name}/f_approx"]["rel_var"], 1e-300))
+        t0 = time.perf_counter()
+        pl = sess.estimate(G, T, pats[pid], args.pilot_samples, 97, mode="learned", pattern_id=pid,
+                           learned=learned[name]["ptrs"])
+        pa = sess.estimate(G, T, pats[pid], args.pilot_samples, 97, mode="switch", pattern_id=pid)
+        pilot_s = time.perf_counter() - t0
+        keep = rel_var(pl) < rel_var(pa)
+        chosen = table[f"{name}/learned" if keep else f"{name}/f_approx"]
+        table[f"{name}/learned_with_fallback"] = {
+            "chosen": "learned" if keep else "f_approx", "pilot_seconds": pilot_s,
+            "seconds": chosen["seconds"] + pilot_s, "samples": chosen["samples"],
+            "converged": chosen["converged"], "estimate": chosen["estimate"], "rel_var": chosen["rel_var"]}
+        log(f"{name}: pilot keeps {'learned' if keep else 'f_approx'}")
+    return table
+
+
+def ablation_leg(args, sess, G, T):
+    """Incremental terms of f_approx and the switching threshold beta (the
+    paper's analysis of the approximation and of beta)."""
+    import synth
+    z2 = 1.959963984540054 ** 2
+    ab = {"samples": args.ablation_samples, "terms": {}, "beta": {}}
+    t0 = time.perf_counter()
+    for name in ["4-clique", "4-path", "5-clique", "5-cycle", "house"]:
+        p = synth.named_pattern(name)
+        row = {}
+        for terms in ("f1", "f1_i1", "all"):
+            r = sess.estimate(G, T, p, args.ablation_samples, 17, mode="switch", terms=terms)
+            rv = rel_var(r)
+            row[terms] = {"rel_var": rv, "samples_needed": z2 * rv / 1e-4, "estimate": r.estimate,
+                          "seconds_per_sample": r.seconds / r.n}
+        ab["terms"][name] = row
+    betas = [("-inf", (-1, 0)), ("1/2", (1, 2)), ("4/5", (4, 5)), ("5/6", (5, 6)), ("1", (1, 1)), ("+inf", (1, 0))]
+    for name in ["house", "5-cycle", "6-cycle", "chordal-7-cycle"]:
+        p = synth.named_pattern(name)
+        row = {}
+        for label, beta in betas:
+            r = sess.estimate(G, T, p, args.ablation_samples, 19, mode="switch", beta=beta)
+            rv = rel_var(r)
+            row[label] = {"rel_var": rv, "samples_needed": z2 * rv / 1e-4, "estimate": r.estimate,
+                          "seconds_per_sample": r.seconds / r.n,
+                          "uniform_steps": int(sum(1 for i in range(p.k) if not r.plan.decision[i]))}
+        ab["beta"][name] = row
+    ab["seconds"] = time.perf_counter() - t0
+    log(f"term ablation and beta sweep: {ab['seconds']:.1f} s")
+    for name, row in ab["terms"].items():
+        log("  terms " + name + ": " + ", ".join(f"{k} {v['rel_var']:.3g}" for k, v in row.items()))
+    for name, row in ab["beta"].items():
+        log("  beta " + name + ": " + ", ".join(f"{k} {v['rel_var']:.3g}" for k, v in row.items()))
+    return ab
+
+
+def batch_leg(args, sess, G, T, restore_tuning):
+    """32 connected patterns of 4-7 vertices (seed 3) with budgets
+    log-uniform in [10^6, 10^9], all run to +-1% in one batched run."""
+    import torch
+    import synth
+    pset = synth.random_pattern_set(32, seed=3)
+    bpats = [p for p, _ in pset]
+    budgets = [max(1, int(b * args.batch_budget_scale)) for _, b in pset]
+    log(f"32-pattern batch to +-1%, total budget {sum(budgets):.3g} samples")
+    btune = tune_batch(args, sess, G, T, bpats, log)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = sess.estimate_batch(G, T, bpats, budgets, 13, mode="switch", eps=0.01, delta=0.05,
+                              check_every=1 << 16, min_samples=1 << 14)
+    torch.cuda.synchronize()
+    bt = time.perf_counter() - t0
+    restore_tuning()
+    out = {"patterns": 32, "tuning": btune, "seconds": bt, "samples": int(sum(r.n for r in res)),
+           "converged": int(sum(r.converged for r in res)), "samples_per_s": sum(r.n for r in res) / bt,
+           "budget_total": int(sum(budgets)),
+           "per_pattern": [{"k": p.k, "edges": len(p.edges), "budget": b, "samples": r.n,
+                            "converged": bool(r.converged), "seconds": r.seconds, "rel_var": rel_var(r)}
+                           for p, b, r in zip(bpats, budgets, res)]}
+    log(f"batch: {bt:.2f} s, {out['converged']}/32 converged, {out['samples']:.3g} samples")
+    return out
+
+
+def oriented_leg(args, sess, G, T):
+    """4- and 5-cliques on the degree-oriented graph vs the symmetric graph."""
+    import torch
+    import synth
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    O = sess.orient(G)
+    TO = sess.tables(O, cv_seed=1)
+    torch.cuda.synchronize()
+    out = {"orient_and_tables_ms": 1e3 * (time.perf_counter() - t0), "nnz": O.nnz, "patterns": {}}
+    for k in (4, 5):
+        p = synth.patterns.clique(k)
+        row = {}
+        for label, (gg, tt) in (("oriented", (O, TO)), ("symmetric", (G, T))):
+            r = sess.estimate(gg, tt, p, args.samples_oriented, 29, mode="switch", pattern_id=k)
+            e = sess.estimate(gg, tt, p, args.eps_budget, 31, mode="switch", pattern_id=k, eps=0.01, delta=0.05,
+                              check_every=args.eps_check, min_samples=args.eps_check)
+            row[label] = {"samples_per_s_kernel": r.n / max(r.sample_kernel_seconds, 1e-12), "rel_var": rel_var(r),
+                          "estimate": r.estimate, "time_to_1pct_s": e.seconds, "samples_to_1pct": e.n,
+                          "converged": bool(e.converged)}
+        out["patterns"][f"{k}-clique"] = row
+        log(f"{k}-clique oriented: {row['oriented']['samples_per_s_kernel']:.3g} samples/s, rel.var "
+            f"{row['oriented']['rel_var']:.3g}, +-1% in {row['oriented']['time_to_1pct_s']:.4f} s; symmetric: "
+            f"{row['symmetric']['samples_per_s_kernel']:.3g} samples/s, rel.var {row['symmetric']['rel_var']:.3g}, "
+            f"+-1% in {row['symmetric']['time_to_1pct_s']:.4f} s")
+    TO.close()
+    O.close()
+    return out
+
+
+def conc_leg(args, sess, G, T):
+    """Concentrations of all connected 4- and 5-vertex patterns, each run to
+    +-1% inside batched runs (the paper's comparison with MCMC)."""
+    import torch
+    out = {}
+    for k in (4, 5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = sess.concentrations(G, T, k, args.conc_budget, 23, mode="switch", eps=0.01, delta=0.05,
+                                check_every=1 << 16, min_samples=1 << 14)
+        torch.cuda.synchronize()
+        ct = time.perf_counter() - t0
+        res = c["results"]
+        out[f"k{k}"] = {
+            "patterns": len(res), "seconds": ct, "budget_per_pattern": args.conc_budget,
+            "converged": int(sum(r.converged for r in res)), "samples": int(sum(r.n for r in res)),
+            "per_pattern": [{"edges": [list(e) for e in p[1]], "copies": r.copies, "eps_hat": r.eps_hat,
+                             "conc_edge": float(ce), "conc_induced": float(ci), "induced": float(ind)}
+                            for p, r, ce, ci, ind in zip(c["patterns"], res, c["conc_edge"], c["conc_induced"],
+                                                          c["induced"])]}
+        log(f"concentrations k={k}: {len(res)} patterns, {out[f'k{k}']['converged']} converged, {ct:.2f} s")
+    return out
+
+
+def c1_gpu_leg(sess, c1):
+    """The Chung-Lu C1 workload on the GPU: triangle, 4-cycle, 4-clique under
+    uniform, switch and always, 10^6 samples each, seed 7."""
+    import synth
+    G = sess.graph(c1.off, c1.nbr)
+    T = sess.tables(G, cv_seed=1)
+    out = {}
+    t_all = 0.0
+    for pid, name in enumerate(("triangle", "4-cycle", "4-clique")):
+        p = synth.named_pattern(name)
+        for mode in ("uniform", "switch", "always"):
+            r = sess.estimate(G, T, p, 10 ** 6, 7, mode=mode, pattern_id=pid)
+            out[f"{name}/{mode}"] = {"estimate": r.estimate, "rel_var": rel_var(r), "seconds": r.seconds}
+            t_all += r.seconds
+    T.close()
+    G.close()
+    return {"runs": out, "seconds": t_all, "samples_per_s": 9e6 / t_all}
 
 
 def bpats_budgets(args):
@@ -264,23 +607,32 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--samples", type=int, default=1 << 22, help="samples per pattern per step")
+    ap.add_argument("--total-samples", type=int, default=C2_SAMPLES,
+                    help="samples per pattern over all timed steps (the R-MAT scale 20 configuration: 10^8)")
+    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="side file for the full per-leg detail")
     ap.add_argument("--eps-budget", type=int, default=10 ** 8, help="sample budget of each run to +-1%%")
+    ap.add_argument("--eps-check", type=int, default=4096, help="check interval (and minimum) of the +-1%% runs")
+    ap.add_argument("--headline-only", action="store_true", help="only the timed steps and their roofline")
     ap.add_argument("--skip-eps", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--bytes-records", type=int, default=1500)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="wall seconds of the R-MAT-20 oracle samples")
+    ap.add_argument("--meter-samples", type=int, default=4096, help="samples metered per pattern for the roofline")
+    ap.add_argument("--bytes-records", type=int, default=1000, help="records per pattern priced by the merge model")
+    ap.add_argument("--skip-gather", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run 3 plain device copies of this many bytes (counter calibration) and exit")
     ap.add_argument("--tune-pilot", type=int, default=1 << 20, help="pilot samples per pattern of the autotuner")
     ap.add_argument("--batch-tune-pilot", type=int, default=1 << 15,
                     help="pilot samples per pattern of the batch legs' autotuning")
+    ap.add_argument("--samples-oriented", type=int, default=1 << 22)
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-ablation", action="store_true")
     ap.add_argument("--skip-conc", action="store_true")
     ap.add_argument("--skip-oriented", action="store_true")
+    ap.add_argument("--skip-c1", action="store_true")
     ap.add_argument("--conc-budget", type=int, default=20_000_000,
                     help="sample budget per pattern of the concentration runs (to +-1%%)")
     ap.add_argument("--skip-large", action="store_true",
@@ -301,6 +653,9 @@ def main():
     ap.add_argument("--batch-budget-scale", type=float, default=1.0,
                     help="multiplier on the 32-pattern set's budgets (log-uniform in [1e6, 1e9])")
     args = ap.parse_args()
+    if args.headline_only:
+        args.skip_eps = args.skip_cpu = args.skip_batch = args.skip_learned = args.skip_ablation = True
+        args.skip_conc = args.skip_oriented = args.skip_large = args.skip_c1 = True
 
     if args.copy_calibration:
         # a plain device copy of known size, for scaling hardware byte counters
@@ -323,6 +678,7 @@ def main():
     import synth
     from paper_2601_01388_amd.session import Session
 
+    wall0 = time.perf_counter()
     log("generating R-MAT scale 20")
     g = synth.rmat(20, 16, seed=20)
     sess = Session(0)
@@ -333,34 +689,14 @@ def main():
     torch.cuda.synchronize()
     tables_s = time.perf_counter() - t0
     log(f"graph n={g.n} nnz={g.nnz} dmax={int(np.diff(g.off).max())}; tables {tables_s * 1e3:.1f} ms")
-
     pats = [synth.named_pattern(n) for n in PATTERNS]
-    # cliques run on the degree-oriented graph, as the method does for them
-    # (Sec. 5.4); it is built once per graph with its tables, like the
-    # symmetric graph's tables (preprocessing, outside the timed steps)
-    O = TO = None
-    orient_s = 0.0
-    if any(is_clique(p) for p in pats):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        O = sess.orient(G)
-        TO = sess.tables(O, cv_seed=1)
-        torch.cuda.synchronize()
-        orient_s = time.perf_counter() - t0
-        log(f"degree-oriented graph for the cliques: nnz={O.nnz}, orientation and tables {orient_s * 1e3:.1f} ms")
-
-    def graph_of(p):
-        return (O, TO) if is_clique(p) else (G, T)
 
     tuning = None
     if not args.no_tune:
-        # tuned on the patterns that run on the symmetric graph (the
-        # launch shape is one per context)
-        tpats = [p for p in pats if not is_clique(p)] or pats
-        log(f"autotuning the sampler launch on {len(tpats)} patterns")
-        tun = sess.autotune(G, T, tpats, args.tune_pilot, mode="switch")
-        tuning = {"variant": tun.variant, "grab": tun.grab, "hub_window": tun.hub_window, "pilot_kernel_s": tun.seconds,
-                  "default_kernel_s": tun.default_seconds}
+        log(f"autotuning the sampler launch on the {len(pats)} headline patterns")
+        tun = sess.autotune(G, T, pats, args.tune_pilot, mode="switch")
+        tuning = {"variant": tun.variant, "grab": tun.grab, "hub_window": tun.hub_window,
+                  "pilot_kernel_s": tun.seconds, "default_kernel_s": tun.default_seconds}
         log(f"tuned: variant {tun.variant} grab {tun.grab} hub window {tun.hub_window} "
             f"({tun.default_seconds:.3f} s -> {tun.seconds:.3f} s)")
 
@@ -369,334 +705,222 @@ def main():
         if tuning is not None:
             sess.set_launch(True, 0, tuning["grab"], tuning["variant"], tuning["hub_window"])
 
-    def step(seed, walls=None):
+    n_step = -(-args.total_samples // args.steps)
+    # what AUTO picks for estimates of n_step samples (the metering run must
+    # take the same paths)
+    rowtab = "on" if n_step >= 65536 else "off"
+
+    def step(seed, first, walls=None):
         res = []
         for pid, p in enumerate(pats):
             t1 = time.perf_counter()
-            gg, tt = graph_of(p)
-            res.append(sess.estimate(gg, tt, p, args.samples, seed, mode="switch", pattern_id=pid))
+            res.append(sess.estimate(G, T, p, n_step, seed, mode="switch", pattern_id=pid, first_sample=first))
             if walls is not None:
                 walls[pid] += time.perf_counter() - t1
         return res
 
-    # the timed steps' clique estimates on the symmetric graph instead, for
-    # comparison (not the headline): their wall time replaces the oriented
-    # ones' (run first, so that the timed launches are the last ones)
-    sym_s = 0.0
-    if O is not None:
-        for pid, p in enumerate(pats):
-            if is_clique(p):
-                sess.estimate(G, T, p, args.samples, 999, mode="switch", pattern_id=pid)  # warmup
-        for k in range(args.steps):
-            for pid, p in enumerate(pats):
-                if is_clique(p):
-                    torch.cuda.synchronize()
-                    t1 = time.perf_counter()
-                    sess.estimate(G, T, p, args.samples, 7 + k, mode="switch", pattern_id=pid)
-                    sym_s += time.perf_counter() - t1
     for w in range(args.warmup):
-        step(1000 + w)
+        step(1000 + w, 0)
         log(f"warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
     walls = [0.0] * len(pats)
     for k in range(args.steps):
-        results.append(step(7 + k, walls))
+        results.append(step(7, k * n_step, walls))
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    value_symmetric = None
-    if O is not None:
-        clique_s = sum(w for w, p in zip(walls, pats) if is_clique(p))
-        value_symmetric = args.steps * len(pats) * args.samples / (elapsed - clique_s + sym_s)
-    total_samples = args.steps * len(pats) * args.samples
-    value = total_samples / elapsed
+    total = args.steps * len(pats) * n_step
+    value = total / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    kern_s = sum(r.sample_kernel_seconds for rs in results for r in rs)
-    launches = sum(r.sample_launches for rs in results for r in rs)
+    log(f"timed: {value:.4g} samples/s, {ms_per_step:.1f} ms/step")
+
+    # the whole-range estimate per pattern, judged by exact counts where known
+    exact = {"4-star": star_closed_form(g, 4)}
+    gold = golden_cliques()
+    if 5 in gold:
+        exact["5-clique"] = gold[5]
     per_pattern = {}
     for pid, name in enumerate(PATTERNS):
-        ks = sum(rs[pid].sample_kernel_seconds for rs in results)
-        per_pattern[name] = {
-            "graph": "degree-oriented" if is_clique(pats[pid]) else "symmetric",
-            "samples_per_s_kernel": args.steps * args.samples / ks,
-            "estimate": results[-1][pid].estimate,
-            "rel_var": results[-1][pid].variance / max(results[-1][pid].estimate ** 2, 1e-300),
-            "tables_ms": 1e3 * results[-1][pid].tables_seconds,
-        }
-    log(f"timed: {value:.4g} samples/s, {ms_per_step:.1f} ms/step"
-        + (f"; cliques on the symmetric graph instead: {value_symmetric:.4g} samples/s" if value_symmetric else ""))
+        rs = [results[k][pid] for k in range(args.steps)]
+        n, mean, var = merge_results(rs)
+        ks = sum(r.sample_kernel_seconds for r in rs)
+        entry = {"samples": int(n), "estimate": mean, "rel_var": var / max(mean * mean, 1e-300),
+                 "std_err_rel": math.sqrt(var / n) / abs(mean) if n and mean else None,
+                 "samples_per_s_kernel": n / ks if ks else None, "wall_s": walls[pid],
+                 "kernel_s": ks, "launches": int(sum(r.sample_launches for r in rs)),
+                 "tables_ms_per_estimate": 1e3 * float(np.mean([r.tables_seconds for r in rs]))}
+        if name in exact:
+            entry["exact"] = exact[name]
+            entry["rel_err_vs_exact"] = (mean - exact[name]) / exact[name]
+            entry["z_vs_exact"] = (mean - exact[name]) / math.sqrt(var / n) if var > 0 else None
+        per_pattern[name] = entry
+        log(f"{name}: estimate {mean:.6g} over {int(n)} samples"
+            + (f", exact {exact[name]:.6g} (rel err {entry['rel_err_vs_exact']:.2e})" if name in exact else ""))
 
-    # algorithmic bytes per sample, from dumped records of the timed stream
-    log("algorithmic bytes from sampled records")
-    bytes_per_sample = {}
-    rng = np.random.Generator(np.random.PCG64(3))
-    idx = np.sort(rng.integers(0, args.samples, size=args.bytes_records, dtype=np.uint64))
-    host_dag = None
-    for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
-        gg, tt = graph_of(p)
-        recs = sess.dump(gg, tt, p, 7, idx, mode="switch", pattern_id=pid)
-        hg = g
-        if gg is O:
-            if host_dag is None:
-                host_dag = HostCSR(*O.csr())
-            hg = host_dag
-        bytes_per_sample[name] = algorithmic_bytes(hg, results[0][pid].plan, recs)
-    # dominant kernel: the sampling kernel; bytes per launch = samples per
-    # launch x mean bytes per sample (equal sample counts per pattern)
-    mean_bytes = float(np.mean([bytes_per_sample[n] for n in PATTERNS]))
-    avg_launch_s = kern_s / launches
-    achieved_gbs = mean_bytes * args.samples / avg_launch_s / 1e9
-    # HBM traffic per launch from the committed FETCH_SIZE / WRITE_SIZE
-    # counter runs (calibrated on a plain copy), valid only while the kernel
-    # sources are the ones the counters were taken with; the counters give
-    # bytes per sample (mean over the four patterns), scaled to this launch
-    traffic = None
-    l2_hit = None
-    if os.path.exists(COUNTERS_FILE):
-        c = json.load(open(COUNTERS_FILE))
-        if c.get("kernel_source_sha") == kernel_source_hash():
-            traffic = c["hbm_bytes_per_sample_mean"] * args.samples
-            rates = [v.get("l2_hit_rate") for v in c["per_pattern"].values()]
-            if all(r is not None for r in rates):
-                l2_hit = {k: v["l2_hit_rate"] for k, v in c["per_pattern"].items()}
-    roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_sample", "avg_launch_ms": 1e3 * avg_launch_s,
-                "algorithmic_bytes_per_launch": mean_bytes * args.samples,
-                "algorithmic_bytes_per_sample": bytes_per_sample,
-                "traffic_gbs": (traffic / avg_launch_s / 1e9) if traffic else None,
-                "l2_hit_rate": l2_hit}
-
-    # learned proposal: one MLP per pattern, trained on extension counts the
-    # sampler produces on a smaller R-MAT graph (scale 18, seed 18), then
-    # BF16 inference into pick tables for this graph
-    learned = {}
-    if not args.skip_learned and not args.skip_eps:
-        from paper_2601_01388_amd.session import mlp_init
-        log("learned proposal: training graph R-MAT scale 18")
-        gtr = synth.rmat(18, 16, seed=18)
-        Gtr = sess.graph(gtr.off, gtr.nbr)
-        Ttr = sess.tables(Gtr, cv_seed=1)
-        ftr = sess.features(Ttr)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fev = sess.features(T)
-        torch.cuda.synchronize()
-        feat_s = time.perf_counter() - t0
-        residual = not args.learned_absolute
-        batch_rows = 4096
-        for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
-            t0 = time.perf_counter()
-            steps = sess.weighted_steps(p, "learned")
-            sums, counts = sess.learn_targets(Gtr, Ttr, p, args.train_samples, 101 + pid, mode="switch")
-            base_tr = sess.step_log_weights(Ttr, p) if residual else None
-            rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2, base=base_tr)
-            del sums, counts, base_tr
-            tg = rows["target"].cpu().numpy()
-            wt = rows["weight"].cpu().numpy()
-            init = mlp_init(7 + pid, float(np.average(tg, weights=wt)) if rows["rows"] else 0.0,
-                            zero_output=residual)
-            params = torch.from_numpy(init).to(sess.device)
-            per_epoch = max(1, -(-rows["rows"] // batch_rows))
-            epochs = max(args.train_epochs, -(-args.train_min_steps // per_epoch))
-            losses = sess.mlp_train(params, ftr, rows, epochs=epochs, batch=batch_rows, lr=3e-3, seed=pid)
-            torch.cuda.synchronize()
-            train_s = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            base_ev = sess.step_log_weights(T, p) if residual else None
-            tabs = sess.learned_tables(params, fev, p, base=base_ev, rows=rows)
-            del base_ev
-            torch.cuda.synchronize()
-            infer_s = time.perf_counter() - t0
-            learned[name] = {"tables": tabs, "ptrs": {i: tab.data_ptr() for i, tab in tabs.items()},
-                             "info": {"train_rows": rows["rows"], "train_seconds": train_s, "epochs": epochs,
-                                      "adam_steps": epochs * per_epoch, "residual": residual,
-                                      "loss_first_last": [losses[0], losses[-1]] if losses else None,
-                                      "infer_seconds": infer_s, "weighted_steps": steps}}
-            log(f"learned {name}: {rows['rows']} rows, {epochs} epochs, train {train_s:.2f} s, loss "
-                f"{losses[0]:.3g} -> {losses[-1]:.3g}, tables {infer_s * 1e3:.1f} ms")
-        Ttr.close()
-        Gtr.close()
-
-    # time to +-1% (95% CI) per pattern and proposal mode
-    eps_table = {}
-    if not args.skip_eps:
-        for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
-            for mode in ("learned", "switch", "always", "uniform"):
-                if mode == "learned" and name not in learned:
-                    continue
-                kw = dict(learned=learned[name]["ptrs"]) if mode == "learned" else {}
-                r = sess.estimate(G, T, p, args.eps_budget, 11, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
-                                  check_every=1 << 16, min_samples=1 << 14, **kw)
-                need = r.n * (r.eps_hat / 0.01) ** 2 if math.isfinite(r.eps_hat) else None
-                label = {"switch": "f_approx", "always": "f_approx_always", "uniform": "f_uniform",
-                         "learned": "learned"}[mode]
-                entry = {
-                    "seconds": r.seconds, "converged": bool(r.converged), "samples": r.n, "estimate": r.estimate,
-                    "eps_hat": r.eps_hat, "rel_var": r.variance / max(r.estimate ** 2, 1e-300),
-                    "samples_needed": need,
-                }
-                if mode == "learned":
-                    entry["seconds_incl_table_inference"] = r.seconds + learned[name]["info"]["infer_seconds"]
-                    entry.update(learned[name]["info"])
-                eps_table[f"{name}/{label}"] = entry
-                log(f"+-1% {name} {label}: {r.seconds:.3f} s, n={r.n}, rel.var {entry['rel_var']:.4g}, "
-                    f"converged={bool(r.converged)}")
-        for pid, name in enumerate(PATTERNS):
-            if f"{name}/learned" not in eps_table:
-                continue
-            eps_table[f"{name}/learned"]["rel_var_vs_f_approx"] = (
-                eps_table[f"{name}/learned"]["rel_var"] / max(eps_table[f"{name}/f_approx"]["rel_var"], 1e-300))
-            # fallback: a pilot of each proposal on fresh samples keeps the
-            # learned tables only if their variance per sample is lower
-            t0 = time.perf_counter()
-            pl = sess.estimate(G, T, pats[pid], args.pilot_samples, 97, mode="learned", pattern_id=pid,
-                               learned=learned[name]["ptrs"])
-            pa = sess.estimate(G, T, pats[pid], args.pilot_samples, 97, mode="switch", pattern_id=pid)
-            pilot_s = time.perf_counter() - t0
-            keep = pl.variance / max(pl.estimate ** 2, 1e-300) < pa.variance / max(pa.estimate ** 2, 1e-300)
-            chosen = eps_table[f"{name}/learned" if keep else f"{name}/f_approx"]
-            eps_table[f"{name}/learned_with_fallback"] = {
-                "chosen": "learned" if keep else "f_approx", "pilot_seconds": pilot_s,
-                "seconds": chosen["seconds"] + pilot_s, "samples": chosen["samples"],
-                "converged": chosen["converged"], "estimate": chosen["estimate"], "rel_var": chosen["rel_var"]}
-            log(f"{name}: pilot keeps {'learned' if keep else 'f_approx'}")
-
-    # incremental terms of f_approx (T[F1]; T[F1] T[I1]; all three) and the
-    # switching threshold beta, as in the paper's analysis of the
-    # approximation and of beta: variance per sample and the samples
-    # Algorithm 1 needs for +-1% at 95% (z^2 rel.var / eps^2)
-    ablation = None
-    if not args.skip_ablation:
-        z2 = 1.959963984540054 ** 2
-        ablation = {"samples": args.ablation_samples, "terms": {}, "beta": {}}
-        t0 = time.perf_counter()
-        for name in ["4-clique", "4-path", "5-clique", "5-cycle", "house"]:
-            p = synth.named_pattern(name)
-            row = {}
-            for terms in ("f1", "f1_i1", "all"):
-                r = sess.estimate(G, T, p, args.ablation_samples, 17, mode="switch", terms=terms)
-                rv = r.variance / max(r.estimate ** 2, 1e-300)
-                row[terms] = {"rel_var": rv, "samples_needed": z2 * rv / 1e-4, "estimate": r.estimate,
-                              "seconds_per_sample": r.seconds / r.n}
-            ablation["terms"][name] = row
-        betas = [("-inf", (-1, 0)), ("1/2", (1, 2)), ("4/5", (4, 5)), ("5/6", (5, 6)), ("1", (1, 1)),
-                 ("+inf", (1, 0))]
-        for name in ["house", "5-cycle", "6-cycle", "chordal-7-cycle"]:
-            p = synth.named_pattern(name)
-            row = {}
-            for label, beta in betas:
-                r = sess.estimate(G, T, p, args.ablation_samples, 19, mode="switch", beta=beta)
-                rv = r.variance / max(r.estimate ** 2, 1e-300)
-                row[label] = {"rel_var": rv, "samples_needed": z2 * rv / 1e-4, "estimate": r.estimate,
-                              "seconds_per_sample": r.seconds / r.n,
-                              "uniform_steps": int(sum(1 for i in range(p.k) if not r.plan.decision[i]))}
-            ablation["beta"][name] = row
-        ablation["seconds"] = time.perf_counter() - t0
-        log(f"term ablation and beta sweep: {ablation['seconds']:.1f} s")
-        for name, row in ablation["terms"].items():
-            log("  terms " + name + ": " + ", ".join(f"{k} {v['rel_var']:.3g}" for k, v in row.items()))
-        for name, row in ablation["beta"].items():
-            log("  beta " + name + ": " + ", ".join(f"{k} {v['rel_var']:.3g}" for k, v in row.items()))
-
-    # 32 connected patterns of 4-7 vertices (seed 3) with uneven budgets,
-    # all run to +-1% in one batch of rounds (each a persistent launch)
-    batch = None
-    if not args.skip_batch:
-        pset = synth.random_pattern_set(32, seed=3)
-        bpats = [p for p, _ in pset]
-        budgets = [max(1, int(b * args.batch_budget_scale)) for _, b in pset]
-        log(f"32-pattern batch to +-1%, total budget {sum(budgets):.3g} samples")
-        btune = tune_batch(args, sess, G, T, bpats, log)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = sess.estimate_batch(G, T, bpats, budgets, 13, mode="switch", eps=0.01, delta=0.05,
-                                  check_every=1 << 16, min_samples=1 << 14)
-        torch.cuda.synchronize()
-        bt = time.perf_counter() - t0
-        restore_tuning()
-        batch = {
-            "patterns": 32, "tuning": btune, "seconds": bt, "samples": int(sum(r.n for r in res)),
-            "converged": int(sum(r.converged for r in res)),
-            "samples_per_s": sum(r.n for r in res) / bt,
-            "budget_total": int(sum(budgets)),
-            "per_pattern": [{"k": p.k, "edges": len(p.edges), "budget": b, "samples": r.n,
-                             "converged": bool(r.converged), "seconds": r.seconds,
-                             "rel_var": r.variance / max(r.estimate ** 2, 1e-300)}
-                            for p, b, r in zip(bpats, budgets, res)],
-        }
-        log(f"batch: {bt:.2f} s, {batch['converged']}/32 converged, {batch['samples']:.3g} samples")
-
-    # cliques on the degree-oriented graph (each clique one trajectory) vs
-    # the symmetric graph: samples/s, variance per sample, time to +-1%
-    oriented = None
+    # the clique on the degree-oriented graph, as the method runs cliques
+    # (Sec. 5.4): the same steps with the 5-clique there instead
+    value_dag = None
+    dag = None
     if not args.skip_oriented:
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
         O = sess.orient(G)
         TO = sess.tables(O, cv_seed=1)
         torch.cuda.synchronize()
-        oriented = {"orient_and_tables_ms": 1e3 * (time.perf_counter() - t0), "nnz": O.nnz, "patterns": {}}
-        for k in (4, 5):
-            p = synth.patterns.clique(k)
-            row = {}
-            for label, (gg, tt) in (("oriented", (O, TO)), ("symmetric", (G, T))):
-                r = sess.estimate(gg, tt, p, args.samples, 29, mode="switch", pattern_id=k)
-                e = sess.estimate(gg, tt, p, args.eps_budget, 31, mode="switch", pattern_id=k, eps=0.01, delta=0.05,
-                                  check_every=1 << 16, min_samples=1 << 14)
-                row[label] = {"samples_per_s_kernel": r.n / max(r.sample_kernel_seconds, 1e-12),
-                              "rel_var": r.variance / max(r.estimate ** 2, 1e-300), "estimate": r.estimate,
-                              "time_to_1pct_s": e.seconds, "samples_to_1pct": e.n, "converged": bool(e.converged)}
-            oriented["patterns"][f"{k}-clique"] = row
-            log(f"{k}-clique oriented: {row['oriented']['samples_per_s_kernel']:.3g} samples/s, rel.var "
-                f"{row['oriented']['rel_var']:.3g}, +-1% in {row['oriented']['time_to_1pct_s']:.4f} s; symmetric: "
-                f"{row['symmetric']['samples_per_s_kernel']:.3g} samples/s, rel.var {row['symmetric']['rel_var']:.3g}, "
-                f"+-1% in {row['symmetric']['time_to_1pct_s']:.4f} s")
+        orient_s = time.perf_counter() - t1
+        cp = pats[PATTERNS.index("5-clique")]
+        sess.estimate(O, TO, cp, n_step, 1000, mode="switch", pattern_id=0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dres = [sess.estimate(O, TO, cp, n_step, 7, mode="switch", pattern_id=0, first_sample=k * n_step)
+                for k in range(args.steps)]
+        torch.cuda.synchronize()
+        dag_s = time.perf_counter() - t1
+        n, mean, var = merge_results(dres)
+        value_dag = total / (elapsed - walls[PATTERNS.index("5-clique")] + dag_s)
+        dag = {"orient_and_tables_ms": 1e3 * orient_s, "nnz": O.nnz, "wall_s": dag_s, "estimate": mean,
+               "rel_var": var / max(mean * mean, 1e-300), "value_with_clique_on_dag": value_dag}
+        if "5-clique" in exact:
+            dag["rel_err_vs_exact"] = (mean - exact["5-clique"]) / exact["5-clique"]
+        log(f"5-clique on the degree DAG: {dag_s:.3f} s for the same samples; steps would run at "
+            f"{value_dag:.4g} samples/s")
         TO.close()
         O.close()
 
-    # concentrations of all connected 4- and 5-vertex patterns (6 and 21),
-    # each pattern run to +-1% inside batched launches, as in the paper's
-    # comparison with MCMC estimators
-    concentration = None
-    if not args.skip_conc:
-        concentration = {}
-        for k in (4, 5):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = sess.concentrations(G, T, k, args.conc_budget, 23, mode="switch", eps=0.01, delta=0.05,
-                                      check_every=1 << 16, min_samples=1 << 14)
-            torch.cuda.synchronize()
-            ct = time.perf_counter() - t0
-            res = out["results"]
-            concentration[f"k{k}"] = {
-                "patterns": len(res), "seconds": ct, "budget_per_pattern": args.conc_budget,
-                "converged": int(sum(r.converged for r in res)), "samples": int(sum(r.n for r in res)),
-                "per_pattern": [{"edges": [list(e) for e in p[1]], "copies": r.copies, "eps_hat": r.eps_hat,
-                                 "conc_edge": float(ce), "conc_induced": float(ci), "induced": float(ind)}
-                                for p, r, ce, ci, ind in zip(out["patterns"], res, out["conc_edge"],
-                                                              out["conc_induced"], out["induced"])]}
-            log(f"concentrations k={k}: {len(res)} patterns, {concentration[f'k{k}']['converged']} converged, "
-                f"{ct:.2f} s")
+    # ---- roofline of the sampling kernel -------------------------------
+    log("roofline: metering sampled indices of the timed range")
+    rng = np.random.Generator(np.random.PCG64(3))
+    idx = np.sort(rng.choice(args.steps * n_step, size=min(args.meter_samples, args.steps * n_step), replace=False))
+    meter = {}
+    bytes_total = merge_total = 0.0
+    kern_total = 0.0
+    launches_total = 0
+    hbm_total = 0.0
+    counters = None
+    if os.path.exists(COUNTERS_FILE):
+        c = json.load(open(COUNTERS_FILE))
+        if c.get("kernel_source_sha") == kernel_source_hash():
+            counters = c
+    for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
+        m = sess.meter(G, T, p, 7, idx, mode="switch", pattern_id=pid, rowtab=rowtab).astype(np.float64)
+        rb, wb, segs, reqs = (float(x) for x in m.mean(axis=0))
+        recs = sess.dump(G, T, p, 7, idx[: args.bytes_records], mode="switch", pattern_id=pid, rowtab=rowtab)
+        mm = algorithmic_bytes(g, results[0][pid].plan, recs)
+        e = per_pattern[name]
+        nsamp = e["samples"]
+        meter[name] = {"read_bytes_per_sample": rb, "write_bytes_per_sample": wb, "segments_per_sample": segs,
+                       "requests_per_sample": reqs, "merge_model_bytes_per_sample": mm,
+                       "achieved_gbs": (rb + wb) * nsamp / e["kernel_s"] / 1e9,
+                       "segment_gbs": 64.0 * segs * nsamp / e["kernel_s"] / 1e9,
+                       "merge_model_gbs": mm * nsamp / e["kernel_s"] / 1e9}
+        bytes_total += (rb + wb) * nsamp
+        merge_total += mm * nsamp
+        kern_total += e["kernel_s"]
+        launches_total += e["launches"]
+        if counters and name in counters.get("per_pattern", {}):
+            hb = counters["per_pattern"][name]["hbm_bytes_per_sample"]
+            meter[name]["traffic_gbs"] = hb * nsamp / e["kernel_s"] / 1e9
+            hbm_total += hb * nsamp
+    achieved = bytes_total / kern_total / 1e9
+    seg_total = sum(meter[nm]["segments_per_sample"] * per_pattern[nm]["samples"] for nm in PATTERNS)
+    bytes_per_segment = bytes_total / max(seg_total, 1.0)
+    gather = None
+    frac_gather = None
+    s_match = None
+    ceiling = None
+    # the footprint the sampler gathers from: neighbour lists, offsets and
+    # vertex records (the per-step tables are a few MB more)
+    hot_bytes = 4 * g.nnz + 8 * (g.n + 1) + 16 * g.n
+    footprint = "128MiB" if hot_bytes <= (256 << 20) else "8GiB"
+    if not args.skip_gather:
+        wpc = 4 * (6 + (tuning["variant"] if tuning else 0))
+        log(f"random-gather ceiling at {wpc} waves per CU")
+        gather = gather_ceiling(sess, wpc)
+        s_match = min(GATHER_SIZES, key=lambda s: abs(math.log2(s) - math.log2(max(bytes_per_segment, 1.0))))
+        ceiling = gather[footprint][s_match]["dependent_gbs"]
+        frac_gather = achieved / ceiling
+        for label, rows in gather.items():
+            for S, row in rows.items():
+                log(f"  gather {label} {S:5d} B: dependent {row['dependent_gbs']:.0f} GB/s, independent "
+                    f"{row['independent_gbs']:.0f} GB/s")
+    roofline = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": (hbm_total / launches_total) if counters else None,
+        "kernel": "k_sample", "avg_launch_ms": 1e3 * kern_total / launches_total,
+        "algorithmic_bytes_per_launch": bytes_total / launches_total,
+        "bytes_model": "request bytes counted per sample by the metering kernel (agis_meter_samples)",
+        "segment_gbs": 64.0 * seg_total / kern_total / 1e9,
+        "bytes_per_segment": bytes_per_segment,
+        "gather_ceiling_gbs": ceiling,
+        "gather_ceiling_segment_bytes": s_match,
+        "gather_ceiling_footprint": footprint,
+        "hot_bytes": hot_bytes,
+        "frac_of_gather_ceiling": frac_gather,
+        "merge_model_gbs": merge_total / kern_total / 1e9,
+        "traffic_gbs": hbm_total / kern_total / 1e9 if counters else None,
+        "traffic_source": os.path.relpath(COUNTERS_FILE, ROOT) if counters else None,
+    }
+    log(f"roofline: {achieved:.0f} GB/s of request bytes ({roofline['frac']:.3f} of HBM peak"
+        + (f", {frac_gather:.2f} of the {s_match}-B dependent-gather ceiling over {footprint}"
+           if frac_gather else "") + ")")
 
-    # R-MAT scale 24 (generated on the GPU): the 32-pattern batch run to
-    # +-1%, and the learned proposal trained on extension counts of the
-    # scale-20 graph, evaluated against f_approx for variance per sample
+    detail = {"per_pattern": per_pattern, "meter": meter, "roofline": roofline, "gather": gather, "tuning": tuning,
+              "dag": dag}
+
+    learned = {}
+    if not args.skip_learned and not args.skip_eps:
+        learned = learned_four(args, sess, T, pats)
+    eps_table = None
+    if not args.skip_eps:
+        eps_table = time_to_eps(args, sess, G, T, pats, learned)
+        detail["time_to_1pct"] = eps_table
+    if not args.skip_ablation:
+        detail["term_ablation_and_beta"] = ablation_leg(args, sess, G, T)
+    batch = None
+    if not args.skip_batch:
+        batch = batch_leg(args, sess, G, T, restore_tuning)
+        detail["batch_32_patterns"] = batch
+    if not args.skip_oriented:
+        detail["cliques_oriented"] = oriented_leg(args, sess, G, T)
+    if not args.skip_conc:
+        detail["concentrations"] = conc_leg(args, sess, G, T)
     large = None
     if not args.skip_large:
         large = large_legs(args, sess, G, T, bpats_budgets(args), log, restore_tuning)
-
+        detail["rmat24"] = large
+    c1 = None
+    c1_gpu = None
+    if not (args.skip_c1 and args.skip_cpu):
+        c1 = synth.chung_lu(n=10000, m=100000, seed=1)
+    if not args.skip_c1:
+        c1_gpu = c1_gpu_leg(sess, c1)
+        detail["c1_gpu"] = c1_gpu
     cpu = None
     if not args.skip_cpu:
-        cpu = cpu_baseline(g, args.cpu_seconds)
-        log(f"cpu baseline {cpu['value']:.4g} samples/s")
+        cpu = cpu_baseline(g, c1, args.cpu_seconds)
+        detail["cpu_baseline"] = cpu
+        log(f"cpu baseline {cpu['value']:.4g} samples/s on {cpu['cores']} threads "
+            f"({cpu['single_thread_value']:.4g} on one); C1 in full {cpu['c1_full']['seconds']:.1f} s")
+        if c1_gpu:
+            diffs = [abs(c1_gpu["runs"][k]["estimate"] - v["mean"]) / max(abs(v["mean"]), 1e-300)
+                     for k, v in cpu["c1_full"]["runs"].items()]
+            detail["c1_gpu_vs_oracle_max_rel_diff"] = max(diffs)
+            log(f"C1: GPU vs oracle estimates, largest relative difference {max(diffs):.2e}")
+
+    detail["wall_seconds"] = time.perf_counter() - wall0
+    try:
+        os.makedirs(os.path.dirname(args.detail), exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump(detail, f, indent=1, default=float)
+        log(f"detail written to {args.detail}")
+    except OSError as e:
+        log(f"could not write the detail file: {e}")
 
     out = {
         "metric": "time to ±1% rel. err (95% CI) + samples/s: learned vs f_approx vs uniform",
         "value": value,
-        "value_cliques_on_symmetric_graph": value_symmetric,
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -708,35 +932,57 @@ def main():
         "dtype": "u32+f64",
         "data": "synthetic",
         "config": {
-            "workload": "R-MAT scale 20 (ef 16, a=.57 b=.19 c=.19), patterns 5-clique/5-cycle/house/4-star, "
-                        "f_approx with switching (beta=4/5); the clique on the degree-oriented graph (Sec. 5.4)",
-            "orientation_and_tables_ms": 1e3 * orient_s,
-            "samples_per_pattern_per_step": args.samples,
-            "graph": {"n": g.n, "nnz": g.nnz, "seed": 20},
-            "tables_ms": 1e3 * tables_s,
+            "workload": (f"R-MAT scale 20 (ef 16, a=.57 b=.19 c=.19, seed 20) symmetric CSR; 5-clique, 5-cycle, "
+                         f"house, 4-star; f_approx with switching (beta 4/5); {args.steps * n_step:.3g} samples per "
+                         f"pattern ({n_step} per step)"),
+            "n": g.n, "nnz": g.nnz, "samples_per_pattern": args.steps * n_step,
+            "graph_tables_ms": round(1e3 * tables_s, 1),
         },
-        "tuning": tuning,
-        "per_pattern": per_pattern,
-        "batch_32_patterns": batch,
-        "rmat24": large,
-        "concentrations": concentration,
-        "cliques_oriented": oriented,
-        "term_ablation_and_beta": ablation,
-        "time_to_1pct": eps_table,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "paper_context": {
-            "hardware": "AMD Ryzen Threadripper PRO 7985WX, 48 cores (C++/OpenMP, one sampler per thread)",
-            "graphs": "real graphs (LiveJournal to GSH-2015), eps = 0.1, delta = 0.01",
-            "geomean_speedup_vs_scalegpm": 28.5,
-            "geomean_speedup_vs_peregrine": 63108,
-            "note": "context only: the paper reports no samples/s and no GPU figure",
-        },
+        "value_cliques_on_degree_dag": value_dag,
+        "estimates": {k: {"estimate": v["estimate"], "rel_err_vs_exact": v.get("rel_err_vs_exact")}
+                      for k, v in per_pattern.items()},
+        "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                                              "avg_launch_ms", "gather_ceiling_gbs", "gather_ceiling_segment_bytes",
+                                              "gather_ceiling_footprint", "frac_of_gather_ceiling",
+                                              "merge_model_gbs", "traffic_gbs",
+                                              "traffic_source")},
     }
-    print(json.dumps(out), flush=True)
+    if eps_table:
+        out["time_to_1pct_s"] = {
+            name: {lab: round(eps_table[f"{name}/{lab}"]["seconds"], 5)
+                   for lab in ("learned", "learned_with_fallback", "f_approx", "f_uniform")
+                   if f"{name}/{lab}" in eps_table}
+            for name in PATTERNS}
+        out["samples_to_1pct"] = {
+            name: {lab: eps_table[f"{name}/{lab}"]["samples"] for lab in ("learned", "f_approx", "f_uniform")
+                   if f"{name}/{lab}" in eps_table}
+            for name in PATTERNS}
+    if batch:
+        out["batch32_rmat20"] = {"seconds": round(batch["seconds"], 3), "samples_per_s": batch["samples_per_s"],
+                                 "converged": batch["converged"]}
+    if large:
+        b = large["batch_32_patterns"]
+        lp = large["learned_32_patterns"]
+        out["rmat24"] = {"batch_seconds": round(b["seconds"], 3), "batch_converged": b["converged"],
+                         "budget_scale": b["budget_scale"],
+                         "learned_geomean_rel_var_vs_f_approx": lp["geomean_rel_var_learned_over_f_approx"],
+                         "with_fallback": lp["geomean_rel_var_with_fallback_over_f_approx"]}
+    if cpu:
+        out["cpu_baseline"] = {"value": cpu["value"], "unit": cpu["unit"], "cores": cpu["cores"], "kind": "oracle",
+                               "sample": cpu["sample"], "single_thread_value": cpu["single_thread_value"],
+                               "c1_full_seconds": round(cpu["c1_full"]["seconds"], 2),
+                               "host_model": cpu["host"]["model"], "nproc": cpu["host"]["nproc"]}
+    out["detail"] = os.path.relpath(args.detail, ROOT)
+    line = json.dumps(out)
+    for drop in ("samples_to_1pct", "estimates", "rmat24", "batch32_rmat20"):
+        if len(line) <= 4000:
+            break
+        out.pop(drop, None)
+        line = json.dumps(out)
     T.close()
     G.close()
     sess.close()
+    print(line, flush=True)
 
 
 if __name__ == "__main__":

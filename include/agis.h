@@ -52,7 +52,8 @@ enum {
     AGIS_E_OOM = -5,           /* device allocation failed */
     AGIS_E_HIP = -6,           /* HIP runtime error (message has the HIP string) */
     AGIS_E_NOT_CONVERGED = -7, /* run-to-epsilon hit its budget; result is filled */
-    AGIS_E_UNSUPPORTED = -8    /* request outside what this build supports */
+    AGIS_E_UNSUPPORTED = -8,   /* request outside what this build supports */
+    AGIS_E_CANCELLED = -9      /* the caller's cancel flag was seen; results hold the samples finished so far */
 };
 
 /* Proposal modes. */
@@ -119,7 +120,20 @@ typedef struct {
  *   (T[F1] only) and AGIS_TERMS_F1_I1 (T[F1] T[I1]).  The decision function
  *   and the reported plan are unchanged.
  * learned: for AGIS_MODE_LEARNED, per step a device int32[n] table of Q16
- *   log2 weights (NULL for steps that are not weighted); ignored otherwise. */
+ *   log2 weights (NULL for steps that are not weighted); ignored otherwise.
+ * first_sample: the run draws samples first_sample, first_sample + 1, ...
+ *   (0 for a fresh run); a run resumed where an earlier one stopped
+ *   continues the same sample sequence, so results over the concatenated
+ *   ranges equal one run over the whole range (checks of a resumed run
+ *   count its own samples).
+ * cancel: host int32 polled between rounds of samples (NULL: none); once
+ *   it reads nonzero the call returns AGIS_E_CANCELLED with every result
+ *   filled from the whole rounds that finished (a prefix of each pattern's
+ *   sample sequence, so a consistent partial estimate).
+ * batch_learned: for AGIS_MODE_LEARNED in agis_estimate_batch, a host array
+ *   of n_patterns x AGIS_MAX_K device table pointers (pattern i's tables at
+ *   [i * AGIS_MAX_K .. + AGIS_MAX_K), as `learned` of a single estimate);
+ *   ignored elsewhere. */
 #define AGIS_RUN_ROWTAB_AUTO 0u
 #define AGIS_RUN_ROWTAB_ON 1u
 #define AGIS_RUN_ROWTAB_OFF 2u
@@ -138,6 +152,9 @@ typedef struct {
     uint64_t check_every;
     uint64_t min_samples;
     const int32_t* learned[AGIS_MAX_K];
+    uint64_t first_sample;
+    const volatile int32_t* cancel;
+    const int32_t* const* batch_learned;
 } agis_run_params;
 
 /* Estimator output.  estimate = mean of the sample weights X (an unbiased
@@ -273,7 +290,7 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
  * exactly its budget.  Every per-pattern result equals what agis_estimate
  * gives for that pattern alone (same samples, same stopping point;
  * estimates to relative 1e-9).  out: host agis_result[n_patterns].
- * Learned mode is not accepted here (its tables are per pattern).
+ * Learned mode takes each pattern's tables from params->batch_learned.
  * Returns AGIS_E_NOT_CONVERGED (results filled) if any pattern did not
  * converge within its budget. */
 int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, uint32_t n_patterns,
@@ -351,10 +368,42 @@ int agis_concentrations(uint32_t n_patterns, const agis_pattern* patterns, const
                         double* induced, double* conc_induced);
 
 /* Runs the samples whose indices are listed in idx (device uint64[m]) and
- * writes one agis_record per index into out (device, m records). */
+ * writes one agis_record per index into out (device, m records).  At most
+ * 2^24 indices per call. */
 int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
                       const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
                       uint64_t m, agis_record* out);
+
+/* Memory requests of individual samples, for the roofline of the sampler
+ * (the random-gather bound of Algorithm 3's steps): runs the samples listed
+ * in idx (device uint64[m], at most 2^24) through the production paths of
+ * the sampling kernel -- the same choices as agis_estimate with the same
+ * params (pass AGIS_RUN_ROWTAB_ON or _OFF to match what the estimate used)
+ * -- and writes per sample four counters into out (device uint64[m][4]):
+ * bytes its global loads asked for, bytes its global stores wrote (the
+ * wave's candidate scratch and the weight slot), the 64-byte segments those
+ * accesses touched (an access spanning consecutive lanes counts each
+ * segment once; the merge-free upper bound of the lines it moves), and its
+ * wave-level memory requests.  LDS accesses are not counted. */
+int agis_meter_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                       const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
+                       uint64_t m, uint64_t* out);
+
+/* Random-gather microbenchmark (the ceiling the sampler's memory traffic is
+ * measured against): waves_per_cu (4..32, a multiple of 4) resident waves
+ * on every compute unit each run `rounds` rounds; in a round every group of
+ * seg_bytes / 16 lanes reads one random seg_bytes-aligned segment of
+ * seg_bytes bytes (one 16-byte word per lane; seg_bytes 4 or 8: every lane
+ * one item) from buffer (device, `bytes` bytes, 16-byte aligned, >= 1 KiB;
+ * its contents only steer the dependent chains).  dependent = 0: addresses
+ * from a counter, up to 8 reads in flight per lane; dependent = 1: each
+ * read's address depends on the previous read's value (a chain of
+ * dependent loads, like a search).  seg_bytes: a power of two in [4, 1024].
+ * sink: device, 8 KiB (folded values, never read back).  *seconds: kernel
+ * time (HIP events on the context's stream); *useful_bytes: bytes read. */
+int agis_gather_bench(agis_ctx* ctx, const void* buffer, uint64_t bytes, uint32_t seg_bytes, int32_t dependent,
+                      uint32_t waves_per_cu, uint32_t rounds, uint64_t seed, void* sink, double* seconds,
+                      double* useful_bytes);
 
 /* ---- Learned proposal ------------------------------------------------
  * A small MLP predicts, for a vertex v and the position of a weighted

@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no vectorisation tricks)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -122,6 +122,15 @@ def lib():
         L.orc_rooted_counts.argtypes = [P, P, u64, u64, P, P, u32, P]
         L.orc_rooted_counts.restype = u64
         L.orc_count_cliques.restype = u64
+        L.orc_build_tables_parallel.argtypes = [P, P, u64, u32, u32, i32, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_build_tables_parallel.restype = ctypes.c_int
+        L.orc_run_parallel.argtypes = [P, P, u64, u64, P, P, P, P, P, P, P, P, u64, u64, u64, u64, ctypes.c_int, P]
+        L.orc_run_parallel.restype = ctypes.c_int
+        L.orc_run_indices_parallel.argtypes = [P, P, u64, u64, P, P, P, P, P, P, P, P, u64, u64, P, u64, ctypes.c_int,
+                                               P]
+        L.orc_run_indices_parallel.restype = ctypes.c_int
+        L.orc_count_cliques_parallel.argtypes = [P, P, u64, u64, u32, ctypes.c_int]
+        L.orc_count_cliques_parallel.restype = u64
         _lib = L
     return _lib
 
@@ -166,9 +175,11 @@ class Tables:
     """Per-vertex proposal tables of Sec. 4.4 (host arrays)."""
 
     def __init__(self, g, cv_seed: int = 0, lc_min: int = LC_MIN_DEFAULT, exact_cv: bool = False,
-                 adjacency=None):
+                 adjacency=None, threads: int = 1):
         """adjacency: for an oriented g, the undirected graph that decides
-        whether two out-neighbours are adjacent (C_v over out-neighbours)."""
+        whether two out-neighbours are adjacent (C_v over out-neighbours).
+        threads != 1: the OpenMP flavour (0 = all host threads; same
+        entries, per vertex)."""
         n = g.n
         self.n = n
         self.deg = np.zeros(n, dtype=np.uint32)
@@ -182,7 +193,11 @@ class Tables:
         self.exact_cv = exact_cv
         off = np.ascontiguousarray(g.off, dtype=np.uint64)
         nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
-        if adjacency is None:
+        if adjacency is None and threads != 1:
+            lib().orc_build_tables_parallel(_p(off), _p(nbr), n, cv_seed & 0xFFFFFFFF, cv_seed >> 32, lc_min,
+                                            1 if exact_cv else 0, threads, _p(self.deg), _p(self.s2), _p(self.hits),
+                                            _p(self.trials), _p(self.la), _p(self.lc))
+        elif adjacency is None:
             lib().orc_build_tables(_p(off), _p(nbr), n, cv_seed & 0xFFFFFFFF, cv_seed >> 32, lc_min,
                                    1 if exact_cv else 0, _p(self.deg), _p(self.s2), _p(self.hits),
                                    _p(self.trials), _p(self.la), _p(self.lc))
@@ -312,13 +327,28 @@ class Sampler:
             raise MemoryError("oracle scratch allocation failed")
         return st, xs, recs
 
-    def records(self, indices) -> np.ndarray:
+    def records(self, indices, threads: int = 1) -> np.ndarray:
+        """threads != 1: the OpenMP flavour (0 = all host threads)."""
         idx = np.ascontiguousarray(indices, dtype=np.uint64)
         recs = np.zeros(idx.size, dtype=RECORD_DTYPE)
-        rc = lib().orc_run_indices(*self._common(), _p(idx), idx.size, _p(recs))
+        if threads != 1:
+            rc = lib().orc_run_indices_parallel(*self._common(), _p(idx), idx.size, threads, _p(recs))
+            rc = 0 if rc > 0 else -1
+        else:
+            rc = lib().orc_run_indices(*self._common(), _p(idx), idx.size, _p(recs))
         if rc != 0:
             raise MemoryError("oracle scratch allocation failed")
         return recs
+
+    def run_parallel(self, start: int, count: int, threads: int = 0):
+        """Samples [start, start + count) on host threads, one sampler per
+        thread over contiguous blocks merged in block order: (Stats, threads
+        used)."""
+        st = Stats()
+        rc = lib().orc_run_parallel(*self._common(), start, count, threads, ctypes.byref(st))
+        if rc < 0:
+            raise MemoryError("oracle scratch allocation failed (or fewer threads than asked)")
+        return st, rc
 
     def log_weights(self, i: int) -> np.ndarray:
         """f_approx Q16 log weight of every vertex at step i (certain zeros

@@ -764,3 +764,138 @@ uint64_t orc_count_cliques(const uint64_t* off, const uint32_t* nbr, uint64_t n,
     free(buf);
     return total;
 }
+
+/* ------------------------------------------------------------------ */
+/* OpenMP flavour: the same functions, the work split across host      */
+/* threads (one sampler per thread, as the paper's CPU implementation   */
+/* runs its samplers).  Every result equals the single-threaded one:    */
+/* table entries and records are per vertex and per sample, and the     */
+/* statistics of contiguous index blocks are merged in block order.     */
+/* ------------------------------------------------------------------ */
+#include <omp.h>
+
+/* orc_build_tables over all vertices on `threads` threads (0 = OpenMP's
+ * default).  Returns the number of threads used. */
+int orc_build_tables_parallel(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint32_t cv_seed_lo,
+                              uint32_t cv_seed_hi, int32_t lc_min, int exact_cv, int threads, uint32_t* deg,
+                              uint64_t* s2, uint64_t* hits, uint64_t* trials, int32_t* la, int32_t* lc) {
+    init_fixed_point();
+    uint32_t key[2] = {cv_seed_lo, cv_seed_hi};
+    int used = 1;
+    int nt = threads > 0 ? threads : omp_get_max_threads();
+#pragma omp parallel num_threads(nt)
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 4096)
+        for (int64_t v = 0; v < (int64_t)n; ++v)
+            tables_of_vertex(off, nbr, off, nbr, (uint64_t)v, key, lc_min, exact_cv, &deg[v], &s2[v], &hits[v],
+                             &trials[v], &la[v], &lc[v]);
+    }
+    return used;
+}
+
+/* Merges statistics b into a (Chan et al.'s pairwise update). */
+static void merge_stats(orc_stats* a, const orc_stats* b) {
+    if (b->n == 0) return;
+    if (a->n == 0) {
+        *a = *b;
+        return;
+    }
+    double na = (double)a->n, nb = (double)b->n, tot = na + nb;
+    double delta = b->mean - a->mean;
+    a->mean = a->mean + delta * (nb / tot);
+    a->m2 = a->m2 + b->m2 + delta * delta * (na * nb / tot);
+    a->n += b->n;
+    a->nonzero += b->nonzero;
+}
+
+/* orc_run over samples [start, start + count) on `threads` threads: thread
+ * t runs the t-th of `threads` contiguous blocks in index order with its own
+ * sampler, and the blocks' statistics are merged in block order into *st.
+ * Returns the number of threads used, or -1 when a scratch allocation
+ * failed. */
+int orc_run_parallel(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint64_t nnz, const uint32_t* deg,
+                     const uint64_t* s2, const int32_t* la, const int32_t* lc, const orc_plan* P,
+                     const int32_t* const* lt, const uint32_t* q1, const uint64_t* pre1, uint64_t Q1, uint64_t seed,
+                     uint64_t start, uint64_t count, int threads, orc_stats* st) {
+    int nt = threads > 0 ? threads : omp_get_max_threads();
+    orc_stats* part = (orc_stats*)calloc((size_t)nt, sizeof(orc_stats));
+    int* bad = (int*)calloc((size_t)nt, sizeof(int));
+    if (!part || !bad) {
+        free(part);
+        free(bad);
+        return -1;
+    }
+#pragma omp parallel num_threads(nt)
+    {
+        int t = omp_get_thread_num();
+        int tn = omp_get_num_threads();
+        uint64_t lo = count * (uint64_t)t / (uint64_t)tn, hi = count * (uint64_t)(t + 1) / (uint64_t)tn;
+        if (tn != nt) bad[t] = 1; /* fewer threads than asked: the blocks would not cover the range */
+        else if (hi > lo)
+            bad[t] = orc_run(off, nbr, n, nnz, deg, s2, la, lc, P, lt, q1, pre1, Q1, seed, start + lo, hi - lo,
+                             &part[t], NULL, NULL) != 0;
+    }
+    int rc = nt;
+    for (int t = 0; t < nt; ++t) {
+        if (bad[t]) rc = -1;
+        merge_stats(st, &part[t]);
+    }
+    free(part);
+    free(bad);
+    return rc;
+}
+
+/* orc_run_indices on `threads` threads (records are per sample). */
+int orc_run_indices_parallel(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint64_t nnz,
+                             const uint32_t* deg, const uint64_t* s2, const int32_t* la, const int32_t* lc,
+                             const orc_plan* P, const int32_t* const* lt, const uint32_t* q1, const uint64_t* pre1,
+                             uint64_t Q1, uint64_t seed, const uint64_t* idx, uint64_t count, int threads,
+                             orc_record* recs) {
+    int nt = threads > 0 ? threads : omp_get_max_threads();
+    int bad = 0;
+#pragma omp parallel num_threads(nt) reduction(| : bad)
+    {
+        int t = omp_get_thread_num();
+        int tn = omp_get_num_threads();
+        uint64_t lo = count * (uint64_t)t / (uint64_t)tn, hi = count * (uint64_t)(t + 1) / (uint64_t)tn;
+        if (hi > lo)
+            bad |= orc_run_indices(off, nbr, n, nnz, deg, s2, la, lc, P, lt, q1, pre1, Q1, seed, idx + lo, hi - lo,
+                                   recs + lo) != 0;
+    }
+    return bad ? -1 : nt;
+}
+
+/* orc_count_cliques with the vertices (each clique counted at its smallest
+ * vertex in the degree order) spread over `threads` threads. */
+uint64_t orc_count_cliques_parallel(const uint64_t* off, const uint32_t* nbr, uint64_t n, uint64_t nnz, uint32_t k,
+                                    int threads) {
+    orc_graph G = {n, nnz, off, nbr};
+    uint64_t md = max_degree(&G) + 1;
+    uint64_t total = 0;
+    int nt = threads > 0 ? threads : omp_get_max_threads();
+#pragma omp parallel num_threads(nt) reduction(+ : total)
+    {
+        uint32_t* out = (uint32_t*)malloc(md * sizeof(uint32_t));
+        uint32_t* buf = (uint32_t*)malloc(md * (uint64_t)(k + 1) * sizeof(uint32_t));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < (int64_t)n; ++v) {
+            uint64_t dv = off[v + 1] - off[v];
+            uint64_t no = 0;
+            for (uint64_t e = off[v]; e < off[v + 1]; ++e) {
+                uint32_t x = nbr[e];
+                uint64_t dx = off[x + 1] - off[x];
+                if (dx > dv || (dx == dv && x > (uint64_t)v)) out[no++] = x;
+            }
+            if (k == 1) {
+                total += 1;
+                continue;
+            }
+            total += clique_rec(&G, out, no, k - 1, buf, md * (uint64_t)(k + 1));
+        }
+        free(out);
+        free(buf);
+    }
+    return total;
+}

@@ -62,10 +62,14 @@ def rooted_counts(g, k, edges, order) -> np.ndarray:
     return out[: g.n]
 
 
-def clique_embeddings(g, k) -> int:
+def clique_embeddings(g, k, threads: int = 1) -> int:
+    """threads != 1: the vertices spread over host threads (0 = all)."""
     off = np.ascontiguousarray(g.off, dtype=np.uint64)
     nbr = np.ascontiguousarray(g.nbr, dtype=np.uint32)
-    copies = int(lib().orc_count_cliques(_p(off), _p(nbr), g.n, g.nnz, k))
+    if threads != 1:
+        copies = int(lib().orc_count_cliques_parallel(_p(off), _p(nbr), g.n, g.nnz, k, threads))
+    else:
+        copies = int(lib().orc_count_cliques(_p(off), _p(nbr), g.n, g.nnz, k))
     return copies * math.factorial(k)
 
 

@@ -30,6 +30,7 @@ AGIS_E_OOM = -5
 AGIS_E_HIP = -6
 AGIS_E_NOT_CONVERGED = -7
 AGIS_E_UNSUPPORTED = -8
+AGIS_E_CANCELLED = -9
 
 AGIS_MODE_UNIFORM = 0
 AGIS_MODE_SWITCH = 1
@@ -51,6 +52,7 @@ LC_MIN_DEFAULT = -10 * 65536
 _ERRNAMES = {
     -1: "AGIS_E_INVALID_ARG", -2: "AGIS_E_INVALID_CSR", -3: "AGIS_E_PATTERN", -4: "AGIS_E_ORDER",
     -5: "AGIS_E_OOM", -6: "AGIS_E_HIP", -7: "AGIS_E_NOT_CONVERGED", -8: "AGIS_E_UNSUPPORTED",
+    -9: "AGIS_E_CANCELLED",
 }
 
 
@@ -81,6 +83,9 @@ class agis_run_params(ctypes.Structure):
         ("eps", ctypes.c_double), ("delta", ctypes.c_double),
         ("check_every", ctypes.c_uint64), ("min_samples", ctypes.c_uint64),
         ("learned", ctypes.c_void_p * MAX_K),
+        ("first_sample", ctypes.c_uint64),
+        ("cancel", ctypes.c_void_p),
+        ("batch_learned", ctypes.c_void_p),
     ]
 
 
@@ -128,6 +133,11 @@ _SIGNATURES = [
                                      ctypes.c_uint64, ctypes.POINTER(agis_run_params), ctypes.POINTER(agis_result)]),
     ("agis_dump_samples", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
                                          ctypes.POINTER(agis_run_params), _P, ctypes.c_uint64, _P]),
+    ("agis_meter_samples", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
+                                          ctypes.POINTER(agis_run_params), _P, ctypes.c_uint64, _P]),
+    ("agis_gather_bench", ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
     ("agis_estimate_batch", ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, _P, ctypes.c_uint64,
                                            ctypes.POINTER(agis_run_params), _P]),
     ("agis_set_launch", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
@@ -231,7 +241,11 @@ def make_pattern(k: int, adj) -> agis_pattern:
 
 
 def make_params(mode="switch", beta=(4, 5), pattern_id=0, eps=0.0, delta=0.05, check_every=0, min_samples=0,
-                learned=None, rowtab="auto", terms="all") -> agis_run_params:
+                learned=None, rowtab="auto", terms="all", first_sample=0, cancel=None,
+                batch_learned=None) -> agis_run_params:
+    """Run parameters.  cancel: a ctypes.c_int32 the caller may set while the
+    call runs (kept alive by the caller); batch_learned: a ctypes array of
+    n_patterns * MAX_K table pointers (kept alive by the caller)."""
     pr = agis_run_params()
     pr.mode = MODE_BY_NAME[mode] if isinstance(mode, str) else int(mode)
     pr.flags = ROWTAB_BY_NAME[rowtab] if isinstance(rowtab, str) else int(rowtab)
@@ -245,7 +259,24 @@ def make_params(mode="switch", beta=(4, 5), pattern_id=0, eps=0.0, delta=0.05, c
     if learned:
         for i, ptr in learned.items():
             pr.learned[i] = ptr
+    pr.first_sample = first_sample
+    if cancel is not None:
+        pr.cancel = ctypes.addressof(cancel)
+    if batch_learned is not None:
+        pr.batch_learned = ctypes.addressof(batch_learned)
     return pr
+
+
+def batch_learned_array(tables_per_pattern):
+    """A host array of n_patterns * MAX_K device pointers for
+    agis_run_params.batch_learned: tables_per_pattern[i] maps step -> ptr
+    (or is None)."""
+    n = len(tables_per_pattern)
+    arr = (ctypes.c_void_p * (n * MAX_K))()
+    for i, tabs in enumerate(tables_per_pattern):
+        for j, ptr in (tabs or {}).items():
+            arr[i * MAX_K + j] = ptr
+    return arr
 
 
 def _order_arg(order):
@@ -268,10 +299,13 @@ def agis_compile_pattern(pattern: agis_pattern, order=None, params: agis_run_par
 
 def agis_estimate(ctx, g, t, pattern: agis_pattern, n_samples: int, seed: int, params: agis_run_params,
                   order=None) -> agis_result:
+    """The result carries .status: AGIS_OK, AGIS_E_NOT_CONVERGED or
+    AGIS_E_CANCELLED (other codes raise)."""
     out = agis_result()
     keep, ptr = _order_arg(order)
-    _check(ctx, lib().agis_estimate(ctx, g, t, ctypes.byref(pattern), ptr, n_samples, seed, ctypes.byref(params),
-                                    ctypes.byref(out)), allow=(AGIS_E_NOT_CONVERGED,))
+    out.status = _check(ctx, lib().agis_estimate(ctx, g, t, ctypes.byref(pattern), ptr, n_samples, seed,
+                                                 ctypes.byref(params), ctypes.byref(out)),
+                        allow=(AGIS_E_NOT_CONVERGED, AGIS_E_CANCELLED))
     del keep
     return out
 
@@ -284,6 +318,24 @@ def agis_dump_samples(ctx, g, t, pattern: agis_pattern, seed: int, params: agis_
     del keep
 
 
+def agis_meter_samples(ctx, g, t, pattern: agis_pattern, seed: int, params: agis_run_params, idx_ptr: int, m: int,
+                       out_ptr: int, order=None):
+    keep, ptr = _order_arg(order)
+    _check(ctx, lib().agis_meter_samples(ctx, g, t, ctypes.byref(pattern), ptr, seed, ctypes.byref(params), idx_ptr,
+                                         m, out_ptr))
+    del keep
+
+
+def agis_gather_bench(ctx, buf_ptr: int, nbytes: int, seg_bytes: int, dependent: bool, waves_per_cu: int,
+                      rounds: int, seed: int, sink_ptr: int):
+    """(seconds, useful_bytes) of one random-gather run."""
+    sec = ctypes.c_double()
+    ub = ctypes.c_double()
+    _check(ctx, lib().agis_gather_bench(ctx, buf_ptr, nbytes, seg_bytes, 1 if dependent else 0, waves_per_cu, rounds,
+                                        seed, sink_ptr, ctypes.byref(sec), ctypes.byref(ub)))
+    return float(sec.value), float(ub.value)
+
+
 def agis_estimate_batch(ctx, g, t, patterns, budgets, seed: int, params: agis_run_params):
     """patterns: list of agis_pattern; budgets: list of ints.  Returns a
     list of agis_result (NOT_CONVERGED is reported in each result)."""
@@ -291,9 +343,13 @@ def agis_estimate_batch(ctx, g, t, patterns, budgets, seed: int, params: agis_ru
     arr = (agis_pattern * n)(*patterns)
     bud = (ctypes.c_uint64 * n)(*budgets)
     out = (agis_result * n)()
-    _check(ctx, lib().agis_estimate_batch(ctx, g, t, n, ctypes.cast(arr, _P), ctypes.cast(bud, _P), seed,
-                                          ctypes.byref(params), ctypes.cast(out, _P)), allow=(AGIS_E_NOT_CONVERGED,))
-    return list(out)
+    rc = _check(ctx, lib().agis_estimate_batch(ctx, g, t, n, ctypes.cast(arr, _P), ctypes.cast(bud, _P), seed,
+                                               ctypes.byref(params), ctypes.cast(out, _P)),
+                allow=(AGIS_E_NOT_CONVERGED, AGIS_E_CANCELLED))
+    res = list(out)
+    for r in res:
+        r.status = rc
+    return res
 
 
 def agis_set_launch(ctx, use_graphs: bool = True, blocks_per_cu: int = 0, grab: int = 0, variant: int = 0,

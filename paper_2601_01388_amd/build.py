@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libagis.so")
-SOURCES = ["api.hip", "kernels.hip", "learned.hip", "pattern.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "learned.hip", "gather.hip", "pattern.cpp"]
 ARCH = os.environ.get("AGIS_OFFLOAD_ARCH", "gfx950")
 
 

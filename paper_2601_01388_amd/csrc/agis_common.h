@@ -225,6 +225,11 @@ struct RoundDesc {
 
 struct Record;
 
+// Sampler kernel modes: production, record-writing, request-metering.
+constexpr int kRun = 0;
+constexpr int kDumpRecords = 1;
+constexpr int kMeterSamples = 2;
+
 // Everything the sampling and reduction kernels of one round read, held in
 // device memory (one pointer argument: the fields are fetched through the
 // scalar cache where used instead of occupying registers for the whole
@@ -235,6 +240,7 @@ struct LaunchDesc {
     AGIS_CMEM const DevPlan* plans;  // read-only while a round runs: scalar loads
     AGIS_GMEM const uint64_t* idx;        // non-null: the single segment's sample indices
     AGIS_GMEM Record* dump;               // non-null: one record per slot
+    AGIS_GMEM uint64_t* meter;            // metering variant: 4 counters per slot
     AGIS_GMEM uint32_t* scratch;          // per wave: cap vertices + cap log weights
     uint64_t cap;
     AGIS_GMEM unsigned long long* queue;  // kQueues counters, kQueueStride apart

@@ -162,6 +162,7 @@ struct SampleLaunch {
     uint64_t max_slots = 0;  // largest round
     uint64_t max_tiles = 0;  // reduction tiles of the largest round
     bool dump = false;       // launch the record-writing variant
+    bool meter = false;      // launch the request-metering variant (needs idx)
     int variant = 0;         // register-budget variant
     uint32_t hub_window = 0; // see LaunchDesc::hub_window
     // the kernel with the pair-hub paths (set by the caller before
@@ -172,7 +173,7 @@ struct SampleLaunch {
 
 // The sampling kernel for (record-writing?, register-budget variant 0..2,
 // pair-hub paths?).
-const void* sample_kernel(bool dump, int variant, bool pairs);
+const void* sample_kernel(bool dump, int variant, bool pairs, bool meter);
 
 // Sizes the persistent grid (resident waves only) and the buffers for
 // rounds of at most max_slots samples over at most max_segs segments.
@@ -193,6 +194,6 @@ hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L
 // Host-side fill of the launch descriptor's buffers and shape (the round
 // part is filled by the caller); upload it to ctx->d_launch before a round.
 void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t, const uint64_t* idx,
-                 Record* dump, LaunchDesc* D);
+                 Record* dump, LaunchDesc* D, uint64_t* meter = nullptr);
 
 }  // namespace agis

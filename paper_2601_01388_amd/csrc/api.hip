@@ -468,7 +468,8 @@ int replay_or_launch(agis_ctx* ctx, const agis::SampleLaunch& L, const agis_grap
 // use indices 0, 1, 2, ... in order, so the stopping point of each pattern
 // depends only on its own samples.
 int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::vector<PatternRun>& runs,
-               const agis_run_params* pp, uint64_t seed) {
+               const agis_run_params* pp, uint64_t seed, bool* cancelled) {
+    *cancelled = false;
     const bool to_eps = pp->eps > 0;
     const uint64_t check = pp->check_every ? pp->check_every : 65536;
     const double z = normal_quantile(1.0 - (to_eps ? pp->delta : 0.05) / 2.0);
@@ -496,6 +497,18 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
     std::vector<uint32_t> members;
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
+        if (pp->cancel && *pp->cancel) {
+            // stop between rounds: every pattern keeps the whole rounds it
+            // finished, a prefix of its sample sequence
+            *cancelled = true;
+            const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            for (PatternRun& r : runs)
+                if (r.active) {
+                    r.active = false;
+                    r.seconds = now;
+                }
+            break;
+        }
         std::memset(&rd, 0, sizeof(rd));
         rd.k0 = (uint32_t)seed;
         rd.k1 = (uint32_t)(seed >> 32);
@@ -510,7 +523,7 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
             if (cnt == 0) continue;
             agis::Segment& S = rd.seg[rd.nseg++];
             S.plan = p;
-            S.start = r.done;
+            S.start = pp->first_sample + r.done;
             S.base = used;
             S.count = cnt;
             S.ntiles = (uint32_t)((cnt + agis::kReduceTileSamples - 1) / agis::kReduceTileSamples);
@@ -852,10 +865,12 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     if (rc != AGIS_OK) return rc;
     runs[0].budget = n_samples;
     const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    rc = run_rounds(ctx, g, t, runs, pp, seed);
+    bool cancelled = false;
+    rc = run_rounds(ctx, g, t, runs, pp, seed, &cancelled);
     if (rc != AGIS_OK) return rc;
     const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
     fill_result(runs[0], z, setup, out);
+    if (cancelled) return fail(ctx, AGIS_E_CANCELLED, "cancelled by the caller");
     if (pp->eps > 0 && !runs[0].converged) return fail(ctx, AGIS_E_NOT_CONVERGED, "sample budget reached before eps");
     return AGIS_OK;
 }
@@ -870,7 +885,8 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
     const agis_run_params dp = default_params();
     const agis_run_params* pp = params ? params : &dp;
     if (pp->eps > 0 && !(pp->delta > 0 && pp->delta < 1)) return fail(ctx, AGIS_E_INVALID_ARG, "delta must be in (0, 1)");
-    if (pp->mode == AGIS_MODE_LEARNED) return fail(ctx, AGIS_E_INVALID_ARG, "learned tables are per pattern: use agis_estimate");
+    if (pp->mode == AGIS_MODE_LEARNED && !pp->batch_learned)
+        return fail(ctx, AGIS_E_INVALID_ARG, "learned mode in a batch needs batch_learned (tables per pattern)");
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
     const auto t0 = std::chrono::steady_clock::now();
     StepTables st;
@@ -878,13 +894,16 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
     for (uint32_t i = 0; i < n_patterns; ++i) {
         agis_run_params pi = *pp;
         pi.pattern_id = pp->pattern_id + i;
+        if (pp->mode == AGIS_MODE_LEARNED)
+            for (int j = 0; j < AGIS_MAX_K; ++j) pi.learned[j] = pp->batch_learned[(size_t)i * AGIS_MAX_K + j];
         rc = prepare(ctx, g, t, &patterns[i], nullptr, &pi, budgets[i], &st, &runs[i].prep);
         if (rc != AGIS_OK) return rc;
         runs[i].budget = budgets[i];
         runs[i].active = budgets[i] > 0;
     }
     const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    rc = run_rounds(ctx, g, t, runs, pp, seed);
+    bool cancelled = false;
+    rc = run_rounds(ctx, g, t, runs, pp, seed, &cancelled);
     if (rc != AGIS_OK) return rc;
     const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
     bool all = true;
@@ -892,16 +911,20 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
         fill_result(runs[i], z, setup, &out[i]);
         all = all && runs[i].converged;
     }
+    if (cancelled) return fail(ctx, AGIS_E_CANCELLED, "cancelled by the caller");
     if (pp->eps > 0 && !all) return fail(ctx, AGIS_E_NOT_CONVERGED, "a pattern reached its budget before eps");
     return AGIS_OK;
 }
 
-int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
-                      const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
-                      uint64_t m, agis_record* out) {
+// Runs the samples listed in idx (device uint64[m]) once: with `out` the
+// record-writing kernel writes one record each; with `meter` the metering
+// kernel (production paths) writes four request counters each.
+static int run_indexed(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                       const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
+                       uint64_t m, agis_record* out, uint64_t* meter) {
     int rc = check_handles(ctx, g, t);
     if (rc != AGIS_OK) return ctx ? fail(ctx, rc, "bad handle") : rc;
-    if (!p || (m > 0 && (!idx || !out))) return fail(ctx, AGIS_E_INVALID_ARG, "null pattern, index list or output");
+    if (!p || (m > 0 && (!idx || (!out && !meter)))) return fail(ctx, AGIS_E_INVALID_ARG, "null pattern, index list or output");
     static_assert(sizeof(agis_record) == sizeof(agis::Record), "record layout");
     const agis_run_params dp = default_params();
     const agis_run_params* pp = params ? params : &dp;
@@ -911,15 +934,16 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     rc = prepare(ctx, g, t, p, order, pp, m, &st, &prep);
     if (rc != AGIS_OK) return rc;
     if (m == 0) return AGIS_OK;
-    if (m > kMaxRoundSlots) return fail(ctx, AGIS_E_INVALID_ARG, "at most 2^24 records per call");
+    if (m > kMaxRoundSlots) return fail(ctx, AGIS_E_INVALID_ARG, "at most 2^24 samples per call");
     agis::SampleLaunch L;
     L.pairs = uses_pair_hubs(prep.hp, t);
     rc = agis::plan_sample_launch(ctx, *g, m, 1, &L, &ctx->err);
     if (rc != AGIS_OK) return rc;
-    L.dump = true;
+    L.dump = out != nullptr;
+    L.meter = out == nullptr;
     agis::LaunchDesc ld;
     std::memset(&ld, 0, sizeof(ld));
-    agis::fill_launch(ctx, L, g->g, dev_tables(t), idx, (agis::Record*)out, &ld);
+    agis::fill_launch(ctx, L, g->g, dev_tables(t), idx, (agis::Record*)out, &ld, meter);
     agis::RoundDesc& rd = ld.round;
     rd.total = m;
     rd.nseg = 1;
@@ -933,6 +957,20 @@ int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, 
     AGIS_HIP(ctx, agis::launch_round(ctx, ctx->stream, L, nullptr, nullptr), "launch sampler");
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "sampler");
     return AGIS_OK;
+}
+
+int agis_dump_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                      const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
+                      uint64_t m, agis_record* out) {
+    if (ctx && m > 0 && !out) return fail(ctx, AGIS_E_INVALID_ARG, "null output");
+    return run_indexed(ctx, g, t, p, order, seed, params, idx, m, out, nullptr);
+}
+
+int agis_meter_samples(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                       const uint8_t* order, uint64_t seed, const agis_run_params* params, const uint64_t* idx,
+                       uint64_t m, uint64_t* out) {
+    if (ctx && m > 0 && !out) return fail(ctx, AGIS_E_INVALID_ARG, "null output");
+    return run_indexed(ctx, g, t, p, order, seed, params, idx, m, nullptr, out);
 }
 
 int agis_set_launch(agis_ctx* ctx, int32_t use_graphs, int32_t blocks_per_cu, uint32_t grab, int32_t variant,

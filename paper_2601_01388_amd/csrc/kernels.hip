@@ -129,6 +129,79 @@ __device__ __forceinline__ void wave_segments(uint32_t key, int& head, bool& tai
     tail = lane == kWave - 1 || next != key;
 }
 
+// Memory-request accounting of the sampler.  The production kernel carries
+// NoMeter (every call compiles to nothing); the metering kernel carries a
+// Meter, which counts for one sample the bytes its global loads (reads) and
+// stores (writes) ask for, the 64-byte segments each wave-level access
+// touches (an access's segments, less the first one when it is the previous
+// lane's last), and the wave-level requests.  Every method is called by the
+// whole wave with wave-uniform counters; LDS traffic is not counted.
+struct NoMeter {
+    static constexpr bool kOn = false;
+    __device__ __forceinline__ void vec(const void*, uint32_t, bool, bool = false) {}
+    __device__ __forceinline__ void uni(const void*, uint32_t, bool = false) {}
+    __device__ __forceinline__ void lanes(uint32_t, uint32_t) {}
+    __device__ __forceinline__ void span(const void*, uint64_t, uint32_t) {}
+};
+
+struct Meter {
+    static constexpr bool kOn = true;
+    uint64_t rbytes = 0, wbytes = 0, segs = 0, reqs = 0;
+    // one access of `width` bytes (per lane) at p by every lane with `active`
+    __device__ __forceinline__ void vec(const void* p, uint32_t width, bool active, bool write = false) {
+        const uint64_t am = __ballot(active);
+        if (am == 0) return;
+        const int lane = lane_id();
+        const uint64_t a = (uint64_t)(uintptr_t)p;
+        const uint64_t s0 = a >> 6, s1 = (a + width - 1) >> 6;
+        const uint64_t prev = __shfl_up(s1, 1, kWave);
+        const bool pact = lane > 0 && ((am >> (lane - 1)) & 1ull);
+        const uint64_t mine = active ? (s1 - s0 + 1 - ((pact && prev == s0) ? 1 : 0)) : 0;
+        const uint64_t b = wave_sum_u64(active ? (uint64_t)width : 0ull);
+        if (write)
+            wbytes += b;
+        else
+            rbytes += b;
+        segs += wave_sum_u64(mine);
+        reqs += 1;
+    }
+    // one wave-uniform access of `width` bytes at p
+    __device__ __forceinline__ void uni(const void* p, uint32_t width, bool write = false) {
+        const uint64_t a = (uint64_t)(uintptr_t)p;
+        if (write)
+            wbytes += width;
+        else
+            rbytes += width;
+        segs += ((a + width - 1) >> 6) - (a >> 6) + 1;
+        reqs += 1;
+    }
+    // independent per-lane loops of `loads` accesses of `width` bytes each
+    // at scattered addresses (binary searches): one segment per access, as
+    // many wave-level requests as the longest loop
+    __device__ __forceinline__ void lanes(uint32_t loads, uint32_t width) {
+        uint64_t v = loads;
+        const uint64_t tot = wave_sum_u64(v);
+        uint32_t mx = loads;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t w = (uint32_t)__shfl_xor((int)mx, o, kWave);
+            mx = w > mx ? w : mx;
+        }
+        rbytes += tot * width;
+        segs += tot;
+        reqs += mx;
+    }
+    // a contiguous read of `bytes` bytes at p in wave-level requests of
+    // `per_req` bytes
+    __device__ __forceinline__ void span(const void* p, uint64_t bytes, uint32_t per_req) {
+        if (bytes == 0) return;
+        const uint64_t a = (uint64_t)(uintptr_t)p;
+        rbytes += bytes;
+        segs += ((a + bytes - 1) >> 6) - (a >> 6) + 1;
+        reqs += (bytes + per_req - 1) / per_req;
+    }
+};
+
 // Inclusive sum of v over this lane's segment so far.
 __device__ __forceinline__ uint64_t wave_segmented_sum_u64(uint64_t v, int head) {
     const uint64_t incl = wave_incl_scan_u64(v);
@@ -154,6 +227,22 @@ __device__ __forceinline__ bool contains_u32(const uint32_t* __restrict__ list, 
     return p < len && list[p] == x;
 }
 
+// contains_u32 that also adds its element reads to `loads`
+__device__ __forceinline__ bool contains_u32_counted(const uint32_t* __restrict__ list, uint32_t len, uint32_t x,
+                                                     uint32_t& loads) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        ++loads;
+        if (list[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo < len) ++loads;
+    return lo < len && list[lo] == x;
+}
+
 // Row of edge slot e: the vertex v with off[v] <= e < off[v + 1].
 __device__ __forceinline__ uint32_t row_of_slot(const uint64_t* __restrict__ off, uint64_t n, uint64_t e) {
     uint64_t lo = 0, hi = n;  // first v with off[v + 1] > e
@@ -169,13 +258,16 @@ __device__ __forceinline__ uint32_t row_of_slot(const uint64_t* __restrict__ off
 
 // Wave-cooperative 64-ary search: first index p in [0, n) with a[p] > r,
 // given a non-decreasing and a[n - 1] > r.  Every lane returns the answer.
-__device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r) {
+template <class MT = NoMeter>
+__device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restrict__ a, uint64_t n, uint64_t r,
+                                                       MT&& mt = MT()) {
     const int lane = lane_id();
     uint64_t lo = 0, hi = n - 1;  // answer in [lo, hi], a[hi] > r
     while (hi - lo + 1 > (uint64_t)kWave) {
         const uint64_t step = (hi - lo + kWave) >> 6;
         const uint64_t p = lo + (uint64_t)lane * step;
         const bool valid = p <= hi;
+        mt.vec(a + p, 8, valid);
         const bool pred = valid && a[p] > r;
         const uint64_t m = __ballot(pred);
         if (m == 0) {
@@ -190,6 +282,7 @@ __device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restric
         }
     }
     const uint64_t p = lo + (uint64_t)lane;
+    mt.vec(a + p, 8, p <= hi);
     const bool pred = p <= hi && a[p] > r;
     const uint64_t m = __ballot(pred);
     return lo + (uint64_t)(__ffsll((unsigned long long)m) - 1);
@@ -197,12 +290,15 @@ __device__ __forceinline__ uint64_t wave_first_greater(const uint64_t* __restric
 
 // Wave-cooperative: first position p in [lo, hi) with list[p] > key, or hi
 // when there is none (list ascending).
-__device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __restrict__ list, uint32_t lo, uint32_t hi, uint32_t key) {
+template <class MT = NoMeter>
+__device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __restrict__ list, uint32_t lo, uint32_t hi,
+                                                           uint32_t key, MT&& mt = MT()) {
     const int lane = lane_id();
     while (hi - lo > (uint32_t)kWave) {  // answer in [lo, hi]
         const uint32_t step = (hi - lo + kWave - 1) >> 6;
         const uint32_t p = lo + (uint32_t)lane * step;
         const bool valid = p < hi;
+        mt.vec(list + p, 4, valid);
         const uint64_t m = __ballot(valid && list[p] > key);
         if (m == 0) {
             const int last = 63 - __clzll(__ballot(valid));
@@ -215,6 +311,7 @@ __device__ __forceinline__ uint32_t wave_first_greater_u32(const uint32_t* __res
         }
     }
     const uint32_t p = lo + (uint32_t)lane;
+    mt.vec(list + p, 4, p < hi);
     const uint64_t m = __ballot(p < hi && list[p] > key);
     return m ? lo + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
 }
@@ -260,8 +357,9 @@ __device__ __forceinline__ bool piece_contains(uint32_t val, uint32_t xv) {
 // Lane q receives the first position whose element is not below its key
 // (d when there is none) and, in `found`, whether that element is the key.
 // Every lane must call it; nq (<= 8, wave-uniform) bounds the query lanes.
+template <class MT>
 __device__ __forceinline__ uint32_t wave_lower_bound_keys(const uint32_t* __restrict__ list, uint32_t d, uint32_t key,
-                                                          bool need, uint32_t nq, bool& found) {
+                                                          bool need, uint32_t nq, bool& found, MT& mt) {
     const int lane = lane_id();
     const int sh = nq <= 4 ? 4 : 3;
     const uint32_t G = 1u << sh;
@@ -286,6 +384,7 @@ __device__ __forceinline__ uint32_t wave_lower_bound_keys(const uint32_t* __rest
         const uint32_t a = div(span), b = span - a * (G + 1u);
         auto at = [&](uint32_t t) { return lo + t * a + div(t * b); };
         const uint32_t p = at(s + 1u);
+        mt.vec(list + p, 4, active);
         const uint32_t val = active ? list[p] : 0u;
         // probes below the key form a prefix of the group's probes
         const uint32_t c = (uint32_t)__popcll(__ballot(active && val < qkey) & gmask);
@@ -306,8 +405,10 @@ __device__ __forceinline__ uint32_t wave_lower_bound_keys(const uint32_t* __rest
     return bperm(lo, src);
 }
 
+template <class MT>
 __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict__ list, uint32_t pos, uint32_t len,
-                                                      uint32_t xv, uint32_t xlast, uint32_t left, bool& member) {
+                                                      uint32_t xv, uint32_t xlast, uint32_t left, bool& member,
+                                                      MT& mt) {
     const int lane = lane_id();
     // expected window (len - pos) * 64 / left <= kStreamMaxWindow, without a
     // division; the streaming path takes positions as 32-bit signed values
@@ -335,12 +436,18 @@ __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict
             // end the window.
             uint32_t v0, v1, v2, v3;
             if (qs >= 0 && qs + 4 * kWave <= ilen) {  // the whole block is in the list
+                mt.vec(list + e, 16, true);
                 const uint4 q = *reinterpret_cast<const uint4*>(list + e);
                 v0 = q.x;
                 v1 = q.y;
                 v2 = q.z;
                 v3 = q.w;
             } else {
+                if constexpr (MT::kOn) {
+                    // the elements of the block inside the list
+                    const int32_t ea = e < 0 ? 0 : e, eb = e + 4 < ilen ? e + 4 : ilen;
+                    mt.vec(list + ea, eb > ea ? 4u * (uint32_t)(eb - ea) : 4u, eb > ea);
+                }
                 v0 = e < 0 ? 0u : (e < ilen ? list[e] : kNone);
                 v1 = e + 1 < 0 ? 0u : (e + 1 < ilen ? list[e + 1] : kNone);
                 v2 = e + 2 < 0 ? 0u : (e + 2 < ilen ? list[e + 2] : kNone);
@@ -375,6 +482,7 @@ __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict
         }
     }
     const uint32_t p = pos + (uint32_t)lane;
+    mt.vec(list + p, 4, p < len);
     const uint32_t val = p < len ? list[p] : 0xFFFFFFFFu;
     const uint64_t gt = __ballot(val > xlast);
     if (gt != 0) {
@@ -382,8 +490,14 @@ __device__ __forceinline__ uint32_t co_iterate_member(const uint32_t* __restrict
         member = member && in;
         return pos + (uint32_t)(__ffsll((unsigned long long)gt) - 1);
     }
-    const uint32_t end = wave_first_greater_u32(list, pos + kWave, len, xlast);
-    if (member) member = contains_u32(list + pos, end - pos, xv);
+    const uint32_t end = wave_first_greater_u32(list, pos + kWave, len, xlast, mt);
+    if constexpr (MT::kOn) {
+        uint32_t loads = 0;
+        if (member) member = contains_u32_counted(list + pos, end - pos, xv, loads);
+        mt.lanes(loads, 4);
+    } else {
+        if (member) member = contains_u32(list + pos, end - pos, xv);
+    }
     return end;
 }
 
@@ -1233,16 +1347,29 @@ namespace {
 // are both pair hubs: the table's |N(a) cap N(b)| less the other matched
 // vertices found in both bitmaps (a and b lie in neither of their own
 // lists).  Returns false, and leaves `out`, when either is not a pair hub.
+template <class MT>
 __device__ __forceinline__ bool pair_hub_count(const DevTables& t, uint32_t my_tau, uint32_t bm, uint32_t i,
-                                               uint64_t& out) {
+                                               uint64_t& out, MT& mt) {
     const int lane = lane_id();
     const uint32_t a = readlane_u32(my_tau, __builtin_ctz(bm));
     const uint32_t b = readlane_u32(my_tau, 31 - __builtin_clz(bm));
+    mt.uni(t.pair_slot + a, 4);
+    mt.uni(t.pair_slot + b, 4);
     const int32_t sa = t.pair_slot[a], sb = t.pair_slot[b];
     if (sa < 0 || sb < 0) return false;
+    mt.uni(t.pair_count + (uint64_t)sa * t.pairs + (uint64_t)sb, 4);
     const uint32_t c = t.pair_count[(uint64_t)sa * t.pairs + (uint64_t)sb];
     bool both = false;
-    if ((uint32_t)lane < i && my_tau != a && my_tau != b) {
+    const bool probe = (uint32_t)lane < i && my_tau != a && my_tau != b;
+    if constexpr (MT::kOn) {
+        if (__ballot(probe)) {
+            mt.uni(t.hub_slot + a, 4);
+            mt.uni(t.hub_slot + b, 4);
+            mt.vec(t.hub_bits + (uint64_t)t.hub_slot[a] * t.hub_words + (my_tau >> 5), 4, probe);
+            mt.vec(t.hub_bits + (uint64_t)t.hub_slot[b] * t.hub_words + (my_tau >> 5), 4, probe);
+        }
+    }
+    if (probe) {
         const auto ba = t.hub_bits + (uint64_t)t.hub_slot[a] * t.hub_words;
         const auto bb = t.hub_bits + (uint64_t)t.hub_slot[b] * t.hub_words;
         const uint32_t w = my_tau >> 5, m = 1u << (my_tau & 31u);
@@ -1260,11 +1387,14 @@ __device__ __forceinline__ bool pair_hub_count(const DevTables& t, uint32_t my_t
 // elements at the cuts).  The part holding rank r is walked 64 elements at
 // a time, each probed in the other hub's bitmap, from its nearer end (ranks
 // then counted from that end).
+template <class MT>
 __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const DevTables& t, uint32_t my_tau, uint32_t bm,
-                                                    uint32_t i, uint64_t r, uint64_t m) {
+                                                    uint32_t i, uint64_t r, uint64_t m, MT& mt) {
     const int lane = lane_id();
     const uint32_t a = readlane_u32(my_tau, __builtin_ctz(bm));
     const uint32_t b = readlane_u32(my_tau, 31 - __builtin_clz(bm));
+    mt.uni(g.off + a, 16);
+    mt.uni(g.off + b, 16);
     const uint64_t oa = g.off[a], ob = g.off[b];
     const uint64_t da = g.off[a + 1] - oa, db = g.off[b + 1] - ob;
     const bool walk_a = da < db || (da == db && a < b);
@@ -1273,7 +1403,16 @@ __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const Dev
     const auto row = t.hub_bits + (uint64_t)t.hub_slot[walk_a ? b : a] * t.hub_words;
     // matched vertices (other than a and b) that lie in both lists
     bool both = false;
-    if ((uint32_t)lane < i && my_tau != a && my_tau != b) {
+    const bool probe = (uint32_t)lane < i && my_tau != a && my_tau != b;
+    if constexpr (MT::kOn) {
+        if (__ballot(probe)) {
+            mt.uni(t.hub_slot + a, 4);
+            mt.uni(t.hub_slot + b, 4);
+            mt.vec(t.hub_bits + (uint64_t)t.hub_slot[a] * t.hub_words + (my_tau >> 5), 4, probe);
+            mt.vec(t.hub_bits + (uint64_t)t.hub_slot[b] * t.hub_words + (my_tau >> 5), 4, probe);
+        }
+    }
+    if (probe) {
         const auto ra = t.hub_bits + (uint64_t)t.hub_slot[a] * t.hub_words;
         const auto rb = t.hub_bits + (uint64_t)t.hub_slot[b] * t.hub_words;
         const uint32_t w = my_tau >> 5, mk = 1u << (my_tau & 31u);
@@ -1283,8 +1422,12 @@ __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const Dev
     // lies between the last cut at or below r and the next)
     const auto q = t.pair_quart + ((uint64_t)t.pair_slot[a] * t.pairs + (uint64_t)t.pair_slot[b]) * (kPairParts - 1);
     uint32_t cutv[kPairParts - 1], qv[kPairParts - 1];
+    mt.uni(t.pair_slot + a, 4);
+    mt.uni(t.pair_slot + b, 4);
+    mt.uni(q, 4 * (kPairParts - 1));
 #pragma unroll
     for (int j = 1; j < kPairParts; ++j) {
+        mt.uni(list + (uint64_t)j * d / kPairParts, 4);
         cutv[j - 1] = list[(uint64_t)j * d / kPairParts];
         qv[j - 1] = q[j - 1];
     }
@@ -1308,7 +1451,9 @@ __device__ __forceinline__ uint32_t pair_hub_select(const DevGraph& g, const Dev
     for (uint64_t c = 0; c < len; c += kWave) {
         const uint64_t e = c + (uint64_t)lane;
         const bool valid = e < len;
+        mt.vec(list + (forward ? from + e : from + len - 1 - e), 4, valid);
         const uint32_t x = valid ? list[forward ? from + e : from + len - 1 - e] : 0u;
+        mt.vec(row + (x >> 5), 4, valid);
         bool keep = valid && ((row[x >> 5] >> (x & 31u)) & 1u) != 0;
         for (uint32_t j = 0; j < i; ++j) keep = keep && x != readlane_u32(my_tau, (int)j);
         uint64_t bal = __ballot(keep);
@@ -1332,6 +1477,21 @@ __device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int
     return lt ? lt[v] : approx_log_weight(r, b, f1, ie, f2);
 }
 
+// The reads step_log_weight makes for the lanes with `active` (called by
+// the whole wave).
+template <class MT>
+__device__ __forceinline__ void meter_step_log_weight(const DevTables& t, const int32_t* sw, const int32_t* lt,
+                                                      uint32_t v, uint32_t b, uint32_t f1, bool active, MT& mt) {
+    if constexpr (MT::kOn) {
+        if (sw) {
+            mt.vec(sw + v, 4, active);
+            return;
+        }
+        mt.vec(t.rec + v, 16, active);
+        if (lt) mt.vec(lt + v, 4, active && t.rec[active ? v : 0].x >= b + f1);
+    }
+}
+
 // In-order sample: returns its weight X; lane 0 writes the record when
 // rec != nullptr.  `my_tau` of lane j holds the data vertex matched at step
 // j (wave-uniform by construction).  sv/sl: this wave's scratch for the
@@ -1339,10 +1499,10 @@ __device__ __forceinline__ int32_t step_log_weight(const DevTables& t, const int
 // candidates per lane up to which a weighted pick keeps them in registers
 constexpr int kPickBlock = 8;
 
-template <bool kDump, bool kPairs>
+template <bool kDump, bool kPairs, class MT>
 __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P,
                              uint32_t k0, uint32_t k1, uint64_t s, uint32_t* __restrict__ sv,
-                             int32_t* __restrict__ sl, Record* __restrict__ rec, uint32_t hub_window) {
+                             int32_t* __restrict__ sl, Record* __restrict__ rec, uint32_t hub_window, MT& mt) {
     const int lane = lane_id();
     const uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = P->pattern_id;
     const uint32_t k = P->k;
@@ -1368,12 +1528,14 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 if (P->s1_guide) {
                     // the answer lies between the guides of r's bucket and the next
                     const uint64_t bkt = r >> P->s1_shift;
+                    mt.uni(P->s1_guide + bkt, 8);
                     const uint32_t lo = P->s1_guide[bkt], hi = P->s1_guide[bkt + 1];
-                    v = lo + (uint32_t)wave_first_greater(P->s1_pre + lo, (uint64_t)(hi - lo) + 1, r);
+                    v = lo + (uint32_t)wave_first_greater(P->s1_pre + lo, (uint64_t)(hi - lo) + 1, r, mt);
                 } else {
-                    v = (uint32_t)wave_first_greater(P->s1_pre, g.n, r);
+                    v = (uint32_t)wave_first_greater(P->s1_pre, g.n, r, mt);
                 }
                 num = P->s1_total;
+                mt.uni(P->s1_q + v, 4);
                 den = P->s1_q[v];
             } else {
                 if (g.nnz == 0) {
@@ -1381,8 +1543,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     break;
                 }
                 const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, g.nnz);
-                v = (uint32_t)wave_first_greater(g.off + 1, g.n, r);
+                v = (uint32_t)wave_first_greater(g.off + 1, g.n, r, mt);
                 num = g.nnz;
+                mt.uni(g.off + v, 16);
                 den = g.off[v + 1] - g.off[v];
             }
             x = (double)num / (double)den;
@@ -1400,6 +1563,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 // weights of matched vertices found in N(w), then search the
                 // prefix segment by segment between their positions.
                 const uint32_t w = readlane_u32(my_tau, __builtin_ctz(bm));
+                mt.uni(g.off + w, 16);
                 const uint64_t o = g.off[w];
                 const uint32_t d = (uint32_t)(g.off[w + 1] - o);
                 const uint32_t* list = g.nbr + o;
@@ -1413,7 +1577,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const bool need = mine && my_row != w;
                 if (__ballot(need)) {
                     bool f;
-                    const uint32_t pq = wave_lower_bound_keys(list, d, my_tau, need, i, f);
+                    const uint32_t pq = wave_lower_bound_keys(list, d, my_tau, need, i, f, mt);
                     if (need) {
                         pos = pq;
                         found = f;
@@ -1422,6 +1586,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 if (mine && my_row == w) {
                     pos = my_rpos;
                     found = true;
+                }
+                if constexpr (MT::kOn) {
+                    mt.vec(pre + (found && pos > 0 ? pos - 1 : pos), found && pos > 0 ? 16u : 8u, found);
+                    if (d) mt.uni(pre + d - 1, 8);
                 }
                 if (found) qx = pre[pos] - (pos > 0 ? pre[pos - 1] : 0ull);
                 const uint64_t qrow = d ? pre[d - 1] : 0ull;
@@ -1444,16 +1612,21 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     }
                     const int L = (int)(key & 0xFF);
                     const uint32_t e = (uint32_t)(key >> 8);
+                    if (e > 0) mt.uni(pre + e - 1, 8);
                     const uint64_t before = e > 0 ? pre[e - 1] : 0ull;
                     if (before - shift > r) {
-                        ans = seg + wave_first_greater(pre + seg, e - seg, r + shift);
+                        ans = seg + wave_first_greater(pre + seg, e - seg, r + shift, mt);
                         break;
                     }
                     shift += readlane_u64(qx, L);
                     seg = e + 1;
                     left &= ~(1ull << L);
                 }
-                if (ans == ~0ull) ans = seg + wave_first_greater(pre + seg, d - seg, r + shift);
+                if (ans == ~0ull) ans = seg + wave_first_greater(pre + seg, d - seg, r + shift, mt);
+                if constexpr (MT::kOn) {
+                    mt.uni(list + ans, 4);
+                    mt.uni(pre + (ans > 0 ? ans - 1 : ans), ans > 0 ? 16u : 8u);
+                }
                 v = list[ans];
                 drawn_row = w;
                 drawn_pos = (uint32_t)ans;
@@ -1464,6 +1637,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 // materialising the set: probe each matched vertex in N(w)
                 // and skip the positions found.
                 const uint32_t w = readlane_u32(my_tau, __builtin_ctz(bm));
+                mt.uni(g.off + w, 16);
                 const uint64_t o = g.off[w];
                 const uint32_t d = (uint32_t)(g.off[w + 1] - o);
                 const uint32_t* list = g.nbr + o;
@@ -1473,7 +1647,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const bool need = mine && my_row != w;
                 if (__ballot(need)) {
                     bool f;
-                    const uint32_t pq = wave_lower_bound_keys(list, d, my_tau, need, i, f);
+                    const uint32_t pq = wave_lower_bound_keys(list, d, my_tau, need, i, f, mt);
                     if (need) {
                         pos = pq;
                         found = f;
@@ -1498,6 +1672,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         if (r + c == idx) break;
                         idx = r + c;
                     }
+                    mt.uni(list + idx, 4);
                     v = list[idx];
                     drawn_row = w;
                     drawn_pos = (uint32_t)idx;
@@ -1505,7 +1680,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 num = m;
                 den = 1;
             } else if (kPairs && count_only && t.pairs != 0 && __builtin_popcount(bm) == 2 &&
-                       pair_hub_count(t, my_tau, bm, i, num)) {
+                       pair_hub_count(t, my_tau, bm, i, num, mt)) {
                 // only the number of common neighbours of two pair hubs
                 // enters X: one table read, less the matched vertices in
                 // both lists
@@ -1517,7 +1692,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 den = 1;
             } else if (kPairs && !weighted && !count_only && P->reuse[i] == 0 && t.pairs != 0 &&
                        __builtin_popcount(bm) == 2 && (i + 1 == k || P->reuse[i + 1] == 0) &&
-                       pair_hub_count(t, my_tau, bm, i, num)) {
+                       pair_hub_count(t, my_tau, bm, i, num, mt)) {
                 // A uniform draw from the common neighbours of two pair hubs
                 // (a set no later step reuses): |S| from the table, then the
                 // drawn rank is found by walking from the nearer end.
@@ -1526,7 +1701,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     break;
                 }
                 const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, num);
-                v = pair_hub_select(g, t, my_tau, bm, i, r, num);
+                v = pair_hub_select(g, t, my_tau, bm, i, r, num, mt);
                 den = 1;
             } else {
                 // Candidate set I = intersection of the backward lists, S = I
@@ -1542,6 +1717,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint32_t lists = reuse ? (bm & ~P->bmask[i - 1]) : bm;
                 uint64_t my_o = 0;
                 uint32_t my_d = 0xFFFFFFFFu;
+                mt.vec(g.off + my_tau, 16, (uint32_t)lane < i && (lists >> lane & 1u));
                 if ((uint32_t)lane < i && (lists >> lane & 1u)) {
                     my_o = g.off[my_tau];
                     my_d = (uint32_t)(g.off[my_tau + 1] - my_o);
@@ -1571,6 +1747,22 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const AGIS_GMEM int32_t* sw = P->sw[i];
                 const uint32_t vprev = readlane_u32(my_tau, (int)i - 1);
                 int32_t lmax_l = kCertainZero;
+                if constexpr (MT::kOn) {
+                    const bool cand = weighted && reuse && (uint32_t)lane + 1 < i && !(bm >> lane & 1u);
+                    uint32_t offl = 0, loads = 0;
+                    bool in_all = true;
+                    if (cand) {
+                        for (uint32_t bits = bm; bits && in_all; bits &= bits - 1) {
+                            const uint32_t w = readlane_u32(my_tau, __builtin_ctz(bits));
+                            const uint64_t o = g.off[w];
+                            ++offl;
+                            in_all = contains_u32_counted(g.nbr + o, (uint32_t)(g.off[w + 1] - o), my_tau, loads);
+                        }
+                    }
+                    mt.lanes(offl, 16);
+                    mt.lanes(loads, 4);
+                    meter_step_log_weight(t, sw, lt, my_tau, b, f1, cand && in_all, mt);
+                }
                 if (weighted && reuse && (uint32_t)lane + 1 < i && !(bm >> lane & 1u)) {
                     // matched vertices were dropped from the reused set; the
                     // normalising maximum still covers those lying in I (a
@@ -1586,6 +1778,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 uint32_t my_pos = 0;  // lane j: window start in backward list j
                 // lane j: bitmap row of backward vertex j when it is a hub
                 int32_t my_slot = -1;
+                mt.vec(t.hub_slot + my_tau, 4,
+                       t.hub_slot && (uint32_t)lane < i && (others >> lane & 1u) &&
+                           (uint64_t)my_d * kWave >= (uint64_t)hub_window * db);
                 if (t.hub_slot && (uint32_t)lane < i && (others >> lane & 1u) &&
                     (uint64_t)my_d * kWave >= (uint64_t)hub_window * db)
                     my_slot = t.hub_slot[my_tau];
@@ -1605,6 +1800,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 // lands below the chunk being read, and the prefetched chunk
                 // lies above both.
                 constexpr uint32_t kNone = 0xFFFFFFFFu;
+                mt.vec(base + lane, 4, (uint32_t)lane < db);
                 uint32_t xa = (uint32_t)lane < db ? base[lane] : kNone, xb = kNone;
                 // (read unconditionally: every load issued so far is then
                 // known to have arrived before the loop)
@@ -1620,6 +1816,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     const bool valid = (uint32_t)lane < nvalid;
                     const uint32_t xlast = xlast_next;
                     const uint32_t nx = c + (uint32_t)kWave + (uint32_t)lane;
+                    mt.vec(base + nx, 4, nx < db);
                     x_next = nx < db ? base[nx] : kNone;
                     bool member = valid;
                     for (uint32_t bits = others; bits; bits &= bits - 1) {
@@ -1627,6 +1824,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         const int32_t slot = (int32_t)readlane_u32((uint32_t)my_slot, j);
                         if (slot >= 0) {
                             // a hub's list: one bit probe per element
+                            mt.vec(t.hub_bits + (uint64_t)slot * t.hub_words + (xv >> 5), 4, member);
                             if (member) {
                                 // xv passes through an empty asm statement, so
                                 // that the probe's address is not computed
@@ -1642,7 +1840,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         const uint32_t* lj = g.nbr + readlane_u64(my_o, j);
                         const uint32_t dj = readlane_u32(my_d, j);
                         const uint32_t pos = readlane_u32(my_pos, j);
-                        const uint32_t end = co_iterate_member(lj, pos, dj, xv, xlast, db - c, member);
+                        const uint32_t end = co_iterate_member(lj, pos, dj, xv, xlast, db - c, member, mt);
                         if (lane == j) my_pos = end;
                     }
                     {
@@ -1653,8 +1851,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     // the previous chunk's weights (kCertainZero is the
                     // identity of the maximum)
                     lmax_l = l_prev > lmax_l ? l_prev : lmax_l;
+                    mt.vec(sl + p_prev, 4, p_prev != kNone, true);
                     if (p_prev != kNone) sl[p_prev] = l_prev;
                     int32_t l = kCertainZero;
+                    meter_step_log_weight(t, sw, lt, xv, b, f1, weighted && member, mt);
                     if (weighted && member) l = step_log_weight(t, sw, lt, xv, b, f1, ie, f2);
                     bool in_tau = false;
                     if (reuse) {
@@ -1665,6 +1865,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     const bool keep = member && !in_tau;
                     const uint64_t km = __ballot(keep);
                     uint32_t p = kNone;
+                    mt.vec(sv + (uint32_t)cnt + (uint32_t)__popcll(km & lanemask_lt()), 4, keep && !count_only, true);
                     if (keep && !count_only) {
                         p = (uint32_t)cnt + (uint32_t)__popcll(km & lanemask_lt());
                         sv[p] = xv;
@@ -1683,6 +1884,8 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 // and the maximum is unchanged.
                 lmax_l = la > lmax_l ? la : lmax_l;
                 lmax_l = lb > lmax_l ? lb : lmax_l;
+                mt.vec(sl + pa, 4, pa != kNone, true);
+                mt.vec(sl + pb, 4, pb != kNone, true);
                 if (pa != kNone) sl[pa] = la;
                 if (pb != kNone) sl[pb] = lb;
                 scnt = cnt;
@@ -1693,6 +1896,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         break;
                     }
                     v = 0;
+                    if constexpr (MT::kOn) {
+                        if (!count_only) mt.uni(sv + bounded_draw(k0, k1, c0, c1, c2, i, cnt), 4);
+                    }
                     if (!count_only) v = sv[bounded_draw(k0, k1, c0, c1, c2, i, cnt)];
                     num = cnt;
                     den = 1;
@@ -1710,6 +1916,11 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     if (cnt <= (uint64_t)kWave * kPickBlock) {
                         const uint32_t B = (uint32_t)((cnt + kWave - 1) / kWave);
                         const uint32_t b0 = (uint32_t)lane * B;
+                        if constexpr (MT::kOn) {
+                            const uint32_t nb = b0 < (uint32_t)cnt ? ((uint32_t)cnt - b0 < B ? (uint32_t)cnt - b0 : B) : 0u;
+                            mt.vec(sl + b0, 4u * (nb ? nb : 1u), nb > 0);
+                            mt.vec(sv + b0, 4u * (nb ? nb : 1u), nb > 0);
+                        }
                         uint32_t wk[kPickBlock], vk[kPickBlock];
 #pragma unroll
                         for (int e = 0; e < kPickBlock; ++e) {
@@ -1759,6 +1970,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         num = Q;
                     } else {
                         uint64_t qs = 0;
+                        mt.span(sl, cnt * 4, 4 * kWave);
                         for (uint64_t c = (uint64_t)lane; c < cnt; c += kWave) {
                             const int32_t l = sl[c];
                             qs += l == kCertainZero ? 0u : weight_from_log(lmax, l, s_exp2tab);
@@ -1775,6 +1987,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         for (uint64_t c0i = 0; c0i < cnt; c0i += kWave) {
                             const uint64_t c = c0i + (uint64_t)lane;
                             uint32_t q = 0;
+                            mt.vec(sl + c, 4, c < cnt);
                             if (c < cnt) {
                                 const int32_t l = sl[c];
                                 q = l == kCertainZero ? 0u : weight_from_log(lmax, l, s_exp2tab);
@@ -1784,6 +1997,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                             if (run + tot > r) {
                                 const uint64_t hm = __ballot(run + incl > r);
                                 const int L = __ffsll((unsigned long long)hm) - 1;
+                                mt.uni(sv + c0i + (uint64_t)L, 4);
                                 v = sv[c0i + (uint64_t)L];
                                 den = readlane_u32(q, L);
                                 break;
@@ -1845,15 +2059,20 @@ __device__ __forceinline__ Partial chan_merge(Partial a, const Partial& b) {
 // at a time and stores each weight at its slot.  The next grab is requested
 // before the current one is processed, so the atomic's round trip overlaps
 // sampling work.  A sample's result does not depend on which wave runs it.
-// kDump: the record-writing variant (index lists and records), compiled
-// apart so the production kernel carries none of that state.  kWavesPerEU:
+// kMode: kRun (production), kDumpRecords (the record-writing variant:
+// index lists and records) or kMeterSamples (production paths, index lists,
+// and per sample the memory requests it made: read bytes, written bytes,
+// 64-byte segments, wave-level requests), compiled apart so the production
+// kernel carries none of that state.  kWavesPerEU:
 // register budget of the variant -- at least that many waves per SIMD must
 // fit (4 leaves the compiler its own choice, 80 registers and 6 waves here;
 // 7 and 8 trade spills for more resident waves); the autotuner picks the
 // fastest.
-template <bool kDump, int kWavesPerEU, bool kPairs>
+template <int kMode, int kWavesPerEU, bool kPairs>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU)))
 void k_sample(const LaunchDesc* __restrict__ D) {
+    constexpr bool kDump = kMode == kDumpRecords;
+    constexpr bool kIdx = kMode != kRun;
     const int lane = lane_id();
     for (uint32_t e = threadIdx.x; e < 4096u; e += blockDim.x) s_exp2tab[e] = c_exp2tab[e];
     __syncthreads();
@@ -1900,11 +2119,26 @@ void k_sample(const LaunchDesc* __restrict__ D) {
             while (sg + 1 < round->nseg && j >= round->seg[sg].base + round->seg[sg].count) ++sg;
             const Segment& S = round->seg[sg];
             const uint64_t off = j - S.base;
-            const uint64_t sidx = kDump ? D->idx[off] : S.start + off;
+            const uint64_t sidx = kIdx ? D->idx[off] : S.start + off;
             Record* rec = kDump ? D->dump + j : nullptr;
-            const double xv =
-                sample_one<kDump, kPairs>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv, sl, rec, hub_window);
-            if (lane == 0) xout[j] = xv;
+            if constexpr (kMode == kMeterSamples) {
+                Meter mt;
+                const double xv = sample_one<false, kPairs>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv,
+                                                            sl, rec, hub_window, mt);
+                mt.uni(xout + j, 8, true);
+                if (lane == 0) {
+                    xout[j] = xv;
+                    D->meter[4 * j + 0] = mt.rbytes;
+                    D->meter[4 * j + 1] = mt.wbytes;
+                    D->meter[4 * j + 2] = mt.segs;
+                    D->meter[4 * j + 3] = mt.reqs;
+                }
+            } else {
+                NoMeter mt;
+                const double xv = sample_one<kDump, kPairs>(g, t, D->plans + S.plan, round->k0, round->k1, sidx, sv,
+                                                            sl, rec, hub_window, mt);
+                if (lane == 0) xout[j] = xv;
+            }
         }
         cur = uniform_u64(next);
     }
@@ -1969,11 +2203,16 @@ __global__ void k_zero_queues(unsigned long long* p) {
 
 template <int kW, bool kPairs>
 const void* sample_kernel_of(bool dump) {
-    return dump ? reinterpret_cast<const void*>(k_sample<true, kW, kPairs>)
-                : reinterpret_cast<const void*>(k_sample<false, kW, kPairs>);
+    return dump ? reinterpret_cast<const void*>(k_sample<kDumpRecords, kW, kPairs>)
+                : reinterpret_cast<const void*>(k_sample<kRun, kW, kPairs>);
 }
 
-const void* sample_kernel(bool dump, int variant, bool pairs) {
+const void* sample_kernel(bool dump, int variant, bool pairs, bool meter) {
+    // the metering variant follows the production paths (one register
+    // budget: the paths do not depend on it)
+    if (meter)
+        return pairs ? reinterpret_cast<const void*>(k_sample<kMeterSamples, 6, true>)
+                     : reinterpret_cast<const void*>(k_sample<kMeterSamples, 6, false>);
     switch (variant) {
         case 1:
             return pairs ? sample_kernel_of<7, true>(dump) : sample_kernel_of<7, false>(dump);
@@ -1987,7 +2226,9 @@ const void* sample_kernel(bool dump, int variant, bool pairs) {
 int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, uint32_t max_segs, SampleLaunch* L,
                        std::string* err) {
     L->threads = 256;
-    L->cap = (uint64_t)g.max_deg + 1;
+    // capacity >= the largest degree, rounded up to 16 entries so that every
+    // wave's two scratch arrays start on a 64-byte boundary
+    L->cap = ((uint64_t)g.max_deg + 1 + 15) / 16 * 16;
     const uint64_t per_wave = L->cap * 2 * sizeof(uint32_t);
     // scratch budget: a quarter of the free device memory, within [8, 64] GiB
     // (a wave may need a whole maximum-degree list: at R-MAT scale 24 that is
@@ -2003,7 +2244,7 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
     int& cached = ctx->sample_blocks_per_cu[L->variant * 2 + (L->pairs ? 1 : 0)];
     if (cached == 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel(false, L->variant, L->pairs), L->threads,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel(false, L->variant, L->pairs, false), L->threads,
                                                          0) !=
                 hipSuccess ||
             nb < 1)
@@ -2067,8 +2308,9 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
 }
 
 void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const DevTables& t, const uint64_t* idx,
-                 Record* dump, LaunchDesc* D) {
+                 Record* dump, LaunchDesc* D, uint64_t* meter) {
     D->g = g;
+    D->meter = gmem(meter);
     D->t = t;
     D->plans = cmem((const DevPlan*)ctx->d_plans);
     D->idx = gmem(idx);
@@ -2090,8 +2332,8 @@ hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L
     if (before && (e = hipEventRecord(before, stream)) != hipSuccess) return e;
     const LaunchDesc* desc = ctx->d_launch;
     void* args[] = {(void*)&desc};
-    e = hipLaunchKernel(sample_kernel(L.dump, L.variant, L.pairs), dim3((unsigned)L.blocks), dim3((unsigned)L.threads), args, 0,
-                        stream);
+    e = hipLaunchKernel(sample_kernel(L.dump, L.variant, L.pairs, L.meter), dim3((unsigned)L.blocks),
+                        dim3((unsigned)L.threads), args, 0, stream);
     if (e != hipSuccess) return e;
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (after && (e = hipEventRecord(after, stream)) != hipSuccess) return e;

@@ -14,7 +14,7 @@ from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, ag
                agis_graph_export, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
                agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
                agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
-               agis_step_log_weights,
+               agis_step_log_weights, agis_meter_samples, agis_gather_bench,
                agis_tables_destroy, agis_tables_export, make_params, make_pattern, lib)
 
 
@@ -185,6 +185,29 @@ class Session:
         agis_dump_samples(self.ctx, graph.handle, tables.handle, p, seed, make_params(**kw), d_idx.data_ptr(), m,
                           d_out.data_ptr(), order=order)
         return d_out.cpu().numpy()[: m * RECORD_BYTES].view(RECORD_DTYPE).copy()
+
+    def meter(self, graph: Graph, tables: Tables, pattern, seed: int, indices, order=None, **kw) -> np.ndarray:
+        """Per sample (rows of the index list): read bytes, written bytes,
+        64-byte segments and wave-level requests of the production paths
+        (agis_meter_samples), as a uint64 array of shape (m, 4)."""
+        torch = _torch()
+        idx = np.ascontiguousarray(indices, dtype=np.uint64)
+        m = idx.size
+        d_idx = torch.from_numpy(idx.view(np.int64) if m else np.zeros(1, dtype=np.int64)).to(self.device)
+        d_out = torch.zeros(max(m, 1) * 4, dtype=torch.int64, device=self.device)
+        p = make_pattern(pattern.k, pattern.adj8())
+        agis_meter_samples(self.ctx, graph.handle, tables.handle, p, seed, make_params(**kw), d_idx.data_ptr(), m,
+                           d_out.data_ptr(), order=order)
+        return d_out.cpu().numpy()[: m * 4].view(np.uint64).reshape(m, 4).copy()
+
+    def gather_bench(self, buf, seg_bytes: int, dependent: bool, waves_per_cu: int = 28, rounds: int = 64,
+                     seed: int = 1):
+        """(seconds, useful bytes) of one random-gather run over the device
+        tensor buf (agis_gather_bench)."""
+        torch = _torch()
+        sink = torch.zeros(1024, dtype=torch.int64, device=self.device)
+        return agis_gather_bench(self.ctx, buf.data_ptr(), buf.numel() * buf.element_size(), seg_bytes, dependent,
+                                 waves_per_cu, rounds, seed, sink.data_ptr())
 
     # ---------------------------------------------------------------- learned proposal
 
