@@ -834,13 +834,18 @@ def main():
     # vertex records (the per-step tables are a few MB more)
     hot_bytes = 4 * g.nnz + 8 * (g.n + 1) + 16 * g.n
     footprint = "128MiB" if hot_bytes <= (256 << 20) else "8GiB"
+    gather_peak = None
     if not args.skip_gather:
         wpc = 4 * (6 + (tuning["variant"] if tuning else 0))
         log(f"random-gather ceiling at {wpc} waves per CU")
         gather = gather_ceiling(sess, wpc)
         s_match = min(GATHER_SIZES, key=lambda s: abs(math.log2(s) - math.log2(max(bytes_per_segment, 1.0))))
         ceiling = gather[footprint][s_match]["dependent_gbs"]
+        # request bytes over the ceiling of segments of the same mean size:
+        # above 1 where the sampler's requests hit in L2 (reuse within a
+        # sample), which the microbenchmark's random segments never do
         frac_gather = achieved / ceiling
+        gather_peak = max(max(r["dependent_gbs"], r["independent_gbs"]) for r in gather[footprint].values())
         for label, rows in gather.items():
             for S, row in rows.items():
                 log(f"  gather {label} {S:5d} B: dependent {row['dependent_gbs']:.0f} GB/s, independent "
@@ -857,14 +862,21 @@ def main():
         "gather_ceiling_segment_bytes": s_match,
         "gather_ceiling_footprint": footprint,
         "hot_bytes": hot_bytes,
-        "frac_of_gather_ceiling": frac_gather,
+        "requests_over_matched_gather_ceiling": frac_gather,
+        "gather_peak_gbs": gather_peak,
+        "traffic_frac": (hbm_total / kern_total / 1e9) / HBM_PEAK_GBS if counters else None,
+        "traffic_frac_of_gather_peak": ((hbm_total / kern_total / 1e9) / gather_peak
+                                        if counters and gather_peak else None),
         "merge_model_gbs": merge_total / kern_total / 1e9,
         "traffic_gbs": hbm_total / kern_total / 1e9 if counters else None,
         "traffic_source": os.path.relpath(COUNTERS_FILE, ROOT) if counters else None,
     }
     log(f"roofline: {achieved:.0f} GB/s of request bytes ({roofline['frac']:.3f} of HBM peak"
-        + (f", {frac_gather:.2f} of the {s_match}-B dependent-gather ceiling over {footprint}"
-           if frac_gather else "") + ")")
+        + (f"; {frac_gather:.2f}x the {s_match}-B dependent-gather ceiling over {footprint}"
+           if frac_gather else "") + ")"
+        + (f"; HBM traffic {roofline['traffic_gbs']:.0f} GB/s ({roofline['traffic_frac']:.3f} of peak"
+           + (f", {roofline['traffic_frac_of_gather_peak']:.3f} of the best gather rate" if gather_peak else "")
+           + ")" if counters else "; no counters for these kernel sources"))
 
     detail = {"per_pattern": per_pattern, "meter": meter, "roofline": roofline, "gather": gather, "tuning": tuning,
               "dag": dag}
@@ -942,10 +954,9 @@ def main():
         "estimates": {k: {"estimate": v["estimate"], "rel_err_vs_exact": v.get("rel_err_vs_exact")}
                       for k, v in per_pattern.items()},
         "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
-                                              "avg_launch_ms", "gather_ceiling_gbs", "gather_ceiling_segment_bytes",
-                                              "gather_ceiling_footprint", "frac_of_gather_ceiling",
-                                              "merge_model_gbs", "traffic_gbs",
-                                              "traffic_source")},
+                                              "avg_launch_ms", "traffic_gbs", "traffic_frac", "gather_peak_gbs",
+                                              "traffic_frac_of_gather_peak", "gather_ceiling_footprint",
+                                              "merge_model_gbs", "traffic_source")},
     }
     if eps_table:
         out["time_to_1pct_s"] = {
