@@ -278,6 +278,25 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
                   const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
                   agis_result* out);
 
+/* agis_estimate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the same
+ * arguments, samples and result -- estimates equal agis_estimate's to
+ * relative 1e-9 -- but no hipMalloc, hipFree or allocating library routine is
+ * called.  Every buffer (first-step table, per-step weight tables, round
+ * weights and partials, the waves' scratch) is carved from a fixed device
+ * workspace of 256 MiB that the library holds on each GPU it runs on until
+ * the process ends.  Per-row pick tables are not built (flags are treated as
+ * AGIS_RUN_ROWTAB_OFF: the same samples), step weight tables that do not fit
+ * fall back to the vertex records, and the grid shrinks to the waves whose
+ * scratch (2 x (max degree + 1) x 4 bytes each) fits.  A graph whose
+ * first-step table (12 bytes per vertex) or one workgroup's scratch does not
+ * fit returns AGIS_E_UNSUPPORTED with the reason.  Calls that overlap on one
+ * GPU share the workspace and race: serialise them.  Rounds are launched
+ * directly (no graph replay). */
+int agis_estimate_noalloc(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                          const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
+                          agis_result* out);
+
 /* Estimates C(G, P) for n_patterns (1..64) patterns at once, the way the
  * paper runs independent samplers in parallel (Sec. 5.4), with uneven
  * sample budgets: budgets[i] host uint64 per pattern.  Each round is one

@@ -131,6 +131,9 @@ _SIGNATURES = [
                                             ctypes.POINTER(agis_plan)]),
     ("agis_estimate", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
                                      ctypes.c_uint64, ctypes.POINTER(agis_run_params), ctypes.POINTER(agis_result)]),
+    ("agis_estimate_noalloc", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
+                                             ctypes.c_uint64, ctypes.POINTER(agis_run_params),
+                                             ctypes.POINTER(agis_result)]),
     ("agis_dump_samples", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
                                          ctypes.POINTER(agis_run_params), _P, ctypes.c_uint64, _P]),
     ("agis_meter_samples", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(agis_pattern), _P, ctypes.c_uint64,
@@ -305,6 +308,19 @@ def agis_estimate(ctx, g, t, pattern: agis_pattern, n_samples: int, seed: int, p
     keep, ptr = _order_arg(order)
     out.status = _check(ctx, lib().agis_estimate(ctx, g, t, ctypes.byref(pattern), ptr, n_samples, seed,
                                                  ctypes.byref(params), ctypes.byref(out)),
+                        allow=(AGIS_E_NOT_CONVERGED, AGIS_E_CANCELLED))
+    del keep
+    return out
+
+
+def agis_estimate_noalloc(ctx, g, t, pattern: agis_pattern, n_samples: int, seed: int, params: agis_run_params,
+                          order=None) -> agis_result:
+    """agis_estimate without device allocation (the library's fixed
+    workspace); the result carries .status as agis_estimate's does."""
+    out = agis_result()
+    keep, ptr = _order_arg(order)
+    out.status = _check(ctx, lib().agis_estimate_noalloc(ctx, g, t, ctypes.byref(pattern), ptr, n_samples, seed,
+                                                         ctypes.byref(params), ctypes.byref(out)),
                         allow=(AGIS_E_NOT_CONVERGED, AGIS_E_CANCELLED))
     del keep
     return out

@@ -43,6 +43,8 @@ struct agis_ctx {
     hipEvent_t ev_out = nullptr;
     hipEvent_t ev_start = nullptr;  // brackets each sampling launch
     hipEvent_t ev_stop = nullptr;
+    // device address of this device's fixed workspace (agis_estimate_noalloc)
+    void* noalloc_scratch = nullptr;
 };
 
 struct agis_graph {
@@ -135,10 +137,33 @@ hipError_t launch_step_log_weights(const agis_tables& t, uint64_t n, uint32_t b,
 hipError_t launch_export_tables(const agis_tables& t, uint64_t n, uint32_t* deg, int32_t* la, int32_t* lc,
                                 hipStream_t stream);
 
+// A bump allocator over a fixed device buffer, for calls that allocate
+// nothing: take() returns the next `bytes` (aligned to 256) or nullptr when
+// they do not fit.
+struct Arena {
+    char* base = nullptr;
+    uint64_t cap = 0;
+    uint64_t used = 0;
+    void* take(uint64_t bytes) {
+        const uint64_t at = (used + 255) / 256 * 256;
+        if (at > cap || bytes > cap - at) return nullptr;
+        used = at + bytes;
+        return base + at;
+    }
+    uint64_t left() const {
+        const uint64_t at = (used + 255) / 256 * 256;
+        return at < cap ? cap - at : 0;
+    }
+};
+
+// Tile sums of the first-step scan (one per kScanTile vertices).
+uint64_t step1_scan_tiles(uint64_t n);
+
 // First-step table for step 0 of the plan `hp`: q1, inclusive prefix pre,
-// total copied into *total (synchronises the stream).
+// total copied into *total (synchronises the stream).  blocksums: device
+// uint64[step1_scan_tiles(n)] of scratch, or nullptr for the context's own.
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
-                       uint32_t* q1, uint64_t* pre, uint64_t* total);
+                       uint32_t* q1, uint64_t* pre, uint64_t* total, uint64_t* blocksums = nullptr);
 
 // Guide of an inclusive prefix pre[0..n) with total = pre[n - 1] > 0:
 // guide[b] = first v with pre[v] > b << shift for b < buckets =
@@ -169,6 +194,11 @@ struct SampleLaunch {
     // plan_sample_launch: some plan has an unweighted step over exactly two
     // backward lists and the tables hold the pair-hub table)
     bool pairs = false;
+    // buffers of the launch (set by plan_sample_launch): the waves' scratch,
+    // the per-slot weights and the reduction tiles
+    void* scratch = nullptr;
+    double* xout = nullptr;
+    Partial* partials = nullptr;
 };
 
 // The sampling kernel for (record-writing?, register-budget variant 0..2,
@@ -176,9 +206,12 @@ struct SampleLaunch {
 const void* sample_kernel(bool dump, int variant, bool pairs, bool meter);
 
 // Sizes the persistent grid (resident waves only) and the buffers for
-// rounds of at most max_slots samples over at most max_segs segments.
+// rounds of at most max_slots samples over at most max_segs segments.  With
+// an arena the buffers are taken from it (no allocation; the grid shrinks to
+// the waves whose scratch fits, AGIS_E_UNSUPPORTED below one workgroup),
+// else they are the context's, grown as needed.
 int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, uint32_t max_segs, SampleLaunch* L,
-                       std::string* err);
+                       std::string* err, Arena* arena = nullptr);
 
 // One round as described by ctx->d_launch (plans in ctx->d_plans): clears
 // the work queue (a kernel, so the sequence can be captured in a graph),

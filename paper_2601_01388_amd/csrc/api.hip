@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,7 +16,35 @@
 using agis::DevPlan;
 using agis::Partial;
 
+// Fixed device workspace of agis_estimate_noalloc (for callers that cannot
+// allocate): every buffer of such a call is carved from it.  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// the name is not a device address: its address on a device comes from
+// hipGetSymbolAddress (kept per device in noalloc_scratch_ptr below).
+constexpr uint64_t kNoAllocBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// The device address of this device's fixed workspace, looked up once per
+// device with that device current.
+hipError_t noalloc_scratch_ptr(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_noalloc_ptr[device] = p;
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
+}
 
 int fail(agis_ctx* ctx, int code, const std::string& msg) {
     if (ctx) ctx->err = msg;
@@ -96,7 +125,9 @@ struct Prepared {
     uint64_t* pre = nullptr;
     uint32_t* guide = nullptr;
     double tables_seconds = 0;
+    bool owns = true;  // false: the buffers are carved from a fixed workspace
     ~Prepared() {
+        if (!owns) return;
         if (q1) (void)hipFree(q1);
         if (pre) (void)hipFree(pre);
         if (guide) (void)hipFree(guide);
@@ -123,10 +154,12 @@ struct StepTables {
     std::vector<Entry> e;
     std::vector<RowEntry> rows;
     uint32_t* long_rows = nullptr;  // scratch of the row-table build (lists of longer rows)
+    agis::Arena* arena = nullptr;   // non-null: buffers are carved from it, never allocated or freed
     StepTables() = default;
     StepTables(const StepTables&) = delete;
     StepTables& operator=(const StepTables&) = delete;
     ~StepTables() {
+        if (arena) return;
         for (Entry& x : e) (void)hipFree(x.buf);
         for (RowEntry& x : rows) (void)hipFree(x.buf);
         if (long_rows) (void)hipFree(long_rows);
@@ -319,7 +352,14 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
                 return e.buf;
         if ((st->e.size() + 1) * g->g.n * sizeof(int32_t) > kStepTableBudgetBytes) return nullptr;
         int32_t* buf = nullptr;
-        hipError_t e = hipMalloc(&buf, g->g.n * sizeof(int32_t));
+        hipError_t e = hipSuccess;
+        if (st->arena) {
+            // no room left in the fixed workspace: the weights come from the records
+            buf = (int32_t*)st->arena->take(g->g.n * sizeof(int32_t));
+            if (!buf) return nullptr;
+        } else {
+            e = hipMalloc(&buf, g->g.n * sizeof(int32_t));
+        }
         if (e == hipSuccess) {
             st->e.push_back(StepTables::Entry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
             e = agis::launch_step_log_weights(*t, g->g.n, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
@@ -333,8 +373,9 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         return buf;
     };
     // per-row pick tables for weighted steps with one backward vertex
-    bool want_rows = params->flags == AGIS_RUN_ROWTAB_ON ||
-                     (params->flags == AGIS_RUN_ROWTAB_AUTO && n_samples >= kRowtabMinSamples);
+    // (never with a fixed workspace: a row table takes 8 bytes per CSR slot)
+    bool want_rows = !st->arena && (params->flags == AGIS_RUN_ROWTAB_ON ||
+                                    (params->flags == AGIS_RUN_ROWTAB_AUTO && n_samples >= kRowtabMinSamples));
     if (want_rows && g->g.nnz > 0) {
         for (uint32_t i = 1; i < hp.k; ++i) {
             if (!hp.weighted[i] || __builtin_popcount(hp.bmask[i]) != 1) continue;
@@ -373,17 +414,29 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         if (buf) hp.sw[i] = agis::gmem(buf);
     }
     if (hp.weighted[0] && g->g.n > 0) {
-        AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");
-        AGIS_HIP(ctx, hipMalloc(&out->pre, g->g.n * sizeof(uint64_t)), "allocate first-step prefix");
+        uint64_t* blocksums = nullptr;
+        if (st->arena) {
+            out->owns = false;
+            out->q1 = (uint32_t*)st->arena->take(g->g.n * sizeof(uint32_t));
+            out->pre = (uint64_t*)st->arena->take(g->g.n * sizeof(uint64_t));
+            out->guide = (uint32_t*)st->arena->take(((1ull << agis::kGuideBits) + 1) * sizeof(uint32_t));
+            blocksums = (uint64_t*)st->arena->take(agis::step1_scan_tiles(g->g.n) * sizeof(uint64_t));
+            if (!out->q1 || !out->pre || !out->guide || !blocksums)
+                return fail(ctx, AGIS_E_UNSUPPORTED, "the first-step table does not fit in the fixed workspace");
+        } else {
+            AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");
+            AGIS_HIP(ctx, hipMalloc(&out->pre, g->g.n * sizeof(uint64_t)), "allocate first-step prefix");
+        }
         uint64_t total = 0;
-        AGIS_HIP(ctx, agis::build_step1(ctx, *g, *t, hp, out->q1, out->pre, &total), "first-step table");
+        AGIS_HIP(ctx, agis::build_step1(ctx, *g, *t, hp, out->q1, out->pre, &total, blocksums), "first-step table");
         hp.s1_q = agis::gmem((const uint32_t*)out->q1);
         hp.s1_pre = agis::gmem((const uint64_t*)out->pre);
         hp.s1_total = total;
         if (total > 0) {
             const uint32_t shift = agis::guide_shift(total);
             const uint64_t buckets = ((total - 1) >> shift) + 1;
-            AGIS_HIP(ctx, hipMalloc(&out->guide, (buckets + 1) * sizeof(uint32_t)), "allocate first-step guide");
+            if (!st->arena)
+                AGIS_HIP(ctx, hipMalloc(&out->guide, (buckets + 1) * sizeof(uint32_t)), "allocate first-step guide");
             AGIS_HIP(ctx, agis::launch_prefix_guide(out->pre, g->g.n, total, shift, out->guide, ctx->stream),
                      "first-step guide");
             hp.s1_guide = agis::gmem((const uint32_t*)out->guide);
@@ -419,10 +472,12 @@ bool uses_pair_hubs(const DevPlan& hp, const agis_tables* t) {
 
 // Rounds of at most this many samples bound the weight buffer (8 B each).
 constexpr uint64_t kMaxRoundSlots = 1ull << 24;
+constexpr uint64_t kFixedRoundSlots = 1ull << 20;
+static_assert(kFixedRoundSlots % agis::kReduceTileSamples == 0, "round size");
 
 int replay_or_launch(agis_ctx* ctx, const agis::SampleLaunch& L, const agis_graph* g, const agis_tables* t,
-                     float* ms) {
-    if (!ctx->use_graphs) {
+                     float* ms, bool direct) {
+    if (!ctx->use_graphs || direct) {
         AGIS_HIP(ctx, agis::launch_round(ctx, ctx->stream, L, ctx->ev_start, ctx->ev_stop), "launch round");
         AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "round");
         AGIS_HIP(ctx, hipEventElapsedTime(ms, ctx->ev_start, ctx->ev_stop), "event time");
@@ -431,7 +486,7 @@ int replay_or_launch(agis_ctx* ctx, const agis::SampleLaunch& L, const agis_grap
     // kernel arguments and grids of the captured sequence: the descriptor's
     // contents may change between replays, its address and the grids not
     const uint64_t key[8] = {(uint64_t)(uintptr_t)ctx->d_launch, (uint64_t)L.blocks, (uint64_t)L.threads,
-                             L.max_tiles, (uint64_t)(uintptr_t)ctx->d_partials, (uint64_t)(uintptr_t)ctx->d_small,
+                             L.max_tiles, (uint64_t)(uintptr_t)L.partials, (uint64_t)(uintptr_t)ctx->d_small,
                              (uint64_t)L.variant, (uint64_t)L.pairs};
     if (!ctx->graph_exec || std::memcmp(key, ctx->graph_key, sizeof(key)) != 0) {
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -468,7 +523,7 @@ int replay_or_launch(agis_ctx* ctx, const agis::SampleLaunch& L, const agis_grap
 // use indices 0, 1, 2, ... in order, so the stopping point of each pattern
 // depends only on its own samples.
 int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::vector<PatternRun>& runs,
-               const agis_run_params* pp, uint64_t seed, bool* cancelled) {
+               const agis_run_params* pp, uint64_t seed, bool* cancelled, agis::Arena* arena = nullptr) {
     *cancelled = false;
     const bool to_eps = pp->eps > 0;
     const uint64_t check = pp->check_every ? pp->check_every : 65536;
@@ -483,11 +538,14 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
         total_budget += r.budget;
         max_slots += to_eps ? std::min(check, r.budget) : r.budget;
     }
-    max_slots = std::min(max_slots, kMaxRoundSlots);
+    // rounds within a fixed workspace hold at most kFixedRoundSlots slots (a
+    // multiple of the reduction tile, so the tiles and hence the estimate are
+    // the same as with larger rounds)
+    max_slots = std::min(max_slots, arena ? kFixedRoundSlots : kMaxRoundSlots);
     if (max_slots == 0) return AGIS_OK;
     agis::SampleLaunch L;
     for (const PatternRun& r : runs) L.pairs = L.pairs || uses_pair_hubs(r.prep.hp, t);
-    int rc = agis::plan_sample_launch(ctx, *g, max_slots, npat, &L, &ctx->err);
+    int rc = agis::plan_sample_launch(ctx, *g, max_slots, npat, &L, &ctx->err, arena);
     if (rc != AGIS_OK) return rc;
     agis::LaunchDesc ld;
     std::memset(&ld, 0, sizeof(ld));
@@ -537,11 +595,11 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
         AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_launch, &ld, sizeof(ld), hipMemcpyHostToDevice, ctx->stream),
                  "upload round");
         float ms = 0.0f;
-        rc = replay_or_launch(ctx, L, g, t, &ms);
+        rc = replay_or_launch(ctx, L, g, t, &ms, arena != nullptr);
         if (rc != AGIS_OK) return rc;
         parts.resize((size_t)tiles);
         AGIS_HIP(ctx,
-                 hipMemcpyAsync(parts.data(), ctx->d_partials, tiles * sizeof(Partial), hipMemcpyDeviceToHost,
+                 hipMemcpyAsync(parts.data(), L.partials, tiles * sizeof(Partial), hipMemcpyDeviceToHost,
                                 ctx->stream),
                  "read partials");
         AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "read partials");
@@ -609,6 +667,15 @@ int agis_create(agis_ctx** out, int device, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc(&ctx->d_plans, agis::kMaxSegs * sizeof(DevPlan));
     if (e == hipSuccess) e = hipMalloc(&ctx->d_launch, sizeof(agis::LaunchDesc));
     if (e == hipSuccess) e = hipMalloc(&ctx->d_small, 4096);
+    if (e == hipSuccess) {
+        // the fixed workspace of agis_estimate_noalloc; a failed lookup only
+        // disables that entry point (it reports the failure)
+        void* p = nullptr;
+        if (noalloc_scratch_ptr(device, &p) == hipSuccess)
+            ctx->noalloc_scratch = p;
+        else
+            (void)hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming);
@@ -867,6 +934,40 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool cancelled = false;
     rc = run_rounds(ctx, g, t, runs, pp, seed, &cancelled);
+    if (rc != AGIS_OK) return rc;
+    const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
+    fill_result(runs[0], z, setup, out);
+    if (cancelled) return fail(ctx, AGIS_E_CANCELLED, "cancelled by the caller");
+    if (pp->eps > 0 && !runs[0].converged) return fail(ctx, AGIS_E_NOT_CONVERGED, "sample budget reached before eps");
+    return AGIS_OK;
+}
+
+int agis_estimate_noalloc(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p,
+                          const uint8_t* order, uint64_t n_samples, uint64_t seed, const agis_run_params* params,
+                          agis_result* out) {
+    int rc = check_handles(ctx, g, t);
+    if (rc != AGIS_OK) return ctx ? fail(ctx, rc, "bad handle") : rc;
+    if (!p || !out) return fail(ctx, AGIS_E_INVALID_ARG, "null pattern or result");
+    const agis_run_params dp = default_params();
+    const agis_run_params* pp = params ? params : &dp;
+    if (pp->eps > 0 && !(pp->delta > 0 && pp->delta < 1)) return fail(ctx, AGIS_E_INVALID_ARG, "delta must be in (0, 1)");
+    if (!ctx->noalloc_scratch) return fail(ctx, AGIS_E_HIP, "the fixed workspace has no device address");
+    AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
+    const auto t0 = std::chrono::steady_clock::now();
+    // every buffer of this call comes from this device's fixed workspace;
+    // calls on one device share it (overlapping calls race)
+    agis::Arena arena;
+    arena.base = (char*)ctx->noalloc_scratch;
+    arena.cap = kNoAllocBytes;
+    StepTables st;
+    st.arena = &arena;
+    std::vector<PatternRun> runs(1);
+    rc = prepare(ctx, g, t, p, order, pp, n_samples, &st, &runs[0].prep);
+    if (rc != AGIS_OK) return rc;
+    runs[0].budget = n_samples;
+    const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool cancelled = false;
+    rc = run_rounds(ctx, g, t, runs, pp, seed, &cancelled, &arena);
     if (rc != AGIS_OK) return rc;
     const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
     fill_result(runs[0], z, setup, out);

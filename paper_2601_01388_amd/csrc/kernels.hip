@@ -1066,28 +1066,33 @@ hipError_t launch_orient_fill(const DevGraph& g, const uint64_t* off_out, uint32
     return hipGetLastError();
 }
 
+uint64_t step1_scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp, uint32_t* q1,
-                       uint64_t* pre, uint64_t* total) {
+                       uint64_t* pre, uint64_t* total, uint64_t* blocksums) {
     const uint64_t n = g.g.n;
     hipStream_t st = ctx->stream;
     int32_t* d_lmax = (int32_t*)ctx->d_small;
     const int32_t init = kCertainZero;
     hipError_t e = hipMemcpyAsync(d_lmax, &init, sizeof(init), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
-    if (ctx->blocksums_cap < ntiles) {
-        if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
-        ctx->d_blocksums = nullptr;
-        e = hipMalloc(&ctx->d_blocksums, ntiles * sizeof(uint64_t));
-        if (e != hipSuccess) return e;
-        ctx->blocksums_cap = ntiles;
+    const uint64_t ntiles = step1_scan_tiles(n);
+    if (!blocksums) {
+        if (ctx->blocksums_cap < ntiles) {
+            if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
+            ctx->d_blocksums = nullptr;
+            e = hipMalloc(&ctx->d_blocksums, ntiles * sizeof(uint64_t));
+            if (e != hipSuccess) return e;
+            ctx->blocksums_cap = ntiles;
+        }
+        blocksums = ctx->d_blocksums;
     }
     hipLaunchKernelGGL(k_step1_max, dim3(grid_for(n, 256)), dim3(256), 0, st, t.rec, hp, n, d_lmax);
     hipLaunchKernelGGL(k_step1_tilesum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, t.rec, hp, n, d_lmax,
-                       ctx->d_blocksums);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, ctx->d_blocksums, ntiles);
+                       blocksums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, blocksums, ntiles);
     hipLaunchKernelGGL(k_step1_final, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, t.rec, hp, n, d_lmax,
-                       ctx->d_blocksums, q1, pre);
+                       blocksums, q1, pre);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(total, pre + (n - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, st);
@@ -2224,7 +2229,7 @@ const void* sample_kernel(bool dump, int variant, bool pairs, bool meter) {
 }
 
 int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, uint32_t max_segs, SampleLaunch* L,
-                       std::string* err) {
+                       std::string* err, Arena* arena) {
     L->threads = 256;
     // capacity >= the largest degree, rounded up to 16 entries so that every
     // wave's two scratch arrays start on a 64-byte boundary
@@ -2257,9 +2262,21 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
     if (ctx->tune_blocks_per_cu > 0 && (uint64_t)ctx->tune_blocks_per_cu < blocks_per_cu)
         blocks_per_cu = (uint64_t)ctx->tune_blocks_per_cu;
     uint64_t waves = (uint64_t)ctx->num_cus * blocks_per_cu * 4;
-    if (waves * per_wave > budget) waves = budget / per_wave;
+    L->max_tiles = (max_slots + kReduceTile - 1) / kReduceTile + max_segs;
+    if (arena) {
+        // the round buffers first, then as many waves as the rest holds
+        L->xout = (double*)arena->take(max_slots * sizeof(double));
+        L->partials = (Partial*)arena->take((uint64_t)L->max_tiles * sizeof(Partial));
+        if (!L->xout || !L->partials) {
+            *err = "the fixed workspace cannot hold the round buffers";
+            return AGIS_E_UNSUPPORTED;
+        }
+        budget = arena->left() > 256 ? arena->left() - 256 : 0;
+    }
+    if (waves * per_wave > budget) waves = budget / per_wave / 4 * 4;
     if (waves < 4) {
-        *err = "maximum degree too large for the sampler scratch budget";
+        *err = arena ? "maximum degree too large for the fixed workspace (one workgroup's scratch does not fit)"
+                     : "maximum degree too large for the sampler scratch budget";
         return AGIS_E_UNSUPPORTED;
     }
     const uint64_t need = (max_slots + 3) / 4 * 4;
@@ -2272,6 +2289,15 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
         L->grab = (uint32_t)(per < 1 ? 1 : (per > 8 ? 8 : per));
     }
     const uint64_t bytes = (uint64_t)L->blocks * 4 * per_wave;
+    if (arena) {
+        L->scratch = arena->take(bytes);
+        if (!L->scratch) {
+            *err = "the fixed workspace cannot hold the sampler scratch";
+            return AGIS_E_UNSUPPORTED;
+        }
+        L->max_slots = max_slots;
+        return AGIS_OK;
+    }
     if (ctx->scratch_bytes < bytes) {
         if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
         ctx->d_scratch = nullptr;
@@ -2282,7 +2308,6 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
         }
         ctx->scratch_bytes = bytes;
     }
-    L->max_tiles = (max_slots + kReduceTile - 1) / kReduceTile + max_segs;
     if (ctx->partials_cap < (size_t)L->max_tiles) {
         if (ctx->d_partials) (void)hipFree(ctx->d_partials);
         ctx->d_partials = nullptr;
@@ -2303,6 +2328,9 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
         }
         ctx->xout_cap = max_slots;
     }
+    L->scratch = ctx->d_scratch;
+    L->partials = ctx->d_partials;
+    L->xout = ctx->d_xout;
     L->max_slots = max_slots;
     return AGIS_OK;
 }
@@ -2315,10 +2343,10 @@ void fill_launch(agis_ctx* ctx, const SampleLaunch& L, const DevGraph& g, const 
     D->plans = cmem((const DevPlan*)ctx->d_plans);
     D->idx = gmem(idx);
     D->dump = gmem(dump);
-    D->scratch = gmem((uint32_t*)ctx->d_scratch);
+    D->scratch = gmem((uint32_t*)L.scratch);
     D->cap = L.cap;
     D->queue = gmem((unsigned long long*)((char*)ctx->d_small + kQueueOffset));
-    D->xout = gmem(ctx->d_xout);
+    D->xout = gmem(L.xout);
     D->grab = L.grab;
     D->hub_window = L.hub_window;
 }
@@ -2338,7 +2366,7 @@ hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (after && (e = hipEventRecord(after, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_x, dim3((unsigned)L.max_tiles), dim3(kReduceThreads), 0, stream, ctx->d_launch,
-                       ctx->d_partials);
+                       L.partials);
     return hipGetLastError();
 }
 
