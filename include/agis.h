@@ -112,7 +112,13 @@ typedef struct {
  * flags: AGIS_RUN_ROWTAB_* -- whether a weighted step with a single matched
  *   neighbour draws through per-row pick tables built for this estimate
  *   (same samples either way; AUTO builds them for runs of >= 65536
- *   samples when they fit in memory).
+ *   samples when they fit in memory).  Also in flags: how a weighted first
+ *   step's distribution over all vertices is held -- AGIS_RUN_STEP1_FULL
+ *   (the integer weight and inclusive prefix of every vertex, 12 bytes per
+ *   vertex) or AGIS_RUN_STEP1_BLOCKS (the prefix over blocks of 256
+ *   vertices, 8 bytes per block; a draw recomputes its block's weights from
+ *   the vertex records); neither = full up to 2 GiB, blocked beyond.  The
+ *   samples are the same either way.
  * terms: which factors of f_approx (Eq. probability_function) enter the
  *   weights -- AGIS_TERMS_ALL (T[F1] T[I1] T[F2], the method), or the
  *   incremental versions of the paper's analysis of the approximation
@@ -137,6 +143,8 @@ typedef struct {
 #define AGIS_RUN_ROWTAB_AUTO 0u
 #define AGIS_RUN_ROWTAB_ON 1u
 #define AGIS_RUN_ROWTAB_OFF 2u
+#define AGIS_RUN_STEP1_BLOCKS 4u
+#define AGIS_RUN_STEP1_FULL 8u
 #define AGIS_TERMS_ALL 0u
 #define AGIS_TERMS_F1 1u
 #define AGIS_TERMS_F1_I1 2u

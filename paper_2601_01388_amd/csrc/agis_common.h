@@ -189,8 +189,16 @@ struct DevPlan {
     // and the next
     AGIS_GMEM const uint32_t* s1_guide;
     uint32_t s1_shift;
-    uint32_t s1_pad;
+    // blocked first-step table (instead of s1_q and s1_pre): s1_blk[b] is
+    // the inclusive prefix of the weights over blocks of kStep1Block
+    // vertices (s1_blk[-1] is 0 and readable), the block's weights are
+    // recomputed from the vertex records against the largest log weight
+    // s1_lmax, and the guide indexes blocks
+    int32_t s1_lmax;
+    AGIS_GMEM const uint64_t* s1_blk;
 };
+
+constexpr uint32_t kStep1Block = 256;
 
 // One launch ("round") of the sampler covers up to kMaxSegs segments: the
 // slots [base, base + count) run samples start .. start + count - 1 of

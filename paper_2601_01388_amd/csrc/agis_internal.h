@@ -165,6 +165,14 @@ uint64_t step1_scan_tiles(uint64_t n);
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
                        uint32_t* q1, uint64_t* pre, uint64_t* total, uint64_t* blocksums = nullptr);
 
+// Blocked first-step table for step 0 of `hp`: blk (device uint64[nblk + 1],
+// nblk = ceil(n / kStep1Block)) receives 0 and then the inclusive prefix of
+// the blocks' weight sums (so blk + 1 is the table and blk[0] its "before
+// block 0"); *lmax_out the largest log weight, *total the sum (synchronises
+// the stream).
+hipError_t build_step1_blocks(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
+                              uint64_t* blk, int32_t* lmax_out, uint64_t* total);
+
 // Guide of an inclusive prefix pre[0..n) with total = pre[n - 1] > 0:
 // guide[b] = first v with pre[v] > b << shift for b < buckets =
 // ((total - 1) >> shift) + 1 <= 2^kGuideBits, guide[buckets] = n - 1.

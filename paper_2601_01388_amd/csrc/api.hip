@@ -171,6 +171,9 @@ constexpr uint64_t kStepTableBudgetBytes = 16ull << 30;
 // (AUTO): their build streams every CSR slot once, which a short run does
 // not amortise.
 constexpr uint64_t kRowtabMinSamples = 65536;
+// First-step tables above this size (12 bytes per vertex) are built blocked
+// unless the run asks for the full table.
+constexpr uint64_t kStep1FullBudget = 2ull << 30;
 constexpr uint64_t kRowtabBudgetBytes = 48ull << 30;
 
 // Neighbourhood bitmaps of the highest-degree vertices (degree >= 64, as
@@ -322,7 +325,11 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
                 return fail(ctx, AGIS_E_UNSUPPORTED, "an oriented graph samples clique patterns only");
         for (uint32_t j = 2; j <= p->k; ++j) out->scale *= (double)j;
     }
-    if (params->flags > AGIS_RUN_ROWTAB_OFF) return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
+    const uint32_t rowtab = params->flags & 3u;
+    const uint32_t step1 = params->flags & (AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL);
+    if (rowtab > AGIS_RUN_ROWTAB_OFF || (params->flags & ~(3u | AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL)) ||
+        step1 == (AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL))
+        return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
     if (params->terms > AGIS_TERMS_F1_I1) return fail(ctx, AGIS_E_INVALID_ARG, "unknown term set");
     DevPlan& hp = out->hp;
     std::memset(&hp, 0, sizeof(hp));
@@ -374,8 +381,8 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     };
     // per-row pick tables for weighted steps with one backward vertex
     // (never with a fixed workspace: a row table takes 8 bytes per CSR slot)
-    bool want_rows = !st->arena && (params->flags == AGIS_RUN_ROWTAB_ON ||
-                                    (params->flags == AGIS_RUN_ROWTAB_AUTO && n_samples >= kRowtabMinSamples));
+    bool want_rows = !st->arena && (rowtab == AGIS_RUN_ROWTAB_ON ||
+                                    (rowtab == AGIS_RUN_ROWTAB_AUTO && n_samples >= kRowtabMinSamples));
     if (want_rows && g->g.nnz > 0) {
         for (uint32_t i = 1; i < hp.k; ++i) {
             if (!hp.weighted[i] || __builtin_popcount(hp.bmask[i]) != 1) continue;
@@ -413,7 +420,42 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         if (step_rc != AGIS_OK) return step_rc;
         if (buf) hp.sw[i] = agis::gmem(buf);
     }
-    if (hp.weighted[0] && g->g.n > 0) {
+    // the blocked first-step table (8 bytes per kStep1Block vertices instead
+    // of 12 per vertex) when asked for, or by default when the full table
+    // would exceed kStep1FullBudget
+    const bool blocked = step1 == AGIS_RUN_STEP1_BLOCKS ||
+                         (step1 == 0 && 12ull * g->g.n > kStep1FullBudget);
+    if (hp.weighted[0] && g->g.n > 0 && blocked) {
+        const uint64_t nblk = (g->g.n + agis::kStep1Block - 1) / agis::kStep1Block;
+        uint64_t* blk = nullptr;
+        if (st->arena) {
+            out->owns = false;
+            blk = (uint64_t*)st->arena->take((nblk + 1) * sizeof(uint64_t));
+            out->guide = (uint32_t*)st->arena->take(((1ull << agis::kGuideBits) + 1) * sizeof(uint32_t));
+            if (!blk || !out->guide)
+                return fail(ctx, AGIS_E_UNSUPPORTED, "the first-step table does not fit in the fixed workspace");
+        } else {
+            AGIS_HIP(ctx, hipMalloc(&blk, (nblk + 1) * sizeof(uint64_t)), "allocate first-step block prefix");
+        }
+        out->pre = blk;  // owned as the prefix buffer
+        uint64_t total = 0;
+        int32_t lmax = 0;
+        AGIS_HIP(ctx, agis::build_step1_blocks(ctx, *g, *t, hp, blk, &lmax, &total), "first-step block table");
+        hp.s1_blk = agis::gmem((const uint64_t*)(blk + 1));
+        hp.s1_lmax = lmax;
+        hp.s1_total = total;
+        if (total > 0) {
+            const uint32_t shift = agis::guide_shift(total);
+            const uint64_t buckets = ((total - 1) >> shift) + 1;
+            if (!st->arena)
+                AGIS_HIP(ctx, hipMalloc(&out->guide, (buckets + 1) * sizeof(uint32_t)), "allocate first-step guide");
+            AGIS_HIP(ctx, agis::launch_prefix_guide(blk + 1, nblk, total, shift, out->guide, ctx->stream),
+                     "first-step guide");
+            hp.s1_guide = agis::gmem((const uint32_t*)out->guide);
+            hp.s1_shift = shift;
+        }
+    }
+    if (hp.weighted[0] && g->g.n > 0 && !blocked) {
         uint64_t* blocksums = nullptr;
         if (st->arena) {
             out->owns = false;

@@ -522,27 +522,31 @@ __global__ void k_validate_rows(DevGraph g, uint32_t* flags) {
     if (g.off[v + 1] < g.off[v] || g.off[v + 1] > g.nnz) atomicOr(flags, 1u);
 }
 
+// Per-slot kernels run a grid-stride loop over 64-bit slot indices on a
+// capped grid (a dispatch holds at most 2^32 work-items, fewer than the
+// slots of the largest graphs).
 __global__ void k_validate_edges(DevGraph g, uint32_t* flags) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.nnz) return;
-    const uint32_t v = row_of_slot(g.off, g.n, e);
-    if (v >= g.n) {
-        atomicOr(flags, 1u);
-        return;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < g.nnz; e += stride) {
+        const uint32_t v = row_of_slot(g.off, g.n, e);
+        if (v >= g.n) {
+            atomicOr(flags, 1u);
+            continue;
+        }
+        // offsets were checked (monotone, within nnz) by k_validate_rows first
+        const uint32_t x = g.nbr[e];
+        uint32_t f = 0;
+        if ((uint64_t)x >= g.n) {
+            atomicOr(flags, 2u);
+            continue;
+        }
+        if (x == v) f |= 4u;
+        if (e + 1 < g.off[v + 1] && g.nbr[e + 1] <= x) f |= 8u;
+        const uint64_t o = g.off[x];
+        const uint64_t d = g.off[x + 1] - o;
+        if (d > 0xFFFFFFFFull || !contains_u32(g.nbr + o, (uint32_t)d, v)) f |= 16u;
+        if (f) atomicOr(flags, f);
     }
-    // offsets were checked (monotone, within nnz) by k_validate_rows first
-    const uint32_t x = g.nbr[e];
-    uint32_t f = 0;
-    if ((uint64_t)x >= g.n) {
-        atomicOr(flags, 2u);
-        return;
-    }
-    if (x == v) f |= 4u;
-    if (e + 1 < g.off[v + 1] && g.nbr[e + 1] <= x) f |= 8u;
-    const uint64_t o = g.off[x];
-    const uint64_t d = g.off[x + 1] - o;
-    if (d > 0xFFFFFFFFull || !contains_u32(g.nbr + o, (uint32_t)d, v)) f |= 16u;
-    if (f) atomicOr(flags, f);
 }
 
 __global__ void k_max_degree(DevGraph g, uint32_t* out) {
@@ -558,13 +562,21 @@ __global__ void k_max_degree(DevGraph g, uint32_t* out) {
 
 static unsigned grid_for(uint64_t n, unsigned threads) { return (unsigned)((n + threads - 1) / threads); }
 
+// Workgroups of a grid-stride launch over n items: enough to cover them up
+// to kStrideBlocks (2^20 workgroups of 256 = 2^28 work-items per pass).
+constexpr uint64_t kStrideBlocks = 1ull << 20;
+static unsigned stride_grid(uint64_t n, unsigned threads) {
+    const uint64_t b = (n + threads - 1) / threads;
+    return (unsigned)(b < kStrideBlocks ? b : kStrideBlocks);
+}
+
 hipError_t launch_validate_rows(const DevGraph& g, uint32_t* d_flags, hipStream_t stream) {
     if (g.n) hipLaunchKernelGGL(k_validate_rows, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, d_flags);
     return hipGetLastError();
 }
 
 hipError_t launch_validate_edges(const DevGraph& g, uint32_t* d_flags, hipStream_t stream) {
-    if (g.nnz) hipLaunchKernelGGL(k_validate_edges, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, d_flags);
+    if (g.nnz) hipLaunchKernelGGL(k_validate_edges, dim3(stride_grid(g.nnz, 256)), dim3(256), 0, stream, g, d_flags);
     return hipGetLastError();
 }
 
@@ -592,7 +604,11 @@ __global__ void k_tables_init(DevGraph g, uint4* rec, uint64_t* s2, uint64_t* hi
 // that are adjacent to x (each edge among N(v) once).
 __global__ __launch_bounds__(256) void k_tables_edges(DevGraph g, DevGraph adj, const uint4* rec, uint64_t* s2,
                                                        uint64_t* hits, uint32_t k0, uint32_t k1, int exact) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // grid-stride over slots; the loop bound is uniform in a workgroup, so
+    // every lane of a wave takes part in the wave-wide sums below
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < g.nnz; base += stride) {
+    const uint64_t e = base + threadIdx.x;
     const bool active = e < g.nnz;
     uint32_t v = 0xFFFFFFFFu;
     uint64_t dx = 0, h = 0;
@@ -628,6 +644,7 @@ __global__ __launch_bounds__(256) void k_tables_edges(DevGraph g, DevGraph adj, 
         atomicAdd((unsigned long long*)&s2[v], (unsigned long long)sdx);
         if (sh) atomicAdd((unsigned long long*)&hits[v], (unsigned long long)sh);
     }
+    }
 }
 
 __global__ void k_tables_finalize(DevGraph g, uint4* rec, const uint64_t* s2, const uint64_t* hits, uint64_t* trials,
@@ -658,7 +675,7 @@ hipError_t launch_build_tables(const DevGraph& g, const DevGraph& adj, uint4* re
     if (!g.n) return hipSuccess;
     hipLaunchKernelGGL(k_tables_init, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, rec, s2, hits);
     if (g.nnz)
-        hipLaunchKernelGGL(k_tables_edges, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, adj, rec, s2, hits,
+        hipLaunchKernelGGL(k_tables_edges, dim3(stride_grid(g.nnz, 256)), dim3(256), 0, stream, g, adj, rec, s2, hits,
                            k0, k1, exact);
     hipLaunchKernelGGL(k_tables_finalize, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, rec, s2, hits, trials,
                        lc_min, exact);
@@ -809,6 +826,25 @@ __global__ __launch_bounds__(kScanThreads) void k_step1_final(const uint4* rec, 
             pre[v] = run;
         }
     }
+}
+
+// Weight sums of blocks of kStep1Block vertices (one wave per block, lane j
+// summing vertices 4j .. 4j + 3 of it) into sums[b]; sums[nblk] = 0.
+__global__ __launch_bounds__(256) void k_step1_blocksum(const uint4* rec, DevPlan P, uint64_t n,
+                                                         const int32_t* lmax_p, uint64_t* sums) {
+    const int32_t lmax = *lmax_p;
+    const uint64_t nblk = (n + kStep1Block - 1) / kStep1Block;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t b = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; b < nblk; b += waves) {
+        const uint64_t v0 = b * kStep1Block + 4ull * (uint64_t)lane_id();
+        uint64_t s = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (v0 + e < n) s += step0_weight(rec, P, v0 + e, lmax);
+        s = wave_sum_u64(s);
+        if (lane_id() == 0) sums[b] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sums[nblk] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -972,18 +1008,19 @@ hipError_t launch_hub_slots(agis_ctx* ctx, const DevGraph& g, uint32_t min_deg, 
 }
 
 __global__ void k_hub_bits(DevGraph g, const int32_t* hub_slot, uint64_t words, uint32_t* bits) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= g.nnz) return;
-    const uint32_t v = row_of_slot(g.off, g.n, e);
-    const int32_t slot = hub_slot[v];
-    if (slot < 0) return;
-    const uint32_t x = g.nbr[e];
-    atomicOr(&bits[(uint64_t)slot * words + (x >> 5)], 1u << (x & 31u));
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < g.nnz; e += stride) {
+        const uint32_t v = row_of_slot(g.off, g.n, e);
+        const int32_t slot = hub_slot[v];
+        if (slot < 0) continue;
+        const uint32_t x = g.nbr[e];
+        atomicOr(&bits[(uint64_t)slot * words + (x >> 5)], 1u << (x & 31u));
+    }
 }
 
 hipError_t launch_hub_bits(const DevGraph& g, const int32_t* hub_slot, uint64_t words, uint32_t* bits,
                            hipStream_t stream) {
-    if (g.nnz) hipLaunchKernelGGL(k_hub_bits, dim3(grid_for(g.nnz, 256)), dim3(256), 0, stream, g, hub_slot, words, bits);
+    if (g.nnz) hipLaunchKernelGGL(k_hub_bits, dim3(stride_grid(g.nnz, 256)), dim3(256), 0, stream, g, hub_slot, words, bits);
     return hipGetLastError();
 }
 
@@ -1067,6 +1104,33 @@ hipError_t launch_orient_fill(const DevGraph& g, const uint64_t* off_out, uint32
 }
 
 uint64_t step1_scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+// The block sums with a trailing 0, scanned exclusively in place: blk[b] is
+// then the total of the blocks before b, so blk[0] = 0, blk[1 + b] is the
+// inclusive prefix of block b and blk[nblk] the total.
+hipError_t build_step1_blocks(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp,
+                              uint64_t* blk, int32_t* lmax_out, uint64_t* total) {
+    const uint64_t n = g.g.n;
+    hipStream_t st = ctx->stream;
+    int32_t* d_lmax = (int32_t*)ctx->d_small;
+    const int32_t init = kCertainZero;
+    hipError_t e = hipMemcpyAsync(d_lmax, &init, sizeof(init), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    const uint64_t nblk = (n + kStep1Block - 1) / kStep1Block;
+    hipLaunchKernelGGL(k_step1_max, dim3(grid_for(n, 256)), dim3(256), 0, st, t.rec, hp, n, d_lmax);
+    const uint64_t wg = (nblk + 3) / 4;
+    hipLaunchKernelGGL(k_step1_blocksum, dim3((unsigned)(wg < kStrideBlocks ? wg : kStrideBlocks)), dim3(256), 0, st,
+                       t.rec, hp, n, d_lmax, blk);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, blk, nblk + 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int32_t lm = 0;
+    e = hipMemcpyAsync(&lm, d_lmax, sizeof(lm), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(total, blk + nblk, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    *lmax_out = lm;
+    return e;
+}
 
 hipError_t build_step1(agis_ctx* ctx, const agis_graph& g, const agis_tables& t, const DevPlan& hp, uint32_t* q1,
                        uint64_t* pre, uint64_t* total, uint64_t* blocksums) {
@@ -1530,18 +1594,70 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     break;
                 }
                 const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, P->s1_total);
-                if (P->s1_guide) {
-                    // the answer lies between the guides of r's bucket and the next
-                    const uint64_t bkt = r >> P->s1_shift;
-                    mt.uni(P->s1_guide + bkt, 8);
-                    const uint32_t lo = P->s1_guide[bkt], hi = P->s1_guide[bkt + 1];
-                    v = lo + (uint32_t)wave_first_greater(P->s1_pre + lo, (uint64_t)(hi - lo) + 1, r, mt);
+                if (P->s1_blk) {
+                    // Blocked table: the block holding r from the block
+                    // prefix (narrowed by the guide), then the block's
+                    // weights recomputed from the vertex records exactly as
+                    // the table was built (lane j: vertices 4j .. 4j + 3),
+                    // once for the lane sums and once more for the chosen
+                    // lane (no weights held across the scan).
+                    const AGIS_GMEM uint64_t* blk = P->s1_blk;
+                    uint64_t bk;
+                    if (P->s1_guide) {
+                        const uint64_t bkt = r >> P->s1_shift;
+                        mt.uni(P->s1_guide + bkt, 8);
+                        const uint32_t lo = P->s1_guide[bkt], hi = P->s1_guide[bkt + 1];
+                        bk = lo + wave_first_greater(blk + lo, (uint64_t)(hi - lo) + 1, r, mt);
+                    } else {
+                        bk = wave_first_greater(blk, (g.n + kStep1Block - 1) / kStep1Block, r, mt);
+                    }
+                    mt.uni(blk + bk - 1, 8);
+                    const uint64_t rr = r - blk[(int64_t)bk - 1];
+                    const uint64_t v0 = bk * kStep1Block + 4ull * (uint64_t)lane;
+                    const AGIS_GMEM int32_t* lt0 = P->lt[0];
+                    mt.vec(t.rec + v0, 64, v0 < g.n);
+                    if (lt0) mt.vec(lt0 + v0, 16, v0 < g.n);
+                    auto q_of = [&](uint64_t vv) -> uint32_t {
+                        if (vv >= g.n) return 0u;
+                        const uint4 rc = t.rec[vv];
+                        const uint32_t f1 = P->f1[0];
+                        if (rc.x < f1) return 0u;
+                        const int32_t l = lt0 ? lt0[vv] : approx_log_weight(rc, 0, f1, P->ie[0], P->f2[0]);
+                        return l == kCertainZero ? 0u : weight_from_log(P->s1_lmax, l, s_exp2tab);
+                    };
+                    uint64_t qs = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) qs += q_of(v0 + (uint64_t)e);
+                    const uint64_t incl = wave_incl_scan_u64(qs);
+                    const int L = __ffsll((unsigned long long)__ballot(incl > rr)) - 1;
+                    uint64_t run = readlane_u64(incl - qs, L);
+                    const uint64_t vL = bk * kStep1Block + 4ull * (uint64_t)L;
+                    v = 0;
+                    den = 0;
+                    for (uint32_t e = 0; e < 4; ++e) {
+                        const uint32_t w = q_of(vL + e);  // the same for every lane
+                        if (run + w > rr) {
+                            v = (uint32_t)(vL + e);
+                            den = w;
+                            break;
+                        }
+                        run += w;
+                    }
+                    num = P->s1_total;
                 } else {
-                    v = (uint32_t)wave_first_greater(P->s1_pre, g.n, r, mt);
+                    if (P->s1_guide) {
+                        // the answer lies between the guides of r's bucket and the next
+                        const uint64_t bkt = r >> P->s1_shift;
+                        mt.uni(P->s1_guide + bkt, 8);
+                        const uint32_t lo = P->s1_guide[bkt], hi = P->s1_guide[bkt + 1];
+                        v = lo + (uint32_t)wave_first_greater(P->s1_pre + lo, (uint64_t)(hi - lo) + 1, r, mt);
+                    } else {
+                        v = (uint32_t)wave_first_greater(P->s1_pre, g.n, r, mt);
+                    }
+                    num = P->s1_total;
+                    mt.uni(P->s1_q + v, 4);
+                    den = P->s1_q[v];
                 }
-                num = P->s1_total;
-                mt.uni(P->s1_q + v, 4);
-                den = P->s1_q[v];
             } else {
                 if (g.nnz == 0) {
                     fail = 0;

@@ -221,3 +221,126 @@ def complete_bipartite(a: int, b: int) -> CSR:
     us = np.repeat(np.arange(a), b)
     vs = np.tile(np.arange(a, a + b), a)
     return csr_from_edges(a + b, us, vs, name=f"K{a}_{b}")
+
+
+# ---------------------------------------------------------------- counter-based R-MAT
+
+_GOLDEN_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix_draws(seed: int, counters: np.ndarray) -> np.ndarray:
+    """Draws `counters` of the counter-based SplitMix64 stream of `seed`
+    (Steele, Lea and Flood, OOPSLA 2014): mix(seed + (i + 1) * gamma)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counters.astype(np.uint64) + np.uint64(1)) * _GOLDEN_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def rmat_counter_edges(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                       seed: int = 30, first: int = 0, count: int = None):
+    """Endpoints (u, v) of edges [first, first + count) of the counter-based
+    R-MAT stream that the GPU generator (synth/csrc/rmat_gen.hip) draws:
+    level l of edge e uses draw e * 32 + l, top 53 bits over 2^53."""
+    total = edge_factor << scale
+    count = total - first if count is None else count
+    e = np.arange(first, first + count, dtype=np.uint64)
+    u = np.zeros(count, dtype=np.uint64)
+    v = np.zeros(count, dtype=np.uint64)
+    ab, abc = a + b, a + b + c
+    for lvl in range(scale):
+        r = (splitmix_draws(seed, e * np.uint64(32) + np.uint64(lvl)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        u = (u << np.uint64(1)) | (r >= ab).astype(np.uint64)
+        v = (v << np.uint64(1)) | (((r >= a) & (r < ab)) | (r >= abc)).astype(np.uint64)
+    return u.astype(np.int64), v.astype(np.int64)
+
+
+def rmat_counter(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                 seed: int = 30) -> CSR:
+    """Host generation of the counter-based R-MAT graph (small scales): the
+    graph rmat_gpu builds for the same arguments."""
+    u, v = rmat_counter_edges(scale, edge_factor, a, b, c, seed)
+    return csr_from_edges(1 << scale, u, v, name=f"rmatc{scale}_ef{edge_factor}_s{seed}")
+
+
+_GENLIB = None
+
+
+def _genlib():
+    import ctypes
+    import os
+    global _GENLIB
+    if _GENLIB is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynthgen.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        P, u64, u32, dbl = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double
+        L.synth_rmat_count.argtypes = [P, u64, u32, dbl, dbl, dbl, u64, P]
+        L.synth_rmat_fill.argtypes = [P, P, P, u64, u32, dbl, dbl, dbl, u64, P]
+        L.synth_sort_dedup_rows.argtypes = [P, P, u64, P, P, u64, P]
+        L.synth_compact_rows.argtypes = [P, P, P, u64, P, u64, P]
+        for f in (L.synth_rmat_count, L.synth_rmat_fill, L.synth_sort_dedup_rows, L.synth_compact_rows):
+            f.restype = ctypes.c_int
+        _GENLIB = L
+    return _GENLIB
+
+
+def rmat_gpu(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+             seed: int = 30, device: str = "cuda", stage_bytes: int = 8 << 30):
+    """The counter-based R-MAT graph built on the GPU in place (count the
+    degrees, scatter both directions into rows, sort and deduplicate each
+    row, move the rows onto the deduplicated offsets): the peak is the
+    undeduplicated neighbour array plus two offset arrays, a degree array
+    and the staging buffer.  Returns (off int64[n + 1], nbr int32[nnz])
+    device tensors (off holds uint64 values, nbr uint32 ids); nbr is a view
+    of the first nnz entries of the undeduplicated buffer."""
+    import torch
+    L = _genlib()
+    n = 1 << scale
+    total = edge_factor * n
+    stream = torch.cuda.current_stream(torch.device(device)).cuda_stream
+
+    def ok(rc, what):
+        if rc != 0:
+            raise RuntimeError(f"R-MAT generator: {what} failed ({rc})")
+
+    deg = torch.zeros(n, dtype=torch.int32, device=device)
+    ok(L.synth_rmat_count(deg.data_ptr(), total, scale, a, b, c, seed, stream), "count")
+    off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(deg, 0, dtype=torch.int64, out=off[1:])
+    slots = int(off[-1].item())
+    nbr = torch.empty(max(slots, 1), dtype=torch.int32, device=device)
+    deg.zero_()
+    ok(L.synth_rmat_fill(off.data_ptr(), deg.data_ptr(), nbr.data_ptr(), total, scale, a, b, c, seed, stream),
+       "fill")
+    stage = torch.empty(int(stage_bytes), dtype=torch.uint8, device=device)
+    ok(L.synth_sort_dedup_rows(off.data_ptr(), nbr.data_ptr(), n, deg.data_ptr(), stage.data_ptr(), stage_bytes,
+                               stream), "sort and deduplicate")
+    new_off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(deg, 0, dtype=torch.int64, out=new_off[1:])
+    del deg
+    ok(L.synth_compact_rows(off.data_ptr(), new_off.data_ptr(), nbr.data_ptr(), n, stage.data_ptr(), stage_bytes,
+                            stream), "compact")
+    del stage, off
+    nnz = int(new_off[-1].item())
+    return new_off, nbr[:nnz]
+
+
+def build_generator() -> str:
+    """Compiles synth/csrc/rmat_gen.hip into synth/libsynthgen.so (gfx950)."""
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    out = os.path.join(here, "libsynthgen.so")
+    hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
+    arch = os.environ.get("AGIS_OFFLOAD_ARCH", "gfx950")
+    cmd = [hipcc, "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={arch}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+           os.path.join(here, "csrc", "rmat_gen.hip"), "-o", out + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed building libsynthgen.so:\n" + res.stdout + res.stderr)
+    os.replace(out + ".tmp", out)
+    return out
