@@ -602,6 +602,128 @@ def large_legs(args, sess, G20, T20, pats_budgets, log, restore_tuning):
     return out
 
 
+def c5_leg(args, sess):
+    """R-MAT scale 30 (2^30 vertices, edge factor 16, ~3.4e10 CSR slots)
+    resident in HBM, generated on the GPU (synth.graphs.rmat_gpu, seed 30):
+    5-clique, 6-cycle and the chordal 7-cycle run to +-1% at 95% CI under
+    learned, f_approx (switching and always) and f_uniform, each run capped
+    at --c5-seconds of wall time (the cancel flag stops it between rounds
+    and the partial result reports the error it reached); the 4-star and
+    3-path closed forms and cross-mode agreement are the judges."""
+    import ctypes
+    import threading
+    import torch
+    import synth
+    from synth import graphs
+    from paper_2601_01388_amd.session import mlp_init
+    out = {}
+
+    def mem():
+        free, total = torch.cuda.mem_get_info()
+        return round(free / 2 ** 30, 1)
+
+    t0 = time.perf_counter()
+    off, nbr = graphs.rmat_gpu(30, 16, seed=30, device=str(sess.device))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    G = sess.graph(off, nbr, validate=True)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    T = sess.tables(G, cv_seed=1)
+    torch.cuda.synchronize()
+    tables_s = time.perf_counter() - t0
+    d = (off[1:] - off[:-1]).double()
+    dmax = int(d.max().item())
+    out["graph"] = {"scale": 30, "seed": 30, "generator": "counter-based R-MAT on the GPU (synth.graphs.rmat_gpu)",
+                    "n": G.n, "nnz": G.nnz, "dmax": dmax, "generate_s": gen_s, "load_validate_s": load_s,
+                    "tables_s": tables_s, "neighbour_bytes": 4 * G.nnz, "offset_bytes": 8 * (G.n + 1),
+                    "free_gib_after_tables": mem()}
+    log(f"C5: R-MAT scale 30 n={G.n} nnz={G.nnz} dmax={dmax}; generated {gen_s:.1f} s, loaded+validated "
+        f"{load_s:.1f} s, tables {tables_s:.1f} s, free {mem()} GiB")
+    sentinels = {}
+    exact4 = float((d * (d - 1) * (d - 2) * (d - 3)).sum().item())
+    exact3p = float((d * (d - 1)).sum().item())  # wedges: 2! x sum C(d, 2)
+    for name, exact in (("4-star", exact4), ("wedge", exact3p)):
+        p = synth.named_pattern(name)
+        r = sess.estimate(G, T, p, 1 << 22, 5, mode="switch")
+        se = math.sqrt(r.variance / r.n)
+        sentinels[name] = {"estimate": r.estimate, "exact": exact, "z": (r.estimate - exact) / se if se else 0.0,
+                           "rel_err": (r.estimate - exact) / exact}
+        log(f"C5 {name}: {r.estimate:.6g} vs closed form {exact:.6g} (z {sentinels[name]['z']:.2f})")
+    out["sentinels"] = sentinels
+    del d
+    # learned tables: one network per pattern trained on extension counts of
+    # the R-MAT scale 20 graph, inferred on this graph's features
+    g20 = synth.rmat(20, 16, seed=20)
+    G20 = sess.graph(g20.off, g20.nbr)
+    T20 = sess.tables(G20, cv_seed=1)
+    f20 = sess.features(T20)
+    f30 = sess.features(T)
+    runs = {}
+    for pid, name in enumerate(("5-clique", "6-cycle", "chordal-7-cycle")):
+        p = synth.named_pattern(name)
+        steps = sess.weighted_steps(p, "learned")
+        sums, counts = sess.learn_targets(G20, T20, p, 1 << 20, 501 + pid, mode="switch")
+        rows = sess.learn_rows(sums, counts, step_mask=sum(1 << i for i in steps), min_count=2,
+                               base=sess.step_log_weights(T20, p))
+        del sums, counts
+        tg = rows["target"].cpu().numpy()
+        wt = rows["weight"].cpu().numpy()
+        params = torch.from_numpy(mlp_init(31 + pid, float(np.average(tg, weights=wt)) if rows["rows"] else 0.0,
+                                           zero_output=True)).to(sess.device)
+        per_epoch = max(1, -(-rows["rows"] // 4096))
+        sess.mlp_train(params, f20, rows, epochs=max(20, -(-1500 // per_epoch)), batch=4096, lr=3e-3, seed=pid)
+        base = sess.step_log_weights(T, p)
+        tabs = sess.learned_tables(params, f30, p, base=base, rows=rows)
+        del base
+        ptrs = {i: tab.data_ptr() for i, tab in tabs.items()}
+        row = {}
+        for mode in ("learned", "switch", "always", "uniform"):
+            flag = ctypes.c_int32(0)
+            timer = threading.Timer(args.c5_seconds, lambda f=flag: setattr(f, "value", 1))
+            timer.start()
+            kw = dict(learned=ptrs) if mode == "learned" else {}
+            r = sess.estimate(G, T, p, args.c5_budget, 61 + pid, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
+                              check_every=1 << 14, min_samples=1 << 14, cancel=flag, **kw)
+            timer.cancel()
+            label = {"switch": "f_approx", "always": "f_approx_always", "uniform": "f_uniform",
+                     "learned": "learned"}[mode]
+            need = r.n * (r.eps_hat / 0.01) ** 2 if r.n and math.isfinite(r.eps_hat) else None
+            row[label] = {"seconds": r.seconds, "samples": r.n, "converged": bool(r.converged),
+                          "stopped_by_time_cap": r.status == -9, "estimate": r.estimate, "eps_hat": r.eps_hat,
+                          "rel_var": rel_var(r) if r.n else None, "samples_needed": need,
+                          "samples_per_s": r.n / r.seconds if r.seconds > 0 else None}
+            log(f"C5 +-1% {name} {label}: {r.seconds:.1f} s, n={r.n}, eps_hat {r.eps_hat:.4f}, "
+                f"converged={bool(r.converged)}, estimate {r.estimate:.6g}")
+        # cross-mode agreement of the estimates (each with its own standard error)
+        labs = [k for k in row if row[k]["samples"]]
+        worst = 0.0
+        for a in labs:
+            for b in labs:
+                if a < b:
+                    ra, rb = row[a], row[b]
+                    se = math.sqrt(ra["rel_var"] * ra["estimate"] ** 2 / ra["samples"]
+                                   + rb["rel_var"] * rb["estimate"] ** 2 / rb["samples"])
+                    if se > 0:
+                        worst = max(worst, abs(ra["estimate"] - rb["estimate"]) / se)
+        row["max_cross_mode_z"] = worst
+        runs[name] = row
+        del tabs, params, rows
+        torch.cuda.empty_cache()
+    out["to_1pct"] = runs
+    out["free_gib_end"] = mem()
+    T20.close()
+    G20.close()
+    T.close()
+    G.close()
+    del off, nbr, f30, f20
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -633,6 +755,10 @@ def main():
     ap.add_argument("--skip-conc", action="store_true")
     ap.add_argument("--skip-oriented", action="store_true")
     ap.add_argument("--skip-c1", action="store_true")
+    ap.add_argument("--c5", action="store_true",
+                    help="only the R-MAT scale 30 leg (3.4e10 CSR slots resident in HBM); prints its own JSON line")
+    ap.add_argument("--c5-seconds", type=float, default=40.0, help="wall-time cap of each C5 run to +-1%%")
+    ap.add_argument("--c5-budget", type=int, default=1 << 31, help="sample budget of each C5 run to +-1%%")
     ap.add_argument("--conc-budget", type=int, default=20_000_000,
                     help="sample budget per pattern of the concentration runs (to +-1%%)")
     ap.add_argument("--skip-large", action="store_true",
@@ -677,6 +803,19 @@ def main():
     import torch
     import synth
     from paper_2601_01388_amd.session import Session
+
+    if args.c5:
+        sess = Session(0)
+        c5 = c5_leg(args, sess)
+        sess.close()
+        try:
+            os.makedirs(os.path.dirname(args.detail), exist_ok=True)
+            with open(args.detail, "w") as f:
+                json.dump({"c5": c5}, f, indent=1, default=float)
+        except OSError as e:
+            log(f"could not write the detail file: {e}")
+        print(json.dumps({"c5": c5}, default=float), flush=True)
+        return
 
     wall0 = time.perf_counter()
     log("generating R-MAT scale 20")

@@ -205,9 +205,10 @@ int synth_rmat_fill(const uint64_t* off, uint32_t* cursor, uint32_t* nbr, uint64
 
 // Sorts every row of (off, nbr) and keeps its distinct values (no value
 // equal to the row id), front-packed; newdeg (device uint32[n]) receives
-// their counts.  stage: device scratch of stage_bytes (two halves: the sort's
-// output and its temporary storage); batches of consecutive rows whose
-// slots fit in a quarter of it (and below 2^30 slots) are sorted at a time.
+// their counts.  stage: device scratch of stage_bytes (a quarter for the
+// sort's output, a quarter for the batch offsets, a half for its temporary
+// storage); batches of consecutive rows whose slots fit in a quarter of it
+// (below 2^30 slots and 2^22 rows) are sorted at a time.
 int synth_sort_dedup_rows(const uint64_t* off, uint32_t* nbr, uint64_t n, uint32_t* newdeg, void* stage,
                           uint64_t stage_bytes, void* stream) {
     hipStream_t st = (hipStream_t)stream;
@@ -222,7 +223,11 @@ int synth_sort_dedup_rows(const uint64_t* off, uint32_t* nbr, uint64_t n, uint32
     int* rel = (int*)(base + stage_bytes / 4);                // a quarter: batch offsets
     char* temp = base + stage_bytes / 2;                      // a half: the sort's temporary storage
     const uint64_t temp_bytes = stage_bytes - stage_bytes / 2;
-    const uint64_t max_rows = stage_bytes / 4 / sizeof(int) - 1;
+    // at most 2^22 segments per sort: the segmented sort's launches grow
+    // with the segment count, and batches of many more short rows (the high
+    // ids of an R-MAT graph) were left unsorted without an error
+    uint64_t max_rows = stage_bytes / 4 / sizeof(int) - 1;
+    if (max_rows > (1ull << 22)) max_rows = 1ull << 22;
     uint64_t r0 = 0;
     uint64_t batch_cap = cap;
     while (r0 < n) {
