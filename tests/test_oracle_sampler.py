@@ -179,6 +179,48 @@ def test_unbiased_exact_enumeration_term_ablation(name, terms):
         assert r["p_total"] == 1 and r["ex"] == exact
 
 
+@pytest.mark.parametrize("name", ["triangle", "4-clique", "house", "5-cycle", "diamond"])
+def test_unbiased_exact_enumeration_learned_tables(name):
+    """Theorem 2 with arbitrary learned tables: the pick and the importance
+    factor use the same integer weights, so E[X] equals the exact count for
+    any table; certain zeros (d(v) - |B| < |F1|) stay zero whatever the
+    table says there; and the weights follow the table's order (a table
+    ignored in favour of f_approx, or consulted for a certain zero, fails)."""
+    rng = np.random.Generator(np.random.PCG64(11 + len(name)))
+    for gi in (0, 3, 4):
+        g = SMALL_GRAPHS[gi]
+        p = synth.named_pattern(name)
+        exact = judges.brute_force(g, p.k, p.edges)
+        c = compile_pattern(p.k, p.edges, mode="learned")
+        deg = np.diff(g.off).astype(np.int64)
+        tabs = {}
+        for i, st in enumerate(c["steps"]):
+            if st["decision"] and st["f1"] > 0:
+                t = rng.integers(-(8 << 16), 8 << 16, size=g.n).astype(np.int32)
+                # the highest values of all at the vertices that cannot extend
+                t[deg < st["b"] + st["f1"]] = 30 << 16
+                tabs[i] = t
+        assert tabs, name
+        s = oracle.Sampler(g, oracle.Tables(g, cv_seed=5), c, seed=3, learned=tabs)
+        r = enumerate_tree(s)
+        assert r["p_total"] == 1 and r["ex"] == exact, (name, gi)
+        prefixes = {tuple(tau[:i]) for tau in r["success"] for i in range(p.k)} | {()}
+        for tau in prefixes:
+            i = len(tau)
+            if i not in tabs:
+                continue
+            st = c["steps"][i]
+            vs, ws = s.step_distribution(i, list(tau))
+            vs = vs.astype(np.int64)
+            ws = ws.astype(np.int64)
+            cz = deg[vs] < st["b"] + st["f1"]
+            assert (ws[cz] == 0).all(), (name, gi, tau)
+            live = ~cz & (ws > 0)
+            lt = tabs[i][vs[live]].astype(np.int64)
+            order = np.argsort(lt, kind="stable")
+            assert (np.diff(ws[live][order]) >= 0).all(), (name, gi, tau)
+
+
 def test_term_ablation_drops_the_right_factor():
     """Step 1 of the diamond has signature (b, f1, ie, f2) = (0, 3, 2, 0) and
     of the house (0, 3, 1, 2): T[F1] is d(d-1)(d-2) / 3! (its log is the sum
