@@ -118,7 +118,12 @@ typedef struct {
  *   vertex) or AGIS_RUN_STEP1_BLOCKS (the prefix over blocks of 256
  *   vertices, 8 bytes per block; a draw recomputes its block's weights from
  *   the vertex records); neither = full up to 2 GiB, blocked beyond.  The
- *   samples are the same either way.
+ *   samples are the same either way.  A run to epsilon (eps > 0) whose
+ *   check_every is a multiple of 2048 runs in one persistent launch that
+ *   merges, checks and stops every pattern on the device;
+ *   AGIS_RUN_HOST_ROUNDS asks for one launch per round of check_every
+ *   samples with the checks on the host instead.  Both stop at the same
+ *   sample counts and give the same results (to relative 1e-9).
  * terms: which factors of f_approx (Eq. probability_function) enter the
  *   weights -- AGIS_TERMS_ALL (T[F1] T[I1] T[F2], the method), or the
  *   incremental versions of the paper's analysis of the approximation
@@ -132,10 +137,11 @@ typedef struct {
  *   continues the same sample sequence, so results over the concatenated
  *   ranges equal one run over the whole range (checks of a resumed run
  *   count its own samples).
- * cancel: host int32 polled between rounds of samples (NULL: none); once
- *   it reads nonzero the call returns AGIS_E_CANCELLED with every result
- *   filled from the whole rounds that finished (a prefix of each pattern's
- *   sample sequence, so a consistent partial estimate).
+ * cancel: host int32 polled while the call runs (NULL: none); once it reads
+ *   nonzero the call returns AGIS_E_CANCELLED with every result filled from
+ *   the samples merged so far: whole reduction tiles of 2048 samples in
+ *   index order (whole rounds of the round-by-round run), a prefix of each
+ *   pattern's sample sequence, so a consistent partial estimate.
  * batch_learned: for AGIS_MODE_LEARNED in agis_estimate_batch, a host array
  *   of n_patterns x AGIS_MAX_K device table pointers (pattern i's tables at
  *   [i * AGIS_MAX_K .. + AGIS_MAX_K), as `learned` of a single estimate);
@@ -145,6 +151,7 @@ typedef struct {
 #define AGIS_RUN_ROWTAB_OFF 2u
 #define AGIS_RUN_STEP1_BLOCKS 4u
 #define AGIS_RUN_STEP1_FULL 8u
+#define AGIS_RUN_HOST_ROUNDS 16u
 #define AGIS_TERMS_ALL 0u
 #define AGIS_TERMS_F1 1u
 #define AGIS_TERMS_F1_I1 2u
@@ -256,9 +263,11 @@ int agis_graph_export(agis_ctx* ctx, const agis_graph* g, uint64_t* n, uint64_t*
  * With them the library builds two search aids of the sampler (they change
  * no sample): neighbourhood bitmaps of the highest-degree vertices (up to
  * 1 GiB), and the common-neighbour counts of every pair among the hubs of
- * highest degree (up to 8,192 of them, 256 MiB, within a bounded build
- * work), which make a uniform step over the common neighbours of two such
- * hubs a table read plus a partial walk. */
+ * highest degree (up to H = 8,192 of them, within a bounded build work),
+ * which make a uniform step over the common neighbours of two such hubs a
+ * table read plus a partial walk.  The pair tables hold 8 counts per
+ * ordered pair (the total and 7 running counts at eighths of the shorter
+ * list), H^2 x 8 x 4 B: at most 2 GiB. */
 int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_seed, int32_t lc_min_q16,
                                int32_t exact_cv, agis_tables** out);
 void agis_tables_destroy(agis_tables* t);

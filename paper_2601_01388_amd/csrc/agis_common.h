@@ -233,6 +233,60 @@ struct RoundDesc {
 
 struct Record;
 
+// Welford/Chan accumulator of the sample weights of one workgroup.
+struct Partial {
+    double n;
+    double mean;
+    double m2;
+    double nonzero;
+};
+
+// Samples per reduction tile of a run to epsilon in one launch (the tiles
+// of the round-by-round path have the same size, so the statistics are
+// merged from the same tiles in the same order).
+constexpr uint64_t kEpsTile = 2048;
+
+// Device state of one pattern of a run to epsilon in one persistent
+// launch (the host fills the first block and zeroes the rest).
+struct EpsPattern {
+    uint64_t budget;       // samples at most
+    uint64_t start;        // index of the first sample
+    uint64_t check;        // samples between checks (a multiple of kEpsTile)
+    uint64_t min_samples;  // no convergence before this many samples
+    uint32_t plan;
+    uint32_t pad0;
+    // run state
+    unsigned long long next;    // next sample slot to hand out (relative to start)
+    unsigned long long merged;  // samples whose tiles are merged, in order
+    uint32_t stop;              // 1: no more samples (converged, budget reached or cancelled)
+    uint32_t owner;             // merge token: 1 while a wave merges
+    uint32_t converged;
+    uint32_t pad1;
+    Partial acc;                       // statistics of the merged samples
+    unsigned long long stop_clock;     // wall clock when the pattern stopped
+};
+
+// The buffers of a run to epsilon in one launch: per pattern a ring of
+// ring_samples weights and ring_samples / kEpsTile tiles (completed-sample
+// counter, partial statistics, and the index + 1 of the tile whose partial
+// is ready); slots are handed out only below merged + window.
+struct EpsDesc {
+    AGIS_GMEM EpsPattern* pat;
+    AGIS_GMEM double* ring;
+    AGIS_GMEM uint32_t* tile_done;
+    AGIS_GMEM Partial* tile_part;
+    AGIS_GMEM unsigned long long* tile_ready;
+    const volatile uint32_t* cancel;     // pinned host flag, set by the host while the launch runs
+    AGIS_GMEM uint32_t* fault;           // set by a wave whose window wait ran out
+    AGIS_GMEM unsigned long long* clock0;  // wall clock at the launch's start
+    uint64_t ring_samples;  // a power of two, a multiple of kEpsTile
+    uint64_t window;
+    uint32_t npat;
+    uint32_t grab;
+    double z;
+    double eps;
+};
+
 // Sampler kernel modes: production, record-writing, request-metering.
 constexpr int kRun = 0;
 constexpr int kDumpRecords = 1;
@@ -253,19 +307,12 @@ struct LaunchDesc {
     uint64_t cap;
     AGIS_GMEM unsigned long long* queue;  // kQueues counters, kQueueStride apart
     AGIS_GMEM double* xout;               // weight per slot
+    EpsDesc eps;                          // run to epsilon in one launch
     uint32_t grab;
     // a hub's bitmap replaces the merge with its list when the list is at
     // least hub_window / 64 times as long as the base it is intersected with
     uint32_t hub_window;
     RoundDesc round;
-};
-
-// Welford/Chan accumulator of the sample weights of one workgroup.
-struct Partial {
-    double n;
-    double mean;
-    double m2;
-    double nonzero;
 };
 
 struct Record {

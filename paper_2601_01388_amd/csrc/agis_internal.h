@@ -45,6 +45,14 @@ struct agis_ctx {
     hipEvent_t ev_stop = nullptr;
     // device address of this device's fixed workspace (agis_estimate_noalloc)
     void* noalloc_scratch = nullptr;
+    // buffers of runs to epsilon in one launch (pattern states, rings, tiles)
+    void* d_eps = nullptr;
+    size_t eps_bytes = 0;
+    // pinned, device-mapped host flag: the cancel request of a run to
+    // epsilon in one launch, read by the kernel while it runs
+    volatile uint32_t* h_cancel = nullptr;
+    const volatile uint32_t* d_cancel = nullptr;
+    int wall_clock_khz = 100000;
 };
 
 struct agis_graph {
@@ -181,6 +189,9 @@ uint32_t guide_shift(uint64_t total);
 hipError_t launch_prefix_guide(const uint64_t* pre, uint64_t n, uint64_t total, uint32_t shift, uint32_t* guide,
                                hipStream_t stream);
 
+// a[0 .. n) = v (a kernel, so that a captured sequence holds no memset).
+hipError_t launch_fill_u32(uint32_t* a, uint64_t n, uint32_t v, hipStream_t stream);
+
 // Per-row pick table (per CSR slot, the inclusive u64 prefix of the integer
 // weights within the slot's row) of a weighted step with one backward vertex
 // whose per-vertex log weights (launch_step_log_weights) are sw.
@@ -212,6 +223,8 @@ struct SampleLaunch {
 // The sampling kernel for (record-writing?, register-budget variant 0..2,
 // pair-hub paths?).
 const void* sample_kernel(bool dump, int variant, bool pairs, bool meter);
+// The persistent run-to-epsilon sampler for (register-budget variant, pair-hub paths?).
+const void* sample_eps_kernel(int variant, bool pairs);
 
 // Sizes the persistent grid (resident waves only) and the buffers for
 // rounds of at most max_slots samples over at most max_segs segments.  With

@@ -8,6 +8,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "agis.h"
@@ -184,7 +185,8 @@ constexpr uint64_t kHubBitmapBudget = 1ull << 30;
 // uniform last step whose candidates are the common neighbours of two such
 // hubs only counts them, so the count is one table read.  The pair hubs are
 // those of degree >= 2^p for the smallest p with at most kPairHubs of them
-// (a table of at most 256 MiB) and an estimated build work of at most
+// (counts and running counts at eighths, H^2 x kPairParts x 4 B: at most
+// 2 GiB) and an estimated build work of at most
 // kPairWork list elements (the shorter list of every pair is walked; about
 // 0.1 s at this bound).
 constexpr uint64_t kPairHubs = 8192;
@@ -327,7 +329,8 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     }
     const uint32_t rowtab = params->flags & 3u;
     const uint32_t step1 = params->flags & (AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL);
-    if (rowtab > AGIS_RUN_ROWTAB_OFF || (params->flags & ~(3u | AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL)) ||
+    if (rowtab > AGIS_RUN_ROWTAB_OFF ||
+        (params->flags & ~(3u | AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL | AGIS_RUN_HOST_ROUNDS)) ||
         step1 == (AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL))
         return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
     if (params->terms > AGIS_TERMS_F1_I1) return fail(ctx, AGIS_E_INVALID_ARG, "unknown term set");
@@ -664,6 +667,158 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
     return AGIS_OK;
 }
 
+// Offsets in the context's small device buffer of the launch's start clock
+// and of the fault flag of a run to epsilon in one launch.
+constexpr uint32_t kClockOffset = 520;
+constexpr uint32_t kFaultOffset = 528;
+
+// Runs every pattern to epsilon (or its budget) in one persistent launch
+// (k_sample_eps): the checks, merges and stops happen on the device at the
+// same check points, over the same reduction tiles, as run_rounds'.  The
+// caller's cancel flag is polled while the launch runs and forwarded to a
+// pinned host flag that the kernel reads (a copy to device memory could not
+// start while the persistent kernel holds the compute units).
+int run_device_eps(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::vector<PatternRun>& runs,
+                   const agis_run_params* pp, uint64_t seed, bool* cancelled) {
+    *cancelled = false;
+    const uint64_t check = pp->check_every ? pp->check_every : 65536;
+    const double z = normal_quantile(1.0 - pp->delta / 2.0);
+    const uint32_t npat = (uint32_t)runs.size();
+    std::vector<DevPlan> plans(npat);
+    uint64_t total = 0;
+    for (uint32_t p = 0; p < npat; ++p) {
+        plans[p] = runs[p].prep.hp;
+        total += runs[p].budget;
+    }
+    AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_plans, plans.data(), npat * sizeof(DevPlan), hipMemcpyHostToDevice, ctx->stream),
+             "upload plans");
+    if (total == 0) return AGIS_OK;
+    agis::SampleLaunch L;
+    for (const PatternRun& r : runs) L.pairs = L.pairs || uses_pair_hubs(r.prep.hp, t);
+    int rc = agis::plan_sample_launch(ctx, *g, std::min<uint64_t>(total, kMaxRoundSlots), npat, &L, &ctx->err);
+    if (rc != AGIS_OK) return rc;
+    // ring: the window of slots ahead of the merged prefix, plus two tiles
+    const uint64_t window = std::max<uint64_t>(2 * check, 1ull << 16);
+    uint64_t ring = agis::kEpsTile;
+    while (ring < window + 2 * agis::kEpsTile) ring <<= 1;
+    const uint64_t rtiles = ring / agis::kEpsTile;
+    const size_t pat_bytes = npat * sizeof(agis::EpsPattern);
+    const size_t ring_bytes = (size_t)npat * ring * sizeof(double);
+    const size_t part_bytes = (size_t)npat * rtiles * sizeof(Partial);
+    const size_t ready_bytes = (size_t)npat * rtiles * sizeof(unsigned long long);
+    const size_t done_bytes = (size_t)npat * rtiles * sizeof(uint32_t);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t need = up(pat_bytes) + up(ring_bytes) + up(part_bytes) + up(ready_bytes) + up(done_bytes);
+    if (ctx->eps_bytes < need) {
+        if (ctx->d_eps) (void)hipFree(ctx->d_eps);
+        ctx->d_eps = nullptr;
+        ctx->eps_bytes = 0;
+        AGIS_HIP(ctx, hipMalloc(&ctx->d_eps, need), "allocate run-to-eps buffers");
+        ctx->eps_bytes = need;
+    }
+    char* base = (char*)ctx->d_eps;
+    agis::EpsPattern* d_pat = (agis::EpsPattern*)base;
+    double* d_ring = (double*)(base + up(pat_bytes));
+    Partial* d_part = (Partial*)((char*)d_ring + up(ring_bytes));
+    unsigned long long* d_ready = (unsigned long long*)((char*)d_part + up(part_bytes));
+    uint32_t* d_done = (uint32_t*)((char*)d_ready + up(ready_bytes));
+    std::vector<agis::EpsPattern> hp(npat);
+    std::memset(hp.data(), 0, pat_bytes);
+    for (uint32_t p = 0; p < npat; ++p) {
+        hp[p].budget = runs[p].budget;
+        hp[p].start = pp->first_sample;
+        hp[p].check = check;
+        hp[p].min_samples = pp->min_samples;
+        hp[p].plan = p;
+        hp[p].stop = runs[p].budget == 0 ? 1u : 0u;
+    }
+    AGIS_HIP(ctx, hipMemcpyAsync(d_pat, hp.data(), pat_bytes, hipMemcpyHostToDevice, ctx->stream), "upload states");
+    // counters and ready marks start at zero (fill kernels, not memsets: the
+    // sequence could be captured)
+    AGIS_HIP(ctx, agis::launch_fill_u32(d_done, npat * rtiles, 0u, ctx->stream), "clear tile counters");
+    AGIS_HIP(ctx, agis::launch_fill_u32((uint32_t*)d_ready, 2 * npat * rtiles, 0u, ctx->stream), "clear tile marks");
+    *ctx->h_cancel = 0;
+    unsigned long long* d_clock = (unsigned long long*)((char*)ctx->d_small + kClockOffset);
+    uint32_t* d_fault = (uint32_t*)((char*)ctx->d_small + kFaultOffset);
+    AGIS_HIP(ctx, agis::launch_fill_u32(d_fault, 1, 0u, ctx->stream), "clear fault flag");
+    agis::LaunchDesc ld;
+    std::memset(&ld, 0, sizeof(ld));
+    agis::fill_launch(ctx, L, g->g, dev_tables(t), nullptr, nullptr, &ld);
+    ld.round.k0 = (uint32_t)seed;
+    ld.round.k1 = (uint32_t)(seed >> 32);
+    agis::EpsDesc& E = ld.eps;
+    E.pat = agis::gmem(d_pat);
+    E.ring = agis::gmem(d_ring);
+    E.tile_done = agis::gmem(d_done);
+    E.tile_part = agis::gmem(d_part);
+    E.tile_ready = agis::gmem(d_ready);
+    E.cancel = (const volatile uint32_t*)ctx->d_cancel;
+    E.fault = agis::gmem(d_fault);
+    E.clock0 = agis::gmem(d_clock);
+    E.ring_samples = ring;
+    E.window = window;
+    E.npat = npat;
+    E.grab = L.grab;
+    E.z = z;
+    E.eps = pp->eps;
+    AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_launch, &ld, sizeof(ld), hipMemcpyHostToDevice, ctx->stream), "upload launch");
+    const auto t0 = std::chrono::steady_clock::now();
+    AGIS_HIP(ctx, hipEventRecord(ctx->ev_start, ctx->stream), "record event");
+    const agis::LaunchDesc* desc = ctx->d_launch;
+    void* args[] = {(void*)&desc};
+    AGIS_HIP(ctx, hipLaunchKernel(agis::sample_eps_kernel(L.variant, L.pairs), dim3((unsigned)L.blocks),
+                                  dim3((unsigned)L.threads), args, 0, ctx->stream),
+             "launch run-to-eps sampler");
+    AGIS_HIP(ctx, hipEventRecord(ctx->ev_stop, ctx->stream), "record event");
+    if (pp->cancel) {
+        // the caller's flag is forwarded to the pinned flag the kernel reads
+        for (;;) {
+            const hipError_t q = hipEventQuery(ctx->ev_stop);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return hip_fail(ctx, q, "run-to-eps sampler");
+            if (!*cancelled && *pp->cancel) {
+                *ctx->h_cancel = 1;
+                *cancelled = true;
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(100));
+        }
+    }
+    AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "run-to-eps sampler");
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    float ms = 0.0f;
+    AGIS_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop), "event time");
+    unsigned long long clock0 = 0;
+    uint32_t fault = 0;
+    AGIS_HIP(ctx, hipMemcpy(hp.data(), d_pat, pat_bytes, hipMemcpyDeviceToHost), "read states");
+    AGIS_HIP(ctx, hipMemcpy(&clock0, d_clock, sizeof(clock0), hipMemcpyDeviceToHost), "read clock");
+    AGIS_HIP(ctx, hipMemcpy(&fault, d_fault, sizeof(fault), hipMemcpyDeviceToHost), "read fault flag");
+    if (fault) return fail(ctx, AGIS_E_HIP, "run to eps: a wave waited too long for the merge (window wait bound)");
+    *ctx->h_cancel = 0;
+    double handed = 0.0;
+    for (uint32_t p = 0; p < npat; ++p) handed += (double)std::min<uint64_t>(hp[p].next, hp[p].budget);
+    const double tick = 1.0 / (1000.0 * (double)ctx->wall_clock_khz);
+    for (uint32_t p = 0; p < npat; ++p) {
+        PatternRun& r = runs[p];
+        const agis::EpsPattern& s = hp[p];
+        r.acc = Acc();
+        r.acc.merge(s.acc);
+        r.done = s.merged;
+        r.converged = s.converged != 0;
+        r.active = false;
+        r.seconds = (s.stop && s.stop_clock >= clock0) ? (double)(s.stop_clock - clock0) * tick : wall;
+        r.kernel_seconds = handed > 0 ? 1e-3 * (double)ms * (double)std::min<uint64_t>(s.next, s.budget) / handed : 0.0;
+        r.launches = 1;
+    }
+    return AGIS_OK;
+}
+
+// Whether a run goes to epsilon in one persistent launch: runs to epsilon
+// whose checks fall on reduction tiles, unless the caller asks for rounds.
+bool device_eps(const agis_run_params* pp) {
+    const uint64_t check = pp->check_every ? pp->check_every : 65536;
+    return pp->eps > 0 && check % agis::kEpsTile == 0 && !(pp->flags & AGIS_RUN_HOST_ROUNDS);
+}
+
 void fill_result(const PatternRun& r, double z, double extra_seconds, agis_result* out) {
     std::memset(out, 0, sizeof(*out));
     const Acc& acc = r.acc;
@@ -718,6 +873,22 @@ int agis_create(agis_ctx** out, int device, void* hip_stream) {
         else
             (void)hipGetLastError();
     }
+    if (e == hipSuccess) {
+        void* h = nullptr;
+        void* d = nullptr;
+        e = hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) {
+            ctx->h_cancel = (volatile uint32_t*)h;
+            *ctx->h_cancel = 0;
+            e = hipHostGetDevicePointer(&d, h, 0);
+            ctx->d_cancel = (const volatile uint32_t*)d;
+        }
+    }
+    if (e == hipSuccess) {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+            ctx->wall_clock_khz = khz;
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming);
@@ -747,6 +918,8 @@ void agis_destroy(agis_ctx* ctx) {
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
     if (ctx->d_xout) (void)hipFree(ctx->d_xout);
     if (ctx->d_blocksums) (void)hipFree(ctx->d_blocksums);
+    if (ctx->d_eps) (void)hipFree(ctx->d_eps);
+    if (ctx->h_cancel) (void)hipHostFree((void*)ctx->h_cancel);
     if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
     if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
     delete ctx;
@@ -975,7 +1148,8 @@ int agis_estimate(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, cons
     runs[0].budget = n_samples;
     const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool cancelled = false;
-    rc = run_rounds(ctx, g, t, runs, pp, seed, &cancelled);
+    rc = device_eps(pp) ? run_device_eps(ctx, g, t, runs, pp, seed, &cancelled)
+                        : run_rounds(ctx, g, t, runs, pp, seed, &cancelled);
     if (rc != AGIS_OK) return rc;
     const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
     fill_result(runs[0], z, setup, out);
@@ -1046,7 +1220,8 @@ int agis_estimate_batch(agis_ctx* ctx, const agis_graph* g, const agis_tables* t
     }
     const double setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool cancelled = false;
-    rc = run_rounds(ctx, g, t, runs, pp, seed, &cancelled);
+    rc = device_eps(pp) ? run_device_eps(ctx, g, t, runs, pp, seed, &cancelled)
+                        : run_rounds(ctx, g, t, runs, pp, seed, &cancelled);
     if (rc != AGIS_OK) return rc;
     const double z = normal_quantile(1.0 - (pp->eps > 0 ? pp->delta : 0.05) / 2.0);
     bool all = true;

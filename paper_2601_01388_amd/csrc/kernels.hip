@@ -1386,6 +1386,16 @@ __global__ __launch_bounds__(kRowtabThreads) void k_rowtab_long(DevGraph g, cons
     }
 }
 
+__global__ void k_fill_u32(uint32_t* a, uint64_t n, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* a, uint64_t n, uint32_t v, hipStream_t stream) {
+    if (n) hipLaunchKernelGGL(k_fill_u32, dim3(stride_grid(n, 256)), dim3(256), 0, stream, a, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_rowtab(agis_ctx* ctx, const DevGraph& g, const int32_t* sw, uint64_t* pre, uint32_t* lists) {
     if (!g.n || !g.nnz) return hipSuccess;
     hipStream_t st = ctx->stream;
@@ -2161,7 +2171,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
 
 }  // namespace
 
+// Chan et al.'s pairwise update, a then b, rounded as written (no fused
+// multiply-adds: the host merges tiles with the same arithmetic).
 __device__ __forceinline__ Partial chan_merge(Partial a, const Partial& b) {
+#pragma clang fp contract(off)
     if (b.n == 0.0) return a;
     if (a.n == 0.0) return b;
     const double n = a.n + b.n;
@@ -2265,12 +2278,30 @@ void k_sample(const LaunchDesc* __restrict__ D) {
     }
 }
 
+// Welford over the (up to) kReducePer weights xs[first ..] below lim, as one
+// thread of the fixed reduction tree.
+constexpr int kReducePer = 8;
+__device__ __forceinline__ Partial welford8(const double* __restrict__ xs, uint64_t first, uint64_t lim) {
+#pragma clang fp contract(off)
+    Partial a{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < kReducePer; ++j) {
+        const uint64_t p = first + j;
+        if (p >= lim) break;
+        const double x = xs[p];
+        a.n += 1.0;
+        const double d = x - a.mean;
+        a.mean += d / a.n;
+        a.m2 += d * (x - a.mean);
+        a.nonzero += x != 0.0 ? 1.0 : 0.0;
+    }
+    return a;
+}
+
 // Estimator statistics of a round's weights in a fixed order: each segment
 // is cut into tiles of kReduceTile consecutive slots; threads run Welford
 // over 8 consecutive weights, then merge pairwise in a fixed tree.  The
 // result depends only on the weights and the segment lengths, not on the
 // launch that produced the weights.
-constexpr int kReducePer = 8;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceTile = kReducePer * kReduceThreads;
 static_assert(kReduceTile == kReduceTileSamples, "tile size");
@@ -2287,17 +2318,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_x(const LaunchDesc* _
     const uint64_t t0 = (uint64_t)(blockIdx.x - S.tile_base) * kReduceTile;
     const uint64_t lim = S.count;
     const uint64_t first = t0 + (uint64_t)threadIdx.x * kReducePer;
-    Partial a{0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j < kReducePer; ++j) {
-        const uint64_t p = first + j;
-        if (p >= lim) break;
-        const double x = xs[S.base + p];
-        a.n += 1.0;
-        const double d = x - a.mean;
-        a.mean += d / a.n;
-        a.m2 += d * (x - a.mean);
-        a.nonzero += x != 0.0 ? 1.0 : 0.0;
-    }
+    Partial a = welford8(xs + S.base, first, lim);
     const int lane = lane_id();
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -2320,6 +2341,251 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_x(const LaunchDesc* _
 
 __global__ void k_zero_queues(unsigned long long* p) {
     if (threadIdx.x < kQueues) p[threadIdx.x * kQueueStride] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Run to epsilon in one persistent launch
+// ---------------------------------------------------------------------------
+// Reads and writes of run state shared by all waves go to memory at device
+// scope (bypassing the caches of the other XCDs).
+__device__ __forceinline__ unsigned long long ld_dev(const AGIS_GMEM unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_dev(const AGIS_GMEM uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(AGIS_GMEM unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(AGIS_GMEM uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Statistics of one tile (len <= kEpsTile weights from xs) by one wave, in
+// the fixed tree of k_reduce_x: 256 "threads" of 8 consecutive weights
+// (lane l plays thread 64 w + l in pass w), a butterfly per 64 threads, the
+// four results merged in order.  Every lane returns the result.
+__device__ __forceinline__ Partial reduce_tile_wave(const AGIS_GMEM double* xs, uint64_t len) {
+    const int lane = lane_id();
+    Partial r{0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < kReduceThreads / kWave; ++w) {
+        const uint64_t first = ((uint64_t)w * kWave + (uint64_t)lane) * kReducePer;
+        Partial a = welford8((const double*)xs, first, len);
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            Partial b;
+            b.n = __shfl_xor(a.n, o, kWave);
+            b.mean = __shfl_xor(a.mean, o, kWave);
+            b.m2 = __shfl_xor(a.m2, o, kWave);
+            b.nonzero = __shfl_xor(a.nonzero, o, kWave);
+            if ((lane & o) == 0) a = chan_merge(a, b);
+        }
+        Partial wp;
+        wp.n = __shfl(a.n, 0, kWave);
+        wp.mean = __shfl(a.mean, 0, kWave);
+        wp.m2 = __shfl(a.m2, 0, kWave);
+        wp.nonzero = __shfl(a.nonzero, 0, kWave);
+        r = w == 0 ? wp : chan_merge(r, wp);
+    }
+    return r;
+}
+
+// Algorithm 1's estimated relative error of the merged statistics.
+__device__ __forceinline__ double eps_hat_dev(const Partial& a, double z) {
+#pragma clang fp contract(off)
+    if (a.n == 0.0 || a.mean == 0.0) return __builtin_huge_val();
+    const double sigma = sqrt(a.m2 > 0 ? a.m2 / a.n : 0.0);
+    return z * sigma / (sqrt(a.n) * fabs(a.mean));
+}
+
+// Merges the ready tiles of pattern p in order (lane 0 does the work; the
+// call is made by the whole wave).  One wave at a time holds the merge
+// token; a wave that finds it taken leaves, and the holder looks for newly
+// ready tiles again after giving it up, so no ready tile is left behind and
+// no wave ever waits for another.  At every check point (a multiple of
+// check samples, or the budget) Algorithm 1 decides whether to stop; once a
+// pattern has stopped (converged, budget, cancel or a fault) nothing more is
+// merged into it.
+__device__ void merge_ready(const EpsDesc& E, uint32_t p) {
+    if (lane_id() != 0) return;
+    AGIS_GMEM EpsPattern* P = E.pat + p;
+    const uint64_t rtiles = E.ring_samples / kEpsTile;
+    for (;;) {
+        // A full fence before looking: the wave that just published a tile
+        // (and fails to take the token) and the holder that just gave the
+        // token up (and looks again) cannot both miss each other.
+        __threadfence();
+        uint64_t m = ld_dev(&P->merged);
+        uint64_t tm = m / kEpsTile;
+        if (ld_dev(&P->stop)) return;
+        if (ld_dev(E.tile_ready + (uint64_t)p * rtiles + (tm & (rtiles - 1))) != tm + 1) return;
+        if (atomicCAS(&P->owner, 0u, 1u) != 0u) return;
+        __threadfence();
+        Partial acc = P->acc;
+        const uint64_t budget = P->budget, check = P->check;
+        bool stopped = false;
+        for (;;) {
+            // the stop is looked at again under the token: the previous
+            // holder may have stopped the pattern after this wave's first
+            // look, and tiles past the stopping point (samples already
+            // handed out) must not be merged
+            if (ld_dev(&P->stop)) {
+                stopped = true;
+                break;
+            }
+            m = ld_dev(&P->merged);
+            tm = m / kEpsTile;
+            const uint64_t slot = (uint64_t)p * rtiles + (tm & (rtiles - 1));
+            if (m >= budget || ld_dev(E.tile_ready + slot) != tm + 1) break;
+            __threadfence();
+            const Partial b = E.tile_part[slot];
+            acc = chan_merge(acc, b);
+            const uint64_t len = (budget - m) < kEpsTile ? (budget - m) : kEpsTile;
+            m += len;
+            P->acc = acc;
+            __threadfence();
+            st_dev(&P->merged, m);
+            if (m % check == 0 || m == budget) {
+                const bool conv = m >= P->min_samples && eps_hat_dev(acc, E.z) <= E.eps;
+                if (conv || m == budget) {
+                    if (conv) st_dev(&P->converged, 1u);
+                    P->stop_clock = wall_clock64();
+                    __threadfence();
+                    st_dev(&P->stop, 1u);
+                    stopped = true;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        atomicExch(&P->owner, 0u);
+        if (stopped) return;
+    }
+}
+
+// Persistent sampler for runs to epsilon: the slots of all patterns are
+// handed out from per-pattern counters, round robin over the patterns that
+// still run, never beyond merged + window (a wave holding such a slot waits
+// for the merge: the wave holding the lowest unfinished slot never waits,
+// so the merge always advances).  A sample's weight goes to the pattern's
+// ring; the wave that completes a tile reduces it and merges what is ready.
+// Samples handed out beyond a pattern's stopping point are dropped.  The
+// waves leave once every pattern has stopped or handed out its budget; the
+// host's cancel flag stops every pattern at its merged prefix.
+constexpr uint32_t kWindowSpins = 1u << 22;
+
+template <int kWavesPerEU, bool kPairs>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU)))
+void k_sample_eps(const LaunchDesc* __restrict__ D) {
+    const int lane = lane_id();
+    for (uint32_t e = threadIdx.x; e < 4096u; e += blockDim.x) s_exp2tab[e] = c_exp2tab[e];
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *D->eps.clock0 = wall_clock64();
+    const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x / kWave) + uniform_u32(threadIdx.x / kWave);
+    const uint64_t cap = D->cap;
+    uint32_t* sv = D->scratch + gw * cap * 2;
+    int32_t* sl = (int32_t*)(sv + cap);
+    const DevGraph g = D->g;
+    const DevTables t = D->t;
+    const uint32_t hub_window = D->hub_window;
+    const EpsDesc& E = D->eps;
+    const uint32_t npat = E.npat;
+    const uint64_t rmask = E.ring_samples - 1, rtiles = E.ring_samples / kEpsTile;
+    const uint32_t grab = E.grab;
+    uint32_t cur = (uint32_t)(gw % npat);
+    uint32_t rounds = 0;
+    for (;;) {
+        // the next pattern from cur on that still hands out samples
+        uint32_t p = 0xFFFFFFFFu;
+        for (uint32_t k = 0; k < npat; ++k) {
+            const uint32_t q = cur + k < npat ? cur + k : cur + k - npat;
+            if (!ld_dev(&E.pat[q].stop) && ld_dev(&E.pat[q].next) < E.pat[q].budget) {
+                p = q;
+                break;
+            }
+        }
+        p = uniform_u32(p);
+        if (p == 0xFFFFFFFFu) break;
+        cur = p + 1 < npat ? p + 1 : 0;
+        if ((++rounds & 15u) == 0 &&
+            uniform_u32(__hip_atomic_load(E.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
+            for (uint32_t q = (uint32_t)lane; q < npat; q += kWave) st_dev(&E.pat[q].stop, 1u);
+            break;
+        }
+        AGIS_GMEM EpsPattern* P = E.pat + p;
+        unsigned long long s0 = 0;
+        if (lane == 0) s0 = atomicAdd(&P->next, (unsigned long long)grab);
+        s0 = uniform_u64(s0);
+        const uint64_t budget = P->budget;
+        for (uint64_t j = s0; j < s0 + grab && j < budget; ++j) {
+            // wait until the slot is inside the window (or the pattern
+            // stops); the wait is bounded all the same: past kWindowSpins
+            // the wave reports a fault, stops every pattern and leaves
+            bool live = true;
+            uint32_t spins = 0;
+            for (;;) {
+                if (ld_dev(&P->stop)) {
+                    live = false;
+                    break;
+                }
+                if (j < ld_dev(&P->merged) + E.window) break;
+                if (++spins > kWindowSpins) {
+                    live = false;
+                    if (lane == 0) {
+                        st_dev(E.fault, 1u);
+                        for (uint32_t q = 0; q < npat; ++q) st_dev(&E.pat[q].stop, 1u);
+                    }
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            if (!uniform_u32(live ? 1u : 0u)) break;
+            NoMeter mt;
+            const double xv = sample_one<false, kPairs>(g, t, D->plans + P->plan, D->round.k0, D->round.k1,
+                                                         P->start + j, sv, sl, nullptr, hub_window, mt);
+            const uint64_t tile = j / kEpsTile;
+            const uint64_t slot = (uint64_t)p * rtiles + (tile & (rtiles - 1));
+            uint32_t last = 0;
+            if (lane == 0) {
+                E.ring[(uint64_t)p * E.ring_samples + (j & rmask)] = xv;
+                __threadfence();
+                const uint64_t rem = budget - tile * kEpsTile;
+                const uint32_t len = (uint32_t)(rem < kEpsTile ? rem : kEpsTile);
+                last = atomicAdd(E.tile_done + slot, 1u) + 1u == len ? 1u : 0u;
+            }
+            if (uniform_u32(last)) {
+                __threadfence();
+                const uint64_t rem = budget - tile * kEpsTile;
+                const uint64_t len = rem < kEpsTile ? rem : kEpsTile;
+                const Partial part =
+                    reduce_tile_wave(E.ring + (uint64_t)p * E.ring_samples + ((tile * kEpsTile) & rmask), len);
+                if (lane == 0) {
+                    E.tile_done[slot] = 0u;
+                    E.tile_part[slot] = part;
+                    __threadfence();
+                    __hip_atomic_store(E.tile_ready + slot, (unsigned long long)(tile + 1), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+                merge_ready(E, p);
+            }
+        }
+    }
+}
+
+template <int kW, bool kPairs>
+const void* sample_eps_kernel_of() {
+    return reinterpret_cast<const void*>(k_sample_eps<kW, kPairs>);
+}
+
+const void* sample_eps_kernel(int variant, bool pairs) {
+    switch (variant) {
+        case 1:
+            return pairs ? sample_eps_kernel_of<7, true>() : sample_eps_kernel_of<7, false>();
+        case 2:
+            return pairs ? sample_eps_kernel_of<8, true>() : sample_eps_kernel_of<8, false>();
+        default:
+            return pairs ? sample_eps_kernel_of<6, true>() : sample_eps_kernel_of<6, false>();
+    }
 }
 
 template <int kW, bool kPairs>

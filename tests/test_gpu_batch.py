@@ -147,3 +147,75 @@ def test_batch_random_patterns_rmat_scale_small(sess):
         _same(res[i], single)
     assert all(r.n == b for r, b in zip(res, budgets))
     assert all(math.isfinite(r.estimate) for r in res)
+
+
+@pytest.mark.parametrize("check", [2048, 1 << 14, 1 << 16])
+def test_one_launch_run_to_eps_equals_host_rounds(sess, c1_state, check):
+    """The persistent run to epsilon (checks, merges and stops on the device)
+    stops every pattern at the same sample count as the round-by-round run
+    with the checks on the host, with the same estimates; budgets that are
+    not multiples of the reduction tile, and minimums between checks."""
+    g, G, T, _ = c1_state
+    pats = _pats()
+    rng = np.random.Generator(np.random.PCG64(check))
+    budgets = [int(x) for x in np.round(10 ** rng.uniform(3.5, 6.3, size=len(pats)))]
+    kw = dict(mode="switch", eps=0.02, delta=0.05, check_every=check, min_samples=3 * check // 2)
+    say(f"one launch vs rounds, check {check}")
+    dev = sess.estimate_batch(G, T, pats, budgets, 21, **kw)
+    host = sess.estimate_batch(G, T, pats, budgets, 21, host_rounds=True, **kw)
+    assert any(r.converged for r in dev) and any(not r.converged for r in dev)
+    for a, b, bud in zip(dev, host, budgets):
+        _same(a, b, rel=1e-12)
+        assert a.n <= bud
+    for p, bud, a in list(zip(pats, budgets, dev))[:4]:
+        single = sess.estimate(G, T, p, bud, 21, pattern_id=pats.index(p), **kw)
+        _same(single, a, rel=1e-12)
+
+
+def test_one_launch_batch_of_many_patterns_converges(sess, c1_state):
+    """64 patterns at once, all to +-2%: every stop point equals the host
+    rounds' (the window and ring hold 64 patterns)."""
+    g, G, T, _ = c1_state
+    pats = [p for p, _ in synth.random_pattern_set(58, seed=9, kmin=3, kmax=6)] + _pats()[:6]
+    budgets = [1 << 22] * len(pats)
+    kw = dict(mode="switch", eps=0.02, delta=0.05, check_every=4096, min_samples=4096)
+    dev = sess.estimate_batch(G, T, pats, budgets, 5, **kw)
+    host = sess.estimate_batch(G, T, pats, budgets, 5, host_rounds=True, **kw)
+    for a, b in zip(dev, host):
+        _same(a, b, rel=1e-12)
+
+
+def test_batch_learned_equals_single_learned(sess, c1_state):
+    """Learned tables per pattern in one batch (batch_learned) give each
+    pattern the samples of its single learned estimate."""
+    import torch
+    g, G, T, OT = c1_state
+    names = ["house", "5-cycle", "4-clique"]
+    pats = [synth.named_pattern(n) for n in names]
+    rng = np.random.Generator(np.random.PCG64(17))
+    tabs_all, ptrs_all = [], []
+    for p in pats:
+        base = sess.step_log_weights(T, p).cpu().numpy()
+        tabs = {}
+        for i in sess.weighted_steps(p, "learned"):
+            t = base[i].astype(np.int64) + rng.integers(-2 << 16, 2 << 16, size=base.shape[1])
+            t = np.where(base[i] == np.iinfo(np.int32).min, np.iinfo(np.int32).min, t).astype(np.int32)
+            tabs[i] = torch.from_numpy(t).to(sess.device)
+        tabs_all.append(tabs)
+        ptrs_all.append({i: tab.data_ptr() for i, tab in tabs.items()})
+    arr = A.batch_learned_array(ptrs_all)
+    budgets = [300_000, 200_000, 250_000]
+    for eps in (0.0, 0.02):
+        kw = dict(mode="learned", eps=eps, delta=0.05, check_every=1 << 14, min_samples=1 << 14)
+        res = sess.estimate_batch(G, T, pats, budgets, 33, batch_learned=arr, **kw)
+        for pid, (p, b, r) in enumerate(zip(pats, budgets, res)):
+            single = sess.estimate(G, T, p, b, 33, learned=ptrs_all[pid], pattern_id=pid, **kw)
+            _same(r, single, rel=1e-12)
+    # and the samples are the oracle's
+    idx = np.arange(2000, dtype=np.uint64)
+    for pid, p in enumerate(pats):
+        got = sess.dump(G, T, p, 33, idx, mode="learned", learned=ptrs_all[pid], pattern_id=pid)
+        ref = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="learned"), seed=33, pattern_id=pid,
+                             learned={i: t.cpu().numpy() for i, t in tabs_all[pid].items()}).records(idx)
+        for f in ("v", "num", "den", "x", "steps", "fail_step"):
+            assert np.array_equal(got[f], ref[f]), (p.name, f)

@@ -146,9 +146,10 @@ def test_cancel_before_start_returns_empty_partial(sess, c1g):
 
 
 def test_cancel_mid_run_keeps_a_consistent_prefix(sess, c1g):
-    """A flag raised while a long run-to-eps is in flight stops it between
-    rounds; the partial result is the estimate of a prefix of the sample
-    sequence (the same as a fixed run of that many samples)."""
+    """A flag raised while a long run-to-eps is in flight stops it; the
+    partial result is the estimate of a prefix of the sample sequence made
+    of whole reduction tiles of 2048 (the same as a fixed run of that many
+    samples), in the one-launch run and in the round-by-round run."""
     g, G, T = c1g
     p = synth.named_pattern("4-clique")
     flag = ctypes.c_int32(0)
@@ -157,15 +158,17 @@ def test_cancel_mid_run_keeps_a_consistent_prefix(sess, c1g):
         time.sleep(0.3)
         flag.value = 1
 
-    th = threading.Thread(target=raise_flag)
-    th.start()
-    # eps far below reach: only the flag (or the large budget) ends the run
-    budget = 1 << 32
-    r = sess.estimate(G, T, p, budget, 7, mode="uniform", eps=1e-9, delta=0.05, check_every=1 << 16,
-                      min_samples=1 << 16, cancel=flag)
-    th.join()
-    say(f"cancelled after {r.n} samples")
-    assert r.status == A.AGIS_E_CANCELLED
-    assert 0 < r.n < budget and r.n % (1 << 16) == 0
-    ref = sess.estimate(G, T, p, r.n, 7, mode="uniform")
-    assert abs(r.estimate - ref.estimate) <= 1e-9 * abs(ref.estimate)
+    for host_rounds in (False, True):
+        flag.value = 0
+        th = threading.Thread(target=raise_flag)
+        th.start()
+        # eps far below reach: only the flag (or the large budget) ends the run
+        budget = 1 << 32
+        r = sess.estimate(G, T, p, budget, 7, mode="uniform", eps=1e-9, delta=0.05, check_every=1 << 16,
+                          min_samples=1 << 16, cancel=flag, host_rounds=host_rounds)
+        th.join()
+        say(f"cancelled after {r.n} samples (host rounds {host_rounds})")
+        assert r.status == A.AGIS_E_CANCELLED
+        assert 0 < r.n < budget and r.n % 2048 == 0
+        ref = sess.estimate(G, T, p, r.n, 7, mode="uniform")
+        assert abs(r.estimate - ref.estimate) <= 1e-9 * abs(ref.estimate)
