@@ -168,6 +168,17 @@ def tune_batch(args, sess, G, T, pats, log):
     return {"variant": tb.variant, "grab": tb.grab, "hub_window": tb.hub_window, "pilot_samples": args.batch_tune_pilot}
 
 
+def is_star(p) -> bool:
+    """A star: its steps after the centre are uniform draws from the centre's
+    row under switching, which the library runs one sample per lane
+    (k_sample_lanes)."""
+    deg = [0] * p.k
+    for a, b in p.edges:
+        deg[a] += 1
+        deg[b] += 1
+    return p.k >= 2 and len(p.edges) == p.k - 1 and max(deg) == p.k - 1
+
+
 def is_clique(p) -> bool:
     return len(p.edges) == p.k * (p.k - 1) // 2
 
@@ -937,6 +948,8 @@ def main():
     kern_total = 0.0
     launches_total = 0
     hbm_total = 0.0
+    # the lane sampler's launches (stars) are a kernel of their own
+    lanes = {"bytes": 0.0, "kernel_s": 0.0, "launches": 0, "hbm": 0.0, "patterns": []}
     counters = None
     if os.path.exists(COUNTERS_FILE):
         c = json.load(open(COUNTERS_FILE))
@@ -954,16 +967,27 @@ def main():
                        "achieved_gbs": (rb + wb) * nsamp / e["kernel_s"] / 1e9,
                        "segment_gbs": 64.0 * segs * nsamp / e["kernel_s"] / 1e9,
                        "merge_model_gbs": mm * nsamp / e["kernel_s"] / 1e9}
+        meter[name]["kernel"] = "k_sample_lanes" if is_star(p) else "k_sample"
+        hb = None
+        if counters and name in counters.get("per_pattern", {}):
+            hb = counters["per_pattern"][name]["hbm_bytes_per_sample"]
+            meter[name]["traffic_gbs"] = hb * nsamp / e["kernel_s"] / 1e9
+        if is_star(p):
+            lanes["bytes"] += (rb + wb) * nsamp
+            lanes["kernel_s"] += e["kernel_s"]
+            lanes["launches"] += e["launches"]
+            lanes["hbm"] += (hb or 0.0) * nsamp
+            lanes["patterns"].append(name)
+            continue
         bytes_total += (rb + wb) * nsamp
         merge_total += mm * nsamp
         kern_total += e["kernel_s"]
         launches_total += e["launches"]
-        if counters and name in counters.get("per_pattern", {}):
-            hb = counters["per_pattern"][name]["hbm_bytes_per_sample"]
-            meter[name]["traffic_gbs"] = hb * nsamp / e["kernel_s"] / 1e9
+        if hb is not None:
             hbm_total += hb * nsamp
     achieved = bytes_total / kern_total / 1e9
-    seg_total = sum(meter[nm]["segments_per_sample"] * per_pattern[nm]["samples"] for nm in PATTERNS)
+    seg_total = sum(meter[nm]["segments_per_sample"] * per_pattern[nm]["samples"] for nm in PATTERNS
+                    if meter[nm]["kernel"] == "k_sample")
     bytes_per_segment = bytes_total / max(seg_total, 1.0)
     gather = None
     frac_gather = None
@@ -1009,7 +1033,15 @@ def main():
         "merge_model_gbs": merge_total / kern_total / 1e9,
         "traffic_gbs": hbm_total / kern_total / 1e9 if counters else None,
         "traffic_source": os.path.relpath(COUNTERS_FILE, ROOT) if counters else None,
+        "patterns": [nm for nm in PATTERNS if meter[nm]["kernel"] == "k_sample"],
     }
+    if lanes["launches"]:
+        la = lanes["bytes"] / lanes["kernel_s"] / 1e9
+        roofline["lanes"] = {
+            "kernel": "k_sample_lanes", "patterns": lanes["patterns"], "achieved": la, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": la / HBM_PEAK_GBS, "avg_launch_ms": 1e3 * lanes["kernel_s"] / lanes["launches"],
+            "algorithmic_bytes_per_launch": lanes["bytes"] / lanes["launches"],
+            "traffic": (lanes["hbm"] / lanes["launches"]) if counters and lanes["hbm"] else None}
     log(f"roofline: {achieved:.0f} GB/s of request bytes ({roofline['frac']:.3f} of HBM peak"
         + (f"; {frac_gather:.2f}x the {s_match}-B dependent-gather ceiling over {footprint}"
            if frac_gather else "") + ")"
@@ -1097,6 +1129,9 @@ def main():
                                               "traffic_frac_of_gather_peak", "gather_ceiling_footprint",
                                               "merge_model_gbs", "traffic_source")},
     }
+    if "lanes" in roofline:
+        out["roofline"]["lanes"] = {k: roofline["lanes"][k] for k in ("kernel", "patterns", "achieved", "frac",
+                                                                       "avg_launch_ms", "traffic")}
     if eps_table:
         out["time_to_1pct_s"] = {
             name: {lab: round(eps_table[f"{name}/{lab}"]["seconds"], 5)

@@ -124,6 +124,11 @@ typedef struct {
  *   AGIS_RUN_HOST_ROUNDS asks for one launch per round of check_every
  *   samples with the checks on the host instead.  Both stop at the same
  *   sample counts and give the same results (to relative 1e-9).
+ *   Plans whose steps after the first are all uniform draws from the row of
+ *   one matched vertex (stars under switching, trees under f_uniform) run
+ *   one sample per lane in fixed-budget runs, records and round-by-round
+ *   runs; AGIS_RUN_WAVE_SAMPLES keeps them on the one-wave-per-sample
+ *   sampler.  The samples are the same either way.
  * terms: which factors of f_approx (Eq. probability_function) enter the
  *   weights -- AGIS_TERMS_ALL (T[F1] T[I1] T[F2], the method), or the
  *   incremental versions of the paper's analysis of the approximation
@@ -152,6 +157,7 @@ typedef struct {
 #define AGIS_RUN_STEP1_BLOCKS 4u
 #define AGIS_RUN_STEP1_FULL 8u
 #define AGIS_RUN_HOST_ROUNDS 16u
+#define AGIS_RUN_WAVE_SAMPLES 32u
 #define AGIS_TERMS_ALL 0u
 #define AGIS_TERMS_F1 1u
 #define AGIS_TERMS_F1_I1 2u

@@ -46,6 +46,7 @@ ROWTAB_BY_NAME = {"auto": 0, "on": 1, "off": 2}
 AGIS_RUN_STEP1_BLOCKS = 4
 AGIS_RUN_STEP1_FULL = 8
 AGIS_RUN_HOST_ROUNDS = 16
+AGIS_RUN_WAVE_SAMPLES = 32
 STEP1_BY_NAME = {"auto": 0, "blocks": AGIS_RUN_STEP1_BLOCKS, "full": AGIS_RUN_STEP1_FULL}
 AGIS_TERMS_ALL = 0
 AGIS_TERMS_F1 = 1
@@ -249,7 +250,7 @@ def make_pattern(k: int, adj) -> agis_pattern:
 
 def make_params(mode="switch", beta=(4, 5), pattern_id=0, eps=0.0, delta=0.05, check_every=0, min_samples=0,
                 learned=None, rowtab="auto", terms="all", first_sample=0, cancel=None,
-                batch_learned=None, step1="auto", host_rounds=False) -> agis_run_params:
+                batch_learned=None, step1="auto", host_rounds=False, wave_samples=False) -> agis_run_params:
     """Run parameters.  cancel: a ctypes.c_int32 the caller may set while the
     call runs (kept alive by the caller); batch_learned: a ctypes array of
     n_patterns * MAX_K table pointers (kept alive by the caller)."""
@@ -258,6 +259,8 @@ def make_params(mode="switch", beta=(4, 5), pattern_id=0, eps=0.0, delta=0.05, c
     pr.flags = (ROWTAB_BY_NAME[rowtab] if isinstance(rowtab, str) else int(rowtab)) | STEP1_BY_NAME[step1]
     if host_rounds:
         pr.flags |= AGIS_RUN_HOST_ROUNDS
+    if wave_samples:
+        pr.flags |= AGIS_RUN_WAVE_SAMPLES
     pr.terms = TERMS_BY_NAME[terms] if isinstance(terms, str) else int(terms)
     pr.beta_num, pr.beta_den = beta
     pr.pattern_id = pattern_id

@@ -210,6 +210,9 @@ constexpr uint32_t kMaxSegs = 64;
 // entries (256 bytes) apart, from byte kQueueOffset of the context's small
 // device buffer; kNoSlot marks an empty part.
 constexpr uint32_t kQueues = 8;
+// XCDs of the device (MI355X: 8, each with its own L2); workgroups are dealt
+// to them round robin by workgroup index
+constexpr uint32_t kXcds = 8;
 constexpr uint32_t kQueueStride = 32;
 constexpr uint32_t kQueueOffset = 2048;
 constexpr uint64_t kNoSlot = ~0ull;
@@ -249,6 +252,11 @@ constexpr uint64_t kEpsTile = 2048;
 // Device state of one pattern of a run to epsilon in one persistent
 // launch (the host fills the first block and zeroes the rest).
 struct EpsPattern {
+    // its own 128-byte line: the slot counter every wave takes grabs from
+    // (kept apart from the state the waves poll, so the atomics and the
+    // polls do not queue behind each other at one address)
+    unsigned long long next;  // next sample slot to hand out (relative to start)
+    uint64_t pad_next[15];
     uint64_t budget;       // samples at most
     uint64_t start;        // index of the first sample
     uint64_t check;        // samples between checks (a multiple of kEpsTile)
@@ -256,7 +264,6 @@ struct EpsPattern {
     uint32_t plan;
     uint32_t pad0;
     // run state
-    unsigned long long next;    // next sample slot to hand out (relative to start)
     unsigned long long merged;  // samples whose tiles are merged, in order
     uint32_t stop;              // 1: no more samples (converged, budget reached or cancelled)
     uint32_t owner;             // merge token: 1 while a wave merges
@@ -264,7 +271,9 @@ struct EpsPattern {
     uint32_t pad1;
     Partial acc;                       // statistics of the merged samples
     unsigned long long stop_clock;     // wall clock when the pattern stopped
+    uint64_t pad_state[3];
 };
+static_assert(sizeof(EpsPattern) == 256, "two 128-byte lines per pattern");
 
 // The buffers of a run to epsilon in one launch: per pattern a ring of
 // ring_samples weights and ring_samples / kEpsTile tiles (completed-sample
@@ -282,7 +291,7 @@ struct EpsDesc {
     uint64_t ring_samples;  // a power of two, a multiple of kEpsTile
     uint64_t window;
     uint32_t npat;
-    uint32_t grab;
+    uint32_t grab;          // slots per take from a pattern's counter
     double z;
     double eps;
 };

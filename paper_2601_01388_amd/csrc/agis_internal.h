@@ -27,6 +27,7 @@ struct agis_ctx {
     agis::DevPlan* d_plans = nullptr;    // kMaxSegs plans
     agis::LaunchDesc* d_launch = nullptr;  // the current round
     int sample_blocks_per_cu[6] = {0, 0, 0, 0, 0, 0};  // resident blocks per CU of each kernel (variant, pairs)
+    int lanes_blocks_per_cu = 0;                       // the same for the lane sampler
     // launch tuning (0 = default): resident blocks per CU, slots per grab
     int tune_blocks_per_cu = 0;
     uint32_t tune_grab = 0;
@@ -66,8 +67,11 @@ struct agis_graph {
     uint32_t* own_nbr = nullptr;
 };
 
+struct TableCache;  // proposal tables of f_approx kept across calls (csrc/api.hip)
+
 struct agis_tables {
     agis_ctx* ctx = nullptr;
+    TableCache* cache = nullptr;
     const agis_graph* graph = nullptr;
     uint4* rec = nullptr;      // {deg, LA, LC, 0}
     uint64_t* s2 = nullptr;
@@ -213,6 +217,9 @@ struct SampleLaunch {
     // plan_sample_launch: some plan has an unweighted step over exactly two
     // backward lists and the tables hold the pair-hub table)
     bool pairs = false;
+    // the lane sampler (one sample per lane; set by the caller before
+    // plan_sample_launch when every plan of the launch is a lane plan)
+    bool lanes = false;
     // buffers of the launch (set by plan_sample_launch): the waves' scratch,
     // the per-slot weights and the reduction tiles
     void* scratch = nullptr;
@@ -223,6 +230,12 @@ struct SampleLaunch {
 // The sampling kernel for (record-writing?, register-budget variant 0..2,
 // pair-hub paths?).
 const void* sample_kernel(bool dump, int variant, bool pairs, bool meter);
+// The lane sampler for (record-writing?, metering?).
+const void* sample_lanes_kernel(bool dump, bool meter);
+// Whether the lane sampler serves a plan: every step after the first is a
+// uniform draw from the row of one backward vertex, and a weighted first
+// step is held in the full table (not blocked).
+bool lane_plan(const DevPlan& hp);
 // The persistent run-to-epsilon sampler for (register-budget variant, pair-hub paths?).
 const void* sample_eps_kernel(int variant, bool pairs);
 

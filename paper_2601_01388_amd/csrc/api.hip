@@ -135,6 +135,94 @@ struct Prepared {
     }
 };
 
+// Proposal tables of f_approx kept with the graph's tables across calls:
+// the per-vertex step weights, the per-row pick tables and the first-step
+// table depend only on the vertex records and the step's signature (b, f1,
+// ie, f2), so the next estimate of the same signature reuses them.  (Tables
+// built from a caller's learned weights are not kept: the caller may change
+// them between calls.)  Entries in use by a running call are never evicted;
+// others go least recently used first when a new one would pass the budget
+// or an allocation fails.  One lock serialises the calls that prepare
+// tables of one graph.
+}  // namespace
+
+enum CacheKind : uint32_t { kCacheStepWeights = 0, kCacheRowPick = 1, kCacheFirstStep = 2 };
+struct CacheEntry {
+    uint32_t kind = 0, b = 0, f1 = 0, ie = 0, f2 = 0, blocked = 0;
+    void* buf[3] = {nullptr, nullptr, nullptr};
+    uint64_t bytes = 0;
+    // first step: total weight, guide shift, largest log weight (blocked)
+    uint64_t total = 0;
+    uint32_t shift = 0;
+    int32_t lmax = 0;
+    uint64_t stamp = 0;  // last use
+    uint32_t users = 0;  // calls holding the entry
+};
+constexpr uint64_t kTableCacheBudget = 16ull << 30;
+
+struct TableCache {
+    std::mutex mu;
+    std::vector<CacheEntry*> v;
+    uint64_t bytes = 0, clock = 0;
+    uint32_t* long_rows = nullptr;  // scratch of the row-table builds (2n + 2 entries)
+    ~TableCache() {
+        for (CacheEntry* e : v) {
+            for (void* b : e->buf)
+                if (b) (void)hipFree(b);
+            delete e;
+        }
+        if (long_rows) (void)hipFree(long_rows);
+    }
+    CacheEntry* find(uint32_t kind, uint32_t b, uint32_t f1, uint32_t ie, uint32_t f2, uint32_t blocked) {
+        for (CacheEntry* e : v)
+            if (e->kind == kind && e->b == b && e->f1 == f1 && e->ie == ie && e->f2 == f2 && e->blocked == blocked) {
+                e->stamp = ++clock;
+                ++e->users;
+                return e;
+            }
+        return nullptr;
+    }
+    // frees unused entries, least recently used first, until `need` more
+    // bytes fit in the budget (all unused entries when need is ~0)
+    void evict(uint64_t need) {
+        for (;;) {
+            if (need != ~0ull && bytes + need <= kTableCacheBudget) return;
+            CacheEntry* victim = nullptr;
+            for (CacheEntry* e : v)
+                if (e->users == 0 && (!victim || e->stamp < victim->stamp)) victim = e;
+            if (!victim) return;
+            for (void* b : victim->buf)
+                if (b) (void)hipFree(b);
+            bytes -= victim->bytes;
+            v.erase(std::find(v.begin(), v.end(), victim));
+            delete victim;
+        }
+    }
+    // device memory for a new entry (evicting for room first, and once more
+    // after a failed allocation); nullptr when it does not fit
+    void* alloc(uint64_t nbytes) {
+        evict(nbytes);
+        void* p = nullptr;
+        if (hipMalloc(&p, nbytes) == hipSuccess) return p;
+        (void)hipGetLastError();
+        evict(~0ull);
+        if (hipMalloc(&p, nbytes) == hipSuccess) return p;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    // takes ownership of the buffers of a built entry, held by the caller
+    CacheEntry* add(const CacheEntry& proto) {
+        CacheEntry* e = new CacheEntry(proto);
+        e->stamp = ++clock;
+        e->users = 1;
+        v.push_back(e);
+        bytes += e->bytes;
+        return e;
+    }
+};
+
+namespace {
+
 // Tables shared by the patterns of one call, one per (b, f1, ie, f2,
 // learned table):
 //  - per-vertex log weights of the weighted steps that build candidate
@@ -146,24 +234,34 @@ struct StepTables {
         uint32_t b, f1, ie, f2;
         const int32_t* lt;
         int32_t* buf;
+        bool cached;  // owned by the graph's table cache
     };
     struct RowEntry {
         uint32_t b, f1, ie, f2;
         const int32_t* lt;
         uint64_t* buf;
+        bool cached;
     };
     std::vector<Entry> e;
     std::vector<RowEntry> rows;
     uint32_t* long_rows = nullptr;  // scratch of the row-table build (lists of longer rows)
     agis::Arena* arena = nullptr;   // non-null: buffers are carved from it, never allocated or freed
+    TableCache* cache = nullptr;    // the graph's cache (set by prepare; none with an arena)
+    std::vector<CacheEntry*> held;  // cache entries this call uses
     StepTables() = default;
     StepTables(const StepTables&) = delete;
     StepTables& operator=(const StepTables&) = delete;
     ~StepTables() {
+        if (cache) {
+            std::lock_guard<std::mutex> lk(cache->mu);
+            for (CacheEntry* c : held) --c->users;
+        }
         if (arena) return;
-        for (Entry& x : e) (void)hipFree(x.buf);
-        for (RowEntry& x : rows) (void)hipFree(x.buf);
-        if (long_rows) (void)hipFree(long_rows);
+        for (Entry& x : e)
+            if (!x.cached) (void)hipFree(x.buf);
+        for (RowEntry& x : rows)
+            if (!x.cached) (void)hipFree(x.buf);
+        if (long_rows && !cache) (void)hipFree(long_rows);
     }
 };
 constexpr uint64_t kStepTableBudgetBytes = 16ull << 30;
@@ -330,7 +428,7 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     const uint32_t rowtab = params->flags & 3u;
     const uint32_t step1 = params->flags & (AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL);
     if (rowtab > AGIS_RUN_ROWTAB_OFF ||
-        (params->flags & ~(3u | AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL | AGIS_RUN_HOST_ROUNDS)) ||
+        (params->flags & ~(3u | AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL | AGIS_RUN_HOST_ROUNDS | AGIS_RUN_WAVE_SAMPLES)) ||
         step1 == (AGIS_RUN_STEP1_BLOCKS | AGIS_RUN_STEP1_FULL))
         return fail(ctx, AGIS_E_INVALID_ARG, "unknown run flag");
     if (params->terms > AGIS_TERMS_F1_I1) return fail(ctx, AGIS_E_INVALID_ARG, "unknown term set");
@@ -353,6 +451,14 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         }
     }
     const auto t0 = std::chrono::steady_clock::now();
+    // the graph's table cache (not with a fixed workspace), locked until the
+    // tables of this pattern are built
+    TableCache* cache = (!st->arena && t->cache) ? t->cache : nullptr;
+    std::unique_lock<std::mutex> cache_lock;
+    if (cache) {
+        cache_lock = std::unique_lock<std::mutex>(cache->mu);
+        st->cache = cache;
+    }
     // per-vertex log weights of step i (shared by the call), nullptr beyond
     // the budget
     int step_rc = AGIS_OK;
@@ -360,25 +466,48 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         for (const StepTables::Entry& e : st->e)
             if (e.b == hp.b[i] && e.f1 == hp.f1[i] && e.ie == hp.ie[i] && e.f2 == hp.f2[i] && e.lt == hp.lt[i])
                 return e.buf;
+        const bool keep = cache && hp.lt[i] == nullptr;
+        if (keep) {
+            if (CacheEntry* c = cache->find(kCacheStepWeights, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], 0)) {
+                st->held.push_back(c);
+                st->e.push_back(StepTables::Entry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], nullptr, (int32_t*)c->buf[0], true});
+                return (const int32_t*)c->buf[0];
+            }
+        }
         if ((st->e.size() + 1) * g->g.n * sizeof(int32_t) > kStepTableBudgetBytes) return nullptr;
+        const uint64_t nbytes = g->g.n * sizeof(int32_t);
         int32_t* buf = nullptr;
         hipError_t e = hipSuccess;
         if (st->arena) {
             // no room left in the fixed workspace: the weights come from the records
-            buf = (int32_t*)st->arena->take(g->g.n * sizeof(int32_t));
+            buf = (int32_t*)st->arena->take(nbytes);
             if (!buf) return nullptr;
+        } else if (keep) {
+            buf = (int32_t*)cache->alloc(nbytes);
+            if (!buf) e = hipErrorOutOfMemory;
         } else {
-            e = hipMalloc(&buf, g->g.n * sizeof(int32_t));
+            e = hipMalloc(&buf, nbytes);
         }
-        if (e == hipSuccess) {
-            st->e.push_back(StepTables::Entry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf});
+        if (e == hipSuccess)
             e = agis::launch_step_log_weights(*t, g->g.n, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
                                               ctx->stream);
-        }
         if (e != hipSuccess) {
+            if (buf && !st->arena) (void)hipFree(buf);
             step_rc = fail(ctx, e == hipErrorOutOfMemory ? AGIS_E_OOM : AGIS_E_HIP,
                            std::string("step weight table: ") + hipGetErrorString(e));
             return nullptr;
+        }
+        st->e.push_back(StepTables::Entry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf, keep});
+        if (keep) {
+            CacheEntry proto;
+            proto.kind = kCacheStepWeights;
+            proto.b = hp.b[i];
+            proto.f1 = hp.f1[i];
+            proto.ie = hp.ie[i];
+            proto.f2 = hp.f2[i];
+            proto.buf[0] = buf;
+            proto.bytes = nbytes;
+            st->held.push_back(cache->add(proto));
         }
         return buf;
     };
@@ -390,20 +519,55 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         for (uint32_t i = 1; i < hp.k; ++i) {
             if (!hp.weighted[i] || __builtin_popcount(hp.bmask[i]) != 1) continue;
             const int32_t* lt = (const int32_t*)hp.lt[i];
+            const bool keep = cache && lt == nullptr;
             uint64_t* buf = nullptr;
             for (const StepTables::RowEntry& r : st->rows)
                 if (r.b == hp.b[i] && r.f1 == hp.f1[i] && r.ie == hp.ie[i] && r.f2 == hp.f2[i] && r.lt == lt)
                     buf = r.buf;
+            if (!buf && keep) {
+                if (CacheEntry* c = cache->find(kCacheRowPick, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], 0)) {
+                    st->held.push_back(c);
+                    buf = (uint64_t*)c->buf[0];
+                    st->rows.push_back(StepTables::RowEntry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], nullptr, buf, true});
+                }
+            }
             if (!buf) {
                 if ((st->rows.size() + 1) * g->g.nnz * sizeof(uint64_t) > kRowtabBudgetBytes) continue;
                 const int32_t* sw = step_table(i);
                 if (step_rc != AGIS_OK) return step_rc;
                 if (!sw) continue;
-                if (!st->long_rows)
-                    AGIS_HIP(ctx, hipMalloc(&st->long_rows, (2 * g->g.n + 2) * sizeof(uint32_t)), "allocate row lists");
-                AGIS_HIP(ctx, hipMalloc(&buf, g->g.nnz * sizeof(uint64_t)), "allocate row pick table");
-                st->rows.push_back(StepTables::RowEntry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], lt, buf});
-                AGIS_HIP(ctx, agis::launch_rowtab(ctx, g->g, sw, buf, st->long_rows), "row pick table");
+                const uint64_t lbytes = (2 * g->g.n + 2) * sizeof(uint32_t);
+                if (cache) {
+                    if (!cache->long_rows)
+                        AGIS_HIP(ctx, hipMalloc(&cache->long_rows, lbytes), "allocate row lists");
+                    st->long_rows = cache->long_rows;
+                } else if (!st->long_rows) {
+                    AGIS_HIP(ctx, hipMalloc(&st->long_rows, lbytes), "allocate row lists");
+                }
+                const uint64_t nbytes = g->g.nnz * sizeof(uint64_t);
+                if (keep) {
+                    buf = (uint64_t*)cache->alloc(nbytes);
+                    if (!buf) return fail(ctx, AGIS_E_OOM, "allocate row pick table: out of device memory");
+                } else {
+                    AGIS_HIP(ctx, hipMalloc(&buf, nbytes), "allocate row pick table");
+                }
+                const hipError_t e = agis::launch_rowtab(ctx, g->g, sw, buf, st->long_rows);
+                if (e != hipSuccess) {
+                    (void)hipFree(buf);
+                    return hip_fail(ctx, e, "row pick table");
+                }
+                st->rows.push_back(StepTables::RowEntry{hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], lt, buf, keep});
+                if (keep) {
+                    CacheEntry proto;
+                    proto.kind = kCacheRowPick;
+                    proto.b = hp.b[i];
+                    proto.f1 = hp.f1[i];
+                    proto.ie = hp.ie[i];
+                    proto.f2 = hp.f2[i];
+                    proto.buf[0] = buf;
+                    proto.bytes = nbytes;
+                    st->held.push_back(cache->add(proto));
+                }
             }
             hp.rowpre[i] = agis::gmem((const uint64_t*)buf);
         }
@@ -428,64 +592,164 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     // would exceed kStep1FullBudget
     const bool blocked = step1 == AGIS_RUN_STEP1_BLOCKS ||
                          (step1 == 0 && 12ull * g->g.n > kStep1FullBudget);
-    if (hp.weighted[0] && g->g.n > 0 && blocked) {
+    const bool keep1 = cache && hp.weighted[0] && hp.lt[0] == nullptr && g->g.n > 0;
+    CacheEntry* c1 = keep1 ? cache->find(kCacheFirstStep, 0, hp.f1[0], hp.ie[0], hp.f2[0], blocked ? 1u : 0u) : nullptr;
+    if (c1) {
+        st->held.push_back(c1);
+        if (blocked) {
+            hp.s1_blk = agis::gmem((const uint64_t*)c1->buf[0] + 1);
+            hp.s1_lmax = c1->lmax;
+        } else {
+            hp.s1_q = agis::gmem((const uint32_t*)c1->buf[0]);
+            hp.s1_pre = agis::gmem((const uint64_t*)c1->buf[1]);
+        }
+        hp.s1_total = c1->total;
+        if (c1->total > 0) {
+            hp.s1_guide = agis::gmem((const uint32_t*)c1->buf[2]);
+            hp.s1_shift = c1->shift;
+        }
+    }
+    // a new first-step buffer: from the fixed workspace, the cache or the call
+    auto alloc1 = [&](void** p, uint64_t nbytes, const char* what) -> int {
+        if (keep1) {
+            *p = cache->alloc(nbytes);
+            return *p ? AGIS_OK : fail(ctx, AGIS_E_OOM, std::string(what) + ": out of device memory");
+        }
+        AGIS_HIP(ctx, hipMalloc(p, nbytes), what);
+        return AGIS_OK;
+    };
+    if (!c1 && hp.weighted[0] && g->g.n > 0 && blocked) {
         const uint64_t nblk = (g->g.n + agis::kStep1Block - 1) / agis::kStep1Block;
         uint64_t* blk = nullptr;
+        uint32_t* guide = nullptr;
         if (st->arena) {
             out->owns = false;
             blk = (uint64_t*)st->arena->take((nblk + 1) * sizeof(uint64_t));
-            out->guide = (uint32_t*)st->arena->take(((1ull << agis::kGuideBits) + 1) * sizeof(uint32_t));
-            if (!blk || !out->guide)
+            guide = (uint32_t*)st->arena->take(((1ull << agis::kGuideBits) + 1) * sizeof(uint32_t));
+            if (!blk || !guide)
                 return fail(ctx, AGIS_E_UNSUPPORTED, "the first-step table does not fit in the fixed workspace");
         } else {
-            AGIS_HIP(ctx, hipMalloc(&blk, (nblk + 1) * sizeof(uint64_t)), "allocate first-step block prefix");
+            rc = alloc1((void**)&blk, (nblk + 1) * sizeof(uint64_t), "allocate first-step block prefix");
+            if (rc != AGIS_OK) return rc;
         }
-        out->pre = blk;  // owned as the prefix buffer
+        if (!keep1) out->pre = blk;  // owned as the prefix buffer
         uint64_t total = 0;
         int32_t lmax = 0;
-        AGIS_HIP(ctx, agis::build_step1_blocks(ctx, *g, *t, hp, blk, &lmax, &total), "first-step block table");
+        uint64_t gbytes = 0;
+        hipError_t e = agis::build_step1_blocks(ctx, *g, *t, hp, blk, &lmax, &total);
         hp.s1_blk = agis::gmem((const uint64_t*)(blk + 1));
         hp.s1_lmax = lmax;
         hp.s1_total = total;
-        if (total > 0) {
+        if (e == hipSuccess && total > 0) {
             const uint32_t shift = agis::guide_shift(total);
             const uint64_t buckets = ((total - 1) >> shift) + 1;
-            if (!st->arena)
-                AGIS_HIP(ctx, hipMalloc(&out->guide, (buckets + 1) * sizeof(uint32_t)), "allocate first-step guide");
-            AGIS_HIP(ctx, agis::launch_prefix_guide(blk + 1, nblk, total, shift, out->guide, ctx->stream),
-                     "first-step guide");
-            hp.s1_guide = agis::gmem((const uint32_t*)out->guide);
+            gbytes = (buckets + 1) * sizeof(uint32_t);
+            if (!st->arena) {
+                rc = alloc1((void**)&guide, gbytes, "allocate first-step guide");
+                if (rc != AGIS_OK) {
+                    if (keep1) (void)hipFree(blk);
+                    return rc;
+                }
+            }
+            if (!keep1) out->guide = guide;
+            e = agis::launch_prefix_guide(blk + 1, nblk, total, shift, guide, ctx->stream);
+            hp.s1_guide = agis::gmem((const uint32_t*)guide);
             hp.s1_shift = shift;
+        }
+        if (e != hipSuccess) {
+            if (keep1) {
+                (void)hipFree(blk);
+                if (guide) (void)hipFree(guide);
+            }
+            return hip_fail(ctx, e, "first-step block table");
+        }
+        if (keep1) {
+            CacheEntry proto;
+            proto.kind = kCacheFirstStep;
+            proto.f1 = hp.f1[0];
+            proto.ie = hp.ie[0];
+            proto.f2 = hp.f2[0];
+            proto.blocked = 1;
+            proto.buf[0] = blk;
+            proto.buf[2] = guide;
+            proto.bytes = (nblk + 1) * sizeof(uint64_t) + gbytes;
+            proto.total = total;
+            proto.shift = hp.s1_shift;
+            proto.lmax = lmax;
+            st->held.push_back(cache->add(proto));
         }
     }
-    if (hp.weighted[0] && g->g.n > 0 && !blocked) {
+    if (!c1 && hp.weighted[0] && g->g.n > 0 && !blocked) {
         uint64_t* blocksums = nullptr;
+        uint32_t* q1 = nullptr;
+        uint64_t* pre = nullptr;
+        uint32_t* guide = nullptr;
         if (st->arena) {
             out->owns = false;
-            out->q1 = (uint32_t*)st->arena->take(g->g.n * sizeof(uint32_t));
-            out->pre = (uint64_t*)st->arena->take(g->g.n * sizeof(uint64_t));
-            out->guide = (uint32_t*)st->arena->take(((1ull << agis::kGuideBits) + 1) * sizeof(uint32_t));
+            q1 = (uint32_t*)st->arena->take(g->g.n * sizeof(uint32_t));
+            pre = (uint64_t*)st->arena->take(g->g.n * sizeof(uint64_t));
+            guide = (uint32_t*)st->arena->take(((1ull << agis::kGuideBits) + 1) * sizeof(uint32_t));
             blocksums = (uint64_t*)st->arena->take(agis::step1_scan_tiles(g->g.n) * sizeof(uint64_t));
-            if (!out->q1 || !out->pre || !out->guide || !blocksums)
+            if (!q1 || !pre || !guide || !blocksums)
                 return fail(ctx, AGIS_E_UNSUPPORTED, "the first-step table does not fit in the fixed workspace");
         } else {
-            AGIS_HIP(ctx, hipMalloc(&out->q1, g->g.n * sizeof(uint32_t)), "allocate first-step weights");
-            AGIS_HIP(ctx, hipMalloc(&out->pre, g->g.n * sizeof(uint64_t)), "allocate first-step prefix");
+            rc = alloc1((void**)&q1, g->g.n * sizeof(uint32_t), "allocate first-step weights");
+            if (rc == AGIS_OK) rc = alloc1((void**)&pre, g->g.n * sizeof(uint64_t), "allocate first-step prefix");
+            if (rc != AGIS_OK) {
+                if (q1) (void)hipFree(q1);
+                return rc;
+            }
+        }
+        if (!keep1) {
+            out->q1 = q1;
+            out->pre = pre;
         }
         uint64_t total = 0;
-        AGIS_HIP(ctx, agis::build_step1(ctx, *g, *t, hp, out->q1, out->pre, &total, blocksums), "first-step table");
-        hp.s1_q = agis::gmem((const uint32_t*)out->q1);
-        hp.s1_pre = agis::gmem((const uint64_t*)out->pre);
+        uint64_t gbytes = 0;
+        hipError_t e = agis::build_step1(ctx, *g, *t, hp, q1, pre, &total, blocksums);
+        hp.s1_q = agis::gmem((const uint32_t*)q1);
+        hp.s1_pre = agis::gmem((const uint64_t*)pre);
         hp.s1_total = total;
-        if (total > 0) {
+        if (e == hipSuccess && total > 0) {
             const uint32_t shift = agis::guide_shift(total);
             const uint64_t buckets = ((total - 1) >> shift) + 1;
-            if (!st->arena)
-                AGIS_HIP(ctx, hipMalloc(&out->guide, (buckets + 1) * sizeof(uint32_t)), "allocate first-step guide");
-            AGIS_HIP(ctx, agis::launch_prefix_guide(out->pre, g->g.n, total, shift, out->guide, ctx->stream),
-                     "first-step guide");
-            hp.s1_guide = agis::gmem((const uint32_t*)out->guide);
+            gbytes = (buckets + 1) * sizeof(uint32_t);
+            if (!st->arena) {
+                rc = alloc1((void**)&guide, gbytes, "allocate first-step guide");
+                if (rc != AGIS_OK) {
+                    if (keep1) {
+                        (void)hipFree(q1);
+                        (void)hipFree(pre);
+                    }
+                    return rc;
+                }
+            }
+            if (!keep1) out->guide = guide;
+            e = agis::launch_prefix_guide(pre, g->g.n, total, shift, guide, ctx->stream);
+            hp.s1_guide = agis::gmem((const uint32_t*)guide);
             hp.s1_shift = shift;
+        }
+        if (e != hipSuccess) {
+            if (keep1) {
+                (void)hipFree(q1);
+                (void)hipFree(pre);
+                if (guide) (void)hipFree(guide);
+            }
+            return hip_fail(ctx, e, "first-step table");
+        }
+        if (keep1) {
+            CacheEntry proto;
+            proto.kind = kCacheFirstStep;
+            proto.f1 = hp.f1[0];
+            proto.ie = hp.ie[0];
+            proto.f2 = hp.f2[0];
+            proto.buf[0] = q1;
+            proto.buf[1] = pre;
+            proto.buf[2] = guide;
+            proto.bytes = g->g.n * 12ull + gbytes;
+            proto.total = total;
+            proto.shift = hp.s1_shift;
+            st->held.push_back(cache->add(proto));
         }
     }
     AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "proposal tables");
@@ -508,6 +772,14 @@ struct PatternRun {
 
 // Whether a plan has a step the pair-hub paths serve (an unweighted step
 // over exactly two backward lists) and the tables have the pair-hub table.
+// Whether a launch over these plans runs on the lane sampler.
+bool use_lanes(const std::vector<PatternRun>& runs, const agis_run_params* pp) {
+    if (pp->flags & AGIS_RUN_WAVE_SAMPLES) return false;
+    for (const PatternRun& r : runs)
+        if (!agis::lane_plan(r.prep.hp)) return false;
+    return !runs.empty();
+}
+
 bool uses_pair_hubs(const DevPlan& hp, const agis_tables* t) {
     if (!t->pair_count || t->pairs == 0) return false;
     for (uint32_t i = 2; i < hp.k; ++i)
@@ -532,7 +804,7 @@ int replay_or_launch(agis_ctx* ctx, const agis::SampleLaunch& L, const agis_grap
     // contents may change between replays, its address and the grids not
     const uint64_t key[8] = {(uint64_t)(uintptr_t)ctx->d_launch, (uint64_t)L.blocks, (uint64_t)L.threads,
                              L.max_tiles, (uint64_t)(uintptr_t)L.partials, (uint64_t)(uintptr_t)ctx->d_small,
-                             (uint64_t)L.variant, (uint64_t)L.pairs};
+                             (uint64_t)L.variant, (uint64_t)L.pairs | ((uint64_t)L.lanes << 1)};
     if (!ctx->graph_exec || std::memcmp(key, ctx->graph_key, sizeof(key)) != 0) {
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
         if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -589,7 +861,8 @@ int run_rounds(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std::ve
     max_slots = std::min(max_slots, arena ? kFixedRoundSlots : kMaxRoundSlots);
     if (max_slots == 0) return AGIS_OK;
     agis::SampleLaunch L;
-    for (const PatternRun& r : runs) L.pairs = L.pairs || uses_pair_hubs(r.prep.hp, t);
+    L.lanes = use_lanes(runs, pp);
+    for (const PatternRun& r : runs) L.pairs = L.pairs || (!L.lanes && uses_pair_hubs(r.prep.hp, t));
     int rc = agis::plan_sample_launch(ctx, *g, max_slots, npat, &L, &ctx->err, arena);
     if (rc != AGIS_OK) return rc;
     agis::LaunchDesc ld;
@@ -697,8 +970,12 @@ int run_device_eps(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std
     for (const PatternRun& r : runs) L.pairs = L.pairs || uses_pair_hubs(r.prep.hp, t);
     int rc = agis::plan_sample_launch(ctx, *g, std::min<uint64_t>(total, kMaxRoundSlots), npat, &L, &ctx->err);
     if (rc != AGIS_OK) return rc;
-    // ring: the window of slots ahead of the merged prefix, plus two tiles
-    const uint64_t window = std::max<uint64_t>(2 * check, 1ull << 16);
+    // ring: the window of slots ahead of the merged prefix, plus two tiles.
+    // A wide window keeps the waves busy while one slow sample holds the
+    // oldest tile open (sample costs are heavy-tailed); handing out stays
+    // demand-driven, so the samples drawn past a stopping point are about
+    // the waves in flight, whatever the window.
+    const uint64_t window = std::max<uint64_t>(2 * check, (1ull << 20) - 2 * agis::kEpsTile);
     uint64_t ring = agis::kEpsTile;
     while (ring < window + 2 * agis::kEpsTile) ring <<= 1;
     const uint64_t rtiles = ring / agis::kEpsTile;
@@ -758,7 +1035,9 @@ int run_device_eps(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, std
     E.ring_samples = ring;
     E.window = window;
     E.npat = npat;
-    E.grab = L.grab;
+    // the largest grab of a wave (grabs grow with the merged count, see
+    // k_sample_eps): 16 slots per atomic on the pattern's counter
+    E.grab = std::max<uint32_t>(L.grab, 16u);
     E.z = z;
     E.eps = pp->eps;
     AGIS_HIP(ctx, hipMemcpyAsync(ctx->d_launch, &ld, sizeof(ld), hipMemcpyHostToDevice, ctx->stream), "upload launch");
@@ -1034,6 +1313,7 @@ int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_s
     if (lc_min_q16 > 0) return fail(ctx, AGIS_E_INVALID_ARG, "log2 of the clustering floor must be <= 0");
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
     agis_tables* t = new (std::nothrow) agis_tables();
+    if (t) t->cache = new (std::nothrow) TableCache();
     if (!t) return fail(ctx, AGIS_E_OOM, "host allocation");
     t->ctx = ctx;
     t->graph = g;
@@ -1058,6 +1338,7 @@ int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_s
 
 void agis_tables_destroy(agis_tables* t) {
     if (!t) return;
+    delete t->cache;
     if (t->rec) (void)hipFree(t->rec);
     if (t->s2) (void)hipFree(t->s2);
     if (t->hits) (void)hipFree(t->hits);
@@ -1099,14 +1380,19 @@ int agis_step1_weights(agis_ctx* ctx, const agis_graph* g, const agis_tables* t,
     const agis_run_params dp = default_params();
     const agis_run_params* pp = params ? params : &dp;
     AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
+    // the weights of every vertex are exported: the full first-step table
+    agis_run_params full = *pp;
+    full.flags = (full.flags & ~AGIS_RUN_STEP1_BLOCKS) | AGIS_RUN_STEP1_FULL;
     StepTables st;
     Prepared prep;
-    rc = prepare(ctx, g, t, p, order, pp, 0, &st, &prep);
+    rc = prepare(ctx, g, t, p, order, &full, 0, &st, &prep);
     if (rc != AGIS_OK) return rc;
     const uint64_t n = g->g.n;
     if (prep.hp.weighted[0]) {
         if (n)
-            AGIS_HIP(ctx, hipMemcpyAsync(q1, prep.q1, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream),
+            AGIS_HIP(ctx,
+                     hipMemcpyAsync(q1, (const uint32_t*)prep.hp.s1_q, n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                    ctx->stream),
                      "copy first-step weights");
         *total = prep.hp.s1_total;
     } else {
@@ -1254,7 +1540,8 @@ static int run_indexed(agis_ctx* ctx, const agis_graph* g, const agis_tables* t,
     if (m == 0) return AGIS_OK;
     if (m > kMaxRoundSlots) return fail(ctx, AGIS_E_INVALID_ARG, "at most 2^24 samples per call");
     agis::SampleLaunch L;
-    L.pairs = uses_pair_hubs(prep.hp, t);
+    L.lanes = !(pp->flags & AGIS_RUN_WAVE_SAMPLES) && agis::lane_plan(prep.hp);
+    L.pairs = !L.lanes && uses_pair_hubs(prep.hp, t);
     rc = agis::plan_sample_launch(ctx, *g, m, 1, &L, &ctx->err);
     if (rc != AGIS_OK) return rc;
     L.dump = out != nullptr;

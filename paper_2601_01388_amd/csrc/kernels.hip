@@ -2278,6 +2278,281 @@ void k_sample(const LaunchDesc* __restrict__ D) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// One lane per sample
+// ---------------------------------------------------------------------------
+// Plans whose steps after the first are all uniform draws from the row of a
+// single backward vertex (stars under switching, every tree under
+// f_uniform) build no candidate set: a sample is the first-step search, one
+// Philox draw and one neighbour load per step, and positions in one row.
+// The wave sampler spends most of such a sample in wave-uniform (scalar)
+// work; here each lane runs its own sample, so 64 samples share every
+// instruction.  The draws, factors and records are those of sample_one.
+
+// A per-lane request meter: every load of a lane counts as one request of
+// its own (lanes do not share segments in this count).
+struct LaneMeter {
+    uint64_t rbytes = 0, wbytes = 0, segs = 0, reqs = 0;
+    __device__ __forceinline__ void ld(const void* p, uint32_t width) {
+        const uint64_t a = (uint64_t)(uintptr_t)p;
+        rbytes += width;
+        segs += ((a + width - 1) >> 6) - (a >> 6) + 1;
+        reqs += 1;
+    }
+};
+struct NoLaneMeter {
+    __device__ __forceinline__ void ld(const void*, uint32_t) {}
+};
+
+// First p in [lo, hi] with a[p] > r, given a[hi] > r (one lane's binary search).
+template <class T, class LM>
+__device__ __forceinline__ uint64_t lane_first_greater(const T* __restrict__ a, uint64_t lo, uint64_t hi, uint64_t r,
+                                                       LM& mt) {
+    while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        mt.ld(a + mid, sizeof(T));
+        if ((uint64_t)a[mid] > r)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Whether x is in list[0, d) (ascending), and where.
+template <class LM>
+__device__ __forceinline__ bool lane_find(const uint32_t* __restrict__ list, uint32_t d, uint32_t x, uint32_t& pos,
+                                          LM& mt) {
+    uint32_t lo = 0, hi = d;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        mt.ld(list + mid, 4);
+        if (list[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo < d) {
+        mt.ld(list + lo, 4);
+        if (list[lo] == x) {
+            pos = lo;
+            return true;
+        }
+    }
+    return false;
+}
+
+// v[j] for a lane-dependent j < kMaxK, by selects (no private-memory array).
+__device__ __forceinline__ uint32_t pick_k(const uint32_t (&v)[kMaxK], uint32_t j) {
+    uint32_t r = v[0];
+#pragma unroll
+    for (uint32_t q = 1; q < (uint32_t)kMaxK; ++q) r = j == q ? v[q] : r;
+    return r;
+}
+
+template <bool kDump, class LM>
+__device__ __forceinline__ double lane_sample(const DevGraph& g, const DevPlan* __restrict__ P, uint32_t k0,
+                                              uint32_t k1, uint64_t s, Record* __restrict__ rec, LM& mt) {
+    const uint32_t c0 = (uint32_t)s, c1 = (uint32_t)(s >> 32), c2 = P->pattern_id;
+    const uint32_t k = P->k;
+    // per matched vertex: the vertex, the row it was drawn from (or none)
+    // and its position there
+    uint32_t tau[kMaxK], row[kMaxK], rpos[kMaxK];
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        tau[j] = 0u;
+        row[j] = 0xFFFFFFFFu;
+        rpos[j] = 0u;
+    }
+    double x = 1.0;
+    int fail = -1;
+    uint32_t steps = 0;
+    // step 0: the weighted first-step table (through its guide) or an
+    // edge-uniform slot
+    {
+        uint64_t num, den;
+        uint32_t v;
+        bool ok = true;
+        if (P->weighted[0]) {
+            if (P->s1_total == 0) {
+                ok = false;
+            } else {
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, P->s1_total);
+                uint64_t lo = 0, hi = g.n - 1;
+                if (P->s1_guide) {
+                    const uint64_t bkt = r >> P->s1_shift;
+                    mt.ld(P->s1_guide + bkt, 8);
+                    lo = P->s1_guide[bkt];
+                    hi = P->s1_guide[bkt + 1];
+                }
+                v = (uint32_t)lane_first_greater(P->s1_pre, lo, hi, r, mt);
+                num = P->s1_total;
+                mt.ld(P->s1_q + v, 4);
+                den = P->s1_q[v];
+            }
+        } else {
+            if (g.nnz == 0) {
+                ok = false;
+            } else {
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, 0, g.nnz);
+                v = (uint32_t)lane_first_greater(g.off + 1, 0, g.n - 1, r, mt);
+                num = g.nnz;
+                mt.ld(g.off + v, 16);
+                den = g.off[v + 1] - g.off[v];
+            }
+        }
+        if (!ok) {
+            fail = 0;
+        } else {
+            x = (double)num / (double)den;
+            tau[0] = v;
+            steps = 1;
+            if (kDump) {
+                rec->v[0] = v;
+                rec->num[0] = num;
+                rec->den[0] = den;
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 1; i < (uint32_t)kMaxK; ++i) {
+        if (fail >= 0 || i >= k) break;
+        // uniform draw from N(w) minus the matched vertices
+        const uint32_t bslot = (uint32_t)__builtin_ctz((uint32_t)P->bmask[i]);
+        const uint32_t w = pick_k(tau, bslot);
+        mt.ld(g.off + w, 16);
+        const uint64_t o = g.off[w];
+        const uint32_t d = (uint32_t)(g.off[w + 1] - o);
+        const uint32_t* list = g.nbr + o;
+        bool found[kMaxK];
+        uint32_t pos[kMaxK];
+        uint32_t ex = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < (uint32_t)kMaxK; ++j) {
+            found[j] = false;
+            pos[j] = 0u;
+            // w itself is matched but never in its own list (no loops)
+            if (j < i && tau[j] != w) {
+                if (row[j] == w) {
+                    pos[j] = rpos[j];
+                    found[j] = true;
+                } else {
+                    found[j] = lane_find(list, d, tau[j], pos[j], mt);
+                }
+                ex += found[j] ? 1u : 0u;
+            }
+        }
+        const uint64_t m = (uint64_t)d - ex;
+        if (m == 0) {
+            fail = (int)i;
+            break;
+        }
+        // at the last step only |S| enters X (see sample_one)
+        const bool count_only = !kDump && i + 1 == k;
+        uint32_t v = 0;
+        if (!count_only) {
+            const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, m);
+            // the r-th position of the row that holds no matched vertex
+            uint64_t idx = r;
+            for (;;) {
+                uint64_t c = 0;
+#pragma unroll
+                for (uint32_t j = 0; j < (uint32_t)kMaxK; ++j) c += (found[j] && (uint64_t)pos[j] <= idx) ? 1u : 0u;
+                if (r + c == idx) break;
+                idx = r + c;
+            }
+            mt.ld(list + idx, 4);
+            v = list[idx];
+#pragma unroll
+            for (uint32_t j = 0; j < (uint32_t)kMaxK; ++j)
+                if (j == i) {
+                    tau[j] = v;
+                    row[j] = w;
+                    rpos[j] = (uint32_t)idx;
+                }
+        }
+        x = x * ((double)m / (double)1ull);
+        steps = i + 1;
+        if (kDump) {
+            rec->v[i] = v;
+            rec->num[i] = m;
+            rec->den[i] = 1;
+        }
+    }
+    if (fail >= 0) x = 0.0;
+    if (kDump) {
+        const uint32_t first = fail >= 0 ? (uint32_t)fail : steps;
+        for (uint32_t j = first; j < (uint32_t)kMaxK; ++j) {
+            rec->v[j] = 0;
+            rec->num[j] = 0;
+            rec->den[j] = 0;
+        }
+        rec->x = x;
+        rec->steps = (int32_t)(fail >= 0 ? (uint32_t)fail : steps);
+        rec->fail_step = fail;
+    }
+    return x;
+}
+
+// Persistent lane sampler over one round (slots and segments as k_sample's):
+// a wave takes 64 x grab consecutive slots per queue access, lane l runs
+// slots cur + l, cur + 64 + l, ...
+template <int kMode>
+__global__ __launch_bounds__(256) void k_sample_lanes(const LaunchDesc* __restrict__ D) {
+    constexpr bool kDump = kMode == kDumpRecords;
+    constexpr bool kIdx = kMode != kRun;
+    const int lane = lane_id();
+    const RoundDesc* __restrict__ round = &D->round;
+    const uint64_t total = round->total;
+    const uint64_t span = (uint64_t)D->grab * kWave;
+    const DevGraph g = D->g;
+    AGIS_GMEM double* xout = D->xout;
+    uint32_t q = blockIdx.x % kQueues;
+    uint64_t lo = total * q / kQueues, hi = total * (q + 1) / kQueues;
+    auto take = [&]() -> uint64_t {
+        unsigned long long o = 0;
+        if (lane == 0) o = atomicAdd(D->queue + (uint64_t)q * kQueueStride, (unsigned long long)span);
+        o = uniform_u64(o);
+        return o < hi - lo ? lo + o : kNoSlot;
+    };
+    uint32_t sg = 0;  // this lane's segment (within a part, a lane's slots only increase)
+    uint32_t unvisited = kQueues - 1;
+    uint64_t cur = take();
+    for (;;) {
+        while (cur == kNoSlot && unvisited > 0) {
+            --unvisited;
+            q = (q + 1) % kQueues;
+            lo = total * q / kQueues;
+            hi = total * (q + 1) / kQueues;
+            sg = 0;
+            cur = take();
+        }
+        if (cur == kNoSlot) break;
+        const uint64_t next = take();
+        const uint64_t j1 = (cur + span) < hi ? (cur + span) : hi;
+        for (uint64_t j = cur + (uint64_t)lane; j < j1; j += kWave) {
+            while (sg + 1 < round->nseg && j >= round->seg[sg].base + round->seg[sg].count) ++sg;
+            const Segment& S = round->seg[sg];
+            const uint64_t off = j - S.base;
+            const uint64_t sidx = kIdx ? D->idx[off] : S.start + off;
+            Record* rec = kDump ? D->dump + j : nullptr;
+            if constexpr (kMode == kMeterSamples) {
+                LaneMeter mt;
+                const double xv = lane_sample<false>(g, D->plans + S.plan, round->k0, round->k1, sidx, rec, mt);
+                xout[j] = xv;
+                D->meter[4 * j + 0] = mt.rbytes;
+                D->meter[4 * j + 1] = mt.wbytes + 8;
+                D->meter[4 * j + 2] = mt.segs + 1;
+                D->meter[4 * j + 3] = mt.reqs + 1;
+            } else {
+                NoLaneMeter mt;
+                xout[j] = lane_sample<kDump>(g, D->plans + S.plan, round->k0, round->k1, sidx, rec, mt);
+            }
+        }
+        cur = uniform_u64(next);
+    }
+}
+
 // Welford over the (up to) kReducePer weights xs[first ..] below lim, as one
 // thread of the fixed reduction tree.
 constexpr int kReducePer = 8;
@@ -2463,15 +2738,18 @@ __device__ void merge_ready(const EpsDesc& E, uint32_t p) {
     }
 }
 
-// Persistent sampler for runs to epsilon: the slots of all patterns are
-// handed out from per-pattern counters, round robin over the patterns that
-// still run, never beyond merged + window (a wave holding such a slot waits
-// for the merge: the wave holding the lowest unfinished slot never waits,
-// so the merge always advances).  A sample's weight goes to the pattern's
-// ring; the wave that completes a tile reduces it and merges what is ready.
-// Samples handed out beyond a pattern's stopping point are dropped.  The
-// waves leave once every pattern has stopped or handed out its budget; the
-// host's cancel flag stops every pattern at its merged prefix.
+// Persistent sampler for runs to epsilon.  Each pattern hands out its slots
+// in grabs from its own counter, never beyond merged + window (a wave whose
+// grab lies beyond waits for the merge: the wave holding the lowest
+// unfinished slot never waits, so the merge always advances).  A wave stays
+// on its pattern while that pattern hands out samples.  A sample's weight
+// goes to the pattern's ring; a wave counts its finished samples into their
+// tile once per tile it touched in the grab (one release, one atomic), and
+// the wave that completes a tile reduces it and merges what is ready.
+// Samples past a pattern's stopping point are dropped: a wave looks at the
+// stop flag before each sample.  The waves leave once every pattern has
+// stopped or handed out its budget; the host's cancel flag stops every
+// pattern at its merged prefix.
 constexpr uint32_t kWindowSpins = 1u << 22;
 
 template <int kWavesPerEU, bool kPairs>
@@ -2492,43 +2770,72 @@ void k_sample_eps(const LaunchDesc* __restrict__ D) {
     const uint32_t npat = E.npat;
     const uint64_t rmask = E.ring_samples - 1, rtiles = E.ring_samples / kEpsTile;
     const uint32_t grab = E.grab;
-    uint32_t cur = (uint32_t)(gw % npat);
+    // The waves of one XCD (workgroups are dealt to the XCDs round robin)
+    // start on their own share of the patterns, so each XCD's L2 holds the
+    // step tables and lists of a few patterns rather than of all of them.
+    uint32_t cur = (uint32_t)(((uint64_t)(blockIdx.x % kXcds) * npat) / kXcds);
     uint32_t rounds = 0;
+    // patterns this wave has seen stopped or out of samples (both final)
+    uint64_t dead = npat < 64 ? ~((1ull << npat) - 1ull) : 0ull;
+    bool fresh = true;  // look at every pattern before the next grab
+    // Grabs grow with the run: min(grab, merged / (4 x waves)) slots (at
+    // least the first check point over the waves), so the samples in flight
+    // stay about a quarter of those already merged (few are drawn past an
+    // early stop) while long runs take up to `grab` slots per atomic.
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    uint64_t seen = 0;  // the current pattern's merged count, as last read
     for (;;) {
-        // the next pattern from cur on that still hands out samples
-        uint32_t p = 0xFFFFFFFFu;
-        for (uint32_t k = 0; k < npat; ++k) {
-            const uint32_t q = cur + k < npat ? cur + k : cur + k - npat;
-            if (!ld_dev(&E.pat[q].stop) && ld_dev(&E.pat[q].next) < E.pat[q].budget) {
-                p = q;
-                break;
-            }
+        if (fresh || (dead >> cur & 1ull)) {
+            // lane q looks at pattern q, all at once
+            const uint32_t q = (uint32_t)lane;
+            bool out = (dead >> q & 1ull) != 0;
+            if (!out) out = ld_dev(&E.pat[q].stop) != 0u || ld_dev(&E.pat[q].next) >= E.pat[q].budget;
+            dead |= __ballot(out);
+            if (dead == ~0ull) break;
+            const uint64_t live = ~dead;
+            const uint64_t from = live & ~((1ull << cur) - 1ull);
+            const uint32_t pick = (uint32_t)__builtin_ctzll(from ? from : live);
+            if (pick != cur) seen = 0;
+            cur = pick;
+            fresh = false;
         }
-        p = uniform_u32(p);
-        if (p == 0xFFFFFFFFu) break;
-        cur = p + 1 < npat ? p + 1 : 0;
+        const uint32_t p = cur;
         if ((++rounds & 15u) == 0 &&
             uniform_u32(__hip_atomic_load(E.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
             for (uint32_t q = (uint32_t)lane; q < npat; q += kWave) st_dev(&E.pat[q].stop, 1u);
             break;
         }
         AGIS_GMEM EpsPattern* P = E.pat + p;
-        unsigned long long s0 = 0;
-        if (lane == 0) s0 = atomicAdd(&P->next, (unsigned long long)grab);
-        s0 = uniform_u64(s0);
         const uint64_t budget = P->budget;
-        for (uint64_t j = s0; j < s0 + grab && j < budget; ++j) {
-            // wait until the slot is inside the window (or the pattern
-            // stops); the wait is bounded all the same: past kWindowSpins
-            // the wave reports a fault, stops every pattern and leaves
-            bool live = true;
+        // (no stop comes before the first check point, so the samples up to
+        // it are spread over all waves at once)
+        const uint64_t chk = P->check;
+        const uint64_t first = ((P->min_samples + chk - 1) / chk) * chk;
+        const uint64_t early = (first > chk ? first : chk) / nwaves;
+        uint64_t take = seen / (4 * nwaves);
+        take = take > early ? take : early;
+        take = take < 1 ? 1 : (take > grab ? grab : take);
+        unsigned long long s0 = 0;
+        if (lane == 0) s0 = atomicAdd(&P->next, (unsigned long long)take);
+        s0 = uniform_u64(s0);
+        if (s0 >= budget) {
+            dead |= 1ull << p;
+            continue;
+        }
+        const uint64_t s1 = (s0 + take) < budget ? (s0 + take) : budget;
+        // wait until the whole grab is inside the window (or the pattern
+        // stops); the wait is bounded all the same: past kWindowSpins the
+        // wave reports a fault, stops every pattern and leaves
+        bool live = true;
+        {
             uint32_t spins = 0;
             for (;;) {
                 if (ld_dev(&P->stop)) {
                     live = false;
                     break;
                 }
-                if (j < ld_dev(&P->merged) + E.window) break;
+                seen = ld_dev(&P->merged);
+                if (s1 - 1 < seen + E.window) break;
                 if (++spins > kWindowSpins) {
                     live = false;
                     if (lane == 0) {
@@ -2537,33 +2844,62 @@ void k_sample_eps(const LaunchDesc* __restrict__ D) {
                     }
                     break;
                 }
-                __builtin_amdgcn_s_sleep(8);
+                // back off after a short wait: thousands of waves polling
+                // one address would queue behind each other
+                if (spins < 64)
+                    __builtin_amdgcn_s_sleep(4);
+                else
+                    __builtin_amdgcn_s_sleep(32);
             }
-            if (!uniform_u32(live ? 1u : 0u)) break;
-            NoMeter mt;
-            const double xv = sample_one<false, kPairs>(g, t, D->plans + P->plan, D->round.k0, D->round.k1,
-                                                         P->start + j, sv, sl, nullptr, hub_window, mt);
-            const uint64_t tile = j / kEpsTile;
-            const uint64_t slot = (uint64_t)p * rtiles + (tile & (rtiles - 1));
+        }
+        if (!uniform_u32(live ? 1u : 0u)) {
+            dead |= 1ull << p;
+            continue;
+        }
+        // the samples of the grab, tile segment by tile segment, each
+        // segment counted into its tile at once
+        bool stopped = false;
+        for (uint64_t j = s0; j < s1 && !stopped;) {
+            const uint64_t tcur = j / kEpsTile;
+            const uint64_t tend = (tcur + 1) * kEpsTile < s1 ? (tcur + 1) * kEpsTile : s1;
+            uint32_t cnt = 0;
+            for (; j < tend; ++j) {
+                // a sample past the stopping point would be dropped: skip
+                // the rest of the grab (its tiles are never merged)
+                if (uniform_u32(ld_dev(&P->stop))) {
+                    stopped = true;
+                    break;
+                }
+                NoMeter mt;
+                const double xv = sample_one<false, kPairs>(g, t, D->plans + P->plan, D->round.k0, D->round.k1,
+                                                             P->start + j, sv, sl, nullptr, hub_window, mt);
+                if (lane == 0) E.ring[(uint64_t)p * E.ring_samples + (j & rmask)] = xv;
+                ++cnt;
+            }
+            if (cnt == 0) break;
+            const uint64_t slot = (uint64_t)p * rtiles + (tcur & (rtiles - 1));
             uint32_t last = 0;
             if (lane == 0) {
-                E.ring[(uint64_t)p * E.ring_samples + (j & rmask)] = xv;
-                __threadfence();
-                const uint64_t rem = budget - tile * kEpsTile;
+                // one release for the weights of this segment: an acquire
+                // here (a cache invalidation) in every wave would cost the
+                // others their cached lists and bitmaps; the wave that
+                // completes the tile acquires once for the whole tile
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const uint64_t rem = budget - tcur * kEpsTile;
                 const uint32_t len = (uint32_t)(rem < kEpsTile ? rem : kEpsTile);
-                last = atomicAdd(E.tile_done + slot, 1u) + 1u == len ? 1u : 0u;
+                last = atomicAdd(E.tile_done + slot, cnt) + cnt == len ? 1u : 0u;
             }
             if (uniform_u32(last)) {
                 __threadfence();
-                const uint64_t rem = budget - tile * kEpsTile;
+                const uint64_t rem = budget - tcur * kEpsTile;
                 const uint64_t len = rem < kEpsTile ? rem : kEpsTile;
                 const Partial part =
-                    reduce_tile_wave(E.ring + (uint64_t)p * E.ring_samples + ((tile * kEpsTile) & rmask), len);
+                    reduce_tile_wave(E.ring + (uint64_t)p * E.ring_samples + ((tcur * kEpsTile) & rmask), len);
                 if (lane == 0) {
                     E.tile_done[slot] = 0u;
                     E.tile_part[slot] = part;
                     __threadfence();
-                    __hip_atomic_store(E.tile_ready + slot, (unsigned long long)(tile + 1), __ATOMIC_RELAXED,
+                    __hip_atomic_store(E.tile_ready + slot, (unsigned long long)(tcur + 1), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                 }
                 merge_ready(E, p);
@@ -2592,6 +2928,20 @@ template <int kW, bool kPairs>
 const void* sample_kernel_of(bool dump) {
     return dump ? reinterpret_cast<const void*>(k_sample<kDumpRecords, kW, kPairs>)
                 : reinterpret_cast<const void*>(k_sample<kRun, kW, kPairs>);
+}
+
+bool lane_plan(const DevPlan& hp) {
+    if (hp.k < 2 || hp.k > (uint32_t)kMaxK) return false;
+    if (hp.weighted[0] && hp.s1_blk) return false;
+    for (uint32_t i = 1; i < hp.k; ++i)
+        if (hp.weighted[i] || __builtin_popcount((uint32_t)hp.bmask[i]) != 1) return false;
+    return true;
+}
+
+const void* sample_lanes_kernel(bool dump, bool meter) {
+    if (meter) return reinterpret_cast<const void*>(k_sample_lanes<kMeterSamples>);
+    return dump ? reinterpret_cast<const void*>(k_sample_lanes<kDumpRecords>)
+                : reinterpret_cast<const void*>(k_sample_lanes<kRun>);
 }
 
 const void* sample_kernel(bool dump, int variant, bool pairs, bool meter) {
@@ -2628,14 +2978,11 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
     }
     L->variant = ctx->tune_variant;
     L->hub_window = ctx->tune_hub_window;
-    int& cached = ctx->sample_blocks_per_cu[L->variant * 2 + (L->pairs ? 1 : 0)];
+    int& cached = L->lanes ? ctx->lanes_blocks_per_cu : ctx->sample_blocks_per_cu[L->variant * 2 + (L->pairs ? 1 : 0)];
     if (cached == 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel(false, L->variant, L->pairs, false), L->threads,
-                                                         0) !=
-                hipSuccess ||
-            nb < 1)
-            nb = 4;
+        const void* kern = L->lanes ? sample_lanes_kernel(false, false) : sample_kernel(false, L->variant, L->pairs, false);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, L->threads, 0) != hipSuccess || nb < 1) nb = 4;
         cached = nb;
     }
     // as many waves as can be resident at once (a persistent grid), scaled
@@ -2655,13 +3002,14 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
         }
         budget = arena->left() > 256 ? arena->left() - 256 : 0;
     }
-    if (waves * per_wave > budget) waves = budget / per_wave / 4 * 4;
+    if (!L->lanes && waves * per_wave > budget) waves = budget / per_wave / 4 * 4;
     if (waves < 4) {
         *err = arena ? "maximum degree too large for the fixed workspace (one workgroup's scratch does not fit)"
                      : "maximum degree too large for the sampler scratch budget";
         return AGIS_E_UNSUPPORTED;
     }
-    const uint64_t need = (max_slots + 3) / 4 * 4;
+    // (a lane-sampler wave runs 64 slots at a time)
+    const uint64_t need = L->lanes ? ((max_slots + kWave - 1) / kWave + 3) / 4 * 4 : (max_slots + 3) / 4 * 4;
     if (waves > need) waves = need < 4 ? 4 : need;
     L->blocks = (int)(waves / 4);
     if (ctx->tune_grab > 0) {
@@ -2670,10 +3018,11 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
         const uint64_t per = max_slots / (waves * 32);
         L->grab = (uint32_t)(per < 1 ? 1 : (per > 8 ? 8 : per));
     }
-    const uint64_t bytes = (uint64_t)L->blocks * 4 * per_wave;
+    // the lane sampler keeps no candidate set: no scratch
+    const uint64_t bytes = L->lanes ? 0 : (uint64_t)L->blocks * 4 * per_wave;
     if (arena) {
-        L->scratch = arena->take(bytes);
-        if (!L->scratch) {
+        L->scratch = bytes ? arena->take(bytes) : nullptr;
+        if (bytes && !L->scratch) {
             *err = "the fixed workspace cannot hold the sampler scratch";
             return AGIS_E_UNSUPPORTED;
         }
@@ -2742,8 +3091,8 @@ hipError_t launch_round(agis_ctx* ctx, hipStream_t stream, const SampleLaunch& L
     if (before && (e = hipEventRecord(before, stream)) != hipSuccess) return e;
     const LaunchDesc* desc = ctx->d_launch;
     void* args[] = {(void*)&desc};
-    e = hipLaunchKernel(sample_kernel(L.dump, L.variant, L.pairs, L.meter), dim3((unsigned)L.blocks),
-                        dim3((unsigned)L.threads), args, 0, stream);
+    const void* kern = L.lanes ? sample_lanes_kernel(L.dump, L.meter) : sample_kernel(L.dump, L.variant, L.pairs, L.meter);
+    e = hipLaunchKernel(kern, dim3((unsigned)L.blocks), dim3((unsigned)L.threads), args, 0, stream);
     if (e != hipSuccess) return e;
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (after && (e = hipEventRecord(after, stream)) != hipSuccess) return e;

@@ -79,14 +79,25 @@ def test_meter_counts_a_star_exactly(sess, c1g):
     g, G, T = c1g
     p = synth.named_pattern("4-star")
     idx = np.arange(2000, dtype=np.uint64)
-    m = sess.meter(G, T, p, 7, idx, mode="switch", rowtab="on")
     recs = sess.dump(G, T, p, 7, idx, mode="switch", rowtab="on")
     ok = recs["fail_step"] < 0
     assert ok.any()
     # steps 1..4: 16 B offsets each, drawn neighbours at steps 1..3, 8 B slot
     fixed = 4 * 16 + 3 * 4
+    # the wave sampler: at least one 64-lane probe of the prefix
+    m = sess.meter(G, T, p, 7, idx, mode="switch", rowtab="on", wave_samples=True)
     assert (m[ok, 0] >= 8 + 4 + 8 * 1 + fixed).all()
     assert (m[ok, 1] == 8).all()  # only the weight slot is written
+    # the lane sampler (the default for stars): the leaves are drawn from
+    # the centre's row, so their positions are known and nothing is
+    # searched after step 0; step 0 reads the guide, 8 B per probe of its
+    # binary search between the guide's bounds (at most log2 n + 1), and
+    # the weight
+    m = sess.meter(G, T, p, 7, idx, mode="switch", rowtab="on")
+    probes = (m[ok, 0].astype(np.int64) - (8 + 4 + fixed))
+    assert (probes >= 0).all() and (probes % 8 == 0).all()
+    assert (probes // 8 <= int(np.log2(g.n)) + 1).all()
+    assert (m[ok, 1] == 8).all()
 
 
 @pytest.mark.parametrize("seg", [4, 16, 64, 256, 1024])

@@ -110,12 +110,16 @@ def test_inputs_beyond_the_workspace_are_refused(sess):
     T = sess.tables(G, cv_seed=1)
     p = synth.named_pattern("4-star")
     with pytest.raises(A.AgisError) as e:
-        _noalloc(sess, G, T, p, 1 << 10, 1, mode="switch")
+        _noalloc(sess, G, T, p, 1 << 10, 1, mode="switch", wave_samples=True)
     assert e.value.code == A.AGIS_E_UNSUPPORTED
     say(f"refused: {e.value}")
     assert "workspace" in str(e.value)
     # the allocating entry point still serves it
-    r = sess.estimate(G, T, p, 1 << 10, 1, mode="switch")
+    r = sess.estimate(G, T, p, 1 << 10, 1, mode="switch", wave_samples=True)
     assert r.n == 1 << 10
+    # the lane sampler (which stars run on by default) keeps no candidate
+    # set, so it needs no scratch and the fixed workspace serves the star
+    a = _noalloc(sess, G, T, p, 1 << 10, 1, mode="switch")
+    _same(a, r, "lanes in the fixed workspace")
     T.close()
     G.close()
