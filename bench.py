@@ -774,7 +774,7 @@ def main():
                     help="sample budget per pattern of the concentration runs (to +-1%%)")
     ap.add_argument("--skip-large", action="store_true",
                     help="skip the R-MAT scale 24 legs (32-pattern batch; learned proposal trained on scale 20)")
-    ap.add_argument("--large-budget-scale", type=float, default=0.1,
+    ap.add_argument("--large-budget-scale", type=float, default=1.0,
                     help="multiplier on the 32-pattern budgets on R-MAT scale 24 (1.0 = the full budgets)")
     ap.add_argument("--large-eval-samples", type=int, default=1 << 20,
                     help="samples per pattern and mode for the learned-vs-f_approx variance on scale 24")

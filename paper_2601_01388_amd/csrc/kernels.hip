@@ -2778,12 +2778,16 @@ void k_sample_eps(const LaunchDesc* __restrict__ D) {
     // patterns this wave has seen stopped or out of samples (both final)
     uint64_t dead = npat < 64 ? ~((1ull << npat) - 1ull) : 0ull;
     bool fresh = true;  // look at every pattern before the next grab
-    // Grabs grow with the run: min(grab, merged / (4 x waves)) slots (at
-    // least the first check point over the waves), so the samples in flight
-    // stay about a quarter of those already merged (few are drawn past an
-    // early stop) while long runs take up to `grab` slots per atomic.
+    // Grab sizes.  Atomics on one counter are served one at a time (a few
+    // million per second), so a grab is just large enough that the waves'
+    // takes stay under one per 200 ns: waves x 200 ns / (the wave's last
+    // sample time), and at most min(grab, max(merged / (4 x waves), first
+    // check point / waves)), so the samples in flight stay about a quarter
+    // of those merged (few drawn past an early stop) and a slow sample
+    // holds few slots behind it (the merge is in index order).
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / kWave);
     uint64_t seen = 0;  // the current pattern's merged count, as last read
+    uint64_t cost = 0;  // wall-clock ticks (10 ns) of this wave's last sample
     for (;;) {
         if (fresh || (dead >> cur & 1ull)) {
             // lane q looks at pattern q, all at once
@@ -2814,6 +2818,8 @@ void k_sample_eps(const LaunchDesc* __restrict__ D) {
         const uint64_t early = (first > chk ? first : chk) / nwaves;
         uint64_t take = seen / (4 * nwaves);
         take = take > early ? take : early;
+        const uint64_t need = cost ? (nwaves * 20 + cost - 1) / cost : 1;
+        take = take < need ? take : need;
         take = take < 1 ? 1 : (take > grab ? grab : take);
         unsigned long long s0 = 0;
         if (lane == 0) s0 = atomicAdd(&P->next, (unsigned long long)take);
@@ -2871,9 +2877,11 @@ void k_sample_eps(const LaunchDesc* __restrict__ D) {
                     break;
                 }
                 NoMeter mt;
+                const uint64_t t0 = wall_clock64();
                 const double xv = sample_one<false, kPairs>(g, t, D->plans + P->plan, D->round.k0, D->round.k1,
                                                              P->start + j, sv, sl, nullptr, hub_window, mt);
                 if (lane == 0) E.ring[(uint64_t)p * E.ring_samples + (j & rmask)] = xv;
+                cost = uniform_u64(wall_clock64() - t0);
                 ++cnt;
             }
             if (cnt == 0) break;
