@@ -619,7 +619,8 @@ def c5_leg(args, sess):
     5-clique, 6-cycle and the chordal 7-cycle run to +-1% at 95% CI under
     learned, f_approx (switching and always) and f_uniform, each run capped
     at --c5-seconds of wall time (the cancel flag stops it between rounds
-    and the partial result reports the error it reached); the 4-star and
+    and the partial result reports the error it reached), then the 32-pattern
+    batch to +-1% in one launch under --c5-batch-seconds; the 4-star and
     3-path closed forms and cross-mode agreement are the judges."""
     import ctypes
     import threading
@@ -725,6 +726,25 @@ def c5_leg(args, sess):
         del tabs, params, rows
         torch.cuda.empty_cache()
     out["to_1pct"] = runs
+    # the 32-pattern batch (seed 3, budgets log-uniform in [10^6, 10^9]) to
+    # +-1% in one launch, capped at --c5-batch-seconds through the cancel flag
+    pset = synth.random_pattern_set(32, seed=3)
+    bp, bb = [q for q, _ in pset], [b for _, b in pset]
+    flag = ctypes.c_int32(0)
+    timer = threading.Timer(args.c5_batch_seconds, lambda f=flag: setattr(f, "value", 1))
+    t0 = time.perf_counter()
+    timer.start()
+    res = sess.estimate_batch(G, T, bp, bb, 13, mode="switch", eps=0.01, delta=0.05, check_every=1 << 14,
+                              min_samples=1 << 14, cancel=flag)
+    timer.cancel()
+    bt = time.perf_counter() - t0
+    out["batch_32_patterns"] = {
+        "seconds": bt, "cap_seconds": args.c5_batch_seconds, "stopped_by_time_cap": res[0].status == -9,
+        "samples": int(sum(r.n for r in res)), "converged": int(sum(r.converged for r in res)),
+        "per_pattern": [{"k": q.k, "edges": len(q.edges), "budget": b, "samples": r.n, "converged": bool(r.converged),
+                         "seconds": r.seconds, "eps_hat": r.eps_hat} for q, b, r in zip(bp, bb, res)]}
+    log(f"C5 32-pattern batch: {bt:.1f} s, {out['batch_32_patterns']['converged']}/32 converged, "
+        f"{out['batch_32_patterns']['samples']:.3g} samples")
     out["free_gib_end"] = mem()
     T20.close()
     G20.close()
@@ -770,6 +790,8 @@ def main():
                     help="only the R-MAT scale 30 leg (3.4e10 CSR slots resident in HBM); prints its own JSON line")
     ap.add_argument("--c5-seconds", type=float, default=40.0, help="wall-time cap of each C5 run to +-1%%")
     ap.add_argument("--c5-budget", type=int, default=1 << 31, help="sample budget of each C5 run to +-1%%")
+    ap.add_argument("--c5-batch-seconds", type=float, default=60.0,
+                    help="wall-time cap of the C5 32-pattern batch to +-1%%")
     ap.add_argument("--conc-budget", type=int, default=20_000_000,
                     help="sample budget per pattern of the concentration runs (to +-1%%)")
     ap.add_argument("--skip-large", action="store_true",

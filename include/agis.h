@@ -273,7 +273,15 @@ int agis_graph_export(agis_ctx* ctx, const agis_graph* g, uint64_t* n, uint64_t*
  * which make a uniform step over the common neighbours of two such hubs a
  * table read plus a partial walk.  The pair tables hold 8 counts per
  * ordered pair (the total and 7 running counts at eighths of the shorter
- * list), H^2 x 8 x 4 B: at most 2 GiB. */
+ * list), H^2 x 8 x 4 B: at most 2 GiB.
+ * The tables also keep, for later calls, the f_approx proposal tables that
+ * estimates with them build (per step signature: per-vertex step weights,
+ * per-row pick tables, the first-step table): at most 16 GiB, least
+ * recently used first, released at a call that finds less than 128 GiB of
+ * device memory free, and freed by agis_tables_destroy.  Tables built from
+ * learned weights are rebuilt at every call (the caller may change them).
+ * Calls that use one tables handle from several threads are serialised
+ * while they prepare their tables. */
 int agis_build_proposal_tables(agis_ctx* ctx, const agis_graph* g, uint64_t cv_seed, int32_t lc_min_q16,
                                int32_t exact_cv, agis_tables** out);
 void agis_tables_destroy(agis_tables* t);

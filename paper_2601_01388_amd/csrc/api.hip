@@ -159,6 +159,8 @@ struct CacheEntry {
     uint32_t users = 0;  // calls holding the entry
 };
 constexpr uint64_t kTableCacheBudget = 16ull << 30;
+// below this much free device memory a call first frees the unused tables
+constexpr uint64_t kTableCacheFreeFloor = 128ull << 30;
 
 struct TableCache {
     std::mutex mu;
@@ -408,6 +410,28 @@ agis::DevTables dev_tables(const agis_tables* t) {
                            t->pair_count ? t->pairs : 0,               agis::gmem((const uint32_t*)t->pair_quart)};
 }
 
+// Device memory for a proposal table: from the cache (keep) or the call.
+// The sampler's scratch that the context keeps between calls is idle while
+// tables are prepared (the sampler sizes it again from the memory then
+// free), so a failed allocation releases it and tries once more.
+void* table_alloc(agis_ctx* ctx, TableCache* cache, bool keep, uint64_t nbytes) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        void* p = nullptr;
+        if (keep) {
+            p = cache->alloc(nbytes);
+            if (p) return p;
+        } else {
+            if (hipMalloc(&p, nbytes) == hipSuccess) return p;
+            (void)hipGetLastError();
+        }
+        if (attempt > 0 || !ctx->d_scratch) break;
+        (void)hipFree(ctx->d_scratch);
+        ctx->d_scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    return nullptr;
+}
+
 int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis_pattern* p, const uint8_t* order,
             const agis_run_params* params, uint64_t n_samples, StepTables* st, Prepared* out) {
     int rc = agis::compile_plan(p, order, params->mode, params->beta_num, params->beta_den, &out->plan, &ctx->err);
@@ -458,6 +482,12 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     if (cache) {
         cache_lock = std::unique_lock<std::mutex>(cache->mu);
         st->cache = cache;
+        // when device memory is scarce (a graph of a large part of the GPU),
+        // the memory of kept tables goes back to this call's tables and the
+        // sampler's scratch, whose size sets the number of waves
+        size_t free_b = 0, total_b = 0;
+        if (cache->bytes && hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b < kTableCacheFreeFloor)
+            cache->evict(~0ull);
     }
     // per-vertex log weights of step i (shared by the call), nullptr beyond
     // the budget
@@ -482,11 +512,9 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
             // no room left in the fixed workspace: the weights come from the records
             buf = (int32_t*)st->arena->take(nbytes);
             if (!buf) return nullptr;
-        } else if (keep) {
-            buf = (int32_t*)cache->alloc(nbytes);
-            if (!buf) e = hipErrorOutOfMemory;
         } else {
-            e = hipMalloc(&buf, nbytes);
+            buf = (int32_t*)table_alloc(ctx, cache, keep, nbytes);
+            if (!buf) e = hipErrorOutOfMemory;
         }
         if (e == hipSuccess)
             e = agis::launch_step_log_weights(*t, g->g.n, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], hp.lt[i], buf,
@@ -545,12 +573,8 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
                     AGIS_HIP(ctx, hipMalloc(&st->long_rows, lbytes), "allocate row lists");
                 }
                 const uint64_t nbytes = g->g.nnz * sizeof(uint64_t);
-                if (keep) {
-                    buf = (uint64_t*)cache->alloc(nbytes);
-                    if (!buf) return fail(ctx, AGIS_E_OOM, "allocate row pick table: out of device memory");
-                } else {
-                    AGIS_HIP(ctx, hipMalloc(&buf, nbytes), "allocate row pick table");
-                }
+                buf = (uint64_t*)table_alloc(ctx, cache, keep, nbytes);
+                if (!buf) return fail(ctx, AGIS_E_OOM, "allocate row pick table: out of device memory");
                 const hipError_t e = agis::launch_rowtab(ctx, g->g, sw, buf, st->long_rows);
                 if (e != hipSuccess) {
                     (void)hipFree(buf);
@@ -611,12 +635,8 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
     }
     // a new first-step buffer: from the fixed workspace, the cache or the call
     auto alloc1 = [&](void** p, uint64_t nbytes, const char* what) -> int {
-        if (keep1) {
-            *p = cache->alloc(nbytes);
-            return *p ? AGIS_OK : fail(ctx, AGIS_E_OOM, std::string(what) + ": out of device memory");
-        }
-        AGIS_HIP(ctx, hipMalloc(p, nbytes), what);
-        return AGIS_OK;
+        *p = table_alloc(ctx, cache, keep1, nbytes);
+        return *p ? AGIS_OK : fail(ctx, AGIS_E_OOM, std::string(what) + ": out of device memory");
     };
     if (!c1 && hp.weighted[0] && g->g.n > 0 && blocked) {
         const uint64_t nblk = (g->g.n + agis::kStep1Block - 1) / agis::kStep1Block;

@@ -2975,13 +2975,13 @@ int plan_sample_launch(agis_ctx* ctx, const agis_graph& g, uint64_t max_slots, u
     // wave's two scratch arrays start on a 64-byte boundary
     L->cap = ((uint64_t)g.max_deg + 1 + 15) / 16 * 16;
     const uint64_t per_wave = L->cap * 2 * sizeof(uint32_t);
-    // scratch budget: a quarter of the free device memory, within [8, 64] GiB
-    // (a wave may need a whole maximum-degree list: at R-MAT scale 24 that is
-    // ~6 MB per wave, 46 GB for a full grid)
+    // scratch budget: half of the free device memory, within [8, 64] GiB (a
+    // wave may need a whole maximum-degree list: 3.2 MB per wave at R-MAT
+    // scale 24, 48 MB at scale 30, where the budget sets the number of waves)
     uint64_t budget = 8ull << 30;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-        const uint64_t q = (uint64_t)free_b / 4 + ctx->scratch_bytes / 4;
+        const uint64_t q = (uint64_t)free_b / 2 + ctx->scratch_bytes / 2;
         budget = q < (8ull << 30) ? (8ull << 30) : (q > (64ull << 30) ? (64ull << 30) : q);
     }
     L->variant = ctx->tune_variant;
