@@ -82,3 +82,36 @@ def test_four_star_matches_closed_form(r20):
     exact = int(sum(math.perm(int(x), 4) for x in d[d >= 4]))
     r = s.estimate(G, T, synth.named_pattern("4-star"), 1 << 22, 5, mode="switch")
     _check(r, exact, "4-star")
+
+
+def test_batch_to_eps_in_one_launch_equals_host_rounds(r20):
+    """The bench's 32-pattern batch on this graph (seed 3, budgets
+    log-uniform in [10^6, 10^9], +-1% at 95%, checks every 2^16 from 2^14):
+    the one-launch run stops every pattern at the same sample count as the
+    round-by-round run with the checks on the host, with the same estimate."""
+    g, s, G, T, O, TO = r20
+    pset = synth.random_pattern_set(32, seed=3)
+    pats, budgets = [p for p, _ in pset], [b for _, b in pset]
+    kw = dict(mode="switch", eps=0.01, delta=0.05, check_every=1 << 16, min_samples=1 << 14)
+    dev = s.estimate_batch(G, T, pats, budgets, 13, **kw)
+    host = s.estimate_batch(G, T, pats, budgets, 13, host_rounds=True, **kw)
+    say(f"batch: {sum(r.converged for r in dev)}/32 converged, {sum(r.n for r in dev)} samples")
+    for a, b in zip(dev, host):
+        assert a.n == b.n and a.converged == b.converged and a.n_nonzero == b.n_nonzero
+        assert abs(a.estimate - b.estimate) <= 1e-12 * abs(b.estimate)
+
+
+@pytest.mark.parametrize("mode", ["switch", "always", "uniform"])
+def test_time_to_eps_in_one_launch_equals_host_rounds(r20, mode):
+    """The bench's time-to-+-1% runs (checks every 4,096 from 4,096, budget
+    10^8) of the four headline patterns: same stop points and estimates on
+    both paths."""
+    g, s, G, T, O, TO = r20
+    kw = dict(mode=mode, eps=0.01, delta=0.05, check_every=4096, min_samples=4096)
+    for pid, name in enumerate(["5-clique", "5-cycle", "house", "4-star"]):
+        p = synth.named_pattern(name)
+        a = s.estimate(G, T, p, 10 ** 8, 17, pattern_id=pid, **kw)
+        b = s.estimate(G, T, p, 10 ** 8, 17, pattern_id=pid, host_rounds=True, **kw)
+        say(f"{name} {mode}: {a.n} samples, converged {bool(a.converged)}")
+        assert a.n == b.n and a.converged == b.converged
+        assert abs(a.estimate - b.estimate) <= 1e-12 * abs(b.estimate)
