@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_sample_rmat20_counters.json")
 GOLDEN_5CLIQUE = os.path.join(ROOT, "tests", "golden", "rmat20_clique_counts.txt")
 KERNEL_SOURCES = ["paper_2601_01388_amd/csrc/kernels.hip", "paper_2601_01388_amd/csrc/agis_common.h"]
-GATHER_SIZES = [4, 16, 64, 256, 1024]
+GATHER_SIZES = [4, 16, 32, 64, 128, 256, 1024]
 
 
 def log(msg):
@@ -218,8 +218,10 @@ def cpu_baseline(g, c1, seconds_target: float):
     nall = max(n1, int(0.35 * seconds_target * threads / max(sum(per), 1e-9)))
     t0 = time.perf_counter()
     used = threads
-    for s in samplers:
-        _, used = s.run_parallel(0, nall, threads=threads)
+    means = {}
+    for name, s in zip(PATTERNS, samplers):
+        st, used = s.run_parallel(0, nall, threads=threads)
+        means[name] = st.mean
     elall = time.perf_counter() - t0
     # C1 in full on every core
     tc = oracle.Tables(c1, cv_seed=1, threads=threads)
@@ -241,6 +243,8 @@ def cpu_baseline(g, c1, seconds_target: float):
                    f"sample indices per pattern with the OpenMP oracle on {used} threads ({elall:.1f} s); "
                    f"single-threaded: first {n1} per pattern ({el1:.1f} s)"),
         "single_thread_value": len(PATTERNS) * n1 / el1,
+        "rmat20_samples_per_pattern": nall,
+        "rmat20_means": means,
         "c1_full": {"samples": 9 * 10 ** 6, "seconds": elc1, "threads": used, "samples_per_s": 9e6 / elc1,
                     "runs": c1_runs},
         "host": info,
@@ -1008,6 +1012,16 @@ def main():
         if hb is not None:
             hbm_total += hb * nsamp
     achieved = bytes_total / kern_total / 1e9
+    # L2 hit rate of the k_sample dispatches (counter pass), weighted by time
+    l2_hit = None
+    if counters:
+        num = den = 0.0
+        for nm in PATTERNS:
+            e = counters["per_pattern"].get(nm)
+            if e and meter[nm]["kernel"] == "k_sample" and e.get("l2_hit_rate") is not None:
+                num += e["l2_hit_rate"] * per_pattern[nm]["kernel_s"]
+                den += per_pattern[nm]["kernel_s"]
+        l2_hit = num / den if den else None
     seg_total = sum(meter[nm]["segments_per_sample"] * per_pattern[nm]["samples"] for nm in PATTERNS
                     if meter[nm]["kernel"] == "k_sample")
     bytes_per_segment = bytes_total / max(seg_total, 1.0)
@@ -1056,6 +1070,7 @@ def main():
         "traffic_gbs": hbm_total / kern_total / 1e9 if counters else None,
         "traffic_source": os.path.relpath(COUNTERS_FILE, ROOT) if counters else None,
         "patterns": [nm for nm in PATTERNS if meter[nm]["kernel"] == "k_sample"],
+        "l2_hit_rate": l2_hit,
     }
     if lanes["launches"]:
         la = lanes["bytes"] / lanes["kernel_s"] / 1e9
@@ -1113,6 +1128,17 @@ def main():
                      for k, v in cpu["c1_full"]["runs"].items()]
             detail["c1_gpu_vs_oracle_max_rel_diff"] = max(diffs)
             log(f"C1: GPU vs oracle estimates, largest relative difference {max(diffs):.2e}")
+        # the same R-MAT-20 sample indices on the GPU (the estimator's mean
+        # over samples [0, n) of each pattern, as the oracle ran them)
+        nr = cpu["rmat20_samples_per_pattern"]
+        rd = []
+        for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
+            r = sess.estimate(G, T, p, nr, 7, mode="switch", pattern_id=pid, rowtab=rowtab)
+            ref = cpu["rmat20_means"][name]
+            rd.append(abs(r.estimate - ref) / max(abs(ref), 1e-300))
+        cpu["rmat20_gpu_vs_oracle_max_rel_diff"] = max(rd)
+        log(f"R-MAT-20: GPU vs oracle means over the first {nr} samples of each pattern, largest relative "
+            f"difference {max(rd):.2e}")
 
     detail["wall_seconds"] = time.perf_counter() - wall0
     try:
@@ -1147,7 +1173,9 @@ def main():
         "estimates": {k: {"estimate": v["estimate"], "rel_err_vs_exact": v.get("rel_err_vs_exact")}
                       for k, v in per_pattern.items()},
         "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
-                                              "avg_launch_ms", "traffic_gbs", "traffic_frac", "gather_peak_gbs",
+                                              "avg_launch_ms", "traffic_gbs", "traffic_frac", "l2_hit_rate",
+                                              "gather_ceiling_gbs", "gather_ceiling_segment_bytes",
+                                              "requests_over_matched_gather_ceiling", "gather_peak_gbs",
                                               "traffic_frac_of_gather_peak", "gather_ceiling_footprint",
                                               "merge_model_gbs", "traffic_source")},
     }
@@ -1177,6 +1205,7 @@ def main():
     if cpu:
         out["cpu_baseline"] = {"value": cpu["value"], "unit": cpu["unit"], "cores": cpu["cores"], "kind": "oracle",
                                "sample": cpu["sample"], "single_thread_value": cpu["single_thread_value"],
+                               "gpu_vs_oracle_max_rel_diff": cpu.get("rmat20_gpu_vs_oracle_max_rel_diff"),
                                "c1_full_seconds": round(cpu["c1_full"]["seconds"], 2),
                                "host_model": cpu["host"]["model"], "nproc": cpu["host"]["nproc"]}
     out["detail"] = os.path.relpath(args.detail, ROOT)

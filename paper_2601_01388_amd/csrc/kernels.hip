@@ -2370,8 +2370,8 @@ __device__ __forceinline__ double lane_sample(const DevGraph& g, const DevPlan* 
     // step 0: the weighted first-step table (through its guide) or an
     // edge-uniform slot
     {
-        uint64_t num, den;
-        uint32_t v;
+        uint64_t num = 0, den = 1;
+        uint32_t v = 0;
         bool ok = true;
         if (P->weighted[0]) {
             if (P->s1_total == 0) {

@@ -338,21 +338,24 @@ def test_rmat20_full_size_sampled_parity(sess, rmat20):
 
 
 def test_rmat20_estimates_match_oracle(sess, rmat20):
-    """The production sampler (count-only last steps, the pair-hub count
-    table for common neighbours of two top hubs) against the oracle's mean
-    over the same sample indices of the full-size graph."""
+    """The production sampler as the bench runs it (count-only last steps,
+    the pair-hub count table for common neighbours of two top hubs, row
+    pick tables on and off, the lane sampler for the 4-star) against the
+    oracle's mean over the same sample indices of the full-size graph (the
+    oracle on all host threads, one sampler per thread)."""
     g = rmat20
     G = sess.graph(g.off, g.nbr)
     T = sess.tables(G, cv_seed=CV_SEED)
-    OT = oracle.Tables(g, cv_seed=CV_SEED)
-    n = 20_000
-    for name in ("5-cycle", "house", "4-cycle", "triangle"):
+    OT = oracle.Tables(g, cv_seed=CV_SEED, threads=0)
+    for name, n in (("5-clique", 1 << 15), ("5-cycle", 1 << 17), ("house", 1 << 17), ("4-star", 1 << 16),
+                    ("4-cycle", 1 << 17), ("triangle", 1 << 17)):
         p = synth.named_pattern(name)
-        say(f"R-MAT-20 estimate {name}")
-        r = sess.estimate(G, T, p, n, SEED, mode="switch")
-        st, _, _ = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="switch"), seed=SEED).run(0, n)
-        assert r.n == n
-        assert abs(r.estimate - st.mean) <= 1e-9 * abs(st.mean), (name, r.estimate, st.mean)
+        st, _ = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="switch"), seed=SEED).run_parallel(0, n)
+        for rowtab in ("on", "off"):
+            say(f"R-MAT-20 estimate {name} n={n} rowtab={rowtab}")
+            r = sess.estimate(G, T, p, n, SEED, mode="switch", rowtab=rowtab)
+            assert r.n == n
+            assert abs(r.estimate - st.mean) <= 1e-9 * abs(st.mean), (name, rowtab, r.estimate, st.mean)
     T.close()
     G.close()
 
