@@ -156,6 +156,16 @@ struct DevTables {
     // positions j d / kPairParts (j = 1 .. kPairParts - 1) of the walked list
     // (the shorter of the two by (degree, id))
     AGIS_GMEM const uint32_t* pair_quart;
+    // the common neighbours of every pair among the "core" hubs (the
+    // highest-degree pair hubs, within a memory budget): core_slot[v] >= 0
+    // for a core vertex, and the list of the pair with slots (a, b), either
+    // order, is core_nbr[core_start[a * cores + b] ...] of core_len[a * cores
+    // + b] vertices, ascending (cores = 0: none)
+    AGIS_GMEM const int32_t* core_slot;
+    AGIS_GMEM const uint64_t* core_start;
+    AGIS_GMEM const uint32_t* core_len;
+    AGIS_GMEM const uint32_t* core_nbr;
+    uint64_t cores;
 };
 
 constexpr int kPairParts = 8;

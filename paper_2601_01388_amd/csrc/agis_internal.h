@@ -89,6 +89,12 @@ struct agis_tables {
     uint32_t* pair_quart = nullptr;
     uint64_t pairs = 0;
     uint32_t pair_min_degree = 0;
+    // common-neighbour lists of the core pairs (see DevTables)
+    int32_t* core_slot = nullptr;
+    uint64_t* core_start = nullptr;
+    uint32_t* core_len = nullptr;
+    uint32_t* core_nbr = nullptr;
+    uint64_t cores = 0;
 };
 
 namespace agis {
@@ -230,6 +236,17 @@ struct SampleLaunch {
 // The sampling kernel for (record-writing?, register-budget variant 0..2,
 // pair-hub paths?).
 const void* sample_kernel(bool dump, int variant, bool pairs, bool meter);
+// Degrees of the pair hubs (deg[i] of pair_hub[i]).
+hipError_t launch_pair_hub_degrees(agis_ctx* ctx, const DevGraph& g, const uint32_t* pair_hub, uint64_t H,
+                                   uint32_t* deg);
+// Core-pair lists: core_slot[core_vertex[c]] = c, and for every pair a < b
+// of core slots the common neighbours of the two vertices, ascending, at
+// core_nbr + core_start[a * C + b] (walking the shorter list and probing the
+// other's hub bitmap).
+hipError_t launch_core_pairs(agis_ctx* ctx, const DevGraph& g, const int32_t* hub_slot, const uint32_t* hub_bits,
+                             uint64_t hub_words, const uint32_t* core_vertex, uint64_t C, int32_t* core_slot,
+                             const uint64_t* core_start, const uint32_t* core_len, uint32_t* core_nbr);
+
 // The lane sampler for (record-writing?, metering?).
 const void* sample_lanes_kernel(bool dump, bool meter);
 // Whether the lane sampler serves a plan: every step after the first is a

@@ -292,6 +292,96 @@ constexpr uint64_t kHubBitmapBudget = 1ull << 30;
 constexpr uint64_t kPairHubs = 8192;
 constexpr double kPairWork = 6.0e10;
 
+// Core-pair lists: the common neighbours of every pair among the
+// highest-degree pair hubs, so that a candidate set over two such hubs is
+// read as one list instead of walking one hub's list against the other's
+// bitmap.  The core is the top C pair hubs by (degree, id) for the largest C
+// (at most kCoreMax) whose lists, sized from the pair-count table, fit in
+// kCorePairBudget and in an eighth of the free memory.  A graph without
+// room for them samples without them (the samples are the same).
+constexpr uint64_t kCorePairBudget = 4ull << 30;
+constexpr uint64_t kCoreMax = 4096;
+
+hipError_t build_core_pairs(agis_ctx* ctx, const agis_graph* g, agis_tables* t, const uint32_t* pair_hub,
+                            uint64_t H) {
+    const uint64_t n = g->g.n;
+    std::vector<uint32_t> hub(H), deg(H), cnt(H * H);
+    uint32_t* d_deg = nullptr;
+    hipError_t e = hipMalloc(&d_deg, H * sizeof(uint32_t));
+    if (e == hipSuccess) e = agis::launch_pair_hub_degrees(ctx, g->g, pair_hub, H, d_deg);
+    if (e == hipSuccess) e = hipMemcpyAsync(deg.data(), d_deg, H * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hub.data(), pair_hub, H * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cnt.data(), t->pair_count, H * H * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (d_deg) (void)hipFree(d_deg);
+    if (e != hipSuccess) return e;
+    std::vector<uint32_t> order(H);
+    for (uint32_t i = 0; i < H; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return deg[a] != deg[b] ? deg[a] > deg[b] : hub[a] < hub[b];
+    });
+    uint64_t budget = kCorePairBudget;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget = std::min<uint64_t>(budget, (uint64_t)free_b / 8);
+    const uint64_t cap = budget / sizeof(uint32_t);
+    uint64_t total = 0, C = 0;
+    for (uint64_t c = 0; c < std::min<uint64_t>(H, kCoreMax); ++c) {
+        uint64_t add = 0;
+        for (uint64_t j = 0; j < c; ++j) add += cnt[(uint64_t)order[c] * H + order[j]];
+        const uint64_t index_bytes = (c + 1) * (c + 1) * (sizeof(uint64_t) + sizeof(uint32_t));
+        if ((total + add) * sizeof(uint32_t) + index_bytes > budget || total + add > cap) break;
+        total += add;
+        C = c + 1;
+    }
+    if (C < 2) return hipSuccess;
+    std::vector<uint32_t> vert(C), len(C * C, 0u);
+    std::vector<uint64_t> start(C * C, 0ull);
+    for (uint64_t c = 0; c < C; ++c) vert[c] = hub[order[c]];
+    uint64_t run = 0;
+    for (uint64_t a = 0; a < C; ++a)
+        for (uint64_t b = a + 1; b < C; ++b) {
+            const uint32_t l = cnt[(uint64_t)order[a] * H + order[b]];
+            start[a * C + b] = start[b * C + a] = run;
+            len[a * C + b] = len[b * C + a] = l;
+            run += l;
+        }
+    uint32_t* d_vert = nullptr;
+    e = hipMalloc(&t->core_slot, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&t->core_start, C * C * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&t->core_len, C * C * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&t->core_nbr, std::max<uint64_t>(run, 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&d_vert, C * sizeof(uint32_t));
+    if (e == hipSuccess) e = agis::launch_fill_u32((uint32_t*)t->core_slot, n, 0xFFFFFFFFu, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t->core_start, start.data(), C * C * sizeof(uint64_t), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t->core_len, len.data(), C * C * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_vert, vert.data(), C * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = agis::launch_core_pairs(ctx, g->g, t->hub_slot, t->hub_bits, t->hub_words, d_vert, C, t->core_slot,
+                                    t->core_start, t->core_len, t->core_nbr);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (d_vert) (void)hipFree(d_vert);
+    if (e == hipSuccess) {
+        t->cores = C;
+        return hipSuccess;
+    }
+    // no room (or a failed build): sample without the core lists
+    for (void* q : {(void*)t->core_slot, (void*)t->core_start, (void*)t->core_len, (void*)t->core_nbr})
+        if (q) (void)hipFree(q);
+    t->core_slot = nullptr;
+    t->core_start = nullptr;
+    t->core_len = nullptr;
+    t->core_nbr = nullptr;
+    t->cores = 0;
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return hipSuccess;
+    }
+    return e;
+}
+
 hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t) {
     const uint64_t n = g->g.n;
     const uint64_t words = (n + 31) / 32;
@@ -396,6 +486,7 @@ hipError_t build_hub_bitmaps(agis_ctx* ctx, const agis_graph* g, agis_tables* t)
             t->pairs = H;
             t->pair_min_degree = 1u << pb;
         }
+        if (e == hipSuccess && t->pair_count) e = build_core_pairs(ctx, g, t, pair_hub, H);
     }
     if (pair_hub) (void)hipFree(pair_hub);
     if (flags) (void)hipFree(flags);
@@ -407,7 +498,10 @@ agis::DevTables dev_tables(const agis_tables* t) {
     return agis::DevTables{agis::gmem((const uint4*)t->rec),        agis::gmem((const uint32_t*)t->hub_bits),
                            agis::gmem((const int32_t*)t->hub_slot),    t->hub_words,
                            agis::gmem((const int32_t*)t->pair_slot),   agis::gmem((const uint32_t*)t->pair_count),
-                           t->pair_count ? t->pairs : 0,               agis::gmem((const uint32_t*)t->pair_quart)};
+                           t->pair_count ? t->pairs : 0,               agis::gmem((const uint32_t*)t->pair_quart),
+                           agis::gmem((const int32_t*)t->core_slot),   agis::gmem((const uint64_t*)t->core_start),
+                           agis::gmem((const uint32_t*)t->core_len),   agis::gmem((const uint32_t*)t->core_nbr),
+                           t->cores};
 }
 
 // Device memory for a proposal table: from the cache (keep) or the call.
@@ -1368,6 +1462,8 @@ void agis_tables_destroy(agis_tables* t) {
     if (t->pair_slot) (void)hipFree(t->pair_slot);
     if (t->pair_count) (void)hipFree(t->pair_count);
     if (t->pair_quart) (void)hipFree(t->pair_quart);
+    for (void* q : {(void*)t->core_slot, (void*)t->core_start, (void*)t->core_len, (void*)t->core_nbr})
+        if (q) (void)hipFree(q);
     delete t;
 }
 

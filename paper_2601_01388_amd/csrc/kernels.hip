@@ -1098,6 +1098,74 @@ hipError_t launch_pair_counts(agis_ctx* ctx, const DevGraph& g, const int32_t* h
     return hipGetLastError();
 }
 
+__global__ void k_pair_hub_degrees(DevGraph g, const uint32_t* __restrict__ pair_hub, uint64_t H,
+                                   uint32_t* __restrict__ deg) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < H) deg[i] = (uint32_t)(g.off[pair_hub[i] + 1] - g.off[pair_hub[i]]);
+}
+
+__global__ void k_core_slots(const uint32_t* __restrict__ core_vertex, uint64_t C, int32_t* __restrict__ core_slot) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C) core_slot[core_vertex[c]] = (int32_t)c;
+}
+
+// One wave per pair a < b of core slots: the shorter list (by (degree, id))
+// is walked in order and its members of the other list (one bit probe of
+// that vertex's hub bitmap each) are appended by ballot, so the list comes
+// out ascending.
+__global__ __launch_bounds__(256) void k_core_fill(DevGraph g, const int32_t* __restrict__ hub_slot,
+                                                    const uint32_t* __restrict__ hub_bits, uint64_t hub_words,
+                                                    const uint32_t* __restrict__ core_vertex, uint64_t C,
+                                                    const uint64_t* __restrict__ core_start,
+                                                    const uint32_t* __restrict__ core_len,
+                                                    uint32_t* __restrict__ core_nbr) {
+    const int lane = lane_id();
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t pr = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; pr < C * C; pr += nw) {
+        const uint64_t a = pr / C, b = pr % C;
+        if (a >= b) continue;  // wave-uniform
+        const uint32_t va = core_vertex[a], vb = core_vertex[b];
+        const uint64_t oa = g.off[va], ob = g.off[vb];
+        const uint64_t da = g.off[va + 1] - oa, db = g.off[vb + 1] - ob;
+        const bool walk_a = da < db || (da == db && va < vb);
+        const uint64_t o = walk_a ? oa : ob, d = walk_a ? da : db;
+        const uint32_t* bits = hub_bits + (uint64_t)hub_slot[walk_a ? vb : va] * hub_words;
+        uint32_t* out = core_nbr + core_start[pr];
+        const uint64_t len = core_len[pr];  // the pair's range: no write beyond it
+        uint64_t at = 0;
+        for (uint64_t e0 = 0; e0 < d; e0 += kWave) {
+            const uint64_t e = e0 + (uint64_t)lane;
+            bool m = false;
+            uint32_t x = 0;
+            if (e < d) {
+                x = g.nbr[o + e];
+                m = ((bits[x >> 5] >> (x & 31u)) & 1u) != 0u;
+            }
+            const uint64_t bm = __ballot(m);
+            const uint64_t w = at + (uint64_t)__popcll(bm & lanemask_lt());
+            if (m && w < len) out[w] = x;
+            at += (uint64_t)__popcll(bm);
+        }
+    }
+}
+
+hipError_t launch_pair_hub_degrees(agis_ctx* ctx, const DevGraph& g, const uint32_t* pair_hub, uint64_t H,
+                                   uint32_t* deg) {
+    hipLaunchKernelGGL(k_pair_hub_degrees, dim3(grid_for(H, 256)), dim3(256), 0, ctx->stream, g, pair_hub, H, deg);
+    return hipGetLastError();
+}
+
+hipError_t launch_core_pairs(agis_ctx* ctx, const DevGraph& g, const int32_t* hub_slot, const uint32_t* hub_bits,
+                             uint64_t hub_words, const uint32_t* core_vertex, uint64_t C, int32_t* core_slot,
+                             const uint64_t* core_start, const uint32_t* core_len, uint32_t* core_nbr) {
+    hipLaunchKernelGGL(k_core_slots, dim3(grid_for(C, 256)), dim3(256), 0, ctx->stream, core_vertex, C, core_slot);
+    const uint64_t waves = C * C;
+    const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, (uint64_t)ctx->num_cus * 8);
+    hipLaunchKernelGGL(k_core_fill, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, g, hub_slot, hub_bits,
+                       hub_words, core_vertex, C, core_start, core_len, core_nbr);
+    return hipGetLastError();
+}
+
 hipError_t launch_orient_fill(const DevGraph& g, const uint64_t* off_out, uint32_t* nbr_out, hipStream_t stream) {
     hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(g.n, 256)), dim3(256), 0, stream, g, off_out, nbr_out);
     return hipGetLastError();
@@ -1861,17 +1929,40 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     db = (uint32_t)scnt;
                     others = lists;
                 } else {
-                    // base = smallest degree, ties to the smallest position
-                    uint64_t key = ((uint64_t)my_d << 8) | (uint64_t)lane;
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        uint64_t w2 = __shfl_xor(key, o, kWave);
-                        key = w2 < key ? w2 : key;
+                    // Two backward vertices of the core: start from their
+                    // common-neighbour list (ascending: the set and order a
+                    // walk of one list against the other would produce) and
+                    // intersect only the remaining lists.
+                    int32_t my_core = -1;
+                    if (t.cores != 0) {
+                        const bool cand = (uint32_t)lane < i && (lists >> lane & 1u);
+                        mt.vec(t.core_slot + my_tau, 4, cand);
+                        if (cand) my_core = t.core_slot[my_tau];
                     }
-                    const int jb = (int)(key & 0xFF);
-                    base = g.nbr + readlane_u64(my_o, jb);
-                    db = readlane_u32(my_d, jb);
-                    others = uniform_u32(lists & ~(1u << jb));
+                    const uint64_t cm = __ballot(my_core >= 0);
+                    if (__popcll(cm) >= 2) {
+                        const int ja = __ffsll((unsigned long long)cm) - 1;
+                        const int jc = __ffsll((unsigned long long)(cm & (cm - 1))) - 1;
+                        const uint64_t pr = (uint64_t)readlane_u32((uint32_t)my_core, ja) * t.cores +
+                                            (uint64_t)readlane_u32((uint32_t)my_core, jc);
+                        mt.uni(t.core_start + pr, 8);
+                        mt.uni(t.core_len + pr, 4);
+                        base = t.core_nbr + t.core_start[pr];
+                        db = t.core_len[pr];
+                        others = uniform_u32(lists & ~(1u << ja) & ~(1u << jc));
+                    } else {
+                        // base = smallest degree, ties to the smallest position
+                        uint64_t key = ((uint64_t)my_d << 8) | (uint64_t)lane;
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) {
+                            uint64_t w2 = __shfl_xor(key, o, kWave);
+                            key = w2 < key ? w2 : key;
+                        }
+                        const int jb = (int)(key & 0xFF);
+                        base = g.nbr + readlane_u64(my_o, jb);
+                        db = readlane_u32(my_d, jb);
+                        others = uniform_u32(lists & ~(1u << jb));
+                    }
                 }
                 const uint32_t b = P->b[i], f1 = P->f1[i], ie = P->ie[i], f2 = P->f2[i];
                 const AGIS_GMEM int32_t* lt = P->lt[i];
