@@ -168,6 +168,9 @@ struct DevTables {
     uint64_t cores;
 };
 
+// Every core-pair list starts on a block of this many entries.
+constexpr uint64_t kCoreBlock = 64;
+
 constexpr int kPairParts = 8;
 
 struct DevPlan {
@@ -206,6 +209,14 @@ struct DevPlan {
     // s1_lmax, and the guide indexes blocks
     int32_t s1_lmax;
     AGIS_GMEM const uint64_t* s1_blk;
+    // step 2 when its backward vertices are the two matched ones (the first
+    // three pattern vertices form a triangle) and it is weighted: the pick
+    // table of its signature over the core-pair lists -- per list entry the
+    // integer weight against the list's largest log weight (cq), and per
+    // block of kCoreBlock entries the inclusive prefix within the list (cbp,
+    // indexed by entry / kCoreBlock) -- or nullptr
+    AGIS_GMEM const uint32_t* cq2;
+    AGIS_GMEM const uint64_t* cbp2;
 };
 
 constexpr uint32_t kStep1Block = 256;

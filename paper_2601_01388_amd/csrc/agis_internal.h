@@ -95,6 +95,7 @@ struct agis_tables {
     uint32_t* core_len = nullptr;
     uint32_t* core_nbr = nullptr;
     uint64_t cores = 0;
+    uint64_t core_entries = 0;  // entries of core_nbr (lists padded to kCoreBlock)
 };
 
 namespace agis {
@@ -246,6 +247,10 @@ hipError_t launch_pair_hub_degrees(agis_ctx* ctx, const DevGraph& g, const uint3
 hipError_t launch_core_pairs(agis_ctx* ctx, const DevGraph& g, const int32_t* hub_slot, const uint32_t* hub_bits,
                              uint64_t hub_words, const uint32_t* core_vertex, uint64_t C, int32_t* core_slot,
                              const uint64_t* core_start, const uint32_t* core_len, uint32_t* core_nbr);
+
+// The pick table of one step signature (per-vertex log weights sw, certain
+// zeros folded in) over the core-pair lists: cq[entry], cbp[entry / kCoreBlock].
+hipError_t launch_core_pick(agis_ctx* ctx, const agis_tables& t, const int32_t* sw, uint32_t* cq, uint64_t* cbp);
 
 // The lane sampler for (record-writing?, metering?).
 const void* sample_lanes_kernel(bool dump, bool meter);

@@ -146,7 +146,7 @@ struct Prepared {
 // tables of one graph.
 }  // namespace
 
-enum CacheKind : uint32_t { kCacheStepWeights = 0, kCacheRowPick = 1, kCacheFirstStep = 2 };
+enum CacheKind : uint32_t { kCacheStepWeights = 0, kCacheRowPick = 1, kCacheFirstStep = 2, kCacheCorePick = 3 };
 struct CacheEntry {
     uint32_t kind = 0, b = 0, f1 = 0, ie = 0, f2 = 0, blocked = 0;
     void* buf[3] = {nullptr, nullptr, nullptr};
@@ -325,10 +325,13 @@ hipError_t build_core_pairs(agis_ctx* ctx, const agis_graph* g, agis_tables* t, 
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget = std::min<uint64_t>(budget, (uint64_t)free_b / 8);
     const uint64_t cap = budget / sizeof(uint32_t);
+    // every pair's list starts on a block of agis::kCoreBlock entries (the
+    // pick tables over the lists keep one prefix per block)
+    auto padded = [](uint64_t l) { return (l + agis::kCoreBlock - 1) / agis::kCoreBlock * agis::kCoreBlock; };
     uint64_t total = 0, C = 0;
     for (uint64_t c = 0; c < std::min<uint64_t>(H, kCoreMax); ++c) {
         uint64_t add = 0;
-        for (uint64_t j = 0; j < c; ++j) add += cnt[(uint64_t)order[c] * H + order[j]];
+        for (uint64_t j = 0; j < c; ++j) add += padded(cnt[(uint64_t)order[c] * H + order[j]]);
         const uint64_t index_bytes = (c + 1) * (c + 1) * (sizeof(uint64_t) + sizeof(uint32_t));
         if ((total + add) * sizeof(uint32_t) + index_bytes > budget || total + add > cap) break;
         total += add;
@@ -344,8 +347,9 @@ hipError_t build_core_pairs(agis_ctx* ctx, const agis_graph* g, agis_tables* t, 
             const uint32_t l = cnt[(uint64_t)order[a] * H + order[b]];
             start[a * C + b] = start[b * C + a] = run;
             len[a * C + b] = len[b * C + a] = l;
-            run += l;
+            run += padded(l);
         }
+    t->core_entries = run;
     uint32_t* d_vert = nullptr;
     e = hipMalloc(&t->core_slot, n * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&t->core_start, C * C * sizeof(uint64_t));
@@ -375,6 +379,7 @@ hipError_t build_core_pairs(agis_ctx* ctx, const agis_graph* g, agis_tables* t, 
     t->core_len = nullptr;
     t->core_nbr = nullptr;
     t->cores = 0;
+    t->core_entries = 0;
     if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
         return hipSuccess;
@@ -704,6 +709,46 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         const int32_t* buf = step_table(i);
         if (step_rc != AGIS_OK) return step_rc;
         if (buf) hp.sw[i] = agis::gmem(buf);
+    }
+    // the pick table over the core-pair lists for a weighted step 2 whose
+    // backward vertices are the two matched ones (built where row tables
+    // are, kept in the cache like them; not for learned weights)
+    if (want_rows && t->cores && hp.k > 2 && hp.weighted[2] && hp.bmask[2] == 3u && hp.lt[2] == nullptr &&
+        hp.sw[2] != nullptr && cache && t->core_entries * 4 + t->core_entries / 8 <= kRowtabBudgetBytes) {
+        CacheEntry* c = cache->find(kCacheCorePick, hp.b[2], hp.f1[2], hp.ie[2], hp.f2[2], 0);
+        if (c) {
+            st->held.push_back(c);
+        } else {
+            const uint64_t qb = t->core_entries * sizeof(uint32_t);
+            const uint64_t pb = (t->core_entries / agis::kCoreBlock + 1) * sizeof(uint64_t);
+            void* cq = table_alloc(ctx, cache, true, qb);
+            void* cbp = cq ? table_alloc(ctx, cache, true, pb) : nullptr;
+            hipError_t e = (cq && cbp) ? agis::launch_core_pick(ctx, *t, (const int32_t*)hp.sw[2], (uint32_t*)cq,
+                                                                (uint64_t*)cbp)
+                                       : hipErrorOutOfMemory;
+            if (e == hipSuccess) {
+                CacheEntry proto;
+                proto.kind = kCacheCorePick;
+                proto.b = hp.b[2];
+                proto.f1 = hp.f1[2];
+                proto.ie = hp.ie[2];
+                proto.f2 = hp.f2[2];
+                proto.buf[0] = cq;
+                proto.buf[1] = cbp;
+                proto.bytes = qb + pb;
+                c = cache->add(proto);
+                st->held.push_back(c);
+            } else {
+                if (cq) (void)hipFree(cq);
+                if (cbp) (void)hipFree(cbp);
+                if (e != hipErrorOutOfMemory) return hip_fail(ctx, e, "core-pair pick table");
+                (void)hipGetLastError();  // no room: step 2 walks the lists
+            }
+        }
+        if (c) {
+            hp.cq2 = agis::gmem((const uint32_t*)c->buf[0]);
+            hp.cbp2 = agis::gmem((const uint64_t*)c->buf[1]);
+        }
     }
     // the blocked first-step table (8 bytes per kStep1Block vertices instead
     // of 12 per vertex) when asked for, or by default when the full table

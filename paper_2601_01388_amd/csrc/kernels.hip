@@ -1149,6 +1149,53 @@ __global__ __launch_bounds__(256) void k_core_fill(DevGraph g, const int32_t* __
     }
 }
 
+// The pick table of one step signature over the core-pair lists, one wave
+// per pair: the list's largest non-certain log weight (the normalising
+// maximum over the intersection of the two backward lists), each entry's
+// integer weight against it (0 for certain zeros and for the padding), and
+// per block the inclusive prefix of the weights within the list.
+__global__ __launch_bounds__(256) void k_core_pick(const uint32_t* __restrict__ core_nbr,
+                                                    const uint64_t* __restrict__ core_start,
+                                                    const uint32_t* __restrict__ core_len, uint64_t C,
+                                                    const int32_t* __restrict__ sw, uint32_t* __restrict__ cq,
+                                                    uint64_t* __restrict__ cbp) {
+    const int lane = lane_id();
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t pr = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; pr < C * C; pr += nw) {
+        const uint64_t a = pr / C, b = pr % C;
+        if (a >= b) continue;  // wave-uniform; (b, a) shares the list
+        const uint64_t st = core_start[pr];
+        const uint64_t len = core_len[pr];
+        int32_t lm = kCertainZero;
+        for (uint64_t e = (uint64_t)lane; e < len; e += kWave) {
+            const int32_t l = sw[core_nbr[st + e]];
+            lm = l > lm ? l : lm;
+        }
+        lm = wave_max_i32(lm);
+        uint64_t run = 0;
+        for (uint64_t e0 = 0; e0 < len; e0 += kWave) {
+            const uint64_t e = e0 + (uint64_t)lane;  // inside the padded list
+            uint32_t q = 0;
+            if (e < len) {
+                const int32_t l = sw[core_nbr[st + e]];
+                q = l == kCertainZero ? 0u : weight_from_log(lm, l, c_exp2tab);
+            }
+            cq[st + e] = q;
+            run += wave_sum_u64(q);
+            if (lane == 0) cbp[(st + e0) / kCoreBlock] = run;
+        }
+    }
+}
+
+hipError_t launch_core_pick(agis_ctx* ctx, const agis_tables& t, const int32_t* sw, uint32_t* cq, uint64_t* cbp) {
+    const uint64_t C = t.cores;
+    const uint64_t waves = C * C;
+    const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, (uint64_t)ctx->num_cus * 8);
+    hipLaunchKernelGGL(k_core_pick, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, t.core_nbr, t.core_start,
+                       t.core_len, C, sw, cq, cbp);
+    return hipGetLastError();
+}
+
 hipError_t launch_pair_hub_degrees(agis_ctx* ctx, const DevGraph& g, const uint32_t* pair_hub, uint64_t H,
                                    uint32_t* deg) {
     hipLaunchKernelGGL(k_pair_hub_degrees, dim3(grid_for(H, 256)), dim3(256), 0, ctx->stream, g, pair_hub, H, deg);
@@ -1646,6 +1693,19 @@ __device__ __forceinline__ void meter_step_log_weight(const DevTables& t, const 
 // candidates per lane up to which a weighted pick keeps them in registers
 constexpr int kPickBlock = 8;
 
+// Whether the vertices matched at steps 0 and 1 (lanes 0 and 1) are both in
+// the core; pr = their pair's index.
+template <class MT>
+__device__ __forceinline__ bool core_pair01(const DevTables& t, uint32_t my_tau, uint64_t& pr, MT& mt) {
+    const int lane = lane_id();
+    mt.vec(t.core_slot + my_tau, 4, lane < 2);
+    const int32_t c = lane < 2 ? t.core_slot[my_tau] : -1;
+    const int32_t ca = (int32_t)readlane_u32((uint32_t)c, 0), cb = (int32_t)readlane_u32((uint32_t)c, 1);
+    if (ca < 0 || cb < 0) return false;
+    pr = (uint64_t)ca * t.cores + (uint64_t)cb;
+    return true;
+}
+
 template <bool kDump, bool kPairs, class MT>
 __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables& t, const DevPlan* __restrict__ P,
                              uint32_t k0, uint32_t k1, uint64_t s, uint32_t* __restrict__ sv,
@@ -1658,6 +1718,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
     // its position there (a later probe of the same row needs no search)
     uint32_t my_row = 0xFFFFFFFFu, my_rpos = 0;
     uint64_t scnt = 0;  // size of the candidate set the scratch holds
+    // the previous step's candidate set when it was a core-pair list drawn
+    // through its pick table (the next step starts from that list)
+    const uint32_t* core_set = nullptr;
     double x = 1.0;
     int fail = -1;
     uint32_t i = 0;
@@ -1756,6 +1819,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
             // kernel counts the set and skips the draw; the record-writing
             // variant still picks the vertex.
             const bool count_only = !kDump && !weighted && i + 1 == k;
+            const uint32_t* prev_core = core_set;
+            core_set = nullptr;
+            uint64_t cpr = 0;
             if (weighted && P->rowpre[i] != nullptr) {
                 // Weighted draw from S = N(w) minus the matched vertices
                 // through the row's prefix of integer weights: subtract the
@@ -1902,6 +1968,41 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, num);
                 v = pair_hub_select(g, t, my_tau, bm, i, r, num, mt);
                 den = 1;
+            } else if (i == 2 && bm == 3u && weighted && P->cq2 != nullptr && t.cores != 0 &&
+                       core_pair01(t, my_tau, cpr, mt)) {
+                // Step 2 over the two matched vertices, both in the core: the
+                // candidates are exactly their common-neighbour list (no
+                // matched vertex lies in it), drawn through the signature's
+                // pick table over the core lists -- the block holding r from
+                // the block prefixes, then the entry within the block.  The
+                // next step starts from the list itself.
+                mt.uni(t.core_start + cpr, 8);
+                mt.uni(t.core_len + cpr, 4);
+                const uint64_t st = t.core_start[cpr];
+                const uint32_t len = t.core_len[cpr];
+                const uint64_t nb = ((uint64_t)len + kCoreBlock - 1) / kCoreBlock;
+                const AGIS_GMEM uint64_t* bp = P->cbp2 + st / kCoreBlock;
+                if (nb) mt.uni(bp + nb - 1, 8);
+                const uint64_t Q = nb ? bp[nb - 1] : 0ull;
+                if (Q == 0) {
+                    fail = (int)i;
+                    break;
+                }
+                const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
+                const uint64_t kb = wave_first_greater(bp, nb, r, mt);
+                if (kb > 0) mt.uni(bp + kb - 1, 8);
+                const uint64_t before = kb > 0 ? bp[kb - 1] : 0ull;
+                const uint64_t e = kb * kCoreBlock + (uint64_t)lane;
+                mt.vec(P->cq2 + st + e, 4, e < len);
+                const uint32_t qv = e < len ? P->cq2[st + e] : 0u;
+                const uint64_t incl = wave_incl_scan_u64((uint64_t)qv);
+                const int L = __ffsll((unsigned long long)__ballot(before + incl > r)) - 1;
+                mt.uni(t.core_nbr + st + kb * kCoreBlock + (uint64_t)L, 4);
+                v = t.core_nbr[st + kb * kCoreBlock + (uint64_t)L];
+                num = Q;
+                den = readlane_u32(qv, L);
+                core_set = t.core_nbr + st;
+                scnt = len;
             } else {
                 // Candidate set I = intersection of the backward lists, S = I
                 // minus the matched vertices, in ascending id order.  The
@@ -1925,7 +2026,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 uint32_t db;
                 uint32_t others;
                 if (reuse) {
-                    base = sv;
+                    base = prev_core ? prev_core : sv;
                     db = (uint32_t)scnt;
                     others = lists;
                 } else {
