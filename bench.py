@@ -411,7 +411,8 @@ def ablation_leg(args, sess, G, T):
 
 def batch_leg(args, sess, G, T, restore_tuning):
     """32 connected patterns of 4-7 vertices (seed 3) with budgets
-    log-uniform in [10^6, 10^9], all run to +-1% in one batched run."""
+    log-uniform in [10^6, 10^9], all run to +-1% in one batched run, and
+    the same 32 runs one estimate at a time for comparison."""
     import torch
     import synth
     pset = synth.random_pattern_set(32, seed=3)
@@ -425,8 +426,17 @@ def batch_leg(args, sess, G, T, restore_tuning):
                               check_every=1 << 16, min_samples=1 << 14)
     torch.cuda.synchronize()
     bt = time.perf_counter() - t0
+    # the same 32 runs one estimate at a time (what the batch replaces)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one = [sess.estimate(G, T, p, b, 13, mode="switch", eps=0.01, delta=0.05, check_every=1 << 16,
+                         min_samples=1 << 14, pattern_id=pid) for pid, (p, b) in enumerate(zip(bpats, budgets))]
+    torch.cuda.synchronize()
+    st = time.perf_counter() - t0
     restore_tuning()
-    out = {"patterns": 32, "tuning": btune, "seconds": bt, "samples": int(sum(r.n for r in res)),
+    log(f"the same 32 runs one at a time: {st:.2f} s, {sum(r.n for r in one):.3g} samples")
+    out = {"patterns": 32, "tuning": btune, "seconds": bt, "one_at_a_time_seconds": st,
+           "one_at_a_time_samples": int(sum(r.n for r in one)), "samples": int(sum(r.n for r in res)),
            "converged": int(sum(r.converged for r in res)), "samples_per_s": sum(r.n for r in res) / bt,
            "budget_total": int(sum(budgets)),
            "per_pattern": [{"k": p.k, "edges": len(p.edges), "budget": b, "samples": r.n,
@@ -1194,7 +1204,8 @@ def main():
             for name in PATTERNS}
     if batch:
         out["batch32_rmat20"] = {"seconds": round(batch["seconds"], 3), "samples_per_s": batch["samples_per_s"],
-                                 "converged": batch["converged"]}
+                                 "converged": batch["converged"],
+                                 "one_at_a_time_seconds": round(batch["one_at_a_time_seconds"], 3)}
     if large:
         b = large["batch_32_patterns"]
         lp = large["learned_32_patterns"]
