@@ -680,16 +680,48 @@ def c5_leg(args, sess):
                            "rel_err": (r.estimate - exact) / exact}
         log(f"C5 {name}: {r.estimate:.6g} vs closed form {exact:.6g} (z {sentinels[name]['z']:.2f})")
     out["sentinels"] = sentinels
+    # the degree arithmetic's temporaries (8 GiB each) go back to the device:
+    # the sampler's scratch budget is a share of the free memory
     del d
+    torch.cuda.empty_cache()
     # learned tables: one network per pattern trained on extension counts of
-    # the R-MAT scale 20 graph, inferred on this graph's features
+    # the R-MAT scale 20 graph, inferred on this graph's features.  The
+    # non-learned modes run first, with nothing else resident: a wave's
+    # scratch holds a maximum-degree list here (48 MB), so the free memory
+    # sets the number of waves, and the features (16 GiB) and a pattern's
+    # learned tables (4 GiB per weighted step) are built only for its
+    # learned run and freed after it.
     g20 = synth.rmat(20, 16, seed=20)
     G20 = sess.graph(g20.off, g20.nbr)
     T20 = sess.tables(G20, cv_seed=1)
     f20 = sess.features(T20)
-    f30 = sess.features(T)
-    runs = {}
-    for pid, name in enumerate(("5-clique", "6-cycle", "chordal-7-cycle")):
+    names = ("5-clique", "6-cycle", "chordal-7-cycle")
+    labels = {"switch": "f_approx", "always": "f_approx_always", "uniform": "f_uniform", "learned": "learned"}
+    runs = {name: {} for name in names}
+
+    def run_mode(pid, name, p, mode, kw):
+        free_before = mem()
+        flag = ctypes.c_int32(0)
+        timer = threading.Timer(args.c5_seconds, lambda f=flag: setattr(f, "value", 1))
+        timer.start()
+        r = sess.estimate(G, T, p, args.c5_budget, 61 + pid, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
+                          check_every=1 << 14, min_samples=1 << 14, cancel=flag, **kw)
+        timer.cancel()
+        label = labels[mode]
+        need = r.n * (r.eps_hat / 0.01) ** 2 if r.n and math.isfinite(r.eps_hat) else None
+        runs[name][label] = {"seconds": r.seconds, "samples": r.n, "converged": bool(r.converged),
+                             "stopped_by_time_cap": r.status == -9, "estimate": r.estimate, "eps_hat": r.eps_hat,
+                             "rel_var": rel_var(r) if r.n else None, "samples_needed": need,
+                             "samples_per_s": r.n / r.seconds if r.seconds > 0 else None,
+                             "free_gib_before": free_before}
+        log(f"C5 +-1% {name} {label}: {r.seconds:.1f} s, n={r.n}, eps_hat {r.eps_hat:.4f}, "
+            f"converged={bool(r.converged)}, estimate {r.estimate:.6g} ({free_before} GiB free before)")
+
+    for pid, name in enumerate(names):
+        p = synth.named_pattern(name)
+        for mode in ("switch", "always", "uniform"):
+            run_mode(pid, name, p, mode, {})
+    for pid, name in enumerate(names):
         p = synth.named_pattern(name)
         steps = sess.weighted_steps(p, "learned")
         sums, counts = sess.learn_targets(G20, T20, p, 1 << 20, 501 + pid, mode="switch")
@@ -702,28 +734,17 @@ def c5_leg(args, sess):
                                            zero_output=True)).to(sess.device)
         per_epoch = max(1, -(-rows["rows"] // 4096))
         sess.mlp_train(params, f20, rows, epochs=max(20, -(-1500 // per_epoch)), batch=4096, lr=3e-3, seed=pid)
+        f30 = sess.features(T)
         base = sess.step_log_weights(T, p)
         tabs = sess.learned_tables(params, f30, p, base=base, rows=rows)
-        del base
+        del base, f30
+        torch.cuda.empty_cache()
         ptrs = {i: tab.data_ptr() for i, tab in tabs.items()}
-        row = {}
-        for mode in ("learned", "switch", "always", "uniform"):
-            flag = ctypes.c_int32(0)
-            timer = threading.Timer(args.c5_seconds, lambda f=flag: setattr(f, "value", 1))
-            timer.start()
-            kw = dict(learned=ptrs) if mode == "learned" else {}
-            r = sess.estimate(G, T, p, args.c5_budget, 61 + pid, mode=mode, pattern_id=pid, eps=0.01, delta=0.05,
-                              check_every=1 << 14, min_samples=1 << 14, cancel=flag, **kw)
-            timer.cancel()
-            label = {"switch": "f_approx", "always": "f_approx_always", "uniform": "f_uniform",
-                     "learned": "learned"}[mode]
-            need = r.n * (r.eps_hat / 0.01) ** 2 if r.n and math.isfinite(r.eps_hat) else None
-            row[label] = {"seconds": r.seconds, "samples": r.n, "converged": bool(r.converged),
-                          "stopped_by_time_cap": r.status == -9, "estimate": r.estimate, "eps_hat": r.eps_hat,
-                          "rel_var": rel_var(r) if r.n else None, "samples_needed": need,
-                          "samples_per_s": r.n / r.seconds if r.seconds > 0 else None}
-            log(f"C5 +-1% {name} {label}: {r.seconds:.1f} s, n={r.n}, eps_hat {r.eps_hat:.4f}, "
-                f"converged={bool(r.converged)}, estimate {r.estimate:.6g}")
+        run_mode(pid, name, p, "learned", dict(learned=ptrs))
+        del tabs, params, rows
+        torch.cuda.empty_cache()
+    for name in names:
+        row = runs[name]
         # cross-mode agreement of the estimates (each with its own standard error)
         labs = [k for k in row if row[k]["samples"]]
         worst = 0.0
@@ -736,9 +757,6 @@ def c5_leg(args, sess):
                     if se > 0:
                         worst = max(worst, abs(ra["estimate"] - rb["estimate"]) / se)
         row["max_cross_mode_z"] = worst
-        runs[name] = row
-        del tabs, params, rows
-        torch.cuda.empty_cache()
     out["to_1pct"] = runs
     # the 32-pattern batch (seed 3, budgets log-uniform in [10^6, 10^9]) to
     # +-1% in one launch, capped at --c5-batch-seconds through the cancel flag
@@ -764,7 +782,7 @@ def c5_leg(args, sess):
     G20.close()
     T.close()
     G.close()
-    del off, nbr, f30, f20
+    del off, nbr, f20
     torch.cuda.empty_cache()
     return out
 

@@ -340,7 +340,8 @@ def test_rmat20_full_size_sampled_parity(sess, rmat20):
 def test_rmat20_estimates_match_oracle(sess, rmat20):
     """The production sampler as the bench runs it (count-only last steps,
     the pair-hub count table for common neighbours of two top hubs, row
-    pick tables on and off, the lane sampler for the 4-star) against the
+    pick tables on and off, the lane sampler for the 4-star, the core-pair
+    lists and pick tables of the cliques) against the
     oracle's mean over the same sample indices of the full-size graph (the
     oracle on all host threads, one sampler per thread)."""
     g = rmat20
@@ -348,7 +349,8 @@ def test_rmat20_estimates_match_oracle(sess, rmat20):
     T = sess.tables(G, cv_seed=CV_SEED)
     OT = oracle.Tables(g, cv_seed=CV_SEED, threads=0)
     for name, n in (("5-clique", 1 << 15), ("5-cycle", 1 << 17), ("house", 1 << 17), ("4-star", 1 << 16),
-                    ("4-cycle", 1 << 17), ("triangle", 1 << 17)):
+                    ("4-cycle", 1 << 17), ("triangle", 1 << 17), ("4-clique", 1 << 16), ("6-clique", 1 << 13),
+                    ("chordal-7-cycle", 1 << 14)):
         p = synth.named_pattern(name)
         st, _ = oracle.Sampler(g, OT, compile_pattern(p.k, p.edges, mode="switch"), seed=SEED).run_parallel(0, n)
         for rowtab in ("on", "off"):
