@@ -135,8 +135,9 @@ def lib():
     return _lib
 
 
-def _p(a: np.ndarray):
-    return a.ctypes.data_as(ctypes.c_void_p)
+def _p(a):
+    """The array's address (None: a null pointer)."""
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
 # ---------------------------------------------------------------- RNG
@@ -207,6 +208,29 @@ class Tables:
             lib().orc_build_tables_oriented(_p(off), _p(nbr), n, _p(aoff), _p(anbr), cv_seed & 0xFFFFFFFF,
                                             cv_seed >> 32, lc_min, 1 if exact_cv else 0, _p(self.deg), _p(self.s2),
                                             _p(self.hits), _p(self.trials), _p(self.la), _p(self.lc))
+
+    @classmethod
+    def degrees_only(cls, g) -> "Tables":
+        """The degrees alone, d(v) = off[v + 1] - off[v]; the other entries
+        are unset and reach the sampler as null pointers.  Enough for plans
+        that read no other entry -- every step uniform (f_uniform, Algorithm
+        3 with D(i) = 0), or every weighted step without the T[I1] and T[F2]
+        terms (a star: its centre weighted by T[F1] alone, its leaves
+        trivial) -- on graphs whose full tables would take too long to build
+        on the host."""
+        t = cls.__new__(cls)
+        t.n = g.n
+        off = np.asarray(g.off, dtype=np.uint64)
+        t.deg = np.empty(g.n, dtype=np.uint32)
+        step = 1 << 26
+        for lo in range(0, g.n, step):
+            hi = min(g.n, lo + step)
+            t.deg[lo:hi] = (off[lo + 1:hi + 1] - off[lo:hi]).astype(np.uint32)
+        t.s2 = t.hits = t.trials = t.la = t.lc = None
+        t.cv_seed = 0
+        t.lc_min = LC_MIN_DEFAULT
+        t.exact_cv = False
+        return t
 
     def cv(self) -> np.ndarray:
         """Clustering coefficient hits / trials (0 where undefined)."""
@@ -309,7 +333,8 @@ class Sampler:
             _fields_ = [("deg", ctypes.c_void_p), ("s2", ctypes.c_void_p), ("la", ctypes.c_void_p),
                         ("lc", ctypes.c_void_p)]
         t = self.t
-        self._ts = T(t.deg.ctypes.data, t.s2.ctypes.data, t.la.ctypes.data, t.lc.ctypes.data)
+        addr = [None if a is None else a.ctypes.data for a in (t.deg, t.s2, t.la, t.lc)]
+        self._ts = T(*addr)
         return ctypes.byref(self._ts)
 
     def _common(self):

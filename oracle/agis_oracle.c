@@ -294,8 +294,9 @@ static int32_t log_weight(const orc_tables* T, const orc_plan* P, int i, uint32_
     if (lt) return lt[v];
     int32_t l = 0;
     for (uint32_t t = 0; t < f1; ++t) l += orc_log2fx((uint64_t)(d - b - t));  /* T[F1] = C(d-b, f1) * f1! */
-    l += (int32_t)P->ie[i] * T->lc[v];                                         /* T[I1] = C_v^|I_eff| */
-    l += (int32_t)P->f2[i] * T->la[v];                                         /* T[F2] = (S2/d)^|F2| */
+    /* (a term with a zero exponent is 1: its table is not read) */
+    if (P->ie[i]) l += (int32_t)P->ie[i] * T->lc[v]; /* T[I1] = C_v^|I_eff| */
+    if (P->f2[i]) l += (int32_t)P->f2[i] * T->la[v]; /* T[F2] = (S2/d)^|F2| */
     return l;
 }
 

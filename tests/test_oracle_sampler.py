@@ -564,3 +564,38 @@ def test_oriented_tables_count_out_neighbours():
         pairs = sum(1 for a, b in itertools.combinations(out, 2) if b in adj[a])
         assert int(t.hits[v]) == pairs
         assert int(t.trials[v]) == len(out) * (len(out) - 1) // 2
+
+
+def test_degrees_only_tables_serve_uniform_plans():
+    """A uniform plan, and a star's weighted plans, read only the degrees:
+    their records with the degrees-only tables (other entries null) equal
+    those with the full tables, so every pin of these samplers carries over
+    to them; the degrees are the row lengths."""
+    g = synth.chung_lu(n=2000, m=12_000, gamma=2.1, seed=4)
+    full = oracle.Tables(g, cv_seed=3)
+    deg = oracle.Tables.degrees_only(g)
+    assert np.array_equal(deg.deg, np.diff(g.off).astype(np.uint32))
+    assert np.array_equal(deg.deg, full.deg)
+    assert deg.la is None and deg.lc is None and deg.s2 is None
+    idx = np.concatenate([np.arange(2000), [2 ** 33 + 3, 2 ** 63 + 11]]).astype(np.uint64)
+    for name in ("5-clique", "6-cycle", "house", "4-star", "chordal-7-cycle"):
+        p = synth.named_pattern(name)
+        c = compile_pattern(p.k, p.edges, mode="uniform")
+        a = oracle.Sampler(g, full, c, seed=5).records(idx)
+        b = oracle.Sampler(g, deg, c, seed=5).records(idx)
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), name
+        assert (a["fail_step"] < 0).any(), name
+    # a star's weighted plans read the degrees alone: the centre first,
+    # weighted by T[F1] only (no I1, no F2), the leaves trivial
+    for name in ("4-star", "3-star"):
+        p = synth.named_pattern(name)
+        for mode in ("switch", "always"):
+            c = compile_pattern(p.k, p.edges, mode=mode)
+            weighted = [s for s in c["steps"] if s["decision"] == 1 and s["f1"] > 0]
+            assert weighted and all(s["ie"] == 0 and s["f2"] == 0 for s in weighted), (name, mode)
+            assert c["steps"][0] in weighted
+            a = oracle.Sampler(g, full, c, seed=5)
+            b = oracle.Sampler(g, deg, c, seed=5)
+            assert a.Q1 == b.Q1 > 0 and np.array_equal(a.q1, b.q1)
+            ra, rb = a.records(idx), b.records(idx)
+            assert np.array_equal(ra.view(np.uint8), rb.view(np.uint8)), (name, mode)
