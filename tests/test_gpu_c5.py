@@ -123,3 +123,41 @@ def test_rmat30_records_match_oracle(sess, r30, name, mode, step1):
         assert wide > idx.size // 2
     if name == "4-star":
         assert done > idx.size // 2
+
+
+@pytest.mark.parametrize("name,step1", [("5-clique", "auto"), ("6-cycle", "auto"), ("chordal-7-cycle", "blocks")])
+def test_rmat30_learned_records_match_oracle(sess, r30, name, step1):
+    """The weighted steps at full scale -- intersections of hub lists,
+    normalising maxima, u64 prefix picks over millions of candidates, the
+    first step over 2^30 vertices -- with seeded random learned tables (one
+    Q16 log weight per vertex and weighted step, the same arrays on both
+    sides): a learned plan reads the degrees (its certain zeros) and the
+    tables alone."""
+    import torch
+    G, T, gh, OT = r30
+    p = synth.named_pattern(name)
+    c = compile_pattern(p.k, p.edges, mode="learned")
+    steps = sess.weighted_steps(p, "learned")
+    assert steps == [i for i, s in enumerate(c["steps"]) if s["decision"] == 1 and s["f1"] > 0]
+    gen = torch.Generator(device=sess.device)
+    gen.manual_seed(300 + len(name))
+    tabs = {i: torch.randint(-(6 << 16), 6 << 16, (G.n,), dtype=torch.int32, device=sess.device, generator=gen)
+            for i in steps}
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(31))
+    idx = np.concatenate([np.arange(600), rng.integers(0, 1 << 40, size=400), [(1 << 63) + 9]]).astype(np.uint64)
+    t0 = time.time()
+    got = sess.dump(G, T, p, SEED, idx, mode="learned", learned={i: t.data_ptr() for i, t in tabs.items()},
+                    step1=step1)
+    host = {i: t.cpu().numpy() for i, t in tabs.items()}
+    del tabs
+    torch.cuda.empty_cache()
+    _SAMPLERS.clear()
+    ref = oracle.Sampler(gh, OT, c, seed=SEED, learned=host).records(idx, threads=0)
+    done = int((got["fail_step"] < 0).sum())
+    say(f"R-MAT-30 {name} learned step1={step1}: {idx.size} records, {done} complete, "
+        f"weighted steps {steps}, {time.time() - t0:.1f} s")
+    _compare(got, ref, f"rmat30/{name}/learned/{step1}")
+    # (random weights favour low degrees, so many samples fail early; the
+    # last weighted step is still drawn on a twentieth of them or more)
+    assert (got["steps"] > steps[-1]).sum() >= idx.size // 20
