@@ -721,6 +721,9 @@ def c5_leg(args, sess):
         p = synth.named_pattern(name)
         for mode in ("switch", "always", "uniform"):
             run_mode(pid, name, p, mode, {})
+    # the sampler's kept scratch (sized to half of the free memory) goes
+    # back before the features and learned tables are allocated
+    sess.release_scratch()
     for pid, name in enumerate(names):
         p = synth.named_pattern(name)
         steps = sess.weighted_steps(p, "learned")
@@ -741,6 +744,7 @@ def c5_leg(args, sess):
         torch.cuda.empty_cache()
         ptrs = {i: tab.data_ptr() for i, tab in tabs.items()}
         run_mode(pid, name, p, "learned", dict(learned=ptrs))
+        sess.release_scratch()
         del tabs, params, rows
         torch.cuda.empty_cache()
     for name in names:

@@ -225,6 +225,17 @@ int agis_create(agis_ctx** out, int device, void* hip_stream);
 void agis_destroy(agis_ctx* ctx);
 const char* agis_last_error(const agis_ctx* ctx);
 
+/* Gives back the device memory a context keeps between estimates for its
+ * sampler: the waves' candidate scratch (sized at an estimate to half of
+ * the device memory then free, with what the context already holds, within
+ * [8, 64] GiB), the round weights and partials, and the run-to-eps
+ * buffers.  For callers that allocate memory of their own between
+ * estimates; the next estimate allocates what it needs again, with the
+ * same results.  Waits for the context's stream and drops its captured
+ * launch graph.  Graphs, tables and their proposal-table caches are kept
+ * (agis_tables_destroy frees those). */
+int agis_release_scratch(agis_ctx* ctx);
+
 /* Registers a symmetric CSR graph (Sec. 5.4: the graph is held in CSR).
  * off: device uint64[n + 1], off[0] = 0, off[n] = nnz, non-decreasing;
  * nbr: device uint32[nnz], each row strictly ascending, ids < n, no

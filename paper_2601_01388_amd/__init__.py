@@ -122,6 +122,7 @@ _SIGNATURES = [
     ("agis_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, _P]),
     ("agis_destroy", None, [_P]),
     ("agis_last_error", ctypes.c_char_p, [_P]),
+    ("agis_release_scratch", ctypes.c_int, [_P]),
     ("agis_load_csr", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.POINTER(ctypes.c_void_p)]),
     ("agis_graph_destroy", None, [_P]),
@@ -213,6 +214,10 @@ def agis_destroy(ctx):
 
 def agis_last_error(ctx) -> str:
     return lib().agis_last_error(ctx).decode()
+
+
+def agis_release_scratch(ctx):
+    _check(ctx, lib().agis_release_scratch(ctx))
 
 
 def agis_load_csr(ctx, off_ptr: int, nbr_ptr: int, n: int, nnz: int, flags: int = AGIS_CSR_VALIDATE):

@@ -1363,6 +1363,27 @@ void agis_destroy(agis_ctx* ctx) {
     delete ctx;
 }
 
+int agis_release_scratch(agis_ctx* ctx) {
+    if (!ctx) return AGIS_E_INVALID_ARG;
+    AGIS_HIP(ctx, hipSetDevice(ctx->device), "set device");
+    AGIS_HIP(ctx, hipStreamSynchronize(ctx->stream), "wait for the context's stream");
+    // the captured round refers to these buffers
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    std::memset(ctx->graph_key, 0, sizeof(ctx->graph_key));
+    for (void** q : {&ctx->d_scratch, (void**)&ctx->d_xout, (void**)&ctx->d_partials, &ctx->d_eps}) {
+        if (*q) AGIS_HIP(ctx, hipFree(*q), "free sampler buffers");
+        *q = nullptr;
+    }
+    ctx->scratch_bytes = 0;
+    ctx->xout_cap = 0;
+    ctx->partials_cap = 0;
+    ctx->eps_bytes = 0;
+    return AGIS_OK;
+}
+
 const char* agis_last_error(const agis_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 int agis_load_csr(agis_ctx* ctx, const uint64_t* off, const uint32_t* nbr, uint64_t n, uint64_t nnz, uint32_t flags,

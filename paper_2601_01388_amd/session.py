@@ -11,7 +11,7 @@ import numpy as np
 from . import (AGIS_CSR_VALIDATE, LC_MIN_DEFAULT, RECORD_DTYPE, RECORD_BYTES, agis_build_proposal_tables,
                agis_autotune, agis_compile_pattern, agis_concentrations, agis_connected_patterns, agis_step1_weights,
                agis_orient,
-               agis_graph_export, agis_create, agis_destroy, agis_dump_samples, agis_estimate,
+               agis_graph_export, agis_create, agis_destroy, agis_dump_samples, agis_estimate, agis_release_scratch,
                agis_estimate_batch, agis_features, agis_graph_destroy, agis_learn_rows, agis_learn_targets,
                agis_load_csr, agis_mlp_grad, agis_mlp_infer, agis_mlp_param_count, agis_mlp_train, agis_set_launch,
                agis_step_log_weights, agis_meter_samples, agis_gather_bench,
@@ -298,6 +298,11 @@ class Session:
             out[i] = self.mlp_infer(params, feats, c, base=None if base is None else base[i],
                                     y_range=ranges.get(c) if rows is not None else None)
         return out
+
+    def release_scratch(self):
+        """Gives back the sampler memory the context keeps between estimates
+        (agis_release_scratch)."""
+        agis_release_scratch(self.ctx)
 
     def close(self):
         if self.ctx:

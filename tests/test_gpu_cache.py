@@ -132,3 +132,29 @@ def test_cache_keeps_the_per_estimate_table_time_down(sess, c1):
     say(f"table seconds: first {a.tables_seconds:.6f}, cached {b.tables_seconds:.6f}")
     assert b.tables_seconds < a.tables_seconds
     T.close()
+
+
+def test_release_scratch_gives_memory_back_with_the_same_results(sess, c1):
+    """agis_release_scratch frees the sampler's kept buffers (the free device
+    memory grows by at least the waves' scratch) and later estimates, fixed
+    budgets and runs to eps alike, equal those before it."""
+    import torch
+    g, G = c1
+    T = sess.tables(G, cv_seed=1)
+    p = synth.named_pattern("house")
+    a = sess.estimate(G, T, p, 300_000, 3)
+    e = sess.estimate(G, T, p, 1 << 24, 4, eps=0.02, check_every=1 << 13, min_samples=1 << 13)
+    torch.cuda.synchronize()
+    before = torch.cuda.mem_get_info()[0]
+    sess.release_scratch()
+    sess.release_scratch()  # nothing left to free: still fine
+    after = torch.cuda.mem_get_info()[0]
+    # a wave's scratch is two arrays of (max degree + 1) entries
+    per_wave = 2 * 4 * (int(np.diff(g.off).max()) + 1)
+    say(f"released {(after - before) / 2 ** 20:.1f} MiB (one wave's scratch {per_wave / 1024:.1f} KiB)")
+    assert after - before >= 256 * per_wave
+    _same(sess.estimate(G, T, p, 300_000, 3), a)
+    e2 = sess.estimate(G, T, p, 1 << 24, 4, eps=0.02, check_every=1 << 13, min_samples=1 << 13)
+    _same(e2, e)
+    assert e2.converged == e.converged
+    T.close()
