@@ -170,6 +170,9 @@ struct DevTables {
 
 // Every core-pair list starts on a block of this many entries.
 constexpr uint64_t kCoreBlock = 64;
+// A reused core list longer than this may give way to a shorter one of
+// the same candidate set (three core vertices: three lists to choose from).
+constexpr uint64_t kCoreSwapMin = 256;
 
 constexpr int kPairParts = 8;
 

@@ -2015,20 +2015,63 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 // the base and only the new backward lists are intersected.
                 const bool reuse = P->reuse[i] != 0;
                 const uint32_t lists = reuse ? (bm & ~P->bmask[i - 1]) : bm;
+                // A long reused core list of (tau_0, tau_1) and one new
+                // backward vertex: the set may be walked from a shorter core
+                // list (below), which takes the lists of tau_0 and tau_1 too.
+                const bool core_swap = reuse && prev_core != nullptr && t.cores != 0 && P->bmask[i - 1] == 3u &&
+                                       __builtin_popcount(lists) == 1 && scnt > kCoreSwapMin;
+                const uint32_t offl = lists | (core_swap ? 3u : 0u);
                 uint64_t my_o = 0;
                 uint32_t my_d = 0xFFFFFFFFu;
-                mt.vec(g.off + my_tau, 16, (uint32_t)lane < i && (lists >> lane & 1u));
-                if ((uint32_t)lane < i && (lists >> lane & 1u)) {
+                mt.vec(g.off + my_tau, 16, (uint32_t)lane < i && (offl >> lane & 1u));
+                if ((uint32_t)lane < i && (offl >> lane & 1u)) {
                     my_o = g.off[my_tau];
                     my_d = (uint32_t)(g.off[my_tau + 1] - my_o);
                 }
                 const uint32_t* base;
                 uint32_t db;
                 uint32_t others;
+                // whether the base is the reused set (else it covers all of I)
+                bool walk_reuse = reuse;
                 if (reuse) {
                     base = prev_core ? prev_core : sv;
                     db = (uint32_t)scnt;
                     others = lists;
+                    if (core_swap) {
+                        // S = N(tau_0) n N(tau_1) n N(tau_n) minus the matched
+                        // vertices is the same set, in the same ascending
+                        // order, whichever two of the three lists are read as
+                        // their common-neighbour list and walked against the
+                        // third: with tau_n in the core, the shortest of the
+                        // three core lists is walked.  The matched vertex such
+                        // a list may hold (tau_1 lies in the list of tau_0
+                        // and tau_n) is dropped by its own list, which does
+                        // not hold it, and every matched vertex is backward
+                        // here: the members are all of I, which is S.
+                        const int jn = __builtin_ctz(lists);
+                        const bool cl = lane == 0 || lane == 1 || lane == jn;
+                        mt.vec(t.core_slot + my_tau, 4, cl);
+                        const int32_t cs = cl ? t.core_slot[my_tau] : -1;
+                        const int32_t sn = (int32_t)readlane_u32((uint32_t)cs, jn);
+                        if (sn >= 0) {
+                            // lane 0: the list of (tau_0, tau_n); lane 1: (tau_1, tau_n)
+                            const bool pl = lane < 2;
+                            const uint64_t pr = (uint64_t)(pl ? cs : 0) * t.cores + (uint64_t)sn;
+                            mt.vec(t.core_len + pr, 4, pl);
+                            const uint32_t len = pl ? t.core_len[pr] : 0xFFFFFFFFu;
+                            const uint32_t l0 = readlane_u32(len, 0), l1 = readlane_u32(len, 1);
+                            const int jk = l0 <= l1 ? 0 : 1;  // the pair's matched vertex besides tau_n
+                            const uint32_t lmin = jk == 0 ? l0 : l1;
+                            if (lmin < db) {
+                                const uint64_t prm = readlane_u64(pr, jk);
+                                mt.uni(t.core_start + prm, 8);
+                                base = t.core_nbr + t.core_start[prm];
+                                db = lmin;
+                                others = 1u << (1 - jk);
+                                walk_reuse = false;
+                            }
+                        }
+                    }
                 } else {
                     // Two backward vertices of the core: start from their
                     // common-neighbour list (ascending: the set and order a
@@ -2071,7 +2114,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint32_t vprev = readlane_u32(my_tau, (int)i - 1);
                 int32_t lmax_l = kCertainZero;
                 if constexpr (MT::kOn) {
-                    const bool cand = weighted && reuse && (uint32_t)lane + 1 < i && !(bm >> lane & 1u);
+                    const bool cand = weighted && walk_reuse && (uint32_t)lane + 1 < i && !(bm >> lane & 1u);
                     uint32_t offl = 0, loads = 0;
                     bool in_all = true;
                     if (cand) {
@@ -2086,7 +2129,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     mt.lanes(loads, 4);
                     meter_step_log_weight(t, sw, lt, my_tau, b, f1, cand && in_all, mt);
                 }
-                if (weighted && reuse && (uint32_t)lane + 1 < i && !(bm >> lane & 1u)) {
+                if (weighted && walk_reuse && (uint32_t)lane + 1 < i && !(bm >> lane & 1u)) {
                     // matched vertices were dropped from the reused set; the
                     // normalising maximum still covers those lying in I (a
                     // backward vertex is not in its own list, so never in I)
@@ -2180,7 +2223,7 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                     meter_step_log_weight(t, sw, lt, xv, b, f1, weighted && member, mt);
                     if (weighted && member) l = step_log_weight(t, sw, lt, xv, b, f1, ie, f2);
                     bool in_tau = false;
-                    if (reuse) {
+                    if (walk_reuse) {
                         in_tau = xv == vprev;
                     } else {
                         for (uint32_t j = 0; j < i; ++j) in_tau |= (xv == readlane_u32(my_tau, (int)j));
