@@ -110,9 +110,11 @@ typedef struct {
  * min_samples: no convergence is declared before this many samples.
  * pattern_id: enters the random stream of every sample (Philox counter).
  * flags: AGIS_RUN_ROWTAB_* -- whether a weighted step with a single matched
- *   neighbour draws through per-row pick tables built for this estimate
- *   (same samples either way; AUTO builds them for runs of >= 65536
- *   samples when they fit in memory).  Also in flags: how a weighted first
+ *   neighbour draws through per-row pick tables built for this estimate,
+ *   and a weighted step over two matched neighbours of the core through
+ *   pick tables over their common-neighbour lists (same samples either
+ *   way; AUTO builds them for runs of >= 65536 samples when they fit in
+ *   memory).  Also in flags: how a weighted first
  *   step's distribution over all vertices is held -- AGIS_RUN_STEP1_FULL
  *   (the integer weight and inclusive prefix of every vertex, 12 bytes per
  *   vertex) or AGIS_RUN_STEP1_BLOCKS (the prefix over blocks of 256
@@ -277,17 +279,21 @@ int agis_graph_export(agis_ctx* ctx, const agis_graph* g, uint64_t* n, uint64_t*
  * counted exactly (exact_cv = 1).  Stored in Q16 log2 form with log2 C_v
  * clamped below at lc_min_q16 (log2 of the paper's small nonzero constant;
  * -655360 = log2 2^-10).  The tables are owned by the library.
- * With them the library builds two search aids of the sampler (they change
- * no sample): neighbourhood bitmaps of the highest-degree vertices (up to
- * 1 GiB), and the common-neighbour counts of every pair among the hubs of
- * highest degree (up to H = 8,192 of them, within a bounded build work),
+ * With them the library builds three search aids of the sampler (they
+ * change no sample): neighbourhood bitmaps of the highest-degree vertices
+ * (up to 1 GiB); the common-neighbour counts of every pair among the hubs
+ * of highest degree (up to H = 8,192 of them, within a bounded build work),
  * which make a uniform step over the common neighbours of two such hubs a
- * table read plus a partial walk.  The pair tables hold 8 counts per
- * ordered pair (the total and 7 running counts at eighths of the shorter
- * list), H^2 x 8 x 4 B: at most 2 GiB.
+ * table read plus a partial walk (8 counts per ordered pair, the total and
+ * 7 running counts at eighths of the shorter list, H^2 x 8 x 4 B: at most
+ * 2 GiB); and the common-neighbour lists themselves of every pair among
+ * the C highest-degree of those hubs (the core; C <= 4,096, the lists
+ * within 4 GiB and an eighth of the free memory), from which a step over
+ * two core vertices starts.
  * The tables also keep, for later calls, the f_approx proposal tables that
  * estimates with them build (per step signature: per-vertex step weights,
- * per-row pick tables, the first-step table): at most 16 GiB, least
+ * per-row pick tables, pick tables over the core-pair lists, the
+ * first-step table): at most 16 GiB, least
  * recently used first, released at a call that finds less than 128 GiB of
  * device memory free, and freed by agis_tables_destroy.  Tables built from
  * learned weights are rebuilt at every call (the caller may change them).

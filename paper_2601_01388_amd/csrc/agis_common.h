@@ -212,14 +212,15 @@ struct DevPlan {
     // s1_lmax, and the guide indexes blocks
     int32_t s1_lmax;
     AGIS_GMEM const uint64_t* s1_blk;
-    // step 2 when its backward vertices are the two matched ones (the first
-    // three pattern vertices form a triangle) and it is weighted: the pick
-    // table of its signature over the core-pair lists -- per list entry the
-    // integer weight against the list's largest log weight (cq), and per
-    // block of kCoreBlock entries the inclusive prefix within the list (cbp,
-    // indexed by entry / kCoreBlock) -- or nullptr
-    AGIS_GMEM const uint32_t* cq2;
-    AGIS_GMEM const uint64_t* cbp2;
+    // a weighted step whose two backward vertices are in the core: the pick
+    // table of its signature over the core-pair lists -- per list its
+    // largest log weight (clm, indexed like core_len; kCertainZero when the
+    // list has no weight), and per block of kCoreBlock entries the inclusive
+    // prefix within the list of the integer weights against it (cbp, indexed
+    // by entry / kCoreBlock); a block's weights are recomputed from sw at the
+    // draw -- or nullptr
+    AGIS_GMEM const int32_t* clm[kMaxK];
+    AGIS_GMEM const uint64_t* cbp[kMaxK];
 };
 
 constexpr uint32_t kStep1Block = 256;

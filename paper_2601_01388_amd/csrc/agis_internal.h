@@ -249,8 +249,9 @@ hipError_t launch_core_pairs(agis_ctx* ctx, const DevGraph& g, const int32_t* hu
                              const uint64_t* core_start, const uint32_t* core_len, uint32_t* core_nbr);
 
 // The pick table of one step signature (per-vertex log weights sw, certain
-// zeros folded in) over the core-pair lists: cq[entry], cbp[entry / kCoreBlock].
-hipError_t launch_core_pick(agis_ctx* ctx, const agis_tables& t, const int32_t* sw, uint32_t* cq, uint64_t* cbp);
+// zeros folded in) over the core-pair lists: clm[pair] (indexed like
+// core_len), cbp[entry / kCoreBlock].
+hipError_t launch_core_pick(agis_ctx* ctx, const agis_tables& t, const int32_t* sw, int32_t* clm, uint64_t* cbp);
 
 // The lane sampler for (record-writing?, metering?).
 const void* sample_lanes_kernel(bool dump, bool meter);

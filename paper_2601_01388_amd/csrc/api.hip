@@ -710,45 +710,43 @@ int prepare(agis_ctx* ctx, const agis_graph* g, const agis_tables* t, const agis
         if (step_rc != AGIS_OK) return step_rc;
         if (buf) hp.sw[i] = agis::gmem(buf);
     }
-    // the pick table over the core-pair lists for a weighted step 2 whose
-    // backward vertices are the two matched ones (built where row tables
-    // are, kept in the cache like them; not for learned weights)
-    if (want_rows && t->cores && hp.k > 2 && hp.weighted[2] && hp.bmask[2] == 3u && hp.lt[2] == nullptr &&
-        hp.sw[2] != nullptr && cache && t->core_entries * 4 + t->core_entries / 8 <= kRowtabBudgetBytes) {
-        CacheEntry* c = cache->find(kCacheCorePick, hp.b[2], hp.f1[2], hp.ie[2], hp.f2[2], 0);
-        if (c) {
-            st->held.push_back(c);
-        } else {
-            const uint64_t qb = t->core_entries * sizeof(uint32_t);
-            const uint64_t pb = (t->core_entries / agis::kCoreBlock + 1) * sizeof(uint64_t);
-            void* cq = table_alloc(ctx, cache, true, qb);
-            void* cbp = cq ? table_alloc(ctx, cache, true, pb) : nullptr;
-            hipError_t e = (cq && cbp) ? agis::launch_core_pick(ctx, *t, (const int32_t*)hp.sw[2], (uint32_t*)cq,
-                                                                (uint64_t*)cbp)
-                                       : hipErrorOutOfMemory;
-            if (e == hipSuccess) {
-                CacheEntry proto;
-                proto.kind = kCacheCorePick;
-                proto.b = hp.b[2];
-                proto.f1 = hp.f1[2];
-                proto.ie = hp.ie[2];
-                proto.f2 = hp.f2[2];
-                proto.buf[0] = cq;
-                proto.buf[1] = cbp;
-                proto.bytes = qb + pb;
-                c = cache->add(proto);
-                st->held.push_back(c);
-            } else {
-                if (cq) (void)hipFree(cq);
+    // the pick tables over the core-pair lists of the weighted steps with
+    // two backward vertices, one per step signature (built where row tables
+    // are and kept in the cache like them; not for learned weights): per
+    // list its largest log weight, per block of kCoreBlock entries a prefix
+    const uint64_t core_lb = t->cores * t->cores * sizeof(int32_t);
+    const uint64_t core_pb = (t->core_entries / agis::kCoreBlock + 1) * sizeof(uint64_t);
+    for (uint32_t i = 2; i < hp.k && want_rows && t->cores && cache && core_lb + core_pb <= kRowtabBudgetBytes; ++i) {
+        if (!hp.weighted[i] || __builtin_popcount(hp.bmask[i]) != 2 || hp.lt[i] != nullptr || hp.sw[i] == nullptr)
+            continue;
+        CacheEntry* c = cache->find(kCacheCorePick, hp.b[i], hp.f1[i], hp.ie[i], hp.f2[i], 0);
+        if (!c) {
+            void* clm = table_alloc(ctx, cache, true, core_lb);
+            void* cbp = clm ? table_alloc(ctx, cache, true, core_pb) : nullptr;
+            hipError_t e = (clm && cbp) ? agis::launch_core_pick(ctx, *t, (const int32_t*)hp.sw[i], (int32_t*)clm,
+                                                                 (uint64_t*)cbp)
+                                        : hipErrorOutOfMemory;
+            if (e != hipSuccess) {
+                if (clm) (void)hipFree(clm);
                 if (cbp) (void)hipFree(cbp);
                 if (e != hipErrorOutOfMemory) return hip_fail(ctx, e, "core-pair pick table");
-                (void)hipGetLastError();  // no room: step 2 walks the lists
+                (void)hipGetLastError();  // no room: the step walks the lists
+                continue;
             }
+            CacheEntry proto;
+            proto.kind = kCacheCorePick;
+            proto.b = hp.b[i];
+            proto.f1 = hp.f1[i];
+            proto.ie = hp.ie[i];
+            proto.f2 = hp.f2[i];
+            proto.buf[0] = clm;
+            proto.buf[1] = cbp;
+            proto.bytes = core_lb + core_pb;
+            c = cache->add(proto);
         }
-        if (c) {
-            hp.cq2 = agis::gmem((const uint32_t*)c->buf[0]);
-            hp.cbp2 = agis::gmem((const uint64_t*)c->buf[1]);
-        }
+        st->held.push_back(c);
+        hp.clm[i] = agis::gmem((const int32_t*)c->buf[0]);
+        hp.cbp[i] = agis::gmem((const uint64_t*)c->buf[1]);
     }
     // the blocked first-step table (8 bytes per kStep1Block vertices instead
     // of 12 per vertex) when asked for, or by default when the full table

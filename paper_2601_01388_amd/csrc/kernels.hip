@@ -1151,19 +1151,20 @@ __global__ __launch_bounds__(256) void k_core_fill(DevGraph g, const int32_t* __
 
 // The pick table of one step signature over the core-pair lists, one wave
 // per pair: the list's largest non-certain log weight (the normalising
-// maximum over the intersection of the two backward lists), each entry's
-// integer weight against it (0 for certain zeros and for the padding), and
-// per block the inclusive prefix of the weights within the list.
+// maximum over the intersection of the two backward lists), and per block
+// the inclusive prefix within the list of the entries' integer weights
+// against it (0 for certain zeros).  The weights themselves are not kept:
+// a draw recomputes the 64 of its block from the step's weight table.
 __global__ __launch_bounds__(256) void k_core_pick(const uint32_t* __restrict__ core_nbr,
                                                     const uint64_t* __restrict__ core_start,
                                                     const uint32_t* __restrict__ core_len, uint64_t C,
-                                                    const int32_t* __restrict__ sw, uint32_t* __restrict__ cq,
+                                                    const int32_t* __restrict__ sw, int32_t* __restrict__ clm,
                                                     uint64_t* __restrict__ cbp) {
     const int lane = lane_id();
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
     for (uint64_t pr = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; pr < C * C; pr += nw) {
         const uint64_t a = pr / C, b = pr % C;
-        if (a >= b) continue;  // wave-uniform; (b, a) shares the list
+        if (a > b) continue;  // wave-uniform; (b, a) shares the list
         const uint64_t st = core_start[pr];
         const uint64_t len = core_len[pr];
         int32_t lm = kCertainZero;
@@ -1172,27 +1173,30 @@ __global__ __launch_bounds__(256) void k_core_pick(const uint32_t* __restrict__ 
             lm = l > lm ? l : lm;
         }
         lm = wave_max_i32(lm);
+        if (lane == 0) {
+            clm[pr] = lm;
+            clm[b * C + a] = lm;
+        }
         uint64_t run = 0;
         for (uint64_t e0 = 0; e0 < len; e0 += kWave) {
-            const uint64_t e = e0 + (uint64_t)lane;  // inside the padded list
+            const uint64_t e = e0 + (uint64_t)lane;
             uint32_t q = 0;
             if (e < len) {
                 const int32_t l = sw[core_nbr[st + e]];
                 q = l == kCertainZero ? 0u : weight_from_log(lm, l, c_exp2tab);
             }
-            cq[st + e] = q;
             run += wave_sum_u64(q);
             if (lane == 0) cbp[(st + e0) / kCoreBlock] = run;
         }
     }
 }
 
-hipError_t launch_core_pick(agis_ctx* ctx, const agis_tables& t, const int32_t* sw, uint32_t* cq, uint64_t* cbp) {
+hipError_t launch_core_pick(agis_ctx* ctx, const agis_tables& t, const int32_t* sw, int32_t* clm, uint64_t* cbp) {
     const uint64_t C = t.cores;
     const uint64_t waves = C * C;
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, (uint64_t)ctx->num_cus * 8);
     hipLaunchKernelGGL(k_core_pick, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, t.core_nbr, t.core_start,
-                       t.core_len, C, sw, cq, cbp);
+                       t.core_len, C, sw, clm, cbp);
     return hipGetLastError();
 }
 
@@ -1693,17 +1697,73 @@ __device__ __forceinline__ void meter_step_log_weight(const DevTables& t, const 
 // candidates per lane up to which a weighted pick keeps them in registers
 constexpr int kPickBlock = 8;
 
-// Whether the vertices matched at steps 0 and 1 (lanes 0 and 1) are both in
-// the core; pr = their pair's index.
+// Whether the two vertices matched at the positions of bm's bits are both
+// in the core; pr = their pair's index.
 template <class MT>
-__device__ __forceinline__ bool core_pair01(const DevTables& t, uint32_t my_tau, uint64_t& pr, MT& mt) {
+__device__ __forceinline__ bool core_pair_of(const DevTables& t, uint32_t my_tau, uint32_t bm, uint64_t& pr, MT& mt) {
     const int lane = lane_id();
-    mt.vec(t.core_slot + my_tau, 4, lane < 2);
-    const int32_t c = lane < 2 ? t.core_slot[my_tau] : -1;
-    const int32_t ca = (int32_t)readlane_u32((uint32_t)c, 0), cb = (int32_t)readlane_u32((uint32_t)c, 1);
+    const int ja = __builtin_ctz(bm), jb = __builtin_ctz(bm & (bm - 1u));
+    const bool mine = lane == ja || lane == jb;
+    mt.vec(t.core_slot + my_tau, 4, mine);
+    const int32_t c = mine ? t.core_slot[my_tau] : -1;
+    const int32_t ca = (int32_t)readlane_u32((uint32_t)c, ja), cb = (int32_t)readlane_u32((uint32_t)c, jb);
     if (ca < 0 || cb < 0) return false;
     pr = (uint64_t)ca * t.cores + (uint64_t)cb;
     return true;
+}
+
+// This lane's entry of block kb of a core-pair list (x; 0 past the list)
+// and its integer weight against the list's largest log weight lm.
+template <class MT>
+__device__ __forceinline__ uint32_t core_block_q(const uint32_t* list, uint32_t len, const AGIS_GMEM int32_t* sw,
+                                                 int32_t lm, uint64_t kb, uint32_t& x, MT& mt) {
+    const uint64_t e = kb * kCoreBlock + (uint64_t)lane_id();
+    mt.vec(list + e, 4, e < len);
+    x = e < len ? list[e] : 0u;
+    mt.vec(sw + x, 4, e < len);
+    const int32_t l = e < len ? sw[x] : kCertainZero;
+    return l == kCertainZero ? 0u : weight_from_log(lm, l, s_exp2tab);
+}
+
+// The vertices matched at step i but not backward there that lie in a
+// core-pair list: lane j (one of them) gets its position, its weight and
+// the list's weight before it (from the block prefixes bp).
+struct CoreMatched {
+    uint64_t qx, px;
+    uint32_t pos, found;
+};
+
+template <class MT>
+__device__ __forceinline__ CoreMatched core_matched(const uint32_t* list, uint32_t len, const AGIS_GMEM int32_t* sw,
+                                                 int32_t lm, const AGIS_GMEM uint64_t* bp, uint32_t my_tau,
+                                                 uint32_t bm, uint32_t i, MT& mt) {
+    const int lane = lane_id();
+    CoreMatched m{0, 0, 0, 0};
+    const bool need = (uint32_t)lane < i && !(bm >> lane & 1u);
+    bool f;
+    const uint32_t pq = wave_lower_bound_keys(list, len, my_tau, need, i, f, mt);
+    if (need && f) {
+        m.pos = pq;
+        m.found = 1;
+    }
+    for (uint64_t fl = __ballot(m.found != 0); fl; fl &= fl - 1) {
+        const int j = __builtin_ctzll(fl);
+        const uint32_t pj = readlane_u32(m.pos, j);
+        const uint64_t kj = pj / kCoreBlock;
+        const int o = (int)(pj % kCoreBlock);
+        uint32_t xj;
+        const uint32_t qj = core_block_q(list, len, sw, lm, kj, xj, mt);
+        const uint64_t inc = wave_incl_scan_u64((uint64_t)qj);
+        if (kj > 0) mt.uni(bp + kj - 1, 8);
+        const uint64_t b0 = kj > 0 ? bp[kj - 1] : 0ull;
+        const uint64_t q0 = (uint64_t)readlane_u32(qj, o);
+        const uint64_t p0 = b0 + readlane_u64(inc, o) - q0;
+        if (lane == j) {
+            m.qx = q0;
+            m.px = p0;
+        }
+    }
+    return m;
 }
 
 template <bool kDump, bool kPairs, class MT>
@@ -1719,8 +1779,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
     uint32_t my_row = 0xFFFFFFFFu, my_rpos = 0;
     uint64_t scnt = 0;  // size of the candidate set the scratch holds
     // the previous step's candidate set when it was a core-pair list drawn
-    // through its pick table (the next step starts from that list)
+    // through its pick table (the next step starts from that list), and
+    // whether that list may hold matched vertices (drawn at step 3 or later)
     const uint32_t* core_set = nullptr;
+    bool core_loose = false;
     double x = 1.0;
     int fail = -1;
     uint32_t i = 0;
@@ -1820,7 +1882,9 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
             // variant still picks the vertex.
             const bool count_only = !kDump && !weighted && i + 1 == k;
             const uint32_t* prev_core = core_set;
+            const bool prev_loose = core_loose;
             core_set = nullptr;
+            core_loose = false;
             uint64_t cpr = 0;
             if (weighted && P->rowpre[i] != nullptr) {
                 // Weighted draw from S = N(w) minus the matched vertices
@@ -1968,40 +2032,74 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, num);
                 v = pair_hub_select(g, t, my_tau, bm, i, r, num, mt);
                 den = 1;
-            } else if (i == 2 && bm == 3u && weighted && P->cq2 != nullptr && t.cores != 0 &&
-                       core_pair01(t, my_tau, cpr, mt)) {
-                // Step 2 over the two matched vertices, both in the core: the
-                // candidates are exactly their common-neighbour list (no
-                // matched vertex lies in it), drawn through the signature's
-                // pick table over the core lists -- the block holding r from
-                // the block prefixes, then the entry within the block.  The
-                // next step starts from the list itself.
+            } else if (weighted && __builtin_popcount(bm) == 2 && P->cbp[i] != nullptr && t.cores != 0 &&
+                       core_pair_of(t, my_tau, bm, cpr, mt)) {
+                // Two backward vertices, both in the core: I is their
+                // common-neighbour list, drawn through the signature's pick
+                // table over the core lists -- the block holding the rank
+                // from the block prefixes, then the entry within the block,
+                // whose 64 weights are recomputed from the step's weights.
+                // S is I minus the matched vertices lying in it (from step 3
+                // on, vertices matched earlier but not backward here): their
+                // weights leave the total and the rank passes over them, as
+                // over a row table.  The next step starts from the list
+                // itself.
                 mt.uni(t.core_start + cpr, 8);
                 mt.uni(t.core_len + cpr, 4);
+                mt.uni(P->clm[i] + cpr, 4);
                 const uint64_t st = t.core_start[cpr];
                 const uint32_t len = t.core_len[cpr];
+                const int32_t lm = P->clm[i][cpr];
+                const uint32_t* list = t.core_nbr + st;
+                const AGIS_GMEM int32_t* swi = P->sw[i];
                 const uint64_t nb = ((uint64_t)len + kCoreBlock - 1) / kCoreBlock;
-                const AGIS_GMEM uint64_t* bp = P->cbp2 + st / kCoreBlock;
+                const AGIS_GMEM uint64_t* bp = P->cbp[i] + st / kCoreBlock;
                 if (nb) mt.uni(bp + nb - 1, 8);
-                const uint64_t Q = nb ? bp[nb - 1] : 0ull;
+                const uint64_t qi = nb ? bp[nb - 1] : 0ull;
+                if (qi == 0) {
+                    fail = (int)i;
+                    break;
+                }
+                // lane j, a matched vertex in the list: its position, its
+                // weight and the list's weight before it
+                CoreMatched cm{0, 0, 0, 0};
+                if (i > 2) cm = core_matched(list, len, swi, lm, bp, my_tau, bm, i, mt);
+                const uint32_t pos = cm.pos;
+                const uint64_t qx = cm.qx, px = cm.px;
+                const bool found = cm.found != 0;
+                const uint64_t Q = qi - wave_sum_u64(qx);
                 if (Q == 0) {
                     fail = (int)i;
                     break;
                 }
                 const uint64_t r = bounded_draw(k0, k1, c0, c1, c2, i, Q);
-                const uint64_t kb = wave_first_greater(bp, nb, r, mt);
+                // the rank within I: past every matched vertex at or below
+                // it, in ascending order of position
+                uint64_t rr = r;
+                for (uint64_t left = __ballot(found); left;) {
+                    uint64_t key = (left >> lane & 1ull) ? (((uint64_t)pos << 8) | (uint64_t)lane) : ~0ull;
+#pragma unroll
+                    for (int of = 32; of > 0; of >>= 1) {
+                        const uint64_t k2 = __shfl_xor(key, of, kWave);
+                        key = k2 < key ? k2 : key;
+                    }
+                    const int L = (int)(key & 0xFF);
+                    if (rr < readlane_u64(px, L)) break;
+                    rr += readlane_u64(qx, L);
+                    left &= ~(1ull << L);
+                }
+                const uint64_t kb = wave_first_greater(bp, nb, rr, mt);
                 if (kb > 0) mt.uni(bp + kb - 1, 8);
                 const uint64_t before = kb > 0 ? bp[kb - 1] : 0ull;
-                const uint64_t e = kb * kCoreBlock + (uint64_t)lane;
-                mt.vec(P->cq2 + st + e, 4, e < len);
-                const uint32_t qv = e < len ? P->cq2[st + e] : 0u;
+                uint32_t xv;
+                const uint32_t qv = core_block_q(list, len, swi, lm, kb, xv, mt);
                 const uint64_t incl = wave_incl_scan_u64((uint64_t)qv);
-                const int L = __ffsll((unsigned long long)__ballot(before + incl > r)) - 1;
-                mt.uni(t.core_nbr + st + kb * kCoreBlock + (uint64_t)L, 4);
-                v = t.core_nbr[st + kb * kCoreBlock + (uint64_t)L];
+                const int L = __ffsll((unsigned long long)__ballot(before + incl > rr)) - 1;
+                v = readlane_u32(xv, L);
                 num = Q;
                 den = readlane_u32(qv, L);
-                core_set = t.core_nbr + st;
+                core_set = list;
+                core_loose = i > 2;
                 scnt = len;
             } else {
                 // Candidate set I = intersection of the backward lists, S = I
@@ -2031,8 +2129,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                 const uint32_t* base;
                 uint32_t db;
                 uint32_t others;
-                // whether the base is the reused set (else it covers all of I)
-                bool walk_reuse = reuse;
+                // whether the base is the reused set (else it covers all of I:
+                // a core list that may hold matched vertices is walked with
+                // every matched vertex tested, like a fresh list)
+                bool walk_reuse = reuse && !(prev_core != nullptr && prev_loose);
                 if (reuse) {
                     base = prev_core ? prev_core : sv;
                     db = (uint32_t)scnt;
@@ -2043,11 +2143,10 @@ __device__ __forceinline__ double sample_one(const DevGraph& g, const DevTables&
                         // order, whichever two of the three lists are read as
                         // their common-neighbour list and walked against the
                         // third: with tau_n in the core, the shortest of the
-                        // three core lists is walked.  The matched vertex such
-                        // a list may hold (tau_1 lies in the list of tau_0
-                        // and tau_n) is dropped by its own list, which does
-                        // not hold it, and every matched vertex is backward
-                        // here: the members are all of I, which is S.
+                        // three core lists is walked.  The walk covers all of
+                        // I (tau_1, say, lies in the list of tau_0 and tau_n
+                        // but not in its own), so every matched vertex is
+                        // tested as over a fresh list.
                         const int jn = __builtin_ctz(lists);
                         const bool cl = lane == 0 || lane == 1 || lane == jn;
                         mt.vec(t.core_slot + my_tau, 4, cl);

@@ -362,6 +362,39 @@ def test_rmat20_estimates_match_oracle(sess, rmat20):
     G.close()
 
 
+# patterns of the seeded 32-pattern set whose weighted steps have two
+# backward vertices: drawn through the core-pair pick tables, at step 2, 3
+# or 4, over the pairs {0, 1}, {1, 2} and {0, 2}, with earlier matched
+# vertices that may lie in the pair's list (12 has two such steps)
+CORE_PICK_BATCH = [12, 14, 19, 22, 25, 28]
+
+
+def test_rmat20_core_pick_steps_match_oracle(sess, rmat20):
+    """Records on sampled indices and estimates (to rel 1e-9) of those
+    patterns on the full-size graph, with row and pick tables on and off."""
+    g = rmat20
+    G = sess.graph(g.off, g.nbr)
+    T = sess.tables(G, cv_seed=CV_SEED)
+    OT = oracle.Tables(g, cv_seed=CV_SEED, threads=0)
+    pset = synth.random_pattern_set(32, seed=3)
+    rng = np.random.Generator(np.random.PCG64(21))
+    idx = np.sort(rng.integers(0, 10 ** 8, size=600, dtype=np.uint64))
+    for which in CORE_PICK_BATCH:
+        p = pset[which][0]
+        c = compile_pattern(p.k, p.edges, mode="switch")
+        S = oracle.Sampler(g, OT, c, seed=SEED, pattern_id=which)
+        ref = S.records(idx, threads=0)
+        st, _ = S.run_parallel(0, 1 << 14)
+        for rowtab in ("on", "off"):
+            say(f"R-MAT-20 batch pattern {which} (k={p.k}, {len(p.edges)} edges) rowtab={rowtab}")
+            got = sess.dump(G, T, p, SEED, idx, mode="switch", pattern_id=which, rowtab=rowtab)
+            _compare_records(got, ref, f"rmat20/batch{which}/{rowtab}")
+            r = sess.estimate(G, T, p, 1 << 14, SEED, mode="switch", pattern_id=which, rowtab=rowtab)
+            assert abs(r.estimate - st.mean) <= 1e-9 * abs(st.mean), (which, rowtab, r.estimate, st.mean)
+    T.close()
+    G.close()
+
+
 @pytest.mark.parametrize("n", [70, 130])
 def test_complete_graph_closed_forms_with_pair_hubs(sess, n):
     """On K_n (n >= 65) every vertex has a neighbourhood bitmap and is a pair
