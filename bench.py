@@ -331,7 +331,10 @@ def learned_four(args, sess, T, pats):
 def time_to_eps(args, sess, G, T, pats, learned):
     """Time to +-1% at 95% CI (Algorithm 1) per pattern and proposal; checks
     every 4096 samples from 4096 on, so that the stop point reflects the
-    proposal rather than the check interval; budget --eps-budget."""
+    proposal rather than the check interval; budget --eps-budget.  (These
+    one-launch runs keep the 5-clique's launch shape: the per-pattern shapes
+    are tuned on fixed-size launches, and the run-to-eps kernel at 7 waves
+    per SIMD reached +-1% later on the 5-cycle and the house.)"""
     table = {}
     ck = args.eps_check
     for pid, (name, p) in enumerate(zip(PATTERNS, pats)):
