@@ -183,3 +183,17 @@ def test_sampler_division_multipliers_are_exact():
         assert m == -(-(1 << (32 + s)) // d) and m * d - (1 << (32 + s)) <= (1 << s)
         for x in [0, 1, d - 1, d, d + 1, (1 << 32) - 1, (1 << 32) - d, (1 << 31) + 5] + list(range(0, 5000)):
             assert ((x * m) >> 32) >> s == x // d
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N with N > 1 exits with status 2 and
+    says so, before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2, (r.returncode, r.stderr[-500:])
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
